@@ -6,7 +6,7 @@ values with index i > N - n in descending order, i.e. the n smallest. For
 non-homogeneous meshes L is replaced by the orthonormalised Laplacian
 L~ = G^{-1/2} L G^{-1/2}.
 
-Readings (see the design notes):
+Readings of points the paper leaves open:
   * keep_nullspace=True (default): P projects onto the eigenvectors of the n
     smallest eigenvalues of L~ *including* the constant (null) mode. The
     literal S^+ S would drop that mode (keep_nullspace=False gives it: modes

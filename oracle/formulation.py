@@ -4,7 +4,7 @@ Paper, Notation and Background (discretised normalised Calderon TE-EFIE and
 TE-MFIE) and Filters Based Fast Direct Solver, 2D case. Unknown y = G^{1/2} j
 (the paper writes j_2 for the normalised unknown; j = G^{-1/2} y is reported).
 
-Readings taken where the printed text is garbled (see the design notes):
+Readings taken where the printed text is garbled or silent:
   * EFIE: Z_e = G^{-1/2} S G^{-1} N G^{-1/2} -> I/4 + compact. The printed
     (ik)^{-1} factor is dropped from Z_2 because C_2 = Z_2 - I/4 must be
     compact; the physical constants sit in the right-hand side, built from

@@ -1,7 +1,7 @@
 """Quadrature rules for the Galerkin double integrals (oracle).
 
-The paper does not state its quadrature. This build's reading (recorded in the
-design notes): every panel pair uses the 8 x 8 tensor Gauss-Legendre rule,
+The paper does not state its quadrature. The rule adopted here: every panel
+pair uses the 8 x 8 tensor Gauss-Legendre rule,
 except that on self and adjacent panel pairs the Laplace singular parts
   -(1/2 pi) log|x - y|          (single layer / Maue hypersingular form)
   (1/2 pi) (x - y).n_y/|x - y|^2 (double layer, adjacent pairs)
