@@ -1,0 +1,226 @@
+/*
+ * fds.h -- C ABI of the filtered fast direct solver for the 2D TE-EFIE /
+ * TE-MFIE / TE-CFIE on AMD Instinct MI355X (gfx950).
+ *
+ * Method: C. Henry et al., "Fast Direct Solvers for Integral Equations at
+ * Low-Frequency Based on Operator Filtering" (arXiv 2210.08580). Section
+ * names below refer to that paper.
+ *
+ * Pipeline and state machine (calls out of order return FDS_ERR_STATE):
+ *     fds_assemble -> fds_filter -> fds_compress -> fds_factor -> fds_solve
+ * fds_rhs_planewave and the fds_op_* views are valid from ASSEMBLED on.
+ *
+ * Conventions
+ *   - Every pointer argument named "device" is a device address on the
+ *     context's GPU; "host" pointers are ordinary host memory.
+ *   - Complex numbers are interleaved (re, im) doubles (complex128).
+ *   - N x N operator matrices are row-major. Blocks of vectors (right-hand
+ *     sides, solutions, filter basis) are stored vector after vector: a block
+ *     of m vectors of length N is m contiguous runs of N entries.
+ *   - All work is enqueued on the context's HIP stream and is asynchronous
+ *     unless stated otherwise; fds_sync waits for it and reports
+ *     asynchronous device errors.
+ *   - Inputs are borrowed: the library never frees caller memory. An fds_op
+ *     owns its device workspace until fds_op_destroy.
+ *   - No C++ exception crosses this interface. On failure a call returns a
+ *     non-zero status and fds_last_error() (thread-local) describes it.
+ */
+#ifndef FDS_H
+#define FDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fds_status {
+    FDS_OK = 0,
+    FDS_ERR_ARG = 1,       /* invalid argument (sizes, NULL, bad geometry)       */
+    FDS_ERR_ALLOC = 2,     /* device allocation failed                            */
+    FDS_ERR_HIP = 3,       /* a HIP runtime call failed                           */
+    FDS_ERR_STATE = 4,     /* call made out of pipeline order                     */
+    FDS_ERR_SINGULAR = 5,  /* Woodbury core numerically singular                  */
+    FDS_ERR_NOCONV = 6,    /* refinement did not reach the requested tolerance    */
+    FDS_ERR_NOTIMPL = 7    /* option not implemented                              */
+} fds_status;
+
+typedef struct fds_ctx_s* fds_ctx;
+typedef struct fds_op_s* fds_op;
+
+/* Optional device allocator (e.g. a framework's caching allocator). alloc
+ * returns a device pointer of at least `bytes` usable on `stream`, or NULL. */
+typedef struct fds_allocator {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*release)(void* ptr, void* stream, void* user);
+    void* user;
+} fds_allocator;
+
+typedef enum fds_form {
+    FDS_EFIE = 0,   /* normalised Calderon TE-EFIE, beta = 1/4                 */
+    FDS_MFIE = 1,   /* normalised TE-MFIE, beta = 1/2                          */
+    FDS_CFIE = 2    /* EFIE + alpha MFIE, beta = (1 + 2 alpha)/4                */
+} fds_form;
+
+typedef enum fds_precision { FDS_FP64 = 0, FDS_FP32 = 1, FDS_BF16 = 2 } fds_precision;
+
+typedef struct fds_asm_opts {
+    int32_t nquad;       /* Gauss points per panel; only 8 is supported          */
+    int32_t precision;   /* FDS_FP64                                            */
+    int32_t reserved[6];
+} fds_asm_opts;
+
+typedef struct fds_filter_opts {
+    int32_t n_modes;          /* filtering point n: number of kept Laplacian modes */
+    int32_t keep_nullspace;   /* 1: keep the constant (null) mode (default)        */
+    double cluster_rtol;      /* grow n while the cut splits eigenvalues closer
+                                 than this relative gap (default 1e-6)            */
+} fds_filter_opts;
+
+typedef struct fds_compress_opts {
+    int32_t rank_cap;      /* r: maximal skeleton rank                           */
+    int32_t oversample;    /* p: sketch width l = r + p                          */
+    int32_t power_iters;   /* q: subspace iterations                             */
+    int32_t precision;     /* FDS_FP64                                           */
+    double tol;            /* eps: keep sigma_i > eps sigma_1 (0: rank cap only)  */
+    uint64_t seed;         /* sketch seed (SplitMix64 counter rule)              */
+} fds_compress_opts;
+
+typedef struct fds_solve_opts {
+    int32_t max_iters;     /* refinement sweeps after the Woodbury solve          */
+    int32_t precision;     /* FDS_FP64                                           */
+    double tol;            /* stop when max_r ||v_r - A y_r|| / ||v_r|| <= tol    */
+} fds_solve_opts;
+
+typedef struct fds_solve_stats {
+    int32_t iters;         /* refinement sweeps done                              */
+    int32_t converged;     /* 1 if the tolerance was met                          */
+    double relres;         /* final max relative residual                         */
+    double history[32];    /* residual after the Woodbury solve and each sweep    */
+} fds_solve_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on GPU `device`; all work is ordered on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). `alloc` may be NULL (the
+ * library then uses hipMalloc/hipFree). */
+fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* alloc,
+                          fds_ctx* out);
+fds_status fds_ctx_destroy(fds_ctx ctx);
+/* Waits for all enqueued work; reports asynchronous device errors. */
+fds_status fds_sync(fds_ctx ctx);
+/* Thread-local description of the last failure of this thread. */
+const char* fds_last_error(void);
+
+/* ------------------------------------------------------- special functions */
+
+/* Bessel functions of the Hankel kernel (paper, Notation and Background:
+ * g2 = (i/4) H0^(1)(k|r - r'|)). x: device [n] doubles, x > 0.
+ * out: device [n][4] doubles = J0, Y0, J1, Y1 at each x. */
+fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out);
+
+/* Kernel values used by the Galerkin quadrature at distances R (device [n],
+ * R >= 0). out: device [n][8] doubles =
+ *   g(R) = (i/4) H0^(1)(kR)                           (re, im)  (R > 0)
+ *   g(R) + log(R)/(2 pi), continuous at R = 0          (re, im)
+ *   c(R) = (ik/4) H1^(1)(kR)/R, dg/dn_y = c (x-y).n_y  (re, im)  (R > 0)
+ *   c(R) - 1/(2 pi R^2)                                (re, im)  (R > 0)  */
+fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n,
+                           double* out);
+
+/* ---------------------------------------------------------------- assembly */
+
+/* Dense Galerkin assembly (paper, Notation and Background: [S]_ij, [N]_ij,
+ * [D]_ij with the P1 hat basis on a straight-segment mesh; N in Maue's
+ * integrated-by-parts form) plus the Gram matrix G and the Laplacian L
+ * (paper, Laplacian Filters, 2D case).
+ * nodes: device [n][2] doubles, counter-clockwise, closed (panel i joins
+ *        node i to node i+1 mod n), no repeated node; 8 <= n.
+ * k:     wave number > 0.
+ * opts:  may be NULL (defaults: nquad 8, FP64).
+ * out:   receives a new operator owning S, N, D (3 n^2 complex128).
+ * Errors: FDS_ERR_ARG for bad sizes/k or a zero-length / non-finite panel,
+ * FDS_ERR_ALLOC when the matrices do not fit. */
+fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
+                        const fds_asm_opts* opts, fds_op* out);
+fds_status fds_op_destroy(fds_op op);
+
+/* Sizes: n, kept filter modes (0 before fds_filter), skeleton rank (0 before
+ * fds_compress). Any output pointer may be NULL. Host call, no sync. */
+fds_status fds_op_info(fds_op op, int64_t* n, int32_t* n_eff, int32_t* rank);
+
+/* Borrowed device views of S, N, D ([n][n] complex128, row-major). */
+fds_status fds_op_matrices(fds_op op, void** S, void** Nmat, void** D);
+
+/* Borrowed device views of the periodic tridiagonal G and L: diag[i] and
+ * off[i] = M[i][i+1 mod n] ([n] doubles each). */
+fds_status fds_op_sparse(fds_op op, const double** g_diag, const double** g_off,
+                         const double** l_diag, const double** l_off);
+
+/* X <- G^{p/2} X for p in {-2, -1, 1} (G^{-1}, G^{-1/2}, G^{1/2}); X: device,
+ * ncols complex128 vectors of length n, in place. Used by the normalised
+ * formulations (paper, Notation and Background). */
+fds_status fds_apply_gram(fds_op op, int32_t p, void* X, int64_t ncols);
+
+/* ------------------------------------------------------------------ filter */
+
+/* Laplacian filter P = V_n V_n^T (paper, Laplacian Filters, eq. LapFilter,
+ * with the orthonormalised Laplacian G^{-1/2} L G^{-1/2} for non-uniform
+ * meshes) and the compact part of the chosen formulation (paper, Filters
+ * Based Fast Direct Solver, 2D case). Builds B = V_n^T C (n_eff x n).
+ * n_eff (host, may be NULL) receives the number of kept modes after the
+ * cluster guard. Errors: FDS_ERR_ARG for n_modes outside [1, n]. */
+fds_status fds_filter(fds_op op, fds_form form, double alpha,
+                      const fds_filter_opts* opts, int32_t* n_eff);
+
+/* Borrowed device view of V_n: n_eff orthonormal real vectors of length n. */
+fds_status fds_op_filter_basis(fds_op op, const double** Vn);
+
+/* ------------------------------------------------------------- compression */
+
+/* Randomised skeleton C_f ~ U W of the filtered compact part (paper,
+ * Inversion of the structured matrices). rank_out (host, may be NULL)
+ * receives r. */
+fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out);
+
+/* Borrowed device views: U (r vectors of length n) and W (r rows of length n,
+ * row-major r x n), complex128. C_f ~ U W. */
+fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* rank);
+
+/* ----------------------------------------------------------------- factor */
+
+/* LU with partial pivoting of the Woodbury core K = I_r + beta^{-1} W U
+ * (paper, Inversion of the structured matrices). Synchronises to check the
+ * pivots; FDS_ERR_SINGULAR if min|pivot| < 64 eps max|K|. */
+fds_status fds_factor(fds_op op);
+
+/* -------------------------------------------------------------------- RHS */
+
+/* Plane waves u = A exp(i k d.x), d = (cos phi, sin phi) (paper, Notation and
+ * Background: e_2, h_2 moments; plane waves stand in for the paper's dipole).
+ * angles: device [nrhs] doubles; amps: device [nrhs] complex128.
+ * f_out: device [nrhs][n] complex128, f_i = <phi_i, du/dn>   (may be NULL)
+ * h_out: device [nrhs][n] complex128, h_i = <phi_i, u>       (may be NULL) */
+fds_status fds_rhs_planewave(fds_op op, const double* angles, const void* amps,
+                             int64_t nrhs, void* f_out, void* h_out);
+
+/* ------------------------------------------------------------------ solve */
+
+/* Solves (beta I + P C) y = v for nrhs right-hand sides built from f and h
+ * (EFIE v = -G^{-1/2} S G^{-1} f, MFIE v = -G^{-1/2} h, CFIE v_e + alpha v_h)
+ * with the Woodbury inverse of beta I + U W, then FP64 iterative refinement
+ * against beta I + P C, and returns j = G^{-1/2} y.
+ * f, h: device [nrhs][n] complex128 (the one the formulation does not use may
+ * be NULL). j_out, y_out: device [nrhs][n] complex128 (y_out may be NULL).
+ * opts may be NULL (defaults: max_iters 4, tol 1e-12). stats (host, may be
+ * NULL) makes the call synchronous and reports the residual history.
+ * FDS_ERR_NOCONV if stats is given and the tolerance was not met. */
+fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs,
+                     void* j_out, void* y_out, const fds_solve_opts* opts,
+                     fds_solve_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDS_H */

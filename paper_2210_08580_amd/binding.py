@@ -1,0 +1,325 @@
+"""Python binding of libfds (ctypes): argument marshalling only.
+
+Each function carries the name of the C entry point it calls (include/fds.h).
+PyTorch provides the device memory (the library allocates through torch's
+caching allocator) and the stream; every computation runs in the HIP kernels
+of libfds.so. There is no fallback: if the library is missing, or no GPU is
+visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfds.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "fds.h")
+
+FDS_EFIE, FDS_MFIE, FDS_CFIE = 0, 1, 2
+FORMS = {"efie": FDS_EFIE, "mfie": FDS_MFIE, "cfie": FDS_CFIE}
+FDS_FP64, FDS_FP32, FDS_BF16 = 0, 1, 2
+STATUS = {0: "FDS_OK", 1: "FDS_ERR_ARG", 2: "FDS_ERR_ALLOC", 3: "FDS_ERR_HIP",
+          4: "FDS_ERR_STATE", 5: "FDS_ERR_SINGULAR", 6: "FDS_ERR_NOCONV", 7: "FDS_ERR_NOTIMPL"}
+
+
+class FdsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+# ----------------------------------------------------------------- C structs
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class fds_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("user", C.c_void_p)]
+
+
+class fds_asm_opts(C.Structure):
+    _fields_ = [("nquad", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class fds_filter_opts(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("keep_nullspace", C.c_int32), ("cluster_rtol", C.c_double)]
+
+
+class fds_compress_opts(C.Structure):
+    _fields_ = [("rank_cap", C.c_int32), ("oversample", C.c_int32), ("power_iters", C.c_int32),
+                ("precision", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64)]
+
+
+class fds_solve_opts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double)]
+
+
+class fds_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("history", C.c_double * 32)]
+
+
+_SIGS = {
+    "fds_last_error": (C.c_char_p, []),
+    "fds_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(fds_allocator), C.POINTER(C.c_void_p)]),
+    "fds_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "fds_sync": (C.c_int, [C.c_void_p]),
+    "fds_hankel_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
+                               C.POINTER(fds_asm_opts), C.POINTER(C.c_void_p)]),
+    "fds_op_destroy": (C.c_int, [C.c_void_p]),
+    "fds_op_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32)]),
+    "fds_op_matrices": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p)]),
+    "fds_op_sparse": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_void_p)] * 4),
+    "fds_apply_gram": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "fds_filter": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.POINTER(fds_filter_opts),
+                             C.POINTER(C.c_int32)]),
+    "fds_op_filter_basis": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fds_compress": (C.c_int, [C.c_void_p, C.POINTER(fds_compress_opts), C.POINTER(C.c_int32)]),
+    "fds_op_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                 C.POINTER(C.c_int32)]),
+    "fds_factor": (C.c_int, [C.c_void_p]),
+    "fds_rhs_planewave": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_void_p]),
+    "fds_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                            C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
+}
+
+_lib = None
+
+
+def header_symbols() -> list[str]:
+    """Entry points declared in include/fds.h."""
+    with open(HEADER) as fh:
+        txt = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:fds_status|const char\*|void)\s+(fds_\w+)\s*\(", txt, re.M)))
+
+
+def lib() -> C.CDLL:
+    """Load libfds.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise FdsError(st, lib().fds_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+class _DevView:
+    """__cuda_array_interface__ over library-owned memory (kept alive by owner)."""
+
+    def __init__(self, ptr, shape, typestr, owner):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
+        self._owner = owner
+
+
+def _view(ptr, shape, dtype, owner):
+    ts = {torch.float64: "<f8", torch.complex128: "<c16"}[dtype]
+    v = torch.as_tensor(_DevView(ptr, shape, ts, owner), device="cuda")
+    return v
+
+
+# ----------------------------------------------------------------- context
+class Ctx:
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libfds runs on the device only")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._keep = []
+        alloc_p = None
+        if use_torch_allocator:
+            dev = device
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+                except Exception:
+                    return None
+
+            def _release(ptr, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            a = fds_allocator(_ALLOC_FN(_alloc), _RELEASE_FN(_release), None)
+            self._keep += [a, a.alloc, a.release]
+            alloc_p = C.byref(a)
+        h = C.c_void_p()
+        _check(lib().fds_ctx_create(device, C.c_void_p(self.stream.cuda_stream), alloc_p, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fds_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fds_ctx_create(device: int = 0, stream=None) -> Ctx:
+    return Ctx(device, stream)
+
+
+def fds_sync(ctx: Ctx):
+    _check(lib().fds_sync(ctx.handle))
+
+
+def fds_hankel_eval(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:
+    out = torch.empty((x.numel(), 4), dtype=torch.float64, device=x.device)
+    _check(lib().fds_hankel_eval(ctx.handle, _ptr(x), x.numel(), _ptr(out)))
+    return out
+
+
+def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:
+    out = torch.empty((R.numel(), 8), dtype=torch.float64, device=R.device)
+    _check(lib().fds_kernel_eval(ctx.handle, float(k), _ptr(R), R.numel(), _ptr(out)))
+    return out
+
+
+# ----------------------------------------------------------------- operator
+class Op:
+    def __init__(self, ctx: Ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fds_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n = C.c_int64()
+        ne = C.c_int32()
+        r = C.c_int32()
+        _check(lib().fds_op_info(self.handle, C.byref(n), C.byref(ne), C.byref(r)))
+        return n.value, ne.value, r.value
+
+    @property
+    def n(self) -> int:
+        return self.info()[0]
+
+
+def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | None = None) -> Op:
+    nodes = nodes.to(device="cuda", dtype=torch.float64).contiguous()
+    h = C.c_void_p()
+    _check(lib().fds_assemble(ctx.handle, _ptr(nodes), nodes.shape[0], float(k),
+                              C.byref(opts) if opts is not None else None, C.byref(h)))
+    return Op(ctx, h)
+
+
+def fds_op_matrices(op: Op):
+    s, n_, d = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().fds_op_matrices(op.handle, C.byref(s), C.byref(n_), C.byref(d)))
+    N = op.n
+    return tuple(_view(p.value, (N, N), torch.complex128, op) for p in (s, n_, d))
+
+
+def fds_op_sparse(op: Op):
+    ps = [C.c_void_p() for _ in range(4)]
+    _check(lib().fds_op_sparse(op.handle, *[C.byref(p) for p in ps]))
+    N = op.n
+    return tuple(_view(p.value, (N,), torch.float64, op) for p in ps)
+
+
+def fds_apply_gram(op: Op, p: int, X: torch.Tensor):
+    _check(lib().fds_apply_gram(op.handle, int(p), _ptr(X), X.numel() // op.n))
+    return X
+
+
+def fds_filter(op: Op, form: str = "efie", alpha: float = 1.0, n_modes: int = 21,
+               keep_nullspace: bool = True, cluster_rtol: float = 1e-6) -> int:
+    o = fds_filter_opts(int(n_modes), int(bool(keep_nullspace)), float(cluster_rtol))
+    ne = C.c_int32()
+    _check(lib().fds_filter(op.handle, FORMS[form], float(alpha), C.byref(o), C.byref(ne)))
+    return ne.value
+
+
+def fds_op_filter_basis(op: Op) -> torch.Tensor:
+    p = C.c_void_p()
+    _check(lib().fds_op_filter_basis(op.handle, C.byref(p)))
+    n, ne, _ = op.info()
+    return _view(p.value, (ne, n), torch.float64, op)
+
+
+def fds_compress(op: Op, rank_cap: int, oversample: int = 10, power_iters: int = 2,
+                 tol: float = 0.0, seed: int = 0, precision: int = FDS_FP64) -> int:
+    o = fds_compress_opts(int(rank_cap), int(oversample), int(power_iters), int(precision),
+                          float(tol), C.c_uint64(seed & ((1 << 64) - 1)))
+    r = C.c_int32()
+    _check(lib().fds_compress(op.handle, C.byref(o), C.byref(r)))
+    return r.value
+
+
+def fds_op_factors(op: Op):
+    u, w, r = C.c_void_p(), C.c_void_p(), C.c_int32()
+    _check(lib().fds_op_factors(op.handle, C.byref(u), C.byref(w), C.byref(r)))
+    n = op.n
+    return (_view(u.value, (r.value, n), torch.complex128, op),
+            _view(w.value, (r.value, n), torch.complex128, op))
+
+
+def fds_factor(op: Op):
+    _check(lib().fds_factor(op.handle))
+
+
+def fds_rhs_planewave(op: Op, angles: torch.Tensor, amps: torch.Tensor):
+    n = op.n
+    nrhs = angles.numel()
+    angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
+    amps = amps.to(device="cuda", dtype=torch.complex128).contiguous()
+    f = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
+    h = torch.empty_like(f)
+    _check(lib().fds_rhs_planewave(op.handle, _ptr(angles), _ptr(amps), nrhs, _ptr(f), _ptr(h)))
+    return f, h
+
+
+def fds_solve(op: Op, f: torch.Tensor | None, h: torch.Tensor | None, max_iters: int = 4,
+              tol: float = 1e-12, want_y: bool = False, stats: bool = True):
+    ref = f if f is not None else h
+    nrhs = ref.shape[0]
+    j = torch.empty((nrhs, op.n), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(j) if want_y else None
+    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol))
+    st = fds_solve_stats()
+    _check(lib().fds_solve(op.handle, _ptr(f), _ptr(h), nrhs, _ptr(j), _ptr(y), C.byref(o),
+                           C.byref(st) if stats else None))
+    hist = list(st.history[: st.iters + 1]) if stats else []
+    return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
+                  "history": hist}

@@ -1,0 +1,302 @@
+// C ABI of libfds: argument checking, the pipeline state machine, device
+// memory ownership and error reporting. All numerical work is in the kernels
+// of the other translation units; this file only orchestrates them on the
+// context's stream.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fds_internal.h"
+#include "hankel.h"
+
+namespace fds {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void* Ctx::dmalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (has_alloc) {
+        p = alloc.alloc(bytes, (void*)stream, alloc.user);
+        if (!p) throw Error{FDS_ERR_ALLOC, "allocator callback returned NULL"};
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{FDS_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    return p;
+}
+
+void Ctx::dfree(void* p) {
+    if (!p) return;
+    if (has_alloc) {
+        alloc.release(p, (void*)stream, alloc.user);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+Op::~Op() {
+    if (!ctx) return;
+    void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D,
+                    Vn, Vg, Bt, gfac, U, W, K, piv};
+    for (void* p : ptrs) ctx->dfree(p);
+}
+
+template <typename F>
+static fds_status guarded(F&& f) {
+    try {
+        f();
+        return FDS_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return FDS_ERR_ALLOC;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FDS_ERR_HIP;
+    }
+}
+
+static void require_stage(const Op& op, Stage s, const char* what) {
+    if ((int)op.stage < (int)s)
+        throw Error{FDS_ERR_STATE, std::string(what) + " called before the required pipeline stage"};
+}
+
+}  // namespace fds
+
+using namespace fds;
+
+extern "C" {
+
+const char* fds_last_error(void) { return g_last_error.c_str(); }
+
+fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* alloc, fds_ctx* out) {
+    return guarded([&] {
+        FDS_REQUIRE(out != nullptr, FDS_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        FDS_HIP_TRY(hipGetDeviceCount(&count));
+        FDS_REQUIRE(device >= 0 && device < count, FDS_ERR_ARG, "device index out of range");
+        FDS_HIP_TRY(hipSetDevice(device));
+        auto* c = new fds_ctx_s();
+        Ctx& x = c->impl;
+        x.device = device;
+        x.stream = (hipStream_t)hip_stream;
+        if (alloc && alloc->alloc && alloc->release) {
+            x.alloc = *alloc;
+            x.has_alloc = true;
+        }
+        try {
+            x.hk_tab = (double*)x.dmalloc(sizeof(double) * HK_TAB_DOUBLES);
+            FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab, &HK_TAB[0][0][0], sizeof(double) * HK_TAB_DOUBLES,
+                                       hipMemcpyHostToDevice, x.stream));
+            double g[64];
+            gauss_legendre_01(32, g, g + 32);
+            x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);
+            FDS_HIP_TRY(hipMemcpyAsync(x.gl32, g, sizeof(g), hipMemcpyHostToDevice, x.stream));
+            FDS_HIP_TRY(hipStreamSynchronize(x.stream));
+        } catch (...) {
+            x.dfree(x.hk_tab);
+            x.dfree(x.gl32);
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+fds_status fds_ctx_destroy(fds_ctx ctx) {
+    return guarded([&] {
+        if (!ctx) return;
+        (void)hipStreamSynchronize(ctx->impl.stream);
+        ctx->impl.dfree(ctx->impl.hk_tab);
+        ctx->impl.dfree(ctx->impl.gl32);
+        delete ctx;
+    });
+}
+
+fds_status fds_sync(fds_ctx ctx) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx != nullptr, FDS_ERR_ARG, "ctx is NULL");
+        FDS_HIP_TRY(hipStreamSynchronize(ctx->impl.stream));
+        FDS_HIP_TRY(hipGetLastError());
+    });
+}
+
+fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && x && out && n >= 0, FDS_ERR_ARG, "bad argument");
+        if (n == 0) return;
+        launch_hankel_eval(ctx->impl, x, n, out);
+    });
+}
+
+fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n, double* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && R && out && n >= 0, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(std::isfinite(k) && k > 0.0, FDS_ERR_ARG, "k must be finite and > 0");
+        if (n == 0) return;
+        launch_kernel_eval(ctx->impl, k, R, n, out);
+    });
+}
+
+fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
+                        const fds_asm_opts* opts, fds_op* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && nodes && out, FDS_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        FDS_REQUIRE(n >= 8 && n <= (int64_t)1 << 20, FDS_ERR_ARG, "n must be in [8, 2^20]");
+        FDS_REQUIRE(std::isfinite(k) && k > 0.0, FDS_ERR_ARG, "k must be finite and > 0");
+        if (opts) {
+            FDS_REQUIRE(opts->nquad == 0 || opts->nquad == 8, FDS_ERR_NOTIMPL,
+                        "only the 8-point rule is implemented");
+            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL,
+                        "only FP64 assembly is implemented");
+        }
+        Ctx& c = ctx->impl;
+        // host-side geometry validation (O(n) copy)
+        std::vector<double> hn(2 * n);
+        FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                                   c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        double area = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t j = (i + 1) % n;
+            const double x0 = hn[2 * i], y0 = hn[2 * i + 1], x1 = hn[2 * j], y1 = hn[2 * j + 1];
+            FDS_REQUIRE(std::isfinite(x0) && std::isfinite(y0), FDS_ERR_ARG, "non-finite node");
+            FDS_REQUIRE(std::hypot(x1 - x0, y1 - y0) > 0.0, FDS_ERR_ARG, "zero-length panel");
+            area += x0 * y1 - x1 * y0;
+        }
+        FDS_REQUIRE(area > 0.0, FDS_ERR_ARG, "nodes must be counter-clockwise");
+
+        auto* o = new fds_op_s();
+        Op& op = o->impl;
+        op.ctx = &c;
+        op.n = n;
+        op.k = k;
+        try {
+            const size_t nd = sizeof(double) * n;
+            op.nodes = (double*)c.dmalloc(2 * nd);
+            op.h = (double*)c.dmalloc(nd);
+            op.nx = (double*)c.dmalloc(nd);
+            op.ny = (double*)c.dmalloc(nd);
+            op.gx = (double*)c.dmalloc(8 * nd);
+            op.gy = (double*)c.dmalloc(8 * nd);
+            op.g_diag = (double*)c.dmalloc(nd);
+            op.g_off = (double*)c.dmalloc(nd);
+            op.l_diag = (double*)c.dmalloc(nd);
+            op.l_off = (double*)c.dmalloc(nd);
+            const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
+            op.S = (double2*)c.dmalloc(mat);
+            op.Nm = (double2*)c.dmalloc(mat);
+            op.D = (double2*)c.dmalloc(mat);
+            FDS_HIP_TRY(hipMemcpyAsync(op.nodes, nodes, 2 * nd, hipMemcpyDeviceToDevice, c.stream));
+            gauss_legendre_01(8, op.rule.xi, op.rule.w);
+            launch_geometry(op);
+            launch_assemble(op);
+            op.stage = Stage::Assembled;
+        } catch (...) {
+            delete o;
+            throw;
+        }
+        *out = o;
+    });
+}
+
+fds_status fds_op_destroy(fds_op op) {
+    return guarded([&] {
+        if (!op) return;
+        (void)hipStreamSynchronize(op->impl.ctx->stream);
+        delete op;
+    });
+}
+
+fds_status fds_op_info(fds_op op, int64_t* n, int32_t* n_eff, int32_t* rank) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        if (n) *n = op->impl.n;
+        if (n_eff) *n_eff = op->impl.n_eff;
+        if (rank) *rank = op->impl.rank;
+    });
+}
+
+fds_status fds_op_matrices(fds_op op, void** S, void** Nmat, void** D) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        if (S) *S = op->impl.S;
+        if (Nmat) *Nmat = op->impl.Nm;
+        if (D) *D = op->impl.D;
+    });
+}
+
+fds_status fds_op_sparse(fds_op op, const double** g_diag, const double** g_off,
+                         const double** l_diag, const double** l_off) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        if (g_diag) *g_diag = op->impl.g_diag;
+        if (g_off) *g_off = op->impl.g_off;
+        if (l_diag) *l_diag = op->impl.l_diag;
+        if (l_off) *l_off = op->impl.l_off;
+    });
+}
+
+fds_status fds_rhs_planewave(fds_op op, const double* angles, const void* amps, int64_t nrhs,
+                             void* f_out, void* h_out) {
+    return guarded([&] {
+        FDS_REQUIRE(op && angles && amps && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Assembled, "fds_rhs_planewave");
+        if (nrhs == 0 || (!f_out && !h_out)) return;
+        launch_rhs_planewave(op->impl, angles, (const double2*)amps, nrhs, (double2*)f_out,
+                             (double2*)h_out);
+    });
+}
+
+fds_status fds_apply_gram(fds_op op, int32_t p, void* X, int64_t ncols) {
+    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_apply_gram not built yet"}; });
+}
+
+fds_status fds_filter(fds_op op, fds_form form, double alpha, const fds_filter_opts* opts,
+                      int32_t* n_eff) {
+    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_filter not built yet"}; });
+}
+
+fds_status fds_op_filter_basis(fds_op op, const double** Vn) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        require_stage(op->impl, Stage::Filtered, "fds_op_filter_basis");
+        if (Vn) *Vn = op->impl.Vn;
+    });
+}
+
+fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out) {
+    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_compress not built yet"}; });
+}
+
+fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* rank) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        require_stage(op->impl, Stage::Compressed, "fds_op_factors");
+        if (U) *U = op->impl.U;
+        if (W) *W = op->impl.W;
+        if (rank) *rank = op->impl.rank;
+    });
+}
+
+fds_status fds_factor(fds_op op) {
+    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_factor not built yet"}; });
+}
+
+fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs, void* j_out,
+                     void* y_out, const fds_solve_opts* opts, fds_solve_stats* stats) {
+    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_solve not built yet"}; });
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Dense Galerkin assembly of S, N (Maue form) and D (paper, Notation and
+// Background: [S]_ij = <phi_i, S phi_j>, [N]_ij = <phi_i, N phi_j>,
+// [D]_ij = <phi_i, D phi_j>, g2 = (i/4) H0^(1)(kR)).
+//
+// For a panel pair (p, q) with x on p and y on q the 2x2 local blocks are
+//   S_ab  = int_p int_q psi_a(x) psi_b(y) g,      I0 = sum_ab S_ab,
+//   N_ab  = s_a s_b I0/(h_p h_q) - k^2 (n_p.n_q) S_ab,   s_0 = -1, s_1 = +1,
+//   D_ab  = int_p int_q psi_a psi_b dg/dn_y,
+// and entry (i, j) sums the blocks of the four pairs (p, q) in
+// {i-1, i} x {j-1, j} (panel p carries psi_0 of node p, psi_1 of node p+1).
+//
+// Far pairs (|p - q| >= 2 mod n): 8 x 8 tensor Gauss rule.
+//   One wavefront owns a 63 x 63 output tile: its 64 lanes hold the 64
+//   column panels j0-1 .. j0+62 (Gauss points in registers); the wave walks
+//   the row panels (wave-uniform, scalar loads), and for each row forms the
+//   column entries from its own psi_1 part plus the psi_0 part of the next
+//   lane (one cross-lane shuffle). S and N are symmetric and D(j,i) uses the
+//   same Hankel values, so a tile above the diagonal also writes its mirror
+//   tile: every Hankel evaluation serves S, N, D and D^T.
+// Near pairs (self, adjacent): logarithmic parts integrated exactly (closed
+//   form on a self pair, Duffy's corner split on adjacent pairs), smooth
+//   remainders with the same 8 x 8 rule; the S and N bands |i - j| <= 2 are
+//   then symmetrised.
+#include "fds_internal.h"
+#include "hankel.h"
+
+namespace fds {
+
+constexpr int TB = 63;          // output columns (= rows) per tile
+constexpr int WAVES = 4;        // wavefronts per workgroup
+
+struct W8 {
+    double wp0[8];   // w_b psi_0(xi_b)
+    double wp1[8];   // w_b psi_1(xi_b)
+};
+
+struct FarParams {
+    const double* __restrict__ gx;
+    const double* __restrict__ gy;
+    const double* __restrict__ h;
+    const double* __restrict__ nx;
+    const double* __restrict__ ny;
+    const double* __restrict__ tab;
+    double2* __restrict__ S;
+    double2* __restrict__ Nm;
+    double2* __restrict__ D;
+    double k;
+    int n;
+    int nsub;
+    int tr;
+    int64_t nwork;
+};
+
+__device__ __forceinline__ double2 fma_cr(double s, double2 a, double2 acc) {
+    return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+
+__device__ __forceinline__ double2 shfl_down1(double2 v) {
+    return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+
+__global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 wt) {
+    __shared__ __attribute__((aligned(16))) double tab[HK_TAB_DOUBLES];
+    __shared__ double wsh[16];          // w_b psi_0(xi_b), w_b psi_1(xi_b)
+    for (int t = threadIdx.x; t < HK_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
+    if (threadIdx.x < 8) {
+        wsh[threadIdx.x] = wt.wp0[threadIdx.x];
+        wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int64_t work = (int64_t)blockIdx.x * WAVES +
+                         __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (work >= P.nwork) return;
+    const int64_t tile = work / P.nsub;
+    const int sub = (int)(work - tile * P.nsub);
+    int J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((int64_t)J * (J + 1) / 2 > tile) --J;
+    while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
+    const int I = (int)(tile - (int64_t)J * (J + 1) / 2);
+    const int n = P.n;
+    const int i0 = I * TB + sub * P.tr;
+    const int i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), n);
+    if (i0 >= i1) return;
+    const int j0 = J * TB;
+    const bool mirror = (I != J);
+
+    const int qraw = j0 - 1 + lane;
+    const bool qvalid = qraw < n;
+    const int q = qraw < 0 ? n - 1 : (qvalid ? qraw : 0);
+    const int col = j0 + lane;
+    const bool writes = (lane < TB) && (col < n);
+
+    const double* __restrict__ qgx = P.gx + 8 * q;
+    const double* __restrict__ qgy = P.gy + 8 * q;
+    const double hq = P.h[q], nxq = P.nx[q], nyq = P.ny[q];
+    const double k = P.k;
+
+    const double2 z = make_double2(0.0, 0.0);
+    double2 pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
+
+    for (int pr = i0 - 1; pr < i1; ++pr) {
+        const int p = pr < 0 ? pr + n : pr;
+        int dd = p - q;
+        dd = dd < 0 ? -dd : dd;
+        const bool active = qvalid && dd > 1 && dd < n - 1;
+        double2 S00 = z, S01 = z, S10 = z, S11 = z;
+        double2 D00 = z, D01 = z, D10 = z, D11 = z;
+        double2 T00 = z, T01 = z, T10 = z, T11 = z;
+        const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
+        if (active) {
+#pragma unroll 1
+            for (int a = 0; a < 8; ++a) {
+                const double xa = P.gx[8 * p + a], ya = P.gy[8 * p + a];
+                double2 Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z;
+#pragma unroll 1
+                for (int b = 0; b < 8; ++b) {
+                    const double dx = xa - qgx[b], dy = ya - qgy[b];
+                    const double R = sqrt(fma(dx, dx, dy * dy));
+                    const Bessel01 bs = hk_eval_hot(k * R, tab);
+                    const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
+                    const double kr = 0.25 * k / R;
+                    const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
+                    const double dq = fma(dx, nxq, dy * nyq);
+                    const double dp = -fma(dx, nxp, dy * nyp);
+                    const double2 cd = cscale(c, dq), ct = cscale(c, dp);
+                    const double w0 = wsh[b], w1 = wsh[8 + b];
+                    Sg0 = fma_cr(w0, g, Sg0);
+                    Sg1 = fma_cr(w1, g, Sg1);
+                    Dg0 = fma_cr(w0, cd, Dg0);
+                    Dg1 = fma_cr(w1, cd, Dg1);
+                    Tg0 = fma_cr(w0, ct, Tg0);
+                    Tg1 = fma_cr(w1, ct, Tg1);
+                }
+                const double wa0 = wsh[a], wa1 = wsh[8 + a];
+                S00 = fma_cr(wa0, Sg0, S00); S01 = fma_cr(wa0, Sg1, S01);
+                S10 = fma_cr(wa1, Sg0, S10); S11 = fma_cr(wa1, Sg1, S11);
+                D00 = fma_cr(wa0, Dg0, D00); D01 = fma_cr(wa0, Dg1, D01);
+                D10 = fma_cr(wa1, Dg0, D10); D11 = fma_cr(wa1, Dg1, D11);
+                T00 = fma_cr(wa0, Tg0, T00); T01 = fma_cr(wa0, Tg1, T01);
+                T10 = fma_cr(wa1, Tg0, T10); T11 = fma_cr(wa1, Tg1, T11);
+            }
+            const double hh = hp * hq;
+            S00 = cscale(S00, hh); S01 = cscale(S01, hh); S10 = cscale(S10, hh); S11 = cscale(S11, hh);
+            D00 = cscale(D00, hh); D01 = cscale(D01, hh); D10 = cscale(D10, hh); D11 = cscale(D11, hh);
+            T00 = cscale(T00, hh); T01 = cscale(T01, hh); T10 = cscale(T10, hh); T11 = cscale(T11, hh);
+        }
+        // Maue form of N from S: N_ab = s_a s_b I0/(hp hq) - k^2 (np.nq) S_ab
+        const double2 I0 = cadd(cadd(S00, S01), cadd(S10, S11));
+        const double2 I0h = cscale(I0, 1.0 / (hp * hq));
+        const double kk = -k * k * fma(nxp, nxq, nyp * nyq);
+        const double2 N00 = cadd(I0h, cscale(S00, kk));
+        const double2 N01 = csub(cscale(S01, kk), I0h);
+        const double2 N10 = csub(cscale(S10, kk), I0h);
+        const double2 N11 = cadd(I0h, cscale(S11, kk));
+
+        if (pr >= i0) {
+            const int i = pr;
+            // row i receives psi_0 of the current row panel and psi_1 of the previous one
+            const double2 rS0 = cadd(S00, pS0), rS1 = cadd(S01, pS1);
+            const double2 rN0 = cadd(N00, pN0), rN1 = cadd(N01, pN1);
+            const double2 rD0 = cadd(D00, pD0), rD1 = cadd(D01, pD1);
+            const double2 rT0 = cadd(T00, pT0), rT1 = cadd(T01, pT1);
+            const double2 nS = shfl_down1(rS0), nN = shfl_down1(rN0);
+            const double2 nD = shfl_down1(rD0), nT = shfl_down1(rT0);
+            if (writes) {
+                const double2 vS = cadd(rS1, nS), vN = cadd(rN1, nN);
+                const double2 vD = cadd(rD1, nD), vT = cadd(rT1, nT);
+                const int64_t rc = (int64_t)i * n + col;
+                P.S[rc] = vS;
+                P.Nm[rc] = vN;
+                P.D[rc] = vD;
+                if (mirror) {
+                    const int64_t cr = (int64_t)col * n + i;
+                    P.S[cr] = vS;
+                    P.Nm[cr] = vN;
+                    P.D[cr] = vT;
+                }
+            }
+        }
+        pS0 = S10; pS1 = S11; pN0 = N10; pN1 = N11;
+        pD0 = D10; pD1 = D11; pT0 = T10; pT1 = T11;
+    }
+}
+
+// ----------------------------------------------------------------- near pairs
+struct NearParams {
+    const double* __restrict__ gx;
+    const double* __restrict__ gy;
+    const double* __restrict__ h;
+    const double* __restrict__ nx;
+    const double* __restrict__ ny;
+    const double* __restrict__ tab;
+    const double* __restrict__ gl32;   // x[32], w[32] on [0,1]
+    double2* __restrict__ nb;          // [n][3][8]: S00 S01 S10 S11 D00 D01 D10 D11
+    double k;
+    int n;
+};
+
+// Linear shape functions of a panel as c0 + c1 s, s = fraction of length from
+// the shared node; `end` = the shared node is the panel's end (xi = 1).
+__device__ __forceinline__ void corner_lin(bool end, int al, double& c0, double& c1) {
+    if (end) {   // psi_0 = s, psi_1 = 1 - s
+        c0 = al == 0 ? 0.0 : 1.0;
+        c1 = al == 0 ? 1.0 : -1.0;
+    } else {     // psi_0 = 1 - s, psi_1 = s
+        c0 = al == 0 ? 1.0 : 0.0;
+        c1 = al == 0 ? -1.0 : 1.0;
+    }
+}
+
+__global__ void asm_near_block_kernel(NearParams P, W8 wt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n;
+    if (t >= 3 * n) return;
+    const int p = t / 3, s = t - 3 * (t / 3);
+    const int q = s == 0 ? (p == 0 ? n - 1 : p - 1) : (s == 1 ? p : (p + 1 == n ? 0 : p + 1));
+    const double k = P.k;
+    const double hp = P.h[p], hq = P.h[q];
+    const double nxp = P.nx[p], nyp = P.ny[p], nxq = P.nx[q], nyq = P.ny[q];
+    double2 Sr[2][2], Dr[2][2];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            Sr[a2][b2] = make_double2(0.0, 0.0);
+            Dr[a2][b2] = make_double2(0.0, 0.0);
+        }
+    for (int a = 0; a < 8; ++a) {
+        const double xa = P.gx[8 * p + a], ya = P.gy[8 * p + a];
+        for (int b = 0; b < 8; ++b) {
+            const double dx = xa - P.gx[8 * q + b], dy = ya - P.gy[8 * q + b];
+            const double R = sqrt(fma(dx, dx, dy * dy));
+            const double2 g = green_reg(k, R, P.tab);
+            const double wa[2] = {wt.wp0[a], wt.wp1[a]};
+            const double wb[2] = {wt.wp0[b], wt.wp1[b]};
+            double2 rem = make_double2(0.0, 0.0);
+            if (s != 1) {
+                const double2 r0 = dlayer_rem(k, R, P.tab);
+                const double dn = fma(dx, nxq, dy * nyq) / R;
+                rem = cscale(r0, dn);
+            }
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    Sr[a2][b2] = fma_cr(wa[a2] * wb[b2], g, Sr[a2][b2]);
+                    Dr[a2][b2] = fma_cr(wa[a2] * wb[b2], rem, Dr[a2][b2]);
+                }
+        }
+    }
+    const double hh = hp * hq;
+    double Lg[2][2], Dl[2][2];
+    if (s == 1) {
+        // int int psi_a psi_b log|x - y| = h^2 (log(h)/4 + J_ab), J_00 = J_11 = -7/16, J_01 = -5/16
+        const double lh = 0.25 * log(hp);
+        Lg[0][0] = Lg[1][1] = hp * hp * (lh - 7.0 / 16.0);
+        Lg[0][1] = Lg[1][0] = hp * hp * (lh - 5.0 / 16.0);
+        Dl[0][0] = Dl[0][1] = Dl[1][0] = Dl[1][1] = 0.0;
+    } else {
+        // directions from the shared node: tau = (-ny, nx)
+        const double tpx = -nyp, tpy = nxp, tqx = -nyq, tqy = nxq;
+        const bool end_x = (s == 2);   // q = p+1: shared node is the end of p, start of q
+        const double ax = end_x ? -tpx : tpx, ay = end_x ? -tpy : tpy;
+        const double bx = end_x ? tqx : -tqx, by = end_x ? tqy : -tqy;
+        const double ab = ax * bx + ay * by;
+        const double anq = ax * nxq + ay * nyq;
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) {
+                Lg[a2][b2] = 0.0;
+                Dl[a2][b2] = 0.0;
+            }
+        for (int it = 0; it < 32; ++it) {
+            const double tt = P.gl32[it], wtt = P.gl32[32 + it];
+            const double f1 = hp * hp + hq * hq * tt * tt - 2.0 * hp * hq * tt * ab;
+            const double f2 = hp * hp * tt * tt + hq * hq - 2.0 * hp * hq * tt * ab;
+            const double lf1 = 0.5 * log(f1), lf2 = 0.5 * log(f2);
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+                double a0, a1;
+                corner_lin(end_x, a2, a0, a1);
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    double b0, b1;
+                    corner_lin(!end_x, b2, b0, b1);
+                    const double c10 = a0 * b0, c11 = a1 * b0 + a0 * b1 * tt, c12 = a1 * b1 * tt;
+                    const double c20 = a0 * b0, c21 = a1 * b0 * tt + a0 * b1, c22 = a1 * b1 * tt;
+                    // int_0^1 rho^(m+1)(log rho + log f) = -1/(m+2)^2 + log f/(m+2)
+                    const double g1 = c10 * (-0.25 + 0.5 * lf1) + c11 * (-1.0 / 9.0 + lf1 / 3.0) +
+                                      c12 * (-1.0 / 16.0 + 0.25 * lf1);
+                    const double g2 = c20 * (-0.25 + 0.5 * lf2) + c21 * (-1.0 / 9.0 + lf2 / 3.0) +
+                                      c22 * (-1.0 / 16.0 + 0.25 * lf2);
+                    Lg[a2][b2] += wtt * (g1 + g2);
+                    const double d1 = (c10 + 0.5 * c11 + c12 / 3.0) * (hp * anq / f1);
+                    const double d2 = (c20 + 0.5 * c21 + c22 / 3.0) * (hp * anq * tt / f2);
+                    Dl[a2][b2] += wtt * (d1 + d2);
+                }
+            }
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) {
+                Lg[a2][b2] *= hh;
+                Dl[a2][b2] *= hh * kInv2Pi;
+            }
+    }
+    double2* out = P.nb + (int64_t)t * 8;
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            const double2 sv = cscale(Sr[a2][b2], hh);
+            out[2 * a2 + b2] = make_double2(sv.x - kInv2Pi * Lg[a2][b2], sv.y);
+            const double2 dv = cscale(Dr[a2][b2], hh);
+            out[4 + 2 * a2 + b2] = make_double2(dv.x + Dl[a2][b2], dv.y);
+        }
+}
+
+struct BandParams {
+    const double* __restrict__ h;
+    const double* __restrict__ nx;
+    const double* __restrict__ ny;
+    const double2* __restrict__ nb;
+    double2* __restrict__ S;
+    double2* __restrict__ Nm;
+    double2* __restrict__ D;
+    double k;
+    int n;
+};
+
+// Near-pair contribution to entry (r, c): pairs (p, q) = (r - a, c - b).
+__device__ void near_entry(const BandParams& P, int r, int c, double2& s, double2& nn, double2& d) {
+    const int n = P.n;
+    s = nn = d = make_double2(0.0, 0.0);
+    for (int a = 0; a < 2; ++a) {
+        const int p = (r - a + n) % n;
+        for (int b = 0; b < 2; ++b) {
+            const int q = (c - b + n) % n;
+            int slot = -1;
+            if (q == p) slot = 1;
+            else if (q == (p + 1) % n) slot = 2;
+            else if (q == (p + n - 1) % n) slot = 0;
+            if (slot < 0) continue;
+            const double2* blk = P.nb + ((int64_t)p * 3 + slot) * 8;
+            const double2 I0 = cadd(cadd(blk[0], blk[1]), cadd(blk[2], blk[3]));
+            const double hh = P.h[p] * P.h[q];
+            const double kk = -P.k * P.k * (P.nx[p] * P.nx[q] + P.ny[p] * P.ny[q]);
+            const double sg = (a == b) ? 1.0 : -1.0;
+            const double2 sab = blk[2 * a + b];
+            s = cadd(s, sab);
+            nn = cadd(nn, cadd(cscale(I0, sg / hh), cscale(sab, kk)));
+            d = cadd(d, blk[4 + 2 * a + b]);
+        }
+    }
+}
+
+__global__ void asm_band_kernel(BandParams P) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n;
+    if (t >= 3 * n) return;
+    const int i = t / 3, dlt = t - 3 * (t / 3);
+    const int j = (i + dlt) % n;
+    double2 s1, n1, d1;
+    near_entry(P, i, j, s1, n1, d1);
+    const int64_t ij = (int64_t)i * n + j, ji = (int64_t)j * n + i;
+    if (dlt == 0) {
+        P.S[ij] = cadd(P.S[ij], s1);
+        P.Nm[ij] = cadd(P.Nm[ij], n1);
+        P.D[ij] = cadd(P.D[ij], d1);
+        return;
+    }
+    double2 s2, n2, d2;
+    near_entry(P, j, i, s2, n2, d2);
+    const double2 sa = cscale(cadd(cadd(P.S[ij], s1), cadd(P.S[ji], s2)), 0.5);
+    const double2 na = cscale(cadd(cadd(P.Nm[ij], n1), cadd(P.Nm[ji], n2)), 0.5);
+    P.S[ij] = sa;
+    P.S[ji] = sa;
+    P.Nm[ij] = na;
+    P.Nm[ji] = na;
+    P.D[ij] = cadd(P.D[ij], d1);
+    P.D[ji] = cadd(P.D[ji], d2);
+}
+
+void launch_assemble(Op& op) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    W8 wt;
+    for (int a = 0; a < 8; ++a) {
+        wt.wp0[a] = op.rule.w[a] * (1.0 - op.rule.xi[a]);
+        wt.wp1[a] = op.rule.w[a] * op.rule.xi[a];
+    }
+    FarParams fp;
+    fp.gx = op.gx; fp.gy = op.gy; fp.h = op.h; fp.nx = op.nx; fp.ny = op.ny;
+    fp.tab = c.hk_tab; fp.S = op.S; fp.Nm = op.Nm; fp.D = op.D; fp.k = op.k; fp.n = n;
+    const int64_t T = (n + TB - 1) / TB;
+    fp.nsub = 2;
+    fp.tr = (TB + fp.nsub - 1) / fp.nsub;
+    fp.nwork = T * (T + 1) / 2 * fp.nsub;
+    const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
+    hipLaunchKernelGGL(asm_far_kernel, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt);
+    FDS_HIP_TRY(hipGetLastError());
+
+    double2* nb = static_cast<double2*>(c.dmalloc(sizeof(double2) * 24 * (size_t)n));
+    NearParams np;
+    np.gx = op.gx; np.gy = op.gy; np.h = op.h; np.nx = op.nx; np.ny = op.ny;
+    np.tab = c.hk_tab; np.gl32 = c.gl32; np.nb = nb; np.k = op.k; np.n = n;
+    hipLaunchKernelGGL(asm_near_block_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream,
+                       np, wt);
+    FDS_HIP_TRY(hipGetLastError());
+    BandParams bp;
+    bp.h = op.h; bp.nx = op.nx; bp.ny = op.ny; bp.nb = nb;
+    bp.S = op.S; bp.Nm = op.Nm; bp.D = op.D; bp.k = op.k; bp.n = n;
+    hipLaunchKernelGGL(asm_band_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(nb);   // stream-ordered release (see Ctx::dfree)
+}
+
+}  // namespace fds

@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP translation units of libfds.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/fds.h"
+
+namespace fds {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    fds_status code;
+    std::string msg;
+};
+
+void set_error(const std::string& msg);
+
+#define FDS_HIP_TRY(expr)                                                         \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess)                                                     \
+            throw ::fds::Error{FDS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define FDS_REQUIRE(cond, code, text)                                             \
+    do {                                                                          \
+        if (!(cond)) throw ::fds::Error{code, text};                              \
+    } while (0)
+
+// ------------------------------------------------------------------ complex
+__host__ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// ------------------------------------------------------------------ context / operator
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fds_allocator alloc{};
+    bool has_alloc = false;
+    double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
+    double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
+    void* dmalloc(size_t bytes);
+    void dfree(void* p);
+};
+
+enum class Stage : int { Assembled = 1, Filtered = 2, Compressed = 3, Factored = 4 };
+
+struct GaussRule8 {
+    double xi[8];
+    double w[8];
+};
+
+struct Op {
+    Ctx* ctx = nullptr;
+    int64_t n = 0;
+    double k = 0.0;
+    Stage stage = Stage::Assembled;
+    // geometry (device)
+    double* nodes = nullptr;      // [n][2]
+    double* h = nullptr;          // [n]
+    double* nx = nullptr;         // [n]
+    double* ny = nullptr;         // [n]
+    double* gx = nullptr;         // [n][8]
+    double* gy = nullptr;         // [n][8]
+    double* g_diag = nullptr;     // Gram diag / off
+    double* g_off = nullptr;
+    double* l_diag = nullptr;     // Laplacian diag / off
+    double* l_off = nullptr;
+    GaussRule8 rule{};
+    // dense operators (device, row-major complex128)
+    double2* S = nullptr;
+    double2* Nm = nullptr;
+    double2* D = nullptr;
+    // filter / compact part
+    int form = 0;
+    double alpha = 1.0;
+    double beta = 0.25;
+    int32_t n_eff = 0;
+    double* Vn = nullptr;         // [n_eff][n]  orthonormal eigenvectors of G^-1/2 L G^-1/2
+    double* Vg = nullptr;         // [n_eff][n]  G^-1/2 Vn (G-orthonormal generalised eigenvectors)
+    double2* Bt = nullptr;        // [n_eff][n]  (V_n^T C)^T : row j of B is vector j
+    // Gram power workspace: periodic tridiagonal factorisation of G
+    double* gfac = nullptr;       // [4n]
+    double cheb_lo = 0.0, cheb_hi = 0.0;
+    // skeleton and Woodbury core
+    int32_t rank = 0;
+    double2* U = nullptr;         // [rank][n]
+    double2* W = nullptr;         // [rank][n] row-major (row j = W_j,:)
+    double2* K = nullptr;         // [rank][rank] LU factors (column-major)
+    int32_t* piv = nullptr;       // [rank]
+    ~Op();
+};
+
+// ------------------------------------------------------------------ launchers
+// geometry.hip
+void launch_geometry(Op& op);
+void launch_rhs_planewave(Op& op, const double* angles, const double2* amps, int64_t nrhs,
+                          double2* f, double2* h);
+void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out);
+void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
+// assemble.hip
+void launch_assemble(Op& op);
+// gauss rules (host)
+void gauss_legendre_01(int n, double* x, double* w);
+
+}  // namespace fds
+
+struct fds_ctx_s {
+    fds::Ctx impl;
+};
+struct fds_op_s {
+    fds::Op impl;
+};

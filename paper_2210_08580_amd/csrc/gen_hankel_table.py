@@ -1,0 +1,190 @@
+"""Generate hankel_table.inc: coefficients of the device Bessel evaluator.
+
+Three regions of the real argument x > 0 (J0, Y0, J1, Y1):
+  x < XS   ascending series (Abramowitz & Stegun 9.1.10, 9.1.11, 9.1.13):
+             J0 = sum (-1)^m q^m/(m!)^2,                   q = x^2/4
+             Y0 = (2/pi)(log(x/2) + gamma) J0 + (2/pi) sum_{m>=1} (-1)^{m+1} H_m q^m/(m!)^2
+             J1 = (x/2) sum (-1)^m q^m/(m!(m+1)!)
+             Y1 = -2/(pi x) + (2/pi) log(x/2) J1
+                  - (x/(2 pi)) sum (-1)^m (psi(m+1) + psi(m+2)) q^m/(m!(m+1)!)
+  XS <= x < XA  piecewise polynomials on unit intervals [c, c+1): each function is
+           interpolated at Chebyshev points (50-digit mpmath values) and stored in
+           the monomial basis of t = x - (c + 1/2); evaluated by Horner.
+  x >= XA  Hankel's asymptotic expansion (A&S 9.2.5-9.2.10):
+             H_nu^(1)(x) = sqrt(2/(pi x)) (P + i Q) exp(i (x - (nu/2 + 1/4) pi)),
+             P = sum_k (-1)^k a_2k(nu) x^-2k,  Q = sum_k (-1)^k a_{2k+1}(nu) x^-(2k+1),
+             a_k(nu) = prod_{j=1..k} (4 nu^2 - (2j-1)^2) / (k! 8^k).
+The script checks a float64 emulation of the device formulas against mpmath and
+refuses to write the table unless every region is within 4e-16 max(|f|, 1).
+
+Run:  python gen_hankel_table.py   (writes hankel_table.inc next to this file)
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 50
+XS, XA = 2, 25
+DEG = 21
+NSER = 16
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def series_coeffs():
+    cj0, cy0, cj1, cy1 = [], [], [], []
+    H = mp.mpf(0)
+    for m in range(NSER):
+        f2 = mp.factorial(m) ** 2
+        f11 = mp.factorial(m) * mp.factorial(m + 1)
+        if m >= 1:
+            H += mp.mpf(1) / m
+        cj0.append((-1) ** m / f2)
+        cy0.append(((-1) ** (m + 1)) * H / f2 if m >= 1 else mp.mpf(0))
+        cj1.append((-1) ** m / f11)
+        cy1.append((-1) ** m * (mp.digamma(m + 1) + mp.digamma(m + 2)) / f11)
+    return cj0, cy0, cj1, cy1
+
+
+def asym_coeffs(nu, nterms):
+    a = [mp.mpf(1)]
+    for k in range(1, 2 * nterms + 2):
+        a.append(a[-1] * (4 * nu * nu - (2 * k - 1) ** 2) / (k * 8))
+    P = [(-1) ** k * a[2 * k] for k in range(nterms)]
+    Q = [(-1) ** k * a[2 * k + 1] for k in range(nterms)]
+    return P, Q, a
+
+
+def asym_terms_needed(x0, tol=2e-18):
+    _, _, a = asym_coeffs(1, 40)
+    _, _, a0 = asym_coeffs(0, 40)
+    for n in range(2, 40):
+        # first neglected terms of P and Q bound the remainders
+        nxt = max(abs(a[2 * n]), abs(a[2 * n + 1]) / x0, abs(a0[2 * n]), abs(a0[2 * n + 1]) / x0)
+        if nxt / mp.mpf(x0) ** (2 * n) < tol:
+            return n
+    raise RuntimeError("asymptotic region starts too low")
+
+
+def fns():
+    return [lambda x: mp.besselj(0, x), lambda x: mp.bessely(0, x),
+            lambda x: mp.besselj(1, x), lambda x: mp.bessely(1, x)]
+
+
+def cheb_monomial(f, c):
+    """Monomial coefficients in t = x - (c + 1/2) of the degree-DEG Chebyshev
+    interpolant of f on [c, c+1]."""
+    n = DEG + 1
+    u = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n)]
+    vals = [f(c + mp.mpf(1) / 2 + uj / 2) for uj in u]
+    # Chebyshev coefficients in u
+    ch = []
+    for k in range(n):
+        s = mp.fsum(vals[j] * mp.cos(k * mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n))
+        ch.append(s * (1 if k == 0 else 2) / n)
+    # T_k(u) in monomials of u, then u = 2 t
+    mono = [mp.mpf(0)] * n
+    Tkm1, Tk = [mp.mpf(1)], [mp.mpf(0), mp.mpf(1)]
+    polys = [Tkm1, Tk]
+    for k in range(2, n):
+        nxt = [mp.mpf(0)] * (k + 1)
+        for i, cc in enumerate(polys[-1]):
+            nxt[i + 1] += 2 * cc
+        for i, cc in enumerate(polys[-2]):
+            nxt[i] -= cc
+        polys.append(nxt)
+    for k in range(n):
+        for i, cc in enumerate(polys[k]):
+            mono[i] += ch[k] * cc
+    return [mono[i] * 2 ** i for i in range(n)]
+
+
+# ---------------------------------------------------------------- float64 emulation
+def horner(c, t):
+    acc = np.float64(c[-1])
+    for v in c[-2::-1]:
+        acc = acc * t + np.float64(v)
+    return acc
+
+
+def emulate(x, tabs, ser, asy):
+    x = np.float64(x)
+    if x < XS:
+        q = x * x / 4
+        cj0, cy0, cj1, cy1 = ser
+        j0 = horner(cj0, q)
+        j1 = 0.5 * x * horner(cj1, q)
+        l = np.log(0.5 * x)
+        y0 = (2 / np.pi) * ((l + np.euler_gamma) * j0 + q * horner(cy0[1:], q))
+        y1 = -2 / (np.pi * x) + (2 / np.pi) * l * j1 - (x / (2 * np.pi)) * horner(cy1, q)
+        return j0, y0, j1, y1
+    if x < XA:
+        c = int(np.floor(x))
+        t = x - (c + 0.5)
+        return tuple(horner(tabs[f][c - XS], t) for f in range(4))
+    P0, Q0, P1, Q1 = asy
+    w = 1.0 / (x * x)
+    p0, q0 = horner(P0, w), horner(Q0, w) / x
+    p1, q1 = horner(P1, w), horner(Q1, w) / x
+    amp = np.sqrt(2.0 / (np.pi * x))
+    s, co = np.sin(x), np.cos(x)
+    r = np.sqrt(0.5)
+    c0, s0 = r * (co + s), r * (s - co)          # cos, sin of x - pi/4
+    c1, s1 = r * (s - co), -r * (s + co)         # cos, sin of x - 3 pi/4
+    return (amp * (p0 * c0 - q0 * s0), amp * (p0 * s0 + q0 * c0),
+            amp * (p1 * c1 - q1 * s1), amp * (p1 * s1 + q1 * c1))
+
+
+def main():
+    ser = series_coeffs()
+    nas = asym_terms_needed(XA)
+    P0, Q0, _ = asym_coeffs(0, nas)
+    P1, Q1, _ = asym_coeffs(1, nas)
+    F = fns()
+    tabs = [[cheb_monomial(F[f], c) for c in range(XS, XA)] for f in range(4)]
+    serd = [[float(v) for v in s] for s in ser]
+    asyd = [[float(v) for v in s] for s in (P0, Q0, P1, Q1)]
+    tabd = [[[float(v) for v in cc] for cc in tf] for tf in tabs]
+    # self-check
+    xs = np.concatenate([np.geomspace(1e-6, XS, 300, endpoint=False),
+                         np.linspace(XS, XA, 2300, endpoint=False),
+                         np.linspace(XA, 120, 400)])
+    worst = 0.0
+    for x in xs:
+        got = emulate(x, tabd, serd, asyd)
+        for f in range(4):
+            ref = F[f](mp.mpf(float(x)))
+            err = abs(float(got[f]) - float(ref)) / max(1.0, abs(float(ref)))
+            worst = max(worst, err)
+    print(f"asymptotic terms: {nas}; worst scaled error {worst:.3e}")
+    if worst > 4e-16:
+        sys.exit("table accuracy check failed")
+    out = os.path.join(HERE, "hankel_table.inc")
+    with open(out, "w") as fh:
+        fh.write("// Generated by gen_hankel_table.py; do not edit.\n")
+        fh.write(f"#define HK_XS {XS}\n#define HK_XA {XA}\n#define HK_DEG {DEG}\n")
+        fh.write(f"#define HK_NSER {NSER}\n#define HK_NASY {nas}\n")
+        names = ("HK_SER_J0", "HK_SER_Y0", "HK_SER_J1", "HK_SER_Y1")
+        for nm, s in zip(names, serd):
+            fh.write(f"static constexpr double {nm}[{len(s)}] = {{" +
+                     ", ".join(repr(v) for v in s) + "};\n")
+        for nm, s in zip(("HK_ASY_P0", "HK_ASY_Q0", "HK_ASY_P1", "HK_ASY_Q1"), asyd):
+            fh.write(f"static constexpr double {nm}[{len(s)}] = {{" +
+                     ", ".join(repr(v) for v in s) + "};\n")
+        nint = XA - XS
+        fh.write(f"// [interval c-{XS}][coefficient of t^m][function J0,Y0,J1,Y1]\n")
+        fh.write(f"static constexpr double HK_TAB[{nint}][{DEG + 1}][4] = {{\n")
+        for c in range(nint):
+            fh.write(" {\n")
+            for m in range(DEG + 1):
+                fh.write("  {" + ", ".join(repr(tabd[f][c][m]) for f in range(4)) + "},\n")
+            fh.write(" },\n")
+        fh.write("};\n")
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()
