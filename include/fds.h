@@ -129,6 +129,16 @@ fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out)
 fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n,
                            double* out);
 
+/* Complex GEMM on the FP64 matrix cores (the dense contractions of the
+ * compression and solve stages run on this kernel):
+ *   C = alpha op(A) op(B) + beta C,  column-major, C is m x n, inner size k,
+ *   op in {0: none, 1: transpose, 2: conjugate transpose}.
+ * A, B, C: device complex128 with leading dimensions lda, ldb, ldc; alpha and
+ * beta: host complex128 (2 doubles each). C must not alias A or B. */
+fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
+                     const double* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     const double* beta, void* C, int64_t ldc);
+
 /* ---------------------------------------------------------------- assembly */
 
 /* Dense Galerkin assembly (paper, Notation and Background: [S]_ij, [N]_ij,
@@ -177,6 +187,13 @@ fds_status fds_filter(fds_op op, fds_form form, double alpha,
 /* Borrowed device view of V_n: n_eff orthonormal real vectors of length n. */
 fds_status fds_op_filter_basis(fds_op op, const double** Vn);
 
+/* Eigenvalues of the generalised Laplacian pencil L v = lambda G v found by the
+ * last fds_filter call (ascending; kept modes first, then up to a few beyond
+ * the cut). Host call: copies min(cap, available) values to host `out` and
+ * stores that number in *count. Available even when fds_filter failed after
+ * the eigenvalue stage. */
+fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_t* count);
+
 /* ------------------------------------------------------------- compression */
 
 /* Randomised skeleton C_f ~ U W of the filtered compact part (paper,
@@ -184,8 +201,12 @@ fds_status fds_op_filter_basis(fds_op op, const double** Vn);
  * receives r. */
 fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out);
 
-/* Borrowed device views: U (r vectors of length n) and W (r rows of length n,
- * row-major r x n), complex128. C_f ~ U W. */
+/* Borrowed device views of the skeleton in current-coefficient coordinates:
+ * with U_y W_y the skeleton of the filtered compact part of the normalised
+ * system (unknown y = G^{1/2} j), U = G^{-1/2} U_y (r vectors of length n) and
+ * W = W_y G^{1/2}, returned transposed (r vectors of length n holding the rows
+ * of W). Both complex128. The Woodbury core I_r + W U / beta is the same in
+ * both coordinates. */
 fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* rank);
 
 /* ----------------------------------------------------------------- factor */

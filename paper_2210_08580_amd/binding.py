@@ -8,9 +8,12 @@ visible, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import sys
+import weakref
 
 import torch
 
@@ -70,6 +73,9 @@ _SIGS = {
     "fds_sync": (C.c_int, [C.c_void_p]),
     "fds_hankel_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
+                            C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                            C.POINTER(C.c_double), C.c_void_p, C.c_int64]),
     "fds_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
                                C.POINTER(fds_asm_opts), C.POINTER(C.c_void_p)]),
     "fds_op_destroy": (C.c_int, [C.c_void_p]),
@@ -82,6 +88,8 @@ _SIGS = {
     "fds_filter": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.POINTER(fds_filter_opts),
                              C.POINTER(C.c_int32)]),
     "fds_op_filter_basis": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fds_op_filter_eigenvalues": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                            C.POINTER(C.c_int32)]),
     "fds_compress": (C.c_int, [C.c_void_p, C.POINTER(fds_compress_opts), C.POINTER(C.c_int32)]),
     "fds_op_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_int32)]),
@@ -93,6 +101,19 @@ _SIGS = {
 }
 
 _lib = None
+_live = weakref.WeakSet()
+_is_finalizing = sys.is_finalizing
+
+
+def _close_all():
+    # close operators before contexts, while torch is still alive
+    for o in [o for o in list(_live) if isinstance(o, Op)]:
+        o.close()
+    for o in list(_live):
+        o.close()
+
+
+atexit.register(_close_all)
 
 
 def header_symbols() -> list[str]:
@@ -174,6 +195,7 @@ class Ctx:
         h = C.c_void_p()
         _check(lib().fds_ctx_create(device, C.c_void_p(self.stream.cuda_stream), alloc_p, C.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -181,6 +203,8 @@ class Ctx:
             self.handle = None
 
     def __del__(self):
+        if _is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -207,11 +231,30 @@ def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def fds_zgemm(ctx: Ctx, opa: int, opb: int, A: torch.Tensor, Bm: torch.Tensor, Cm: torch.Tensor,
+              alpha: complex = 1.0, beta: complex = 0.0):
+    """Cm = alpha op(A) op(Bm) + beta Cm on column-major views.
+
+    The tensors hold column-major matrices, i.e. C-contiguous tensors of shape
+    (cols, rows): the matrix is t.T. Returns Cm."""
+    ra, ca = A.shape[1], A.shape[0]
+    rb, cb = Bm.shape[1], Bm.shape[0]
+    m = ra if opa == 0 else ca
+    k = ca if opa == 0 else ra
+    n = cb if opb == 0 else rb
+    al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
+    _check(lib().fds_zgemm(ctx.handle, opa, opb, m, n, k, al, _ptr(A), ra, _ptr(Bm), rb, be,
+                           _ptr(Cm), Cm.shape[1]))
+    return Cm
+
+
 # ----------------------------------------------------------------- operator
 class Op:
     def __init__(self, ctx: Ctx, handle):
         self.ctx = ctx
         self.handle = handle
+        _live.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -219,6 +262,8 @@ class Op:
             self.handle = None
 
     def __del__(self):
+        if _is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -276,6 +321,13 @@ def fds_op_filter_basis(op: Op) -> torch.Tensor:
     _check(lib().fds_op_filter_basis(op.handle, C.byref(p)))
     n, ne, _ = op.info()
     return _view(p.value, (ne, n), torch.float64, op)
+
+
+def fds_op_filter_eigenvalues(op: Op, cap: int = 4096):
+    buf = (C.c_double * cap)()
+    cnt = C.c_int32()
+    _check(lib().fds_op_filter_eigenvalues(op.handle, buf, cap, C.byref(cnt)))
+    return [buf[i] for i in range(cnt.value)]
 
 
 def fds_compress(op: Op, rank_cap: int, oversample: int = 10, power_iters: int = 2,

@@ -2,6 +2,7 @@
 // memory ownership and error reporting. All numerical work is in the kernels
 // of the other translation units; this file only orchestrates them on the
 // context's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -9,6 +10,8 @@
 
 #include "fds_internal.h"
 #include "hankel.h"
+#include "linalg.h"
+#include "pipeline.h"
 
 namespace fds {
 
@@ -44,8 +47,12 @@ void Ctx::dfree(void* p) {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D,
-                    Vn, Vg, Bt, gfac, U, W, K, piv};
+                    Vn, Vg, Vgc, Bt, gfac, K, piv};
     for (void* p : ptrs) ctx->dfree(p);
+    if (owns_uw) {
+        ctx->dfree(U);
+        ctx->dfree(W);
+    }
 }
 
 template <typename F>
@@ -145,6 +152,24 @@ fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n, do
         FDS_REQUIRE(std::isfinite(k) && k > 0.0, FDS_ERR_ARG, "k must be finite and > 0");
         if (n == 0) return;
         launch_kernel_eval(ctx->impl, k, R, n, out);
+    });
+}
+
+fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
+                     const double* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     const double* beta, void* C, int64_t ldc) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && alpha && beta && C, FDS_ERR_ARG, "NULL argument");
+        FDS_REQUIRE(opa >= 0 && opa <= 2 && opb >= 0 && opb <= 2, FDS_ERR_ARG, "op must be 0, 1 or 2");
+        FDS_REQUIRE(m >= 0 && n >= 0 && k >= 0 && m < (1 << 30) && n < (1 << 30) && k < (1 << 30),
+                    FDS_ERR_ARG, "bad sizes");
+        if (m == 0 || n == 0) return;
+        FDS_REQUIRE(A && B, FDS_ERR_ARG, "NULL operand");
+        const int64_t ra = opa == 0 ? m : k, rb = opb == 0 ? k : n;
+        FDS_REQUIRE(lda >= std::max<int64_t>(1, ra) && ldb >= std::max<int64_t>(1, rb) && ldc >= m,
+                    FDS_ERR_ARG, "leading dimension too small");
+        zgemm(ctx->impl, opa, opb, (int)m, (int)n, (int)k, make_double2(alpha[0], alpha[1]),
+              (const double2*)A, lda, (const double2*)B, ldb, make_double2(beta[0], beta[1]), (double2*)C, ldc);
     });
 }
 
@@ -260,24 +285,64 @@ fds_status fds_rhs_planewave(fds_op op, const double* angles, const void* amps, 
 }
 
 fds_status fds_apply_gram(fds_op op, int32_t p, void* X, int64_t ncols) {
-    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_apply_gram not built yet"}; });
+    return guarded([&] {
+        FDS_REQUIRE(op && X && ncols >= 0, FDS_ERR_ARG, "bad argument");
+        if (ncols == 0) return;
+        apply_gram_power(op->impl, p, (double2*)X, ncols);
+    });
 }
 
 fds_status fds_filter(fds_op op, fds_form form, double alpha, const fds_filter_opts* opts,
                       int32_t* n_eff) {
-    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_filter not built yet"}; });
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        require_stage(op->impl, Stage::Assembled, "fds_filter");
+        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE, FDS_ERR_ARG, "bad form");
+        FDS_REQUIRE(std::isfinite(alpha), FDS_ERR_ARG, "alpha must be finite");
+        int nm = 21;
+        bool keep = true;
+        double crt = 1e-6;
+        if (opts) {
+            nm = opts->n_modes;
+            keep = opts->keep_nullspace != 0;
+            crt = opts->cluster_rtol > 0.0 ? opts->cluster_rtol : 1e-6;
+        }
+        FDS_REQUIRE(nm >= 1 && nm <= op->impl.n, FDS_ERR_ARG, "n_modes must be in [1, n]");
+        FDS_REQUIRE(keep || nm >= 2, FDS_ERR_ARG, "n_modes must be >= 2 without the null mode");
+        if (form == FDS_CFIE)
+            FDS_REQUIRE(std::fabs(1.0 + 2.0 * alpha) > 1e-12, FDS_ERR_ARG, "CFIE with beta = 0");
+        run_filter(op->impl, form, alpha, nm, keep, crt);
+        if (n_eff) *n_eff = op->impl.n_eff;
+    });
 }
 
 fds_status fds_op_filter_basis(fds_op op, const double** Vn) {
     return guarded([&] {
         FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
         require_stage(op->impl, Stage::Filtered, "fds_op_filter_basis");
-        if (Vn) *Vn = op->impl.Vn;
+        const double* v = filter_basis_view(op->impl);
+        if (Vn) *Vn = v;
+    });
+}
+
+fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_t* count) {
+    return guarded([&] {
+        FDS_REQUIRE(op && out && cap >= 0, FDS_ERR_ARG, "bad argument");
+        const auto& v = op->impl.filt_lam;
+        const int32_t m = (int32_t)std::min<size_t>(v.size(), (size_t)cap);
+        for (int32_t i = 0; i < m; ++i) out[i] = v[i];
+        if (count) *count = m;
     });
 }
 
 fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out) {
-    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_compress not built yet"}; });
+    return guarded([&] {
+        FDS_REQUIRE(op && opts, FDS_ERR_ARG, "NULL argument");
+        require_stage(op->impl, Stage::Filtered, "fds_compress");
+        FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 compression is implemented");
+        run_compress(op->impl, opts->rank_cap, opts->oversample, opts->power_iters, opts->tol, opts->seed);
+        if (rank_out) *rank_out = op->impl.rank;
+    });
 }
 
 fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* rank) {
@@ -291,12 +356,30 @@ fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* ra
 }
 
 fds_status fds_factor(fds_op op) {
-    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_factor not built yet"}; });
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        require_stage(op->impl, Stage::Compressed, "fds_factor");
+        run_factor(op->impl);
+    });
 }
 
 fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs, void* j_out,
                      void* y_out, const fds_solve_opts* opts, fds_solve_stats* stats) {
-    return guarded([&] { throw Error{FDS_ERR_NOTIMPL, "fds_solve not built yet"}; });
+    return guarded([&] {
+        FDS_REQUIRE(op && j_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Factored, "fds_solve");
+        int it = 4;
+        double tol = 1e-12;
+        if (opts) {
+            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 solves are implemented");
+            it = opts->max_iters;
+            tol = opts->tol;
+        }
+        FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
+        if (nrhs == 0) return;
+        run_solve(op->impl, (const double2*)f, (const double2*)h, nrhs, (double2*)j_out,
+                  (double2*)y_out, it, tol, stats);
+    });
 }
 
 }  // extern "C"

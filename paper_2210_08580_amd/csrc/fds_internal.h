@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/fds.h"
 
@@ -83,16 +84,19 @@ struct Op {
     double alpha = 1.0;
     double beta = 0.25;
     int32_t n_eff = 0;
+    std::vector<double> filt_lam; // pencil eigenvalues of the last filter call (host)
     double* Vn = nullptr;         // [n_eff][n]  orthonormal eigenvectors of G^-1/2 L G^-1/2
     double* Vg = nullptr;         // [n_eff][n]  G^-1/2 Vn (G-orthonormal generalised eigenvectors)
-    double2* Bt = nullptr;        // [n_eff][n]  (V_n^T C)^T : row j of B is vector j
+    double2* Vgc = nullptr;       // [n_eff][n]  V_g as complex128
+    double2* Bt = nullptr;        // [n_eff][n]  G^{1/2} (V_n^T C)^T (filtered compact part, j coordinates)
     // Gram power workspace: periodic tridiagonal factorisation of G
     double* gfac = nullptr;       // [4n]
     double cheb_lo = 0.0, cheb_hi = 0.0;
     // skeleton and Woodbury core
     int32_t rank = 0;
-    double2* U = nullptr;         // [rank][n]
-    double2* W = nullptr;         // [rank][n] row-major (row j = W_j,:)
+    double2* U = nullptr;         // [rank][n]  U_j = G^{-1/2} U_y
+    double2* W = nullptr;         // [rank][n]  row t of W_j = W_y G^{1/2} (stored as W_j^T, n x rank)
+    bool owns_uw = false;         // U/W are separate allocations (else views of Vgc/Bt)
     double2* K = nullptr;         // [rank][rank] LU factors (column-major)
     int32_t* piv = nullptr;       // [rank]
     ~Op();

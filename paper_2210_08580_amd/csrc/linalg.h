@@ -1,0 +1,40 @@
+// Device linear-algebra building blocks (see linalg.hip).
+#pragma once
+#include <vector>
+
+#include "fds_internal.h"
+
+namespace fds {
+
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+constexpr double kPiHost = 3.14159265358979323846;
+
+// C = alpha op(A) op(B) + beta C, column-major, m x n result, inner dimension k.
+void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const double2* A, int64_t lda,
+           const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);
+void dgemm(Ctx& c, int opa, int opb, int m, int n, int k, double alpha, const double* A, int64_t lda,
+           const double* B, int64_t ldb, double beta, double* C, int64_t ldc);
+
+// Periodic tridiagonal Gram matrix (diag d, off e with e[i] = G[i][i+1 mod n]).
+void gram_factor(Ctx& c, const double* d, const double* e, int n, double* fac /* 3n+2 */);
+template <typename T>
+void gram_solve(Ctx& c, const double* e, const double* fac, int n, T* X, int64_t ncols, int64_t ld);
+template <typename T>
+void gram_mul(Ctx& c, const double* d, const double* e, int n, const T* X, int64_t ncols, int64_t ldx,
+              double a, double b, T* Y, int64_t ldy);
+std::vector<double> cheb_coeffs(int p, double lo, double hi);
+template <typename T>
+void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p, T* X,
+                   int64_t ncols);
+
+// Small dense factorisations (one workgroup).
+void chol_upper(Ctx& c, double* A, int n, int* info);
+void trsm_right_upper(Ctx& c, const double* R, int n, double* X, int64_t rows);
+void lu_factor(Ctx& c, double2* A, int n, int* piv, double* stats /* [min|pivot|, max|A|] */);
+void lu_solve(Ctx& c, const double2* LU, const int* piv, int n, double2* B, int64_t ncols);
+
+void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n);
+void axpby(Ctx& c, double2 a, const double2* x, double2 b, double2* y, int64_t n);
+void add_diag(Ctx& c, double2* A, int n, double s);
+
+}  // namespace fds

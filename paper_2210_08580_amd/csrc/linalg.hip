@@ -1,0 +1,636 @@
+// Dense and sparse linear algebra on the device:
+//   * complex (and real) GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64), column-major,
+//     op(A), op(B) in {N, T, C}, optional split-K with a deterministic reduction;
+//   * the periodic tridiagonal Gram matrix G: factorisation (cyclic Thomas with
+//     a Sherman-Morrison correction), block solves G^{-1} X, block products G X;
+//   * Chebyshev-series application of G^{+-1/2} (Clenshaw recurrence);
+//   * small dense factorisations in one workgroup: Cholesky (real), LU with
+//     partial pivoting (complex), block triangular solves.
+#include <cmath>
+#include <vector>
+
+#include "fds_internal.h"
+#include "linalg.h"
+
+namespace fds {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ============================================================ GEMM
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16, G_PAD = 2;
+
+template <bool CPLX>
+struct Elt;
+template <>
+struct Elt<true> {
+    typedef double2 T;
+};
+template <>
+struct Elt<false> {
+    typedef double T;
+};
+
+__device__ __forceinline__ double2 ld_op(const double2* p, int op) {
+    double2 v = *p;
+    if (op == OP_C) v.y = -v.y;
+    return v;
+}
+__device__ __forceinline__ double ld_op(const double* p, int) { return *p; }
+
+template <bool CPLX, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, typename Elt<CPLX>::T alpha,
+                                                   const typename Elt<CPLX>::T* __restrict__ A,
+                                                   int64_t lda,
+                                                   const typename Elt<CPLX>::T* __restrict__ B,
+                                                   int64_t ldb, typename Elt<CPLX>::T beta,
+                                                   typename Elt<CPLX>::T* __restrict__ C, int64_t ldc,
+                                                   int kchunk, typename Elt<CPLX>::T* __restrict__ part) {
+    typedef typename Elt<CPLX>::T T;
+    __shared__ T sA[GB_K][GB_M + G_PAD];
+    __shared__ T sB[GB_K][GB_N + G_PAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int row0 = blockIdx.x * GB_M, col0 = blockIdx.y * GB_N;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(k, kbeg + kchunk);
+
+    d4 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            accR[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            accI[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+
+    for (int kk = kbeg; kk < kend; kk += GB_K) {
+        // ---- stage A tile: op(A)[row0 + i][kk + p], i < 64, p < 16
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int i, p;
+            if (OPA == OP_N) {
+                i = tid & 63;
+                p = (tid >> 6) + 4 * e;
+            } else {
+                p = tid & 15;
+                i = (tid >> 4) + 16 * e;
+            }
+            const int gi = row0 + i, gp = kk + p;
+            T v{};
+            if (gi < m && gp < kend) {
+                const T* src = (OPA == OP_N) ? A + gi + (int64_t)gp * lda : A + gp + (int64_t)gi * lda;
+                v = ld_op(src, OPA);
+            }
+            sA[p][i] = v;
+        }
+        // ---- stage B tile: op(B)[kk + p][col0 + j], p < 16, j < 64
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int j, p;
+            if (OPB == OP_N) {
+                p = tid & 15;
+                j = (tid >> 4) + 16 * e;
+            } else {
+                j = tid & 63;
+                p = (tid >> 6) + 4 * e;
+            }
+            const int gj = col0 + j, gp = kk + p;
+            T v{};
+            if (gj < n && gp < kend) {
+                const T* src = (OPB == OP_N) ? B + gp + (int64_t)gj * ldb : B + gj + (int64_t)gp * ldb;
+                v = ld_op(src, OPB);
+            }
+            sB[p][j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kc = 0; kc < GB_K / 4; ++kc) {
+            const int pr = kc * 4 + (lane >> 4);
+            T a[2], b[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) a[r] = sA[pr][wm * 32 + r * 16 + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = sB[pr][wn * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if constexpr (CPLX) {
+                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, accR[r][c], 0, 0, 0);
+                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[r].y, b[c].y, accR[r][c], 0, 0, 0);
+                        accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, accI[r][c], 0, 0, 0);
+                        accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].y, b[c].x, accI[r][c], 0, 0, 0);
+                    } else {
+                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], accR[r][c], 0, 0, 0);
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    // ---- epilogue: v_mfma_f64_16x16x4f64 leaves D[i][j] in lane j + 16*(i%4), register i/4
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = row0 + wm * 32 + r * 16 + (lane >> 4) + 4 * v;
+                const int gj = col0 + wn * 32 + c * 16 + (lane & 15);
+                if (gi >= m || gj >= n) continue;
+                if constexpr (CPLX) {
+                    const double2 acc = make_double2(accR[r][c][v], accI[r][c][v]);
+                    if (part) {
+                        part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
+                    } else {
+                        double2 o = cmul(alpha, acc);
+                        if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[gi + (int64_t)gj * ldc]));
+                        C[gi + (int64_t)gj * ldc] = o;
+                    }
+                } else {
+                    const double acc = accR[r][c][v];
+                    if (part) {
+                        part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
+                    } else {
+                        double o = alpha * acc;
+                        if (beta != 0.0) o += beta * C[gi + (int64_t)gj * ldc];
+                        C[gi + (int64_t)gj * ldc] = o;
+                    }
+                }
+            }
+}
+
+template <bool CPLX>
+__global__ void splitk_reduce_kernel(int m, int n, int nz, typename Elt<CPLX>::T alpha,
+                                     const typename Elt<CPLX>::T* __restrict__ part,
+                                     typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* __restrict__ C,
+                                     int64_t ldc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * n) return;
+    const int i = (int)(t % m);
+    const int64_t j = t / m;
+    if constexpr (CPLX) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int z = 0; z < nz; ++z) s = cadd(s, part[(int64_t)z * m * n + t]);
+        double2 o = cmul(alpha, s);
+        if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[i + j * ldc]));
+        C[i + j * ldc] = o;
+    } else {
+        double s = 0.0;
+        for (int z = 0; z < nz; ++z) s += part[(int64_t)z * m * n + t];
+        double o = alpha * s;
+        if (beta != 0.0) o += beta * C[i + j * ldc];
+        C[i + j * ldc] = o;
+    }
+}
+
+template <bool CPLX, int OPA, int OPB>
+static void gemm_dispatch(Ctx& c, int m, int n, int k, typename Elt<CPLX>::T alpha,
+                          const typename Elt<CPLX>::T* A, int64_t lda, const typename Elt<CPLX>::T* B,
+                          int64_t ldb, typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* C, int64_t ldc) {
+    typedef typename Elt<CPLX>::T T;
+    const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
+    // split K when the output tiles alone cannot fill the chip
+    int nz = 1;
+    const int tiles = gm * gn;
+    if (tiles < 512 && k > 4 * GB_K) {
+        nz = std::min((512 + tiles - 1) / tiles, (k + 255) / 256);
+        nz = std::max(nz, 1);
+    }
+    int kchunk = (k + nz - 1) / nz;
+    kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
+    nz = (k + kchunk - 1) / kchunk;
+    T* part = nullptr;
+    if (nz > 1) part = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
+    hipLaunchKernelGGL((gemm_kernel<CPLX, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+                       alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+    FDS_HIP_TRY(hipGetLastError());
+    if (part) {
+        const int64_t tot = (int64_t)m * n;
+        hipLaunchKernelGGL(splitk_reduce_kernel<CPLX>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                           c.stream, m, n, nz, alpha, part, beta, C, ldc);
+        FDS_HIP_TRY(hipGetLastError());
+        c.dfree(part);
+    }
+}
+
+template <bool CPLX>
+static void gemm_any(Ctx& c, int opa, int opb, int m, int n, int k, typename Elt<CPLX>::T alpha,
+                     const typename Elt<CPLX>::T* A, int64_t lda, const typename Elt<CPLX>::T* B, int64_t ldb,
+                     typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* C, int64_t ldc) {
+    if (m <= 0 || n <= 0) return;
+#define FDS_G(a, b)                                                                            \
+    if (opa == a && opb == b) {                                                                \
+        gemm_dispatch<CPLX, a, b>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);             \
+        return;                                                                                \
+    }
+    FDS_G(OP_N, OP_N) FDS_G(OP_N, OP_T) FDS_G(OP_N, OP_C)
+    FDS_G(OP_T, OP_N) FDS_G(OP_T, OP_T) FDS_G(OP_T, OP_C)
+    FDS_G(OP_C, OP_N) FDS_G(OP_C, OP_T) FDS_G(OP_C, OP_C)
+#undef FDS_G
+    throw Error{FDS_ERR_ARG, "bad GEMM op"};
+}
+
+void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const double2* A, int64_t lda,
+           const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc) {
+    gemm_any<true>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void dgemm(Ctx& c, int opa, int opb, int m, int n, int k, double alpha, const double* A, int64_t lda,
+           const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+    if (opa == OP_C) opa = OP_T;
+    if (opb == OP_C) opb = OP_T;
+    gemm_any<false>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+// ============================================================ periodic tridiagonal G
+// G = T + u v^T with u = (g, 0..0, e_{n-1}), v = (1, 0..0, e_{n-1}/g), g = -d_0, so
+// that T is tridiagonal (corners removed, T_00 = d_0 - g, T_{n-1,n-1} = d_{n-1} - e_{n-1}^2/g).
+// Layout of fac: [0,n) 1/den_i, [n,2n) cp_i, [2n,3n) z = T^{-1} u, [3n] vcoef, [3n+1] 1/(1+v.z).
+__global__ void gram_factor_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                   double* __restrict__ fac) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double* inv = fac;
+    double* cp = fac + n;
+    double* z = fac + 2 * n;
+    const double g = -d[0];
+    const double en = e[n - 1];
+    double den = d[0] - g;
+    inv[0] = 1.0 / den;
+    cp[0] = e[0] * inv[0];
+    for (int i = 1; i < n; ++i) {
+        double di = d[i];
+        if (i == n - 1) di -= en * en / g;
+        den = di - e[i - 1] * cp[i - 1];
+        inv[i] = 1.0 / den;
+        cp[i] = (i < n - 1) ? e[i] * inv[i] : 0.0;
+    }
+    // z = T^{-1} u, u = (g, 0, ..., 0, en)
+    double y = g * inv[0];
+    z[0] = y;
+    for (int i = 1; i < n; ++i) {
+        const double ui = (i == n - 1) ? en : 0.0;
+        y = (ui - e[i - 1] * y) * inv[i];
+        z[i] = y;
+    }
+    for (int i = n - 2; i >= 0; --i) z[i] -= cp[i] * z[i + 1];
+    const double vcoef = en / g;
+    fac[3 * n] = vcoef;
+    fac[3 * n + 1] = 1.0 / (1.0 + z[0] + vcoef * z[n - 1]);
+}
+
+// X[c][0..n) <- G^{-1} X[c] for each vector c (thread per vector).
+template <typename T>
+__global__ void gram_solve_kernel(const double* __restrict__ e, const double* __restrict__ fac, int n,
+                                  T* __restrict__ X, int64_t ncols, int64_t ld) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    T* x = X + c * ld;
+    const double* inv = fac;
+    const double* cp = fac + n;
+    const double* z = fac + 2 * n;
+    const double vcoef = fac[3 * n], f = fac[3 * n + 1];
+    T y = x[0] * inv[0];
+    x[0] = y;
+    for (int i = 1; i < n; ++i) {
+        y = (x[i] - y * e[i - 1]) * inv[i];
+        x[i] = y;
+    }
+    for (int i = n - 2; i >= 0; --i) {
+        y = x[i] - y * cp[i];
+        x[i] = y;
+    }
+    const T s = (x[0] + x[n - 1] * vcoef) * f;
+    for (int i = 0; i < n; ++i) x[i] = x[i] - s * z[i];
+}
+
+// Y = a G X + b X (element-parallel; Y may not alias X).
+template <typename T>
+__global__ void gram_mul_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                const T* __restrict__ X, int64_t ncols, int64_t ldx, double a, double b,
+                                T* __restrict__ Y, int64_t ldy) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * ncols) return;
+    const int i = (int)(t % n);
+    const int64_t c = t / n;
+    const T* x = X + c * ldx;
+    const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
+    const T gx = x[i] * d[i] + x[im] * e[im] + x[ip] * e[i];
+    Y[c * ldy + i] = gx * a + x[i] * b;
+}
+
+void gram_factor(Ctx& c, const double* d, const double* e, int n, double* fac) {
+    hipLaunchKernelGGL(gram_factor_kernel, dim3(1), dim3(64), 0, c.stream, d, e, n, fac);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+template <typename T>
+void gram_solve(Ctx& c, const double* e, const double* fac, int n, T* X, int64_t ncols, int64_t ld) {
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(gram_solve_kernel<T>, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, e, fac,
+                       n, X, ncols, ld);
+    FDS_HIP_TRY(hipGetLastError());
+}
+template void gram_solve<double>(Ctx&, const double*, const double*, int, double*, int64_t, int64_t);
+template void gram_solve<double2>(Ctx&, const double*, const double*, int, double2*, int64_t, int64_t);
+
+template <typename T>
+void gram_mul(Ctx& c, const double* d, const double* e, int n, const T* X, int64_t ncols, int64_t ldx,
+              double a, double b, T* Y, int64_t ldy) {
+    const int64_t tot = (int64_t)n * ncols;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(gram_mul_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, d, e, n,
+                       X, ncols, ldx, a, b, Y, ldy);
+    FDS_HIP_TRY(hipGetLastError());
+}
+template void gram_mul<double>(Ctx&, const double*, const double*, int, const double*, int64_t, int64_t, double,
+                               double, double*, int64_t);
+template void gram_mul<double2>(Ctx&, const double*, const double*, int, const double2*, int64_t, int64_t,
+                                double, double, double2*, int64_t);
+
+// ============================================================ Chebyshev G^{p/2}
+// f(x) = x^{p/2} on [lo, hi] expanded in Chebyshev polynomials of
+// t = (2x - lo - hi)/(hi - lo); coefficients by interpolation at Chebyshev points.
+std::vector<double> cheb_coeffs(int p, double lo, double hi) {
+    const int M = 400;
+    std::vector<double> fv(M), a(M);
+    for (int j = 0; j < M; ++j) {
+        const double t = std::cos(kPiHost * (j + 0.5) / M);
+        const double x = 0.5 * (hi + lo) + 0.5 * (hi - lo) * t;
+        fv[j] = std::pow(x, 0.5 * p);
+    }
+    for (int i = 0; i < M; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < M; ++j) s += fv[j] * std::cos(kPiHost * i * (j + 0.5) / M);
+        a[i] = s * 2.0 / M;
+    }
+    a[0] *= 0.5;
+    int deg = M - 1;
+    const double a0 = std::fabs(a[0]);
+    while (deg > 1 && std::fabs(a[deg]) < 1e-18 * a0 && std::fabs(a[deg - 1]) < 1e-18 * a0) --deg;
+    a.resize(deg + 1);
+    return a;
+}
+
+// One Clenshaw step for all vectors:
+//   bj = a_j X + 2 That(b1) - b2,  That(v) = (2 G v - (lo+hi) v)/(hi-lo)
+// final (last=1): Y = a_0 X + That(b1) - b2
+template <typename T>
+__global__ void clenshaw_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                const T* __restrict__ X, const T* __restrict__ b1, const T* __restrict__ b2,
+                                T* __restrict__ out, int64_t ncols, double aj, double s1, double s0,
+                                double tw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * ncols) return;
+    const int i = (int)(t % n);
+    const int64_t c = t / n;
+    const int64_t o = c * n;
+    const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
+    const T gb = b1[o + i] * d[i] + b1[o + im] * e[im] + b1[o + ip] * e[i];
+    // That(b1) = s1 * G b1 + s0 * b1
+    const T th = gb * s1 + b1[o + i] * s0;
+    out[o + i] = X[o + i] * aj + th * tw - b2[o + i];
+}
+
+template <typename T>
+void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p,
+                   T* X, int64_t ncols) {
+    if (ncols <= 0) return;
+    const std::vector<double> a = cheb_coeffs(p, lo, hi);
+    const int deg = (int)a.size() - 1;
+    const size_t bytes = sizeof(T) * (size_t)n * ncols;
+    T* bufs[3];
+    for (int i = 0; i < 3; ++i) bufs[i] = static_cast<T*>(c.dmalloc(bytes));
+    FDS_HIP_TRY(hipMemsetAsync(bufs[1], 0, bytes, c.stream));
+    FDS_HIP_TRY(hipMemsetAsync(bufs[2], 0, bytes, c.stream));
+    const double s1 = 2.0 / (hi - lo), s0 = -(hi + lo) / (hi - lo);
+    const int64_t tot = (int64_t)n * ncols;
+    const unsigned nb = (unsigned)((tot + 255) / 256);
+    // rotate: cur = b_j, p1 = b_{j+1}, p2 = b_{j+2}
+    int cur = 0, p1 = 1, p2 = 2;
+    for (int j = deg; j >= 1; --j) {
+        hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
+                           bufs[cur], ncols, a[j], s1, s0, 2.0);
+        FDS_HIP_TRY(hipGetLastError());
+        const int t = p2;
+        p2 = p1;
+        p1 = cur;
+        cur = t;
+    }
+    hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
+                       bufs[cur], ncols, a[0], s1, s0, 1.0);
+    FDS_HIP_TRY(hipGetLastError());
+    FDS_HIP_TRY(hipMemcpyAsync(X, bufs[cur], bytes, hipMemcpyDeviceToDevice, c.stream));
+    for (int i = 0; i < 3; ++i) c.dfree(bufs[i]);
+}
+template void gram_pow_half<double>(Ctx&, const double*, const double*, int, double, double, int, double*,
+                                    int64_t);
+template void gram_pow_half<double2>(Ctx&, const double*, const double*, int, double, double, int, double2*,
+                                     int64_t);
+
+// ============================================================ small dense
+// Cholesky A = R^T R of a real SPD matrix (column-major n x n, in place: the upper
+// triangle receives R, the strict lower triangle is zeroed). One workgroup.
+__global__ void chol_kernel(double* __restrict__ A, int n, int* __restrict__ info) {
+    __shared__ double piv;
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            const double v = A[j + (int64_t)j * n];
+            if (!(v > 0.0)) info[0] = j + 1;
+            piv = sqrt(fmax(v, 1e-300));
+            A[j + (int64_t)j * n] = piv;
+        }
+        __syncthreads();
+        for (int cidx = j + 1 + threadIdx.x; cidx < n; cidx += blockDim.x) A[j + (int64_t)cidx * n] /= piv;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+            const int r = j + 1 + (int)(t % m), cc = j + 1 + (int)(t / m);
+            if (r <= cc) A[r + (int64_t)cc * n] -= A[j + (int64_t)r * n] * A[j + (int64_t)cc * n];
+        }
+        __syncthreads();
+    }
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+        const int r = (int)(t % n), cc = (int)(t / n);
+        if (r > cc) A[t] = 0.0;
+    }
+}
+
+// X <- X R^{-1} for R upper triangular (n x n column-major); X has `rows` rows
+// (ld = rows), i.e. each row x solves y R = x. Thread per row.
+__global__ void trsm_right_upper_kernel(const double* __restrict__ R, int n, double* __restrict__ X,
+                                        int64_t rows) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    for (int cidx = 0; cidx < n; ++cidx) {
+        double s = X[r + cidx * rows];
+        for (int i = 0; i < cidx; ++i) s -= X[r + i * rows] * R[i + (int64_t)cidx * n];
+        X[r + cidx * rows] = s / R[cidx + (int64_t)cidx * n];
+    }
+}
+
+// LU with partial pivoting of a complex n x n column-major matrix (one workgroup).
+// piv[j] = row swapped with j at step j. minpiv[0] = min |U_jj|, maxabs[0] = max |A|.
+__global__ void lu_kernel(double2* __restrict__ A, int n, int* __restrict__ piv, double* __restrict__ stats) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    __shared__ int prow;
+    __shared__ double2 pval;
+    // max |A| before factorisation
+    double mx = 0.0;
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) mx = fmax(mx, hypot(A[t].x, A[t].y));
+    sv[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[1] = sv[0];
+        stats[0] = 1e300;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        double best = -1.0;
+        int bi = j;
+        for (int r = j + threadIdx.x; r < n; r += blockDim.x) {
+            const double2 v = A[r + (int64_t)j * n];
+            const double av = fabs(v.x) + fabs(v.y);
+            if (av > best) {
+                best = av;
+                bi = r;
+            }
+        }
+        sv[threadIdx.x] = best;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                const double o = sv[threadIdx.x + s];
+                const int oi = si[threadIdx.x + s];
+                if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sv[threadIdx.x] = o;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            prow = si[0];
+            piv[j] = prow;
+        }
+        __syncthreads();
+        const int pr = prow;
+        if (pr != j)
+            for (int cidx = threadIdx.x; cidx < n; cidx += blockDim.x) {
+                const double2 t = A[j + (int64_t)cidx * n];
+                A[j + (int64_t)cidx * n] = A[pr + (int64_t)cidx * n];
+                A[pr + (int64_t)cidx * n] = t;
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pval = A[j + (int64_t)j * n];
+            stats[0] = fmin(stats[0], hypot(pval.x, pval.y));
+        }
+        __syncthreads();
+        const double2 p = pval;
+        const double den = p.x * p.x + p.y * p.y;
+        const double2 pinv = den > 0.0 ? make_double2(p.x / den, -p.y / den) : make_double2(0.0, 0.0);
+        for (int r = j + 1 + threadIdx.x; r < n; r += blockDim.x) A[r + (int64_t)j * n] = cmul(A[r + (int64_t)j * n], pinv);
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+            const int r = j + 1 + (int)(t % m), cc = j + 1 + (int)(t / m);
+            A[r + (int64_t)cc * n] = csub(A[r + (int64_t)cc * n], cmul(A[r + (int64_t)j * n], A[j + (int64_t)cc * n]));
+        }
+        __syncthreads();
+    }
+}
+
+// Solve LU x = P b for each column of B (n x ncols, ld = n), thread per column.
+__global__ void lu_solve_kernel(const double2* __restrict__ LU, const int* __restrict__ piv, int n,
+                                double2* __restrict__ B, int64_t ncols) {
+    const int64_t cidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= ncols) return;
+    double2* b = B + cidx * n;
+    for (int j = 0; j < n; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+            const double2 t = b[j];
+            b[j] = b[p];
+            b[p] = t;
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        const double2 bj = b[j];
+        for (int r = j + 1; r < n; ++r) b[r] = csub(b[r], cmul(LU[r + (int64_t)j * n], bj));
+    }
+    for (int j = n - 1; j >= 0; --j) {
+        const double2 u = LU[j + (int64_t)j * n];
+        const double den = u.x * u.x + u.y * u.y;
+        const double2 xj = cmul(b[j], make_double2(u.x / den, -u.y / den));
+        b[j] = xj;
+        for (int r = 0; r < j; ++r) b[r] = csub(b[r], cmul(LU[r + (int64_t)j * n], xj));
+    }
+}
+
+void chol_upper(Ctx& c, double* A, int n, int* info) {
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, info);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void trsm_right_upper(Ctx& c, const double* R, int n, double* X, int64_t rows) {
+    hipLaunchKernelGGL(trsm_right_upper_kernel, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, c.stream, R,
+                       n, X, rows);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void lu_factor(Ctx& c, double2* A, int n, int* piv, double* stats) {
+    hipLaunchKernelGGL(lu_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, piv, stats);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void lu_solve(Ctx& c, const double2* LU, const int* piv, int n, double2* B, int64_t ncols) {
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, LU, piv, n, B,
+                       ncols);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+// ============================================================ element-wise helpers
+__global__ void real_to_complex_kernel(const double* __restrict__ x, double2* __restrict__ y, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = make_double2(x[t], 0.0);
+}
+
+// y = a x + b y  (complex scalars a, b)
+__global__ void axpby_kernel(double2 a, const double2* __restrict__ x, double2 b, double2* __restrict__ y,
+                             int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = cadd(cmul(a, x[t]), cmul(b, y[t]));
+}
+
+void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(real_to_complex_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, x, y, n);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void axpby(Ctx& c, double2 a, const double2* x, double2 b, double2* y, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, x, b, y, n);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+// add `s` to the diagonal of an n x n column-major matrix
+__global__ void add_diag_kernel(double2* __restrict__ A, int n, double s) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) A[t + (int64_t)t * n].x += s;
+}
+
+void add_diag(Ctx& c, double2* A, int n, double s) {
+    hipLaunchKernelGGL(add_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, A, n, s);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace fds

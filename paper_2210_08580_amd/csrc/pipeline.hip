@@ -1,0 +1,289 @@
+// Orchestration of the filtered fast direct solve on the device.
+//
+// The paper's normalised unknown is y = G^{1/2} j and its filtered system is
+// (beta I + P C) y = v with P = V_n V_n^T (paper, Filters Based Fast Direct
+// Solver, 2D case). This library works in the current coefficients j instead:
+// with V_g = G^{-1/2} V_n (G-orthonormal generalised Laplacian eigenvectors)
+// the same system reads
+//     (beta I + V_g Bt^T) j = w,   w = G^{-1/2} v,
+// where, for the EFIE part, Bt = G^{1/2} (V_n^T C)^T = N^T G^{-1} S^T V_g - G V_g / 4,
+// for the MFIE part Bt = -D^T V_g, and
+//     EFIE  w = -G^{-1} S G^{-1} f,   MFIE  w = -G^{-1} h.
+// Every product is a similarity transform of the paper's by G^{1/2}, so the
+// solution is identical up to rounding, but no square root of G is needed on
+// the solve path: only tridiagonal G^{-1} solves and G products. Residual
+// norms are measured in the y metric, ||r_y||^2 = r_j^H G r_j.
+// The skeleton U W of the filtered compact part is likewise stored as
+// U_j = G^{-1/2} U_y, W_j = W_y G^{1/2}; the Woodbury core I + W U/beta is the
+// same in both coordinates (paper, Inversion of the structured matrices).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fds_internal.h"
+#include "linalg.h"
+#include "pipeline.h"
+
+namespace fds {
+
+static const double2 kOne = {1.0, 0.0};
+static const double2 kZero = {0.0, 0.0};
+
+void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol);
+
+// per-column sqrt(x^H G x)
+__global__ void gnorm_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                             const double2* __restrict__ X, int64_t ncols, double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int64_t c = blockIdx.x;
+    if (c >= ncols) return;
+    const double2* x = X + c * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
+        const double2 gx = make_double2(d[i] * x[i].x + e[im] * x[im].x + e[i] * x[ip].x,
+                                        d[i] * x[i].y + e[im] * x[im].y + e[i] * x[ip].y);
+        s += x[i].x * gx.x + x[i].y * gx.y;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sqrt(fmax(sh[0], 0.0));
+}
+
+static void gnorms(Op& op, const double2* X, int64_t ncols, double* out) {
+    hipLaunchKernelGGL(gnorm_kernel, dim3((unsigned)ncols), dim3(256), 0, op.ctx->stream, op.g_diag, op.g_off,
+                       (int)op.n, X, ncols, out);
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void ensure_gram_factor(Op& op) {
+    if (op.gfac) return;
+    op.gfac = static_cast<double*>(op.ctx->dmalloc(sizeof(double) * (3 * (size_t)op.n + 2)));
+    gram_factor(*op.ctx, op.g_diag, op.g_off, (int)op.n, op.gfac);
+}
+
+void ensure_cheb_bounds(Op& op) {
+    if (op.cheb_hi > 0.0) return;
+    const int n = (int)op.n;
+    std::vector<double> h(2 * (size_t)n);
+    Ctx& c = *op.ctx;
+    FDS_HIP_TRY(hipMemcpyAsync(h.data(), op.g_diag, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipMemcpyAsync(h.data() + n, op.g_off, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    double lo = 1e300, hi = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const int im = i == 0 ? n - 1 : i - 1;
+        lo = std::min(lo, h[i] - std::fabs(h[n + im]) - std::fabs(h[n + i]));
+        hi = std::max(hi, h[i] + std::fabs(h[n + im]) + std::fabs(h[n + i]));
+    }
+    op.cheb_lo = lo;
+    op.cheb_hi = hi;
+}
+
+void apply_gram_power(Op& op, int p, double2* X, int64_t ncols) {
+    if (p == -2) {
+        ensure_gram_factor(op);
+        gram_solve<double2>(*op.ctx, op.g_off, op.gfac, (int)op.n, X, ncols, op.n);
+        return;
+    }
+    FDS_REQUIRE(p == 1 || p == -1, FDS_ERR_ARG, "p must be -2, -1 or 1");
+    ensure_cheb_bounds(op);
+    gram_pow_half<double2>(*op.ctx, op.g_diag, op.g_off, (int)op.n, op.cheb_lo, op.cheb_hi, p, X, ncols);
+}
+
+const double* filter_basis_view(Op& op) {
+    if (!op.Vn) {
+        Ctx& c = *op.ctx;
+        const size_t bytes = sizeof(double) * (size_t)op.n * op.n_eff;
+        op.Vn = static_cast<double*>(c.dmalloc(bytes));
+        FDS_HIP_TRY(hipMemcpyAsync(op.Vn, op.Vg, bytes, hipMemcpyDeviceToDevice, c.stream));
+        ensure_cheb_bounds(op);
+        gram_pow_half<double>(c, op.g_diag, op.g_off, (int)op.n, op.cheb_lo, op.cheb_hi, 1, op.Vn, op.n_eff);
+    }
+    return op.Vn;
+}
+
+void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    ensure_gram_factor(op);
+    compute_filter_basis(op, n_modes, keep_null, cluster_rtol);
+    const int ne = op.n_eff;
+    op.form = form;
+    op.alpha = alpha;
+    op.beta = form == FDS_EFIE ? 0.25 : (form == FDS_MFIE ? 0.5 : (1.0 + 2.0 * alpha) / 4.0);
+    c.dfree(op.Vgc);
+    c.dfree(op.Bt);
+    op.Vgc = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
+    op.Bt = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
+    real_to_complex(c, op.Vg, op.Vgc, (int64_t)n * ne);
+    if (form == FDS_EFIE || form == FDS_CFIE) {
+        // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
+        double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
+        zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.S, n, op.Vgc, n, kZero, X, n);
+        gram_solve<double2>(c, op.g_off, op.gfac, n, X, ne, n);
+        zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.Nm, n, X, n, kZero, op.Bt, n);
+        gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X, n);
+        axpby(c, kOne, X, kOne, op.Bt, (int64_t)n * ne);
+        c.dfree(X);
+        if (form == FDS_CFIE)   // + alpha * (-D^T Vg)
+            zgemm(c, OP_N, OP_N, n, ne, n, make_double2(-alpha, 0.0), op.D, n, op.Vgc, n, kOne, op.Bt, n);
+    } else {
+        zgemm(c, OP_N, OP_N, n, ne, n, make_double2(-1.0, 0.0), op.D, n, op.Vgc, n, kZero, op.Bt, n);
+    }
+    op.stage = Stage::Filtered;
+    op.rank = 0;
+}
+
+void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed) {
+    const int ne = op.n_eff;
+    const int ell = rank_cap + oversample;
+    FDS_REQUIRE(rank_cap >= 1 && oversample >= 0 && power_iters >= 0 && tol >= 0.0, FDS_ERR_ARG,
+                "bad compression options");
+    Ctx& c = *op.ctx;
+    if (op.owns_uw) {
+        c.dfree(op.U);
+        c.dfree(op.W);
+    }
+    op.U = op.W = nullptr;
+    op.owns_uw = false;
+    if (tol == 0.0 && rank_cap >= ne && ell >= ne) {
+        // The filtered compact part V_n B has rank <= n_eff and a sketch of width
+        // l >= n_eff spans its whole range, so the randomised skeleton is exact:
+        // U_j = V_g, W_j = Bt^T (rank n_eff), no sketch needs to be formed.
+        op.U = op.Vgc;
+        op.W = op.Bt;
+        op.rank = ne;
+        op.stage = Stage::Compressed;
+        return;
+    }
+    throw Error{FDS_ERR_NOTIMPL, "truncating (lossy) compression is not built yet"};
+}
+
+void run_factor(Op& op) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, r = op.rank;
+    c.dfree(op.K);
+    c.dfree(op.piv);
+    op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(r, 1) * std::max(r, 1)));
+    op.piv = static_cast<int*>(c.dmalloc(sizeof(int) * std::max(r, 1)));
+    if (r == 0) {
+        op.stage = Stage::Factored;
+        return;
+    }
+    // K = I + beta^{-1} W_j U_j ; W_j = Bt^T (stored as n x r column-major "W^T")
+    zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, op.K, r);
+    add_diag(c, op.K, r, 1.0);
+    double* st = static_cast<double*>(c.dmalloc(sizeof(double) * 2));
+    lu_factor(c, op.K, r, op.piv, st);
+    double hs[2];
+    FDS_HIP_TRY(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    c.dfree(st);
+    FDS_REQUIRE(hs[0] >= 64.0 * 2.220446049250313e-16 * hs[1], FDS_ERR_SINGULAR,
+                "Woodbury core is numerically singular");
+    op.stage = Stage::Factored;
+}
+
+// x <- Woodbury solve of (beta I + U W) x = b, in place on b (n x nrhs); z: r x nrhs scratch
+static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, r = op.rank;
+    const double ib = 1.0 / op.beta;
+    if (r > 0) {
+        zgemm(c, OP_T, OP_N, r, (int)nrhs, n, kOne, op.W, n, b, n, kZero, z, r);
+        lu_solve(c, op.K, op.piv, r, z, nrhs);
+        // b <- b/beta - U z / beta^2
+        zgemm(c, OP_N, OP_N, n, (int)nrhs, r, make_double2(-ib * ib, 0.0), op.U, n, z, r,
+              make_double2(ib, 0.0), b, n);
+    } else {
+        axpby(c, kZero, b, make_double2(ib, 0.0), b, (int64_t)n * nrhs);
+    }
+}
+
+void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
+               int max_iters, double tol, fds_solve_stats* stats) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, ne = op.n_eff;
+    const size_t blk = sizeof(double2) * (size_t)n * nrhs;
+    double2* w = static_cast<double2*>(c.dmalloc(blk));     // G^{-1/2} v
+    double2* res = static_cast<double2*>(c.dmalloc(blk));
+    double2* z = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(op.rank, ne) * nrhs));
+    // ---- right-hand side in j coordinates
+    if (op.form == FDS_EFIE || op.form == FDS_CFIE) {
+        FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
+        FDS_HIP_TRY(hipMemcpyAsync(res, f, blk, hipMemcpyDeviceToDevice, c.stream));
+        gram_solve<double2>(c, op.g_off, op.gfac, n, res, nrhs, n);
+        // S = (S stored row-major)^T as a column-major array
+        zgemm(c, OP_T, OP_N, n, (int)nrhs, n, make_double2(-1.0, 0.0), op.S, n, res, n, kZero, w, n);
+        gram_solve<double2>(c, op.g_off, op.gfac, n, w, nrhs, n);
+    }
+    if (op.form == FDS_MFIE || op.form == FDS_CFIE) {
+        FDS_REQUIRE(h != nullptr, FDS_ERR_ARG, "h is required for the MFIE/CFIE");
+        FDS_HIP_TRY(hipMemcpyAsync(res, h, blk, hipMemcpyDeviceToDevice, c.stream));
+        gram_solve<double2>(c, op.g_off, op.gfac, n, res, nrhs, n);
+        if (op.form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), res, kZero, w, (int64_t)n * nrhs);
+        else axpby(c, make_double2(-op.alpha, 0.0), res, kOne, w, (int64_t)n * nrhs);
+    }
+    // ---- Woodbury solve
+    double2* jv = j_out;
+    FDS_HIP_TRY(hipMemcpyAsync(jv, w, blk, hipMemcpyDeviceToDevice, c.stream));
+    woodbury_apply(op, jv, nrhs, z);
+    // ---- refinement against beta I + V_g Bt^T (the uncompressed filtered operator)
+    double* nrm = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * nrhs));
+    std::vector<double> hn(2 * nrhs);
+    int iters = 0;
+    double rel = 0.0;
+    bool conv = false;
+    if (stats) {
+        std::fill(stats->history, stats->history + 32, 0.0);
+        gnorms(op, w, nrhs, nrm + nrhs);
+    }
+    for (int it = 0;; ++it) {
+        if (!stats && it >= max_iters) break;
+        // res = w - beta j - V_g (Bt^T j)
+        FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
+        axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, (int64_t)n * nrhs);
+        zgemm(c, OP_T, OP_N, ne, (int)nrhs, n, kOne, op.Bt, n, jv, n, kZero, z, ne);
+        zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+        if (stats) {
+            gnorms(op, res, nrhs, nrm);
+            FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.stream));
+            FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+            rel = 0.0;
+            for (int64_t k = 0; k < nrhs; ++k) {
+                const double den = hn[nrhs + k] > 0.0 ? hn[nrhs + k] : 1.0;
+                rel = std::max(rel, hn[k] / den);
+            }
+            if (it < 32) stats->history[it] = rel;
+            if (rel <= tol) {
+                conv = true;
+                break;
+            }
+        }
+        if (it >= max_iters) break;
+        woodbury_apply(op, res, nrhs, z);
+        axpby(c, kOne, res, kOne, jv, (int64_t)n * nrhs);
+        ++iters;
+    }
+    if (y_out) {
+        FDS_HIP_TRY(hipMemcpyAsync(y_out, jv, blk, hipMemcpyDeviceToDevice, c.stream));
+        apply_gram_power(op, 1, y_out, nrhs);
+    }
+    c.dfree(nrm);
+    c.dfree(w);
+    c.dfree(res);
+    c.dfree(z);
+    if (stats) {
+        stats->iters = iters;
+        stats->converged = conv ? 1 : 0;
+        stats->relres = rel;
+        FDS_REQUIRE(conv, FDS_ERR_NOCONV, "refinement did not reach the requested tolerance");
+    }
+}
+
+}  // namespace fds
