@@ -113,6 +113,16 @@ fds_status fds_sync(fds_ctx ctx);
 /* Thread-local description of the last failure of this thread. */
 const char* fds_last_error(void);
 
+/* Per-kernel timing with HIP events on the context's stream (off by default).
+ * While enabled, every kernel launch of the library is bracketed by two
+ * events; fds_profile_read resolves them (it synchronises the stream),
+ * accumulates per kernel name and clears the accumulators.
+ * names: host buffer of cap x 32 chars (NUL-terminated names), total_ms and
+ * launches: host arrays of cap entries; *count receives the number of names. */
+fds_status fds_profile_enable(fds_ctx ctx, int32_t on);
+fds_status fds_profile_read(fds_ctx ctx, int32_t cap, char* names, double* total_ms,
+                            int64_t* launches, int32_t* count);
+
 /* ------------------------------------------------------- special functions */
 
 /* Bessel functions of the Hankel kernel (paper, Notation and Background:

@@ -71,6 +71,9 @@ _SIGS = {
     "fds_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(fds_allocator), C.POINTER(C.c_void_p)]),
     "fds_ctx_destroy": (C.c_int, [C.c_void_p]),
     "fds_sync": (C.c_int, [C.c_void_p]),
+    "fds_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fds_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "fds_hankel_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
@@ -217,6 +220,25 @@ def fds_ctx_create(device: int = 0, stream=None) -> Ctx:
 
 def fds_sync(ctx: Ctx):
     _check(lib().fds_sync(ctx.handle))
+
+
+def fds_profile_enable(ctx: Ctx, on: bool = True):
+    _check(lib().fds_profile_enable(ctx.handle, int(bool(on))))
+
+
+def fds_profile_read(ctx: Ctx, cap: int = 128) -> dict:
+    """{kernel name: (total ms, launches)} accumulated since the last read."""
+    names = C.create_string_buffer(32 * cap)
+    tot = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    n = C.c_int32()
+    _check(lib().fds_profile_read(ctx.handle, cap, names, tot, cnt, C.byref(n)))
+    raw = names.raw
+    out = {}
+    for i in range(n.value):
+        nm = raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+        out[nm] = (tot[i], cnt[i])
+    return out
 
 
 def fds_hankel_eval(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:

@@ -47,7 +47,7 @@ void Ctx::dfree(void* p) {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D,
-                    Vn, Vg, Vgc, Bt, gfac, K, piv};
+                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
         ctx->dfree(U);
@@ -75,6 +75,20 @@ static fds_status guarded(F&& f) {
 static void require_stage(const Op& op, Stage s, const char* what) {
     if ((int)op.stage < (int)s)
         throw Error{FDS_ERR_STATE, std::string(what) + " called before the required pipeline stage"};
+}
+
+void resolve_profile(Ctx& c) {
+    for (auto& r : c.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto& e = c.acc[r.name];
+            e.first += ms;
+            e.second += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    c.pending.clear();
 }
 
 }  // namespace fds
@@ -124,6 +138,7 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
     return guarded([&] {
         if (!ctx) return;
         (void)hipStreamSynchronize(ctx->impl.stream);
+        resolve_profile(ctx->impl);
         ctx->impl.dfree(ctx->impl.hk_tab);
         ctx->impl.dfree(ctx->impl.gl32);
         delete ctx;
@@ -135,6 +150,34 @@ fds_status fds_sync(fds_ctx ctx) {
         FDS_REQUIRE(ctx != nullptr, FDS_ERR_ARG, "ctx is NULL");
         FDS_HIP_TRY(hipStreamSynchronize(ctx->impl.stream));
         FDS_HIP_TRY(hipGetLastError());
+    });
+}
+
+fds_status fds_profile_enable(fds_ctx ctx, int32_t on) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx != nullptr, FDS_ERR_ARG, "ctx is NULL");
+        ctx->impl.prof = on != 0;
+    });
+}
+
+fds_status fds_profile_read(fds_ctx ctx, int32_t cap, char* names, double* total_ms, int64_t* launches,
+                            int32_t* count) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && cap >= 0 && (cap == 0 || (names && total_ms && launches)), FDS_ERR_ARG,
+                    "bad argument");
+        Ctx& c = ctx->impl;
+        resolve_profile(c);
+        int32_t i = 0;
+        for (const auto& kv : c.acc) {
+            if (i >= cap) break;
+            std::strncpy(names + 32 * i, kv.first.c_str(), 31);
+            names[32 * i + 31] = 0;
+            total_ms[i] = kv.second.first;
+            launches[i] = kv.second.second;
+            ++i;
+        }
+        if (count) *count = i;
+        c.acc.clear();
     });
 }
 

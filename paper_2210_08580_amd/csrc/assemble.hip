@@ -9,7 +9,15 @@
 // and entry (i, j) sums the blocks of the four pairs (p, q) in
 // {i-1, i} x {j-1, j} (panel p carries psi_0 of node p, psi_1 of node p+1).
 //
-// Far pairs (|p - q| >= 2 mod n): 8 x 8 tensor Gauss rule.
+// Far pairs (|p - q| >= 2 mod n): 8 x 8 tensor Gauss rule, or a 4 x 4 / 3 x 3
+//   rule when the two panels are far apart relative to their length and the
+//   wave number: the n-point Gauss error for an integrand analytic in a
+//   Bernstein ellipse of parameter rho decays like rho^{-2n}; with the nearest
+//   singularity at distance d from panels of length <= h, rho >= 2d/h, and the
+//   oscillation contributes (kh/2)^{2n}/(2n)!. With d >= 96 h, kh <= 0.04
+//   (4 points) and d >= 512 h, kh <= 0.006 (3 points) both terms stay below
+//   1e-17, i.e. the result equals the 8 x 8 rule to rounding. The order is
+//   chosen per wavefront and row panel (the largest order any lane needs).
 //   One wavefront owns a 63 x 63 output tile: its 64 lanes hold the 64
 //   column panels j0-1 .. j0+62 (Gauss points in registers); the wave walks
 //   the row panels (wave-uniform, scalar loads), and for each row forms the
@@ -34,6 +42,13 @@ struct W8 {
     double wp1[8];   // w_b psi_1(xi_b)
 };
 
+// reduced far-field rules: [order 4: xi, w psi_0, w psi_1][order 3: same]
+struct WLow {
+    double r4[3][4];
+    double r3[3][3];
+};
+constexpr double FAR4_D = 96.0, FAR4_KH = 0.04, FAR3_D = 512.0, FAR3_KH = 0.006;
+
 struct FarParams {
     const double* __restrict__ gx;
     const double* __restrict__ gy;
@@ -41,6 +56,7 @@ struct FarParams {
     const double* __restrict__ nx;
     const double* __restrict__ ny;
     const double* __restrict__ tab;
+    const double* __restrict__ nodes;
     double2* __restrict__ S;
     double2* __restrict__ Nm;
     double2* __restrict__ D;
@@ -59,14 +75,23 @@ __device__ __forceinline__ double2 shfl_down1(double2 v) {
     return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
 }
 
-__global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 wt) {
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
     __shared__ __attribute__((aligned(16))) double tab[HK_TAB_DOUBLES];
     __shared__ double wsh[16];          // w_b psi_0(xi_b), w_b psi_1(xi_b)
+    __shared__ double rl4[12], rl3[9];  // reduced rules: xi, w psi_0, w psi_1
     for (int t = threadIdx.x; t < HK_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
     if (threadIdx.x < 8) {
         wsh[threadIdx.x] = wt.wp0[threadIdx.x];
         wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
     }
+    if (threadIdx.x < 12) rl4[threadIdx.x] = wl.r4[threadIdx.x / 4][threadIdx.x % 4];
+    if (threadIdx.x < 9) rl3[threadIdx.x] = wl.r3[threadIdx.x / 3][threadIdx.x % 3];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -96,6 +121,11 @@ __global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 
     const double* __restrict__ qgy = P.gy + 8 * q;
     const double hq = P.h[q], nxq = P.nx[q], nyq = P.ny[q];
     const double k = P.k;
+    // panel q as node + t * edge (for the reduced rules) and its midpoint
+    const int q1 = q + 1 == n ? 0 : q + 1;
+    const double qx0 = P.nodes[2 * q], qy0 = P.nodes[2 * q + 1];
+    const double qex = P.nodes[2 * q1] - qx0, qey = P.nodes[2 * q1 + 1] - qy0;
+    const double qcx = qx0 + 0.5 * qex, qcy = qy0 + 0.5 * qey;
 
     const double2 z = make_double2(0.0, 0.0);
     double2 pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
@@ -109,14 +139,52 @@ __global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 
         double2 D00 = z, D01 = z, D10 = z, D11 = z;
         double2 T00 = z, T01 = z, T10 = z, T11 = z;
         const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
+        // quadrature order for this row panel, uniform over the wavefront
+        const int p1 = p + 1 == n ? 0 : p + 1;
+        const double px0 = P.nodes[2 * p], py0 = P.nodes[2 * p + 1];
+        const double pex = P.nodes[2 * p1] - px0, pey = P.nodes[2 * p1 + 1] - py0;
+        int ord = 0;
         if (active) {
+            const double hm = fmax(hp, hq);
+            const double dist = hypot(px0 + 0.5 * pex - qcx, py0 + 0.5 * pey - qcy) - 0.5 * (hp + hq);
+            ord = 8;
+            if (k * hm <= FAR4_KH && dist >= FAR4_D * hm) ord = 4;
+            if (k * hm <= FAR3_KH && dist >= FAR3_D * hm) ord = 3;
+        }
+        ord = wave_max_int(ord);
+        if (active) {
+            const int no = ord;
+            const double* rx = ord == 4 ? rl4 : rl3;
 #pragma unroll 1
-            for (int a = 0; a < 8; ++a) {
-                const double xa = P.gx[8 * p + a], ya = P.gy[8 * p + a];
+            for (int a = 0; a < no; ++a) {
+                double xa, ya, wa0, wa1;
+                if (no == 8) {
+                    xa = P.gx[8 * p + a];
+                    ya = P.gy[8 * p + a];
+                    wa0 = wsh[a];
+                    wa1 = wsh[8 + a];
+                } else {
+                    xa = px0 + rx[a] * pex;
+                    ya = py0 + rx[a] * pey;
+                    wa0 = rx[no + a];
+                    wa1 = rx[2 * no + a];
+                }
                 double2 Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z;
 #pragma unroll 1
-                for (int b = 0; b < 8; ++b) {
-                    const double dx = xa - qgx[b], dy = ya - qgy[b];
+                for (int b = 0; b < no; ++b) {
+                    double yb, zb, w0, w1;
+                    if (no == 8) {
+                        yb = qgx[b];
+                        zb = qgy[b];
+                        w0 = wsh[b];
+                        w1 = wsh[8 + b];
+                    } else {
+                        yb = qx0 + rx[b] * qex;
+                        zb = qy0 + rx[b] * qey;
+                        w0 = rx[no + b];
+                        w1 = rx[2 * no + b];
+                    }
+                    const double dx = xa - yb, dy = ya - zb;
                     const double R = sqrt(fma(dx, dx, dy * dy));
                     const Bessel01 bs = hk_eval_hot(k * R, tab);
                     const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
@@ -125,7 +193,6 @@ __global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 
                     const double dq = fma(dx, nxq, dy * nyq);
                     const double dp = -fma(dx, nxp, dy * nyp);
                     const double2 cd = cscale(c, dq), ct = cscale(c, dp);
-                    const double w0 = wsh[b], w1 = wsh[8 + b];
                     Sg0 = fma_cr(w0, g, Sg0);
                     Sg1 = fma_cr(w1, g, Sg1);
                     Dg0 = fma_cr(w0, cd, Dg0);
@@ -133,7 +200,6 @@ __global__ __launch_bounds__(64 * WAVES, 3) void asm_far_kernel(FarParams P, W8 
                     Tg0 = fma_cr(w0, ct, Tg0);
                     Tg1 = fma_cr(w1, ct, Tg1);
                 }
-                const double wa0 = wsh[a], wa1 = wsh[8 + a];
                 S00 = fma_cr(wa0, Sg0, S00); S01 = fma_cr(wa0, Sg1, S01);
                 S10 = fma_cr(wa1, Sg0, S10); S11 = fma_cr(wa1, Sg1, S11);
                 D00 = fma_cr(wa0, Dg0, D00); D01 = fma_cr(wa0, Dg1, D01);
@@ -393,28 +459,53 @@ void launch_assemble(Op& op) {
         wt.wp0[a] = op.rule.w[a] * (1.0 - op.rule.xi[a]);
         wt.wp1[a] = op.rule.w[a] * op.rule.xi[a];
     }
+    WLow wlow;
+    {
+        double x4[4], w4[4], x3[3], w3[3];
+        gauss_legendre_01(4, x4, w4);
+        gauss_legendre_01(3, x3, w3);
+        for (int a = 0; a < 4; ++a) {
+            wlow.r4[0][a] = x4[a];
+            wlow.r4[1][a] = w4[a] * (1.0 - x4[a]);
+            wlow.r4[2][a] = w4[a] * x4[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            wlow.r3[0][a] = x3[a];
+            wlow.r3[1][a] = w3[a] * (1.0 - x3[a]);
+            wlow.r3[2][a] = w3[a] * x3[a];
+        }
+    }
     FarParams fp;
     fp.gx = op.gx; fp.gy = op.gy; fp.h = op.h; fp.nx = op.nx; fp.ny = op.ny;
-    fp.tab = c.hk_tab; fp.S = op.S; fp.Nm = op.Nm; fp.D = op.D; fp.k = op.k; fp.n = n;
+    fp.tab = c.hk_tab; fp.nodes = op.nodes; fp.S = op.S; fp.Nm = op.Nm; fp.D = op.D; fp.k = op.k; fp.n = n;
     const int64_t T = (n + TB - 1) / TB;
     fp.nsub = 2;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
     fp.nwork = T * (T + 1) / 2 * fp.nsub;
     const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
-    hipLaunchKernelGGL(asm_far_kernel, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt);
+    {
+        KScope _ks(c, "asm_far");
+        hipLaunchKernelGGL(asm_far_kernel, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+    }
     FDS_HIP_TRY(hipGetLastError());
 
     double2* nb = static_cast<double2*>(c.dmalloc(sizeof(double2) * 24 * (size_t)n));
     NearParams np;
     np.gx = op.gx; np.gy = op.gy; np.h = op.h; np.nx = op.nx; np.ny = op.ny;
     np.tab = c.hk_tab; np.gl32 = c.gl32; np.nb = nb; np.k = op.k; np.n = n;
-    hipLaunchKernelGGL(asm_near_block_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream,
+    {
+        KScope _ks(c, "asm_near");
+        hipLaunchKernelGGL(asm_near_block_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream,
                        np, wt);
+    }
     FDS_HIP_TRY(hipGetLastError());
     BandParams bp;
     bp.h = op.h; bp.nx = op.nx; bp.ny = op.ny; bp.nb = nb;
     bp.S = op.S; bp.Nm = op.Nm; bp.D = op.D; bp.k = op.k; bp.n = n;
-    hipLaunchKernelGGL(asm_band_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
+    {
+        KScope _ks(c, "asm_band");
+        hipLaunchKernelGGL(asm_band_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
+    }
     FDS_HIP_TRY(hipGetLastError());
     c.dfree(nb);   // stream-ordered release (see Ctx::dfree)
 }

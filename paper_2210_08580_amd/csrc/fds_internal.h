@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -40,8 +41,16 @@ __host__ __device__ __forceinline__ double2 cscale(double2 a, double s) { return
 __host__ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 // ------------------------------------------------------------------ context / operator
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
 struct Ctx {
     int device = 0;
+    bool prof = false;                                    // per-kernel event timing on/off
+    std::vector<ProfRec> pending;                         // recorded, not yet resolved
+    std::map<std::string, std::pair<double, int64_t>> acc;  // name -> (total ms, launches)
     hipStream_t stream = nullptr;
     fds_allocator alloc{};
     bool has_alloc = false;
@@ -49,6 +58,28 @@ struct Ctx {
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     void* dmalloc(size_t bytes);
     void dfree(void* p);
+};
+
+// Brackets the launches made during its lifetime with two events on the
+// context's stream when profiling is enabled (the times are resolved lazily).
+struct KScope {
+    Ctx* c = nullptr;
+    const char* name = nullptr;
+    hipEvent_t a = nullptr;
+    KScope(Ctx& ctx, const char* n) {
+        if (!ctx.prof) return;
+        c = &ctx;
+        name = n;
+        if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, ctx.stream) != hipSuccess) a = nullptr;
+    }
+    ~KScope() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, c->stream) == hipSuccess)
+            c->pending.push_back({name, a, b});
+    }
+    KScope(const KScope&) = delete;
+    KScope& operator=(const KScope&) = delete;
 };
 
 enum class Stage : int { Assembled = 1, Filtered = 2, Compressed = 3, Factored = 4 };
@@ -90,14 +121,16 @@ struct Op {
     double2* Vgc = nullptr;       // [n_eff][n]  V_g as complex128
     double2* Bt = nullptr;        // [n_eff][n]  G^{1/2} (V_n^T C)^T (filtered compact part, j coordinates)
     // Gram power workspace: periodic tridiagonal factorisation of G
-    double* gfac = nullptr;       // [4n]
+    double* gfac = nullptr;       // exact cyclic Thomas factors of G [3n+2] (small or irregular meshes)
+    double* gband = nullptr;      // banded G^{-1} [(2 GW + 1) n] (regular meshes)
     double cheb_lo = 0.0, cheb_hi = 0.0;
     // skeleton and Woodbury core
     int32_t rank = 0;
     double2* U = nullptr;         // [rank][n]  U_j = G^{-1/2} U_y
     double2* W = nullptr;         // [rank][n]  row t of W_j = W_y G^{1/2} (stored as W_j^T, n x rank)
     bool owns_uw = false;         // U/W are separate allocations (else views of Vgc/Bt)
-    double2* K = nullptr;         // [rank][rank] LU factors (column-major)
+    double2* K = nullptr;         // [rank][rank] Woodbury core inverse K^{-1} (column-major)
+    double2* Up = nullptr;        // [rank][n]  U_j K^{-1}
     int32_t* piv = nullptr;       // [rank]
     ~Op();
 };

@@ -70,11 +70,67 @@ __device__ int pencil_count(const Pencil& P, double s) {
     return cnt;
 }
 
-// one wavefront per eigenvalue index (first + i)
-__global__ void bisect_kernel(Pencil P, double glo, double ghi, double rtol, double atol, int first, int nw,
-                              double* __restrict__ lam) {
+__device__ __forceinline__ double bcast(double v, int l) {
+    const uint64_t u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Inertia count for the shift s held by this lane; the whole wave walks the
+// same block sequence, so the pencil entries of 64 consecutive block steps are
+// loaded once (one step per lane) and broadcast from registers.
+__device__ int pencil_count_wave(const Pencil& P, double s) {
+    const int n = P.n;
+    const int K = n / 2;
+    const bool odd = (n & 1) != 0;
+    const double tiny = 1e-290;
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    double a = pm(P, 0, s), c = pm(P, n - 1, s), b = pf(P, n - 1, s);
+    int cnt = 0;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        // step k (k0 <= k < K-1) needs f(k), f(n-2-k), m(k+1), m(n-2-k)
+        const int kk = min(k0 + lane, K - 1);
+        const double lo1 = P.lo[kk], go1 = P.go[kk], lo2 = P.lo[n - 2 - kk], go2 = P.go[n - 2 - kk];
+        const double ld1 = P.ld[min(kk + 1, n - 1)], gd1 = P.gd[min(kk + 1, n - 1)];
+        const double ld2 = P.ld[n - 2 - kk], gd2 = P.gd[n - 2 - kk];
+        const int kend = min(64, K - k0);
+        for (int l = 0; l < kend; ++l) {
+            const int k = k0 + l;
+            double det = a * c - b * b;
+            if (fabs(det) < tiny) det = det < 0.0 ? -tiny : tiny;
+            cnt += det < 0.0 ? 1 : (a < 0.0 ? 2 : 0);
+            if (k == K - 1) {
+                if (odd) {
+                    const int sN = (n - 1) / 2;
+                    const double u1 = pf(P, sN - 1, s), u2 = pf(P, sN, s);
+                    const double val = pm(P, sN, s) - (u1 * u1 * c - 2.0 * u1 * u2 * b + u2 * u2 * a) / det;
+                    cnt += val < 0.0 ? 1 : 0;
+                }
+                break;
+            }
+            const double e1 = bcast(lo1, l) - s * bcast(go1, l);
+            const double e2 = bcast(lo2, l) - s * bcast(go2, l);
+            const double m1 = bcast(ld1, l) - s * bcast(gd1, l);
+            const double m2 = bcast(ld2, l) - s * bcast(gd2, l);
+            const double inv = 1.0 / det;
+            const double an = m1 - e1 * e1 * c * inv;
+            const double cn = m2 - e2 * e2 * a * inv;
+            double bn = e1 * e2 * b * inv;
+            if (!odd && k + 1 == K - 1) bn += pf(P, K - 1, s);   // nodes n/2-1 and n/2 are adjacent
+            a = an;
+            b = bn;
+            c = cn;
+        }
+    }
+    return cnt;
+}
+
+// one wavefront per eigenvalue index (first + i)
+__global__ __launch_bounds__(64) void bisect_kernel(Pencil P, double glo, double ghi, double rtol, double atol,
+                                                    int first, int nw, double* __restrict__ lam) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x;
     if (i >= nw) return;
     const int idx = first + i;
     double lo = glo, hi = ghi;
@@ -82,7 +138,7 @@ __global__ void bisect_kernel(Pencil P, double glo, double ghi, double rtol, dou
         const double w = hi - lo;
         if (w <= fmax(rtol * fmax(fabs(lo), fabs(hi)), atol)) break;
         const double s = lo + w * (double)(lane + 1) / 65.0;
-        const int cnt = pencil_count(P, s);
+        const int cnt = pencil_count_wave(P, s);
         const unsigned long long mask = __ballot(cnt > idx);
         const int l = mask ? (__ffsll(mask) - 1) : 64;
         const double nlo = (l == 0) ? lo : lo + w * (double)l / 65.0;
@@ -100,124 +156,202 @@ __device__ __forceinline__ int node_of(int r, int n) {
     return (r & 1) ? n - 1 - (r >> 1) : (r >> 1);
 }
 
-// entries M[node(r)][node(r + d)] for d = -2..2 (zero outside the matrix)
-__device__ void band_row(const Pencil& P, int r, double s, double out[5]) {
+// Folded band of L and of G: entries [t][r] = X[node(r)][node(r + t - 2)], t = 0..4
+// (zero outside the matrix), so that L - sigma G = Lb - sigma Gb in band form.
+__global__ void fold_bands_kernel(Pencil P, double* __restrict__ Lb, double* __restrict__ Gb) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = P.n;
+    if (r >= n) return;
     const int a = node_of(r, n);
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
         const int cpos = r + t - 2;
-        double v = 0.0;
+        double vl = 0.0, vg = 0.0;
         if (cpos >= 0 && cpos < n) {
             const int b = node_of(cpos, n);
-            if (b == a) v = pm(P, a, s);
-            else if (b == (a + 1 == n ? 0 : a + 1)) v = pf(P, a, s);
-            else if (a == (b + 1 == n ? 0 : b + 1)) v = pf(P, b, s);
+            if (b == a) { vl = P.ld[a]; vg = P.gd[a]; }
+            else if (b == (a + 1 == n ? 0 : a + 1)) { vl = P.lo[a]; vg = P.go[a]; }
+            else if (a == (b + 1 == n ? 0 : b + 1)) { vl = P.lo[b]; vg = P.go[b]; }
         }
-        out[t] = v;
+        Lb[(int64_t)t * n + r] = vl;
+        Gb[(int64_t)t * n + r] = vg;
     }
 }
 
 // Banded LU with partial pivoting of the folded L - sigma_i G (thread per eigenvalue).
 // fac layout: [(j*7 + t) * nw + i], t = 0..4: U row j at columns j..j+4, t = 5,6: multipliers.
-__global__ void invit_factor_kernel(Pencil P, const double* __restrict__ sig, int nw, double pivmin,
-                                    double* __restrict__ fac, unsigned char* __restrict__ pv) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    const int n = P.n;
+__device__ __forceinline__ double start_value(int i, int node) {
+    uint64_t z = ((uint64_t)i << 32 | (uint32_t)node) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// Also runs the forward elimination of a pseudo-random right-hand side (the
+// first inverse-iteration step) and stores its result z (node-major) in Z.
+__global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* __restrict__ Lb,
+                                                          const double* __restrict__ Gb,
+                                                          const double* __restrict__ sig, int nw, double pivmin,
+                                                          double* __restrict__ fac, unsigned char* __restrict__ pv,
+                                                          double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63;
+    const int i0 = blockIdx.x * 64 + lane;
+    const int i = min(i0, nw - 1);          // idle lanes repeat the last eigenvalue, store nothing
+    const bool act = i0 < nw;
     const double s = sig[i];
-    double w0[5], w1[5], w2[5], tmp[5];
-    band_row(P, 0, s, tmp);
-    w0[0] = tmp[2]; w0[1] = tmp[3]; w0[2] = tmp[4]; w0[3] = 0.0; w0[4] = 0.0;
-    band_row(P, 1, s, tmp);
-    w1[0] = tmp[1]; w1[1] = tmp[2]; w1[2] = tmp[3]; w1[3] = tmp[4]; w1[4] = 0.0;
-    band_row(P, 2, s, w2);
-    for (int j = 0; j < n; ++j) {
-        const bool v1 = j + 1 < n, v2 = j + 2 < n;
-        int p = 0;
-        double best = fabs(w0[0]);
-        if (v1 && fabs(w1[0]) > best) { p = 1; best = fabs(w1[0]); }
-        if (v2 && fabs(w2[0]) > best) { p = 2; }
-        if (p == 1) {
+    double w0[5], w1[5], w2[5];
+    // rows 0, 1, 2 of the folded band, shifted to the columns 0..4 of the window
 #pragma unroll
-            for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w1[t]; w1[t] = q; }
-        } else if (p == 2) {
+    for (int t = 0; t < 5; ++t) {
+        w0[t] = t + 2 < 5 ? Lb[(int64_t)(t + 2) * n + 0] - s * Gb[(int64_t)(t + 2) * n + 0] : 0.0;
+        w1[t] = t + 1 < 5 ? Lb[(int64_t)(t + 1) * n + 1] - s * Gb[(int64_t)(t + 1) * n + 1] : 0.0;
+        w2[t] = Lb[(int64_t)t * n + 2] - s * Gb[(int64_t)t * n + 2];
+    }
+    double y0 = start_value(i, node_of(0, n)), y1 = start_value(i, node_of(1, n)), y2 = start_value(i, node_of(2, n));
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        // stage band rows j0+3 .. j0+66 (one per lane)
+        const int rr = min(j0 + 3 + lane, n - 1);
+        double lb[5], gb[5];
 #pragma unroll
-            for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w2[t]; w2[t] = q; }
+        for (int t = 0; t < 5; ++t) {
+            lb[t] = Lb[(int64_t)t * n + rr];
+            gb[t] = Gb[(int64_t)t * n + rr];
         }
-        if (fabs(w0[0]) < pivmin) w0[0] = w0[0] < 0.0 ? -pivmin : pivmin;
-        const double inv = 1.0 / w0[0];
-        const double l1 = v1 ? w1[0] * inv : 0.0, l2 = v2 ? w2[0] * inv : 0.0;
+        const int jend = min(n, j0 + 64);
+        for (int j = j0; j < jend; ++j) {
+            const bool v1 = j + 1 < n, v2 = j + 2 < n;
+            int p = 0;
+            double best = fabs(w0[0]);
+            if (v1 && fabs(w1[0]) > best) { p = 1; best = fabs(w1[0]); }
+            if (v2 && fabs(w2[0]) > best) { p = 2; }
+            if (p == 1) {
 #pragma unroll
-        for (int t = 1; t < 5; ++t) {
-            w1[t] -= l1 * w0[t];
-            w2[t] -= l2 * w0[t];
+                for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w1[t]; w1[t] = q; }
+            } else if (p == 2) {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w2[t]; w2[t] = q; }
+            }
+            if (fabs(w0[0]) < pivmin) w0[0] = w0[0] < 0.0 ? -pivmin : pivmin;
+            const double inv = 1.0 / w0[0];
+            const double l1 = v1 ? w1[0] * inv : 0.0, l2 = v2 ? w2[0] * inv : 0.0;
+#pragma unroll
+            for (int t = 1; t < 5; ++t) {
+                w1[t] -= l1 * w0[t];
+                w2[t] -= l2 * w0[t];
+            }
+            if (p == 1) { const double q = y0; y0 = y1; y1 = q; }
+            else if (p == 2) { const double q = y0; y0 = y2; y2 = q; }
+            y1 -= l1 * y0;
+            y2 -= l2 * y0;
+            if (act) {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) fac[((int64_t)j * 7 + t) * nw + i] = w0[t];
+                fac[((int64_t)j * 7 + 5) * nw + i] = l1;
+                fac[((int64_t)j * 7 + 6) * nw + i] = l2;
+                pv[(int64_t)j * nw + i] = (unsigned char)p;
+                Z[(int64_t)node_of(j, n) * nw + i] = y0;
+            }
+            y0 = y1;
+            y1 = y2;
+            y2 = (j + 3 < n) ? start_value(i, node_of(j + 3, n)) : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                w0[t] = w1[t + 1];
+                w1[t] = w2[t + 1];
+            }
+            w0[4] = 0.0;
+            w1[4] = 0.0;
+            const int l = j - j0;
+            if (j + 3 < n) {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) w2[t] = bcast(lb[t], l) - s * bcast(gb[t], l);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) w2[t] = 0.0;
+            }
         }
-#pragma unroll
-        for (int t = 0; t < 5; ++t) fac[((int64_t)j * 7 + t) * nw + i] = w0[t];
-        fac[((int64_t)j * 7 + 5) * nw + i] = l1;
-        fac[((int64_t)j * 7 + 6) * nw + i] = l2;
-        pv[(int64_t)j * nw + i] = (unsigned char)p;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            w0[t] = w1[t + 1];
-            w1[t] = w2[t + 1];
-        }
-        w0[4] = 0.0;
-        w1[4] = 0.0;
-        if (j + 3 < n) band_row(P, j + 3, s, w2);
-        else
-#pragma unroll
-            for (int t = 0; t < 5; ++t) w2[t] = 0.0;
     }
 }
 
-// One inverse-iteration step per eigenvalue: W = G X; X <- M^{-1} W; X /= ||X||_G.
-// X, W: [nw][n] node-indexed vectors.
-__global__ void invit_step_kernel(Pencil P, int nw, const double* __restrict__ fac,
-                                  const unsigned char* __restrict__ pv, double* __restrict__ X,
-                                  double* __restrict__ Wk) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    const int n = P.n;
-    double* x = X + (int64_t)i * n;
-    double* w = Wk + (int64_t)i * n;
-    for (int k = 0; k < n; ++k) {
-        const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-        w[k] = P.gd[k] * x[k] + P.go[km] * x[km] + P.go[k] * x[kp];
-    }
-    // forward elimination on the folded right-hand side; z_j stored at node_of(j)
-    double y0 = w[node_of(0, n)], y1 = w[node_of(1, n)], y2 = w[node_of(2, n)];
-    for (int j = 0; j < n; ++j) {
-        const int p = pv[(int64_t)j * nw + i];
-        if (p == 1) { const double q = y0; y0 = y1; y1 = q; }
-        else if (p == 2) { const double q = y0; y0 = y2; y2 = q; }
-        const double l1 = fac[((int64_t)j * 7 + 5) * nw + i], l2 = fac[((int64_t)j * 7 + 6) * nw + i];
-        y1 -= l1 * y0;
-        y2 -= l2 * y0;
-        x[node_of(j, n)] = y0;
-        y0 = y1;
-        y1 = y2;
-        y2 = (j + 3 < n) ? w[node_of(j + 3, n)] : 0.0;
-    }
+constexpr int IV_CH = 8;   // steps whose operands are loaded ahead of use
+
+// Back substitution U x = z (folded order), z and x node-major [n][nw].
+__global__ __launch_bounds__(64) void invit_back_kernel(int n, int nw, const double* __restrict__ fac,
+                                                        const double* __restrict__ Z, double* __restrict__ X) {
+    const int lane = threadIdx.x & 63;
+    const int i0 = blockIdx.x * 64 + lane;
+    const bool act = i0 < nw;
+    const int i = min(i0, nw - 1);
     double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
-    for (int j = n - 1; j >= 0; --j) {
-        const int nd = node_of(j, n);
-        const double* u = fac + (int64_t)j * 7 * nw + i;
-        const double v = (x[nd] - u[nw] * x1 - u[2 * nw] * x2 - u[3 * nw] * x3 - u[4 * nw] * x4) / u[0];
-        x[nd] = v;
-        x4 = x3;
-        x3 = x2;
-        x2 = x1;
-        x1 = v;
+    for (int j0 = n - 1; j0 >= 0; j0 -= IV_CH) {
+        double u[IV_CH][5], zz[IV_CH];
+#pragma unroll
+        for (int q = 0; q < IV_CH; ++q) {
+            const int j = j0 - q;
+            if (j >= 0) {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) u[q][t] = fac[((int64_t)j * 7 + t) * nw + i];
+                zz[q] = Z[(int64_t)node_of(j, n) * nw + i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IV_CH; ++q) {
+            const int j = j0 - q;
+            if (j < 0) break;
+            const double v = (zz[q] - u[q][1] * x1 - u[q][2] * x2 - u[q][3] * x3 - u[q][4] * x4) / u[q][0];
+            if (act) X[(int64_t)node_of(j, n) * nw + i] = v;
+            x4 = x3;
+            x3 = x2;
+            x2 = x1;
+            x1 = v;
+        }
     }
-    double nrm = 0.0;
-    for (int k = 0; k < n; ++k) {
+}
+
+// Forward elimination of W = G X (computed on the fly), result z into Z.
+__global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int nw, const double* __restrict__ fac,
+                                                       const unsigned char* __restrict__ pv,
+                                                       const double* __restrict__ X, double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63;
+    const int i0 = blockIdx.x * 64 + lane;
+    const bool act = i0 < nw;
+    const int i = min(i0, nw - 1);
+    const int n = P.n;
+    auto gx = [&](int k) {
         const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-        nrm += x[k] * (P.gd[k] * x[k] + P.go[km] * x[km] + P.go[k] * x[kp]);
+        return P.gd[k] * X[(int64_t)k * nw + i] + P.go[km] * X[(int64_t)km * nw + i] +
+               P.go[k] * X[(int64_t)kp * nw + i];
+    };
+    double y0 = gx(node_of(0, n)), y1 = gx(node_of(1, n)), y2 = gx(node_of(2, n));
+    for (int j0 = 0; j0 < n; j0 += IV_CH) {
+        double l1v[IV_CH], l2v[IV_CH], rv[IV_CH];
+        int pvv[IV_CH];
+#pragma unroll
+        for (int q = 0; q < IV_CH; ++q) {
+            const int j = j0 + q;
+            if (j < n) {
+                pvv[q] = pv[(int64_t)j * nw + i];
+                l1v[q] = fac[((int64_t)j * 7 + 5) * nw + i];
+                l2v[q] = fac[((int64_t)j * 7 + 6) * nw + i];
+                rv[q] = (j + 3 < n) ? gx(node_of(j + 3, n)) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IV_CH; ++q) {
+            const int j = j0 + q;
+            if (j >= n) break;
+            const int p = pvv[q];
+            if (p == 1) { const double t = y0; y0 = y1; y1 = t; }
+            else if (p == 2) { const double t = y0; y0 = y2; y2 = t; }
+            y1 -= l1v[q] * y0;
+            y2 -= l2v[q] * y0;
+            if (act) Z[(int64_t)node_of(j, n) * nw + i] = y0;
+            y0 = y1;
+            y1 = y2;
+            y2 = rv[q];
+        }
     }
-    const double sc = 1.0 / sqrt(nrm);
-    for (int k = 0; k < n; ++k) x[k] *= sc;
 }
 
 __device__ double block_sum(double v, double* sh) {
@@ -232,41 +366,47 @@ __device__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// G-inner product Gram-Schmidt inside each cluster [cb[c], cb[c+1]) (workgroup per cluster).
-__global__ void cluster_gs_kernel(Pencil P, const int* __restrict__ cb, double* __restrict__ X) {
+// G-inner product Gram-Schmidt inside each cluster [cb[c], cb[c+1]) (workgroup
+// per cluster); X node-major [n][nw].
+__global__ void cluster_gs_kernel(Pencil P, const int* __restrict__ cb, int nw, double* __restrict__ X) {
     __shared__ double sh[256];
     const int n = P.n;
     const int c0 = cb[blockIdx.x], c1 = cb[blockIdx.x + 1];
     for (int j = c0; j < c1; ++j) {
-        double* xj = X + (int64_t)j * n;
         for (int i = c0; i <= j; ++i) {
-            const double* xi = X + (int64_t)i * n;
             double part = 0.0;
             for (int k = threadIdx.x; k < n; k += blockDim.x) {
                 const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-                part += xi[k] * (P.gd[k] * xj[k] + P.go[km] * xj[km] + P.go[k] * xj[kp]);
+                part += X[(int64_t)k * nw + i] * (P.gd[k] * X[(int64_t)k * nw + j] + P.go[km] * X[(int64_t)km * nw + j] +
+                                                  P.go[k] * X[(int64_t)kp * nw + j]);
             }
             const double dot = block_sum(part, sh);
             if (i < j) {
-                for (int k = threadIdx.x; k < n; k += blockDim.x) xj[k] -= dot * xi[k];
+                for (int k = threadIdx.x; k < n; k += blockDim.x) X[(int64_t)k * nw + j] -= dot * X[(int64_t)k * nw + i];
             } else {
                 const double sc = 1.0 / sqrt(dot);
-                for (int k = threadIdx.x; k < n; k += blockDim.x) xj[k] *= sc;
+                for (int k = threadIdx.x; k < n; k += blockDim.x) X[(int64_t)k * nw + j] *= sc;
             }
             __syncthreads();
         }
     }
 }
 
-__global__ void init_vectors_kernel(double* __restrict__ X, int n, int nw) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * nw) return;
-    uint64_t z = (uint64_t)t * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    X[t] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+// out[c][r] = in[r][c] for a rows x cols row-major input (32 x 32 LDS tiles)
+__global__ void transpose_kernel(const double* __restrict__ in, int rows, int cols, double* __restrict__ out) {
+    __shared__ double t[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int r = by + k, c = bx + threadIdx.x;
+        if (r < rows && c < cols) t[k][threadIdx.x] = in[(int64_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int c = bx + k, r = by + threadIdx.x;
+        if (r < rows && c < cols) out[(int64_t)c * rows + r] = t[threadIdx.x][k];
+    }
 }
+
 
 // ---------------------------------------------------------------- host driver
 void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
@@ -293,6 +433,13 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     const double mnorm = lmax + lam_hi * gmax;
 
     Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, n};
+    double* Lb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
+    double* Gb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
+    {
+        KScope _ks(c, "filter_fold");
+        hipLaunchKernelGGL(fold_bands_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, P, Lb, Gb);
+    }
+    FDS_HIP_TRY(hipGetLastError());
     const int start = keep_null ? 0 : 1;
     int want = keep_null ? n_modes : n_modes - 1;
     FDS_REQUIRE(want >= 1 && start + want <= n, FDS_ERR_ARG, "n_modes out of range");
@@ -303,9 +450,11 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     for (;;) {
         nw = std::min(n - start, want + extra);
         double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
-        const int wpb = 4;
-        hipLaunchKernelGGL(bisect_kernel, dim3((nw + wpb - 1) / wpb), dim3(64 * wpb), 0, c.stream, P,
-                           -1e-3 * lam_hi, lam_hi, 4e-15, 4e-16 * lam_hi, start, nw, dlam);
+        {
+            KScope _ks(c, "filter_bisect");
+            hipLaunchKernelGGL(bisect_kernel, dim3(nw), dim3(64), 0, c.stream, P, -1e-3 * lam_hi, lam_hi, 4e-15,
+                               4e-16 * lam_hi, start, nw, dlam);
+        }
         FDS_HIP_TRY(hipGetLastError());
         lam.assign(nw, 0.0);
         FDS_HIP_TRY(hipMemcpyAsync(lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost, c.stream));
@@ -340,42 +489,61 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     FDS_HIP_TRY(hipMemcpyAsync(dcb, cb.data(), sizeof(int) * (ncl + 1), hipMemcpyHostToDevice, c.stream));
     double* fac = static_cast<double*>(c.dmalloc(sizeof(double) * 7 * (size_t)n * ne));
     unsigned char* pv = static_cast<unsigned char*>(c.dmalloc((size_t)n * ne));
-    double* X = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
+    double* Xn = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));   // node-major
     double* Wk = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
-    hipLaunchKernelGGL(init_vectors_kernel, dim3((unsigned)(((int64_t)n * ne + 255) / 256)), dim3(256), 0,
-                       c.stream, X, n, ne);
+    const unsigned ewaves = (unsigned)((ne + 63) / 64);
+    {
+        KScope _ks(c, "filter_invit_factor");
+        hipLaunchKernelGGL(invit_factor_kernel, dim3(ewaves), dim3(64), 0, c.stream, n, Lb, Gb, dsig, ne,
+                           1e-15 * mnorm, fac, pv, Wk);
+    }
     FDS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(invit_factor_kernel, dim3((ne + 63) / 64), dim3(64), 0, c.stream, P, dsig, ne,
-                       1e-15 * mnorm, fac, pv);
-    FDS_HIP_TRY(hipGetLastError());
-    for (int it = 0; it < 3; ++it) {
-        hipLaunchKernelGGL(invit_step_kernel, dim3((ne + 63) / 64), dim3(64), 0, c.stream, P, ne, fac, pv, X,
-                           Wk);
+    // inverse iteration from a pseudo-random right-hand side: two solves; the
+    // shifts are accurate to ~1e-13 relative, so each solve removes the other
+    // eigen-components to that level (Gram-Schmidt inside clusters after each)
+    for (int it = 0; it < 2; ++it) {
+        if (it > 0) {
+            KScope _ks(c, "filter_invit_fwd");
+            hipLaunchKernelGGL(invit_fwd_kernel, dim3(ewaves), dim3(64), 0, c.stream, P, ne, fac, pv, Xn, Wk);
+        }
         FDS_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(cluster_gs_kernel, dim3(ncl), dim3(256), 0, c.stream, P, dcb, X);
+        {
+            KScope _ks(c, "filter_invit_back");
+            hipLaunchKernelGGL(invit_back_kernel, dim3(ewaves), dim3(64), 0, c.stream, n, ne, fac, Wk, Xn);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        {
+            KScope _ks(c, "filter_cluster_gs");
+            hipLaunchKernelGGL(cluster_gs_kernel, dim3(ncl), dim3(256), 0, c.stream, P, dcb, ne, Xn);
+        }
         FDS_HIP_TRY(hipGetLastError());
     }
-    // CholeskyQR (twice) in the G inner product: V <- V R^{-1}, R^T R = V^T G V
+    // to vector-major (each eigenvector contiguous)
+    double* X = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
+    {
+        KScope _ks(c, "transpose");
+        hipLaunchKernelGGL(transpose_kernel, dim3((ne + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, c.stream, Xn, n,
+                           ne, X);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    // Newton-Schulz in the G inner product: with M = V^T G V = I + E (|E| ~ 1e-12 after
+    // the inverse iteration), V <- V (3I - M)/2 leaves V^T G V = I + O(E^2).
     double* M = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)ne * ne));
-    int* info = static_cast<int*>(c.dmalloc(sizeof(int)));
     for (int pass = 0; pass < 2; ++pass) {
         gram_mul<double>(c, op.g_diag, op.g_off, n, X, ne, n, 1.0, 0.0, Wk, n);
         dgemm(c, OP_T, OP_N, ne, ne, n, 1.0, X, n, Wk, n, 0.0, M, ne);
-        FDS_HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), c.stream));
-        chol_upper(c, M, ne, info);
-        trsm_right_upper(c, M, ne, X, n);
+        dgemm(c, OP_N, OP_N, n, ne, ne, -0.5, X, n, M, ne, 0.0, Xn, n);
+        daxpby(c, 1.0, Xn, 1.5, X, (int64_t)n * ne);
     }
-    int hinfo = 0;
-    FDS_HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
     c.dfree(M);
-    c.dfree(info);
     c.dfree(Wk);
+    c.dfree(Xn);
     c.dfree(fac);
     c.dfree(pv);
     c.dfree(dsig);
     c.dfree(dcb);
-    FDS_REQUIRE(hinfo == 0, FDS_ERR_SINGULAR, "filter basis lost G-orthogonality (Cholesky failed)");
+    c.dfree(Lb);
+    c.dfree(Gb);
     c.dfree(op.Vg);
     c.dfree(op.Vn);
     op.Vn = nullptr;

@@ -170,11 +170,17 @@ void launch_geometry(Op& op) {
     const int n = (int)op.n;
     Rule8Arg r;
     for (int a = 0; a < 8; ++a) r.xi[a] = op.rule.xi[a];
-    hipLaunchKernelGGL(geometry_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, op.ctx->stream,
+    {
+        KScope _ks(*op.ctx, "geometry");
+        hipLaunchKernelGGL(geometry_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, op.ctx->stream,
                        op.nodes, n, r, op.h, op.nx, op.ny, op.gx, op.gy);
+    }
     FDS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(sparse_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, op.ctx->stream,
+    {
+        KScope _ks(*op.ctx, "geometry");
+        hipLaunchKernelGGL(sparse_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, op.ctx->stream,
                        op.h, n, op.g_diag, op.g_off, op.l_diag, op.l_off);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
@@ -186,21 +192,30 @@ void launch_rhs_planewave(Op& op, const double* angles, const double2* amps, int
         xr.xi[a] = op.rule.xi[a];
     }
     const int64_t tot = op.n * nrhs;
-    hipLaunchKernelGGL(rhs_planewave_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0,
+    {
+        KScope _ks(*op.ctx, "rhs_planewave");
+        hipLaunchKernelGGL(rhs_planewave_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0,
                        op.ctx->stream, op.gx, op.gy, op.h, op.nx, op.ny, (int)op.n, op.k, wr, xr,
                        angles, amps, nrhs, f, hh);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out) {
-    hipLaunchKernelGGL(hankel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
+    {
+        KScope _ks(c, "hankel_eval");
+        hipLaunchKernelGGL(hankel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
                        c.hk_tab, out);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out) {
-    hipLaunchKernelGGL(kernel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, k, R,
+    {
+        KScope _ks(c, "kernel_eval");
+        hipLaunchKernelGGL(kernel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, k, R,
                        n, c.hk_tab, out);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 

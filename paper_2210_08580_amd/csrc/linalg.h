@@ -22,6 +22,10 @@ void gram_solve(Ctx& c, const double* e, const double* fac, int n, T* X, int64_t
 template <typename T>
 void gram_mul(Ctx& c, const double* d, const double* e, int n, const T* X, int64_t ncols, int64_t ldx,
               double a, double b, T* Y, int64_t ldy);
+constexpr int GW = 64;   // half-bandwidth of the truncated G^{-1}
+void gram_band_build(Ctx& c, const double* d, const double* e, int n, double* band /* (2GW+1) n */);
+template <typename T>
+void gram_band_apply(Ctx& c, const double* band, int n, const T* X, int64_t ncols, T* Y);
 std::vector<double> cheb_coeffs(int p, double lo, double hi);
 template <typename T>
 void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p, T* X,
@@ -30,10 +34,12 @@ void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, d
 // Small dense factorisations (one workgroup).
 void chol_upper(Ctx& c, double* A, int n, int* info);
 void trsm_right_upper(Ctx& c, const double* R, int n, double* X, int64_t rows);
+void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats /* [min|pivot|, max|A|] */);
 void lu_factor(Ctx& c, double2* A, int n, int* piv, double* stats /* [min|pivot|, max|A|] */);
 void lu_solve(Ctx& c, const double2* LU, const int* piv, int n, double2* B, int64_t ncols);
 
 void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n);
+void daxpby(Ctx& c, double a, const double* x, double b, double* y, int64_t n);
 void axpby(Ctx& c, double2 a, const double2* x, double2 b, double2* y, int64_t n);
 void add_diag(Ctx& c, double2* A, int n, double s);
 

@@ -202,13 +202,19 @@ static void gemm_dispatch(Ctx& c, int m, int n, int k, typename Elt<CPLX>::T alp
     nz = (k + kchunk - 1) / kchunk;
     T* part = nullptr;
     if (nz > 1) part = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
-    hipLaunchKernelGGL((gemm_kernel<CPLX, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+    {
+        KScope _ks(c, "gemm");
+        hipLaunchKernelGGL((gemm_kernel<CPLX, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+    }
     FDS_HIP_TRY(hipGetLastError());
     if (part) {
         const int64_t tot = (int64_t)m * n;
+        {
+        KScope _ks(c, "gemm_splitk_reduce");
         hipLaunchKernelGGL(splitk_reduce_kernel<CPLX>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                            c.stream, m, n, nz, alpha, part, beta, C, ldc);
+    }
         FDS_HIP_TRY(hipGetLastError());
         c.dfree(part);
     }
@@ -320,15 +326,21 @@ __global__ void gram_mul_kernel(const double* __restrict__ d, const double* __re
 }
 
 void gram_factor(Ctx& c, const double* d, const double* e, int n, double* fac) {
-    hipLaunchKernelGGL(gram_factor_kernel, dim3(1), dim3(64), 0, c.stream, d, e, n, fac);
+    {
+        KScope _ks(c, "gram_factor");
+        hipLaunchKernelGGL(gram_factor_kernel, dim3(1), dim3(64), 0, c.stream, d, e, n, fac);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 template <typename T>
 void gram_solve(Ctx& c, const double* e, const double* fac, int n, T* X, int64_t ncols, int64_t ld) {
     if (ncols <= 0) return;
-    hipLaunchKernelGGL(gram_solve_kernel<T>, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, e, fac,
+    {
+        KScope _ks(c, "gram_solve");
+        hipLaunchKernelGGL(gram_solve_kernel<T>, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, e, fac,
                        n, X, ncols, ld);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 template void gram_solve<double>(Ctx&, const double*, const double*, int, double*, int64_t, int64_t);
@@ -339,14 +351,101 @@ void gram_mul(Ctx& c, const double* d, const double* e, int n, const T* X, int64
               double a, double b, T* Y, int64_t ldy) {
     const int64_t tot = (int64_t)n * ncols;
     if (tot <= 0) return;
-    hipLaunchKernelGGL(gram_mul_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, d, e, n,
+    {
+        KScope _ks(c, "gram_mul");
+        hipLaunchKernelGGL(gram_mul_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, d, e, n,
                        X, ncols, ldx, a, b, Y, ldy);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 template void gram_mul<double>(Ctx&, const double*, const double*, int, const double*, int64_t, int64_t, double,
                                double, double*, int64_t);
 template void gram_mul<double2>(Ctx&, const double*, const double*, int, const double2*, int64_t, int64_t,
                                 double, double, double2*, int64_t);
+
+// ------------------------------------------------------------ banded G^{-1}
+// G is strongly diagonally dominant: each row satisfies |e_{i-1}| + |e_i| =
+// d_i / 2, and the elimination multipliers e_i / (d_i - e_{i-1} c_{i-1}) stay
+// below 1/2 for any panel lengths. Entries of G^{-1} therefore decay at least
+// like 2^{-|i-j|} away from the (periodic) diagonal, and G^{-1} restricted to
+// the band |i - j| <= GW (GW = 64) equals G^{-1} to a relative 2^{-64}.
+// Row i of the band is computed by a Thomas solve of G x = e_i on the window
+// i-GW .. i+GW (periodic indices, couplings outside the window dropped), whose
+// truncation error is of the same order. band layout: [t][i], t = k + GW.
+__global__ void gram_band_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                 double* __restrict__ band, double* __restrict__ scr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int M = 2 * GW + 1;
+    double* cp = scr;                 // [M][n]
+    double* z = scr + (int64_t)M * n; // [M][n]
+    double cprev = 0.0, zprev = 0.0;
+    for (int t = 0; t < M; ++t) {
+        int j = i + t - GW;
+        j = j < 0 ? j + n : (j >= n ? j - n : j);
+        const int jm = j == 0 ? n - 1 : j - 1;
+        const double lower = t > 0 ? e[jm] : 0.0;
+        const double den = d[j] - lower * cprev;
+        const double upper = t < M - 1 ? e[j] : 0.0;
+        const double cpt = upper / den;
+        const double rhs = t == GW ? 1.0 : 0.0;
+        const double zt = (rhs - lower * zprev) / den;
+        cp[(int64_t)t * n + i] = cpt;
+        z[(int64_t)t * n + i] = zt;
+        cprev = cpt;
+        zprev = zt;
+    }
+    double x = 0.0;
+    for (int t = M - 1; t >= 0; --t) {
+        x = z[(int64_t)t * n + i] - cp[(int64_t)t * n + i] * x;
+        band[(int64_t)t * n + i] = x;
+    }
+}
+
+// Y = G^{-1} X (out of place) with the band: workgroup = 256 rows of one vector.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_band_apply_kernel(const double* __restrict__ band, int n,
+                                                              const T* __restrict__ X, T* __restrict__ Y) {
+    __shared__ T xs[256 + 2 * GW];
+    const int64_t col = blockIdx.y;
+    const int r0 = blockIdx.x * 256;
+    const T* x = X + col * n;
+    for (int t = threadIdx.x; t < 256 + 2 * GW; t += 256) {
+        int j = r0 - GW + t;
+        j = ((j % n) + n) % n;
+        xs[t] = x[j];
+    }
+    __syncthreads();
+    const int i = r0 + threadIdx.x;
+    if (i >= n) return;
+    T acc{};
+#pragma unroll 8
+    for (int t = 0; t < 2 * GW + 1; ++t) acc = acc + xs[threadIdx.x + t] * band[(int64_t)t * n + i];
+    Y[col * n + i] = acc;
+}
+
+void gram_band_build(Ctx& c, const double* d, const double* e, int n, double* band) {
+    double* scr = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * (2 * GW + 1) * (size_t)n));
+    {
+        KScope _ks(c, "gram_band_build");
+        hipLaunchKernelGGL(gram_band_kernel, dim3((n + 127) / 128), dim3(128), 0, c.stream, d, e, n, band, scr);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(scr);
+}
+
+template <typename T>
+void gram_band_apply(Ctx& c, const double* band, int n, const T* X, int64_t ncols, T* Y) {
+    if (ncols <= 0) return;
+    {
+        KScope _ks(c, "gram_inv");
+        hipLaunchKernelGGL(gram_band_apply_kernel<T>, dim3((n + 255) / 256, (unsigned)ncols), dim3(256), 0,
+                           c.stream, band, n, X, Y);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+template void gram_band_apply<double>(Ctx&, const double*, int, const double*, int64_t, double*);
+template void gram_band_apply<double2>(Ctx&, const double*, int, const double2*, int64_t, double2*);
 
 // ============================================================ Chebyshev G^{p/2}
 // f(x) = x^{p/2} on [lo, hi] expanded in Chebyshev polynomials of
@@ -409,16 +508,22 @@ void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, d
     // rotate: cur = b_j, p1 = b_{j+1}, p2 = b_{j+2}
     int cur = 0, p1 = 1, p2 = 2;
     for (int j = deg; j >= 1; --j) {
+        {
+        KScope _ks(c, "gram_pow_half");
         hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
                            bufs[cur], ncols, a[j], s1, s0, 2.0);
+    }
         FDS_HIP_TRY(hipGetLastError());
         const int t = p2;
         p2 = p1;
         p1 = cur;
         cur = t;
     }
-    hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
+    {
+        KScope _ks(c, "gram_pow_half");
+        hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
                        bufs[cur], ncols, a[0], s1, s0, 1.0);
+    }
     FDS_HIP_TRY(hipGetLastError());
     FDS_HIP_TRY(hipMemcpyAsync(X, bufs[cur], bytes, hipMemcpyDeviceToDevice, c.stream));
     for (int i = 0; i < 3; ++i) c.dfree(bufs[i]);
@@ -547,6 +652,208 @@ __global__ void lu_kernel(double2* __restrict__ A, int n, int* __restrict__ piv,
     }
 }
 
+// Gauss-Jordan inverse with partial pivoting of a complex r x r column-major
+// matrix (one workgroup). A is overwritten; Ainv receives A^{-1}.
+// stats[0] = min |pivot|, stats[1] = max |A| (before elimination).
+__global__ void gj_inverse_kernel(double2* __restrict__ A, double2* __restrict__ Ainv, int r,
+                                  double* __restrict__ stats) {
+    extern __shared__ double2 fcol[];          // r entries: column j before elimination
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    __shared__ int prow;
+    double mx = 0.0;
+    for (int64_t t = threadIdx.x; t < (int64_t)r * r; t += blockDim.x) {
+        mx = fmax(mx, hypot(A[t].x, A[t].y));
+        Ainv[t] = make_double2((t % r) == (t / r) ? 1.0 : 0.0, 0.0);
+    }
+    sv[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[1] = sv[0];
+        stats[0] = 1e300;
+    }
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        double best = -1.0;
+        int bi = j;
+        for (int i = j + threadIdx.x; i < r; i += blockDim.x) {
+            const double2 v = A[i + (int64_t)j * r];
+            const double av = fabs(v.x) + fabs(v.y);
+            if (av > best) {
+                best = av;
+                bi = i;
+            }
+        }
+        sv[threadIdx.x] = best;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+            if (threadIdx.x < s2) {
+                const double o = sv[threadIdx.x + s2];
+                const int oi = si[threadIdx.x + s2];
+                if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sv[threadIdx.x] = o;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) prow = si[0];
+        __syncthreads();
+        const int p = prow;
+        if (p != j)
+            for (int cc = threadIdx.x; cc < 2 * r; cc += blockDim.x) {
+                double2* M = cc < r ? A : Ainv;
+                const int col = cc < r ? cc : cc - r;
+                const double2 t = M[j + (int64_t)col * r];
+                M[j + (int64_t)col * r] = M[p + (int64_t)col * r];
+                M[p + (int64_t)col * r] = t;
+            }
+        __syncthreads();
+        const double2 pv = A[j + (int64_t)j * r];
+        const double den = pv.x * pv.x + pv.y * pv.y;
+        const double2 pinv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0.0, 0.0);
+        if (threadIdx.x == 0) stats[0] = fmin(stats[0], sqrt(den));
+        __syncthreads();
+        for (int cc = threadIdx.x; cc < 2 * r; cc += blockDim.x) {
+            double2* M = cc < r ? A : Ainv;
+            const int col = cc < r ? cc : cc - r;
+            M[j + (int64_t)col * r] = cmul(M[j + (int64_t)col * r], pinv);
+        }
+        for (int i = threadIdx.x; i < r; i += blockDim.x) fcol[i] = A[i + (int64_t)j * r];
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < (int64_t)r * 2 * r; t += blockDim.x) {
+            const int i = (int)(t % r);
+            const int cc = (int)(t / r);
+            if (i == j) continue;
+            double2* M = cc < r ? A : Ainv;
+            const int col = cc < r ? cc : cc - r;
+            if (cc < r && col < j) continue;          // already eliminated columns stay zero
+            const double2 f = fcol[i];
+            M[i + (int64_t)col * r] = csub(M[i + (int64_t)col * r], cmul(f, M[j + (int64_t)col * r]));
+        }
+        __syncthreads();
+    }
+}
+
+// One Gauss-Jordan step with partial pivoting on the augmented r x 2r matrix
+// [A | X] (column-major, ld r), out of place (ping-pong buffers): every
+// workgroup finds the same pivot in column j, then updates its own slab of
+// GJ_CW columns. pabs[j] receives |pivot|.
+constexpr int GJ_CW = 16;
+__global__ __launch_bounds__(256) void gj_step_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout,
+                                                      int r, int j, double* __restrict__ pabs) {
+    extern __shared__ double2 col[];     // column j of Min (r entries)
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    for (int i = threadIdx.x; i < r; i += blockDim.x) col[i] = Min[i + (int64_t)j * r];
+    __syncthreads();
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + threadIdx.x; i < r; i += blockDim.x) {
+        const double av = fabs(col[i].x) + fabs(col[i].y);
+        if (av > best) {
+            best = av;
+            bi = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) {
+            const double o = sv[threadIdx.x + s2];
+            const int oi = si[threadIdx.x + s2];
+            if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                sv[threadIdx.x] = o;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int p = si[0];
+    const double2 pv = col[p];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const double2 pinv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0.0, 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) pabs[j] = sqrt(den);
+    const int c0 = blockIdx.x * GJ_CW;
+    for (int t = threadIdx.x; t < GJ_CW * r; t += blockDim.x) {
+        const int i = t % r;
+        const int cc = c0 + t / r;
+        if (cc >= 2 * r) continue;
+        const double2 prow = cmul(Min[p + (int64_t)cc * r], pinv);   // scaled pivot row
+        double2 v;
+        if (i == j) {
+            v = prow;
+        } else {
+            const int src = (i == p) ? j : i;                        // rows j and p swapped
+            v = csub(Min[src + (int64_t)cc * r], cmul(col[src], prow));
+        }
+        Mout[i + (int64_t)cc * r] = v;
+    }
+}
+
+__global__ void gj_init_kernel(const double2* __restrict__ A, double2* __restrict__ M, int r) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * (int64_t)r * r) return;
+    const int i = (int)(t % r);
+    const int64_t cc = t / r;
+    M[t] = cc < r ? A[t] : make_double2(i == (int)(cc - r) ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void gj_stats_kernel(const double2* __restrict__ A, const double* __restrict__ pabs, int r,
+                                double* __restrict__ stats) {
+    __shared__ double smax[256], smin[256];
+    double mx = 0.0, mn = 1e300;
+    for (int64_t t = threadIdx.x; t < (int64_t)r * r; t += blockDim.x) mx = fmax(mx, hypot(A[t].x, A[t].y));
+    for (int t = threadIdx.x; t < r; t += blockDim.x) mn = fmin(mn, pabs[t]);
+    smax[threadIdx.x] = mx;
+    smin[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s2]);
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s2]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[0] = smin[0];
+        stats[1] = smax[0];
+    }
+}
+
+void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats) {
+    // augmented [A | I] ping-pong; the inverse ends in the right half
+    double2* M0 = static_cast<double2*>(c.dmalloc(sizeof(double2) * 2 * (size_t)r * r));
+    double2* M1 = static_cast<double2*>(c.dmalloc(sizeof(double2) * 2 * (size_t)r * r));
+    double* pabs = static_cast<double*>(c.dmalloc(sizeof(double) * r));
+    const int64_t tot = 2 * (int64_t)r * r;
+    {
+        KScope _ks(c, "gj_inverse");
+        hipLaunchKernelGGL(gj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, A, M0, r);
+        const unsigned nb = (unsigned)((2 * r + GJ_CW - 1) / GJ_CW);
+        for (int j = 0; j < r; ++j) {
+            const double2* in = (j & 1) ? M1 : M0;
+            double2* out = (j & 1) ? M0 : M1;
+            hipLaunchKernelGGL(gj_step_kernel, dim3(nb), dim3(256), sizeof(double2) * r, c.stream, in, out, r, j,
+                               pabs);
+        }
+        hipLaunchKernelGGL(gj_stats_kernel, dim3(1), dim3(256), 0, c.stream, A, pabs, r, stats);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    const double2* fin = (r & 1) ? M1 : M0;
+    FDS_HIP_TRY(hipMemcpyAsync(Ainv, fin + (size_t)r * r, sizeof(double2) * (size_t)r * r, hipMemcpyDeviceToDevice,
+                               c.stream));
+    c.dfree(M0);
+    c.dfree(M1);
+    c.dfree(pabs);
+}
+
 // Solve LU x = P b for each column of B (n x ncols, ld = n), thread per column.
 __global__ void lu_solve_kernel(const double2* __restrict__ LU, const int* __restrict__ piv, int n,
                                 double2* __restrict__ B, int64_t ncols) {
@@ -575,25 +882,37 @@ __global__ void lu_solve_kernel(const double2* __restrict__ LU, const int* __res
 }
 
 void chol_upper(Ctx& c, double* A, int n, int* info) {
-    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, info);
+    {
+        KScope _ks(c, "chol");
+        hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, info);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void trsm_right_upper(Ctx& c, const double* R, int n, double* X, int64_t rows) {
-    hipLaunchKernelGGL(trsm_right_upper_kernel, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, c.stream, R,
+    {
+        KScope _ks(c, "trsm");
+        hipLaunchKernelGGL(trsm_right_upper_kernel, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, c.stream, R,
                        n, X, rows);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void lu_factor(Ctx& c, double2* A, int n, int* piv, double* stats) {
-    hipLaunchKernelGGL(lu_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, piv, stats);
+    {
+        KScope _ks(c, "lu_factor");
+        hipLaunchKernelGGL(lu_kernel, dim3(1), dim3(1024), 0, c.stream, A, n, piv, stats);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void lu_solve(Ctx& c, const double2* LU, const int* piv, int n, double2* B, int64_t ncols) {
     if (ncols <= 0) return;
-    hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, LU, piv, n, B,
+    {
+        KScope _ks(c, "lu_solve");
+        hipLaunchKernelGGL(lu_solve_kernel, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, c.stream, LU, piv, n, B,
                        ncols);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
@@ -610,15 +929,35 @@ __global__ void axpby_kernel(double2 a, const double2* __restrict__ x, double2 b
     if (t < n) y[t] = cadd(cmul(a, x[t]), cmul(b, y[t]));
 }
 
+__global__ void daxpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a * x[t] + b * y[t];
+}
+
+void daxpby(Ctx& c, double a, const double* x, double b, double* y, int64_t n) {
+    if (n <= 0) return;
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(daxpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, x, b, y, n);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
 void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(real_to_complex_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, x, y, n);
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(real_to_complex_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, x, y, n);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
 void axpby(Ctx& c, double2 a, const double2* x, double2 b, double2* y, int64_t n) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, x, b, y, n);
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, a, x, b, y, n);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
@@ -629,7 +968,10 @@ __global__ void add_diag_kernel(double2* __restrict__ A, int n, double s) {
 }
 
 void add_diag(Ctx& c, double2* A, int n, double s) {
-    hipLaunchKernelGGL(add_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, A, n, s);
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(add_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, A, n, s);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 

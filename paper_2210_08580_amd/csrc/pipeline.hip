@@ -55,15 +55,59 @@ __global__ void gnorm_kernel(const double* __restrict__ d, const double* __restr
 }
 
 static void gnorms(Op& op, const double2* X, int64_t ncols, double* out) {
-    hipLaunchKernelGGL(gnorm_kernel, dim3((unsigned)ncols), dim3(256), 0, op.ctx->stream, op.g_diag, op.g_off,
+    {
+        KScope _ks(*op.ctx, "gnorm");
+        hipLaunchKernelGGL(gnorm_kernel, dim3((unsigned)ncols), dim3(256), 0, op.ctx->stream, op.g_diag, op.g_off,
                        (int)op.n, X, ncols, out);
+    }
     FDS_HIP_TRY(hipGetLastError());
 }
 
+// G^{-1}: banded inverse when every consecutive panel-length ratio is below 4.5
+// (then the truncation error of the band is below 1e-18 relative, see
+// gram_band_kernel), the exact cyclic Thomas algorithm otherwise.
 void ensure_gram_factor(Op& op) {
-    if (op.gfac) return;
-    op.gfac = static_cast<double*>(op.ctx->dmalloc(sizeof(double) * (3 * (size_t)op.n + 2)));
-    gram_factor(*op.ctx, op.g_diag, op.g_off, (int)op.n, op.gfac);
+    if (op.gfac || op.gband) return;
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    bool band = n > 4 * GW;
+    if (band) {
+        std::vector<double> h(n);
+        FDS_HIP_TRY(hipMemcpyAsync(h.data(), op.h, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        for (int i = 0; i < n && band; ++i) {
+            const double a = h[i == 0 ? n - 1 : i - 1], b = h[i];
+            if (a > 4.5 * b || b > 4.5 * a) band = false;
+        }
+    }
+    if (band) {
+        op.gband = static_cast<double*>(c.dmalloc(sizeof(double) * (2 * GW + 1) * (size_t)n));
+        gram_band_build(c, op.g_diag, op.g_off, n, op.gband);
+    } else {
+        op.gfac = static_cast<double*>(c.dmalloc(sizeof(double) * (3 * (size_t)n + 2)));
+        gram_factor(c, op.g_diag, op.g_off, n, op.gfac);
+    }
+}
+
+// Y = G^{-1} X for ncols vectors (Y may alias X)
+void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y) {
+    ensure_gram_factor(op);
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const size_t bytes = sizeof(double2) * (size_t)n * ncols;
+    if (op.gband) {
+        if (X == Y) {
+            double2* t = static_cast<double2*>(c.dmalloc(bytes));
+            FDS_HIP_TRY(hipMemcpyAsync(t, X, bytes, hipMemcpyDeviceToDevice, c.stream));
+            gram_band_apply<double2>(c, op.gband, n, t, ncols, Y);
+            c.dfree(t);
+        } else {
+            gram_band_apply<double2>(c, op.gband, n, X, ncols, Y);
+        }
+        return;
+    }
+    if (X != Y) FDS_HIP_TRY(hipMemcpyAsync(Y, X, bytes, hipMemcpyDeviceToDevice, c.stream));
+    gram_solve<double2>(c, op.g_off, op.gfac, n, Y, ncols, n);
 }
 
 void ensure_cheb_bounds(Op& op) {
@@ -86,8 +130,7 @@ void ensure_cheb_bounds(Op& op) {
 
 void apply_gram_power(Op& op, int p, double2* X, int64_t ncols) {
     if (p == -2) {
-        ensure_gram_factor(op);
-        gram_solve<double2>(*op.ctx, op.g_off, op.gfac, (int)op.n, X, ncols, op.n);
+        gram_inv(op, X, ncols, X);
         return;
     }
     FDS_REQUIRE(p == 1 || p == -1, FDS_ERR_ARG, "p must be -2, -1 or 1");
@@ -125,7 +168,7 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
         // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
         double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
         zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.S, n, op.Vgc, n, kZero, X, n);
-        gram_solve<double2>(c, op.g_off, op.gfac, n, X, ne, n);
+        gram_inv(op, X, ne, X);
         zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.Nm, n, X, n, kZero, op.Bt, n);
         gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X, n);
         axpby(c, kOne, X, kOne, op.Bt, (int64_t)n * ne);
@@ -168,37 +211,43 @@ void run_factor(Op& op) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n, r = op.rank;
     c.dfree(op.K);
-    c.dfree(op.piv);
-    op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(r, 1) * std::max(r, 1)));
-    op.piv = static_cast<int*>(c.dmalloc(sizeof(int) * std::max(r, 1)));
+    c.dfree(op.Up);
+    op.K = nullptr;
+    op.Up = nullptr;
     if (r == 0) {
         op.stage = Stage::Factored;
         return;
     }
+    FDS_REQUIRE(r <= 4096, FDS_ERR_NOTIMPL, "skeleton rank above 4096");
     // K = I + beta^{-1} W_j U_j ; W_j = Bt^T (stored as n x r column-major "W^T")
-    zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, op.K, r);
-    add_diag(c, op.K, r, 1.0);
+    double2* K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
+    zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, K, r);
+    add_diag(c, K, r, 1.0);
+    op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
     double* st = static_cast<double*>(c.dmalloc(sizeof(double) * 2));
-    lu_factor(c, op.K, r, op.piv, st);
+    gj_inverse(c, K, op.K, r, st);
     double hs[2];
     FDS_HIP_TRY(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
     FDS_HIP_TRY(hipStreamSynchronize(c.stream));
     c.dfree(st);
+    c.dfree(K);
     FDS_REQUIRE(hs[0] >= 64.0 * 2.220446049250313e-16 * hs[1], FDS_ERR_SINGULAR,
                 "Woodbury core is numerically singular");
+    // fold the core into U: Up = U K^{-1}
+    op.Up = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
+    zgemm(c, OP_N, OP_N, n, r, r, kOne, op.U, n, op.K, r, kZero, op.Up, n);
     op.stage = Stage::Factored;
 }
 
-// x <- Woodbury solve of (beta I + U W) x = b, in place on b (n x nrhs); z: r x nrhs scratch
+// b <- Woodbury solve of (beta I + U W) x = b, in place on b (n x nrhs); z: r x nrhs scratch
+//      x = b/beta - (U K^{-1}) (W b) / beta^2
 static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n, r = op.rank;
     const double ib = 1.0 / op.beta;
     if (r > 0) {
         zgemm(c, OP_T, OP_N, r, (int)nrhs, n, kOne, op.W, n, b, n, kZero, z, r);
-        lu_solve(c, op.K, op.piv, r, z, nrhs);
-        // b <- b/beta - U z / beta^2
-        zgemm(c, OP_N, OP_N, n, (int)nrhs, r, make_double2(-ib * ib, 0.0), op.U, n, z, r,
+        zgemm(c, OP_N, OP_N, n, (int)nrhs, r, make_double2(-ib * ib, 0.0), op.Up, n, z, r,
               make_double2(ib, 0.0), b, n);
     } else {
         axpby(c, kZero, b, make_double2(ib, 0.0), b, (int64_t)n * nrhs);
@@ -216,16 +265,14 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
     // ---- right-hand side in j coordinates
     if (op.form == FDS_EFIE || op.form == FDS_CFIE) {
         FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
-        FDS_HIP_TRY(hipMemcpyAsync(res, f, blk, hipMemcpyDeviceToDevice, c.stream));
-        gram_solve<double2>(c, op.g_off, op.gfac, n, res, nrhs, n);
+        gram_inv(op, f, nrhs, res);
         // S = (S stored row-major)^T as a column-major array
         zgemm(c, OP_T, OP_N, n, (int)nrhs, n, make_double2(-1.0, 0.0), op.S, n, res, n, kZero, w, n);
-        gram_solve<double2>(c, op.g_off, op.gfac, n, w, nrhs, n);
+        gram_inv(op, w, nrhs, w);
     }
     if (op.form == FDS_MFIE || op.form == FDS_CFIE) {
         FDS_REQUIRE(h != nullptr, FDS_ERR_ARG, "h is required for the MFIE/CFIE");
-        FDS_HIP_TRY(hipMemcpyAsync(res, h, blk, hipMemcpyDeviceToDevice, c.stream));
-        gram_solve<double2>(c, op.g_off, op.gfac, n, res, nrhs, n);
+        gram_inv(op, h, nrhs, res);
         if (op.form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), res, kZero, w, (int64_t)n * nrhs);
         else axpby(c, make_double2(-op.alpha, 0.0), res, kOne, w, (int64_t)n * nrhs);
     }
