@@ -207,9 +207,27 @@ fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_
 /* ------------------------------------------------------------- compression */
 
 /* Randomised skeleton C_f ~ U W of the filtered compact part (paper,
- * Inversion of the structured matrices). rank_out (host, may be NULL)
- * receives r. */
+ * Inversion of the structured matrices; randomised range finder with
+ * subspace iteration of Halko, Martinsson & Tropp). With l = rank_cap +
+ * oversample:
+ *   - tol == 0, rank_cap >= n_eff, l >= n_eff: C_f has rank <= n_eff and the
+ *     sketch spans its range, so the skeleton is exact (rank n_eff, no sketch
+ *     is formed);
+ *   - l < n_eff: Y = C_f Omega with the SplitMix64 sketch Omega (n x l,
+ *     fds_compress_opts.seed), power_iters subspace iterations with
+ *     Householder re-orthonormalisation, B = Q^H C_f, SVD of B;
+ *   - otherwise (l >= n_eff but truncating): SVD of C_f itself.
+ * The rank is r = min(rank_cap, #{sigma_i > max(tol, 1e-13) sigma_1}), lowered
+ * while sigma_r < (1 + 1e-6) sigma_{r+1} (no split of a repeated value).
+ * Synchronises. rank_out (host, may be NULL) receives r. Errors: FDS_ERR_ARG
+ * if l > n on the sketched branch; FDS_ERR_NOCONV if the Jacobi SVD of the
+ * projected block does not converge. */
 fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out);
+
+/* Singular values (descending) of the projected block B of the last
+ * truncating fds_compress call (none after the exact skeleton). Host call:
+ * copies min(cap, available) values to host `out`, the number to *count. */
+fds_status fds_op_singular_values(fds_op op, double* out, int32_t cap, int32_t* count);
 
 /* Borrowed device views of the skeleton in current-coefficient coordinates:
  * with U_y W_y the skeleton of the filtered compact part of the normalised

@@ -94,6 +94,8 @@ _SIGS = {
     "fds_op_filter_eigenvalues": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                             C.POINTER(C.c_int32)]),
     "fds_compress": (C.c_int, [C.c_void_p, C.POINTER(fds_compress_opts), C.POINTER(C.c_int32)]),
+    "fds_op_singular_values": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(C.c_int32)]),
     "fds_op_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_int32)]),
     "fds_factor": (C.c_int, [C.c_void_p]),
@@ -359,6 +361,13 @@ def fds_compress(op: Op, rank_cap: int, oversample: int = 10, power_iters: int =
     r = C.c_int32()
     _check(lib().fds_compress(op.handle, C.byref(o), C.byref(r)))
     return r.value
+
+
+def fds_op_singular_values(op: Op, cap: int = 4096):
+    buf = (C.c_double * cap)()
+    cnt = C.c_int32()
+    _check(lib().fds_op_singular_values(op.handle, buf, cap, C.byref(cnt)))
+    return [buf[i] for i in range(cnt.value)]
 
 
 def fds_op_factors(op: Op):

@@ -388,6 +388,17 @@ fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_
     });
 }
 
+fds_status fds_op_singular_values(fds_op op, double* out, int32_t cap, int32_t* count) {
+    return guarded([&] {
+        FDS_REQUIRE(op && count && cap >= 0 && (out || cap == 0), FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Compressed, "fds_op_singular_values");
+        const auto& sv = op->impl.sv;
+        const int32_t k = std::min<int32_t>(cap, (int32_t)sv.size());
+        for (int32_t i = 0; i < k; ++i) out[i] = sv[i];
+        *count = k;
+    });
+}
+
 fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* rank) {
     return guarded([&] {
         FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");

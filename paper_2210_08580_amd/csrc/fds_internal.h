@@ -126,6 +126,7 @@ struct Op {
     double cheb_lo = 0.0, cheb_hi = 0.0;
     // skeleton and Woodbury core
     int32_t rank = 0;
+    std::vector<double> sv;       // singular values of the last truncating compression (host)
     double2* U = nullptr;         // [rank][n]  U_j = G^{-1/2} U_y
     double2* W = nullptr;         // [rank][n]  row t of W_j = W_y G^{1/2} (stored as W_j^T, n x rank)
     bool owns_uw = false;         // U/W are separate allocations (else views of Vgc/Bt)

@@ -1,0 +1,395 @@
+// Dense building blocks of the truncating skeleton compression: the counter-
+// based sketch, Householder QR of tall complex blocks with the explicit
+// orthonormal factor, and the one-sided (Hestenes) Jacobi SVD of small square
+// blocks.
+//
+// Householder QR follows the standard complex reflector construction
+// (Golub & Van Loan, Matrix Computations, sec. 5.1-5.2): column j is mapped to
+// beta e_j by H_j = I - tau_j v_j v_j^H with v_j(j) = 1 and real beta, A is
+// overwritten by R (upper triangle) and the v_j (below it), and
+// Q = H_0 H_1 ... H_{m-1} [I; 0] is formed explicitly. One launch per column:
+// the workgroup owning a column applies the previous reflector to it and the
+// owner of the next pivot column then builds the next reflector, so no two
+// workgroups ever touch the same column within a launch.
+//
+// One-sided Jacobi (Hestenes 1958; Demmel & Veselic, SIAM J. Matrix Anal.
+// Appl. 13, 1992) rotates pairs of columns of X until they are mutually
+// orthogonal: X V = U Sigma with V unitary. Pairs are visited in the round-
+// robin (circle) order, m/2 disjoint pairs per launch, one workgroup per pair.
+// The relative accuracy of small singular values is what the truncation rule
+// needs, which a Gram-matrix eigensolver would not deliver.
+#include <algorithm>
+#include <cmath>
+
+#include "fds_internal.h"
+#include "lowrank.h"
+
+namespace fds {
+
+static constexpr int LR_BS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup of up to 4 values (LR_BS threads). sh: 4 * (LR_BS/64) doubles.
+template <int K>
+__device__ __forceinline__ void block_sum_k(double (&v)[K], double* sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NW = LR_BS / 64;
+#pragma unroll
+    for (int t = 0; t < K; ++t) v[t] = wave_sum(v[t]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) sh[t * NW + wv] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sh[t * NW + w];
+        v[t] = s;
+    }
+}
+
+// ----------------------------------------------------------------- sketch
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), one output step of state z.
+__device__ __forceinline__ uint64_t splitmix64_out(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Omega (n x ell, column-major): entry (i, j) from state seed ^ (i ell + j),
+// ((1 - 2 b0) + i (1 - 2 b1)) / sqrt(2) with b0, b1 the two low output bits.
+__global__ void sketch_kernel(uint64_t seed, int64_t n, int ell, double2* __restrict__ Om) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * ell) return;
+    const int64_t j = t / n, i = t % n;
+    const uint64_t z = splitmix64_out(seed ^ ((uint64_t)i * (uint64_t)ell + (uint64_t)j));
+    const double r = 0.70710678118654752440;
+    Om[t] = make_double2((z & 1ull) ? -r : r, (z & 2ull) ? -r : r);
+}
+
+void sketch(Ctx& c, uint64_t seed, int64_t n, int ell, double2* Om) {
+    const int64_t tot = n * ell;
+    {
+        KScope _ks(c, "sketch");
+        hipLaunchKernelGGL(sketch_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, seed, n,
+                           ell, Om);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- Householder QR
+// Launch j: workgroup b owns column c = j + b. For j > 0 it applies
+// H_{j-1}^H (a <- a - conj(tau) v (v^H a)) to its column over rows j-1..M-1;
+// the owner of column j then builds H_j from rows j..M-1. Every thread walks
+// the same rows in every loop, so it only re-reads what it wrote itself.
+__global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A, int64_t lda, int M, int j,
+                                                        double2* __restrict__ tau) {
+    __shared__ double sh[4 * (LR_BS / 64)];
+    __shared__ double2 alpha_sh;
+    const int c = j + blockIdx.x;
+    const int tid = threadIdx.x;
+    double2* a = A + (int64_t)c * lda;
+    const int base = j > 0 ? j - 1 : 0;
+    double nrm2 = 0.0;
+    if (j > 0) {
+        const double2* v = A + (int64_t)(j - 1) * lda;
+        const double2 tj = tau[j - 1];
+        double s[2] = {0.0, 0.0};
+        for (int r = base + tid; r < M; r += LR_BS) {
+            const double2 vr = r == j - 1 ? make_double2(1.0, 0.0) : v[r];
+            const double2 ar = a[r];
+            s[0] += vr.x * ar.x + vr.y * ar.y;     // conj(v) a
+            s[1] += vr.x * ar.y - vr.y * ar.x;
+        }
+        block_sum_k<2>(s, sh);
+        const double2 f = cmul(cconj(tj), make_double2(s[0], s[1]));
+        for (int r = base + tid; r < M; r += LR_BS) {
+            const double2 vr = r == j - 1 ? make_double2(1.0, 0.0) : v[r];
+            const double2 ar = csub(a[r], cmul(vr, f));
+            a[r] = ar;
+            if (c == j) {
+                if (r == j) alpha_sh = ar;
+                else if (r > j) nrm2 += ar.x * ar.x + ar.y * ar.y;
+            }
+        }
+    } else {
+        for (int r = tid; r < M; r += LR_BS) {
+            const double2 ar = a[r];
+            if (r == 0) alpha_sh = ar;
+            else nrm2 += ar.x * ar.x + ar.y * ar.y;
+        }
+    }
+    if (c != j) return;
+    double t[1] = {nrm2};
+    block_sum_k<1>(t, sh);            // contains a barrier: alpha_sh is visible afterwards
+    const double2 alpha = alpha_sh;
+    nrm2 = t[0];
+    if (nrm2 == 0.0 && alpha.y == 0.0) {
+        if (tid == 0) tau[j] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + nrm2), alpha.x);
+    const double2 tj = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double2 d = make_double2(alpha.x - beta, alpha.y);
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 sc = make_double2(d.x / dd, -d.y / dd);   // 1 / (alpha - beta)
+    for (int r = base + tid; r < M; r += LR_BS) {
+        if (r > j) a[r] = cmul(a[r], sc);
+        else if (r == j) a[r] = make_double2(beta, 0.0);
+    }
+    if (tid == 0) tau[j] = tj;
+}
+
+// Q <- H_j Q on columns j..m-1 (rows j..M-1), Q initially [I; 0].
+__global__ __launch_bounds__(LR_BS) void hh_formq_kernel(const double2* __restrict__ A, int64_t lda,
+                                                         const double2* __restrict__ tau, int M, int j,
+                                                         double2* __restrict__ Q, int64_t ldq) {
+    __shared__ double sh[4 * (LR_BS / 64)];
+    const double2 tj = tau[j];
+    if (tj.x == 0.0 && tj.y == 0.0) return;
+    const int c = j + blockIdx.x;
+    const int tid = threadIdx.x;
+    const double2* v = A + (int64_t)j * lda;
+    double2* q = Q + (int64_t)c * ldq;
+    double s[2] = {0.0, 0.0};
+    for (int r = j + tid; r < M; r += LR_BS) {
+        const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
+        const double2 qr = q[r];
+        s[0] += vr.x * qr.x + vr.y * qr.y;
+        s[1] += vr.x * qr.y - vr.y * qr.x;
+    }
+    block_sum_k<2>(s, sh);
+    const double2 f = cmul(tj, make_double2(s[0], s[1]));
+    for (int r = j + tid; r < M; r += LR_BS) {
+        const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
+        q[r] = csub(q[r], cmul(vr, f));
+    }
+}
+
+__global__ void eye_kernel(double2* __restrict__ Q, int64_t ldq, int M, int m) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * m) return;
+    const int64_t c = t / M, r = t % M;
+    Q[c * ldq + r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+}
+
+// X (m x m) = R^H, R the upper triangle of the factored A
+__global__ void r_adjoint_kernel(const double2* __restrict__ A, int64_t lda, int m, double2* __restrict__ X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * m) return;
+    const int c = (int)(t / m), r = (int)(t % m);
+    X[t] = c <= r ? cconj(A[(int64_t)r * lda + c]) : make_double2(0.0, 0.0);
+}
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) {
+    FDS_REQUIRE(m >= 1 && M >= m, FDS_ERR_ARG, "Householder QR needs rows >= columns >= 1");
+    {
+        KScope _ks(c, "qr_householder");
+        for (int j = 0; j < m; ++j) {
+            const unsigned g = j == 0 ? 1u : (unsigned)(m - j);
+            hipLaunchKernelGGL(hh_step_kernel, dim3(g), dim3(LR_BS), 0, c.stream, A, (int64_t)M, M, j, tau);
+        }
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    if (!Q) return;
+    {
+        KScope _ks(c, "qr_form_q");
+        hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)M * m, 256)), dim3(256), 0, c.stream, Q, (int64_t)M, M,
+                           m);
+        for (int j = m - 1; j >= 0; --j)
+            hipLaunchKernelGGL(hh_formq_kernel, dim3((unsigned)(m - j)), dim3(LR_BS), 0, c.stream, A, (int64_t)M,
+                               tau, M, j, Q, (int64_t)M);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void r_adjoint(Ctx& c, const double2* A, int M, int m, double2* X) {
+    {
+        KScope _ks(c, "qr_form_q");
+        hipLaunchKernelGGL(r_adjoint_kernel, dim3(nblk((int64_t)m * m, 256)), dim3(256), 0, c.stream, A,
+                           (int64_t)M, m, X);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- one-sided Jacobi
+// Round `round` of the circle method on mpad (even) players: pair 0 is
+// (round, mpad-1), pair k > 0 is ((round+k) mod (mpad-1), (round-k) mod (mpad-1)).
+// Columns >= m are absent (odd m). The rotation
+//     [x_p', x_q'] = [x_p, x_q] [[c, s], [-s e, c e]],   e = conj(g)/|g|, g = x_p^H x_q,
+// with t = tan(theta) the smaller root of t^2 + 2 zeta t - 1 = 0,
+// zeta = (|x_q|^2 - |x_p|^2) / (2|g|), makes the pair orthogonal; V gets the
+// same rotation.
+__global__ __launch_bounds__(LR_BS) void jacobi_round_kernel(double2* __restrict__ X, int rows,
+                                                             double2* __restrict__ V, int m, int mpad,
+                                                             int round, double tol, int* __restrict__ counter) {
+    __shared__ double sh[4 * (LR_BS / 64)];
+    const int k = blockIdx.x;
+    const int L = mpad - 1;
+    int p, q;
+    if (k == 0) {
+        p = round;
+        q = L;
+    } else {
+        p = (round + k) % L;
+        q = (round - k + L) % L;
+    }
+    if (p >= m || q >= m) return;
+    const int tid = threadIdx.x;
+    double2* xp = X + (int64_t)p * rows;
+    double2* xq = X + (int64_t)q * rows;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = tid; r < rows; r += LR_BS) {
+        const double2 a = xp[r], b = xq[r];
+        s[0] += a.x * a.x + a.y * a.y;
+        s[1] += b.x * b.x + b.y * b.y;
+        s[2] += a.x * b.x + a.y * b.y;   // conj(a) b
+        s[3] += a.x * b.y - a.y * b.x;
+    }
+    block_sum_k<4>(s, sh);
+    const double al = s[0], be = s[1];
+    const double ag = hypot(s[2], s[3]);
+    if (!(al > 0.0 && be > 0.0) || !(ag > tol * sqrt(al) * sqrt(be))) return;
+    const double zeta = (be - al) / (2.0 * ag);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    const double2 e = make_double2(s[2] / ag, -s[3] / ag);
+    const double2 se = cscale(e, sn), ce = cscale(e, cs);
+    for (int r = tid; r < rows; r += LR_BS) {
+        const double2 a = xp[r], b = xq[r];
+        xp[r] = csub(cscale(a, cs), cmul(se, b));
+        xq[r] = cadd(cscale(a, sn), cmul(ce, b));
+    }
+    double2* vp = V + (int64_t)p * m;
+    double2* vq = V + (int64_t)q * m;
+    for (int r = tid; r < m; r += LR_BS) {
+        const double2 a = vp[r], b = vq[r];
+        vp[r] = csub(cscale(a, cs), cmul(se, b));
+        vq[r] = cadd(cscale(a, sn), cmul(ce, b));
+    }
+    if (tid == 0) atomicAdd(counter, 1);
+}
+
+__global__ void colnorm_kernel(const double2* __restrict__ X, int rows, double* __restrict__ out) {
+    __shared__ double sh[4 * (LR_BS / 64)];
+    const double2* x = X + (int64_t)blockIdx.x * rows;
+    double s[1] = {0.0};
+    for (int r = threadIdx.x; r < rows; r += LR_BS) s[0] += x[r].x * x[r].x + x[r].y * x[r].y;
+    block_sum_k<1>(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s[0]);
+}
+
+// position of column c in the descending order of sigma (ties by index)
+__global__ void sort_rank_kernel(const double* __restrict__ sig, int m, int* __restrict__ pos) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    const double v = sig[c];
+    int r = 0;
+    for (int k = 0; k < m; ++k) {
+        const double w = sig[k];
+        r += (w > v || (w == v && k < c)) ? 1 : 0;
+    }
+    pos[c] = r;
+}
+
+// sorted outputs: U(:, pos c) = X(:, c) / sigma_c, V(:, pos c) = V(:, c), sigma sorted
+__global__ void svd_gather_kernel(const double2* __restrict__ X, int rows, const double2* __restrict__ V, int m,
+                                  const double* __restrict__ sig, const int* __restrict__ pos,
+                                  double2* __restrict__ Uo, double2* __restrict__ Vo, double* __restrict__ so) {
+    const int c = blockIdx.x;
+    const int d = pos[c];
+    const double sc = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x)
+        Uo[(int64_t)d * rows + r] = cscale(X[(int64_t)c * rows + r], sc);
+    for (int r = threadIdx.x; r < m; r += blockDim.x) Vo[(int64_t)d * m + r] = V[(int64_t)c * m + r];
+    if (threadIdx.x == 0) so[d] = sig[c];
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+int jacobi_svd(Ctx& c, double2* X, int m, double2* Uo, double2* Vo, double* sig, int max_sweeps) {
+    FDS_REQUIRE(m >= 1, FDS_ERR_ARG, "empty Jacobi SVD");
+    double2* V = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m * m));
+    double* sw = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)m));
+    int* iw = static_cast<int*>(c.dmalloc(sizeof(int) * ((size_t)m + 1)));
+    int* counter = iw + m;
+    const int mpad = m + (m & 1);
+    const double tol = 2.0 * std::sqrt((double)m) * 2.220446049250313e-16;
+    hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)m * m, 256)), dim3(256), 0, c.stream, V, (int64_t)m, m, m);
+    FDS_HIP_TRY(hipGetLastError());
+    int sweeps = 0;
+    bool conv = m == 1;
+    while (!conv && sweeps < max_sweeps) {
+        {
+            KScope _ks(c, "svd_jacobi");
+            hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c.stream, counter);
+            for (int rd = 0; rd < mpad - 1; ++rd)
+                hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)(mpad / 2)), dim3(LR_BS), 0, c.stream, X, m,
+                                   V, m, mpad, rd, tol, counter);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        int hc = 0;
+        FDS_HIP_TRY(hipMemcpyAsync(&hc, counter, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        ++sweeps;
+        conv = hc == 0;
+    }
+    if (!conv) {
+        c.dfree(V);
+        c.dfree(sw);
+        c.dfree(iw);
+        throw Error{FDS_ERR_NOCONV, "Jacobi SVD did not converge"};
+    }
+    {
+        KScope _ks(c, "svd_jacobi");
+        hipLaunchKernelGGL(colnorm_kernel, dim3((unsigned)m), dim3(LR_BS), 0, c.stream, X, m, sw);
+        hipLaunchKernelGGL(sort_rank_kernel, dim3(nblk(m, 256)), dim3(256), 0, c.stream, sw, m, iw);
+        hipLaunchKernelGGL(svd_gather_kernel, dim3((unsigned)m), dim3(256), 0, c.stream, X, m, V, m, sw, iw, Uo, Vo,
+                           sig);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(V);
+    c.dfree(sw);
+    c.dfree(iw);
+    return sweeps;
+}
+
+// ----------------------------------------------------------------- small elementwise helpers
+__global__ void conj_kernel(const double2* __restrict__ x, double2* __restrict__ y, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = cconj(x[t]);
+}
+
+__global__ void scale_cols_kernel(double2* __restrict__ X, int64_t rows, int cols, const double* __restrict__ s) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    X[t] = cscale(X[t], s[t / rows]);
+}
+
+void conj_copy(Ctx& c, const double2* x, double2* y, int64_t n) {
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(conj_kernel, dim3(nblk(n, 256)), dim3(256), 0, c.stream, x, y, n);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void scale_cols(Ctx& c, double2* X, int64_t rows, int cols, const double* s) {
+    {
+        KScope _ks(c, "elementwise");
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(nblk(rows * cols, 256)), dim3(256), 0, c.stream, X, rows, cols, s);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace fds

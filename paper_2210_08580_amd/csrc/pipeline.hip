@@ -22,6 +22,7 @@
 
 #include "fds_internal.h"
 #include "linalg.h"
+#include "lowrank.h"
 #include "pipeline.h"
 
 namespace fds {
@@ -182,6 +183,19 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
     op.rank = 0;
 }
 
+// Truncation of the projected block's singular values (descending):
+// r = min(rank_cap, #{s_i > max(tol, 1e-13) s_0}), lowered while s_{r-1} < (1 + 1e-6) s_r
+// so that a numerically repeated singular value is never split.
+static int truncation_rank(const std::vector<double>& s, int rank_cap, double tol) {
+    if (s.empty() || !(s[0] > 0.0)) return 0;
+    const double thr = std::max(tol, 1e-13) * s[0];
+    int cnt = 0;
+    for (double v : s) cnt += v > thr ? 1 : 0;
+    int r = std::min(rank_cap, cnt);
+    while (r > 0 && r < (int)s.size() && s[r - 1] < (1.0 + 1e-6) * s[r]) --r;
+    return r;
+}
+
 void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed) {
     const int ne = op.n_eff;
     const int ell = rank_cap + oversample;
@@ -194,6 +208,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
     }
     op.U = op.W = nullptr;
     op.owns_uw = false;
+    op.sv.clear();
     if (tol == 0.0 && rank_cap >= ne && ell >= ne) {
         // The filtered compact part V_n B has rank <= n_eff and a sketch of width
         // l >= n_eff spans its whole range, so the randomised skeleton is exact:
@@ -204,7 +219,96 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
         op.stage = Stage::Compressed;
         return;
     }
-    throw Error{FDS_ERR_NOTIMPL, "truncating (lossy) compression is not built yet"};
+    FDS_REQUIRE(ne >= 1, FDS_ERR_STATE, "empty filter basis");
+    const int n = (int)op.n;
+    const bool sketched = ell < ne;     // else the range of the compact part is found exactly
+    FDS_REQUIRE(!sketched || ell <= n, FDS_ERR_ARG, "rank_cap + oversample exceeds the system size");
+    const int m = sketched ? ell : ne;  // width of the final projected block
+    const size_t nm = (size_t)n * m;
+    // B_y^H = G^{-1/2} conj(Bt)  (N x n_eff): A_y = V_n B_y is the filtered compact part
+    double2* cBt = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
+    conj_copy(c, op.Bt, cBt, (int64_t)n * ne);
+    double2* Z = static_cast<double2*>(c.dmalloc(sizeof(double2) * nm));
+    double2* tau = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(m, ne)));
+    double2* Qz = nullptr;   // n_eff x ell orthonormal range coordinates (Q = V_n Qz)
+    if (sketched) {
+        // Randomised subspace iteration (Halko, Martinsson & Tropp 2011) in the
+        // coordinates of V_n: A_y X = V_n (B_y X), A_y^H V_n Y = B_y^H Y, and
+        // orth(V_n Y) = V_n orth(Y).
+        double2* T = static_cast<double2*>(c.dmalloc(sizeof(double2) * nm));
+        double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)ne * m));
+        Qz = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)ne * m));
+        double2* Qp = static_cast<double2*>(c.dmalloc(sizeof(double2) * nm));
+        sketch(c, seed, n, m, T);
+        for (int it = 0;; ++it) {
+            // X = B_y T = Bt^T G^{-1/2} T ; Qz = orth(X)
+            apply_gram_power(op, -1, T, m);
+            zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
+            householder_qr(c, X, ne, m, tau, Qz);
+            if (it == power_iters) break;
+            // Z = B_y^H Qz ; T = orth(Z)
+            zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+            apply_gram_power(op, -1, Z, m);
+            householder_qr(c, Z, n, m, tau, Qp);
+            std::swap(T, Qp);
+        }
+        // projected block B = Q^H A_y = Qz^H B_y, held as B^H = B_y^H Qz
+        zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+        apply_gram_power(op, -1, Z, m);
+        c.dfree(T);
+        c.dfree(X);
+        c.dfree(Qp);
+    } else {
+        FDS_HIP_TRY(hipMemcpyAsync(Z, cBt, sizeof(double2) * nm, hipMemcpyDeviceToDevice, c.stream));
+        apply_gram_power(op, -1, Z, m);
+    }
+    c.dfree(cBt);
+    // B^H = Q_P R (Householder), R^H = Uh diag(s) Vh^H (Jacobi):
+    //     B = Uh diag(s) (Q_P Vh)^H
+    double2* QP = static_cast<double2*>(c.dmalloc(sizeof(double2) * nm));
+    householder_qr(c, Z, n, m, tau, QP);
+    double2* RH = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m * m));
+    r_adjoint(c, Z, n, m, RH);
+    c.dfree(Z);
+    c.dfree(tau);
+    double2* Uh = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m * m));
+    double2* Vh = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m * m));
+    double* sg = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)m));
+    jacobi_svd(c, RH, m, Uh, Vh, sg, 60);
+    c.dfree(RH);
+    op.sv.assign(m, 0.0);
+    FDS_HIP_TRY(hipMemcpyAsync(op.sv.data(), sg, sizeof(double) * m, hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    const int r = truncation_rank(op.sv, rank_cap, tol);
+    if (r > 0) {
+        // U_j = G^{-1/2} V_n Qz Uh_r diag(s_r) = V_g (Qz Uh_r) diag(s_r)
+        double2* Ur = Uh;
+        double2* T1 = nullptr;
+        if (Qz) {
+            T1 = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)ne * r));
+            zgemm(c, OP_N, OP_N, ne, r, m, kOne, Qz, ne, Uh, m, kZero, T1, ne);
+            Ur = T1;
+        }
+        scale_cols(c, Ur, ne, r, sg);
+        op.U = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
+        zgemm(c, OP_N, OP_N, n, r, ne, kOne, op.Vgc, n, Ur, ne, kZero, op.U, n);
+        if (T1) c.dfree(T1);
+        // W_j^T = (W_y G^{1/2})^T = G^{1/2} conj(Q_P Vh_r)
+        double2* T2 = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
+        zgemm(c, OP_N, OP_N, n, r, m, kOne, QP, n, Vh, m, kZero, T2, n);
+        op.W = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
+        conj_copy(c, T2, op.W, (int64_t)n * r);
+        c.dfree(T2);
+        apply_gram_power(op, 1, op.W, r);
+        op.owns_uw = true;
+    }
+    if (Qz) c.dfree(Qz);
+    c.dfree(QP);
+    c.dfree(Uh);
+    c.dfree(Vh);
+    c.dfree(sg);
+    op.rank = r;
+    op.stage = Stage::Compressed;
 }
 
 void run_factor(Op& op) {
