@@ -96,6 +96,64 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
     }
 
 
+def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
+    """Times `steps` full steps of one precision variant; returns (seconds, profile, info, j)."""
+    import torch
+    info = {}
+
+    def step():
+        op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
+        ne = B.fds_filter(op, w.form, w.alpha, w.n_modes)
+        r = B.fds_compress(op, w.rank_cap, w.oversample, w.power_iters, w.tol, w.seed)
+        B.fds_factor(op)
+        f, h = B.fds_rhs_planewave(op, angles, amps)
+        j, _, st = B.fds_solve(op, f, h, max_iters=3, tol=1e-10)
+        info.update(n_eff=ne, rank=r, refine=st)
+        op.close()
+        return j
+
+    for i in range(warmup):
+        log(f"{precision}: warmup step {i + 1}/{warmup}")
+        step()
+    torch.cuda.synchronize()
+    B.fds_profile_read(ctx)            # drop warmup records
+    B.fds_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    j = None
+    for i in range(steps):
+        j = step()
+        log(f"{precision}: timed step {i + 1}/{steps}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.fds_profile_enable(ctx, False)
+    prof = B.fds_profile_read(ctx)
+    return t1 - t0, prof, info, j
+
+
+def roofline(prof, n, ne, nrhs, sweeps, steps):
+    """Roofline of the kernel family with the largest total time."""
+    name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    if name == "asm_far":
+        work = 32.0 * n * n * FLOP_PER_POINT_PAIR
+        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
+    elif name == "gemm":
+        work = gemm_flops(n, ne, nrhs, sweeps)
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
+        launches = steps       # the per-step work above is summed over the step's GEMM launches
+    else:
+        work = None
+        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
+    per_launch_s = (tot_ms / 1e3) / max(launches, 1)
+    if work is not None:
+        ach = work / per_launch_s / 1e12
+        roof.update(achieved=ach, frac=ach / roof["peak"])
+    else:
+        roof.update(achieved=None, frac=None)
+    roof.update(kernel=name, avg_launch_ms=per_launch_s * 1e3, traffic=None)
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +161,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star8192")
     ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--variants", default="fp64,fp32",
+                    help="assembly precisions to time: fp64 (plain) and/or fp32 (mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     args = ap.parse_args()
@@ -124,77 +184,48 @@ def main():
     amps = torch.from_numpy(w.amps).cuda()
     torch.cuda.synchronize()
 
-    info = {}
-
-    def step():
-        op = B.fds_assemble(ctx, nodes, w.k)
-        ne = B.fds_filter(op, w.form, w.alpha, w.n_modes)
-        r = B.fds_compress(op, w.rank_cap, w.oversample, w.power_iters, w.tol, w.seed)
-        B.fds_factor(op)
-        f, h = B.fds_rhs_planewave(op, angles, amps)
-        j, _, st = B.fds_solve(op, f, h, max_iters=3, tol=1e-10)
-        info.update(n_eff=ne, rank=r, refine=st)
-        op.close()
-        return j
-
-    for i in range(args.warmup):
-        log(f"warmup step {i + 1}/{args.warmup}")
-        step()
-    torch.cuda.synchronize()
-    B.fds_profile_read(ctx)            # drop warmup records
-    B.fds_profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        log(f"timed step {i + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    B.fds_profile_enable(ctx, False)
-    prof = B.fds_profile_read(ctx)
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
-    value = nrhs * args.steps / elapsed
-
-    # dominant kernel and its roofline
-    name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
-    ne = info["n_eff"]
-    sweeps = info["refine"]["iters"]
-    if name == "asm_far":
-        units = 32.0 * n * n
-        work = units * FLOP_PER_POINT_PAIR
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-    elif name == "gemm":
-        work = gemm_flops(n, ne, nrhs, sweeps)
-        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-        launches = args.steps       # per-step work above is summed over the step's GEMM launches
-    else:
-        work = None
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-    per_launch_s = (tot_ms / 1e3) / max(launches, 1)
-    if work is not None:
-        ach = work / per_launch_s / 1e12
-        roof.update(achieved=ach, frac=ach / roof["peak"])
-    else:
-        roof.update(achieved=None, frac=None)
-    roof.update(kernel=name, avg_launch_ms=per_launch_s * 1e3, traffic=None)
-
-    asm_ms = prof.get("asm_far", (0.0, 1))[0] / max(prof.get("asm_far", (0.0, 1))[1], 1)
-    extra = {
-        "assembly_entries_per_s": 3.0 * n * n / (asm_ms / 1e3) if asm_ms > 0 else None,
-        "n_eff": ne, "rank": info["rank"], "refine_iters": sweeps,
-        "final_relres": info["refine"]["relres"],
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
-    }
+    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    res = {}
+    for prec in variants:
+        el, prof, info, j = run_variant(B, ctx, w, nodes, angles, amps, prec, args.steps, args.warmup)
+        far = prof.get("asm_far", (0.0, 1))
+        asm_ms = far[0] / max(far[1], 1)
+        res[prec] = {
+            "value": nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+            "prof": prof, "info": info, "j": j,
+            "assembly_entries_per_s": 3.0 * n * n / (asm_ms / 1e3) if asm_ms > 0 else None,
+        }
+    main_v = "fp32" if "fp32" in res else variants[0]
+    r = res[main_v]
+    info = r["info"]
+    ne, sweeps = info["n_eff"], info["refine"]["iters"]
+    roof = roofline(r["prof"], n, ne, nrhs, sweeps, args.steps)
+    extra = {"n_eff": ne, "rank": info["rank"]}
+    for prec, rv in res.items():
+        extra[prec] = {
+            "value": rv["value"], "ms_per_step": rv["ms_per_step"],
+            "assembly_entries_per_s": rv["assembly_entries_per_s"],
+            "refine_iters": rv["info"]["refine"]["iters"], "final_relres": rv["info"]["refine"]["relres"],
+            "kernel_ms_per_step": {k: v[0] / args.steps
+                                   for k, v in sorted(rv["prof"].items(), key=lambda kv: -kv[1][0])},
+        }
+    if "fp32" in res and "fp64" in res:
+        a, b = res["fp32"]["j"], res["fp64"]["j"]
+        rel = (torch.linalg.vector_norm(a - b, dim=1) / torch.linalg.vector_norm(b, dim=1)).max().item()
+        extra["mixed_relerr_vs_fp64"] = rel
+        extra["mixed_speedup_vs_fp64"] = res["fp32"]["value"] / res["fp64"]["value"]
+    precision = {"fp64": "fp64 plain", "fp32": "mixed: FP32 far-field assembly, complex64 operators, "
+                 "FP64 products, FP64 Woodbury and refinement"}[main_v]
     out = {
-        "metric": METRIC, "value": value, "unit": "RHS solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "metric": METRIC, "value": r["value"], "unit": "RHS solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if main_v == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: star r=1+0.3cos5t N={n} k={w.k} {w.form.upper()} "
                                f"n_modes={w.n_modes} r={w.rank_cap} p={w.oversample} "
                                f"q={w.power_iters} nrhs={nrhs}",
-                   "precision": "fp64 plain"},
+                   "precision": precision},
         "roofline": roof,
         "extra": extra,
     }

@@ -67,7 +67,12 @@ typedef enum fds_precision { FDS_FP64 = 0, FDS_FP32 = 1, FDS_BF16 = 2 } fds_prec
 
 typedef struct fds_asm_opts {
     int32_t nquad;       /* Gauss points per panel; only 8 is supported          */
-    int32_t precision;   /* FDS_FP64                                            */
+    int32_t precision;   /* FDS_FP64: complex128 operators;
+                            FDS_FP32: complex64 operators, far-pair kernel values
+                            and accumulation in FP32 (distances and Bessel
+                            arguments in FP64), self/adjacent-pair quadrature in
+                            FP64; every product with S, N, D then runs on the
+                            FP32 matrix cores (mixed precision)                */
     int32_t reserved[6];
 } fds_asm_opts;
 
@@ -130,6 +135,10 @@ fds_status fds_profile_read(fds_ctx ctx, int32_t cap, char* names, double* total
  * out: device [n][4] doubles = J0, Y0, J1, Y1 at each x. */
 fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out);
 
+/* Single-precision evaluation used by the FP32 far-field assembly (scaled
+ * error below 2e-7 max(|f|, 1)); x: device [n] doubles, out: device [n][4] floats. */
+fds_status fds_hankel_eval_f32(fds_ctx ctx, const double* x, int64_t n, float* out);
+
 /* Kernel values used by the Galerkin quadrature at distances R (device [n],
  * R >= 0). out: device [n][8] doubles =
  *   g(R) = (i/4) H0^(1)(kR)                           (re, im)  (R > 0)
@@ -149,6 +158,12 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
                      const double* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                      const double* beta, void* C, int64_t ldc);
 
+/* fds_zgemm for complex64 operands on the FP32 matrix cores (FP32 accumulation);
+ * alpha and beta: host complex64 (2 floats each). */
+fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
+                     const float* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     const float* beta, void* C, int64_t ldc);
+
 /* ---------------------------------------------------------------- assembly */
 
 /* Dense Galerkin assembly (paper, Notation and Background: [S]_ij, [N]_ij,
@@ -159,7 +174,8 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
  *        node i to node i+1 mod n), no repeated node; 8 <= n.
  * k:     wave number > 0.
  * opts:  may be NULL (defaults: nquad 8, FP64).
- * out:   receives a new operator owning S, N, D (3 n^2 complex128).
+ * out:   receives a new operator owning S, N, D (3 n^2 complex128, or
+ *        complex64 with FDS_FP32).
  * Errors: FDS_ERR_ARG for bad sizes/k or a zero-length / non-finite panel,
  * FDS_ERR_ALLOC when the matrices do not fit. */
 fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
@@ -170,8 +186,21 @@ fds_status fds_op_destroy(fds_op op);
  * fds_compress). Any output pointer may be NULL. Host call, no sync. */
 fds_status fds_op_info(fds_op op, int64_t* n, int32_t* n_eff, int32_t* rank);
 
-/* Borrowed device views of S, N, D ([n][n] complex128, row-major). */
+/* Borrowed device views of S, N, D ([n][n] row-major; complex128, or
+ * complex64 for an operator assembled with FDS_FP32). */
 fds_status fds_op_matrices(fds_op op, void** S, void** Nmat, void** D);
+
+/* FP32 operators only (NULL and width 0 otherwise): borrowed device view of
+ * N on the cyclic band |d| <= w, w = min(63, (n - 1)/2), in complex128:
+ * [n][2w + 1] with N[i][(i + d) mod n] at [i][d + w]. The complex64 N returned
+ * by fds_op_matrices holds zeros on this band. The Galerkin matrix of the
+ * hypersingular operator has O(1) entries near the diagonal but eigenvalues
+ * O(h) on smooth vectors, so FP32 errors there would be amplified by 1/h;
+ * the band is computed and kept in FP64. Host call. */
+fds_status fds_op_nband(fds_op op, const void** Nband, int32_t* width);
+
+/* Storage precision of S, N, D (FDS_FP64 or FDS_FP32). Host call. */
+fds_status fds_op_precision(fds_op op, int32_t* precision);
 
 /* Borrowed device views of the periodic tridiagonal G and L: diag[i] and
  * off[i] = M[i][i+1 mod n] ([n] doubles each). */

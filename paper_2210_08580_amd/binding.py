@@ -75,6 +75,12 @@ _SIGS = {
     "fds_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "fds_hankel_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_hankel_eval_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_cgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
+                            C.POINTER(C.c_float), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                            C.POINTER(C.c_float), C.c_void_p, C.c_int64]),
+    "fds_op_precision": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "fds_op_nband": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
@@ -168,7 +174,7 @@ class _DevView:
 
 
 def _view(ptr, shape, dtype, owner):
-    ts = {torch.float64: "<f8", torch.complex128: "<c16"}[dtype]
+    ts = {torch.float64: "<f8", torch.complex128: "<c16", torch.complex64: "<c8", torch.float32: "<f4"}[dtype]
     v = torch.as_tensor(_DevView(ptr, shape, ts, owner), device="cuda")
     return v
 
@@ -249,6 +255,12 @@ def fds_hankel_eval(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def fds_hankel_eval_f32(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:
+    out = torch.empty((x.numel(), 4), dtype=torch.float32, device=x.device)
+    _check(lib().fds_hankel_eval_f32(ctx.handle, _ptr(x), x.numel(), _ptr(out)))
+    return out
+
+
 def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:
     out = torch.empty((R.numel(), 8), dtype=torch.float64, device=R.device)
     _check(lib().fds_kernel_eval(ctx.handle, float(k), _ptr(R), R.numel(), _ptr(out)))
@@ -269,6 +281,21 @@ def fds_zgemm(ctx: Ctx, opa: int, opb: int, A: torch.Tensor, Bm: torch.Tensor, C
     al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
     be = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
     _check(lib().fds_zgemm(ctx.handle, opa, opb, m, n, k, al, _ptr(A), ra, _ptr(Bm), rb, be,
+                           _ptr(Cm), Cm.shape[1]))
+    return Cm
+
+
+def fds_cgemm(ctx: Ctx, opa: int, opb: int, A: torch.Tensor, Bm: torch.Tensor, Cm: torch.Tensor,
+              alpha: complex = 1.0, beta: complex = 0.0):
+    """fds_zgemm for complex64 tensors (FP32 matrix cores)."""
+    ra, ca = A.shape[1], A.shape[0]
+    rb, cb = Bm.shape[1], Bm.shape[0]
+    m = ra if opa == 0 else ca
+    k = ca if opa == 0 else ra
+    n = cb if opb == 0 else rb
+    al = (C.c_float * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (C.c_float * 2)(complex(beta).real, complex(beta).imag)
+    _check(lib().fds_cgemm(ctx.handle, opa, opb, m, n, k, al, _ptr(A), ra, _ptr(Bm), rb, be,
                            _ptr(Cm), Cm.shape[1]))
     return Cm
 
@@ -305,8 +332,14 @@ class Op:
         return self.info()[0]
 
 
-def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | None = None) -> Op:
+def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | None = None,
+                 precision: str | None = None) -> Op:
+    """precision: "fp64" (default) or "fp32" (complex64 operators, mixed precision)."""
     nodes = nodes.to(device="cuda", dtype=torch.float64).contiguous()
+    if precision is not None:
+        opts = fds_asm_opts()
+        opts.nquad = 8
+        opts.precision = {"fp64": FDS_FP64, "fp32": FDS_FP32}[precision]
     h = C.c_void_p()
     _check(lib().fds_assemble(ctx.handle, _ptr(nodes), nodes.shape[0], float(k),
                               C.byref(opts) if opts is not None else None, C.byref(h)))
@@ -317,7 +350,25 @@ def fds_op_matrices(op: Op):
     s, n_, d = C.c_void_p(), C.c_void_p(), C.c_void_p()
     _check(lib().fds_op_matrices(op.handle, C.byref(s), C.byref(n_), C.byref(d)))
     N = op.n
-    return tuple(_view(p.value, (N, N), torch.complex128, op) for p in (s, n_, d))
+    dt = torch.complex64 if fds_op_precision(op) == FDS_FP32 else torch.complex128
+    return tuple(_view(p.value, (N, N), dt, op) for p in (s, n_, d))
+
+
+def fds_op_nband(op: Op):
+    """FP32 operators: (band, w) with the complex128 band of N as an (n, 2w + 1)
+    tensor (N[i][(i + d) mod n] at [i][d + w]); (None, 0) otherwise."""
+    p = C.c_void_p()
+    w = C.c_int32()
+    _check(lib().fds_op_nband(op.handle, C.byref(p), C.byref(w)))
+    if not p.value:
+        return None, 0
+    return _view(p.value, (op.n, 2 * w.value + 1), torch.complex128, op), w.value
+
+
+def fds_op_precision(op: Op) -> int:
+    p = C.c_int32()
+    _check(lib().fds_op_precision(op.handle, C.byref(p)))
+    return p.value
 
 
 def fds_op_sparse(op: Op):

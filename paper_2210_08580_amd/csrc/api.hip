@@ -46,7 +46,7 @@ void Ctx::dfree(void* p) {
 
 Op::~Op() {
     if (!ctx) return;
-    void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D,
+    void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
                     Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
@@ -119,6 +119,9 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.hk_tab = (double*)x.dmalloc(sizeof(double) * HK_TAB_DOUBLES);
             FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab, &HK_TAB[0][0][0], sizeof(double) * HK_TAB_DOUBLES,
                                        hipMemcpyHostToDevice, x.stream));
+            x.hk_tab32 = (float*)x.dmalloc(sizeof(float) * HK32_TAB_FLOATS);
+            FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab32, &HK32_TAB[0][0][0], sizeof(float) * HK32_TAB_FLOATS,
+                                       hipMemcpyHostToDevice, x.stream));
             double g[64];
             gauss_legendre_01(32, g, g + 32);
             x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);
@@ -126,6 +129,7 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             FDS_HIP_TRY(hipStreamSynchronize(x.stream));
         } catch (...) {
             x.dfree(x.hk_tab);
+            x.dfree(x.hk_tab32);
             x.dfree(x.gl32);
             delete c;
             throw;
@@ -140,6 +144,7 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
         (void)hipStreamSynchronize(ctx->impl.stream);
         resolve_profile(ctx->impl);
         ctx->impl.dfree(ctx->impl.hk_tab);
+        ctx->impl.dfree(ctx->impl.hk_tab32);
         ctx->impl.dfree(ctx->impl.gl32);
         delete ctx;
     });
@@ -189,6 +194,14 @@ fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out)
     });
 }
 
+fds_status fds_hankel_eval_f32(fds_ctx ctx, const double* x, int64_t n, float* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && x && out && n >= 0, FDS_ERR_ARG, "bad argument");
+        if (n == 0) return;
+        launch_hankel_eval_f32(ctx->impl, x, n, out);
+    });
+}
+
 fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n, double* out) {
     return guarded([&] {
         FDS_REQUIRE(ctx && R && out && n >= 0, FDS_ERR_ARG, "bad argument");
@@ -216,6 +229,24 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
     });
 }
 
+fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
+                     const float* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     const float* beta, void* C, int64_t ldc) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && alpha && beta && C, FDS_ERR_ARG, "NULL argument");
+        FDS_REQUIRE(opa >= 0 && opa <= 2 && opb >= 0 && opb <= 2, FDS_ERR_ARG, "op must be 0, 1 or 2");
+        FDS_REQUIRE(m >= 0 && n >= 0 && k >= 0 && m < (1 << 30) && n < (1 << 30) && k < (1 << 30),
+                    FDS_ERR_ARG, "bad sizes");
+        if (m == 0 || n == 0) return;
+        FDS_REQUIRE(A && B, FDS_ERR_ARG, "NULL operand");
+        const int64_t ra = opa == 0 ? m : k, rb = opb == 0 ? k : n;
+        FDS_REQUIRE(lda >= std::max<int64_t>(1, ra) && ldb >= std::max<int64_t>(1, rb) && ldc >= m,
+                    FDS_ERR_ARG, "leading dimension too small");
+        cgemm(ctx->impl, opa, opb, (int)m, (int)n, (int)k, make_float2(alpha[0], alpha[1]),
+              (const float2*)A, lda, (const float2*)B, ldb, make_float2(beta[0], beta[1]), (float2*)C, ldc);
+    });
+}
+
 fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
                         const fds_asm_opts* opts, fds_op* out) {
     return guarded([&] {
@@ -226,8 +257,8 @@ fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
         if (opts) {
             FDS_REQUIRE(opts->nquad == 0 || opts->nquad == 8, FDS_ERR_NOTIMPL,
                         "only the 8-point rule is implemented");
-            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL,
-                        "only FP64 assembly is implemented");
+            FDS_REQUIRE(opts->precision == FDS_FP64 || opts->precision == FDS_FP32, FDS_ERR_NOTIMPL,
+                        "assembly precision must be FDS_FP64 or FDS_FP32");
         }
         Ctx& c = ctx->impl;
         // host-side geometry validation (O(n) copy)
@@ -250,6 +281,7 @@ fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
         op.ctx = &c;
         op.n = n;
         op.k = k;
+        op.prec = opts ? opts->precision : FDS_FP64;
         try {
             const size_t nd = sizeof(double) * n;
             op.nodes = (double*)c.dmalloc(2 * nd);
@@ -262,10 +294,20 @@ fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
             op.g_off = (double*)c.dmalloc(nd);
             op.l_diag = (double*)c.dmalloc(nd);
             op.l_off = (double*)c.dmalloc(nd);
-            const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
-            op.S = (double2*)c.dmalloc(mat);
-            op.Nm = (double2*)c.dmalloc(mat);
-            op.D = (double2*)c.dmalloc(mat);
+            if (op.prec == FDS_FP32) {
+                const size_t mat = sizeof(float2) * (size_t)n * (size_t)n;
+                op.S32 = (float2*)c.dmalloc(mat);
+                op.N32 = (float2*)c.dmalloc(mat);
+                op.D32 = (float2*)c.dmalloc(mat);
+                // cyclic band |d| <= nbw, with 2 nbw + 1 <= n so that the taps are distinct
+                op.nbw = (int)std::min<int64_t>(63, (n - 1) / 2);
+                op.Nband = (double2*)c.dmalloc(sizeof(double2) * (2 * op.nbw + 1) * (size_t)n);
+            } else {
+                const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
+                op.S = (double2*)c.dmalloc(mat);
+                op.Nm = (double2*)c.dmalloc(mat);
+                op.D = (double2*)c.dmalloc(mat);
+            }
             FDS_HIP_TRY(hipMemcpyAsync(op.nodes, nodes, 2 * nd, hipMemcpyDeviceToDevice, c.stream));
             gauss_legendre_01(8, op.rule.xi, op.rule.w);
             launch_geometry(op);
@@ -299,9 +341,25 @@ fds_status fds_op_info(fds_op op, int64_t* n, int32_t* n_eff, int32_t* rank) {
 fds_status fds_op_matrices(fds_op op, void** S, void** Nmat, void** D) {
     return guarded([&] {
         FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
-        if (S) *S = op->impl.S;
-        if (Nmat) *Nmat = op->impl.Nm;
-        if (D) *D = op->impl.D;
+        const bool f32 = op->impl.prec == FDS_FP32;
+        if (S) *S = f32 ? (void*)op->impl.S32 : (void*)op->impl.S;
+        if (Nmat) *Nmat = f32 ? (void*)op->impl.N32 : (void*)op->impl.Nm;
+        if (D) *D = f32 ? (void*)op->impl.D32 : (void*)op->impl.D;
+    });
+}
+
+fds_status fds_op_nband(fds_op op, const void** Nband, int32_t* width) {
+    return guarded([&] {
+        FDS_REQUIRE(op && Nband && width, FDS_ERR_ARG, "NULL argument");
+        *Nband = op->impl.Nband;
+        *width = op->impl.nbw;
+    });
+}
+
+fds_status fds_op_precision(fds_op op, int32_t* precision) {
+    return guarded([&] {
+        FDS_REQUIRE(op && precision, FDS_ERR_ARG, "NULL argument");
+        *precision = op->impl.prec;
     });
 }
 

@@ -29,6 +29,8 @@
 //   form on a self pair, Duffy's corner split on adjacent pairs), smooth
 //   remainders with the same 8 x 8 rule; the S and N bands |i - j| <= 2 are
 //   then symmetrised.
+#include <type_traits>
+
 #include "fds_internal.h"
 #include "hankel.h"
 
@@ -55,11 +57,14 @@ struct FarParams {
     const double* __restrict__ h;
     const double* __restrict__ nx;
     const double* __restrict__ ny;
-    const double* __restrict__ tab;
+    const void* __restrict__ tab;     // HK_TAB (FP64) or HK32_TAB (FP32)
     const double* __restrict__ nodes;
-    double2* __restrict__ S;
-    double2* __restrict__ Nm;
-    double2* __restrict__ D;
+    void* __restrict__ S;             // complex128 or complex64, row-major n x n
+    void* __restrict__ Nm;
+    void* __restrict__ D;
+    double2* __restrict__ nband;      // N on the cyclic band |d| <= bw (FP32 operators)
+    int bw;                           // band half-width (0: no band)
+    int band_only;                    // 1: FP64 pass over the tiles touching the band, N band only
     double k;
     int n;
     int nsub;
@@ -70,9 +75,15 @@ struct FarParams {
 __device__ __forceinline__ double2 fma_cr(double s, double2 a, double2 acc) {
     return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
 }
+__device__ __forceinline__ float2 fma_cr(float s, float2 a, float2 acc) {
+    return make_float2(fmaf(s, a.x, acc.x), fmaf(s, a.y, acc.y));
+}
 
 __device__ __forceinline__ double2 shfl_down1(double2 v) {
     return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+__device__ __forceinline__ float2 shfl_down1(float2 v) {
+    return make_float2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -81,11 +92,50 @@ __device__ __forceinline__ int wave_max_int(int v) {
     return v;
 }
 
+// Element types of the far-field kernel: FP64 throughout, or FP32 kernel values
+// and accumulation (geometry, distances and Bessel arguments stay FP64).
+template <bool F32>
+struct FarT;
+template <>
+struct FarT<false> {
+    typedef double R;
+    typedef double2 C;
+    static constexpr int TAB_BYTES = 8 * HK_TAB_DOUBLES;
+};
+template <>
+struct FarT<true> {
+    typedef float R;
+    typedef float2 C;
+    static constexpr int TAB_BYTES = 4 * HK32_TAB_FLOATS;
+};
+
+// g = (i/4) H0(kR) and c = (ik/4) H1(kR)/R at one point pair
+__device__ __forceinline__ void far_kernel_values(double k, double R, const void* tab, double2& g, double2& c) {
+    const Bessel01 bs = hk_eval_hot(k * R, static_cast<const double*>(tab));
+    g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
+    const double kr = 0.25 * k / R;
+    c = make_double2(-kr * bs.y1, kr * bs.j1);
+}
+__device__ __forceinline__ void far_kernel_values(double k, double R, const void* tab, float2& g, float2& c) {
+    const Bessel01f bs = hk32_eval_hot(k * R, static_cast<const float*>(tab));
+    g = make_float2(-0.25f * bs.y0, 0.25f * bs.j0);
+    const float kr = (float)(0.25 * k) * __builtin_amdgcn_rcpf((float)R);
+    c = make_float2(-kr * bs.y1, kr * bs.j1);
+}
+
+template <bool F32>
 __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
-    __shared__ __attribute__((aligned(16))) double tab[HK_TAB_DOUBLES];
+    typedef typename FarT<F32>::R RT;
+    typedef typename FarT<F32>::C CT;
+    __shared__ __attribute__((aligned(16))) char tabraw[FarT<F32>::TAB_BYTES];
     __shared__ double wsh[16];          // w_b psi_0(xi_b), w_b psi_1(xi_b)
     __shared__ double rl4[12], rl3[9];  // reduced rules: xi, w psi_0, w psi_1
-    for (int t = threadIdx.x; t < HK_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
+    {
+        const int4* src = static_cast<const int4*>(P.tab);
+        int4* dst = reinterpret_cast<int4*>(tabraw);
+        for (int t = threadIdx.x; t < FarT<F32>::TAB_BYTES / 16; t += blockDim.x) dst[t] = src[t];
+    }
+    const void* tab = tabraw;
     if (threadIdx.x < 8) {
         wsh[threadIdx.x] = wt.wp0[threadIdx.x];
         wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
@@ -100,16 +150,29 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
     if (work >= P.nwork) return;
     const int64_t tile = work / P.nsub;
     const int sub = (int)(work - tile * P.nsub);
-    int J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
-    while ((int64_t)J * (J + 1) / 2 > tile) --J;
-    while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
-    const int I = (int)(tile - (int64_t)J * (J + 1) / 2);
     const int n = P.n;
+    int I, J;
+    if (P.band_only) {
+        // tiles (I, I + o mod T), o = 0, 1, 2, and their mirrors: with bw <= TB
+        // every entry within the band lies in one of them (only the last tile can
+        // be narrower than the band, so a neighbour may sit two tiles away)
+        const int T = (n + TB - 1) / TB;
+        I = (int)(tile / 3);
+        J = (I + (int)(tile % 3)) % T;
+    } else {
+        J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+        while ((int64_t)J * (J + 1) / 2 > tile) --J;
+        while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
+        I = (int)(tile - (int64_t)J * (J + 1) / 2);
+    }
     const int i0 = I * TB + sub * P.tr;
     const int i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), n);
     if (i0 >= i1) return;
     const int j0 = J * TB;
     const bool mirror = (I != J);
+    CT* __restrict__ oS = static_cast<CT*>(P.S);
+    CT* __restrict__ oN = static_cast<CT*>(P.Nm);
+    CT* __restrict__ oD = static_cast<CT*>(P.D);
 
     const int qraw = j0 - 1 + lane;
     const bool qvalid = qraw < n;
@@ -127,18 +190,21 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
     const double qex = P.nodes[2 * q1] - qx0, qey = P.nodes[2 * q1 + 1] - qy0;
     const double qcx = qx0 + 0.5 * qex, qcy = qy0 + 0.5 * qey;
 
-    const double2 z = make_double2(0.0, 0.0);
-    double2 pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
+    const CT z = CT{0, 0};
+    CT pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z, pH0 = z, pH1 = z;
 
     for (int pr = i0 - 1; pr < i1; ++pr) {
         const int p = pr < 0 ? pr + n : pr;
         int dd = p - q;
         dd = dd < 0 ? -dd : dd;
         const bool active = qvalid && dd > 1 && dd < n - 1;
-        double2 S00 = z, S01 = z, S10 = z, S11 = z;
-        double2 D00 = z, D01 = z, D10 = z, D11 = z;
-        double2 T00 = z, T01 = z, T10 = z, T11 = z;
+        CT S00 = z, S01 = z, S10 = z, S11 = z;
+        CT D00 = z, D01 = z, D10 = z, D11 = z;
+        CT T00 = z, T01 = z, T10 = z, T11 = z;
+        CT H00 = z, H01 = z, H10 = z, H11 = z;   // FP32 only: far N blocks, non-Maue form
         const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
+        const RT nnpq = (RT)fma(nxp, nxq, nyp * nyq);
+        const RT kk2 = (RT)(k * k);
         // quadrature order for this row panel, uniform over the wavefront
         const int p1 = p + 1 == n ? 0 : p + 1;
         const double px0 = P.nodes[2 * p], py0 = P.nodes[2 * p + 1];
@@ -169,7 +235,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
                     wa0 = rx[no + a];
                     wa1 = rx[2 * no + a];
                 }
-                double2 Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z;
+                CT Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z, Hg0 = z, Hg1 = z;
 #pragma unroll 1
                 for (int b = 0; b < no; ++b) {
                     double yb, zb, w0, w1;
@@ -186,67 +252,113 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
                     }
                     const double dx = xa - yb, dy = ya - zb;
                     const double R = sqrt(fma(dx, dx, dy * dy));
-                    const Bessel01 bs = hk_eval_hot(k * R, tab);
-                    const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
-                    const double kr = 0.25 * k / R;
-                    const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
-                    const double dq = fma(dx, nxq, dy * nyq);
-                    const double dp = -fma(dx, nxp, dy * nyp);
-                    const double2 cd = cscale(c, dq), ct = cscale(c, dp);
-                    Sg0 = fma_cr(w0, g, Sg0);
-                    Sg1 = fma_cr(w1, g, Sg1);
-                    Dg0 = fma_cr(w0, cd, Dg0);
-                    Dg1 = fma_cr(w1, cd, Dg1);
-                    Tg0 = fma_cr(w0, ct, Tg0);
-                    Tg1 = fma_cr(w1, ct, Tg1);
+                    CT g, c;
+                    far_kernel_values(k, R, tab, g, c);
+                    const RT dq = (RT)fma(dx, nxq, dy * nyq);
+                    const RT dp = (RT)(-fma(dx, nxp, dy * nyp));
+                    const CT cd = CT{c.x * dq, c.y * dq}, ct = CT{c.x * dp, c.y * dp};
+                    Sg0 = fma_cr((RT)w0, g, Sg0);
+                    Sg1 = fma_cr((RT)w1, g, Sg1);
+                    Dg0 = fma_cr((RT)w0, cd, Dg0);
+                    Dg1 = fma_cr((RT)w1, cd, Dg1);
+                    Tg0 = fma_cr((RT)w0, ct, Tg0);
+                    Tg1 = fma_cr((RT)w1, ct, Tg1);
+                    if constexpr (F32) {
+                        // N kernel without the Maue cancellation (far entries only):
+                        // d_sx d_sy g - k^2 (n_p.n_q) g = k^2 g (u v - nn) + c (nn - 2 u v),
+                        // u = tau_p.d/R, v = tau_q.d/R, nn = n_p.n_q = tau_p.tau_q
+                        const RT ir = (RT)__builtin_amdgcn_rcpf((float)R);
+                        const RT u = (RT)fma(-dx, nyp, dy * nxp) * ir;
+                        const RT v = (RT)fma(-dx, nyq, dy * nxq) * ir;
+                        const RT uv = u * v;
+                        const RT a1 = kk2 * (uv - nnpq), a2 = nnpq - 2.0f * uv;
+                        const CT hk = CT{fmaf(a1, g.x, a2 * c.x), fmaf(a1, g.y, a2 * c.y)};
+                        Hg0 = fma_cr((RT)w0, hk, Hg0);
+                        Hg1 = fma_cr((RT)w1, hk, Hg1);
+                    }
                 }
-                S00 = fma_cr(wa0, Sg0, S00); S01 = fma_cr(wa0, Sg1, S01);
-                S10 = fma_cr(wa1, Sg0, S10); S11 = fma_cr(wa1, Sg1, S11);
-                D00 = fma_cr(wa0, Dg0, D00); D01 = fma_cr(wa0, Dg1, D01);
-                D10 = fma_cr(wa1, Dg0, D10); D11 = fma_cr(wa1, Dg1, D11);
-                T00 = fma_cr(wa0, Tg0, T00); T01 = fma_cr(wa0, Tg1, T01);
-                T10 = fma_cr(wa1, Tg0, T10); T11 = fma_cr(wa1, Tg1, T11);
+                const RT a0 = (RT)wa0, a1 = (RT)wa1;
+                S00 = fma_cr(a0, Sg0, S00); S01 = fma_cr(a0, Sg1, S01);
+                S10 = fma_cr(a1, Sg0, S10); S11 = fma_cr(a1, Sg1, S11);
+                D00 = fma_cr(a0, Dg0, D00); D01 = fma_cr(a0, Dg1, D01);
+                D10 = fma_cr(a1, Dg0, D10); D11 = fma_cr(a1, Dg1, D11);
+                T00 = fma_cr(a0, Tg0, T00); T01 = fma_cr(a0, Tg1, T01);
+                T10 = fma_cr(a1, Tg0, T10); T11 = fma_cr(a1, Tg1, T11);
+                if constexpr (F32) {
+                    H00 = fma_cr(a0, Hg0, H00); H01 = fma_cr(a0, Hg1, H01);
+                    H10 = fma_cr(a1, Hg0, H10); H11 = fma_cr(a1, Hg1, H11);
+                }
             }
-            const double hh = hp * hq;
+            const RT hh = (RT)(hp * hq);
             S00 = cscale(S00, hh); S01 = cscale(S01, hh); S10 = cscale(S10, hh); S11 = cscale(S11, hh);
             D00 = cscale(D00, hh); D01 = cscale(D01, hh); D10 = cscale(D10, hh); D11 = cscale(D11, hh);
             T00 = cscale(T00, hh); T01 = cscale(T01, hh); T10 = cscale(T10, hh); T11 = cscale(T11, hh);
+            if constexpr (F32) {
+                H00 = cscale(H00, hh); H01 = cscale(H01, hh); H10 = cscale(H10, hh); H11 = cscale(H11, hh);
+            }
         }
         // Maue form of N from S: N_ab = s_a s_b I0/(hp hq) - k^2 (np.nq) S_ab
-        const double2 I0 = cadd(cadd(S00, S01), cadd(S10, S11));
-        const double2 I0h = cscale(I0, 1.0 / (hp * hq));
-        const double kk = -k * k * fma(nxp, nxq, nyp * nyq);
-        const double2 N00 = cadd(I0h, cscale(S00, kk));
-        const double2 N01 = csub(cscale(S01, kk), I0h);
-        const double2 N10 = csub(cscale(S10, kk), I0h);
-        const double2 N11 = cadd(I0h, cscale(S11, kk));
+        const CT I0 = cadd(cadd(S00, S01), cadd(S10, S11));
+        const CT I0h = cscale(I0, (RT)(1.0 / (hp * hq)));
+        const RT kk = (RT)(-k * k * fma(nxp, nxq, nyp * nyq));
+        const CT N00 = cadd(I0h, cscale(S00, kk));
+        const CT N01 = csub(cscale(S01, kk), I0h);
+        const CT N10 = csub(cscale(S10, kk), I0h);
+        const CT N11 = cadd(I0h, cscale(S11, kk));
 
         if (pr >= i0) {
             const int i = pr;
             // row i receives psi_0 of the current row panel and psi_1 of the previous one
-            const double2 rS0 = cadd(S00, pS0), rS1 = cadd(S01, pS1);
-            const double2 rN0 = cadd(N00, pN0), rN1 = cadd(N01, pN1);
-            const double2 rD0 = cadd(D00, pD0), rD1 = cadd(D01, pD1);
-            const double2 rT0 = cadd(T00, pT0), rT1 = cadd(T01, pT1);
-            const double2 nS = shfl_down1(rS0), nN = shfl_down1(rN0);
-            const double2 nD = shfl_down1(rD0), nT = shfl_down1(rT0);
-            if (writes) {
-                const double2 vS = cadd(rS1, nS), vN = cadd(rN1, nN);
-                const double2 vD = cadd(rD1, nD), vT = cadd(rT1, nT);
+            const CT rS0 = cadd(S00, pS0), rS1 = cadd(S01, pS1);
+            const CT rN0 = cadd(N00, pN0), rN1 = cadd(N01, pN1);
+            const CT rD0 = cadd(D00, pD0), rD1 = cadd(D01, pD1);
+            const CT rT0 = cadd(T00, pT0), rT1 = cadd(T01, pT1);
+            const CT nS = shfl_down1(rS0), nN = shfl_down1(rN0);
+            const CT nD = shfl_down1(rD0), nT = shfl_down1(rT0);
+            CT vN = cadd(rN1, nN);
+            if constexpr (F32) {
+                // In FP32 the Maue sum of the four panel pairs of a far entry cancels
+                // like (h/R)^2; entries whose four pairs are all far (cyclic |i - j| >= 3)
+                // take the integrated-back kernel instead, which is cancellation-free.
+                const CT rH0 = cadd(H00, pH0), rH1 = cadd(H01, pH1);
+                const CT nH = shfl_down1(rH0);
+                int dij = i - col;
+                dij = dij < 0 ? -dij : dij;
+                if (dij >= 3 && dij <= n - 3) vN = cadd(rH1, nH);
+            }
+            // cyclic offset col - i in (-n/2, n/2]
+            int dcy = col - i;
+            dcy = dcy < 0 ? dcy + n : dcy;
+            dcy = 2 * dcy > n ? dcy - n : dcy;
+            const bool inband = (dcy < 0 ? -dcy : dcy) <= P.bw;
+            if (P.band_only) {
+                if (writes && inband) {
+                    const int bs = 2 * P.bw + 1;
+                    const double2 vb = make_double2((double)vN.x, (double)vN.y);
+                    P.nband[(int64_t)i * bs + dcy + P.bw] = vb;
+                    P.nband[(int64_t)col * bs - dcy + P.bw] = vb;
+                }
+            } else if (writes) {
+                if constexpr (F32) {
+                    if (inband) vN = CT{0, 0};   // held in FP64 in the band array
+                }
+                const CT vS = cadd(rS1, nS);
+                const CT vD = cadd(rD1, nD), vT = cadd(rT1, nT);
                 const int64_t rc = (int64_t)i * n + col;
-                P.S[rc] = vS;
-                P.Nm[rc] = vN;
-                P.D[rc] = vD;
+                oS[rc] = vS;
+                oN[rc] = vN;
+                oD[rc] = vD;
                 if (mirror) {
                     const int64_t cr = (int64_t)col * n + i;
-                    P.S[cr] = vS;
-                    P.Nm[cr] = vN;
-                    P.D[cr] = vT;
+                    oS[cr] = vS;
+                    oN[cr] = vN;
+                    oD[cr] = vT;
                 }
             }
         }
         pS0 = S10; pS1 = S11; pN0 = N10; pN1 = N11;
         pD0 = D10; pD1 = D11; pT0 = T10; pT1 = T11;
+        pH0 = H10; pH1 = H11;
     }
 }
 
@@ -391,9 +503,11 @@ struct BandParams {
     const double* __restrict__ nx;
     const double* __restrict__ ny;
     const double2* __restrict__ nb;
-    double2* __restrict__ S;
-    double2* __restrict__ Nm;
-    double2* __restrict__ D;
+    void* __restrict__ S;
+    void* __restrict__ Nm;
+    void* __restrict__ D;
+    double2* __restrict__ nband;     // FP32 operators: N on the cyclic band |d| <= bw (complex128)
+    int bw;
     double k;
     int n;
 };
@@ -424,31 +538,61 @@ __device__ void near_entry(const BandParams& P, int r, int c, double2& s, double
     }
 }
 
+__device__ __forceinline__ double2 ld_c(const double2* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double2 ld_c(const float2* p, int64_t i) {
+    const float2 v = p[i];
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_c(double2* p, int64_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void st_c(float2* p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
+// Adds the near-pair blocks to the band |i - j| <= 2 (in FP64) and symmetrises S, N there.
+template <typename CT>
 __global__ void asm_band_kernel(BandParams P) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = P.n;
     if (t >= 3 * n) return;
+    CT* S = static_cast<CT*>(P.S);
+    CT* Nm = static_cast<CT*>(P.Nm);
+    CT* D = static_cast<CT*>(P.D);
     const int i = t / 3, dlt = t - 3 * (t / 3);
     const int j = (i + dlt) % n;
     double2 s1, n1, d1;
     near_entry(P, i, j, s1, n1, d1);
     const int64_t ij = (int64_t)i * n + j, ji = (int64_t)j * n + i;
+    // N: FP32 operators keep N near the diagonal in the complex128 band array
+    // (filled by the FP64 band pass of the far kernel); the near pairs add there.
+    constexpr bool split = std::is_same<CT, float2>::value;
+    const int bs = 2 * P.bw + 1;
     if (dlt == 0) {
-        P.S[ij] = cadd(P.S[ij], s1);
-        P.Nm[ij] = cadd(P.Nm[ij], n1);
-        P.D[ij] = cadd(P.D[ij], d1);
+        st_c(S, ij, cadd(ld_c(S, ij), s1));
+        if constexpr (split) {
+            double2* e = P.nband + (int64_t)i * bs + P.bw;
+            *e = cadd(*e, n1);
+        } else {
+            st_c(Nm, ij, cadd(ld_c(Nm, ij), n1));
+        }
+        st_c(D, ij, cadd(ld_c(D, ij), d1));
         return;
     }
     double2 s2, n2, d2;
     near_entry(P, j, i, s2, n2, d2);
-    const double2 sa = cscale(cadd(cadd(P.S[ij], s1), cadd(P.S[ji], s2)), 0.5);
-    const double2 na = cscale(cadd(cadd(P.Nm[ij], n1), cadd(P.Nm[ji], n2)), 0.5);
-    P.S[ij] = sa;
-    P.S[ji] = sa;
-    P.Nm[ij] = na;
-    P.Nm[ji] = na;
-    P.D[ij] = cadd(P.D[ij], d1);
-    P.D[ji] = cadd(P.D[ji], d2);
+    const double2 sa = cscale(cadd(cadd(ld_c(S, ij), s1), cadd(ld_c(S, ji), s2)), 0.5);
+    st_c(S, ij, sa);
+    st_c(S, ji, sa);
+    if constexpr (split) {
+        double2* eij = P.nband + (int64_t)i * bs + P.bw + dlt;
+        double2* eji = P.nband + (int64_t)j * bs + P.bw - dlt;
+        const double2 na = cscale(cadd(cadd(*eij, n1), cadd(*eji, n2)), 0.5);
+        *eij = na;
+        *eji = na;
+    } else {
+        const double2 na = cscale(cadd(cadd(ld_c(Nm, ij), n1), cadd(ld_c(Nm, ji), n2)), 0.5);
+        st_c(Nm, ij, na);
+        st_c(Nm, ji, na);
+    }
+    st_c(D, ij, cadd(ld_c(D, ij), d1));
+    st_c(D, ji, cadd(ld_c(D, ji), d2));
 }
 
 void launch_assemble(Op& op) {
@@ -477,7 +621,17 @@ void launch_assemble(Op& op) {
     }
     FarParams fp;
     fp.gx = op.gx; fp.gy = op.gy; fp.h = op.h; fp.nx = op.nx; fp.ny = op.ny;
-    fp.tab = c.hk_tab; fp.nodes = op.nodes; fp.S = op.S; fp.Nm = op.Nm; fp.D = op.D; fp.k = op.k; fp.n = n;
+    const bool f32 = op.prec == FDS_FP32;
+    fp.tab = f32 ? (const void*)c.hk_tab32 : (const void*)c.hk_tab;
+    fp.nodes = op.nodes;
+    fp.S = f32 ? (void*)op.S32 : (void*)op.S;
+    fp.Nm = f32 ? (void*)op.N32 : (void*)op.Nm;
+    fp.D = f32 ? (void*)op.D32 : (void*)op.D;
+    fp.k = op.k;
+    fp.n = n;
+    fp.nband = op.Nband;
+    fp.bw = f32 ? op.nbw : -1;
+    fp.band_only = 0;
     const int64_t T = (n + TB - 1) / TB;
     fp.nsub = 2;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
@@ -485,9 +639,25 @@ void launch_assemble(Op& op) {
     const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
     {
         KScope _ks(c, "asm_far");
-        hipLaunchKernelGGL(asm_far_kernel, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+        if (f32)
+            hipLaunchKernelGGL(asm_far_kernel<true>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+        else
+            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
     }
     FDS_HIP_TRY(hipGetLastError());
+    if (f32) {
+        // FP64 pass over the tiles that touch the band: N there in complex128
+        FarParams bpf = fp;
+        bpf.tab = c.hk_tab;
+        bpf.band_only = 1;
+        bpf.nwork = 3 * T * bpf.nsub;
+        const unsigned nb2 = (unsigned)((bpf.nwork + WAVES - 1) / WAVES);
+        {
+            KScope _ks(c, "asm_far_band");
+            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt, wlow);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+    }
 
     double2* nb = static_cast<double2*>(c.dmalloc(sizeof(double2) * 24 * (size_t)n));
     NearParams np;
@@ -501,10 +671,15 @@ void launch_assemble(Op& op) {
     FDS_HIP_TRY(hipGetLastError());
     BandParams bp;
     bp.h = op.h; bp.nx = op.nx; bp.ny = op.ny; bp.nb = nb;
-    bp.S = op.S; bp.Nm = op.Nm; bp.D = op.D; bp.k = op.k; bp.n = n;
+    bp.S = fp.S; bp.Nm = fp.Nm; bp.D = fp.D; bp.k = op.k; bp.n = n;
+    bp.nband = op.Nband;
+    bp.bw = op.nbw;
     {
         KScope _ks(c, "asm_band");
-        hipLaunchKernelGGL(asm_band_kernel, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
+        if (f32)
+            hipLaunchKernelGGL(asm_band_kernel<float2>, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
+        else
+            hipLaunchKernelGGL(asm_band_kernel<double2>, dim3((3 * n + 127) / 128), dim3(128), 0, c.stream, bp);
     }
     FDS_HIP_TRY(hipGetLastError());
     c.dfree(nb);   // stream-ordered release (see Ctx::dfree)

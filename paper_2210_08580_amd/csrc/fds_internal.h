@@ -39,6 +39,9 @@ __host__ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __host__ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 __host__ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // ------------------------------------------------------------------ context / operator
 struct ProfRec {
@@ -55,6 +58,7 @@ struct Ctx {
     fds_allocator alloc{};
     bool has_alloc = false;
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
+    float* hk_tab32 = nullptr;    // device copy of the single-precision table
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     void* dmalloc(size_t bytes);
     void dfree(void* p);
@@ -106,10 +110,17 @@ struct Op {
     double* l_diag = nullptr;     // Laplacian diag / off
     double* l_off = nullptr;
     GaussRule8 rule{};
-    // dense operators (device, row-major complex128)
+    // dense operators (device, row-major): complex128, or complex64 when prec == FDS_FP32
+    int prec = FDS_FP64;
     double2* S = nullptr;
     double2* Nm = nullptr;
     double2* D = nullptr;
+    float2* S32 = nullptr;
+    float2* N32 = nullptr;
+    float2* D32 = nullptr;
+    double2* Nband = nullptr;     // FP32 operators: N on the cyclic band |d| <= nbw in complex128,
+                                  // [n][2 nbw + 1] (N[i][(i + d) mod n] at [i][d + nbw]); N32 is zero there
+    int nbw = 0;
     // filter / compact part
     int form = 0;
     double alpha = 1.0;
@@ -142,6 +153,7 @@ void launch_geometry(Op& op);
 void launch_rhs_planewave(Op& op, const double* angles, const double2* amps, int64_t nrhs,
                           double2* f, double2* h);
 void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out);
+void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out);
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
 // assemble.hip
 void launch_assemble(Op& op);

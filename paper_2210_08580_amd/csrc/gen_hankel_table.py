@@ -17,6 +17,11 @@ Three regions of the real argument x > 0 (J0, Y0, J1, Y1):
 The script checks a float64 emulation of the device formulas against mpmath and
 refuses to write the table unless every region is within 4e-16 max(|f|, 1).
 
+A second, single-precision set (HK32_*) serves the FP32 far-field assembly: the
+same three regions with degree-DEG32 interpolants and shorter series/expansions,
+checked in a float32 emulation (argument x and the table variable t formed in
+float64, everything after in float32) against 4e-7 max(|f|, 1).
+
 Run:  python gen_hankel_table.py   (writes hankel_table.inc next to this file)
 """
 from __future__ import annotations
@@ -31,6 +36,8 @@ mp.mp.dps = 50
 XS, XA = 2, 25
 DEG = 21
 NSER = 16
+DEG32 = 9
+NSER32 = 9
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -74,10 +81,10 @@ def fns():
             lambda x: mp.besselj(1, x), lambda x: mp.bessely(1, x)]
 
 
-def cheb_monomial(f, c):
-    """Monomial coefficients in t = x - (c + 1/2) of the degree-DEG Chebyshev
+def cheb_monomial(f, c, deg=DEG):
+    """Monomial coefficients in t = x - (c + 1/2) of the degree-`deg` Chebyshev
     interpolant of f on [c, c+1]."""
-    n = DEG + 1
+    n = deg + 1
     u = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n)]
     vals = [f(c + mp.mpf(1) / 2 + uj / 2) for uj in u]
     # Chebyshev coefficients in u
@@ -138,6 +145,67 @@ def emulate(x, tabs, ser, asy):
             amp * (p1 * c1 - q1 * s1), amp * (p1 * s1 + q1 * c1))
 
 
+def emulate32(x, tabs, ser, asy):
+    f4 = np.float32
+    x = np.float64(x)
+
+    def h32(c, t):
+        acc = f4(c[-1])
+        for v in c[-2::-1]:
+            acc = f4(acc * t + f4(v))
+        return acc
+    if x < XS:
+        q = f4(x * x / 4)
+        xf = f4(x)
+        cj0, cy0, cj1, cy1 = ser
+        j0 = h32(cj0, q)
+        j1 = f4(f4(0.5) * xf * h32(cj1, q))
+        l = f4(np.log(f4(0.5) * xf))
+        tp = f4(2 / np.pi)
+        y0 = f4(tp * f4(f4(l + f4(np.euler_gamma)) * j0 + q * h32(cy0[1:], q)))
+        y1 = f4(f4(-tp / xf) + tp * l * j1 - f4(xf * f4(0.5 / np.pi)) * h32(cy1, q))
+        return j0, y0, j1, y1
+    if x < XA:
+        c = int(np.floor(x))
+        t = f4(x - (c + 0.5))
+        return tuple(h32(tabs[f][c - XS], t) for f in range(4))
+    P0, Q0, P1, Q1 = asy
+    xf = f4(x)
+    w = f4(f4(1) / (xf * xf))
+    rx = f4(f4(1) / xf)
+    p0, q0 = h32(P0, w), f4(h32(Q0, w) * rx)
+    p1, q1 = h32(P1, w), f4(h32(Q1, w) * rx)
+    amp = f4(np.sqrt(f4(2 / np.pi) * rx))
+    xr = f4(x - 2 * np.pi * np.rint(x / (2 * np.pi)))     # phase reduced in float64
+    sn, co = np.sin(xr, dtype=np.float32), np.cos(xr, dtype=np.float32)
+    r = f4(np.sqrt(0.5))
+    c0, s0 = r * (co + sn), r * (sn - co)
+    c1, s1 = r * (sn - co), -r * (sn + co)
+    return (amp * (p0 * c0 - q0 * s0), amp * (p0 * s0 + q0 * c0),
+            amp * (p1 * c1 - q1 * s1), amp * (p1 * s1 + q1 * c1))
+
+
+def table32():
+    ser = [[float(v) for v in s[:NSER32]] for s in series_coeffs()]
+    nas = asym_terms_needed(XA, tol=2e-9)
+    asy = [[float(v) for v in s] for s in (*asym_coeffs(0, nas)[:2], *asym_coeffs(1, nas)[:2])]
+    F = fns()
+    tabs = [[[float(v) for v in cheb_monomial(F[f], c, DEG32)] for c in range(XS, XA)] for f in range(4)]
+    xs = np.concatenate([np.geomspace(1e-4, XS, 300, endpoint=False),
+                         np.linspace(XS, XA, 2300, endpoint=False),
+                         np.linspace(XA, 200, 600)])
+    worst = 0.0
+    for x in xs:
+        got = emulate32(x, tabs, ser, asy)
+        for f in range(4):
+            ref = float(F[f](mp.mpf(float(x))))
+            worst = max(worst, abs(float(got[f]) - ref) / max(1.0, abs(ref)))
+    print(f"fp32 set: asymptotic terms {nas}; worst scaled error {worst:.3e}")
+    if worst > 4e-7:
+        sys.exit("fp32 table accuracy check failed")
+    return ser, asy, tabs, nas
+
+
 def main():
     ser = series_coeffs()
     nas = asym_terms_needed(XA)
@@ -162,6 +230,7 @@ def main():
     print(f"asymptotic terms: {nas}; worst scaled error {worst:.3e}")
     if worst > 4e-16:
         sys.exit("table accuracy check failed")
+    ser32, asy32, tab32, nas32 = table32()
     out = os.path.join(HERE, "hankel_table.inc")
     with open(out, "w") as fh:
         fh.write("// Generated by gen_hankel_table.py; do not edit.\n")
@@ -181,6 +250,20 @@ def main():
             fh.write(" {\n")
             for m in range(DEG + 1):
                 fh.write("  {" + ", ".join(repr(tabd[f][c][m]) for f in range(4)) + "},\n")
+            fh.write(" },\n")
+        fh.write("};\n")
+        fh.write(f"#define HK32_DEG {DEG32}\n#define HK32_NSER {NSER32}\n#define HK32_NASY {nas32}\n")
+        for nm, v in zip(("HK32_SER_J0", "HK32_SER_Y0", "HK32_SER_J1", "HK32_SER_Y1"), ser32):
+            fh.write(f"static constexpr float {nm}[{len(v)}] = {{" + ", ".join(repr(x) + "f" for x in
+                                                                            np.float32(v).tolist()) + "};\n")
+        for nm, v in zip(("HK32_ASY_P0", "HK32_ASY_Q0", "HK32_ASY_P1", "HK32_ASY_Q1"), asy32):
+            fh.write(f"static constexpr float {nm}[{len(v)}] = {{" + ", ".join(repr(x) + "f" for x in
+                                                                            np.float32(v).tolist()) + "};\n")
+        fh.write(f"static constexpr float HK32_TAB[{nint}][{DEG32 + 1}][4] = {{\n")
+        for c in range(nint):
+            fh.write(" {\n")
+            for m in range(DEG32 + 1):
+                fh.write("  {" + ", ".join(repr(float(np.float32(tab32[f][c][m]))) + "f" for f in range(4)) + "},\n")
             fh.write(" },\n")
         fh.write("};\n")
     print("wrote", out)

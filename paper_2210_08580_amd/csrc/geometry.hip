@@ -140,6 +140,17 @@ __global__ void hankel_eval_kernel(const double* __restrict__ x, int64_t n,
     out[4 * i + 3] = b.y1;
 }
 
+__global__ void hankel_eval_f32_kernel(const double* __restrict__ x, int64_t n, const float* __restrict__ tab,
+                                       float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Bessel01f b = hk32_eval_hot(x[i], tab);
+    out[4 * i + 0] = b.j0;
+    out[4 * i + 1] = b.y0;
+    out[4 * i + 2] = b.j1;
+    out[4 * i + 3] = b.y1;
+}
+
 __global__ void kernel_eval_kernel(double k, const double* __restrict__ Rs, int64_t n,
                                    const double* __restrict__ tab, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,6 +217,15 @@ void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out) {
         KScope _ks(c, "hankel_eval");
         hipLaunchKernelGGL(hankel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
                        c.hk_tab, out);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out) {
+    {
+        KScope _ks(c, "hankel_eval");
+        hipLaunchKernelGGL(hankel_eval_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
+                           c.hk_tab32, out);
     }
     FDS_HIP_TRY(hipGetLastError());
 }

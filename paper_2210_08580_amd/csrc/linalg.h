@@ -12,6 +12,12 @@ constexpr double kPiHost = 3.14159265358979323846;
 // C = alpha op(A) op(B) + beta C, column-major, m x n result, inner dimension k.
 void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const double2* A, int64_t lda,
            const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);
+// zgemm with a complex64 A operand, widened to complex128 on load (FP64 MFMA).
+void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const float2* A, int64_t lda,
+               const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);
+// Complex64 variant on the FP32 matrix cores (FP32 accumulation).
+void cgemm(Ctx& c, int opa, int opb, int m, int n, int k, float2 alpha, const float2* A, int64_t lda,
+           const float2* B, int64_t ldb, float2 beta, float2* C, int64_t ldc);
 void dgemm(Ctx& c, int opa, int opb, int m, int n, int k, double alpha, const double* A, int64_t lda,
            const double* B, int64_t ldb, double beta, double* C, int64_t ldc);
 

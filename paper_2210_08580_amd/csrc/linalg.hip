@@ -1,5 +1,6 @@
 // Dense and sparse linear algebra on the device:
-//   * complex (and real) GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64), column-major,
+//   * complex (and real) GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64) and complex64
+//     GEMM on FP32 MFMA (v_mfma_f32_16x16x4f32, FP32 accumulation), column-major,
 //     op(A), op(B) in {N, T, C}, optional split-K with a deterministic reduction;
 //   * the periodic tridiagonal Gram matrix G: factorisation (cyclic Thomas with
 //     a Sherman-Morrison correction), block solves G^{-1} X, block products G X;
@@ -7,6 +8,7 @@
 //   * small dense factorisations in one workgroup: Cholesky (real), LU with
 //     partial pivoting (complex), block triangular solves.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "fds_internal.h"
@@ -17,35 +19,81 @@ namespace fds {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ============================================================ GEMM
+// 64 x 64 output tile per workgroup of 4 wavefronts (2 x 2 of 32 x 32), K staged
+// through LDS 16 at a time; each wavefront holds 2 x 2 MFMA 16 x 16 accumulators
+// (real and imaginary parts separately: 4 real MFMAs per complex product).
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16, G_PAD = 2;
 
-template <bool CPLX>
-struct Elt;
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct GT;
 template <>
-struct Elt<true> {
-    typedef double2 T;
+struct GT<double> {
+    typedef double R;
+    typedef d4 Acc;
+    static constexpr bool CPLX = false;
 };
 template <>
-struct Elt<false> {
-    typedef double T;
+struct GT<double2> {
+    typedef double R;
+    typedef d4 Acc;
+    static constexpr bool CPLX = true;
 };
+template <>
+struct GT<float2> {
+    typedef float R;
+    typedef f4 Acc;
+    static constexpr bool CPLX = true;
+};
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of accumulator register v of a lane within the 16 x 16 tile (column = lane & 15):
+// v_mfma_f64_16x16x4f64 places D[i][j] in lane j + 16 (i % 4), register i / 4;
+// v_mfma_f32_16x16x4f32 places it in lane j + 16 (i / 4), register i % 4.
+__device__ __forceinline__ int acc_row(double, int lane, int v) { return (lane >> 4) + 4 * v; }
+__device__ __forceinline__ int acc_row(float, int lane, int v) { return 4 * (lane >> 4) + v; }
 
 __device__ __forceinline__ double2 ld_op(const double2* p, int op) {
     double2 v = *p;
     if (op == OP_C) v.y = -v.y;
     return v;
 }
+__device__ __forceinline__ float2 ld_op(const float2* p, int op) {
+    float2 v = *p;
+    if (op == OP_C) v.y = -v.y;
+    return v;
+}
 __device__ __forceinline__ double ld_op(const double* p, int) { return *p; }
+// complex64 operand widened to complex128 on load (FP64 arithmetic on FP32-stored matrices)
+__device__ __forceinline__ void ld_into(const float2* p, int op, double2& v) {
+    const float2 f = *p;
+    v = make_double2(f.x, op == OP_C ? -f.y : f.y);
+}
+template <typename T>
+__device__ __forceinline__ void ld_into(const T* p, int op, T& v) { v = ld_op(p, op); }
 
-template <bool CPLX, int OPA, int OPB>
-__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, typename Elt<CPLX>::T alpha,
-                                                   const typename Elt<CPLX>::T* __restrict__ A,
-                                                   int64_t lda,
-                                                   const typename Elt<CPLX>::T* __restrict__ B,
-                                                   int64_t ldb, typename Elt<CPLX>::T beta,
-                                                   typename Elt<CPLX>::T* __restrict__ C, int64_t ldc,
-                                                   int kchunk, typename Elt<CPLX>::T* __restrict__ part) {
-    typedef typename Elt<CPLX>::T T;
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ bool nonzero(double2 b) { return b.x != 0.0 || b.y != 0.0; }
+__device__ __forceinline__ bool nonzero(float2 b) { return b.x != 0.0f || b.y != 0.0f; }
+__device__ __forceinline__ bool nonzero(double b) { return b != 0.0; }
+__device__ __forceinline__ double cmul(double a, double b) { return a * b; }
+__device__ __forceinline__ double cadd(double a, double b) { return a + b; }
+
+template <typename T, typename TA, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha, const TA* __restrict__ A,
+                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta,
+                                                   T* __restrict__ C, int64_t ldc, int kchunk,
+                                                   T* __restrict__ part) {
+    typedef typename GT<T>::R RT;
+    typedef typename GT<T>::Acc Acc;
     __shared__ T sA[GB_K][GB_M + G_PAD];
     __shared__ T sB[GB_K][GB_N + G_PAD];
     const int tid = threadIdx.x;
@@ -55,13 +103,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, typename
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(k, kbeg + kchunk);
 
-    d4 accR[2][2], accI[2][2];
+    Acc accR[2][2], accI[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            accR[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-            accI[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            accR[a][b] = Acc{0, 0, 0, 0};
+            accI[a][b] = Acc{0, 0, 0, 0};
         }
 
     for (int kk = kbeg; kk < kend; kk += GB_K) {
@@ -79,8 +127,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, typename
             const int gi = row0 + i, gp = kk + p;
             T v{};
             if (gi < m && gp < kend) {
-                const T* src = (OPA == OP_N) ? A + gi + (int64_t)gp * lda : A + gp + (int64_t)gi * lda;
-                v = ld_op(src, OPA);
+                const TA* src = (OPA == OP_N) ? A + gi + (int64_t)gp * lda : A + gp + (int64_t)gi * lda;
+                ld_into(src, OPA, v);
             }
             sA[p][i] = v;
         }
@@ -116,79 +164,62 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, typename
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    if constexpr (CPLX) {
-                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, accR[r][c], 0, 0, 0);
-                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[r].y, b[c].y, accR[r][c], 0, 0, 0);
-                        accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, accI[r][c], 0, 0, 0);
-                        accI[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].y, b[c].x, accI[r][c], 0, 0, 0);
+                    if constexpr (GT<T>::CPLX) {
+                        accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
+                        accR[r][c] = mfma16(-a[r].y, b[c].y, accR[r][c]);
+                        accI[r][c] = mfma16(a[r].x, b[c].y, accI[r][c]);
+                        accI[r][c] = mfma16(a[r].y, b[c].x, accI[r][c]);
                     } else {
-                        accR[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], accR[r][c], 0, 0, 0);
+                        accR[r][c] = mfma16(a[r], b[c], accR[r][c]);
                     }
                 }
         }
         __syncthreads();
     }
-    // ---- epilogue: v_mfma_f64_16x16x4f64 leaves D[i][j] in lane j + 16*(i%4), register i/4
+    // ---- epilogue
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gi = row0 + wm * 32 + r * 16 + (lane >> 4) + 4 * v;
+                const int gi = row0 + wm * 32 + r * 16 + acc_row(RT{}, lane, v);
                 const int gj = col0 + wn * 32 + c * 16 + (lane & 15);
                 if (gi >= m || gj >= n) continue;
-                if constexpr (CPLX) {
-                    const double2 acc = make_double2(accR[r][c][v], accI[r][c][v]);
-                    if (part) {
-                        part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
-                    } else {
-                        double2 o = cmul(alpha, acc);
-                        if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[gi + (int64_t)gj * ldc]));
-                        C[gi + (int64_t)gj * ldc] = o;
-                    }
+                T acc;
+                if constexpr (GT<T>::CPLX) {
+                    acc.x = accR[r][c][v];
+                    acc.y = accI[r][c][v];
                 } else {
-                    const double acc = accR[r][c][v];
-                    if (part) {
-                        part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
-                    } else {
-                        double o = alpha * acc;
-                        if (beta != 0.0) o += beta * C[gi + (int64_t)gj * ldc];
-                        C[gi + (int64_t)gj * ldc] = o;
-                    }
+                    acc = accR[r][c][v];
+                }
+                if (part) {
+                    part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
+                } else {
+                    T o = cmul(alpha, acc);
+                    if (nonzero(beta)) o = cadd(o, cmul(beta, C[gi + (int64_t)gj * ldc]));
+                    C[gi + (int64_t)gj * ldc] = o;
                 }
             }
 }
 
-template <bool CPLX>
-__global__ void splitk_reduce_kernel(int m, int n, int nz, typename Elt<CPLX>::T alpha,
-                                     const typename Elt<CPLX>::T* __restrict__ part,
-                                     typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* __restrict__ C,
-                                     int64_t ldc) {
+template <typename T>
+__global__ void splitk_reduce_kernel(int m, int n, int nz, T alpha, const T* __restrict__ part, T beta,
+                                     T* __restrict__ C, int64_t ldc) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)m * n) return;
     const int i = (int)(t % m);
     const int64_t j = t / m;
-    if constexpr (CPLX) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int z = 0; z < nz; ++z) s = cadd(s, part[(int64_t)z * m * n + t]);
-        double2 o = cmul(alpha, s);
-        if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[i + j * ldc]));
-        C[i + j * ldc] = o;
-    } else {
-        double s = 0.0;
-        for (int z = 0; z < nz; ++z) s += part[(int64_t)z * m * n + t];
-        double o = alpha * s;
-        if (beta != 0.0) o += beta * C[i + j * ldc];
-        C[i + j * ldc] = o;
-    }
+    T s{};
+    for (int z = 0; z < nz; ++z) s = cadd(s, part[(int64_t)z * m * n + t]);
+    T o = cmul(alpha, s);
+    if (nonzero(beta)) o = cadd(o, cmul(beta, C[i + j * ldc]));
+    C[i + j * ldc] = o;
 }
 
-template <bool CPLX, int OPA, int OPB>
-static void gemm_dispatch(Ctx& c, int m, int n, int k, typename Elt<CPLX>::T alpha,
-                          const typename Elt<CPLX>::T* A, int64_t lda, const typename Elt<CPLX>::T* B,
-                          int64_t ldb, typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* C, int64_t ldc) {
-    typedef typename Elt<CPLX>::T T;
+template <typename T, typename TA, int OPA, int OPB>
+static void gemm_dispatch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
+                          T beta, T* C, int64_t ldc) {
     const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
     // split K when the output tiles alone cannot fill the chip
     int nz = 1;
@@ -203,32 +234,31 @@ static void gemm_dispatch(Ctx& c, int m, int n, int k, typename Elt<CPLX>::T alp
     T* part = nullptr;
     if (nz > 1) part = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
     {
-        KScope _ks(c, "gemm");
-        hipLaunchKernelGGL((gemm_kernel<CPLX, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
-                       alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+        KScope _ks(c, std::is_same<T, float2>::value ? "gemm_c64" : "gemm");
+        hipLaunchKernelGGL((gemm_kernel<T, TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k, alpha, A,
+                           lda, B, ldb, beta, C, ldc, kchunk, part);
     }
     FDS_HIP_TRY(hipGetLastError());
     if (part) {
         const int64_t tot = (int64_t)m * n;
         {
-        KScope _ks(c, "gemm_splitk_reduce");
-        hipLaunchKernelGGL(splitk_reduce_kernel<CPLX>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                           c.stream, m, n, nz, alpha, part, beta, C, ldc);
-    }
+            KScope _ks(c, "gemm_splitk_reduce");
+            hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream,
+                               m, n, nz, alpha, part, beta, C, ldc);
+        }
         FDS_HIP_TRY(hipGetLastError());
         c.dfree(part);
     }
 }
 
-template <bool CPLX>
-static void gemm_any(Ctx& c, int opa, int opb, int m, int n, int k, typename Elt<CPLX>::T alpha,
-                     const typename Elt<CPLX>::T* A, int64_t lda, const typename Elt<CPLX>::T* B, int64_t ldb,
-                     typename Elt<CPLX>::T beta, typename Elt<CPLX>::T* C, int64_t ldc) {
+template <typename T, typename TA = T>
+static void gemm_any(Ctx& c, int opa, int opb, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B,
+                     int64_t ldb, T beta, T* C, int64_t ldc) {
     if (m <= 0 || n <= 0) return;
-#define FDS_G(a, b)                                                                            \
-    if (opa == a && opb == b) {                                                                \
-        gemm_dispatch<CPLX, a, b>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);             \
-        return;                                                                                \
+#define FDS_G(a, b)                                                                    \
+    if (opa == a && opb == b) {                                                        \
+        gemm_dispatch<T, TA, a, b>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);   \
+        return;                                                                        \
     }
     FDS_G(OP_N, OP_N) FDS_G(OP_N, OP_T) FDS_G(OP_N, OP_C)
     FDS_G(OP_T, OP_N) FDS_G(OP_T, OP_T) FDS_G(OP_T, OP_C)
@@ -239,14 +269,24 @@ static void gemm_any(Ctx& c, int opa, int opb, int m, int n, int k, typename Elt
 
 void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const double2* A, int64_t lda,
            const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc) {
-    gemm_any<true>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    gemm_any<double2>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const float2* A, int64_t lda,
+               const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc) {
+    gemm_any<double2, float2>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void cgemm(Ctx& c, int opa, int opb, int m, int n, int k, float2 alpha, const float2* A, int64_t lda,
+           const float2* B, int64_t ldb, float2 beta, float2* C, int64_t ldc) {
+    gemm_any<float2>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 void dgemm(Ctx& c, int opa, int opb, int m, int n, int k, double alpha, const double* A, int64_t lda,
            const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
     if (opa == OP_C) opa = OP_T;
     if (opb == OP_C) opb = OP_T;
-    gemm_any<false>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    gemm_any<double>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 // ============================================================ periodic tridiagonal G

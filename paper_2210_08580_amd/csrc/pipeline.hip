@@ -32,6 +32,54 @@ static const double2 kZero = {0.0, 0.0};
 
 void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol);
 
+// Y = alpha op(M) X + beta Y for the column-major view M of a stored operator
+// (which: 0 = S, 1 = N, 2 = D; the row-major n x n matrix read column-major is
+// its transpose). X, Y: n x ncols complex128. Complex64 operators are widened on
+// load and multiplied in FP64: N is hypersingular and the filtered products
+// apply it to smooth vectors, where FP32 accumulation (or FP32 rounding of the
+// vectors) would be amplified by ||N|| / |lambda_N(low modes)| ~ 1/h.
+// Y += alpha Nband X (the complex128 band of N, half-width w; N is symmetric,
+// so op(N) = N for OP_N and OP_T)
+__global__ void nband_apply_kernel(const double2* __restrict__ nb, int w, int n, int64_t ncols, double2 alpha,
+                                   const double2* __restrict__ X, double2* __restrict__ Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * ncols) return;
+    const int i = (int)(t % n);
+    const int64_t col = t / n;
+    const double2* x = X + col * n;
+    const double2* row = nb + (int64_t)i * (2 * w + 1) + w;
+    double2 s = make_double2(0.0, 0.0);
+    for (int d = -w; d <= w; ++d) {
+        int j = i + d;
+        j = j < 0 ? j + n : (j >= n ? j - n : j);
+        s = cadd(s, cmul(row[d], x[j]));
+    }
+    Y[t] = cadd(Y[t], cmul(alpha, s));
+}
+
+static void op_gemm(Op& op, int which, int opa, int64_t ncols, double2 alpha, const double2* X, double2 beta,
+                    double2* Y) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    if (op.prec == FDS_FP32) {
+        const float2* M = which == 0 ? op.S32 : (which == 1 ? op.N32 : op.D32);
+        zgemm_a32(c, opa, OP_N, n, (int)ncols, n, alpha, M, n, X, n, beta, Y, n);
+        if (which == 1) {
+            FDS_REQUIRE(opa != OP_C, FDS_ERR_ARG, "conjugated product with N");
+            const int64_t tot = (int64_t)n * ncols;
+            {
+                KScope _ks(c, "nband_apply");
+                hipLaunchKernelGGL(nband_apply_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream,
+                                   op.Nband, op.nbw, n, ncols, alpha, X, Y);
+            }
+            FDS_HIP_TRY(hipGetLastError());
+        }
+        return;
+    }
+    const double2* M = which == 0 ? op.S : (which == 1 ? op.Nm : op.D);
+    zgemm(c, opa, OP_N, n, (int)ncols, n, alpha, M, n, X, n, beta, Y, n);
+}
+
 // per-column sqrt(x^H G x)
 __global__ void gnorm_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
                              const double2* __restrict__ X, int64_t ncols, double* __restrict__ out) {
@@ -168,16 +216,16 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
     if (form == FDS_EFIE || form == FDS_CFIE) {
         // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
         double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
-        zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.S, n, op.Vgc, n, kZero, X, n);
+        op_gemm(op, 0, OP_N, ne, kOne, op.Vgc, kZero, X);
         gram_inv(op, X, ne, X);
-        zgemm(c, OP_N, OP_N, n, ne, n, kOne, op.Nm, n, X, n, kZero, op.Bt, n);
+        op_gemm(op, 1, OP_N, ne, kOne, X, kZero, op.Bt);
         gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X, n);
         axpby(c, kOne, X, kOne, op.Bt, (int64_t)n * ne);
         c.dfree(X);
         if (form == FDS_CFIE)   // + alpha * (-D^T Vg)
-            zgemm(c, OP_N, OP_N, n, ne, n, make_double2(-alpha, 0.0), op.D, n, op.Vgc, n, kOne, op.Bt, n);
+            op_gemm(op, 2, OP_N, ne, make_double2(-alpha, 0.0), op.Vgc, kOne, op.Bt);
     } else {
-        zgemm(c, OP_N, OP_N, n, ne, n, make_double2(-1.0, 0.0), op.D, n, op.Vgc, n, kZero, op.Bt, n);
+        op_gemm(op, 2, OP_N, ne, make_double2(-1.0, 0.0), op.Vgc, kZero, op.Bt);
     }
     op.stage = Stage::Filtered;
     op.rank = 0;
@@ -371,7 +419,7 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
         FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
         gram_inv(op, f, nrhs, res);
         // S = (S stored row-major)^T as a column-major array
-        zgemm(c, OP_T, OP_N, n, (int)nrhs, n, make_double2(-1.0, 0.0), op.S, n, res, n, kZero, w, n);
+        op_gemm(op, 0, OP_T, nrhs, make_double2(-1.0, 0.0), res, kZero, w);
         gram_inv(op, w, nrhs, w);
     }
     if (op.form == FDS_MFIE || op.form == FDS_CFIE) {

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "curve_nodes", "circle", "star", "ellipse", "perturbed_circle",
-    "random_polar", "planewaves", "workload",
+    "random_polar", "random_coeffs", "random_curve", "planewaves", "workload",
 ]
 
 
@@ -81,9 +81,14 @@ def random_coeffs(seed: int, modes: int = 16, scale: float = 0.1,
             return c
 
 
+def random_curve(n: int, seed: int = 1000) -> np.ndarray:
+    """A smooth random curve: random_polar with random_coeffs(seed)."""
+    return random_polar(n, random_coeffs(seed))
+
+
 def curve_nodes(kind: str, n: int, **kw) -> np.ndarray:
     fn = {"circle": circle, "star": star, "ellipse": ellipse,
-          "perturbed_circle": perturbed_circle}[kind]
+          "perturbed_circle": perturbed_circle, "random": random_curve}[kind]
     return np.ascontiguousarray(fn(n, **kw), dtype=np.float64)
 
 
