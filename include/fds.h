@@ -96,6 +96,13 @@ typedef struct fds_solve_opts {
     int32_t max_iters;     /* refinement sweeps after the Woodbury solve          */
     int32_t precision;     /* FDS_FP64                                           */
     double tol;            /* stop when max_r ||v_r - A y_r|| / ||v_r|| <= tol    */
+    int32_t unfiltered;    /* 0: refine against the filtered operator beta I + P C
+                              (the paper's filtered solution); 1: against the
+                              unfiltered beta I + C, so that the iteration
+                              converges to the Galerkin solution of N j = -f
+                              (EFIE), (G/2 - D) j = -h (MFIE); the filtered
+                              Woodbury solve is then the preconditioner        */
+    int32_t reserved;
 } fds_solve_opts;
 
 typedef struct fds_solve_stats {
@@ -297,6 +304,36 @@ fds_status fds_rhs_planewave(fds_op op, const double* angles, const void* amps,
 fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs,
                      void* j_out, void* y_out, const fds_solve_opts* opts,
                      fds_solve_stats* stats);
+
+/* --------------------------------------------------------- inverse problem */
+
+/* Far fields of currents j (device [nrhs][n] complex128) at angles thetas
+ * (device [nang] doubles): out (device [nrhs][nang] complex128),
+ *   u_inf(theta) = e^{i pi/4}/sqrt(8 pi k) int (-i k th.n_y) e^{-i k th.y} u(y) ds_y,
+ * u = -sum_i j_i phi_i (the total field on the sound-hard boundary, sign of the
+ * paper's TE-MFIE), th = (cos theta, sin theta), 8-point Gauss rule per panel.
+ * The paper names inverse problems as a use case (Introduction) but fixes no
+ * far-field formula; this is the standard 2D one (convention u_s ~ u_inf
+ * e^{ikr}/sqrt(r)). */
+fds_status fds_farfield(fds_op op, const void* j, int64_t nrhs, const double* thetas, int64_t nang, void* out);
+
+/* Objective J = sum_r sum_l |u_inf,r(theta_l) - T_lr|^2 of the unfiltered
+ * Galerkin TE-EFIE N j_r = -f_r with plane waves (angles [nrhs] doubles, amps
+ * [nrhs] complex128, both device), and its gradient by the adjoint method:
+ * one forward and one adjoint solve (the filtered Woodbury solve as the
+ * preconditioner, refinement against the unfiltered operator with opts:
+ * max_iters, tol), one GEMM M = mu J^T and one pass over all panel pairs that
+ * recomputes the kernel (far pairs analytically, self/adjacent pairs by central
+ * differences of their singular quadrature).
+ * Requires a factored EFIE operator. target: device [nrhs][nang] complex128.
+ * J: host double. grad_nodes: device [n][2] doubles, dJ/d(node coordinates).
+ * grad_amps: device [nrhs] complex128, dJ/dRe A_r + i dJ/dIm A_r.
+ * farfield_out: device [nrhs][nang] complex128 or NULL. stats: host, forward
+ * solve, may be NULL. Synchronises. */
+fds_status fds_farfield_objective_grad(fds_op op, const double* angles, const void* amps, int64_t nrhs,
+                                       const double* thetas, int64_t nang, const void* target,
+                                       const fds_solve_opts* opts, double* J, double* grad_nodes,
+                                       void* grad_amps, void* farfield_out, fds_solve_stats* stats);
 
 #ifdef __cplusplus
 }

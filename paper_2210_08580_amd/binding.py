@@ -58,7 +58,8 @@ class fds_compress_opts(C.Structure):
 
 
 class fds_solve_opts(C.Structure):
-    _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double)]
+    _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
+                ("unfiltered", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fds_solve_stats(C.Structure):
@@ -81,6 +82,11 @@ _SIGS = {
                             C.POINTER(C.c_float), C.c_void_p, C.c_int64]),
     "fds_op_precision": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fds_op_nband": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "fds_farfield": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_farfield_objective_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                              C.c_int64, C.c_void_p, C.POINTER(fds_solve_opts),
+                                              C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.POINTER(fds_solve_stats)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
@@ -445,15 +451,48 @@ def fds_rhs_planewave(op: Op, angles: torch.Tensor, amps: torch.Tensor):
 
 
 def fds_solve(op: Op, f: torch.Tensor | None, h: torch.Tensor | None, max_iters: int = 4,
-              tol: float = 1e-12, want_y: bool = False, stats: bool = True):
+              tol: float = 1e-12, want_y: bool = False, stats: bool = True, unfiltered: bool = False):
     ref = f if f is not None else h
     nrhs = ref.shape[0]
     j = torch.empty((nrhs, op.n), dtype=torch.complex128, device="cuda")
     y = torch.empty_like(j) if want_y else None
-    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol))
+    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol), int(bool(unfiltered)), 0)
     st = fds_solve_stats()
     _check(lib().fds_solve(op.handle, _ptr(f), _ptr(h), nrhs, _ptr(j), _ptr(y), C.byref(o),
                            C.byref(st) if stats else None))
     hist = list(st.history[: st.iters + 1]) if stats else []
     return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
                   "history": hist}
+
+
+# ----------------------------------------------------------------- inverse problem
+def fds_farfield(op: Op, j: torch.Tensor, thetas: torch.Tensor) -> torch.Tensor:
+    """Far fields (nrhs, nang) of currents j (nrhs, n)."""
+    j = j.to(device="cuda", dtype=torch.complex128).contiguous()
+    thetas = thetas.to(device="cuda", dtype=torch.float64).contiguous()
+    out = torch.empty((j.shape[0], thetas.numel()), dtype=torch.complex128, device="cuda")
+    _check(lib().fds_farfield(op.handle, _ptr(j), j.shape[0], _ptr(thetas), thetas.numel(), _ptr(out)))
+    return out
+
+
+def fds_farfield_objective_grad(op: Op, angles: torch.Tensor, amps: torch.Tensor, thetas: torch.Tensor,
+                                target: torch.Tensor, max_iters: int = 8, tol: float = 1e-12):
+    """(J, dJ/dnodes (n, 2), dJ/dRe A + i dJ/dIm A (nrhs,), far fields (nrhs, nang), stats)."""
+    angles = angles.to(device="cuda", dtype=torch.float64).contiguous()
+    amps = amps.to(device="cuda", dtype=torch.complex128).contiguous()
+    thetas = thetas.to(device="cuda", dtype=torch.float64).contiguous()
+    target = target.to(device="cuda", dtype=torch.complex128).contiguous()
+    nrhs, nang = angles.numel(), thetas.numel()
+    assert target.shape == (nrhs, nang)
+    gn = torch.empty((op.n, 2), dtype=torch.float64, device="cuda")
+    ga = torch.empty((nrhs,), dtype=torch.complex128, device="cuda")
+    ff = torch.empty((nrhs, nang), dtype=torch.complex128, device="cuda")
+    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol), 1, 0)
+    st = fds_solve_stats()
+    J = C.c_double()
+    _check(lib().fds_farfield_objective_grad(op.handle, _ptr(angles), _ptr(amps), nrhs, _ptr(thetas), nang,
+                                             _ptr(target), C.byref(o), C.byref(J), _ptr(gn), _ptr(ga),
+                                             _ptr(ff), C.byref(st)))
+    stats = {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres}
+    return J.value, gn, ga, ff, stats
+

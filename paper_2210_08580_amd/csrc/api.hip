@@ -482,15 +482,49 @@ fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs, void
         require_stage(op->impl, Stage::Factored, "fds_solve");
         int it = 4;
         double tol = 1e-12;
+        bool unf = false;
+        if (opts) {
+            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 solves are implemented");
+            it = opts->max_iters;
+            tol = opts->tol;
+            unf = opts->unfiltered != 0;
+        }
+        FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
+        if (nrhs == 0) return;
+        run_solve(op->impl, (const double2*)f, (const double2*)h, nrhs, (double2*)j_out,
+                  (double2*)y_out, it, tol, stats, unf);
+    });
+}
+
+fds_status fds_farfield(fds_op op, const void* j, int64_t nrhs, const double* thetas, int64_t nang, void* out) {
+    return guarded([&] {
+        FDS_REQUIRE(op && j && thetas && out && nrhs >= 0 && nang >= 0 && nang < (1 << 24), FDS_ERR_ARG,
+                    "bad argument");
+        if (nrhs == 0 || nang == 0) return;
+        run_farfield(op->impl, (const double2*)j, nrhs, thetas, (int)nang, (double2*)out);
+    });
+}
+
+fds_status fds_farfield_objective_grad(fds_op op, const double* angles, const void* amps, int64_t nrhs,
+                                       const double* thetas, int64_t nang, const void* target,
+                                       const fds_solve_opts* opts, double* J, double* grad_nodes,
+                                       void* grad_amps, void* farfield_out, fds_solve_stats* stats) {
+    return guarded([&] {
+        FDS_REQUIRE(op && angles && amps && thetas && target && J && grad_nodes && grad_amps, FDS_ERR_ARG,
+                    "NULL argument");
+        FDS_REQUIRE(nrhs >= 1 && nang >= 1 && nang < (1 << 24) && nrhs < (1 << 24), FDS_ERR_ARG, "bad sizes");
+        require_stage(op->impl, Stage::Factored, "fds_farfield_objective_grad");
+        FDS_REQUIRE(op->impl.form == FDS_EFIE, FDS_ERR_NOTIMPL, "the adjoint gradient uses the EFIE model");
+        int it = 8;
+        double tol = 1e-12;
         if (opts) {
             FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 solves are implemented");
             it = opts->max_iters;
             tol = opts->tol;
         }
         FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
-        if (nrhs == 0) return;
-        run_solve(op->impl, (const double2*)f, (const double2*)h, nrhs, (double2*)j_out,
-                  (double2*)y_out, it, tol, stats);
+        run_farfield_grad(op->impl, angles, (const double2*)amps, nrhs, thetas, (int)nang, (const double2*)target,
+                          it, tol, J, grad_nodes, (double2*)grad_amps, (double2*)farfield_out, stats);
     });
 }
 

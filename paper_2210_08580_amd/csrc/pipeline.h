@@ -11,6 +11,12 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
 void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed);
 void run_factor(Op& op);
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
-               int max_iters, double tol, fds_solve_stats* stats);
+               int max_iters, double tol, fds_solve_stats* stats, bool unfiltered = false);
+void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y);
+// adjoint.hip
+void run_farfield(Op& op, const double2* J, int64_t nrhs, const double* thetas, int nang, double2* out);
+void run_farfield_grad(Op& op, const double* angles, const double2* amps, int64_t nrhs, const double* thetas,
+                       int nang, const double2* T, int max_iters, double tol, double* Jout, double* grad,
+                       double2* gamp, double2* ff_out, fds_solve_stats* stats);
 
 }  // namespace fds

@@ -406,8 +406,34 @@ static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
     }
 }
 
+// r = w - (beta I + C_j) j with the unfiltered compact part in j coordinates,
+// C_j = G^{-1} S G^{-1} N - I/4 (EFIE), -G^{-1} D (MFIE), EFIE + alpha MFIE (CFIE).
+static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int64_t nrhs, double2* res,
+                                double2* t1, double2* t2) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const int64_t tot = (int64_t)n * nrhs;
+    const size_t blk = sizeof(double2) * (size_t)tot;
+    FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
+    axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, tot);
+    if (op.form == FDS_EFIE || op.form == FDS_CFIE) {
+        op_gemm(op, 1, OP_T, nrhs, kOne, jv, kZero, t1);          // N j
+        gram_inv(op, t1, nrhs, t1);
+        op_gemm(op, 0, OP_T, nrhs, kOne, t1, kZero, t2);          // S G^-1 N j
+        gram_inv(op, t2, nrhs, t2);
+        axpby(c, make_double2(-1.0, 0.0), t2, kOne, res, tot);
+        axpby(c, make_double2(0.25, 0.0), jv, kOne, res, tot);
+    }
+    if (op.form == FDS_MFIE || op.form == FDS_CFIE) {
+        const double a = op.form == FDS_MFIE ? 1.0 : op.alpha;
+        op_gemm(op, 2, OP_T, nrhs, kOne, jv, kZero, t1);          // D j
+        gram_inv(op, t1, nrhs, t1);
+        axpby(c, make_double2(a, 0.0), t1, kOne, res, tot);
+    }
+}
+
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
-               int max_iters, double tol, fds_solve_stats* stats) {
+               int max_iters, double tol, fds_solve_stats* stats, bool unfiltered) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n, ne = op.n_eff;
     const size_t blk = sizeof(double2) * (size_t)n * nrhs;
@@ -442,13 +468,23 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
         std::fill(stats->history, stats->history + 32, 0.0);
         gnorms(op, w, nrhs, nrm + nrhs);
     }
+    double2* t1 = nullptr;
+    double2* t2 = nullptr;
+    if (unfiltered) {
+        t1 = static_cast<double2*>(c.dmalloc(blk));
+        t2 = static_cast<double2*>(c.dmalloc(blk));
+    }
     for (int it = 0;; ++it) {
         if (!stats && it >= max_iters) break;
-        // res = w - beta j - V_g (Bt^T j)
-        FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
-        axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, (int64_t)n * nrhs);
-        zgemm(c, OP_T, OP_N, ne, (int)nrhs, n, kOne, op.Bt, n, jv, n, kZero, z, ne);
-        zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+        if (unfiltered) {
+            unfiltered_residual(op, w, jv, nrhs, res, t1, t2);
+        } else {
+            // res = w - beta j - V_g (Bt^T j)
+            FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
+            axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, (int64_t)n * nrhs);
+            zgemm(c, OP_T, OP_N, ne, (int)nrhs, n, kOne, op.Bt, n, jv, n, kZero, z, ne);
+            zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+        }
         if (stats) {
             gnorms(op, res, nrhs, nrm);
             FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.stream));
@@ -477,6 +513,8 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
     c.dfree(w);
     c.dfree(res);
     c.dfree(z);
+    c.dfree(t1);
+    c.dfree(t2);
     if (stats) {
         stats->iters = iters;
         stats->converged = conv ? 1 : 0;
