@@ -135,6 +135,16 @@ fds_status fds_profile_enable(fds_ctx ctx, int32_t on);
 fds_status fds_profile_read(fds_ctx ctx, int32_t cap, char* names, double* total_ms,
                             int64_t* launches, int32_t* count);
 
+/* GEMM autotuning (off by default). When on, the first GEMM of each shape
+ * class (operand types, ops, m, n, k rounded up to powers of two) times the
+ * split-K candidates 1, 2, 4, ... (the K extent per workgroup) on a scratch
+ * output, synchronising, and caches the fastest in the context; later GEMMs of
+ * the class reuse it. Nothing is tuned while the stream is being captured. */
+fds_status fds_autotune(fds_ctx ctx, int32_t on);
+/* Copies the cache: keys (host, cap x 160 chars, may be NULL), split_k (host,
+ * cap ints, may be NULL); *count receives the number of entries. */
+fds_status fds_autotune_read(fds_ctx ctx, int32_t cap, char* keys, int32_t* split_k, int32_t* count);
+
 /* ------------------------------------------------------- special functions */
 
 /* Bessel functions of the Hankel kernel (paper, Notation and Background:
@@ -189,6 +199,15 @@ fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
                         const fds_asm_opts* opts, fds_op* out);
 fds_status fds_op_destroy(fds_op op);
 
+/* Batched assembly of `count` FP64 operators of uneven sizes (nodes[j]: device
+ * [n[j]][2], k[j]; host arrays of pointers / sizes / wave numbers): the far
+ * panel pairs of all operators are processed by one persistent launch whose
+ * wavefronts draw 63 x 63 half-tiles from a shared work queue; the near pairs
+ * and band corrections follow per operator. Same results as fds_assemble on
+ * each operator. out: host array of `count` handles; on error none is created. */
+fds_status fds_assemble_batch(fds_ctx ctx, int32_t count, const double* const* nodes, const int64_t* n,
+                              const double* k, fds_op* out);
+
 /* Sizes: n, kept filter modes (0 before fds_filter), skeleton rank (0 before
  * fds_compress). Any output pointer may be NULL. Host call, no sync. */
 fds_status fds_op_info(fds_op op, int64_t* n, int32_t* n_eff, int32_t* rank);
@@ -229,6 +248,13 @@ fds_status fds_apply_gram(fds_op op, int32_t p, void* X, int64_t ncols);
  * cluster guard. Errors: FDS_ERR_ARG for n_modes outside [1, n]. */
 fds_status fds_filter(fds_op op, fds_form form, double alpha,
                       const fds_filter_opts* opts, int32_t* n_eff);
+
+/* fds_filter on `count` FP64 operators of one context (uneven sizes): the
+ * eigensolver runs per operator and every dense product stage of all operators
+ * is one grouped GEMM launch. opts: host array of `count` (one keep_nullspace
+ * and cluster_rtol per batch, taken from opts[0]); n_eff: host [count] or NULL. */
+fds_status fds_filter_batch(int32_t count, fds_op* ops, fds_form form, double alpha,
+                            const fds_filter_opts* opts, int32_t* n_eff);
 
 /* Borrowed device view of V_n: n_eff orthonormal real vectors of length n. */
 fds_status fds_op_filter_basis(fds_op op, const double** Vn);

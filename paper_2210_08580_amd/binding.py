@@ -75,6 +75,9 @@ _SIGS = {
     "fds_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "fds_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "fds_autotune": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fds_autotune_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
     "fds_hankel_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_hankel_eval_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_cgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
@@ -94,6 +97,8 @@ _SIGS = {
     "fds_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
                                C.POINTER(fds_asm_opts), C.POINTER(C.c_void_p)]),
     "fds_op_destroy": (C.c_int, [C.c_void_p]),
+    "fds_assemble_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_void_p)]),
     "fds_op_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32)]),
     "fds_op_matrices": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -102,6 +107,8 @@ _SIGS = {
     "fds_apply_gram": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "fds_filter": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.POINTER(fds_filter_opts),
                              C.POINTER(C.c_int32)]),
+    "fds_filter_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.c_int, C.c_double,
+                                   C.POINTER(fds_filter_opts), C.POINTER(C.c_int32)]),
     "fds_op_filter_basis": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "fds_op_filter_eigenvalues": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                             C.POINTER(C.c_int32)]),
@@ -255,6 +262,19 @@ def fds_profile_read(ctx: Ctx, cap: int = 128) -> dict:
     return out
 
 
+def fds_autotune(ctx: Ctx, on: bool = True):
+    _check(lib().fds_autotune(ctx.handle, int(bool(on))))
+
+
+def fds_autotune_read(ctx: Ctx, cap: int = 256) -> dict:
+    keys = C.create_string_buffer(160 * cap)
+    vals = (C.c_int32 * cap)()
+    cnt = C.c_int32()
+    _check(lib().fds_autotune_read(ctx.handle, cap, keys, vals, C.byref(cnt)))
+    raw = keys.raw
+    return {raw[160 * i:160 * (i + 1)].split(b"\0")[0].decode(): vals[i] for i in range(min(cnt.value, cap))}
+
+
 def fds_hankel_eval(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:
     out = torch.empty((x.numel(), 4), dtype=torch.float64, device=x.device)
     _check(lib().fds_hankel_eval(ctx.handle, _ptr(x), x.numel(), _ptr(out)))
@@ -352,6 +372,18 @@ def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | N
     return Op(ctx, h)
 
 
+def fds_assemble_batch(ctx: Ctx, nodes_list, ks) -> list:
+    """Assemble several FP64 operators with one persistent far-field launch."""
+    nodes_list = [x.to(device="cuda", dtype=torch.float64).contiguous() for x in nodes_list]
+    cnt = len(nodes_list)
+    ptrs = (C.c_void_p * cnt)(*[_ptr(x) for x in nodes_list])
+    ns = (C.c_int64 * cnt)(*[x.shape[0] for x in nodes_list])
+    kk = (C.c_double * cnt)(*[float(v) for v in ks])
+    hs = (C.c_void_p * cnt)()
+    _check(lib().fds_assemble_batch(ctx.handle, cnt, ptrs, ns, kk, hs))
+    return [Op(ctx, C.c_void_p(h)) for h in hs]
+
+
 def fds_op_matrices(op: Op):
     s, n_, d = C.c_void_p(), C.c_void_p(), C.c_void_p()
     _check(lib().fds_op_matrices(op.handle, C.byref(s), C.byref(n_), C.byref(d)))
@@ -395,6 +427,19 @@ def fds_filter(op: Op, form: str = "efie", alpha: float = 1.0, n_modes: int = 21
     ne = C.c_int32()
     _check(lib().fds_filter(op.handle, FORMS[form], float(alpha), C.byref(o), C.byref(ne)))
     return ne.value
+
+
+def fds_filter_batch(ops: list, form: str = "efie", alpha: float = 1.0, n_modes=21,
+                     keep_nullspace: bool = True, cluster_rtol: float = 1e-6) -> list:
+    """fds_filter on several operators (grouped GEMMs); returns the kept mode counts."""
+    cnt = len(ops)
+    nms = list(n_modes) if hasattr(n_modes, "__len__") else [n_modes] * cnt
+    opts = (fds_filter_opts * cnt)(*[fds_filter_opts(int(m), int(bool(keep_nullspace)), float(cluster_rtol))
+                                     for m in nms])
+    hs = (C.c_void_p * cnt)(*[o.handle.value if isinstance(o.handle, C.c_void_p) else o.handle for o in ops])
+    ne = (C.c_int32 * cnt)()
+    _check(lib().fds_filter_batch(cnt, hs, FORMS[form], float(alpha), opts, ne))
+    return list(ne)
 
 
 def fds_op_filter_basis(op: Op) -> torch.Tensor:

@@ -186,6 +186,20 @@ fds_status fds_profile_read(fds_ctx ctx, int32_t cap, char* names, double* total
     });
 }
 
+fds_status fds_autotune(fds_ctx ctx, int32_t on) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx != nullptr, FDS_ERR_ARG, "ctx is NULL");
+        ctx->impl.autotune = on != 0;
+    });
+}
+
+fds_status fds_autotune_read(fds_ctx ctx, int32_t cap, char* keys, int32_t* split_k, int32_t* count) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && count && cap >= 0, FDS_ERR_ARG, "bad argument");
+        *count = autotune_entries(ctx->impl, cap, keys, split_k);
+    });
+}
+
 fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out) {
     return guarded([&] {
         FDS_REQUIRE(ctx && x && out && n >= 0, FDS_ERR_ARG, "bad argument");
@@ -247,77 +261,108 @@ fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
     });
 }
 
+// Validates the geometry, allocates the operator and builds its panels, Gram
+// and Laplacian matrices; the dense assembly is left to the caller.
+static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, const fds_asm_opts* opts) {
+    FDS_REQUIRE(nodes != nullptr, FDS_ERR_ARG, "NULL nodes");
+    FDS_REQUIRE(n >= 8 && n <= (int64_t)1 << 20, FDS_ERR_ARG, "n must be in [8, 2^20]");
+    FDS_REQUIRE(std::isfinite(k) && k > 0.0, FDS_ERR_ARG, "k must be finite and > 0");
+    if (opts) {
+        FDS_REQUIRE(opts->nquad == 0 || opts->nquad == 8, FDS_ERR_NOTIMPL,
+                    "only the 8-point rule is implemented");
+        FDS_REQUIRE(opts->precision == FDS_FP64 || opts->precision == FDS_FP32, FDS_ERR_NOTIMPL,
+                    "assembly precision must be FDS_FP64 or FDS_FP32");
+    }
+    // host-side geometry validation (O(n) copy)
+    std::vector<double> hn(2 * n);
+    FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    double area = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = (i + 1) % n;
+        const double x0 = hn[2 * i], y0 = hn[2 * i + 1], x1 = hn[2 * j], y1 = hn[2 * j + 1];
+        FDS_REQUIRE(std::isfinite(x0) && std::isfinite(y0), FDS_ERR_ARG, "non-finite node");
+        FDS_REQUIRE(std::hypot(x1 - x0, y1 - y0) > 0.0, FDS_ERR_ARG, "zero-length panel");
+        area += x0 * y1 - x1 * y0;
+    }
+    FDS_REQUIRE(area > 0.0, FDS_ERR_ARG, "nodes must be counter-clockwise");
+
+    auto* o = new fds_op_s();
+    Op& op = o->impl;
+    op.ctx = &c;
+    op.n = n;
+    op.k = k;
+    op.prec = opts ? opts->precision : FDS_FP64;
+    try {
+        const size_t nd = sizeof(double) * n;
+        op.nodes = (double*)c.dmalloc(2 * nd);
+        op.h = (double*)c.dmalloc(nd);
+        op.nx = (double*)c.dmalloc(nd);
+        op.ny = (double*)c.dmalloc(nd);
+        op.gx = (double*)c.dmalloc(8 * nd);
+        op.gy = (double*)c.dmalloc(8 * nd);
+        op.g_diag = (double*)c.dmalloc(nd);
+        op.g_off = (double*)c.dmalloc(nd);
+        op.l_diag = (double*)c.dmalloc(nd);
+        op.l_off = (double*)c.dmalloc(nd);
+        if (op.prec == FDS_FP32) {
+            const size_t mat = sizeof(float2) * (size_t)n * (size_t)n;
+            op.S32 = (float2*)c.dmalloc(mat);
+            op.N32 = (float2*)c.dmalloc(mat);
+            op.D32 = (float2*)c.dmalloc(mat);
+            // cyclic band |d| <= nbw, with 2 nbw + 1 <= n so that the taps are distinct
+            op.nbw = (int)std::min<int64_t>(63, (n - 1) / 2);
+            op.Nband = (double2*)c.dmalloc(sizeof(double2) * (2 * op.nbw + 1) * (size_t)n);
+        } else {
+            const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
+            op.S = (double2*)c.dmalloc(mat);
+            op.Nm = (double2*)c.dmalloc(mat);
+            op.D = (double2*)c.dmalloc(mat);
+        }
+        FDS_HIP_TRY(hipMemcpyAsync(op.nodes, nodes, 2 * nd, hipMemcpyDeviceToDevice, c.stream));
+        gauss_legendre_01(8, op.rule.xi, op.rule.w);
+        launch_geometry(op);
+    } catch (...) {
+        delete o;
+        throw;
+    }
+    return o;
+}
+
 fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
                         const fds_asm_opts* opts, fds_op* out) {
     return guarded([&] {
         FDS_REQUIRE(ctx && nodes && out, FDS_ERR_ARG, "NULL argument");
         *out = nullptr;
-        FDS_REQUIRE(n >= 8 && n <= (int64_t)1 << 20, FDS_ERR_ARG, "n must be in [8, 2^20]");
-        FDS_REQUIRE(std::isfinite(k) && k > 0.0, FDS_ERR_ARG, "k must be finite and > 0");
-        if (opts) {
-            FDS_REQUIRE(opts->nquad == 0 || opts->nquad == 8, FDS_ERR_NOTIMPL,
-                        "only the 8-point rule is implemented");
-            FDS_REQUIRE(opts->precision == FDS_FP64 || opts->precision == FDS_FP32, FDS_ERR_NOTIMPL,
-                        "assembly precision must be FDS_FP64 or FDS_FP32");
-        }
-        Ctx& c = ctx->impl;
-        // host-side geometry validation (O(n) copy)
-        std::vector<double> hn(2 * n);
-        FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
-                                   c.stream));
-        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-        double area = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            const int64_t j = (i + 1) % n;
-            const double x0 = hn[2 * i], y0 = hn[2 * i + 1], x1 = hn[2 * j], y1 = hn[2 * j + 1];
-            FDS_REQUIRE(std::isfinite(x0) && std::isfinite(y0), FDS_ERR_ARG, "non-finite node");
-            FDS_REQUIRE(std::hypot(x1 - x0, y1 - y0) > 0.0, FDS_ERR_ARG, "zero-length panel");
-            area += x0 * y1 - x1 * y0;
-        }
-        FDS_REQUIRE(area > 0.0, FDS_ERR_ARG, "nodes must be counter-clockwise");
-
-        auto* o = new fds_op_s();
-        Op& op = o->impl;
-        op.ctx = &c;
-        op.n = n;
-        op.k = k;
-        op.prec = opts ? opts->precision : FDS_FP64;
+        fds_op_s* o = new_operator(ctx->impl, nodes, n, k, opts);
         try {
-            const size_t nd = sizeof(double) * n;
-            op.nodes = (double*)c.dmalloc(2 * nd);
-            op.h = (double*)c.dmalloc(nd);
-            op.nx = (double*)c.dmalloc(nd);
-            op.ny = (double*)c.dmalloc(nd);
-            op.gx = (double*)c.dmalloc(8 * nd);
-            op.gy = (double*)c.dmalloc(8 * nd);
-            op.g_diag = (double*)c.dmalloc(nd);
-            op.g_off = (double*)c.dmalloc(nd);
-            op.l_diag = (double*)c.dmalloc(nd);
-            op.l_off = (double*)c.dmalloc(nd);
-            if (op.prec == FDS_FP32) {
-                const size_t mat = sizeof(float2) * (size_t)n * (size_t)n;
-                op.S32 = (float2*)c.dmalloc(mat);
-                op.N32 = (float2*)c.dmalloc(mat);
-                op.D32 = (float2*)c.dmalloc(mat);
-                // cyclic band |d| <= nbw, with 2 nbw + 1 <= n so that the taps are distinct
-                op.nbw = (int)std::min<int64_t>(63, (n - 1) / 2);
-                op.Nband = (double2*)c.dmalloc(sizeof(double2) * (2 * op.nbw + 1) * (size_t)n);
-            } else {
-                const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
-                op.S = (double2*)c.dmalloc(mat);
-                op.Nm = (double2*)c.dmalloc(mat);
-                op.D = (double2*)c.dmalloc(mat);
-            }
-            FDS_HIP_TRY(hipMemcpyAsync(op.nodes, nodes, 2 * nd, hipMemcpyDeviceToDevice, c.stream));
-            gauss_legendre_01(8, op.rule.xi, op.rule.w);
-            launch_geometry(op);
-            launch_assemble(op);
-            op.stage = Stage::Assembled;
+            launch_assemble(o->impl);
+            o->impl.stage = Stage::Assembled;
         } catch (...) {
             delete o;
             throw;
         }
         *out = o;
+    });
+}
+
+fds_status fds_assemble_batch(fds_ctx ctx, int32_t count, const double* const* nodes, const int64_t* n,
+                              const double* k, fds_op* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && nodes && n && k && out && count >= 1, FDS_ERR_ARG, "bad argument");
+        for (int32_t j = 0; j < count; ++j) out[j] = nullptr;
+        std::vector<fds_op_s*> made;
+        try {
+            for (int32_t j = 0; j < count; ++j) made.push_back(new_operator(ctx->impl, nodes[j], n[j], k[j], nullptr));
+            std::vector<Op*> ops;
+            for (auto* o : made) ops.push_back(&o->impl);
+            launch_assemble_batch(ctx->impl, ops.data(), count);
+            for (auto* o : made) o->impl.stage = Stage::Assembled;
+        } catch (...) {
+            for (auto* o : made) delete o;
+            throw;
+        }
+        for (int32_t j = 0; j < count; ++j) out[j] = made[j];
     });
 }
 
@@ -414,6 +459,36 @@ fds_status fds_filter(fds_op op, fds_form form, double alpha, const fds_filter_o
             FDS_REQUIRE(std::fabs(1.0 + 2.0 * alpha) > 1e-12, FDS_ERR_ARG, "CFIE with beta = 0");
         run_filter(op->impl, form, alpha, nm, keep, crt);
         if (n_eff) *n_eff = op->impl.n_eff;
+    });
+}
+
+fds_status fds_filter_batch(int32_t count, fds_op* ops, fds_form form, double alpha,
+                            const fds_filter_opts* opts, int32_t* n_eff) {
+    return guarded([&] {
+        FDS_REQUIRE(ops && opts && count >= 1, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE, FDS_ERR_ARG, "bad form");
+        FDS_REQUIRE(std::isfinite(alpha), FDS_ERR_ARG, "alpha must be finite");
+        if (form == FDS_CFIE)
+            FDS_REQUIRE(std::fabs(1.0 + 2.0 * alpha) > 1e-12, FDS_ERR_ARG, "CFIE with beta = 0");
+        std::vector<Op*> v(count);
+        std::vector<int> nm(count);
+        for (int32_t j = 0; j < count; ++j) {
+            FDS_REQUIRE(ops[j] != nullptr, FDS_ERR_ARG, "NULL operator");
+            FDS_REQUIRE(ops[j]->impl.ctx == ops[0]->impl.ctx, FDS_ERR_ARG, "operators of different contexts");
+            require_stage(ops[j]->impl, Stage::Assembled, "fds_filter_batch");
+            v[j] = &ops[j]->impl;
+            nm[j] = opts[j].n_modes;
+            FDS_REQUIRE(nm[j] >= 1 && nm[j] <= v[j]->n, FDS_ERR_ARG, "n_modes must be in [1, n]");
+            FDS_REQUIRE(opts[j].keep_nullspace == opts[0].keep_nullspace, FDS_ERR_ARG,
+                        "one null-space choice per batch");
+        }
+        const bool keep = opts[0].keep_nullspace != 0;
+        FDS_REQUIRE(keep || *std::min_element(nm.begin(), nm.end()) >= 2, FDS_ERR_ARG,
+                    "n_modes must be >= 2 without the null mode");
+        const double crt = opts[0].cluster_rtol > 0.0 ? opts[0].cluster_rtol : 1e-6;
+        run_filter_batch(v.data(), count, form, alpha, nm.data(), keep, crt);
+        if (n_eff)
+            for (int32_t j = 0; j < count; ++j) n_eff[j] = v[j]->n_eff;
     });
 }
 

@@ -29,7 +29,9 @@
 //   form on a self pair, Duffy's corner split on adjacent pairs), smooth
 //   remainders with the same 8 x 8 rule; the S and N bands |i - j| <= 2 are
 //   then symmetrised.
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "fds_internal.h"
 #include "hankel.h"
@@ -117,31 +119,39 @@ __device__ __forceinline__ void far_kernel_values(double k, double R, const void
     c = make_float2(-kr * bs.y1, kr * bs.j1);
 }
 
+// LDS copies shared by the workgroup: the Bessel table and the quadrature rules.
 template <bool F32>
-__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
+struct FarShared {
+    __attribute__((aligned(16))) char tab[FarT<F32>::TAB_BYTES];
+    double wsh[16];            // w_b psi_0(xi_b), w_b psi_1(xi_b)
+    double rl4[12], rl3[9];    // reduced rules: xi, w psi_0, w psi_1
+};
+
+template <bool F32>
+__device__ __forceinline__ void far_shared_setup(FarShared<F32>& sh, const void* tabg, const W8& wt,
+                                                 const WLow& wl) {
+    const int4* src = static_cast<const int4*>(tabg);
+    int4* dst = reinterpret_cast<int4*>(sh.tab);
+    for (int t = threadIdx.x; t < FarT<F32>::TAB_BYTES / 16; t += blockDim.x) dst[t] = src[t];
+    if (threadIdx.x < 8) {
+        sh.wsh[threadIdx.x] = wt.wp0[threadIdx.x];
+        sh.wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
+    }
+    if (threadIdx.x < 12) sh.rl4[threadIdx.x] = wl.r4[threadIdx.x / 4][threadIdx.x % 4];
+    if (threadIdx.x < 9) sh.rl3[threadIdx.x] = wl.r3[threadIdx.x / 3][threadIdx.x % 3];
+    __syncthreads();
+}
+
+// One work item (half of a 63 x 63 tile) of one operator, executed by one wavefront.
+template <bool F32>
+__device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, FarShared<F32>& sh) {
     typedef typename FarT<F32>::R RT;
     typedef typename FarT<F32>::C CT;
-    __shared__ __attribute__((aligned(16))) char tabraw[FarT<F32>::TAB_BYTES];
-    __shared__ double wsh[16];          // w_b psi_0(xi_b), w_b psi_1(xi_b)
-    __shared__ double rl4[12], rl3[9];  // reduced rules: xi, w psi_0, w psi_1
-    {
-        const int4* src = static_cast<const int4*>(P.tab);
-        int4* dst = reinterpret_cast<int4*>(tabraw);
-        for (int t = threadIdx.x; t < FarT<F32>::TAB_BYTES / 16; t += blockDim.x) dst[t] = src[t];
-    }
-    const void* tab = tabraw;
-    if (threadIdx.x < 8) {
-        wsh[threadIdx.x] = wt.wp0[threadIdx.x];
-        wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
-    }
-    if (threadIdx.x < 12) rl4[threadIdx.x] = wl.r4[threadIdx.x / 4][threadIdx.x % 4];
-    if (threadIdx.x < 9) rl3[threadIdx.x] = wl.r3[threadIdx.x / 3][threadIdx.x % 3];
-    __syncthreads();
-
+    const void* tab = sh.tab;
+    const double* wsh = sh.wsh;
+    const double* rl4 = sh.rl4;
+    const double* rl3 = sh.rl3;
     const int lane = threadIdx.x & 63;
-    const int64_t work = (int64_t)blockIdx.x * WAVES +
-                         __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (work >= P.nwork) return;
     const int64_t tile = work / P.nsub;
     const int sub = (int)(work - tile * P.nsub);
     const int n = P.n;
@@ -356,6 +366,45 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
     }
 }
 
+template <bool F32>
+__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
+    __shared__ FarShared<F32> sh;
+    far_shared_setup<F32>(sh, P.tab, wt, wl);
+    const int64_t work = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (work >= P.nwork) return;
+    far_work_item<F32>(P, work, sh);
+}
+
+// Many operators in one launch: a persistent grid whose wavefronts take work
+// items from a global counter until the queue (all tiles of all operators,
+// prefix[j] = first item of operator j) is exhausted; every wavefront exits
+// once the counter passes the total.
+__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarParams* __restrict__ jobs,
+                                                                      const int64_t* __restrict__ prefix, int njobs,
+                                                                      unsigned long long* __restrict__ counter,
+                                                                      const double* __restrict__ tabg, W8 wt,
+                                                                      WLow wl) {
+    __shared__ FarShared<false> sh;
+    far_shared_setup<false>(sh, tabg, wt, wl);
+    const int64_t total = prefix[njobs];
+    for (;;) {
+        unsigned long long w = 0;
+        if ((threadIdx.x & 63) == 0) w = atomicAdd(counter, 1ull);
+        w = __shfl(w, 0, 64);
+        if ((int64_t)w >= total) break;
+        int lo = 0, hi = njobs - 1;   // last j with prefix[j] <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= (int64_t)w) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = __builtin_amdgcn_readfirstlane(lo);
+        far_work_item<false>(jobs[j], (int64_t)w - prefix[j], sh);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
 // ----------------------------------------------------------------- near pairs
 struct NearParams {
     const double* __restrict__ gx;
@@ -486,30 +535,29 @@ __global__ void asm_band_kernel(BandParams P) {
     st_c(D, ji, cadd(ld_c(D, ji), d2));
 }
 
-void launch_assemble(Op& op) {
-    Ctx& c = *op.ctx;
-    const int n = (int)op.n;
-    W8 wt;
+static void far_rules(const Op& op, W8& wt, WLow& wlow) {
     for (int a = 0; a < 8; ++a) {
         wt.wp0[a] = op.rule.w[a] * (1.0 - op.rule.xi[a]);
         wt.wp1[a] = op.rule.w[a] * op.rule.xi[a];
     }
-    WLow wlow;
-    {
-        double x4[4], w4[4], x3[3], w3[3];
-        gauss_legendre_01(4, x4, w4);
-        gauss_legendre_01(3, x3, w3);
-        for (int a = 0; a < 4; ++a) {
-            wlow.r4[0][a] = x4[a];
-            wlow.r4[1][a] = w4[a] * (1.0 - x4[a]);
-            wlow.r4[2][a] = w4[a] * x4[a];
-        }
-        for (int a = 0; a < 3; ++a) {
-            wlow.r3[0][a] = x3[a];
-            wlow.r3[1][a] = w3[a] * (1.0 - x3[a]);
-            wlow.r3[2][a] = w3[a] * x3[a];
-        }
+    double x4[4], w4[4], x3[3], w3[3];
+    gauss_legendre_01(4, x4, w4);
+    gauss_legendre_01(3, x3, w3);
+    for (int a = 0; a < 4; ++a) {
+        wlow.r4[0][a] = x4[a];
+        wlow.r4[1][a] = w4[a] * (1.0 - x4[a]);
+        wlow.r4[2][a] = w4[a] * x4[a];
     }
+    for (int a = 0; a < 3; ++a) {
+        wlow.r3[0][a] = x3[a];
+        wlow.r3[1][a] = w3[a] * (1.0 - x3[a]);
+        wlow.r3[2][a] = w3[a] * x3[a];
+    }
+}
+
+static FarParams far_params(Op& op) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
     FarParams fp;
     fp.gx = op.gx; fp.gy = op.gy; fp.h = op.h; fp.nx = op.nx; fp.ny = op.ny;
     const bool f32 = op.prec == FDS_FP32;
@@ -527,29 +575,14 @@ void launch_assemble(Op& op) {
     fp.nsub = 2;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
     fp.nwork = T * (T + 1) / 2 * fp.nsub;
-    const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
-    {
-        KScope _ks(c, "asm_far");
-        if (f32)
-            hipLaunchKernelGGL(asm_far_kernel<true>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
-        else
-            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
-    }
-    FDS_HIP_TRY(hipGetLastError());
-    if (f32) {
-        // FP64 pass over the tiles that touch the band: N there in complex128
-        FarParams bpf = fp;
-        bpf.tab = c.hk_tab;
-        bpf.band_only = 1;
-        bpf.nwork = 3 * T * bpf.nsub;
-        const unsigned nb2 = (unsigned)((bpf.nwork + WAVES - 1) / WAVES);
-        {
-            KScope _ks(c, "asm_far_band");
-            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt, wlow);
-        }
-        FDS_HIP_TRY(hipGetLastError());
-    }
+    return fp;
+}
 
+// self / adjacent pairs and the band correction of one operator
+static void launch_near_band(Op& op, const FarParams& fp, const W8& wt) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const bool f32 = op.prec == FDS_FP32;
     double2* nb = static_cast<double2*>(c.dmalloc(sizeof(double2) * 24 * (size_t)n));
     NearParams np;
     np.gx = op.gx; np.gy = op.gy; np.h = op.h; np.nx = op.nx; np.ny = op.ny;
@@ -574,6 +607,77 @@ void launch_assemble(Op& op) {
     }
     FDS_HIP_TRY(hipGetLastError());
     c.dfree(nb);   // stream-ordered release (see Ctx::dfree)
+}
+
+void launch_assemble(Op& op) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    W8 wt;
+    WLow wlow;
+    far_rules(op, wt, wlow);
+    const FarParams fp = far_params(op);
+    const bool f32 = op.prec == FDS_FP32;
+    const int64_t T = (n + TB - 1) / TB;
+    const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
+    {
+        KScope _ks(c, "asm_far");
+        if (f32)
+            hipLaunchKernelGGL(asm_far_kernel<true>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+        else
+            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    if (f32) {
+        // FP64 pass over the tiles that touch the band: N there in complex128
+        FarParams bpf = fp;
+        bpf.tab = c.hk_tab;
+        bpf.band_only = 1;
+        bpf.nwork = 3 * T * bpf.nsub;
+        const unsigned nb2 = (unsigned)((bpf.nwork + WAVES - 1) / WAVES);
+        {
+            KScope _ks(c, "asm_far_band");
+            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt, wlow);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+    }
+    launch_near_band(op, fp, wt);
+}
+
+// All far tiles of several FP64 operators in one persistent launch, then the
+// per-operator near-pair and band kernels. Geometry must already be built.
+void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
+    if (nops <= 0) return;
+    std::vector<FarParams> jobs(nops);
+    std::vector<int64_t> prefix(nops + 1, 0);
+    W8 wt;
+    WLow wlow;
+    far_rules(*ops[0], wt, wlow);
+    for (int j = 0; j < nops; ++j) {
+        FDS_REQUIRE(ops[j]->prec == FDS_FP64, FDS_ERR_NOTIMPL, "batched assembly is FP64 only");
+        jobs[j] = far_params(*ops[j]);
+        prefix[j + 1] = prefix[j] + jobs[j].nwork;
+    }
+    const size_t jb = sizeof(FarParams) * nops, pb = sizeof(int64_t) * (nops + 1);
+    char* dbuf = static_cast<char*>(c.dmalloc(jb + pb + 256));
+    FarParams* djobs = reinterpret_cast<FarParams*>(dbuf);
+    int64_t* dprefix = reinterpret_cast<int64_t*>(dbuf + jb);
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(dbuf + jb + pb + 128 - ((jb + pb) % 128));
+    FDS_HIP_TRY(hipMemcpyAsync(djobs, jobs.data(), jb, hipMemcpyHostToDevice, c.stream));
+    FDS_HIP_TRY(hipMemcpyAsync(dprefix, prefix.data(), pb, hipMemcpyHostToDevice, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));   // the host tables go out of scope below
+    int ncu = 0;
+    FDS_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+    const int64_t want = (prefix[nops] + WAVES - 1) / WAVES;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 2 * (int64_t)std::max(ncu, 1)));
+    {
+        KScope _ks(c, "asm_far_batch");
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, c.stream, counter);
+        hipLaunchKernelGGL(asm_far_batch_kernel, dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs, dprefix, nops,
+                           counter, c.hk_tab, wt, wlow);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    for (int j = 0; j < nops; ++j) launch_near_band(*ops[j], jobs[j], wt);
+    c.dfree(dbuf);
 }
 
 }  // namespace fds

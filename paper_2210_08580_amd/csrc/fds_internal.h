@@ -57,6 +57,8 @@ struct Ctx {
     hipStream_t stream = nullptr;
     fds_allocator alloc{};
     bool has_alloc = false;
+    bool autotune = false;                     // time GEMM split-K candidates on first use
+    std::map<std::string, int> tuned;          // shape class -> chosen split-K factor
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
     float* hk_tab32 = nullptr;    // device copy of the single-precision table
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
@@ -157,6 +159,7 @@ void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out);
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
 // assemble.hip
 void launch_assemble(Op& op);
+void launch_assemble_batch(Ctx& c, Op* const* ops, int nops);
 // gauss rules (host)
 void gauss_legendre_01(int n, double* x, double* w);
 

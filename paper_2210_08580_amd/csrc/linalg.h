@@ -12,6 +12,20 @@ constexpr double kPiHost = 3.14159265358979323846;
 // C = alpha op(A) op(B) + beta C, column-major, m x n result, inner dimension k.
 void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const double2* A, int64_t lda,
            const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);
+// Grouped complex GEMM C_g = alpha_g A_g B_g + beta_g C_g (no transposes), one launch.
+struct GemmSpec {
+    int m, n, k;
+    double2 alpha, beta;
+    const double2* A;
+    int64_t lda;
+    const double2* B;
+    int64_t ldb;
+    double2* C;
+    int64_t ldc;
+};
+void zgemm_grouped_nn(Ctx& c, const std::vector<GemmSpec>& specs);
+// Split-K autotuner cache: number of entries; keys: cap x 160 chars, values: cap ints.
+int autotune_entries(Ctx& c, int cap, char* keys, int* values);
 // zgemm with a complex64 A operand, widened to complex128 on load (FP64 MFMA).
 void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const float2* A, int64_t lda,
                const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);

@@ -8,7 +8,9 @@
 //   * small dense factorisations in one workgroup: Cholesky (real), LU with
 //     partial pivoting (complex), block triangular solves.
 #include <cmath>
+#include <cstdio>
 #include <type_traits>
+#include <typeinfo>
 #include <vector>
 
 #include "fds_internal.h"
@@ -87,20 +89,32 @@ __device__ __forceinline__ bool nonzero(double b) { return b != 0.0; }
 __device__ __forceinline__ double cmul(double a, double b) { return a * b; }
 __device__ __forceinline__ double cadd(double a, double b) { return a + b; }
 
+// Grouped GEMM problem descriptor (complex128, op N x N).
+struct GemmProblem {
+    int m, n, k;
+    double2 alpha, beta;
+    const double2* A;
+    int64_t lda;
+    const double2* B;
+    int64_t ldb;
+    double2* C;
+    int64_t ldc;
+    int64_t tile_begin;
+};
+
+// One 64 x 64 output tile (bx, by) and K-range bz of C = alpha op(A) op(B) + beta C.
 template <typename T, typename TA, int OPA, int OPB>
-__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha, const TA* __restrict__ A,
-                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta,
-                                                   T* __restrict__ C, int64_t ldc, int kchunk,
-                                                   T* __restrict__ part) {
+__device__ __forceinline__ void gemm_tile(int m, int n, int k, T alpha, const TA* __restrict__ A, int64_t lda,
+                                          const T* __restrict__ B, int64_t ldb, T beta, T* __restrict__ C,
+                                          int64_t ldc, int kchunk, T* __restrict__ part, int bx, int by, int bz,
+                                          T (&sA)[GB_K][GB_M + G_PAD], T (&sB)[GB_K][GB_N + G_PAD]) {
     typedef typename GT<T>::R RT;
     typedef typename GT<T>::Acc Acc;
-    __shared__ T sA[GB_K][GB_M + G_PAD];
-    __shared__ T sB[GB_K][GB_N + G_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
-    const int row0 = blockIdx.x * GB_M, col0 = blockIdx.y * GB_N;
-    const int kbeg = blockIdx.z * kchunk;
+    const int row0 = bx * GB_M, col0 = by * GB_N;
+    const int kbeg = bz * kchunk;
     const int kend = min(k, kbeg + kchunk);
 
     Acc accR[2][2], accI[2][2];
@@ -194,13 +208,44 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha,
                     acc = accR[r][c][v];
                 }
                 if (part) {
-                    part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
+                    part[(int64_t)bz * m * n + gi + (int64_t)gj * m] = acc;
                 } else {
                     T o = cmul(alpha, acc);
                     if (nonzero(beta)) o = cadd(o, cmul(beta, C[gi + (int64_t)gj * ldc]));
                     C[gi + (int64_t)gj * ldc] = o;
                 }
             }
+}
+
+template <typename T, typename TA, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha, const TA* __restrict__ A,
+                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta,
+                                                   T* __restrict__ C, int64_t ldc, int kchunk,
+                                                   T* __restrict__ part) {
+    __shared__ T sA[GB_K][GB_M + G_PAD];
+    __shared__ T sB[GB_K][GB_N + G_PAD];
+    gemm_tile<T, TA, OPA, OPB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, blockIdx.x, blockIdx.y,
+                               blockIdx.z, sA, sB);
+}
+
+// Grouped GEMM: problems of uneven sizes in one launch; workgroup b takes tile
+// b - tile_begin[g] of the problem g with tile_begin[g] <= b < tile_begin[g + 1].
+__global__ __launch_bounds__(256) void gemm_grouped_kernel_nn(const GemmProblem* __restrict__ probs, int count) {
+    __shared__ double2 sA[GB_K][GB_M + G_PAD];
+    __shared__ double2 sB[GB_K][GB_N + G_PAD];
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmProblem& P = probs[lo];
+    const int64_t t = b - P.tile_begin;
+    const int gm = (P.m + GB_M - 1) / GB_M;
+    const int bx = (int)(t % gm), by = (int)(t / gm);
+    gemm_tile<double2, double2, OP_N, OP_N>(P.m, P.n, P.k, P.alpha, P.A, P.lda, P.B, P.ldb, P.beta, P.C, P.ldc,
+                                            P.k + GB_K, nullptr, bx, by, 0, sA, sB);
 }
 
 template <typename T>
@@ -218,16 +263,81 @@ __global__ void splitk_reduce_kernel(int m, int n, int nz, T alpha, const T* __r
 }
 
 template <typename T, typename TA, int OPA, int OPB>
+static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
+                        T beta, T* C, int64_t ldc, int nz);
+
+static int bucket(int v) {   // shape classes: powers of two
+    int b = 1;
+    while (b < v) b <<= 1;
+    return b;
+}
+
+// Split-K factor: a heuristic (split when the output tiles cannot fill the chip),
+// or, with autotuning on, the fastest of the candidates timed once per shape
+// class (operand types, ops, m, n, k rounded up to powers of two) on a scratch
+// output, and cached in the context. Never tunes while the stream is captured.
+template <typename T, typename TA, int OPA, int OPB>
+static int choose_split(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, const T* B, int64_t ldb) {
+    const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
+    const int tiles = gm * gn;
+    int nz = 1;
+    if (tiles < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + tiles - 1) / tiles, (k + 255) / 256));
+    if (!c.autotune || tiles >= 1024) return nz;   // enough tiles: no split to choose
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nz;
+    char key[160];
+    snprintf(key, sizeof(key), "%s/%s/%d%d/%d/%d/%d", typeid(T).name(), typeid(TA).name(), OPA, OPB, bucket(m),
+             bucket(n), bucket(k));
+    auto it = c.tuned.find(key);
+    if (it != c.tuned.end()) return it->second;
+    std::vector<int> cand;
+    for (int z = 1; z <= 64; z *= 2)
+        if (z == 1 || ((int64_t)z * 2 * GB_K <= k && (int64_t)z * m * n * sizeof(T) <= ((int64_t)1 << 29)))
+            cand.push_back(z);
+    T* scratch = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)m * n));
+    hipEvent_t e0, e1;
+    FDS_HIP_TRY(hipEventCreate(&e0));
+    FDS_HIP_TRY(hipEventCreate(&e1));
+    const bool prof = c.prof;
+    c.prof = false;
+    float best = 1e30f;
+    int bz = nz;
+    T one{}, zero{};
+    if constexpr (GT<T>::CPLX) one.x = 1; else one = 1;
+    for (int z : cand) {
+        gemm_launch<T, TA, OPA, OPB>(c, m, n, k, one, A, lda, B, ldb, zero, scratch, m, z);   // warm
+        FDS_HIP_TRY(hipEventRecord(e0, c.stream));
+        for (int rep = 0; rep < 3; ++rep)
+            gemm_launch<T, TA, OPA, OPB>(c, m, n, k, one, A, lda, B, ldb, zero, scratch, m, z);
+        FDS_HIP_TRY(hipEventRecord(e1, c.stream));
+        FDS_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        FDS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bz = z;
+        }
+    }
+    c.prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.dfree(scratch);
+    c.tuned[key] = bz;
+    return bz;
+}
+
+template <typename T, typename TA, int OPA, int OPB>
 static void gemm_dispatch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
                           T beta, T* C, int64_t ldc) {
+    const int nz = choose_split<T, TA, OPA, OPB>(c, m, n, k, A, lda, B, ldb);
+    gemm_launch<T, TA, OPA, OPB>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nz);
+}
+
+template <typename T, typename TA, int OPA, int OPB>
+static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
+                        T beta, T* C, int64_t ldc, int nz) {
     const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
-    // split K when the output tiles alone cannot fill the chip
-    int nz = 1;
-    const int tiles = gm * gn;
-    if (tiles < 512 && k > 4 * GB_K) {
-        nz = std::min((512 + tiles - 1) / tiles, (k + 255) / 256);
-        nz = std::max(nz, 1);
-    }
+    nz = std::max(1, nz);
     int kchunk = (k + nz - 1) / nz;
     kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
     nz = (k + kchunk - 1) / kchunk;
@@ -275,6 +385,44 @@ void zgemm(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const d
 void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const float2* A, int64_t lda,
                const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc) {
     gemm_any<double2, float2>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int autotune_entries(Ctx& c, int cap, char* keys, int* values) {
+    int i = 0;
+    for (const auto& kv : c.tuned) {
+        if (i < cap) {
+            if (keys) snprintf(keys + 160 * i, 160, "%s", kv.first.c_str());
+            if (values) values[i] = kv.second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+void zgemm_grouped_nn(Ctx& c, const std::vector<GemmSpec>& specs) {
+    std::vector<GemmProblem> probs;
+    int64_t tiles = 0;
+    for (const auto& g : specs) {
+        if (g.m <= 0 || g.n <= 0) continue;
+        GemmProblem P;
+        P.m = g.m; P.n = g.n; P.k = g.k;
+        P.alpha = g.alpha; P.beta = g.beta;
+        P.A = g.A; P.lda = g.lda; P.B = g.B; P.ldb = g.ldb; P.C = g.C; P.ldc = g.ldc;
+        P.tile_begin = tiles;
+        tiles += (int64_t)((g.m + GB_M - 1) / GB_M) * ((g.n + GB_N - 1) / GB_N);
+        probs.push_back(P);
+    }
+    if (probs.empty()) return;
+    FDS_REQUIRE(tiles < (int64_t)1 << 31, FDS_ERR_ARG, "grouped GEMM too large");
+    GemmProblem* d = static_cast<GemmProblem*>(c.dmalloc(sizeof(GemmProblem) * probs.size()));
+    FDS_HIP_TRY(hipMemcpyAsync(d, probs.data(), sizeof(GemmProblem) * probs.size(), hipMemcpyHostToDevice, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));   // the host table goes out of scope below
+    {
+        KScope _ks(c, "gemm_grouped");
+        hipLaunchKernelGGL(gemm_grouped_kernel_nn, dim3((unsigned)tiles), dim3(256), 0, c.stream, d, (int)probs.size());
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(d);
 }
 
 void cgemm(Ctx& c, int opa, int opb, int m, int n, int k, float2 alpha, const float2* A, int64_t lda,

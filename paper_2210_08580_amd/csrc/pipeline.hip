@@ -199,7 +199,7 @@ const double* filter_basis_view(Op& op) {
     return op.Vn;
 }
 
-void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
+static void filter_prepare(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
     ensure_gram_factor(op);
@@ -213,6 +213,13 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
     op.Vgc = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
     op.Bt = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
     real_to_complex(c, op.Vg, op.Vgc, (int64_t)n * ne);
+}
+
+void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    filter_prepare(op, form, alpha, n_modes, keep_null, cluster_rtol);
+    const int ne = op.n_eff;
     if (form == FDS_EFIE || form == FDS_CFIE) {
         // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
         double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
@@ -229,6 +236,59 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
     }
     op.stage = Stage::Filtered;
     op.rank = 0;
+}
+
+// Several FP64 operators: per-operator eigensolver, then each dense product
+// stage of all operators as one grouped GEMM launch.
+void run_filter_batch(Op* const* ops, int count, int form, double alpha, const int* n_modes, bool keep_null,
+                      double cluster_rtol) {
+    if (count <= 0) return;
+    Ctx& c = *ops[0]->ctx;
+    for (int j = 0; j < count; ++j) {
+        FDS_REQUIRE(ops[j]->prec == FDS_FP64, FDS_ERR_NOTIMPL, "batched filter is FP64 only");
+        filter_prepare(*ops[j], form, alpha, n_modes[j], keep_null, cluster_rtol);
+    }
+    std::vector<double2*> X(count, nullptr);
+    std::vector<GemmSpec> g;
+    if (form == FDS_EFIE || form == FDS_CFIE) {
+        for (int j = 0; j < count; ++j) {
+            Op& op = *ops[j];
+            const int n = (int)op.n, ne = op.n_eff;
+            X[j] = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
+            g.push_back({n, ne, n, kOne, kZero, op.S, n, op.Vgc, n, X[j], n});
+        }
+        zgemm_grouped_nn(c, g);
+        g.clear();
+        for (int j = 0; j < count; ++j) {
+            Op& op = *ops[j];
+            const int n = (int)op.n, ne = op.n_eff;
+            gram_inv(op, X[j], ne, X[j]);
+            g.push_back({n, ne, n, kOne, kZero, op.Nm, n, X[j], n, op.Bt, n});
+        }
+        zgemm_grouped_nn(c, g);
+        g.clear();
+        for (int j = 0; j < count; ++j) {
+            Op& op = *ops[j];
+            const int n = (int)op.n, ne = op.n_eff;
+            gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X[j], n);
+            axpby(c, kOne, X[j], kOne, op.Bt, (int64_t)n * ne);
+            c.dfree(X[j]);
+        }
+    }
+    if (form == FDS_MFIE || form == FDS_CFIE) {
+        const double a = form == FDS_MFIE ? -1.0 : -alpha;
+        const double2 b = form == FDS_MFIE ? kZero : kOne;
+        for (int j = 0; j < count; ++j) {
+            Op& op = *ops[j];
+            const int n = (int)op.n, ne = op.n_eff;
+            g.push_back({n, ne, n, make_double2(a, 0.0), b, op.D, n, op.Vgc, n, op.Bt, n});
+        }
+        zgemm_grouped_nn(c, g);
+    }
+    for (int j = 0; j < count; ++j) {
+        ops[j]->stage = Stage::Filtered;
+        ops[j]->rank = 0;
+    }
 }
 
 // Truncation of the projected block's singular values (descending):
