@@ -150,6 +150,155 @@ __global__ __launch_bounds__(64) void bisect_kernel(Pencil P, double glo, double
     if (lane == 0) lam[i] = 0.5 * (lo + hi);
 }
 
+// ---------------------------------------------------------------- scaled inertia count
+// Step k (0 <= k < K-1) of the block recurrence over the node pairs (k, n-1-k):
+// coupling E_k = diag(f(k), f(n-2-k)), next diagonal block D = [[m(k+1), x], [x, m(n-2-k)]]
+// with x = f(K-1) on the last step of an even n (the middle nodes are adjacent), else 0.
+struct SturmStep {
+    double lo1, go1, lo2, go2, ld1, gd1, ld2, gd2, xl, xg;
+};
+
+__global__ void sturm_steps_kernel(Pencil P, SturmStep* __restrict__ st) {
+    const int n = P.n, K = n / 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K - 1) return;
+    const bool odd = (n & 1) != 0;
+    SturmStep t;
+    t.lo1 = P.lo[k];
+    t.go1 = P.go[k];
+    t.lo2 = P.lo[n - 2 - k];
+    t.go2 = P.go[n - 2 - k];
+    t.ld1 = P.ld[k + 1];
+    t.gd1 = P.gd[k + 1];
+    t.ld2 = P.ld[n - 2 - k];
+    t.gd2 = P.gd[n - 2 - k];
+    const bool mid = !odd && k + 1 == K - 1;
+    t.xl = mid ? P.lo[K - 1] : 0.0;
+    t.xg = mid ? P.go[K - 1] : 0.0;
+    st[k] = t;
+}
+
+// Number of eigenvalues of the pencil below s by the block LDL^T recurrence
+// A_{k+1} = D_{k+1} - E_k A_k^{-1} E_k carried without division: B_k = s_k A_k with
+//     B_{k+1} = det(B_k) D_{k+1} - s_k E_k adj(B_k) E_k,   s_{k+1} = det(B_k),
+// (a block's inertia is read from sign det(B_k) = sign det(A_k) and
+// sign(b11) sign(s_k) = sign(a_k)), and B_k, s_k rescaled together by a power
+// of two after every step. The dependency chain per step is a few FMAs.
+// Power-of-two factor 2^-e with e the binary exponent of v (v > 0 finite).
+__device__ __forceinline__ double inv_pow2_of(double v) {
+    const long long bits = __double_as_longlong(v);
+    const long long e = (bits >> 52) & 0x7ff;             // biased exponent of v
+    return __longlong_as_double((2046 - e) << 52);          // 2^(1023 - (e - 1023)) = 2^-(e-1023)
+}
+
+constexpr int BS_WAVES = 4;            // wavefronts per eigenvalue: 256 shifts per round
+constexpr int BS_CHUNK = 64 * BS_WAVES;  // recurrence steps staged in LDS at a time
+
+__device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict__ st, double sig,
+                                   SturmStep* __restrict__ sh) {
+    const int n = P.n;
+    const int K = n / 2;
+    const bool odd = (n & 1) != 0;
+    double b11 = pm(P, 0, sig), b22 = pm(P, n - 1, sig), b12 = pf(P, n - 1, sig), sc = 1.0;
+    int cnt = 0;
+    for (int k0 = 0; k0 < K - 1; k0 += BS_CHUNK) {
+        const int kend = min(K - 1, k0 + BS_CHUNK);
+        __syncthreads();
+        if (k0 + (int)threadIdx.x < kend) sh[threadIdx.x] = st[k0 + threadIdx.x];
+        __syncthreads();
+        for (int k = k0; k < kend; ++k) {
+            const SturmStep t = sh[k - k0];
+            double det = fma(b11, b22, -b12 * b12);
+            if (det == 0.0) det = 1e-300 * (fabs(b11 * b22) + b12 * b12 + 1e-300);
+            cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
+            const double e1 = fma(-sig, t.go1, t.lo1), e2 = fma(-sig, t.go2, t.lo2);
+            const double m1 = fma(-sig, t.gd1, t.ld1), m2 = fma(-sig, t.gd2, t.ld2);
+            const double x = fma(-sig, t.xg, t.xl);
+            const double s1 = sc * e1, s2 = sc * e2;
+            const double n11 = fma(det, m1, -(s1 * e1) * b22);
+            const double n22 = fma(det, m2, -(s2 * e2) * b11);
+            const double n12 = fma(det, x, (s1 * e2) * b12);
+            const double f = inv_pow2_of(fmax(fmax(fabs(n11), fabs(n22)), fmax(fabs(n12), 1e-300)));
+            b11 = n11 * f;
+            b22 = n22 * f;
+            b12 = n12 * f;
+            sc = det * f;
+        }
+    }
+    double det = fma(b11, b22, -b12 * b12);
+    if (det == 0.0) det = 1e-300 * (fabs(b11 * b22) + b12 * b12 + 1e-300);
+    cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
+    if (odd) {
+        // middle node: val = m - (u1^2 c - 2 u1 u2 b + u2^2 a)/det(A), with A = B/sc
+        const int sN = (n - 1) / 2;
+        const double u1 = pf(P, sN - 1, sig), u2 = pf(P, sN, sig);
+        const double q = u1 * u1 * b22 - 2.0 * u1 * u2 * b12 + u2 * u2 * b11;
+        const double v = fma(pm(P, sN, sig), det, -sc * q);
+        cnt += ((v < 0.0) != (det < 0.0)) ? 1 : 0;
+    }
+    return cnt;
+}
+
+// One workgroup per eigenvalue index first + i. Each round evaluates 256 shifts
+// spread over [lo, hi] (endpoints included) and keeps the sub-interval that
+// holds the eigenvalue. The first round tries the caller's tight bracket
+// (lo0[i], hi0[i]) and falls back to the global bracket when its endpoint counts
+// do not enclose the index.
+__global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, const SturmStep* __restrict__ st,
+                                                                      const double* __restrict__ lo0,
+                                                                      const double* __restrict__ hi0, double glo,
+                                                                      double ghi, double rtol, double atol,
+                                                                      int first, int nw, double* __restrict__ lam) {
+    __shared__ unsigned long long mk[BS_WAVES];
+    __shared__ int flags[2];
+    __shared__ SturmStep stsh[BS_CHUNK];
+    const int i = blockIdx.x;
+    if (i >= nw) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int idx = first + i;
+    const int NS = 64 * BS_WAVES;
+    double lo = lo0[i], hi = hi0[i];
+    if (!(hi > lo)) {
+        lo = glo;
+        hi = ghi;
+    }
+    bool checked = false;
+    for (int it = 0; it < 48; ++it) {
+        const double w = hi - lo;
+        if (w <= fmax(rtol * fmax(fabs(lo), fabs(hi)), atol)) break;
+        const double s = tid == NS - 1 ? hi : lo + w * (double)tid / (double)(NS - 1);
+        const int cnt = pencil_count_scaled(P, st, s, stsh);
+        const unsigned long long m = __ballot(cnt > idx);
+        if (lane == 0) mk[wv] = m;
+        if (tid == 0) flags[0] = cnt > idx;                 // eigenvalue below lo
+        if (tid == NS - 1) flags[1] = cnt <= idx;           // eigenvalue above hi
+        __syncthreads();
+        int j = NS;
+        for (int q = 0; q < BS_WAVES; ++q)
+            if (mk[q]) {
+                j = q * 64 + __ffsll(mk[q]) - 1;
+                break;
+            }
+        const bool bad = flags[0] || flags[1];
+        __syncthreads();
+        if (bad) {
+            if (checked) break;   // cannot happen for a valid global bracket; keep the last interval
+            lo = glo;
+            hi = ghi;
+            checked = true;
+            continue;
+        }
+        checked = true;
+        // j >= 1: count(s_{j-1}) <= idx < count(s_j)
+        const double nlo = lo + w * (double)(j - 1) / (double)(NS - 1);
+        const double nhi = j == NS - 1 ? hi : lo + w * (double)j / (double)(NS - 1);
+        if (!(nhi - nlo < w)) break;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (tid == 0) lam[i] = 0.5 * (lo + hi);
+}
+
 // ---------------------------------------------------------------- folded ordering
 __device__ __forceinline__ int node_of(int r, int n) {
     if ((n & 1) && r == n - 1) return (n - 1) / 2;
@@ -179,7 +328,8 @@ __global__ void fold_bands_kernel(Pencil P, double* __restrict__ Lb, double* __r
 }
 
 // Banded LU with partial pivoting of the folded L - sigma_i G (thread per eigenvalue).
-// fac layout: [(j*7 + t) * nw + i], t = 0..4: U row j at columns j..j+4, t = 5,6: multipliers.
+// fac layout: [(j*7 + t) * nw + i]: t = 0: 1/U_jj, t = 1..4: U row j at columns j+1..j+4,
+// t = 5, 6: multipliers.
 __device__ __forceinline__ double start_value(int i, int node) {
     uint64_t z = ((uint64_t)i << 32 | (uint32_t)node) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -245,8 +395,9 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
             y1 -= l1 * y0;
             y2 -= l2 * y0;
             if (act) {
+                fac[((int64_t)j * 7 + 0) * nw + i] = inv;   // reciprocal pivot for the back substitution
 #pragma unroll
-                for (int t = 0; t < 5; ++t) fac[((int64_t)j * 7 + t) * nw + i] = w0[t];
+                for (int t = 1; t < 5; ++t) fac[((int64_t)j * 7 + t) * nw + i] = w0[t];
                 fac[((int64_t)j * 7 + 5) * nw + i] = l1;
                 fac[((int64_t)j * 7 + 6) * nw + i] = l2;
                 pv[(int64_t)j * nw + i] = (unsigned char)p;
@@ -274,9 +425,10 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
     }
 }
 
-constexpr int IV_CH = 8;   // steps whose operands are loaded ahead of use
+constexpr int IV_CH = 16;  // steps whose operands are loaded ahead of use
 
-// Back substitution U x = z (folded order), z and x node-major [n][nw].
+// Back substitution U x = z (folded order), z and x node-major [n][nw]. Full
+// chunks of IV_CH steps load all their operands before the dependent chain.
 __global__ __launch_bounds__(64) void invit_back_kernel(int n, int nw, const double* __restrict__ fac,
                                                         const double* __restrict__ Z, double* __restrict__ X) {
     const int lane = threadIdx.x & 63;
@@ -284,32 +436,41 @@ __global__ __launch_bounds__(64) void invit_back_kernel(int n, int nw, const dou
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
     double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
-    for (int j0 = n - 1; j0 >= 0; j0 -= IV_CH) {
+    // u[0] holds the reciprocal of the pivot; the terms of older unknowns are
+    // summed first so that the chain between steps is one FMA and one product
+    auto step = [&](int j, const double (&u)[5], double z) {
+        const double part = fma(-u[4], x4, fma(-u[3], x3, fma(-u[2], x2, z)));
+        const double v = fma(-u[1], x1, part) * u[0];
+        if (act) X[(int64_t)node_of(j, n) * nw + i] = v;
+        x4 = x3;
+        x3 = x2;
+        x2 = x1;
+        x1 = v;
+    };
+    int j0 = n - 1;
+    for (; j0 - (IV_CH - 1) >= 0; j0 -= IV_CH) {
         double u[IV_CH][5], zz[IV_CH];
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
             const int j = j0 - q;
-            if (j >= 0) {
 #pragma unroll
-                for (int t = 0; t < 5; ++t) u[q][t] = fac[((int64_t)j * 7 + t) * nw + i];
-                zz[q] = Z[(int64_t)node_of(j, n) * nw + i];
-            }
+            for (int t = 0; t < 5; ++t) u[q][t] = fac[((int64_t)j * 7 + t) * nw + i];
+            zz[q] = Z[(int64_t)node_of(j, n) * nw + i];
         }
 #pragma unroll
-        for (int q = 0; q < IV_CH; ++q) {
-            const int j = j0 - q;
-            if (j < 0) break;
-            const double v = (zz[q] - u[q][1] * x1 - u[q][2] * x2 - u[q][3] * x3 - u[q][4] * x4) / u[q][0];
-            if (act) X[(int64_t)node_of(j, n) * nw + i] = v;
-            x4 = x3;
-            x3 = x2;
-            x2 = x1;
-            x1 = v;
-        }
+        for (int q = 0; q < IV_CH; ++q) step(j0 - q, u[q], zz[q]);
+    }
+    for (; j0 >= 0; --j0) {
+        double u[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) u[t] = fac[((int64_t)j0 * 7 + t) * nw + i];
+        step(j0, u, Z[(int64_t)node_of(j0, n) * nw + i]);
     }
 }
 
-// Forward elimination of W = G X (computed on the fly), result z into Z.
+// Forward elimination of W = G X (computed on the fly), result z into Z. The
+// operands of IV_CH steps (pivots, multipliers and the three entries of X that
+// G x needs) are loaded before any of them is used.
 __global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int nw, const double* __restrict__ fac,
                                                        const unsigned char* __restrict__ pv,
                                                        const double* __restrict__ X, double* __restrict__ Z) {
@@ -324,34 +485,43 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int nw, const d
                P.go[k] * X[(int64_t)kp * nw + i];
     };
     double y0 = gx(node_of(0, n)), y1 = gx(node_of(1, n)), y2 = gx(node_of(2, n));
-    for (int j0 = 0; j0 < n; j0 += IV_CH) {
-        double l1v[IV_CH], l2v[IV_CH], rv[IV_CH];
+    auto step = [&](int j, int p, double l1, double l2, double r) {
+        if (p == 1) { const double t = y0; y0 = y1; y1 = t; }
+        else if (p == 2) { const double t = y0; y0 = y2; y2 = t; }
+        y1 -= l1 * y0;
+        y2 -= l2 * y0;
+        if (act) Z[(int64_t)node_of(j, n) * nw + i] = y0;
+        y0 = y1;
+        y1 = y2;
+        y2 = r;
+    };
+    int j0 = 0;
+    for (; j0 + IV_CH + 3 <= n; j0 += IV_CH) {
+        double l1v[IV_CH], l2v[IV_CH], xa[IV_CH], xb[IV_CH], xc[IV_CH];
         int pvv[IV_CH];
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
             const int j = j0 + q;
-            if (j < n) {
-                pvv[q] = pv[(int64_t)j * nw + i];
-                l1v[q] = fac[((int64_t)j * 7 + 5) * nw + i];
-                l2v[q] = fac[((int64_t)j * 7 + 6) * nw + i];
-                rv[q] = (j + 3 < n) ? gx(node_of(j + 3, n)) : 0.0;
-            }
+            pvv[q] = pv[(int64_t)j * nw + i];
+            l1v[q] = fac[((int64_t)j * 7 + 5) * nw + i];
+            l2v[q] = fac[((int64_t)j * 7 + 6) * nw + i];
+            const int k = node_of(j + 3, n);
+            const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
+            xa[q] = X[(int64_t)k * nw + i];
+            xb[q] = X[(int64_t)km * nw + i];
+            xc[q] = X[(int64_t)kp * nw + i];
         }
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
-            const int j = j0 + q;
-            if (j >= n) break;
-            const int p = pvv[q];
-            if (p == 1) { const double t = y0; y0 = y1; y1 = t; }
-            else if (p == 2) { const double t = y0; y0 = y2; y2 = t; }
-            y1 -= l1v[q] * y0;
-            y2 -= l2v[q] * y0;
-            if (act) Z[(int64_t)node_of(j, n) * nw + i] = y0;
-            y0 = y1;
-            y1 = y2;
-            y2 = rv[q];
+            const int k = node_of(j0 + q + 3, n);
+            const int km = k == 0 ? n - 1 : k - 1;
+            const double r = P.gd[k] * xa[q] + P.go[km] * xb[q] + P.go[k] * xc[q];
+            step(j0 + q, pvv[q], l1v[q], l2v[q], r);
         }
     }
+    for (; j0 < n; ++j0)
+        step(j0, pv[(int64_t)j0 * nw + i], fac[((int64_t)j0 * 7 + 5) * nw + i], fac[((int64_t)j0 * 7 + 6) * nw + i],
+             (j0 + 3 < n) ? gx(node_of(j0 + 3, n)) : 0.0);
 }
 
 __device__ double block_sum(double v, double* sh) {
@@ -447,15 +617,54 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     std::vector<double> lam;
     int nw = 0;
     int extra = 8;
+    // Tight brackets: the P1 pencil is the Rayleigh-Ritz discretisation of -d^2/ds^2
+    // on the polygon of perimeter Ph, whose eigenvalues are (2 pi k/Ph)^2 (k = 0, 1, 1,
+    // 2, 2, ...), so eigenvalue index idx lies above lam_c = (2 pi ceil(idx/2)/Ph)^2, and
+    // its relative excess is O(h^2 lam) (about h^2 lam/12 on uniform meshes). The kernel
+    // checks each bracket with the inertia counts and falls back to the global one.
+    double Ph = 0.0, hmax = 0.0;
+    {
+        std::vector<double> hh(n);
+        FDS_HIP_TRY(hipMemcpyAsync(hh.data(), op.h, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        for (double v : hh) {
+            Ph += v;
+            hmax = std::max(hmax, v);
+        }
+    }
+    const int K = n / 2;
+    SturmStep* dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
+    {
+        KScope _ks(c, "filter_bisect");
+        hipLaunchKernelGGL(sturm_steps_kernel, dim3((K + 255) / 256), dim3(256), 0, c.stream, P, dst);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    const double l1c = (2.0 * kPiHost / Ph) * (2.0 * kPiHost / Ph);
     for (;;) {
         nw = std::min(n - start, want + extra);
+        std::vector<double> br(2 * (size_t)nw);
+        for (int i = 0; i < nw; ++i) {
+            const int idx = start + i;
+            const int kk = (idx + 1) / 2;
+            const double lc = l1c * kk * kk;
+            if (idx == 0) {
+                br[i] = -1e-6 * l1c;
+                br[nw + i] = 0.5 * l1c;
+            } else {
+                br[i] = lc * (1.0 - 1e-9);
+                br[nw + i] = lc * (1.0 + 0.5 * hmax * hmax * lc) * (1.0 + 1e-6) + 1e-6 * l1c;
+            }
+        }
+        double* dbr = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * nw));
+        FDS_HIP_TRY(hipMemcpyAsync(dbr, br.data(), sizeof(double) * 2 * nw, hipMemcpyHostToDevice, c.stream));
         double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
         {
             KScope _ks(c, "filter_bisect");
-            hipLaunchKernelGGL(bisect_kernel, dim3(nw), dim3(64), 0, c.stream, P, -1e-3 * lam_hi, lam_hi, 4e-15,
-                               4e-16 * lam_hi, start, nw, dlam);
+            hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, dbr,
+                               dbr + nw, -1e-3 * lam_hi, lam_hi, 4e-15, 4e-16 * lam_hi, start, nw, dlam);
         }
         FDS_HIP_TRY(hipGetLastError());
+        c.dfree(dbr);
         lam.assign(nw, 0.0);
         FDS_HIP_TRY(hipMemcpyAsync(lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost, c.stream));
         FDS_HIP_TRY(hipStreamSynchronize(c.stream));
@@ -544,6 +753,7 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     c.dfree(dcb);
     c.dfree(Lb);
     c.dfree(Gb);
+    c.dfree(dst);
     c.dfree(op.Vg);
     c.dfree(op.Vn);
     op.Vn = nullptr;
