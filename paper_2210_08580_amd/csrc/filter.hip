@@ -330,12 +330,16 @@ __global__ void fold_bands_kernel(Pencil P, double* __restrict__ Lb, double* __r
 // Banded LU with partial pivoting of the folded L - sigma_i G (thread per eigenvalue).
 // fac layout: [(j*7 + t) * nw + i]: t = 0: 1/U_jj, t = 1..4: U row j at columns j+1..j+4,
 // t = 5, 6: multipliers.
+// Pseudo-random start vector entries in [-1/2, 1/2): a 32-bit integer hash of
+// (eigenvalue index, node), cheap enough to sit beside the elimination.
 __device__ __forceinline__ double start_value(int i, int node) {
-    uint64_t z = ((uint64_t)i << 32 | (uint32_t)node) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    uint32_t z = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)node * 0x85EBCA77u;
+    z ^= z >> 15;
+    z *= 0x2C1B3C6Du;
+    z ^= z >> 12;
+    z *= 0x297A2D39u;
+    z ^= z >> 15;
+    return (double)z * (1.0 / 4294967296.0) - 0.5;
 }
 
 // Also runs the forward elimination of a pseudo-random right-hand side (the
@@ -359,15 +363,17 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
         w2[t] = Lb[(int64_t)t * n + 2] - s * Gb[(int64_t)t * n + 2];
     }
     double y0 = start_value(i, node_of(0, n)), y1 = start_value(i, node_of(1, n)), y2 = start_value(i, node_of(2, n));
+    __shared__ double rows[64][10];
     for (int j0 = 0; j0 < n; j0 += 64) {
-        // stage band rows j0+3 .. j0+66 (one per lane)
+        // stage band rows j0+3 .. j0+66 in LDS (one per lane); every lane reads them all
         const int rr = min(j0 + 3 + lane, n - 1);
-        double lb[5], gb[5];
+        __syncthreads();
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
-            lb[t] = Lb[(int64_t)t * n + rr];
-            gb[t] = Gb[(int64_t)t * n + rr];
+            rows[lane][t] = Lb[(int64_t)t * n + rr];
+            rows[lane][5 + t] = Gb[(int64_t)t * n + rr];
         }
+        __syncthreads();
         const int jend = min(n, j0 + 64);
         for (int j = j0; j < jend; ++j) {
             const bool v1 = j + 1 < n, v2 = j + 2 < n;
@@ -416,7 +422,7 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
             const int l = j - j0;
             if (j + 3 < n) {
 #pragma unroll
-                for (int t = 0; t < 5; ++t) w2[t] = bcast(lb[t], l) - s * bcast(gb[t], l);
+                for (int t = 0; t < 5; ++t) w2[t] = fma(-s, rows[l][5 + t], rows[l][t]);
             } else {
 #pragma unroll
                 for (int t = 0; t < 5; ++t) w2[t] = 0.0;

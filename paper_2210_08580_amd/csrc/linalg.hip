@@ -228,6 +228,127 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha,
                                blockIdx.z, sA, sB);
 }
 
+// Large problems: 128 x 64 output tile per workgroup (4 wavefronts of 64 x 32,
+// 4 x 2 MFMA tiles each), the next K slice loaded into registers while the
+// matrix cores work on the current one (complex128 output; A may be complex64,
+// widened on load).
+constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
+
+template <typename TA, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, double2 alpha,
+                                                       const TA* __restrict__ A, int64_t lda,
+                                                       const double2* __restrict__ B, int64_t ldb, double2 beta,
+                                                       double2* __restrict__ C, int64_t ldc, int kchunk,
+                                                       double2* __restrict__ part) {
+    __shared__ double2 sA[BB_K][BB_M + BB_PAD];
+    __shared__ double2 sB[BB_K][BB_N + BB_PAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int row0 = blockIdx.x * BB_M, col0 = blockIdx.y * BB_N;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(k, kbeg + kchunk);
+    d4 accR[4][2], accI[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            accR[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            accI[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    double2 ra[8], rb[4];
+    auto loadAB = [&](int kk) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int i, p;
+            if (OPA == OP_N) {
+                i = tid & 127;
+                p = (tid >> 7) + 2 * e;
+            } else {
+                p = tid & 15;
+                i = (tid >> 4) + 16 * e;
+            }
+            const int gi = row0 + i, gp = kk + p;
+            double2 v = make_double2(0.0, 0.0);
+            if (gi < m && gp < kend) {
+                const TA* src = (OPA == OP_N) ? A + gi + (int64_t)gp * lda : A + gp + (int64_t)gi * lda;
+                ld_into(src, OPA, v);
+            }
+            ra[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int j, p;
+            if (OPB == OP_N) {
+                p = tid & 15;
+                j = (tid >> 4) + 16 * e;
+            } else {
+                j = tid & 63;
+                p = (tid >> 6) + 4 * e;
+            }
+            const int gj = col0 + j, gp = kk + p;
+            double2 v = make_double2(0.0, 0.0);
+            if (gj < n && gp < kend) {
+                const double2* src = (OPB == OP_N) ? B + gp + (int64_t)gj * ldb : B + gj + (int64_t)gp * ldb;
+                v = ld_op(src, OPB);
+            }
+            rb[e] = v;
+        }
+    };
+    if (kbeg < kend) loadAB(kbeg);
+    for (int kk = kbeg; kk < kend; kk += BB_K) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (OPA == OP_N) sA[(tid >> 7) + 2 * e][tid & 127] = ra[e];
+            else sA[tid & 15][(tid >> 4) + 16 * e] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (OPB == OP_N) sB[tid & 15][(tid >> 4) + 16 * e] = rb[e];
+            else sB[(tid >> 6) + 4 * e][tid & 63] = rb[e];
+        }
+        __syncthreads();
+        if (kk + BB_K < kend) loadAB(kk + BB_K);
+#pragma unroll
+        for (int kc = 0; kc < BB_K / 4; ++kc) {
+            const int pr = kc * 4 + (lane >> 4);
+            double2 a[4], b[2];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = sA[pr][wm * 64 + r * 16 + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = sB[pr][wn * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
+                    accR[r][c] = mfma16(-a[r].y, b[c].y, accR[r][c]);
+                    accI[r][c] = mfma16(a[r].x, b[c].y, accI[r][c]);
+                    accI[r][c] = mfma16(a[r].y, b[c].x, accI[r][c]);
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = row0 + wm * 64 + r * 16 + acc_row(0.0, lane, v);
+                const int gj = col0 + wn * 32 + c * 16 + (lane & 15);
+                if (gi >= m || gj >= n) continue;
+                const double2 acc = make_double2(accR[r][c][v], accI[r][c][v]);
+                if (part) {
+                    part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
+                } else {
+                    double2 o = cmul(alpha, acc);
+                    if (beta.x != 0.0 || beta.y != 0.0) o = cadd(o, cmul(beta, C[gi + (int64_t)gj * ldc]));
+                    C[gi + (int64_t)gj * ldc] = o;
+                }
+            }
+}
+
 // Grouped GEMM: problems of uneven sizes in one launch; workgroup b takes tile
 // b - tile_begin[g] of the problem g with tile_begin[g] <= b < tile_begin[g + 1].
 __global__ __launch_bounds__(256) void gemm_grouped_kernel_nn(const GemmProblem* __restrict__ probs, int count) {
@@ -276,24 +397,51 @@ static int bucket(int v) {   // shape classes: powers of two
 // or, with autotuning on, the fastest of the candidates timed once per shape
 // class (operand types, ops, m, n, k rounded up to powers of two) on a scratch
 // output, and cached in the context. Never tunes while the stream is captured.
+template <typename T, typename TA>
+static constexpr bool big_ok() {
+    return std::is_same<T, double2>::value;
+}
+
+// Kernel configuration: split-K factor (bits 0..7) and the 128 x 128 tile (bit 8).
+// Heuristic: large tiles when both dimensions reach 128 (complex128 output), and
+// split K when the output tiles alone cannot fill the chip; or, with autotuning
+// on, the fastest candidate timed once per shape class (operand types, ops, m, n,
+// k rounded up to powers of two) on a scratch output, cached in the context.
+// Never tunes while the stream is being captured.
 template <typename T, typename TA, int OPA, int OPB>
-static int choose_split(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, const T* B, int64_t ldb) {
-    const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
-    const int tiles = gm * gn;
-    int nz = 1;
-    if (tiles < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + tiles - 1) / tiles, (k + 255) / 256));
-    if (!c.autotune || tiles >= 1024) return nz;   // enough tiles: no split to choose
+static int choose_config(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, const T* B, int64_t ldb) {
+    auto split_for = [&](int tiles) {
+        int nz = 1;
+        if (tiles < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + tiles - 1) / tiles, (k + 255) / 256));
+        return std::min(nz, 64);
+    };
+    const bool bigp = big_ok<T, TA>() && m >= BB_M && n >= BB_N;
+    int cfg;
+    if (bigp) {
+        const int tb = ((m + BB_M - 1) / BB_M) * ((n + BB_N - 1) / BB_N);
+        cfg = 256 | split_for(4 * tb);
+    } else {
+        cfg = split_for(((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N));
+    }
+    if (!c.autotune) return cfg;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nz;
+    if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return cfg;
     char key[160];
     snprintf(key, sizeof(key), "%s/%s/%d%d/%d/%d/%d", typeid(T).name(), typeid(TA).name(), OPA, OPB, bucket(m),
              bucket(n), bucket(k));
     auto it = c.tuned.find(key);
     if (it != c.tuned.end()) return it->second;
     std::vector<int> cand;
-    for (int z = 1; z <= 64; z *= 2)
-        if (z == 1 || ((int64_t)z * 2 * GB_K <= k && (int64_t)z * m * n * sizeof(T) <= ((int64_t)1 << 29)))
-            cand.push_back(z);
+    for (int big = 0; big <= (bigp ? 1 : 0); ++big) {
+        const int tiles = big ? ((m + BB_M - 1) / BB_M) * ((n + BB_N - 1) / BB_N)
+                              : ((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N);
+        for (int z = 1; z <= 64; z *= 2) {
+            if (z > 1 && ((int64_t)z * 2 * GB_K > k || (int64_t)z * m * n * sizeof(T) > ((int64_t)1 << 29) ||
+                          (int64_t)tiles * z > 8192))
+                continue;
+            cand.push_back((big ? 256 : 0) | z);
+        }
+    }
     T* scratch = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)m * n));
     hipEvent_t e0, e1;
     FDS_HIP_TRY(hipEventCreate(&e0));
@@ -301,7 +449,7 @@ static int choose_split(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, c
     const bool prof = c.prof;
     c.prof = false;
     float best = 1e30f;
-    int bz = nz;
+    int bc = cfg;
     T one{}, zero{};
     if constexpr (GT<T>::CPLX) one.x = 1; else one = 1;
     for (int z : cand) {
@@ -315,29 +463,31 @@ static int choose_split(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, c
         FDS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best) {
             best = ms;
-            bz = z;
+            bc = z;
         }
     }
     c.prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c.dfree(scratch);
-    c.tuned[key] = bz;
-    return bz;
+    c.tuned[key] = bc;
+    return bc;
 }
 
 template <typename T, typename TA, int OPA, int OPB>
 static void gemm_dispatch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
                           T beta, T* C, int64_t ldc) {
-    const int nz = choose_split<T, TA, OPA, OPB>(c, m, n, k, A, lda, B, ldb);
-    gemm_launch<T, TA, OPA, OPB>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nz);
+    const int cfg = choose_config<T, TA, OPA, OPB>(c, m, n, k, A, lda, B, ldb);
+    gemm_launch<T, TA, OPA, OPB>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cfg);
 }
 
 template <typename T, typename TA, int OPA, int OPB>
 static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
-                        T beta, T* C, int64_t ldc, int nz) {
-    const int gm = (m + GB_M - 1) / GB_M, gn = (n + GB_N - 1) / GB_N;
-    nz = std::max(1, nz);
+                        T beta, T* C, int64_t ldc, int cfg) {
+    const bool big = big_ok<T, TA>() && (cfg & 256);
+    const int bm = big ? BB_M : GB_M, bn = big ? BB_N : GB_N;
+    const int gm = (m + bm - 1) / bm, gn = (n + bn - 1) / bn;
+    int nz = std::max(1, cfg & 255);
     int kchunk = (k + nz - 1) / nz;
     kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
     nz = (k + kchunk - 1) / kchunk;
@@ -345,8 +495,18 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
     if (nz > 1) part = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
     {
         KScope _ks(c, std::is_same<T, float2>::value ? "gemm_c64" : "gemm");
-        hipLaunchKernelGGL((gemm_kernel<T, TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k, alpha, A,
-                           lda, B, ldb, beta, C, ldc, kchunk, part);
+        if constexpr (big_ok<T, TA>()) {
+            if (big) {
+                hipLaunchKernelGGL((gemm_big_kernel<TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+                                   alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+            } else {
+                hipLaunchKernelGGL((gemm_kernel<T, TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+                                   alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+            }
+        } else {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+                               alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+        }
     }
     FDS_HIP_TRY(hipGetLastError());
     if (part) {

@@ -105,7 +105,8 @@ def test_graph_captured_solves(sctx):
     nr = [3, 5, 2, 4]
     ang = [torch.from_numpy(rs.uniform(0, 2 * np.pi, r)) for r in nr]
     amp = [torch.from_numpy(wl.random_amplitudes(i, r)) for i, r in enumerate(nr)]
-    eager = [j.clone() for j in pipe.solve_eager(ang, amp)]
+    with torch.cuda.stream(sctx.stream):   # the clones must follow the solves on the same stream
+        eager = [j.clone() for j in pipe.solve_eager(ang, amp)]
     pipe.capture(ang, amp)
     for rep in range(3):
         # eager work between replays
