@@ -264,8 +264,8 @@ __global__ __launch_bounds__(PG_BS) void pair_grad_far_kernel(const double* __re
             const double dist =
                 hypot(px0 + 0.5 * epx - qx0 - 0.5 * eqx, py0 + 0.5 * epy - qy0 - 0.5 * eqy) - 0.5 * (hp + hq);
             int no = 8;
-            if (k * hm <= 0.04 && dist >= 96.0 * hm) no = 4;
-            if (k * hm <= 0.006 && dist >= 512.0 * hm) no = 3;
+            if (k * hm <= 0.1 && dist >= 96.0 * hm) no = 4;
+            if (k * hm <= 0.016 && dist >= 512.0 * hm) no = 3;
             const double* xs = no == 8 ? rs.x8 : (no == 4 ? rs.x4 : rs.x3);
             const double* ws = no == 8 ? rs.w8 : (no == 4 ? rs.w4 : rs.w3);
             const double2 M00 = m_eff(M, n, p, qq), M01 = m_eff(M, n, p, q1);

@@ -11,13 +11,14 @@
 //
 // Far pairs (|p - q| >= 2 mod n): 8 x 8 tensor Gauss rule, or a 4 x 4 / 3 x 3
 //   rule when the two panels are far apart relative to their length and the
-//   wave number: the n-point Gauss error for an integrand analytic in a
-//   Bernstein ellipse of parameter rho decays like rho^{-2n}; with the nearest
-//   singularity at distance d from panels of length <= h, rho >= 2d/h, and the
-//   oscillation contributes (kh/2)^{2n}/(2n)!. With d >= 96 h, kh <= 0.04
-//   (4 points) and d >= 512 h, kh <= 0.006 (3 points) both terms stay below
-//   1e-17, i.e. the result equals the 8 x 8 rule to rounding. The order is
-//   chosen per wavefront and row panel (the largest order any lane needs).
+//   wave number. The n-point Gauss rule on [0, 1] errs by
+//   (n!)^4 / ((2n+1) ((2n)!)^3) max |f^(2n)|; along a panel the phase kR moves by at
+//   most kh, so the oscillation contributes 5.6e-10 (kh)^8 (n = 4) and
+//   5.0e-7 (kh)^6 (n = 3), and the nearest singularity at distance d gives a
+//   Bernstein ellipse rho >= 2d/h and a term ~ rho^{-2n}. With d >= 96 h and
+//   kh <= 0.1 (4 points), d >= 512 h and kh <= 0.016 (3 points) every term stays
+//   below 1e-17 relative, i.e. the result equals the 8 x 8 rule to rounding. The
+//   order is chosen per wavefront and row panel (the largest any lane needs).
 //   One wavefront owns a 63 x 63 output tile: its 64 lanes hold the 64
 //   column panels j0-1 .. j0+62 (Gauss points in registers); the wave walks
 //   the row panels (wave-uniform, scalar loads), and for each row forms the
@@ -48,7 +49,7 @@ struct WLow {
     double r4[3][4];
     double r3[3][3];
 };
-constexpr double FAR4_D = 96.0, FAR4_KH = 0.04, FAR3_D = 512.0, FAR3_KH = 0.006;
+constexpr double FAR4_D = 96.0, FAR4_KH = 0.1, FAR3_D = 512.0, FAR3_KH = 0.016;
 
 struct FarParams {
     const double* __restrict__ gx;

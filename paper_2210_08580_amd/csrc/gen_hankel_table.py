@@ -34,7 +34,7 @@ import numpy as np
 
 mp.mp.dps = 50
 XS, XA = 2, 25
-DEG = 21
+DEG = 15
 NSER = 16
 DEG32 = 9
 NSER32 = 9
