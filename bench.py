@@ -32,18 +32,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gemm_flops(n, ne, nrhs, refine_sweeps):
-    """Algorithmic FP64 flops of the complex GEMMs in one step (8 flop per complex MAC)."""
-    f = 0.0
-    f += 2 * 8.0 * n * n * ne            # Bt = N^T G^-1 S^T V_g: two N x N x n_eff products
-    f += 8.0 * ne * ne * n               # Woodbury core W U
-    f += 8.0 * n * n * nrhs              # right-hand side S G^-1 f
-    f += 2 * 8.0 * ne * n * nrhs         # Woodbury apply
-    f += (refine_sweeps + 1) * 2 * 8.0 * ne * n * nrhs   # residuals with the full filtered operator
-    f += refine_sweeps * 2 * 8.0 * ne * n * nrhs         # Woodbury apply per sweep
-    return f
-
-
 def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
     """Time the CPU oracle stage by stage at N = n_sample on the same curve, k,
     formulation and filter, and scale each stage to N = n_full by its
@@ -131,26 +119,51 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
     return t1 - t0, prof, info, j
 
 
-def roofline(prof, n, ne, nrhs, sweeps, steps):
-    """Roofline of the kernel family with the largest total time."""
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "gemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_op_n_star8192.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the GEMM source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def roofline(prof, n, ne, steps, precision):
+    """Roofline of the kernel family with the largest total time (HIP events on
+    the context stream): achieved = algorithmic work per launch / mean launch time."""
     name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
-    if name == "asm_far":
+    per_launch_s = (tot_ms / 1e3) / max(launches, 1)
+    traffic = None
+    if name == "gemm_op_n":
+        # the filter's products S^T V_g and N^T (G^-1 S^T V_g): n x n_eff outputs with
+        # inner dimension n, 8 flop per complex multiply-add
+        work = 8.0 * n * n * ne
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
+                "kernel_symbol": "gemm_big_kernel<%s, 0, 0>" % ("float2" if precision == "fp32" else "double2")}
+        traffic = measured_traffic(name + ":" + precision)
+    elif name == "asm_far":
         work = 32.0 * n * n * FLOP_PER_POINT_PAIR
         roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-    elif name == "gemm":
-        work = gemm_flops(n, ne, nrhs, sweeps)
-        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-        launches = steps       # the per-step work above is summed over the step's GEMM launches
     else:
         work = None
         roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-    per_launch_s = (tot_ms / 1e3) / max(launches, 1)
     if work is not None:
         ach = work / per_launch_s / 1e12
         roof.update(achieved=ach, frac=ach / roof["peak"])
     else:
         roof.update(achieved=None, frac=None)
-    roof.update(kernel=name, avg_launch_ms=per_launch_s * 1e3, traffic=None)
+    roof.update(kernel=name, launches=launches, avg_launch_ms=per_launch_s * 1e3, traffic=traffic)
     return roof
 
 
@@ -165,6 +178,8 @@ def main():
                     help="assembly precisions to time: fp64 (plain) and/or fp32 (mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
@@ -183,6 +198,12 @@ def main():
     angles = torch.from_numpy(w.angles).cuda()
     amps = torch.from_numpy(w.amps).cuda()
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     res = {}
@@ -198,8 +219,8 @@ def main():
     main_v = "fp32" if "fp32" in res else variants[0]
     r = res[main_v]
     info = r["info"]
-    ne, sweeps = info["n_eff"], info["refine"]["iters"]
-    roof = roofline(r["prof"], n, ne, nrhs, sweeps, args.steps)
+    ne = info["n_eff"]
+    roof = roofline(r["prof"], n, ne, args.steps, main_v)
     extra = {"n_eff": ne, "rank": info["rank"]}
     for prec, rv in res.items():
         extra[prec] = {

@@ -43,6 +43,34 @@ namespace fds {
 constexpr int TB = 63;          // output columns (= rows) per tile
 constexpr int WAVES = 4;        // wavefronts per workgroup
 
+// Does tile (I, J) of the TB x TB tiling hold an entry (i, c) with cyclic
+// |c - i| <= bw? The differences c - i over the tile fill [dmin, dmax].
+__host__ __device__ inline bool tile_in_band(int I, int J, int n, int bw) {
+    if (bw < 0) return false;
+    const int r0 = I * TB, r1 = (n < r0 + TB ? n : r0 + TB) - 1;
+    const int c0 = J * TB, c1 = (n < c0 + TB ? n : c0 + TB) - 1;
+    const int dmin = c0 - r1, dmax = c1 - r0;
+    for (int m = -1; m <= 1; ++m)
+        if (dmax >= m * n - bw && dmin <= m * n + bw) return true;
+    return false;
+}
+
+// Band tiles by index t in [0, 3T): (I, I + o mod T), I = t / 3, o = t % 3. With
+// bw <= TB every band entry lies within cyclic tile distance 2 (2 only across the
+// narrow last tile); an index whose unordered pair {I, J} misses the band or was
+// already produced by a smaller index yields false, so each band tile comes once.
+__host__ __device__ inline bool band_tile(int t, int T, int n, int bw, int& I, int& J) {
+    I = t / 3;
+    const int o = t % 3;
+    J = (I + o) % T;
+    if (!tile_in_band(I, J, n, bw)) return false;
+    for (int o2 = 0; o2 < o; ++o2)
+        if ((I + o2) % T == J) return false;
+    for (int o2 = 0; o2 < 3; ++o2)
+        if ((J + o2) % T == I && 3 * J + o2 < t) return false;
+    return true;
+}
+
 
 // reduced far-field rules: [order 4: xi, w psi_0, w psi_1][order 3: same]
 struct WLow {
@@ -63,8 +91,8 @@ struct FarParams {
     void* __restrict__ Nm;
     void* __restrict__ D;
     double2* __restrict__ nband;      // N on the cyclic band |d| <= bw (FP32 operators)
-    int bw;                           // band half-width (0: no band)
-    int band_only;                    // 1: FP64 pass over the tiles touching the band, N band only
+    int bw;                           // band half-width (-1: no band)
+    int band_pass;                    // 1: the tiles holding band entries (FP32 operators), 0: the others
     double k;
     int n;
     int nsub;
@@ -82,6 +110,10 @@ __device__ __forceinline__ double2 shfl_down1(double2 v) {
 __device__ __forceinline__ float2 shfl_down1(float2 v) {
     return make_float2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
 }
+
+__device__ __forceinline__ void to_out(double2 v, double2& o) { o = v; }
+__device__ __forceinline__ void to_out(double2 v, float2& o) { o = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void to_out(float2 v, float2& o) { o = v; }
 
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
@@ -143,11 +175,13 @@ __device__ __forceinline__ void far_shared_setup(FarShared<F32>& sh, const void*
     __syncthreads();
 }
 
-// One work item (half of a 63 x 63 tile) of one operator, executed by one wavefront.
-template <bool F32>
+// One work item (nsub-th of a 63 x 63 tile) of one operator, executed by one
+// wavefront. F32: kernel values and sums in FP32; OUT32: complex64 outputs.
+template <bool F32, bool OUT32>
 __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, FarShared<F32>& sh) {
     typedef typename FarT<F32>::R RT;
     typedef typename FarT<F32>::C CT;
+    typedef typename std::conditional<OUT32, float2, double2>::type OT;
     const void* tab = sh.tab;
     const double* wsh = sh.wsh;
     const double* rl4 = sh.rl4;
@@ -157,27 +191,23 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
     const int sub = (int)(work - tile * P.nsub);
     const int n = P.n;
     int I, J;
-    if (P.band_only) {
-        // tiles (I, I + o mod T), o = 0, 1, 2, and their mirrors: with bw <= TB
-        // every entry within the band lies in one of them (only the last tile can
-        // be narrower than the band, so a neighbour may sit two tiles away)
-        const int T = (n + TB - 1) / TB;
-        I = (int)(tile / 3);
-        J = (I + (int)(tile % 3)) % T;
+    if (P.band_pass) {
+        if (!band_tile((int)tile, (n + TB - 1) / TB, n, P.bw, I, J)) return;
     } else {
         J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
         while ((int64_t)J * (J + 1) / 2 > tile) --J;
         while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
         I = (int)(tile - (int64_t)J * (J + 1) / 2);
+        if (tile_in_band(I, J, n, P.bw)) return;   // done by the band pass
     }
     const int i0 = I * TB + sub * P.tr;
     const int i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), n);
     if (i0 >= i1) return;
     const int j0 = J * TB;
     const bool mirror = (I != J);
-    CT* __restrict__ oS = static_cast<CT*>(P.S);
-    CT* __restrict__ oN = static_cast<CT*>(P.Nm);
-    CT* __restrict__ oD = static_cast<CT*>(P.D);
+    OT* __restrict__ oS = static_cast<OT*>(P.S);
+    OT* __restrict__ oN = static_cast<OT*>(P.Nm);
+    OT* __restrict__ oD = static_cast<OT*>(P.D);
 
     const int qraw = j0 - 1 + lane;
     const bool qvalid = qraw < n;
@@ -336,28 +366,30 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
             dcy = dcy < 0 ? dcy + n : dcy;
             dcy = 2 * dcy > n ? dcy - n : dcy;
             const bool inband = (dcy < 0 ? -dcy : dcy) <= P.bw;
-            if (P.band_only) {
-                if (writes && inband) {
+            if (writes) {
+                if (inband) {
+                    // N on the band is kept in complex128 (written by the FP64 band
+                    // pass); the complex64 matrix holds zeros there
                     const int bs = 2 * P.bw + 1;
                     const double2 vb = make_double2((double)vN.x, (double)vN.y);
                     P.nband[(int64_t)i * bs + dcy + P.bw] = vb;
-                    P.nband[(int64_t)col * bs - dcy + P.bw] = vb;
+                    if (mirror) P.nband[(int64_t)col * bs - dcy + P.bw] = vb;
+                    vN = CT{0, 0};
                 }
-            } else if (writes) {
-                if constexpr (F32) {
-                    if (inband) vN = CT{0, 0};   // held in FP64 in the band array
-                }
-                const CT vS = cadd(rS1, nS);
-                const CT vD = cadd(rD1, nD), vT = cadd(rT1, nT);
+                OT wS, wN, wD, wT;
+                to_out(cadd(rS1, nS), wS);
+                to_out(vN, wN);
+                to_out(cadd(rD1, nD), wD);
+                to_out(cadd(rT1, nT), wT);
                 const int64_t rc = (int64_t)i * n + col;
-                oS[rc] = vS;
-                oN[rc] = vN;
-                oD[rc] = vD;
+                oS[rc] = wS;
+                oN[rc] = wN;
+                oD[rc] = wD;
                 if (mirror) {
                     const int64_t cr = (int64_t)col * n + i;
-                    oS[cr] = vS;
-                    oN[cr] = vN;
-                    oD[cr] = vT;
+                    oS[cr] = wS;
+                    oN[cr] = wN;
+                    oD[cr] = wT;
                 }
             }
         }
@@ -367,13 +399,13 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
     }
 }
 
-template <bool F32>
+template <bool F32, bool OUT32>
 __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
     __shared__ FarShared<F32> sh;
     far_shared_setup<F32>(sh, P.tab, wt, wl);
     const int64_t work = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (work >= P.nwork) return;
-    far_work_item<F32>(P, work, sh);
+    far_work_item<F32, OUT32>(P, work, sh);
 }
 
 // Many operators in one launch: a persistent grid whose wavefronts take work
@@ -400,7 +432,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarP
             else hi = mid - 1;
         }
         const int j = __builtin_amdgcn_readfirstlane(lo);
-        far_work_item<false>(jobs[j], (int64_t)w - prefix[j], sh);
+        far_work_item<false, false>(jobs[j], (int64_t)w - prefix[j], sh);
     }
 }
 
@@ -571,7 +603,7 @@ static FarParams far_params(Op& op) {
     fp.n = n;
     fp.nband = op.Nband;
     fp.bw = f32 ? op.nbw : -1;
-    fp.band_only = 0;
+    fp.band_pass = 0;
     const int64_t T = (n + TB - 1) / TB;
     fp.nsub = 2;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
@@ -623,21 +655,26 @@ void launch_assemble(Op& op) {
     {
         KScope _ks(c, "asm_far");
         if (f32)
-            hipLaunchKernelGGL(asm_far_kernel<true>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+            hipLaunchKernelGGL((asm_far_kernel<true, true>), dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
         else
-            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+            hipLaunchKernelGGL((asm_far_kernel<false, false>), dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt,
+                               wlow);
     }
     FDS_HIP_TRY(hipGetLastError());
     if (f32) {
-        // FP64 pass over the tiles that touch the band: N there in complex128
+        // the tiles holding band entries, in FP64 (complex64 output, N on the band
+        // in complex128), split 8 ways for occupancy
         FarParams bpf = fp;
         bpf.tab = c.hk_tab;
-        bpf.band_only = 1;
+        bpf.band_pass = 1;
+        bpf.nsub = 8;
+        bpf.tr = (TB + bpf.nsub - 1) / bpf.nsub;
         bpf.nwork = 3 * T * bpf.nsub;
         const unsigned nb2 = (unsigned)((bpf.nwork + WAVES - 1) / WAVES);
         {
             KScope _ks(c, "asm_far_band");
-            hipLaunchKernelGGL(asm_far_kernel<false>, dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt, wlow);
+            hipLaunchKernelGGL((asm_far_kernel<false, true>), dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt,
+                               wlow);
         }
         FDS_HIP_TRY(hipGetLastError());
     }

@@ -57,6 +57,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     fds_allocator alloc{};
     bool has_alloc = false;
+    const char* gemm_tag = nullptr;            // profiling name of GEMM launches (nullptr: "gemm")
     bool autotune = false;                     // time GEMM split-K candidates on first use
     std::map<std::string, int> tuned;          // shape class -> chosen split-K factor
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
@@ -86,6 +87,16 @@ struct KScope {
     }
     KScope(const KScope&) = delete;
     KScope& operator=(const KScope&) = delete;
+};
+
+// Sets the profiling name of the GEMM launches made during its lifetime.
+struct GemmTag {
+    Ctx& c;
+    const char* old;
+    GemmTag(Ctx& ctx, const char* t) : c(ctx), old(ctx.gemm_tag) { ctx.gemm_tag = t; }
+    ~GemmTag() { c.gemm_tag = old; }
+    GemmTag(const GemmTag&) = delete;
+    GemmTag& operator=(const GemmTag&) = delete;
 };
 
 enum class Stage : int { Assembled = 1, Filtered = 2, Compressed = 3, Factored = 4 };

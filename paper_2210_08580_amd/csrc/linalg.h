@@ -26,9 +26,18 @@ struct GemmSpec {
 void zgemm_grouped_nn(Ctx& c, const std::vector<GemmSpec>& specs);
 // Split-K autotuner cache: number of entries; keys: cap x 160 chars, values: cap ints.
 int autotune_entries(Ctx& c, int cap, char* keys, int* values);
-// zgemm with a complex64 A operand, widened to complex128 on load (FP64 MFMA).
+// Complex128 band of a square, symmetric complex64-stored operand: the entries
+// of op(A) with cyclic |column - row| <= w are read as nb[row * (2w + 1) + column
+// - row + w] instead of from A (nb == nullptr: no band).
+struct BandA {
+    const double2* nb = nullptr;
+    int w = -1;
+    int n = 0;
+};
+// zgemm with a complex64 A operand, widened to complex128 on load (FP64 MFMA),
+// optionally with a complex128 band (requires m == k == band.n and opa != C).
 void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, const float2* A, int64_t lda,
-               const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc);
+               const double2* B, int64_t ldb, double2 beta, double2* C, int64_t ldc, const BandA& band = BandA());
 // Complex64 variant on the FP32 matrix cores (FP32 accumulation).
 void cgemm(Ctx& c, int opa, int opb, int m, int n, int k, float2 alpha, const float2* A, int64_t lda,
            const float2* B, int64_t ldb, float2 beta, float2* C, int64_t ldc);
@@ -51,12 +60,9 @@ template <typename T>
 void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p, T* X,
                    int64_t ncols);
 
-// Small dense factorisations (one workgroup).
-void chol_upper(Ctx& c, double* A, int n, int* info);
-void trsm_right_upper(Ctx& c, const double* R, int n, double* X, int64_t rows);
-void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats /* [min|pivot|, max|A|] */);
-void lu_factor(Ctx& c, double2* A, int n, int* piv, double* stats /* [min|pivot|, max|A|] */);
-void lu_solve(Ctx& c, const double2* LU, const int* piv, int n, double2* B, int64_t ncols);
+// Inverse of a complex r x r column-major matrix (A is left unchanged).
+// stats[0] = min |pivot|, stats[1] = max |A|.
+void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats);
 
 void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n);
 void daxpby(Ctx& c, double a, const double* x, double b, double* y, int64_t n);

@@ -38,42 +38,23 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
 // load and multiplied in FP64: N is hypersingular and the filtered products
 // apply it to smooth vectors, where FP32 accumulation (or FP32 rounding of the
 // vectors) would be amplified by ||N|| / |lambda_N(low modes)| ~ 1/h.
-// Y += alpha Nband X (the complex128 band of N, half-width w; N is symmetric,
-// so op(N) = N for OP_N and OP_T)
-__global__ void nband_apply_kernel(const double2* __restrict__ nb, int w, int n, int64_t ncols, double2 alpha,
-                                   const double2* __restrict__ X, double2* __restrict__ Y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * ncols) return;
-    const int i = (int)(t % n);
-    const int64_t col = t / n;
-    const double2* x = X + col * n;
-    const double2* row = nb + (int64_t)i * (2 * w + 1) + w;
-    double2 s = make_double2(0.0, 0.0);
-    for (int d = -w; d <= w; ++d) {
-        int j = i + d;
-        j = j < 0 ? j + n : (j >= n ? j - n : j);
-        s = cadd(s, cmul(row[d], x[j]));
-    }
-    Y[t] = cadd(Y[t], cmul(alpha, s));
-}
-
+// The complex128 band of N (half-width w) replaces the zeros of the complex64
+// matrix on load (N is symmetric, so op(N) = N for OP_N and OP_T).
 static void op_gemm(Op& op, int which, int opa, int64_t ncols, double2 alpha, const double2* X, double2 beta,
                     double2* Y) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
+    GemmTag tag(c, opa == OP_N ? "gemm_op_n" : "gemm_op_t");   // n x n operator products
     if (op.prec == FDS_FP32) {
         const float2* M = which == 0 ? op.S32 : (which == 1 ? op.N32 : op.D32);
-        zgemm_a32(c, opa, OP_N, n, (int)ncols, n, alpha, M, n, X, n, beta, Y, n);
+        BandA band;
         if (which == 1) {
             FDS_REQUIRE(opa != OP_C, FDS_ERR_ARG, "conjugated product with N");
-            const int64_t tot = (int64_t)n * ncols;
-            {
-                KScope _ks(c, "nband_apply");
-                hipLaunchKernelGGL(nband_apply_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream,
-                                   op.Nband, op.nbw, n, ncols, alpha, X, Y);
-            }
-            FDS_HIP_TRY(hipGetLastError());
+            band.nb = op.Nband;
+            band.w = op.nbw;
+            band.n = n;
         }
+        zgemm_a32(c, opa, OP_N, n, (int)ncols, n, alpha, M, n, X, n, beta, Y, n, band);
         return;
     }
     const double2* M = which == 0 ? op.S : (which == 1 ? op.Nm : op.D);
@@ -430,7 +411,7 @@ void run_factor(Op& op) {
         op.stage = Stage::Factored;
         return;
     }
-    FDS_REQUIRE(r <= 4096, FDS_ERR_NOTIMPL, "skeleton rank above 4096");
+    FDS_REQUIRE(r <= 2048, FDS_ERR_NOTIMPL, "skeleton rank above 2048");
     // K = I + beta^{-1} W_j U_j ; W_j = Bt^T (stored as n x r column-major "W^T")
     double2* K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
     zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, K, r);
