@@ -12,9 +12,10 @@
 // eigenvalues as the sum over blocks. One wavefront refines one eigenvalue,
 // its 64 lanes evaluating 64 shifts per round (multisection).
 // Eigenvectors: inverse iteration (L - lambda G) x_new = G x_old with a banded
-// LU with partial pivoting of the same folded ordering (bandwidth 2), one
-// thread per eigenvalue, G-Gram-Schmidt inside clusters of close eigenvalues,
-// and a final CholeskyQR in the G inner product.
+// LU with partial pivoting of the same folded ordering (bandwidth 2), run from
+// both ends of the band at once (one thread per eigenvalue and half, a 4 x 4
+// interface system in the middle), G-Gram-Schmidt inside clusters of close
+// eigenvalues, and a final Newton-Schulz orthonormalisation in the G inner product.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -327,9 +328,34 @@ __global__ void fold_bands_kernel(Pencil P, double* __restrict__ Lb, double* __r
     }
 }
 
-// Banded LU with partial pivoting of the folded L - sigma_i G (thread per eigenvalue).
-// fac layout: [(j*7 + t) * nw + i]: t = 0: 1/U_jj, t = 1..4: U row j at columns j+1..j+4,
-// t = 5, 6: multipliers.
+// ---------------------------------------------------------------- two-ended inverse iteration
+// The folded band A = L - sigma G (bandwidth 2) is eliminated from both ends at
+// once: the top half eliminates columns 0 .. mt-1 downward (rows j, j+1, j+2 as
+// pivot candidates, partial pivoting), the bottom half eliminates columns
+// n-1 .. n-mb upward, i.e. the same downward elimination of the reversed matrix
+// A' = J A J (A'[j][j + t - 2] is band entry 4 - t of row n-1-j), with
+// mt + mb = n - 4. The rows each half touches are disjoint (top: rows <= mt+1,
+// bottom: rows >= mt+2), so both are the partial-pivoting LU steps of the
+// one-ended elimination, and they leave four rows coupling the four unknowns
+// x_{mt} .. x_{mt+3}: the two reduced rows of each half. That 4 x 4 system is
+// solved with partial pivoting, then each half back-substitutes outward.
+// One thread per (eigenvalue, half); the chains are n/2 long instead of n.
+//
+// Factor record per (half, step j, eigenvalue), FS doubles: l1, l2, pivot choice
+// (0, 1, 2 as a double), 1/u_jj, u_{j,j+1} .. u_{j,j+4} (so that the forward
+// sweep reads the first 32 bytes and the back substitution the last 48).
+constexpr int FS = 8;
+
+__device__ __forceinline__ int trow(int h, int j, int n) { return h == 0 ? j : n - 1 - j; }
+
+// 1/d: hardware reciprocal estimate refined by two Newton steps r <- r + r (1 - d r)
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // Pseudo-random start vector entries in [-1/2, 1/2): a 32-bit integer hash of
 // (eigenvalue index, node), cheap enough to sit beside the elimination.
 __device__ __forceinline__ double start_value(int i, int node) {
@@ -342,45 +368,56 @@ __device__ __forceinline__ double start_value(int i, int node) {
     return (double)z * (1.0 / 4294967296.0) - 0.5;
 }
 
-// Also runs the forward elimination of a pseudo-random right-hand side (the
-// first inverse-iteration step) and stores its result z (node-major) in Z.
-__global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* __restrict__ Lb,
+// Factorisation of both halves (blockIdx.y = half) with the forward elimination
+// of the pseudo-random right-hand side (the first inverse-iteration step): z into
+// Z (node-major), the reduced interface rows and their right-hand sides into IF
+// ([half][10][nw]: row mt (or mt+3) coefficients, row mt+1 (or mt+2)
+// coefficients, two right-hand sides).
+__global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb, const double* __restrict__ Lb,
                                                           const double* __restrict__ Gb,
                                                           const double* __restrict__ sig, int nw, double pivmin,
-                                                          double* __restrict__ fac, unsigned char* __restrict__ pv,
-                                                          double* __restrict__ Z) {
+                                                          double* __restrict__ fac, int64_t hstride,
+                                                          double* __restrict__ Z, double* __restrict__ IF) {
+    const int h = blockIdx.y;
+    const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 64 + lane;
     const int i = min(i0, nw - 1);          // idle lanes repeat the last eigenvalue, store nothing
     const bool act = i0 < nw;
     const double s = sig[i];
+    double* __restrict__ F = fac + h * hstride;
+    auto band = [&](const double* B, int t, int j) {   // entry t of row j of A (h = 0) or A' (h = 1)
+        return h == 0 ? B[(int64_t)t * n + j] : B[(int64_t)(4 - t) * n + (n - 1 - j)];
+    };
     double w0[5], w1[5], w2[5];
-    // rows 0, 1, 2 of the folded band, shifted to the columns 0..4 of the window
+    // rows 0, 1, 2, shifted to the columns 0..4 of the window
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
-        w0[t] = t + 2 < 5 ? Lb[(int64_t)(t + 2) * n + 0] - s * Gb[(int64_t)(t + 2) * n + 0] : 0.0;
-        w1[t] = t + 1 < 5 ? Lb[(int64_t)(t + 1) * n + 1] - s * Gb[(int64_t)(t + 1) * n + 1] : 0.0;
-        w2[t] = Lb[(int64_t)t * n + 2] - s * Gb[(int64_t)t * n + 2];
+        w0[t] = t + 2 < 5 ? band(Lb, t + 2, 0) - s * band(Gb, t + 2, 0) : 0.0;
+        w1[t] = t + 1 < 5 ? band(Lb, t + 1, 1) - s * band(Gb, t + 1, 1) : 0.0;
+        w2[t] = band(Lb, t, 2) - s * band(Gb, t, 2);
     }
-    double y0 = start_value(i, node_of(0, n)), y1 = start_value(i, node_of(1, n)), y2 = start_value(i, node_of(2, n));
+    double y0 = start_value(i, node_of(trow(h, 0, n), n));
+    double y1 = start_value(i, node_of(trow(h, 1, n), n));
+    double y2 = start_value(i, node_of(trow(h, 2, n), n));
     __shared__ double rows[64][10];
-    for (int j0 = 0; j0 < n; j0 += 64) {
+    for (int j0 = 0; j0 < m; j0 += 64) {
         // stage band rows j0+3 .. j0+66 in LDS (one per lane); every lane reads them all
         const int rr = min(j0 + 3 + lane, n - 1);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
-            rows[lane][t] = Lb[(int64_t)t * n + rr];
-            rows[lane][5 + t] = Gb[(int64_t)t * n + rr];
+            rows[lane][t] = band(Lb, t, rr);
+            rows[lane][5 + t] = band(Gb, t, rr);
         }
         __syncthreads();
-        const int jend = min(n, j0 + 64);
+        const int jend = min(m, j0 + 64);
         for (int j = j0; j < jend; ++j) {
-            const bool v1 = j + 1 < n, v2 = j + 2 < n;
+            // rows j+1, j+2 exist: j + 2 <= m + 1 <= n - 3
             int p = 0;
             double best = fabs(w0[0]);
-            if (v1 && fabs(w1[0]) > best) { p = 1; best = fabs(w1[0]); }
-            if (v2 && fabs(w2[0]) > best) { p = 2; }
+            if (fabs(w1[0]) > best) { p = 1; best = fabs(w1[0]); }
+            if (fabs(w2[0]) > best) { p = 2; }
             if (p == 1) {
 #pragma unroll
                 for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w1[t]; w1[t] = q; }
@@ -389,29 +426,32 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
                 for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w2[t]; w2[t] = q; }
             }
             if (fabs(w0[0]) < pivmin) w0[0] = w0[0] < 0.0 ? -pivmin : pivmin;
-            const double inv = 1.0 / w0[0];
-            const double l1 = v1 ? w1[0] * inv : 0.0, l2 = v2 ? w2[0] * inv : 0.0;
+            const double inv = recip(w0[0]);
+            const double l1 = w1[0] * inv, l2 = w2[0] * inv;
 #pragma unroll
             for (int t = 1; t < 5; ++t) {
                 w1[t] -= l1 * w0[t];
                 w2[t] -= l2 * w0[t];
             }
-            if (p == 1) { const double q = y0; y0 = y1; y1 = q; }
-            else if (p == 2) { const double q = y0; y0 = y2; y2 = q; }
+            {
+                const double a0 = y0, a1 = y1, a2 = y2;
+                y0 = p == 1 ? a1 : (p == 2 ? a2 : a0);
+                y1 = p == 1 ? a0 : a1;
+                y2 = p == 2 ? a0 : a2;
+            }
             y1 -= l1 * y0;
             y2 -= l2 * y0;
             if (act) {
-                fac[((int64_t)j * 7 + 0) * nw + i] = inv;   // reciprocal pivot for the back substitution
-#pragma unroll
-                for (int t = 1; t < 5; ++t) fac[((int64_t)j * 7 + t) * nw + i] = w0[t];
-                fac[((int64_t)j * 7 + 5) * nw + i] = l1;
-                fac[((int64_t)j * 7 + 6) * nw + i] = l2;
-                pv[(int64_t)j * nw + i] = (unsigned char)p;
-                Z[(int64_t)node_of(j, n) * nw + i] = y0;
+                double2* f = reinterpret_cast<double2*>(F + ((int64_t)j * nw + i) * FS);
+                f[0] = make_double2(l1, l2);
+                f[1] = make_double2((double)p, inv);
+                f[2] = make_double2(w0[1], w0[2]);
+                f[3] = make_double2(w0[3], w0[4]);
+                Z[(int64_t)node_of(trow(h, j, n), n) * nw + i] = y0;
             }
             y0 = y1;
             y1 = y2;
-            y2 = (j + 3 < n) ? start_value(i, node_of(j + 3, n)) : 0.0;
+            y2 = start_value(i, node_of(trow(h, j + 3, n), n));   // j + 3 <= n - 2
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 w0[t] = w1[t + 1];
@@ -420,98 +460,201 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, const double* _
             w0[4] = 0.0;
             w1[4] = 0.0;
             const int l = j - j0;
-            if (j + 3 < n) {
 #pragma unroll
-                for (int t = 0; t < 5; ++t) w2[t] = fma(-s, rows[l][5 + t], rows[l][t]);
-            } else {
-#pragma unroll
-                for (int t = 0; t < 5; ++t) w2[t] = 0.0;
-            }
+            for (int t = 0; t < 5; ++t) w2[t] = fma(-s, rows[l][5 + t], rows[l][t]);
         }
+    }
+    if (act) {
+        double* q = IF + (int64_t)h * 10 * nw + i;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            q[(int64_t)t * nw] = w0[t];
+            q[(int64_t)(4 + t) * nw] = w1[t];
+        }
+        q[(int64_t)8 * nw] = y0;
+        q[(int64_t)9 * nw] = y1;
+    }
+}
+
+// The interface unknowns x_{mt} .. x_{mt+3} from the four reduced rows (Gaussian
+// elimination with partial pivoting, pivots kept above pivmin in magnitude).
+__device__ __forceinline__ void interface_solve(const double* __restrict__ IF, int nw, int i, double pivmin,
+                                                double (&x)[4]) {
+    double a[4][4], b[4];
+    const double* T = IF + i;
+    const double* B = IF + (int64_t)10 * nw + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a[0][q] = T[(int64_t)q * nw];
+        a[1][q] = T[(int64_t)(4 + q) * nw];
+        a[2][q] = B[(int64_t)(3 - q) * nw];          // bottom rows: reversed column order
+        a[3][q] = B[(int64_t)(7 - q) * nw];
+    }
+    b[0] = T[(int64_t)8 * nw];
+    b[1] = T[(int64_t)9 * nw];
+    b[2] = B[(int64_t)8 * nw];
+    b[3] = B[(int64_t)9 * nw];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        double best = fabs(a[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r)
+            if (fabs(a[r][k]) > best) {
+                best = fabs(a[r][k]);
+                p = r;
+            }
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r)
+            if (p == r) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double t = a[k][c];
+                    a[k][c] = a[r][c];
+                    a[r][c] = t;
+                }
+                const double t = b[k];
+                b[k] = b[r];
+                b[r] = t;
+            }
+        if (fabs(a[k][k]) < pivmin) a[k][k] = a[k][k] < 0.0 ? -pivmin : pivmin;
+        const double inv = 1.0 / a[k][k];
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            const double f = a[r][k] * inv;
+#pragma unroll
+            for (int c = k + 1; c < 4; ++c) a[r][c] -= f * a[k][c];
+            b[r] -= f * b[k];
+        }
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        double v = b[k];
+#pragma unroll
+        for (int c = k + 1; c < 4; ++c) v -= a[k][c] * x[c];
+        x[k] = v / a[k][k];
     }
 }
 
 constexpr int IV_CH = 16;  // steps whose operands are loaded ahead of use
 
-// Back substitution U x = z (folded order), z and x node-major [n][nw]. Full
-// chunks of IV_CH steps load all their operands before the dependent chain.
-__global__ __launch_bounds__(64) void invit_back_kernel(int n, int nw, const double* __restrict__ fac,
-                                                        const double* __restrict__ Z, double* __restrict__ X) {
+// Interface solve, then back substitution U x = z of each half outward from the
+// interface (z and x node-major [n][nw]). Full chunks of IV_CH steps load all
+// their operands before the dependent chain.
+__global__ __launch_bounds__(64) void invit_back_kernel(int n, int mt, int mb, int nw,
+                                                        const double* __restrict__ fac, int64_t hstride,
+                                                        const double* __restrict__ Z, const double* __restrict__ IF,
+                                                        double pivmin, double* __restrict__ X) {
+    const int h = blockIdx.y;
+    const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 64 + lane;
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
-    double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
+    const double* __restrict__ F = fac + h * hstride;
+    double xi[4];
+    interface_solve(IF, nw, i, pivmin, xi);
+    double x1, x2, x3, x4;   // x_{j+1} .. x_{j+4} in the half's own row order
+    if (h == 0) {
+        x1 = xi[0]; x2 = xi[1]; x3 = xi[2]; x4 = xi[3];
+        if (act) {
+            X[(int64_t)node_of(mt, n) * nw + i] = xi[0];
+            X[(int64_t)node_of(mt + 1, n) * nw + i] = xi[1];
+        }
+    } else {
+        x1 = xi[3]; x2 = xi[2]; x3 = xi[1]; x4 = xi[0];
+        if (act) {
+            X[(int64_t)node_of(mt + 2, n) * nw + i] = xi[2];
+            X[(int64_t)node_of(mt + 3, n) * nw + i] = xi[3];
+        }
+    }
     // u[0] holds the reciprocal of the pivot; the terms of older unknowns are
     // summed first so that the chain between steps is one FMA and one product
     auto step = [&](int j, const double (&u)[5], double z) {
         const double part = fma(-u[4], x4, fma(-u[3], x3, fma(-u[2], x2, z)));
         const double v = fma(-u[1], x1, part) * u[0];
-        if (act) X[(int64_t)node_of(j, n) * nw + i] = v;
+        if (act) X[(int64_t)node_of(trow(h, j, n), n) * nw + i] = v;
         x4 = x3;
         x3 = x2;
         x2 = x1;
         x1 = v;
     };
-    int j0 = n - 1;
+    auto load = [&](int j, double (&u)[5]) {
+        const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j * nw + i) * FS);
+        const double2 a = f[1], b = f[2], c = f[3];
+        u[0] = a.y;
+        u[1] = b.x;
+        u[2] = b.y;
+        u[3] = c.x;
+        u[4] = c.y;
+    };
+    int j0 = m - 1;
     for (; j0 - (IV_CH - 1) >= 0; j0 -= IV_CH) {
         double u[IV_CH][5], zz[IV_CH];
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
             const int j = j0 - q;
-#pragma unroll
-            for (int t = 0; t < 5; ++t) u[q][t] = fac[((int64_t)j * 7 + t) * nw + i];
-            zz[q] = Z[(int64_t)node_of(j, n) * nw + i];
+            load(j, u[q]);
+            zz[q] = Z[(int64_t)node_of(trow(h, j, n), n) * nw + i];
         }
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) step(j0 - q, u[q], zz[q]);
     }
     for (; j0 >= 0; --j0) {
         double u[5];
-#pragma unroll
-        for (int t = 0; t < 5; ++t) u[t] = fac[((int64_t)j0 * 7 + t) * nw + i];
-        step(j0, u, Z[(int64_t)node_of(j0, n) * nw + i]);
+        load(j0, u);
+        step(j0, u, Z[(int64_t)node_of(trow(h, j0, n), n) * nw + i]);
     }
 }
 
-// Forward elimination of W = G X (computed on the fly), result z into Z. The
-// operands of IV_CH steps (pivots, multipliers and the three entries of X that
-// G x needs) are loaded before any of them is used.
-__global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int nw, const double* __restrict__ fac,
-                                                       const unsigned char* __restrict__ pv,
-                                                       const double* __restrict__ X, double* __restrict__ Z) {
+// Forward elimination of W = G X (computed on the fly) for both halves, z into
+// Z, the interface right-hand sides into IF. The operands of IV_CH steps
+// (pivot choices, multipliers and the three entries of X that G x needs) are
+// loaded before any of them is used.
+__global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int mt, int mb, int nw,
+                                                       const double* __restrict__ fac, int64_t hstride,
+                                                       const double* __restrict__ X, double* __restrict__ Z,
+                                                       double* __restrict__ IF) {
+    const int h = blockIdx.y;
+    const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 64 + lane;
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
     const int n = P.n;
+    const double* __restrict__ F = fac + h * hstride;
     auto gx = [&](int k) {
         const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
         return P.gd[k] * X[(int64_t)k * nw + i] + P.go[km] * X[(int64_t)km * nw + i] +
                P.go[k] * X[(int64_t)kp * nw + i];
     };
-    double y0 = gx(node_of(0, n)), y1 = gx(node_of(1, n)), y2 = gx(node_of(2, n));
+    auto rnode = [&](int j) { return node_of(trow(h, j, n), n); };
+    double y0 = gx(rnode(0)), y1 = gx(rnode(1)), y2 = gx(rnode(2));
     auto step = [&](int j, int p, double l1, double l2, double r) {
-        if (p == 1) { const double t = y0; y0 = y1; y1 = t; }
-        else if (p == 2) { const double t = y0; y0 = y2; y2 = t; }
+        // row interchange as selects (an indexed form would go through scratch memory)
+        const double a0 = y0, a1 = y1, a2 = y2;
+        y0 = p == 1 ? a1 : (p == 2 ? a2 : a0);
+        y1 = p == 1 ? a0 : a1;
+        y2 = p == 2 ? a0 : a2;
         y1 -= l1 * y0;
         y2 -= l2 * y0;
-        if (act) Z[(int64_t)node_of(j, n) * nw + i] = y0;
+        if (act) Z[(int64_t)rnode(j) * nw + i] = y0;
         y0 = y1;
         y1 = y2;
         y2 = r;
     };
+    // row j + 3 <= m + 2 <= n - 2 always exists
     int j0 = 0;
-    for (; j0 + IV_CH + 3 <= n; j0 += IV_CH) {
-        double l1v[IV_CH], l2v[IV_CH], xa[IV_CH], xb[IV_CH], xc[IV_CH];
-        int pvv[IV_CH];
+    for (; j0 + IV_CH <= m; j0 += IV_CH) {
+        double2 lv[IV_CH];
+        double pvv[IV_CH], xa[IV_CH], xb[IV_CH], xc[IV_CH];
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
             const int j = j0 + q;
-            pvv[q] = pv[(int64_t)j * nw + i];
-            l1v[q] = fac[((int64_t)j * 7 + 5) * nw + i];
-            l2v[q] = fac[((int64_t)j * 7 + 6) * nw + i];
-            const int k = node_of(j + 3, n);
+            const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j * nw + i) * FS);
+            lv[q] = f[0];
+            pvv[q] = f[1].x;
+            const int k = rnode(j + 3);
             const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
             xa[q] = X[(int64_t)k * nw + i];
             xb[q] = X[(int64_t)km * nw + i];
@@ -519,15 +662,21 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int nw, const d
         }
 #pragma unroll
         for (int q = 0; q < IV_CH; ++q) {
-            const int k = node_of(j0 + q + 3, n);
+            const int k = rnode(j0 + q + 3);
             const int km = k == 0 ? n - 1 : k - 1;
             const double r = P.gd[k] * xa[q] + P.go[km] * xb[q] + P.go[k] * xc[q];
-            step(j0 + q, pvv[q], l1v[q], l2v[q], r);
+            step(j0 + q, (int)pvv[q], lv[q].x, lv[q].y, r);
         }
     }
-    for (; j0 < n; ++j0)
-        step(j0, pv[(int64_t)j0 * nw + i], fac[((int64_t)j0 * 7 + 5) * nw + i], fac[((int64_t)j0 * 7 + 6) * nw + i],
-             (j0 + 3 < n) ? gx(node_of(j0 + 3, n)) : 0.0);
+    for (; j0 < m; ++j0) {
+        const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j0 * nw + i) * FS);
+        const double2 l = f[0];
+        step(j0, (int)f[1].x, l.x, l.y, gx(rnode(j0 + 3)));
+    }
+    if (act) {
+        IF[(int64_t)(h * 10 + 8) * nw + i] = y0;
+        IF[(int64_t)(h * 10 + 9) * nw + i] = y1;
+    }
 }
 
 __device__ double block_sum(double v, double* sh) {
@@ -702,15 +851,19 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     FDS_HIP_TRY(hipMemcpyAsync(dsig, lam.data(), sizeof(double) * ne, hipMemcpyHostToDevice, c.stream));
     int* dcb = static_cast<int*>(c.dmalloc(sizeof(int) * (ncl + 1)));
     FDS_HIP_TRY(hipMemcpyAsync(dcb, cb.data(), sizeof(int) * (ncl + 1), hipMemcpyHostToDevice, c.stream));
-    double* fac = static_cast<double*>(c.dmalloc(sizeof(double) * 7 * (size_t)n * ne));
-    unsigned char* pv = static_cast<unsigned char*>(c.dmalloc((size_t)n * ne));
+    // two-ended elimination: mt steps from the top, mb from the bottom, 4 interface rows
+    const int mt = (n - 4) / 2, mb = n - 4 - mt;
+    const int64_t hstride = (int64_t)mb * ne * FS;
+    double* fac = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * (size_t)hstride));
+    double* IF = static_cast<double*>(c.dmalloc(sizeof(double) * 20 * (size_t)ne));
     double* Xn = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));   // node-major
     double* Wk = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
-    const unsigned ewaves = (unsigned)((ne + 63) / 64);
+    const dim3 egrid((unsigned)((ne + 63) / 64), 2);
+    const double pivmin = 1e-15 * mnorm;
     {
         KScope _ks(c, "filter_invit_factor");
-        hipLaunchKernelGGL(invit_factor_kernel, dim3(ewaves), dim3(64), 0, c.stream, n, Lb, Gb, dsig, ne,
-                           1e-15 * mnorm, fac, pv, Wk);
+        hipLaunchKernelGGL(invit_factor_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, Lb, Gb, dsig, ne, pivmin,
+                           fac, hstride, Wk, IF);
     }
     FDS_HIP_TRY(hipGetLastError());
     // inverse iteration from a pseudo-random right-hand side: two solves; the
@@ -719,12 +872,14 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     for (int it = 0; it < 2; ++it) {
         if (it > 0) {
             KScope _ks(c, "filter_invit_fwd");
-            hipLaunchKernelGGL(invit_fwd_kernel, dim3(ewaves), dim3(64), 0, c.stream, P, ne, fac, pv, Xn, Wk);
+            hipLaunchKernelGGL(invit_fwd_kernel, egrid, dim3(64), 0, c.stream, P, mt, mb, ne, fac, hstride, Xn, Wk,
+                               IF);
         }
         FDS_HIP_TRY(hipGetLastError());
         {
             KScope _ks(c, "filter_invit_back");
-            hipLaunchKernelGGL(invit_back_kernel, dim3(ewaves), dim3(64), 0, c.stream, n, ne, fac, Wk, Xn);
+            hipLaunchKernelGGL(invit_back_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, ne, fac, hstride, Wk, IF,
+                               pivmin, Xn);
         }
         FDS_HIP_TRY(hipGetLastError());
         {
@@ -754,7 +909,7 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     c.dfree(Wk);
     c.dfree(Xn);
     c.dfree(fac);
-    c.dfree(pv);
+    c.dfree(IF);
     c.dfree(dsig);
     c.dfree(dcb);
     c.dfree(Lb);

@@ -305,11 +305,11 @@ template void gram_pow_half<double2>(Ctx&, const double*, const double*, int, do
 // M = [A | I] (column-major, leading dimension r), nb columns per panel:
 //  * gj_panel_kernel (one workgroup): the panel rows at or below j0 in LDS, LU
 //    with row interchanges (pivot: largest |re| + |im|, ties to the lower row)
-//    fixes the pivot order perm and |pivot|; from M itself the pivot block
-//    A_pp (rows perm[j0 .. j0 + nb)) is then inverted without pivoting (its
-//    pivots are the same), F = A_pp^{-1}, and the row multipliers formed:
-//    W[i] = F[i - j0] - e_{i - j0} on the pivot positions, W[i] = -M[perm[i]] F
-//    (panel columns) elsewhere;
+//    fixes the pivot order perm and |pivot|. With P A_panel = L U (L11 the unit
+//    lower pivot block, L21 the rows below it), A_pp^{-1} = F = U^{-1} L11^{-1}
+//    and the row multipliers are W[i] = F[i - j0] - e_{i - j0} on the pivot
+//    positions, W[i] = -L21[i] L11^{-1} below them and W[i] = -M[i] F (panel
+//    columns) above j0;
 //  * gj_update_kernel: Mout[i][c] = M[perm[i]][c] + sum_b W[i][b] M[perm[j0 + b]][c],
 //    the panel's row operations on every column (columns left of j0 + nb
 //    become unit vectors).
@@ -356,6 +356,7 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double2* __restrict
                                                        double* __restrict__ pabs) {
     extern __shared__ double2 P[];   // (r - j0) rows of stride ps = nb | 1 (odd: no bank conflicts), then (r - j0) ints
     __shared__ double2 F[GJ_NB][2 * GJ_NB];   // right half: A_pp^{-1}
+    __shared__ double spiv[GJ_NB];            // |pivot|^2
     __shared__ double sv[4];
     __shared__ int si[4];
     const int tid = threadIdx.x;
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double2* __restrict
         const double2 pv = P[jj * ps + jj];
         const double den = pv.x * pv.x + pv.y * pv.y;
         const double2 pinv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0.0, 0.0);
-        if (tid == 0) pabs[j0 + jj] = sqrt(den);
+        if (tid == 0) spiv[jj] = den;   // global stores stay out of the loop (barriers would wait on them)
         double2 prow[GJ_NB];
 #pragma unroll
         for (int b = 0; b < GJ_NB; ++b) prow[b] = P[jj * ps + min(b, nb - 1)];
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double2* __restrict
         }
     }
     __syncthreads();
+    if (tid < nb) pabs[j0 + tid] = sqrt(spiv[tid]);
     // row order and multipliers W (r x nb, column-major): F[i - j0] - e_{i - j0}
     // on the pivot positions, -L21[i] L11^{-1} below them, -M[i] F above j0
     for (int i = tid; i < r; i += blockDim.x) {
