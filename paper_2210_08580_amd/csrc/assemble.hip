@@ -9,16 +9,18 @@
 // and entry (i, j) sums the blocks of the four pairs (p, q) in
 // {i-1, i} x {j-1, j} (panel p carries psi_0 of node p, psi_1 of node p+1).
 //
-// Far pairs (|p - q| >= 2 mod n): 8 x 8 tensor Gauss rule, or a 4 x 4 / 3 x 3
-//   rule when the two panels are far apart relative to their length and the
-//   wave number. The n-point Gauss rule on [0, 1] errs by
-//   (n!)^4 / ((2n+1) ((2n)!)^3) max |f^(2n)|; along a panel the phase kR moves by at
-//   most kh, so the oscillation contributes 5.6e-10 (kh)^8 (n = 4) and
-//   5.0e-7 (kh)^6 (n = 3), and the nearest singularity at distance d gives a
-//   Bernstein ellipse rho >= 2d/h and a term ~ rho^{-2n}. With d >= 96 h and
-//   kh <= 0.1 (4 points), d >= 512 h and kh <= 0.016 (3 points) every term stays
-//   below 1e-17 relative, i.e. the result equals the 8 x 8 rule to rounding. The
-//   order is chosen per wavefront and row panel (the largest any lane needs).
+// Far pairs (|p - q| >= 2 mod n): tensor Gauss rules of 8 down to 2 points per
+//   panel, the order chosen per wavefront and row panel (the largest any lane
+//   needs) from the gap d between the panels, h = max(h_p, h_q) and kh. The
+//   n-point error has an oscillation part ~ C_n (kh)^{2n} (phase kR moves by at
+//   most kh along a panel; C_2 ~ 1.4e-2, C_3 ~ 1.9e-4, C_4 ~ 5e-8 for these
+//   kernels) and a part from the kernel's singularity at distance d that decays
+//   like (d/h)^{-2n} (Bernstein ellipse). Against a 20-point rule the thresholds
+//   below keep both at the rounding level of the arithmetic used:
+//     FP64 (<= ~1e-15 relative): 6 points for d >= 12 h and 5 for d >= 24 h
+//       (kh <= 0.2), 4 for d >= 64 h (kh <= 0.1), 3 for d >= 512 h (kh <= 0.016);
+//     FP32 (<= ~1e-8, below its rounding): 4 points for d >= 6 h (kh <= 0.5),
+//       3 for d >= 16 h (kh <= 0.15), 2 for d >= 200 h (kh <= 0.025).
 //   One wavefront owns a 63 x 63 output tile: its 64 lanes hold the 64
 //   column panels j0-1 .. j0+62 (Gauss points in registers); the wave walks
 //   the row panels (wave-uniform, scalar loads), and for each row forms the
@@ -73,11 +75,14 @@ __host__ __device__ inline bool band_tile(int t, int T, int n, int bw, int& I, i
 
 
 // reduced far-field rules: [order 4: xi, w psi_0, w psi_1][order 3: same]
+// Reduced Gauss rules on [0, 1] for n = 2 .. 6 points, rule n at offset
+// low_rule_offset(n): xi[n], w psi_0(xi)[n], w psi_1(xi)[n].
+constexpr int WLOW_DOUBLES = 60;
 struct WLow {
-    double r4[3][4];
-    double r3[3][3];
+    double r[WLOW_DOUBLES];
 };
-constexpr double FAR4_D = 96.0, FAR4_KH = 0.1, FAR3_D = 512.0, FAR3_KH = 0.016;
+__host__ __device__ constexpr int low_rule_offset(int n) { return 3 * ((n - 1) * n / 2 - 1); }
+static_assert(low_rule_offset(7) == WLOW_DOUBLES, "reduced-rule table size");
 
 struct FarParams {
     const double* __restrict__ gx;
@@ -157,7 +162,7 @@ template <bool F32>
 struct FarShared {
     __attribute__((aligned(16))) char tab[FarT<F32>::TAB_BYTES];
     double wsh[16];            // w_b psi_0(xi_b), w_b psi_1(xi_b)
-    double rl4[12], rl3[9];    // reduced rules: xi, w psi_0, w psi_1
+    double rl[WLOW_DOUBLES];   // reduced rules (n = 2 .. 6): xi, w psi_0, w psi_1
 };
 
 template <bool F32>
@@ -170,8 +175,7 @@ __device__ __forceinline__ void far_shared_setup(FarShared<F32>& sh, const void*
         sh.wsh[threadIdx.x] = wt.wp0[threadIdx.x];
         sh.wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
     }
-    if (threadIdx.x < 12) sh.rl4[threadIdx.x] = wl.r4[threadIdx.x / 4][threadIdx.x % 4];
-    if (threadIdx.x < 9) sh.rl3[threadIdx.x] = wl.r3[threadIdx.x / 3][threadIdx.x % 3];
+    if (threadIdx.x < WLOW_DOUBLES) sh.rl[threadIdx.x] = wl.r[threadIdx.x];
     __syncthreads();
 }
 
@@ -184,8 +188,6 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
     typedef typename std::conditional<OUT32, float2, double2>::type OT;
     const void* tab = sh.tab;
     const double* wsh = sh.wsh;
-    const double* rl4 = sh.rl4;
-    const double* rl3 = sh.rl3;
     const int lane = threadIdx.x & 63;
     const int64_t tile = work / P.nsub;
     const int sub = (int)(work - tile * P.nsub);
@@ -248,14 +250,23 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
         if (active) {
             const double hm = fmax(hp, hq);
             const double dist = hypot(px0 + 0.5 * pex - qcx, py0 + 0.5 * pey - qcy) - 0.5 * (hp + hq);
+            const double kh = k * hm;
             ord = 8;
-            if (k * hm <= FAR4_KH && dist >= FAR4_D * hm) ord = 4;
-            if (k * hm <= FAR3_KH && dist >= FAR3_D * hm) ord = 3;
+            if constexpr (F32) {
+                if (kh <= 0.5 && dist >= 6.0 * hm) ord = 4;
+                if (kh <= 0.15 && dist >= 16.0 * hm) ord = 3;
+                if (kh <= 0.025 && dist >= 200.0 * hm) ord = 2;
+            } else {
+                if (kh <= 0.2 && dist >= 12.0 * hm) ord = 6;
+                if (kh <= 0.2 && dist >= 24.0 * hm) ord = 5;
+                if (kh <= 0.1 && dist >= 64.0 * hm) ord = 4;
+                if (kh <= 0.016 && dist >= 512.0 * hm) ord = 3;
+            }
         }
         ord = wave_max_int(ord);
         if (active) {
             const int no = ord;
-            const double* rx = ord == 4 ? rl4 : rl3;
+            const double* rx = sh.rl + low_rule_offset(no < 8 ? no : 2);
 #pragma unroll 1
             for (int a = 0; a < no; ++a) {
                 double xa, ya, wa0, wa1;
@@ -573,18 +584,15 @@ static void far_rules(const Op& op, W8& wt, WLow& wlow) {
         wt.wp0[a] = op.rule.w[a] * (1.0 - op.rule.xi[a]);
         wt.wp1[a] = op.rule.w[a] * op.rule.xi[a];
     }
-    double x4[4], w4[4], x3[3], w3[3];
-    gauss_legendre_01(4, x4, w4);
-    gauss_legendre_01(3, x3, w3);
-    for (int a = 0; a < 4; ++a) {
-        wlow.r4[0][a] = x4[a];
-        wlow.r4[1][a] = w4[a] * (1.0 - x4[a]);
-        wlow.r4[2][a] = w4[a] * x4[a];
-    }
-    for (int a = 0; a < 3; ++a) {
-        wlow.r3[0][a] = x3[a];
-        wlow.r3[1][a] = w3[a] * (1.0 - x3[a]);
-        wlow.r3[2][a] = w3[a] * x3[a];
+    for (int nq = 2; nq <= 6; ++nq) {
+        double x[6], w[6];
+        gauss_legendre_01(nq, x, w);
+        double* r = wlow.r + low_rule_offset(nq);
+        for (int a = 0; a < nq; ++a) {
+            r[a] = x[a];
+            r[nq + a] = w[a] * (1.0 - x[a]);
+            r[2 * nq + a] = w[a] * x[a];
+        }
     }
 }
 
