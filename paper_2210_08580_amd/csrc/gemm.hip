@@ -252,9 +252,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha,
 }
 
 // Large problems: 128 x 64 output tile per workgroup (4 wavefronts of 64 x 32,
-// 4 x 2 MFMA tiles each), the next K slice loaded into registers while the
-// matrix cores work on the current one (complex128 output; A may be complex64,
-// widened on load).
+// 4 x 2 MFMA tiles each). The K slices pass through registers (loaded two
+// slices ahead) into two alternating LDS buffers, so the matrix cores work on
+// one slice while the next is staged (complex128 output; A may be complex64,
+// widened when staged).
 constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
 
 template <typename TA, int OPA, int OPB>
@@ -263,8 +264,9 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                                                        const double2* __restrict__ B, int64_t ldb, double2 beta,
                                                        double2* __restrict__ C, int64_t ldc, int kchunk,
                                                        double2* __restrict__ part, BandA bd) {
-    __shared__ double2 sA[BB_K][BB_M + BB_PAD];
-    __shared__ double2 sB[BB_K][BB_N + BB_PAD];
+    // two LDS buffers: slice i is multiplied from one while slice i + 1 is staged into the other
+    __shared__ double2 sA[2][BB_K][BB_M + BB_PAD];
+    __shared__ double2 sB[2][BB_K][BB_N + BB_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
@@ -326,9 +328,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             if (dmax >= q * bd.n - bd.w && dmin <= q * bd.n + bd.w) return true;
         return false;
     };
-    if (kbeg < kend) loadAB(kbeg);
-    for (int kk = kbeg; kk < kend; kk += BB_K) {
-        __syncthreads();
+    auto stage = [&](int kk, int buf) {
         const bool bsl = std::is_same<TA, float2>::value && band_slice(kk);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -342,23 +342,23 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             }
             double2 v = widen_op(ra[e], OPA);
             if (bsl && row0 + i < m && kk + p < kend) band_lookup(bd, row0 + i, kk + p, v);
-            sA[p][i] = v;
+            sA[buf][p][i] = v;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (OPB == OP_N) sB[tid & 15][(tid >> 4) + 16 * e] = rb[e];
-            else sB[(tid >> 6) + 4 * e][tid & 63] = rb[e];
+            if (OPB == OP_N) sB[buf][tid & 15][(tid >> 4) + 16 * e] = rb[e];
+            else sB[buf][(tid >> 6) + 4 * e][tid & 63] = rb[e];
         }
-        __syncthreads();
-        if (kk + BB_K < kend) loadAB(kk + BB_K);
+    };
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kc = 0; kc < BB_K / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
             double2 a[4], b[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = sA[pr][wm * 64 + r * 16 + (lane & 15)];
+            for (int r = 0; r < 4; ++r) a[r] = sA[buf][pr][wm * 64 + r * 16 + (lane & 15)];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) b[c] = sB[pr][wn * 32 + c * 16 + (lane & 15)];
+            for (int c = 0; c < 2; ++c) b[c] = sB[buf][pr][wn * 32 + c * 16 + (lane & 15)];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -369,6 +369,24 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                     accI[r][c] = mfma16(a[r].y, b[c].x, accI[r][c]);
                 }
         }
+    };
+    // slice i in buffer i & 1; one barrier per slice: every wavefront has finished
+    // multiplying from a buffer before anyone stages into it again
+    if (kbeg < kend) {
+        loadAB(kbeg);
+        stage(kbeg, 0);
+        if (kbeg + BB_K < kend) loadAB(kbeg + BB_K);
+        __syncthreads();
+    }
+    int buf = 0;
+    for (int kk = kbeg; kk < kend; kk += BB_K) {
+        compute(buf);
+        if (kk + BB_K < kend) {
+            stage(kk + BB_K, buf ^ 1);
+            if (kk + 2 * BB_K < kend) loadAB(kk + 2 * BB_K);
+        }
+        __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
