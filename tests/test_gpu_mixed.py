@@ -59,7 +59,9 @@ def test_cgemm_parity(ctx, opa, opb, m, n, k):
 
 
 ASM_CASES = [("star", 300, 10.0), ("ellipse", 257, 5.0), ("circle", 64, 1.0), ("random", 400, 20.0),
-             ("star", 190, 10.0), ("star", 40, 3.0)]
+             ("star", 190, 10.0), ("star", 40, 3.0),
+             # band tiles next to a narrow last tile (127 = 2 x 63 + 1, 130 = 2 x 63 + 4, 64 = 63 + 1)
+             ("ellipse", 127, 4.0), ("random", 130, 6.0), ("star", 64, 2.0)]
 
 
 @pytest.mark.parametrize("kind,n,k", ASM_CASES)
