@@ -120,7 +120,7 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_op_n_star8192.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_star8192.json")
 
 
 def measured_traffic(kernel):
@@ -134,23 +134,28 @@ def measured_traffic(kernel):
             digest = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_sha256") != digest:
+    if rec.get("source_sha256") != digest:
         return None
-    return rec.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
-def roofline(prof, n, ne, steps, precision):
+def roofline(prof, n, ne, nrhs, steps, precision):
     """Roofline of the kernel family with the largest total time (HIP events on
     the context stream): achieved = algorithmic work per launch / mean launch time."""
     name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     per_launch_s = (tot_ms / 1e3) / max(launches, 1)
     traffic = None
-    if name == "gemm_op_n":
-        # the filter's products S^T V_g and N^T (G^-1 S^T V_g): n x n_eff outputs with
-        # inner dimension n, 8 flop per complex multiply-add
-        work = 8.0 * n * n * ne
+    sym = {"fp32": "float2", "fp64": "double2"}[precision]
+    if name in ("gemm_op", "gemm_op_vg"):
+        # N x N operator products on one kernel symbol each, 8 flop per complex
+        # multiply-add (4 with the real V_g). gemm_op_vg: S^T V_g (n_eff columns);
+        # gemm_op: N^T (G^-1 S^T V_g) (n_eff columns) and S^T (G^-1 f) (nrhs columns),
+        # one launch of each per step of this workload
+        per_step = 4.0 * n * n * ne if name == "gemm_op_vg" else 8.0 * n * n * (ne + nrhs)
+        work = per_step * steps / max(launches, 1)
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
-                "kernel_symbol": "gemm_big_kernel<%s, 0, 0>" % ("float2" if precision == "fp32" else "double2")}
+                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0>" % (sym, "double" if name == "gemm_op_vg" else "double2")}
         traffic = measured_traffic(name + ":" + precision)
     elif name == "asm_far":
         work = 32.0 * n * n * FLOP_PER_POINT_PAIR
@@ -178,6 +183,8 @@ def main():
                     help="assembly precisions to time: fp64 (plain) and/or fp32 (mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the GEMM autotuner time tile / split-K candidates per shape class (first use)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -194,6 +201,8 @@ def main():
     w = wl.workload(args.workload, nrhs=args.nrhs)
     n, nrhs = w.n, w.nrhs
     ctx = B.fds_ctx_create(0)
+    if args.autotune:
+        B.fds_autotune(ctx, True)
     nodes = torch.from_numpy(w.nodes).cuda()
     angles = torch.from_numpy(w.angles).cuda()
     amps = torch.from_numpy(w.amps).cuda()
@@ -220,7 +229,7 @@ def main():
     r = res[main_v]
     info = r["info"]
     ne = info["n_eff"]
-    roof = roofline(r["prof"], n, ne, args.steps, main_v)
+    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v)
     extra = {"n_eff": ne, "rank": info["rank"]}
     for prec, rv in res.items():
         extra[prec] = {
@@ -253,6 +262,8 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle sample at N={args.cpu_sample_n}")
         out["cpu_baseline"] = cpu_baseline(args.workload, n, nrhs, args.cpu_sample_n)
+    if args.autotune:
+        out["extra"]["autotune"] = B.fds_autotune_read(ctx)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -175,6 +175,17 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
                      const double* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                      const double* beta, void* C, int64_t ldc);
 
+/* Inverse of a dense complex128 r x r matrix by the routine that inverts the
+ * Woodbury core I + W U / beta (paper, Inversion of the structured matrices):
+ * blocked Gauss-Jordan, first without row interchanges and kept when
+ * max |A Ainv - I| <= 8 eps r, else with partial pivoting. A and Ainv: device,
+ * column-major, leading dimension r, caller-owned, not aliased (A is not
+ * modified). stats (host, 2 doubles, may be NULL): min |pivot| and max |A|; a
+ * caller treats A as singular when stats[0] < 64 eps stats[1].
+ * FDS_ERR_ARG for r < 1 or NULL pointers, FDS_ERR_NOTIMPL for r > 2048.
+ * Synchronises the context stream. Test and diagnostic entry point. */
+fds_status fds_zinv(fds_ctx ctx, int64_t r, const void* A, void* Ainv, double* stats);
+
 /* fds_zgemm for complex64 operands on the FP32 matrix cores (FP32 accumulation);
  * alpha and beta: host complex64 (2 floats each). */
 fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,

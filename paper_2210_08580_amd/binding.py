@@ -91,6 +91,7 @@ _SIGS = {
                                               C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.POINTER(fds_solve_stats)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_zinv": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64]),
@@ -291,6 +292,17 @@ def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:
     out = torch.empty((R.numel(), 8), dtype=torch.float64, device=R.device)
     _check(lib().fds_kernel_eval(ctx.handle, float(k), _ptr(R), R.numel(), _ptr(out)))
     return out
+
+
+def fds_zinv(ctx: Ctx, A: torch.Tensor):
+    """Inverse of the square complex128 column-major matrix held by A (shape (r, r),
+    the matrix is A.T); returns (Ainv in the same layout, (min |pivot|, max |A|))."""
+    r = A.shape[0]
+    assert A.dtype == torch.complex128 and A.is_contiguous() and A.shape == (r, r)
+    out = torch.empty_like(A)
+    st = (C.c_double * 2)()
+    _check(lib().fds_zinv(ctx.handle, r, _ptr(A), _ptr(out), st))
+    return out, (st[0], st[1])
 
 
 def fds_zgemm(ctx: Ctx, opa: int, opb: int, A: torch.Tensor, Bm: torch.Tensor, Cm: torch.Tensor,

@@ -243,6 +243,24 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
     });
 }
 
+fds_status fds_zinv(fds_ctx ctx, int64_t r, const void* A, void* Ainv, double* stats) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && A && Ainv && r >= 1, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(r <= 2048, FDS_ERR_NOTIMPL, "dense inverse of order above 2048");
+        Ctx& c = ctx->impl;
+        double* st = static_cast<double*>(c.dmalloc(sizeof(double) * 2));
+        gj_inverse(c, (double2*)const_cast<void*>(A), (double2*)Ainv, (int)r, st);
+        double hs[2];
+        FDS_HIP_TRY(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        c.dfree(st);
+        if (stats) {
+            stats[0] = hs[0];
+            stats[1] = hs[1];
+        }
+    });
+}
+
 fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
                      const float* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                      const float* beta, void* C, int64_t ldc) {

@@ -297,7 +297,16 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
                         w1 = rx[2 * no + b];
                     }
                     const double dx = xa - yb, dy = ya - zb;
-                    const double R = sqrt(fma(dx, dx, dy * dy));
+                    const double R2 = fma(dx, dx, dy * dy);
+                    double R;
+                    if constexpr (F32) {
+                        // FP32 reciprocal square root refined by one Newton step in FP64
+                        // (relative error ~1e-14, ample for FP32 kernel values)
+                        const double r0 = (double)__builtin_amdgcn_rsqf((float)R2);
+                        R = R2 * (r0 * fma(-0.5 * R2, r0 * r0, 1.5));
+                    } else {
+                        R = sqrt(R2);
+                    }
                     CT g, c;
                     far_kernel_values(k, R, tab, g, c);
                     const RT dq = (RT)fma(dx, nxq, dy * nyq);

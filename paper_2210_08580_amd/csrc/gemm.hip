@@ -258,33 +258,41 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha,
 // widened when staged).
 constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
 
-template <typename TA, int OPA, int OPB>
+// TB = double: a real B operand (two real MFMAs per complex-by-real tile step).
+template <typename TA, typename TB, int OPA, int OPB>
 __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, double2 alpha,
                                                        const TA* __restrict__ A, int64_t lda,
-                                                       const double2* __restrict__ B, int64_t ldb, double2 beta,
+                                                       const TB* __restrict__ B, int64_t ldb, double2 beta,
                                                        double2* __restrict__ C, int64_t ldc, int kchunk,
                                                        double2* __restrict__ part, BandA bd) {
+    constexpr bool BCPLX = std::is_same<TB, double2>::value;
+    constexpr bool GAUSS3 = BCPLX && OPA == OP_N;   // transposed-A loads leave no registers for a third product
     // two LDS buffers: slice i is multiplied from one while slice i + 1 is staged into the other
     __shared__ double2 sA[2][BB_K][BB_M + BB_PAD];
-    __shared__ double2 sB[2][BB_K][BB_N + BB_PAD];
+    __shared__ TB sB[2][BB_K][BB_N + BB_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     const int row0 = blockIdx.x * BB_M, col0 = blockIdx.y * BB_N;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(k, kbeg + kchunk);
-    d4 accR[4][2], accI[4][2];
+    // complex B and untransposed A: Gauss's three products per tile, T1 = ar br,
+    // T2 = ai bi, T3 = (ar + ai)(br + bi); Re = T1 - T2, Im = T3 - T1 - T2 (the sums
+    // are formed after the LDS reads). Other complex cases: four products. Real B:
+    // accR = ar b, accI = ai b.
+    d4 accR[4][2], accI[4][2], acc3[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             accR[a][b] = d4{0.0, 0.0, 0.0, 0.0};
             accI[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            acc3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
         }
     // raw operands in flight (complex64 A is widened when staged to LDS, so the
     // loads of the next slice are not waited on while the current one computes)
     TA ra[8];
-    double2 rb[4];
+    TB rb[4];
     auto loadAB = [&](int kk) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -312,9 +320,9 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                 p = (tid >> 6) + 4 * e;
             }
             const int gj = col0 + j, gp = kk + p;
-            double2 v = make_double2(0.0, 0.0);
+            TB v{};
             if (gj < n && gp < kend) {
-                const double2* src = (OPB == OP_N) ? B + gp + (int64_t)gj * ldb : B + gj + (int64_t)gp * ldb;
+                const TB* src = (OPB == OP_N) ? B + gp + (int64_t)gj * ldb : B + gj + (int64_t)gp * ldb;
                 v = ld_op(src, OPB);
             }
             rb[e] = v;
@@ -354,20 +362,45 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
 #pragma unroll
         for (int kc = 0; kc < BB_K / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
-            double2 a[4], b[2];
+            double2 a[4];
+            TB b[2];
 #pragma unroll
             for (int r = 0; r < 4; ++r) a[r] = sA[buf][pr][wm * 64 + r * 16 + (lane & 15)];
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = sB[buf][pr][wn * 32 + c * 16 + (lane & 15)];
+            if constexpr (GAUSS3) {
+                double as[4], bs[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < 4; ++r) as[r] = a[r].x + a[r].y;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
-                    accR[r][c] = mfma16(-a[r].y, b[c].y, accR[r][c]);
-                    accI[r][c] = mfma16(a[r].x, b[c].y, accI[r][c]);
-                    accI[r][c] = mfma16(a[r].y, b[c].x, accI[r][c]);
-                }
+                for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
+                        accI[r][c] = mfma16(a[r].y, b[c].y, accI[r][c]);
+                        acc3[r][c] = mfma16(as[r], bs[c], acc3[r][c]);
+                    }
+            } else if constexpr (BCPLX) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
+                        accR[r][c] = mfma16(-a[r].y, b[c].y, accR[r][c]);
+                        accI[r][c] = mfma16(a[r].x, b[c].y, accI[r][c]);
+                        accI[r][c] = mfma16(a[r].y, b[c].x, accI[r][c]);
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        accR[r][c] = mfma16(a[r].x, b[c], accR[r][c]);
+                        accI[r][c] = mfma16(a[r].y, b[c], accI[r][c]);
+                    }
+            }
         }
     };
     // slice i in buffer i & 1; one barrier per slice: every wavefront has finished
@@ -397,7 +430,9 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                 const int gi = row0 + wm * 64 + r * 16 + acc_row(0.0, lane, v);
                 const int gj = col0 + wn * 32 + c * 16 + (lane & 15);
                 if (gi >= m || gj >= n) continue;
-                const double2 acc = make_double2(accR[r][c][v], accI[r][c][v]);
+                const double2 acc = GAUSS3 ? make_double2(accR[r][c][v] - accI[r][c][v],
+                                                         acc3[r][c][v] - accR[r][c][v] - accI[r][c][v])
+                                          : make_double2(accR[r][c][v], accI[r][c][v]);
                 if (part) {
                     part[(int64_t)blockIdx.z * m * n + gi + (int64_t)gj * m] = acc;
                 } else {
@@ -557,7 +592,7 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
         KScope _ks(c, c.gemm_tag ? c.gemm_tag : (std::is_same<T, float2>::value ? "gemm_c64" : "gemm"));
         if constexpr (big_ok<T, TA>()) {
             if (big) {
-                hipLaunchKernelGGL((gemm_big_kernel<TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
+                hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
                                    alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
             } else {
                 hipLaunchKernelGGL((gemm_kernel<T, TA, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
@@ -609,6 +644,55 @@ void zgemm_a32(Ctx& c, int opa, int opb, int m, int n, int k, double2 alpha, con
                     "banded complex64 GEMM: square symmetric operand, no conjugate");
     }
     gemm_any<double2, float2>(c, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, band);
+}
+
+// C = alpha A B + beta C (no transposes) with a complex A (complex128, or complex64
+// with an optional complex128 band) and a real B, on the 128 x 64 tile kernel;
+// false (nothing launched) when the output is smaller than one tile.
+template <typename TA>
+static bool gemm_real_b(Ctx& c, int m, int n, int k, double2 alpha, const TA* A, int64_t lda, const double* B,
+                        int64_t ldb, double2 beta, double2* C, int64_t ldc, const BandA& bd) {
+    if (m < BB_M || n < BB_N || k <= 0) return false;
+    const int gm = (m + BB_M - 1) / BB_M, gn = (n + BB_N - 1) / BB_N;
+    int nz = 1;
+    if (4 * gm * gn < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + 4 * gm * gn - 1) / (4 * gm * gn), (k + 255) / 256));
+    nz = std::min(nz, 64);
+    int kchunk = (k + nz - 1) / nz;
+    kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
+    nz = (k + kchunk - 1) / kchunk;
+    double2* part = nullptr;
+    if (nz > 1) part = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)nz * m * n));
+    {
+        KScope _ks(c, c.gemm_tag ? c.gemm_tag : "gemm");
+        hipLaunchKernelGGL((gemm_big_kernel<TA, double, OP_N, OP_N>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n,
+                           k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    if (part) {
+        const int64_t tot = (int64_t)m * n;
+        {
+            KScope _ks(c, "gemm_splitk_reduce");
+            hipLaunchKernelGGL(splitk_reduce_kernel<double2>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                               c.stream, m, n, nz, alpha, part, beta, C, ldc);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        c.dfree(part);
+    }
+    return true;
+}
+
+bool zgemm_real_b(Ctx& c, int m, int n, int k, double2 alpha, const double2* A, int64_t lda, const double* B,
+                  int64_t ldb, double2 beta, double2* C, int64_t ldc) {
+    return gemm_real_b<double2>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, BandA());
+}
+
+bool zgemm_a32_real_b(Ctx& c, int m, int n, int k, double2 alpha, const float2* A, int64_t lda, const double* B,
+                      int64_t ldb, double2 beta, double2* C, int64_t ldc, const BandA& band) {
+    if (band.nb) {
+        FDS_REQUIRE(m == band.n && k == band.n && band.w >= 0 && 2 * band.w < band.n, FDS_ERR_ARG,
+                    "banded complex64 GEMM: square symmetric operand");
+    }
+    return gemm_real_b<float2>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, band);
 }
 
 int autotune_entries(Ctx& c, int cap, char* keys, int* values) {

@@ -44,7 +44,10 @@ static void op_gemm(Op& op, int which, int opa, int64_t ncols, double2 alpha, co
                     double2* Y) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
-    GemmTag tag(c, opa == OP_N ? "gemm_op_n" : "gemm_op_t");   // n x n operator products
+    // S and N are stored exactly symmetric (mirror writes of one value, symmetrised
+    // near band), so their transposed products are the untransposed ones
+    if (which != 2 && opa == OP_T) opa = OP_N;
+    GemmTag tag(c, opa == OP_N ? "gemm_op" : "gemm_op_t");   // n x n operator products
     if (op.prec == FDS_FP32) {
         const float2* M = which == 0 ? op.S32 : (which == 1 ? op.N32 : op.D32);
         BandA band;
@@ -59,6 +62,32 @@ static void op_gemm(Op& op, int which, int opa, int64_t ncols, double2 alpha, co
     }
     const double2* M = which == 0 ? op.S : (which == 1 ? op.Nm : op.D);
     zgemm(c, opa, OP_N, n, (int)ncols, n, alpha, M, n, X, n, beta, Y, n);
+}
+
+// Y = alpha M V_g + beta Y for a stored operator M (column-major view, OP_N) and
+// the real filter basis V_g (n x n_eff): the complex-by-real kernel (half the
+// MFMAs of a complex product) when the shape allows it, else the complex copy.
+static void op_gemm_vg(Op& op, int which, double2 alpha, double2 beta, double2* Y) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, ne = op.n_eff;
+    bool done;
+    {
+        GemmTag tag(c, "gemm_op_vg");
+        if (op.prec == FDS_FP32) {
+            const float2* M = which == 0 ? op.S32 : (which == 1 ? op.N32 : op.D32);
+            BandA band;
+            if (which == 1) {
+                band.nb = op.Nband;
+                band.w = op.nbw;
+                band.n = n;
+            }
+            done = zgemm_a32_real_b(c, n, ne, n, alpha, M, n, op.Vg, n, beta, Y, n, band);
+        } else {
+            const double2* M = which == 0 ? op.S : (which == 1 ? op.Nm : op.D);
+            done = zgemm_real_b(c, n, ne, n, alpha, M, n, op.Vg, n, beta, Y, n);
+        }
+    }
+    if (!done) op_gemm(op, which, OP_N, ne, alpha, op.Vgc, beta, Y);
 }
 
 // per-column sqrt(x^H G x)
@@ -204,16 +233,16 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
     if (form == FDS_EFIE || form == FDS_CFIE) {
         // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
         double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
-        op_gemm(op, 0, OP_N, ne, kOne, op.Vgc, kZero, X);
+        op_gemm_vg(op, 0, kOne, kZero, X);
         gram_inv(op, X, ne, X);
         op_gemm(op, 1, OP_N, ne, kOne, X, kZero, op.Bt);
         gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X, n);
         axpby(c, kOne, X, kOne, op.Bt, (int64_t)n * ne);
         c.dfree(X);
         if (form == FDS_CFIE)   // + alpha * (-D^T Vg)
-            op_gemm(op, 2, OP_N, ne, make_double2(-alpha, 0.0), op.Vgc, kOne, op.Bt);
+            op_gemm_vg(op, 2, make_double2(-alpha, 0.0), kOne, op.Bt);
     } else {
-        op_gemm(op, 2, OP_N, ne, make_double2(-1.0, 0.0), op.Vgc, kZero, op.Bt);
+        op_gemm_vg(op, 2, make_double2(-1.0, 0.0), kZero, op.Bt);
     }
     op.stage = Stage::Filtered;
     op.rank = 0;

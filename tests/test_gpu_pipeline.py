@@ -164,3 +164,40 @@ def test_state_machine_errors(ctx):
         B.fds_solve(op, f, None)
     assert e.value.name == "FDS_ERR_STATE"
     op.close()
+
+
+@pytest.mark.parametrize("r,kind", [(1, "random"), (7, "zero_lead"), (255, "second_kind"), (300, "zero_lead"),
+                                    (64, "permuted"), (33, "random")])
+def test_dense_inverse(ctx, r, kind):
+    """The Woodbury-core inverse: the unpivoted fast path (second-kind matrices) and the
+    partial-pivoting fallback (a zero leading pivot, a permuted identity-like matrix)."""
+    _say(f"case: dense inverse r={r} {kind}")
+    rs = np.random.default_rng(r + len(kind))
+    R = rs.standard_normal((r, r)) + 1j * rs.standard_normal((r, r))
+    if kind == "second_kind":
+        A = np.eye(r) + 0.3 * R / np.sqrt(r)
+    elif kind == "zero_lead":
+        A = R.copy()
+        A[0, 0] = 0.0
+    elif kind == "permuted":
+        A = (np.eye(r) + 0.05 * R / np.sqrt(r))[rs.permutation(r)]
+    else:
+        A = R
+    At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    X, (pmin, amax) = B.fds_zinv(ctx, At)
+    Xn = X.cpu().numpy().T
+    ref = np.linalg.inv(A)
+    cond = np.linalg.cond(A)
+    assert np.abs(A @ Xn - np.eye(r)).max() <= 1e-13 * cond * max(1, r / 16)
+    assert np.abs(Xn - ref).max() <= 1e-14 * cond * r * np.abs(ref).max()
+    assert pmin >= 64 * EPS * amax
+    assert torch.equal(At, torch.from_numpy(np.ascontiguousarray(A.T)).cuda())   # input untouched
+
+
+def test_dense_inverse_singular(ctx):
+    _say("case: dense inverse singular")
+    rs = np.random.default_rng(5)
+    A = rs.standard_normal((20, 20)) + 1j * rs.standard_normal((20, 20))
+    A[:, 7] = A[:, 3]
+    _, (pmin, amax) = B.fds_zinv(ctx, torch.from_numpy(np.ascontiguousarray(A.T)).cuda())
+    assert pmin < 64 * EPS * amax
