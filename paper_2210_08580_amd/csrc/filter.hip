@@ -864,7 +864,13 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // eigenvalues start .. start+nw-1 (a few beyond the cut for the cluster guard)
     std::vector<double> lam;
     int nw = 0;
-    int extra = 8;
+    // One workgroup per eigenvalue, each alone on a compute unit for the whole
+    // latency-bound recurrence: two eigenvalues past the cut guard it against a
+    // split cluster, one when the second would put a workgroup past a multiple
+    // of the CU count (a wider cluster at the cut is found and bisected again).
+    int ncu = 0;
+    FDS_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+    int extra = (ncu > 0 && (want + 2) % ncu == 1) ? 1 : 2;
     // Tight brackets: the P1 pencil is the Rayleigh-Ritz discretisation of -d^2/ds^2
     // on the polygon of perimeter Ph, whose eigenvalues are (2 pi k/Ph)^2 (k = 0, 1, 1,
     // 2, 2, ...), so eigenvalue index idx lies above lam_c = (2 pi ceil(idx/2)/Ph)^2, and

@@ -217,23 +217,32 @@ template void gram_band_apply<double2>(Ctx&, const double*, int, const double2*,
 // ============================================================ Chebyshev G^{p/2}
 // f(x) = x^{p/2} on [lo, hi] expanded in Chebyshev polynomials of
 // t = (2x - lo - hi)/(hi - lo); coefficients by interpolation at Chebyshev points.
+// The branch point x = 0 sits at t0 = -(hi + lo)/(hi - lo), so f is analytic
+// inside the Bernstein ellipse of parameter rho = |t0| + sqrt(t0^2 - 1) and its
+// coefficients decay like rho^{-k} (Trefethen, Approximation Theory and
+// Approximation Practice, thm. 8.1). The degree is the one at which that
+// geometric tail falls below 1e-17 relative; rounding puts a floor near 1e-16
+// under the computed coefficients, so a test on their size would never stop.
 std::vector<double> cheb_coeffs(int p, double lo, double hi) {
-    const int M = 400;
+    FDS_REQUIRE(lo > 0.0 && hi > lo, FDS_ERR_STATE, "Gram spectrum bounds must satisfy 0 < lo < hi");
+    const double t0 = (hi + lo) / (hi - lo);
+    const double rho = t0 + std::sqrt(t0 * t0 - 1.0);
+    const double lr = std::log(rho);
+    const double need = (std::log(1e17) - std::log1p(-1.0 / rho)) / lr + 4.0;
+    const int deg = (int)std::min(4000.0, std::ceil(need));
+    const int M = deg + 9;
     std::vector<double> fv(M), a(M);
     for (int j = 0; j < M; ++j) {
         const double t = std::cos(kPiHost * (j + 0.5) / M);
         const double x = 0.5 * (hi + lo) + 0.5 * (hi - lo) * t;
         fv[j] = std::pow(x, 0.5 * p);
     }
-    for (int i = 0; i < M; ++i) {
+    for (int i = 0; i <= deg; ++i) {
         double s = 0.0;
         for (int j = 0; j < M; ++j) s += fv[j] * std::cos(kPiHost * i * (j + 0.5) / M);
         a[i] = s * 2.0 / M;
     }
     a[0] *= 0.5;
-    int deg = M - 1;
-    const double a0 = std::fabs(a[0]);
-    while (deg > 1 && std::fabs(a[deg]) < 1e-18 * a0 && std::fabs(a[deg - 1]) < 1e-18 * a0) --deg;
     a.resize(deg + 1);
     return a;
 }

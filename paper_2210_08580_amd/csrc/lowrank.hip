@@ -27,17 +27,21 @@
 namespace fds {
 
 static constexpr int LR_BS = 256;
+// Householder steps stream whole columns of a tall block through one workgroup
+// each; 1024 threads with four rows in flight per thread keep enough loads
+// outstanding for a single CU to run near its share of the memory bandwidth.
+static constexpr int HH_BS = 1024;
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// Sum over the workgroup of up to 4 values (LR_BS threads). sh: 4 * (LR_BS/64) doubles.
-template <int K>
+// Sum over the workgroup of up to 4 values (BS threads). sh: 4 * (BS/64) doubles.
+template <int K, int BS = LR_BS>
 __device__ __forceinline__ void block_sum_k(double (&v)[K], double* sh) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int NW = LR_BS / 64;
+    constexpr int NW = BS / 64;
 #pragma unroll
     for (int t = 0; t < K; ++t) v[t] = wave_sum(v[t]);
     __syncthreads();
@@ -90,9 +94,9 @@ void sketch(Ctx& c, uint64_t seed, int64_t n, int ell, double2* Om) {
 // H_{j-1}^H (a <- a - conj(tau) v (v^H a)) to its column over rows j-1..M-1;
 // the owner of column j then builds H_j from rows j..M-1. Every thread walks
 // the same rows in every loop, so it only re-reads what it wrote itself.
-__global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A, int64_t lda, int M, int j,
+__global__ __launch_bounds__(HH_BS) void hh_step_kernel(double2* __restrict__ A, int64_t lda, int M, int j,
                                                         double2* __restrict__ tau) {
-    __shared__ double sh[4 * (LR_BS / 64)];
+    __shared__ double sh[4 * (HH_BS / 64)];
     __shared__ double2 alpha_sh;
     const int c = j + blockIdx.x;
     const int tid = threadIdx.x;
@@ -103,15 +107,17 @@ __global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A,
         const double2* v = A + (int64_t)(j - 1) * lda;
         const double2 tj = tau[j - 1];
         double s[2] = {0.0, 0.0};
-        for (int r = base + tid; r < M; r += LR_BS) {
+#pragma unroll 4
+        for (int r = base + tid; r < M; r += HH_BS) {
             const double2 vr = r == j - 1 ? make_double2(1.0, 0.0) : v[r];
             const double2 ar = a[r];
             s[0] += vr.x * ar.x + vr.y * ar.y;     // conj(v) a
             s[1] += vr.x * ar.y - vr.y * ar.x;
         }
-        block_sum_k<2>(s, sh);
+        block_sum_k<2, HH_BS>(s, sh);
         const double2 f = cmul(cconj(tj), make_double2(s[0], s[1]));
-        for (int r = base + tid; r < M; r += LR_BS) {
+#pragma unroll 4
+        for (int r = base + tid; r < M; r += HH_BS) {
             const double2 vr = r == j - 1 ? make_double2(1.0, 0.0) : v[r];
             const double2 ar = csub(a[r], cmul(vr, f));
             a[r] = ar;
@@ -121,7 +127,8 @@ __global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A,
             }
         }
     } else {
-        for (int r = tid; r < M; r += LR_BS) {
+#pragma unroll 4
+        for (int r = tid; r < M; r += HH_BS) {
             const double2 ar = a[r];
             if (r == 0) alpha_sh = ar;
             else nrm2 += ar.x * ar.x + ar.y * ar.y;
@@ -129,7 +136,7 @@ __global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A,
     }
     if (c != j) return;
     double t[1] = {nrm2};
-    block_sum_k<1>(t, sh);            // contains a barrier: alpha_sh is visible afterwards
+    block_sum_k<1, HH_BS>(t, sh);            // contains a barrier: alpha_sh is visible afterwards
     const double2 alpha = alpha_sh;
     nrm2 = t[0];
     if (nrm2 == 0.0 && alpha.y == 0.0) {
@@ -141,7 +148,8 @@ __global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A,
     const double2 d = make_double2(alpha.x - beta, alpha.y);
     const double dd = d.x * d.x + d.y * d.y;
     const double2 sc = make_double2(d.x / dd, -d.y / dd);   // 1 / (alpha - beta)
-    for (int r = base + tid; r < M; r += LR_BS) {
+#pragma unroll 4
+    for (int r = base + tid; r < M; r += HH_BS) {
         if (r > j) a[r] = cmul(a[r], sc);
         else if (r == j) a[r] = make_double2(beta, 0.0);
     }
@@ -149,10 +157,10 @@ __global__ __launch_bounds__(LR_BS) void hh_step_kernel(double2* __restrict__ A,
 }
 
 // Q <- H_j Q on columns j..m-1 (rows j..M-1), Q initially [I; 0].
-__global__ __launch_bounds__(LR_BS) void hh_formq_kernel(const double2* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(HH_BS) void hh_formq_kernel(const double2* __restrict__ A, int64_t lda,
                                                          const double2* __restrict__ tau, int M, int j,
                                                          double2* __restrict__ Q, int64_t ldq) {
-    __shared__ double sh[4 * (LR_BS / 64)];
+    __shared__ double sh[4 * (HH_BS / 64)];
     const double2 tj = tau[j];
     if (tj.x == 0.0 && tj.y == 0.0) return;
     const int c = j + blockIdx.x;
@@ -160,15 +168,17 @@ __global__ __launch_bounds__(LR_BS) void hh_formq_kernel(const double2* __restri
     const double2* v = A + (int64_t)j * lda;
     double2* q = Q + (int64_t)c * ldq;
     double s[2] = {0.0, 0.0};
-    for (int r = j + tid; r < M; r += LR_BS) {
+#pragma unroll 4
+    for (int r = j + tid; r < M; r += HH_BS) {
         const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
         const double2 qr = q[r];
         s[0] += vr.x * qr.x + vr.y * qr.y;
         s[1] += vr.x * qr.y - vr.y * qr.x;
     }
-    block_sum_k<2>(s, sh);
+    block_sum_k<2, HH_BS>(s, sh);
     const double2 f = cmul(tj, make_double2(s[0], s[1]));
-    for (int r = j + tid; r < M; r += LR_BS) {
+#pragma unroll 4
+    for (int r = j + tid; r < M; r += HH_BS) {
         const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
         q[r] = csub(q[r], cmul(vr, f));
     }
@@ -197,7 +207,7 @@ void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) 
         KScope _ks(c, "qr_householder");
         for (int j = 0; j < m; ++j) {
             const unsigned g = j == 0 ? 1u : (unsigned)(m - j);
-            hipLaunchKernelGGL(hh_step_kernel, dim3(g), dim3(LR_BS), 0, c.stream, A, (int64_t)M, M, j, tau);
+            hipLaunchKernelGGL(hh_step_kernel, dim3(g), dim3(HH_BS), 0, c.stream, A, (int64_t)M, M, j, tau);
         }
     }
     FDS_HIP_TRY(hipGetLastError());
@@ -207,7 +217,7 @@ void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) 
         hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)M * m, 256)), dim3(256), 0, c.stream, Q, (int64_t)M, M,
                            m);
         for (int j = m - 1; j >= 0; --j)
-            hipLaunchKernelGGL(hh_formq_kernel, dim3((unsigned)(m - j)), dim3(LR_BS), 0, c.stream, A, (int64_t)M,
+            hipLaunchKernelGGL(hh_formq_kernel, dim3((unsigned)(m - j)), dim3(HH_BS), 0, c.stream, A, (int64_t)M,
                                tau, M, j, Q, (int64_t)M);
     }
     FDS_HIP_TRY(hipGetLastError());

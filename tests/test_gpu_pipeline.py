@@ -57,13 +57,30 @@ def _op_and_oracle(kind, n, k):
     return nodes, m
 
 
-def test_gram_powers_parity(ctx):
-    _say("case: apply_gram star n=400")
-    nodes, m = _op_and_oracle("star", 400, 4.0)
+def _graded_circle(n, a):
+    """Unit circle with nodes at t = s + a sin s, s uniform: panel ratio (1 + a)/(1 - a)."""
+    s = 2.0 * np.pi * np.arange(n) / n
+    t = s + a * np.sin(s)
+    return np.stack([np.cos(t), np.sin(t)], axis=1)
+
+
+# (curve, n, grading): grading a > 0 replaces the curve by a graded circle whose
+# Gram spectrum is wide (panel ratio 3 and 99), so the Chebyshev degree is high.
+GRAM_CASES = [("star", 400, 0.0), ("ellipse", 512, 0.0), ("graded", 300, 0.5), ("graded", 256, 0.98)]
+
+
+@pytest.mark.parametrize("kind,n,a", GRAM_CASES)
+def test_gram_powers_parity(ctx, kind, n, a):
+    _say(f"case: apply_gram {kind} n={n} a={a}")
+    if kind == "graded":
+        nodes = _graded_circle(n, a)
+        m = geometry.mesh(nodes)
+    else:
+        nodes, m = _op_and_oracle(kind, n, 4.0)
     op = B.fds_assemble(ctx, torch.from_numpy(nodes).cuda(), 4.0)
     Gh, Gmh, Gi = formulation.gram_powers(*assembly.gram(m))
     rs = np.random.default_rng(2)
-    X = _crand(rs, (5, 400))
+    X = _crand(rs, (5, n))
     for p, R in ((-2, Gi), (-1, Gmh), (1, Gh)):
         t = torch.from_numpy(X.copy()).cuda()
         B.fds_apply_gram(op, p, t)
