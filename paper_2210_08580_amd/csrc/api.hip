@@ -53,6 +53,7 @@ Op::~Op() {
         ctx->dfree(U);
         ctx->dfree(W);
     }
+    if (ev_mesh) (void)hipEventDestroy(ev_mesh);
 }
 
 template <typename F>
@@ -142,6 +143,11 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
     return guarded([&] {
         if (!ctx) return;
         (void)hipStreamSynchronize(ctx->impl.stream);
+        if (ctx->impl.side) {
+            (void)hipStreamSynchronize(ctx->impl.side);
+            (void)hipStreamDestroy(ctx->impl.side);
+            ctx->impl.side = nullptr;
+        }
         resolve_profile(ctx->impl);
         ctx->impl.dfree(ctx->impl.hk_tab);
         ctx->impl.dfree(ctx->impl.hk_tab32);
@@ -340,6 +346,9 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
         FDS_HIP_TRY(hipMemcpyAsync(op.nodes, nodes, 2 * nd, hipMemcpyDeviceToDevice, c.stream));
         gauss_legendre_01(8, op.rule.xi, op.rule.w);
         launch_geometry(op);
+        FDS_HIP_TRY(hipEventCreateWithFlags(&op.ev_mesh, hipEventDisableTiming));
+        FDS_HIP_TRY(hipEventRecord(op.ev_mesh, c.stream));
+        op.ev_mesh_fresh = true;
     } catch (...) {
         delete o;
         throw;

@@ -55,6 +55,7 @@ struct Ctx {
     std::vector<ProfRec> pending;                         // recorded, not yet resolved
     std::map<std::string, std::pair<double, int64_t>> acc;  // name -> (total ms, launches)
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;   // non-blocking, default priority: work that only needs the mesh
     fds_allocator alloc{};
     bool has_alloc = false;
     const char* gemm_tag = nullptr;            // profiling name of GEMM launches (nullptr: "gemm")
@@ -87,6 +88,38 @@ struct KScope {
     }
     KScope(const KScope&) = delete;
     KScope& operator=(const KScope&) = delete;
+};
+
+// Moves the context onto its side stream for the enclosed work, which is
+// ordered after the event `after` (recorded on the main stream); on exit the
+// main stream is ordered after everything the enclosed work launched. Every
+// launch, copy, allocation and timing made through the context in between goes
+// to the side stream, so the main stream's queued kernels keep running beside it.
+struct SideStream {
+    Ctx& c;
+    hipStream_t main;
+    SideStream(Ctx& ctx, hipEvent_t after) : c(ctx), main(ctx.stream) {
+        if (!c.side && hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) {
+            c.side = nullptr;
+            throw Error{FDS_ERR_HIP, "hipStreamCreateWithFlags failed"};
+        }
+        if (hipStreamWaitEvent(c.side, after, 0) != hipSuccess)
+            throw Error{FDS_ERR_HIP, "hipStreamWaitEvent failed"};
+        c.stream = c.side;
+    }
+    ~SideStream() {
+        c.stream = main;
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess && hipEventRecord(e, c.side) == hipSuccess &&
+            hipStreamWaitEvent(main, e, 0) == hipSuccess) {
+            (void)hipEventDestroy(e);
+            return;
+        }
+        if (e) (void)hipEventDestroy(e);
+        (void)hipStreamSynchronize(c.side);
+    }
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
 };
 
 // Sets the profiling name of the GEMM launches made during its lifetime.
@@ -123,6 +156,10 @@ struct Op {
     double* l_diag = nullptr;     // Laplacian diag / off
     double* l_off = nullptr;
     GaussRule8 rule{};
+    // recorded on the main stream once the mesh arrays above are built; the first
+    // filter call orders its eigensolver after it alone, not after the dense assembly
+    hipEvent_t ev_mesh = nullptr;
+    bool ev_mesh_fresh = false;
     // dense operators (device, row-major): complex128, or complex64 when prec == FDS_FP32
     int prec = FDS_FP64;
     double2* S = nullptr;

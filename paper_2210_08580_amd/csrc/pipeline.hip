@@ -212,8 +212,18 @@ const double* filter_basis_view(Op& op) {
 static void filter_prepare(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
-    ensure_gram_factor(op);
-    compute_filter_basis(op, n_modes, keep_null, cluster_rtol);
+    // The eigensolver and the Gram factor need only the mesh: right after the
+    // assembly they run on the side stream beside the still-running dense
+    // assembly kernels (their chains are latency-bound and leave most of the
+    // chip idle); a later call orders them after all earlier work instead.
+    if (!op.ev_mesh) FDS_HIP_TRY(hipEventCreateWithFlags(&op.ev_mesh, hipEventDisableTiming));
+    if (!op.ev_mesh_fresh) FDS_HIP_TRY(hipEventRecord(op.ev_mesh, c.stream));
+    op.ev_mesh_fresh = false;
+    {
+        SideStream side(c, op.ev_mesh);
+        ensure_gram_factor(op);
+        compute_filter_basis(op, n_modes, keep_null, cluster_rtol);
+    }
     const int ne = op.n_eff;
     op.form = form;
     op.alpha = alpha;
