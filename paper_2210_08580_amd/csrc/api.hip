@@ -47,7 +47,7 @@ void Ctx::dfree(void* p) {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
-                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv};
+                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
         ctx->dfree(U);
@@ -302,11 +302,13 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
     FDS_HIP_TRY(hipMemcpyAsync(hn.data(), nodes, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c.stream));
     FDS_HIP_TRY(hipStreamSynchronize(c.stream));
     double area = 0.0;
+    std::vector<double> hh(n);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t j = (i + 1) % n;
         const double x0 = hn[2 * i], y0 = hn[2 * i + 1], x1 = hn[2 * j], y1 = hn[2 * j + 1];
         FDS_REQUIRE(std::isfinite(x0) && std::isfinite(y0), FDS_ERR_ARG, "non-finite node");
-        FDS_REQUIRE(std::hypot(x1 - x0, y1 - y0) > 0.0, FDS_ERR_ARG, "zero-length panel");
+        hh[i] = std::hypot(x1 - x0, y1 - y0);
+        FDS_REQUIRE(hh[i] > 0.0, FDS_ERR_ARG, "zero-length panel");
         area += x0 * y1 - x1 * y0;
     }
     FDS_REQUIRE(area > 0.0, FDS_ERR_ARG, "nodes must be counter-clockwise");
@@ -317,6 +319,7 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
     op.n = n;
     op.k = k;
     op.prec = opts ? opts->precision : FDS_FP64;
+    op.h_host = std::move(hh);
     try {
         const size_t nd = sizeof(double) * n;
         op.nodes = (double*)c.dmalloc(2 * nd);
@@ -531,7 +534,14 @@ fds_status fds_op_filter_basis(fds_op op, const double** Vn) {
 fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_t* count) {
     return guarded([&] {
         FDS_REQUIRE(op && out && cap >= 0, FDS_ERR_ARG, "bad argument");
-        const auto& v = op->impl.filt_lam;
+        Op& o = op->impl;
+        if (o.lam_dev_n > 0) {
+            FDS_HIP_TRY(hipMemcpyAsync(o.filt_lam.data(), o.lam_dev, sizeof(double) * o.lam_dev_n,
+                                       hipMemcpyDeviceToHost, o.ctx->stream));
+            FDS_HIP_TRY(hipStreamSynchronize(o.ctx->stream));
+            o.lam_dev_n = 0;
+        }
+        const auto& v = o.filt_lam;
         const int32_t m = (int32_t)std::min<size_t>(v.size(), (size_t)cap);
         for (int32_t i = 0; i < m; ++i) out[i] = v[i];
         if (count) *count = m;

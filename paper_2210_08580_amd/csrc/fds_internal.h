@@ -155,6 +155,8 @@ struct Op {
     double* g_off = nullptr;
     double* l_diag = nullptr;     // Laplacian diag / off
     double* l_off = nullptr;
+    std::vector<double> h_host;   // panel lengths computed on the host from the caller's nodes: the
+                                  // mesh bounds (Gershgorin, perimeter, h_max) need no device copy
     GaussRule8 rule{};
     // recorded on the main stream once the mesh arrays above are built; the first
     // filter call orders its eigensolver after it alone, not after the dense assembly
@@ -177,6 +179,8 @@ struct Op {
     double beta = 0.25;
     int32_t n_eff = 0;
     std::vector<double> filt_lam; // pencil eigenvalues of the last filter call (host)
+    double* lam_dev = nullptr;    // Rayleigh-Ritz values of the kept modes, copied into filt_lam
+    int32_t lam_dev_n = 0;        //   on first read (0: filt_lam is current)
     double* Vn = nullptr;         // [n_eff][n]  orthonormal eigenvectors of G^-1/2 L G^-1/2
     double* Vg = nullptr;         // [n_eff][n]  G^-1/2 Vn (G-orthonormal generalised eigenvectors)
     double2* Vgc = nullptr;       // [n_eff][n]  V_g as complex128
@@ -205,6 +209,8 @@ void launch_rhs_planewave(Op& op, const double* angles, const double2* amps, int
 void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out);
 void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out);
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
+// pipeline.hip: Gershgorin interval of the Gram matrix from host panel lengths
+void gram_gershgorin(const std::vector<double>& h, double& lo, double& hi);
 // assemble.hip
 void launch_assemble(Op& op);
 void launch_assemble_batch(Ctx& c, Op* const* ops, int nops);

@@ -246,8 +246,7 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
 // (lo0[i], hi0[i]) and falls back to the global bracket when its endpoint counts
 // do not enclose the index.
 __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, const SturmStep* __restrict__ st,
-                                                                      const double* __restrict__ lo0,
-                                                                      const double* __restrict__ hi0, double glo,
+                                                                      double l1c, double hfac, double glo,
                                                                       double ghi, double rtol, double atol,
                                                                       int first, int nw, double* __restrict__ lam) {
     __shared__ unsigned long long mk[BS_WAVES];
@@ -258,7 +257,18 @@ __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int idx = first + i;
     const int NS = 64 * BS_WAVES;
-    double lo = lo0[i], hi = hi0[i];
+    // tight bracket: eigenvalue idx of the P1 pencil lies above lc = l1c ceil(idx/2)^2 and
+    // below lc (1 + hfac lc) (hfac = h_max^2 / 6), with small safety margins
+    double lo, hi;
+    if (idx == 0) {
+        lo = -1e-6 * l1c;
+        hi = 0.5 * l1c;
+    } else {
+        const double kk = (double)((idx + 1) / 2);
+        const double lc = l1c * kk * kk;
+        lo = lc * (1.0 - 1e-9);
+        hi = lc * (1.0 + hfac * lc) * (1.0 + 1e-6) + 1e-6 * l1c;
+    }
     if (!(hi > lo)) {
         lo = glo;
         hi = ghi;
@@ -341,10 +351,31 @@ __global__ void fold_bands_kernel(Pencil P, double* __restrict__ Lb, double* __r
 // solved with partial pivoting, then each half back-substitutes outward.
 // One thread per (eigenvalue, half); the chains are n/2 long instead of n.
 //
-// Factor record per (half, step j, eigenvalue), FS doubles: l1, l2, pivot choice
-// (0, 1, 2 as a double), 1/u_jj, u_{j,j+1} .. u_{j,j+4} (so that the forward
-// sweep reads the first 32 bytes and the back substitution the last 48).
-constexpr int FS = 8;
+// Factor records, per half, as separate arrays indexed [step j][eigenvalue i]
+// (each wave's load of one field is one contiguous 512 or 1024-byte run):
+// multipliers (l1, l2), (u_{j,j+1}, u_{j,j+2}), (u_{j,j+3}, u_{j,j+4}), (1/u_jj, z_j)
+// with z the forward-eliminated right-hand side of the current solve, and the
+// pivot choice (0, 1, 2). M = steps x eigenvalues entries per array.
+struct FacView {
+    double2* L;
+    double2* U12;
+    double2* U34;
+    double2* IZ;
+    int* P;
+};
+
+__host__ __device__ inline size_t fac_half_bytes(int64_t M) { return (size_t)M * (4 * 16 + 4); }
+
+__device__ __forceinline__ FacView fac_view(char* base, int64_t M, int h) {
+    char* b = base + (size_t)h * fac_half_bytes(M);
+    FacView f;
+    f.L = reinterpret_cast<double2*>(b);
+    f.U12 = reinterpret_cast<double2*>(b + (size_t)M * 16);
+    f.U34 = reinterpret_cast<double2*>(b + (size_t)M * 32);
+    f.IZ = reinterpret_cast<double2*>(b + (size_t)M * 48);
+    f.P = reinterpret_cast<int*>(b + (size_t)M * 64);
+    return f;
+}
 
 __device__ __forceinline__ int trow(int h, int j, int n) { return h == 0 ? j : n - 1 - j; }
 
@@ -370,14 +401,14 @@ __device__ __forceinline__ double start_value(int i, int node) {
 
 // Factorisation of both halves (blockIdx.y = half) with the forward elimination
 // of the pseudo-random right-hand side (the first inverse-iteration step): z into
-// Z (node-major), the reduced interface rows and their right-hand sides into IF
+// the factor records, the reduced interface rows and their right-hand sides into IF
 // ([half][10][nw]: row mt (or mt+3) coefficients, row mt+1 (or mt+2)
 // coefficients, two right-hand sides).
 __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb, const double* __restrict__ Lb,
                                                           const double* __restrict__ Gb,
                                                           const double* __restrict__ sig, int nw, double pivmin,
-                                                          double* __restrict__ fac, int64_t hstride,
-                                                          double* __restrict__ Z, double* __restrict__ IF) {
+                                                          char* __restrict__ fac, int64_t M,
+                                                          double* __restrict__ IF) {
     const int h = blockIdx.y;
     const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
@@ -385,7 +416,7 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
     const int i = min(i0, nw - 1);          // idle lanes repeat the last eigenvalue, store nothing
     const bool act = i0 < nw;
     const double s = sig[i];
-    double* __restrict__ F = fac + h * hstride;
+    const FacView F = fac_view(fac, M, h);
     auto band = [&](const double* B, int t, int j) {   // entry t of row j of A (h = 0) or A' (h = 1)
         return h == 0 ? B[(int64_t)t * n + j] : B[(int64_t)(4 - t) * n + (n - 1 - j)];
     };
@@ -450,12 +481,12 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
             y1 -= l1 * y0;
             y2 -= l2 * y0;
             if (act) {
-                double2* f = reinterpret_cast<double2*>(F + ((int64_t)j * nw + i) * FS);
-                f[0] = make_double2(l1, l2);
-                f[1] = make_double2((double)p, inv);
-                f[2] = make_double2(w0[1], w0[2]);
-                f[3] = make_double2(w0[3], w0[4]);
-                Z[(int64_t)node_of(trow(h, j, n), n) * nw + i] = y0;
+                const int64_t e = (int64_t)j * nw + i;
+                F.L[e] = make_double2(l1, l2);
+                F.P[e] = p;
+                F.IZ[e] = make_double2(inv, y0);
+                F.U12[e] = make_double2(w0[1], w0[2]);
+                F.U34[e] = make_double2(w0[3], w0[4]);
             }
             y0 = y1;
             y1 = y2;
@@ -543,22 +574,28 @@ __device__ __forceinline__ void interface_solve(const double* __restrict__ IF, i
     }
 }
 
-constexpr int IV_CH = 16;  // steps whose operands are loaded ahead of use
+// steps whose operands are in flight ahead of use (load chunks of the back
+// substitution, register ring of the forward elimination)
+constexpr int IV_DB = 16;
+constexpr int IV_DF = 15;
 
 // Interface solve, then back substitution U x = z of each half outward from the
-// interface (z and x node-major [n][nw]). Full chunks of IV_CH steps load all
-// their operands before the dependent chain.
+// interface (x node-major [n][nw]). Each wave runs one dependent chain per lane,
+// so only loads issued well ahead hide the memory latency: the operands of
+// IV_DB steps ((1/u_jj, z_j) and the four superdiagonal entries, three loads per
+// step, within the 63 outstanding memory operations a wave can track) are all
+// issued before the first of those steps runs.
 __global__ __launch_bounds__(64) void invit_back_kernel(int n, int mt, int mb, int nw,
-                                                        const double* __restrict__ fac, int64_t hstride,
-                                                        const double* __restrict__ Z, const double* __restrict__ IF,
-                                                        double pivmin, double* __restrict__ X) {
+                                                        char* __restrict__ fac, int64_t M,
+                                                        const double* __restrict__ IF, double pivmin,
+                                                        double* __restrict__ X) {
     const int h = blockIdx.y;
     const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 64 + lane;
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
-    const double* __restrict__ F = fac + h * hstride;
+    const FacView F = fac_view(fac, M, h);
     double xi[4];
     interface_solve(IF, nw, i, pivmin, xi);
     double x1, x2, x3, x4;   // x_{j+1} .. x_{j+4} in the half's own row order
@@ -575,110 +612,121 @@ __global__ __launch_bounds__(64) void invit_back_kernel(int n, int mt, int mb, i
             X[(int64_t)node_of(mt + 3, n) * nw + i] = xi[3];
         }
     }
-    // u[0] holds the reciprocal of the pivot; the terms of older unknowns are
-    // summed first so that the chain between steps is one FMA and one product
-    auto step = [&](int j, const double (&u)[5], double z) {
-        const double part = fma(-u[4], x4, fma(-u[3], x3, fma(-u[2], x2, z)));
-        const double v = fma(-u[1], x1, part) * u[0];
+    // the terms of older unknowns are summed first so that the chain between
+    // steps is one FMA and one product
+    auto step = [&](int j, double inv, double2 u12, double2 u34, double z) {
+        const double part = fma(-u34.y, x4, fma(-u34.x, x3, fma(-u12.y, x2, z)));
+        const double v = fma(-u12.x, x1, part) * inv;
         if (act) X[(int64_t)node_of(trow(h, j, n), n) * nw + i] = v;
         x4 = x3;
         x3 = x2;
         x2 = x1;
         x1 = v;
     };
-    auto load = [&](int j, double (&u)[5]) {
-        const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j * nw + i) * FS);
-        const double2 a = f[1], b = f[2], c = f[3];
-        u[0] = a.y;
-        u[1] = b.x;
-        u[2] = b.y;
-        u[3] = c.x;
-        u[4] = c.y;
-    };
-    int j0 = m - 1;
-    for (; j0 - (IV_CH - 1) >= 0; j0 -= IV_CH) {
-        double u[IV_CH][5], zz[IV_CH];
+    // chunks of IV_DB steps: all their loads are issued before the first step of
+    // the chunk runs
+    int j0 = m - 1;     // next step to run (descending)
+    for (; j0 - (IV_DB - 1) >= 0; j0 -= IV_DB) {
+        double2 riz[IV_DB], ru12[IV_DB], ru34[IV_DB];
 #pragma unroll
-        for (int q = 0; q < IV_CH; ++q) {
-            const int j = j0 - q;
-            load(j, u[q]);
-            zz[q] = Z[(int64_t)node_of(trow(h, j, n), n) * nw + i];
+        for (int q = 0; q < IV_DB; ++q) {
+            const int64_t e = (int64_t)(j0 - q) * nw + i;
+            riz[q] = F.IZ[e];
+            ru12[q] = F.U12[e];
+            ru34[q] = F.U34[e];
         }
 #pragma unroll
-        for (int q = 0; q < IV_CH; ++q) step(j0 - q, u[q], zz[q]);
+        for (int q = 0; q < IV_DB; ++q) step(j0 - q, riz[q].x, ru12[q], ru34[q], riz[q].y);
     }
     for (; j0 >= 0; --j0) {
-        double u[5];
-        load(j0, u);
-        step(j0, u, Z[(int64_t)node_of(trow(h, j0, n), n) * nw + i]);
+        const int64_t e = (int64_t)j0 * nw + i;
+        const double2 iz = F.IZ[e];
+        step(j0, iz.x, F.U12[e], F.U34[e], iz.y);
     }
 }
 
-// Forward elimination of W = G X (computed on the fly) for both halves, z into
-// Z, the interface right-hand sides into IF. The operands of IV_CH steps
-// (pivot choices, multipliers and the three entries of X that G x needs) are
-// loaded before any of them is used.
-__global__ __launch_bounds__(64) void invit_fwd_kernel(Pencil P, int mt, int mb, int nw,
-                                                       const double* __restrict__ fac, int64_t hstride,
-                                                       const double* __restrict__ X, double* __restrict__ Z,
-                                                       double* __restrict__ IF) {
+// W = G X for node-major X [n][nw] (the right-hand side of the second solve).
+__global__ void gx_nodemajor_kernel(Pencil P, int nw, const double* __restrict__ X, double* __restrict__ W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n;
+    if (t >= (int64_t)n * nw) return;
+    const int k = (int)(t / nw), i = (int)(t % nw);
+    const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
+    W[t] = P.gd[k] * X[(int64_t)k * nw + i] + P.go[km] * X[(int64_t)km * nw + i] +
+           P.go[k] * X[(int64_t)kp * nw + i];
+}
+
+// Forward elimination of W (node-major, G X) for both halves, z into the factor
+// records, the interface right-hand sides into IF. Step j works on the window
+// rows (y0, y1) and the entering row j + 2 of W; the multipliers, pivot choices and entering rows run IV_DF - 1
+// steps ahead in a register ring, as in the back substitution. Slot q holds the
+// operands of the next step j = q (mod IV_DF), and the entering row of step j - 1
+// stays in its slot until step j has used it, so no ring register is copied
+// while its load is in flight.
+__global__ __launch_bounds__(64) void invit_fwd_kernel(int n, int mt, int mb, int nw,
+                                                       char* __restrict__ fac, int64_t M,
+                                                       const double* __restrict__ WZ, double* __restrict__ IF) {
     const int h = blockIdx.y;
     const int m = h == 0 ? mt : mb;
     const int lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 64 + lane;
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
-    const int n = P.n;
-    const double* __restrict__ F = fac + h * hstride;
-    auto gx = [&](int k) {
-        const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-        return P.gd[k] * X[(int64_t)k * nw + i] + P.go[km] * X[(int64_t)km * nw + i] +
-               P.go[k] * X[(int64_t)kp * nw + i];
-    };
+    const FacView F = fac_view(fac, M, h);
+    double* __restrict__ izd = reinterpret_cast<double*>(F.IZ);   // z_j goes to the odd entries
     auto rnode = [&](int j) { return node_of(trow(h, j, n), n); };
-    double y0 = gx(rnode(0)), y1 = gx(rnode(1)), y2 = gx(rnode(2));
-    auto step = [&](int j, int p, double l1, double l2, double r) {
+    double y0 = WZ[(int64_t)rnode(0) * nw + i], y1 = WZ[(int64_t)rnode(1) * nw + i];
+    // one elimination step on the rows (y0, y1, a2): returns nothing, leaves the
+    // two reduced rows in (y0, y1)
+    auto step = [&](int j, int p, double2 l, double a2) {
         // row interchange as selects (an indexed form would go through scratch memory)
-        const double a0 = y0, a1 = y1, a2 = y2;
-        y0 = p == 1 ? a1 : (p == 2 ? a2 : a0);
-        y1 = p == 1 ? a0 : a1;
-        y2 = p == 2 ? a0 : a2;
-        y1 -= l1 * y0;
-        y2 -= l2 * y0;
-        if (act) Z[(int64_t)rnode(j) * nw + i] = y0;
-        y0 = y1;
-        y1 = y2;
-        y2 = r;
+        const double a0 = y0, a1 = y1;
+        const double u = p == 1 ? a1 : (p == 2 ? a2 : a0);
+        const double b1 = p == 1 ? a0 : a1;
+        const double b2 = p == 2 ? a0 : a2;
+        if (act) izd[2 * ((int64_t)j * nw + i) + 1] = u;
+        y0 = fma(-l.x, u, b1);
+        y1 = fma(-l.y, u, b2);
     };
+    int rp[IV_DF];
+    double2 rl[IV_DF];
+    double rr[IV_DF];
     // row j + 3 <= m + 2 <= n - 2 always exists
+    auto load = [&](int j, int q) {
+        const int64_t e = (int64_t)j * nw + i;
+        rl[q] = F.L[e];
+        rp[q] = F.P[e];
+        rr[q] = WZ[(int64_t)rnode(j + 3) * nw + i];
+    };
     int j0 = 0;
-    for (; j0 + IV_CH <= m; j0 += IV_CH) {
-        double2 lv[IV_CH];
-        double pvv[IV_CH], xa[IV_CH], xb[IV_CH], xc[IV_CH];
+    if (m >= 2 * IV_DF - 1) {
+        rr[IV_DF - 1] = WZ[(int64_t)rnode(2) * nw + i];
 #pragma unroll
-        for (int q = 0; q < IV_CH; ++q) {
-            const int j = j0 + q;
-            const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j * nw + i) * FS);
-            lv[q] = f[0];
-            pvv[q] = f[1].x;
-            const int k = rnode(j + 3);
-            const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-            xa[q] = X[(int64_t)k * nw + i];
-            xb[q] = X[(int64_t)km * nw + i];
-            xc[q] = X[(int64_t)kp * nw + i];
-        }
+        for (int q = 0; q < IV_DF - 1; ++q) load(q, q);
+        for (; j0 + 2 * IV_DF - 1 <= m; j0 += IV_DF) {
+            step(j0, rp[0], rl[0], rr[IV_DF - 1]);
+            load(j0 - 1 + IV_DF, IV_DF - 1);
 #pragma unroll
-        for (int q = 0; q < IV_CH; ++q) {
-            const int k = rnode(j0 + q + 3);
-            const int km = k == 0 ? n - 1 : k - 1;
-            const double r = P.gd[k] * xa[q] + P.go[km] * xb[q] + P.go[k] * xc[q];
-            step(j0 + q, (int)pvv[q], lv[q].x, lv[q].y, r);
+            for (int q = 1; q < IV_DF; ++q) {
+                step(j0 + q, rp[q], rl[q], rr[q - 1]);
+                load(j0 + q - 1 + IV_DF, q - 1);
+            }
         }
+        // slots 0 .. IV_DF - 2 hold steps j0 .. j0 + IV_DF - 2 (all < m), slot IV_DF - 1
+        // the entering row of step j0 - 1
+        step(j0, rp[0], rl[0], rr[IV_DF - 1]);
+#pragma unroll
+        for (int q = 1; q < IV_DF - 1; ++q) step(j0 + q, rp[q], rl[q], rr[q - 1]);
+        j0 += IV_DF - 1;
     }
+    // W is read-only here: the entering row of step j0 is row j0 + 2
+    double y2 = WZ[(int64_t)rnode(j0 + 2) * nw + i];
     for (; j0 < m; ++j0) {
-        const double2* f = reinterpret_cast<const double2*>(F + ((int64_t)j0 * nw + i) * FS);
-        const double2 l = f[0];
-        step(j0, (int)f[1].x, l.x, l.y, gx(rnode(j0 + 3)));
+        const int64_t e = (int64_t)j0 * nw + i;
+        const double r = WZ[(int64_t)rnode(j0 + 3) * nw + i];
+        const double2 l = F.L[e];
+        step(j0, F.P[e], make_double2(l.x, l.y), y2);
+        y2 = r;
     }
     if (act) {
         IF[(int64_t)(h * 10 + 8) * nw + i] = y0;
@@ -830,20 +878,14 @@ __global__ void cluster_ritz_kernel(const double* __restrict__ h, int n, const d
 void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
-    // bounds of the pencil's spectrum: 0 <= lambda <= max_i 4/(h_{i-1} h_i) / lambda_min(G) (Gershgorin)
-    std::vector<double> hd(4 * (size_t)n);
-    FDS_HIP_TRY(hipMemcpyAsync(hd.data(), op.g_diag, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipMemcpyAsync(hd.data() + n, op.g_off, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipMemcpyAsync(hd.data() + 2 * n, op.l_diag, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipMemcpyAsync(hd.data() + 3 * n, op.l_off, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    double gmin = 1e300, gmax = 0.0, lmax = 0.0;
+    // bounds of the pencil's spectrum (Gershgorin on the host panel lengths):
+    // 0 <= lambda <= max_i (|l_ii| + |l_i,i-1| + |l_i,i+1|) / lambda_min(G)
+    const std::vector<double>& hh = op.h_host;
+    double gmin = 0.0, gmax = 0.0, lmax = 0.0;
+    gram_gershgorin(hh, gmin, gmax);
     for (int i = 0; i < n; ++i) {
-        const int im = i == 0 ? n - 1 : i - 1;
-        const double gd = hd[i], go1 = std::fabs(hd[n + im]), go2 = std::fabs(hd[n + i]);
-        gmin = std::min(gmin, gd - go1 - go2);
-        gmax = std::max(gmax, gd + go1 + go2);
-        lmax = std::max(lmax, std::fabs(hd[2 * n + i]) + std::fabs(hd[3 * n + im]) + std::fabs(hd[3 * n + i]));
+        const double hm = hh[i == 0 ? n - 1 : i - 1], hp = hh[i];
+        lmax = std::max(lmax, 2.0 / hm + 2.0 / hp);
     }
     op.cheb_lo = gmin;
     op.cheb_hi = gmax;
@@ -884,14 +926,9 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // (relative gap), and the reported eigenvalues are the Rayleigh quotients of the
     // final vectors (Rayleigh-Ritz inside each cluster).
     double Ph = 0.0, hmax = 0.0;
-    {
-        std::vector<double> hh(n);
-        FDS_HIP_TRY(hipMemcpyAsync(hh.data(), op.h, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-        for (double v : hh) {
-            Ph += v;
-            hmax = std::max(hmax, v);
-        }
+    for (double v : hh) {
+        Ph += v;
+        hmax = std::max(hmax, v);
     }
     const int K = n / 2;
     SturmStep* dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
@@ -903,29 +940,13 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     const double l1c = (2.0 * kPiHost / Ph) * (2.0 * kPiHost / Ph);
     for (;;) {
         nw = std::min(n - start, want + extra);
-        std::vector<double> br(2 * (size_t)nw);
-        for (int i = 0; i < nw; ++i) {
-            const int idx = start + i;
-            const int kk = (idx + 1) / 2;
-            const double lc = l1c * kk * kk;
-            if (idx == 0) {
-                br[i] = -1e-6 * l1c;
-                br[nw + i] = 0.5 * l1c;
-            } else {
-                br[i] = lc * (1.0 - 1e-9);
-                br[nw + i] = lc * (1.0 + hmax * hmax * lc / 6.0) * (1.0 + 1e-6) + 1e-6 * l1c;
-            }
-        }
-        double* dbr = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * nw));
-        FDS_HIP_TRY(hipMemcpyAsync(dbr, br.data(), sizeof(double) * 2 * nw, hipMemcpyHostToDevice, c.stream));
         double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
         {
             KScope _ks(c, "filter_bisect");
-            hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, dbr,
-                               dbr + nw, -1e-3 * lam_hi, lam_hi, 3e-10, 4e-16 * lam_hi, start, nw, dlam);
+            hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, l1c,
+                               hmax * hmax / 6.0, -1e-3 * lam_hi, lam_hi, 3e-10, 4e-16 * lam_hi, start, nw, dlam);
         }
         FDS_HIP_TRY(hipGetLastError());
-        c.dfree(dbr);
         lam.assign(nw, 0.0);
         FDS_HIP_TRY(hipMemcpyAsync(lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost, c.stream));
         FDS_HIP_TRY(hipStreamSynchronize(c.stream));
@@ -959,8 +980,8 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     FDS_HIP_TRY(hipMemcpyAsync(dcb, cb.data(), sizeof(int) * (ncl + 1), hipMemcpyHostToDevice, c.stream));
     // two-ended elimination: mt steps from the top, mb from the bottom, 4 interface rows
     const int mt = (n - 4) / 2, mb = n - 4 - mt;
-    const int64_t hstride = (int64_t)mb * ne * FS;
-    double* fac = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * (size_t)hstride));
+    const int64_t facM = (int64_t)mb * ne;     // entries per record array (mb >= mt)
+    char* fac = static_cast<char*>(c.dmalloc(2 * fac_half_bytes(facM)));
     double* IF = static_cast<double*>(c.dmalloc(sizeof(double) * 20 * (size_t)ne));
     double* Xn = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));   // node-major
     double* Wk = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
@@ -969,7 +990,7 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     {
         KScope _ks(c, "filter_invit_factor");
         hipLaunchKernelGGL(invit_factor_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, Lb, Gb, dsig, ne, pivmin,
-                           fac, hstride, Wk, IF);
+                           fac, facM, IF);
     }
     FDS_HIP_TRY(hipGetLastError());
     // inverse iteration from a pseudo-random right-hand side: two solves; the
@@ -978,13 +999,15 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     for (int it = 0; it < 2; ++it) {
         if (it > 0) {
             KScope _ks(c, "filter_invit_fwd");
-            hipLaunchKernelGGL(invit_fwd_kernel, egrid, dim3(64), 0, c.stream, P, mt, mb, ne, fac, hstride, Xn, Wk,
-                               IF);
+            const int64_t tot = (int64_t)n * ne;
+            hipLaunchKernelGGL(gx_nodemajor_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, P,
+                               ne, Xn, Wk);
+            hipLaunchKernelGGL(invit_fwd_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, ne, fac, facM, Wk, IF);
         }
         FDS_HIP_TRY(hipGetLastError());
         {
             KScope _ks(c, "filter_invit_back");
-            hipLaunchKernelGGL(invit_back_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, ne, fac, hstride, Wk, IF,
+            hipLaunchKernelGGL(invit_back_kernel, egrid, dim3(64), 0, c.stream, n, mt, mb, ne, fac, facM, IF,
                                pivmin, Xn);
         }
         FDS_HIP_TRY(hipGetLastError());
@@ -1018,13 +1041,14 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
         hipLaunchKernelGGL(cluster_ritz_kernel, dim3(ncl), dim3(256), 0, c.stream, op.h, n, X, dcb, dsig);
     }
     FDS_HIP_TRY(hipGetLastError());
-    FDS_HIP_TRY(hipMemcpyAsync(op.filt_lam.data(), dsig, sizeof(double) * ne, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    // the Ritz values stay on the device until they are read (no host wait here)
+    c.dfree(op.lam_dev);
+    op.lam_dev = dsig;
+    op.lam_dev_n = ne;
     c.dfree(Wk);
     c.dfree(Xn);
     c.dfree(fac);
     c.dfree(IF);
-    c.dfree(dsig);
     c.dfree(dcb);
     c.dfree(Lb);
     c.dfree(Gb);

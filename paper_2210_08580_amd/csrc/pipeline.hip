@@ -131,9 +131,7 @@ void ensure_gram_factor(Op& op) {
     const int n = (int)op.n;
     bool band = n > 4 * GW;
     if (band) {
-        std::vector<double> h(n);
-        FDS_HIP_TRY(hipMemcpyAsync(h.data(), op.h, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        const std::vector<double>& h = op.h_host;
         for (int i = 0; i < n && band; ++i) {
             const double a = h[i == 0 ? n - 1 : i - 1], b = h[i];
             if (a > 4.5 * b || b > 4.5 * a) band = false;
@@ -169,22 +167,26 @@ void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y) {
     gram_solve<double2>(c, op.g_off, op.gfac, n, Y, ncols, n);
 }
 
+// Gershgorin interval of G (P1 mass matrix: diagonal (h_{i-1} + h_i)/3, off-diagonal
+// h_i/6) from the host panel lengths, widened by 1e-12 relative so that rounding
+// differences between the host and the device lengths cannot put an eigenvalue outside.
+void gram_gershgorin(const std::vector<double>& h, double& lo, double& hi) {
+    const size_t n = h.size();
+    lo = 1e300;
+    hi = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double hm = h[i == 0 ? n - 1 : i - 1], hp = h[i];
+        const double d = (hm + hp) / 3.0, r = hm / 6.0 + hp / 6.0;
+        lo = std::min(lo, d - r);
+        hi = std::max(hi, d + r);
+    }
+    lo *= 1.0 - 1e-12;
+    hi *= 1.0 + 1e-12;
+}
+
 void ensure_cheb_bounds(Op& op) {
     if (op.cheb_hi > 0.0) return;
-    const int n = (int)op.n;
-    std::vector<double> h(2 * (size_t)n);
-    Ctx& c = *op.ctx;
-    FDS_HIP_TRY(hipMemcpyAsync(h.data(), op.g_diag, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipMemcpyAsync(h.data() + n, op.g_off, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    double lo = 1e300, hi = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const int im = i == 0 ? n - 1 : i - 1;
-        lo = std::min(lo, h[i] - std::fabs(h[n + im]) - std::fabs(h[n + i]));
-        hi = std::max(hi, h[i] + std::fabs(h[n + im]) + std::fabs(h[n + i]));
-    }
-    op.cheb_lo = lo;
-    op.cheb_hi = hi;
+    gram_gershgorin(op.h_host, op.cheb_lo, op.cheb_hi);
 }
 
 void apply_gram_power(Op& op, int p, double2* X, int64_t ncols) {
