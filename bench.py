@@ -121,8 +121,17 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
         return j
 
     def step():
-        op = build()
-        j = solve(op)
+        # the right-hand side is formed right after the assembly, so that its dense
+        # product runs on the device beside the filter's eigensolver
+        op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
+        f, h = B.fds_rhs_planewave(op, angles, amps)
+        wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
+        ne = B.fds_filter(op, w.form, w.alpha, w.n_modes)
+        r = B.fds_compress(op, w.rank_cap, w.oversample, w.power_iters, w.tol, w.seed)
+        B.fds_factor(op)
+        info.update(n_eff=ne, rank=r)
+        j, _, st = B.fds_solve_system(op, wv, max_iters=iters, tol=tol)
+        info.update(refine=st)
         op.close()
         return j
 

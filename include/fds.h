@@ -342,6 +342,25 @@ fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs,
                      void* j_out, void* y_out, const fds_solve_opts* opts,
                      fds_solve_stats* stats);
 
+/* The solve in two parts, so that the dense right-hand-side product can be
+ * enqueued right after fds_assemble and run on the device beside the filter's
+ * eigensolver (whose kernels leave most of the chip idle).
+ *
+ * fds_rhs_system: w = G^{-1/2} v, the right-hand side in current coefficients
+ * (paper, Notation and Background: the moments e_2, h_2 and the Calderon
+ * normalisation): EFIE w = -G^{-1} S G^{-1} f, MFIE w = -G^{-1} h, CFIE the EFIE
+ * one + alpha times the MFIE one. Valid from ASSEMBLED on; form and alpha must
+ * be those the later fds_filter call uses. f, h, w_out: device [nrhs][n]
+ * complex128 (the input the formulation does not use may be NULL; w_out may
+ * not alias f or h). Asynchronous.
+ *
+ * fds_solve_system: fds_solve from w (fds_rhs_system output): the Woodbury
+ * solve, refinement, outputs, opts and stats exactly as fds_solve. */
+fds_status fds_rhs_system(fds_op op, fds_form form, double alpha, const void* f, const void* h,
+                          int64_t nrhs, void* w_out);
+fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out, void* y_out,
+                            const fds_solve_opts* opts, fds_solve_stats* stats);
+
 /* --------------------------------------------------------- inverse problem */
 
 /* Far fields of currents j (device [nrhs][n] complex128) at angles thetas

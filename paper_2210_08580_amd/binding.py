@@ -123,6 +123,10 @@ _SIGS = {
                                     C.c_void_p]),
     "fds_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                             C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
+    "fds_rhs_system": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.c_void_p]),
+    "fds_solve_system": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
 }
 
 _lib = None
@@ -517,6 +521,31 @@ def fds_solve(op: Op, f: torch.Tensor | None, h: torch.Tensor | None, max_iters:
     st = fds_solve_stats()
     _check(lib().fds_solve(op.handle, _ptr(f), _ptr(h), nrhs, _ptr(j), _ptr(y), C.byref(o),
                            C.byref(st) if stats else None))
+    hist = list(st.history[: st.iters + 1]) if stats else []
+    return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
+                  "history": hist}
+
+
+def fds_rhs_system(op: Op, form: str, alpha: float, f: torch.Tensor | None,
+                   h: torch.Tensor | None) -> torch.Tensor:
+    """w (nrhs, n): the right-hand side in current coefficients for `form` (valid
+    from the assembled stage on; asynchronous)."""
+    ref = f if f is not None else h
+    w = torch.empty((ref.shape[0], op.n), dtype=torch.complex128, device="cuda")
+    _check(lib().fds_rhs_system(op.handle, FORMS[form], float(alpha), _ptr(f), _ptr(h), ref.shape[0], _ptr(w)))
+    return w
+
+
+def fds_solve_system(op: Op, w: torch.Tensor, max_iters: int = 4, tol: float = 1e-12, want_y: bool = False,
+                     stats: bool = True, unfiltered: bool = False):
+    """fds_solve from w = fds_rhs_system(...); same outputs as fds_solve."""
+    nrhs = w.shape[0]
+    j = torch.empty((nrhs, op.n), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(j) if want_y else None
+    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol), int(bool(unfiltered)), 0)
+    st = fds_solve_stats()
+    _check(lib().fds_solve_system(op.handle, _ptr(w), nrhs, _ptr(j), _ptr(y), C.byref(o),
+                                  C.byref(st) if stats else None))
     hist = list(st.history[: st.iters + 1]) if stats else []
     return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
                   "history": hist}

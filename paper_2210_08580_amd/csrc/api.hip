@@ -608,6 +608,38 @@ fds_status fds_solve(fds_op op, const void* f, const void* h, int64_t nrhs, void
     });
 }
 
+fds_status fds_rhs_system(fds_op op, fds_form form, double alpha, const void* f, const void* h, int64_t nrhs,
+                          void* w_out) {
+    return guarded([&] {
+        FDS_REQUIRE(op && w_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Assembled, "fds_rhs_system");
+        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE, FDS_ERR_ARG, "bad form");
+        FDS_REQUIRE(std::isfinite(alpha), FDS_ERR_ARG, "alpha must be finite");
+        if (nrhs == 0) return;
+        run_rhs_system(op->impl, form, alpha, (const double2*)f, (const double2*)h, nrhs, (double2*)w_out);
+    });
+}
+
+fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out, void* y_out,
+                            const fds_solve_opts* opts, fds_solve_stats* stats) {
+    return guarded([&] {
+        FDS_REQUIRE(op && w && j_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Factored, "fds_solve_system");
+        int it = 4;
+        double tol = 1e-12;
+        bool unf = false;
+        if (opts) {
+            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 solves are implemented");
+            it = opts->max_iters;
+            tol = opts->tol;
+            unf = opts->unfiltered != 0;
+        }
+        FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
+        if (nrhs == 0) return;
+        run_solve_system(op->impl, (const double2*)w, nrhs, (double2*)j_out, (double2*)y_out, it, tol, stats, unf);
+    });
+}
+
 fds_status fds_farfield(fds_op op, const void* j, int64_t nrhs, const double* thetas, int64_t nang, void* out) {
     return guarded([&] {
         FDS_REQUIRE(op && j && thetas && out && nrhs >= 0 && nang >= 0 && nang < (1 << 24), FDS_ERR_ARG,

@@ -359,7 +359,10 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
         }
     };
     auto compute = [&](int buf) {
-#pragma unroll
+        // two k-steps per iteration: a full unroll makes the compiler hoist the LDS
+        // fragments of all four, and the extra live registers then spill to AGPRs
+        // (moves every slice)
+#pragma unroll 2
         for (int kc = 0; kc < BB_K / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
             double2 a[4];

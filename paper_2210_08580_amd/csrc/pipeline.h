@@ -12,6 +12,10 @@ void run_filter_batch(Op* const* ops, int count, int form, double alpha, const i
                       double cluster_rtol);
 void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed);
 void run_factor(Op& op);
+void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,
+                    double2* w);
+void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, double2* y_out, int max_iters,
+                      double tol, fds_solve_stats* stats, bool unfiltered);
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
                int max_iters, double tol, fds_solve_stats* stats, bool unfiltered = false);
 void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y);

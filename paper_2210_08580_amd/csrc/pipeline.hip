@@ -514,28 +514,53 @@ static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int
     }
 }
 
+// Right-hand side in j coordinates, w = G^{-1/2} v: -G^{-1} S G^{-1} f (EFIE),
+// -G^{-1} h (MFIE), the EFIE one + alpha times the MFIE one (CFIE). Needs only the
+// assembled operator.
+void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,
+                    double2* w) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const size_t blk = sizeof(double2) * (size_t)n * nrhs;
+    double2* t = static_cast<double2*>(c.dmalloc(blk));
+    if (form == FDS_EFIE || form == FDS_CFIE) {
+        FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
+        gram_inv(op, f, nrhs, t);
+        // S = (S stored row-major)^T as a column-major array
+        op_gemm(op, 0, OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, w);
+        gram_inv(op, w, nrhs, w);
+    }
+    if (form == FDS_MFIE || form == FDS_CFIE) {
+        FDS_REQUIRE(h != nullptr, FDS_ERR_ARG, "h is required for the MFIE/CFIE");
+        gram_inv(op, h, nrhs, t);
+        if (form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), t, kZero, w, (int64_t)n * nrhs);
+        else axpby(c, make_double2(-alpha, 0.0), t, kOne, w, (int64_t)n * nrhs);
+    }
+    c.dfree(t);
+}
+
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
                int max_iters, double tol, fds_solve_stats* stats, bool unfiltered) {
     Ctx& c = *op.ctx;
+    double2* w = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)op.n * nrhs));
+    try {
+        run_rhs_system(op, op.form, op.alpha, f, h, nrhs, w);
+        run_solve_system(op, w, nrhs, j_out, y_out, max_iters, tol, stats, unfiltered);
+    } catch (...) {
+        c.dfree(w);
+        throw;
+    }
+    c.dfree(w);
+}
+
+// The Woodbury solve and refinement from w (j coordinates, the filter's form).
+void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, double2* y_out, int max_iters,
+                      double tol, fds_solve_stats* stats, bool unfiltered) {
+    Ctx& c = *op.ctx;
     const int n = (int)op.n, ne = op.n_eff;
     const size_t blk = sizeof(double2) * (size_t)n * nrhs;
-    double2* w = static_cast<double2*>(c.dmalloc(blk));     // G^{-1/2} v
     double2* res = static_cast<double2*>(c.dmalloc(blk));
     double2* z = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(op.rank, ne) * nrhs));
-    // ---- right-hand side in j coordinates
-    if (op.form == FDS_EFIE || op.form == FDS_CFIE) {
-        FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
-        gram_inv(op, f, nrhs, res);
-        // S = (S stored row-major)^T as a column-major array
-        op_gemm(op, 0, OP_T, nrhs, make_double2(-1.0, 0.0), res, kZero, w);
-        gram_inv(op, w, nrhs, w);
-    }
-    if (op.form == FDS_MFIE || op.form == FDS_CFIE) {
-        FDS_REQUIRE(h != nullptr, FDS_ERR_ARG, "h is required for the MFIE/CFIE");
-        gram_inv(op, h, nrhs, res);
-        if (op.form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), res, kZero, w, (int64_t)n * nrhs);
-        else axpby(c, make_double2(-op.alpha, 0.0), res, kOne, w, (int64_t)n * nrhs);
-    }
     // ---- Woodbury solve
     double2* jv = j_out;
     FDS_HIP_TRY(hipMemcpyAsync(jv, w, blk, hipMemcpyDeviceToDevice, c.stream));
@@ -592,7 +617,6 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
         apply_gram_power(op, 1, y_out, nrhs);
     }
     c.dfree(nrm);
-    c.dfree(w);
     c.dfree(res);
     c.dfree(z);
     c.dfree(t1);

@@ -218,3 +218,45 @@ def test_dense_inverse_singular(ctx):
     A[:, 7] = A[:, 3]
     _, (pmin, amax) = B.fds_zinv(ctx, torch.from_numpy(np.ascontiguousarray(A.T)).cuda())
     assert pmin < 64 * EPS * amax
+
+
+SPLIT_CASES = [("star", 600, 10.0, "efie", 63, "fp64"), ("ellipse", 301, 5.0, "cfie", 41, "fp64"),
+               ("circle", 256, 1.0, "mfie", 21, "fp64"), ("star", 600, 10.0, "efie", 63, "fp32")]
+
+
+@pytest.mark.parametrize("kind,n,k,form,nm,prec", SPLIT_CASES)
+def test_split_solve_matches_solve(ctx, kind, n, k, form, nm, prec):
+    """fds_rhs_system enqueued right after the assembly (before the filter) and
+    fds_solve_system give fds_solve's solution; the oracle pins it as well."""
+    _say(f"case: split solve {kind} n={n} k={k} {form} {prec}")
+    nodes, m = _op_and_oracle(kind, n, k)
+    ang, _ = wl.planewaves(11, 6)
+    amps = wl.random_amplitudes(12, 6)
+    op = B.fds_assemble(ctx, torch.from_numpy(nodes).cuda(), k, precision=prec)
+    f, h = B.fds_rhs_planewave(op, torch.from_numpy(ang), torch.from_numpy(amps))
+    w = B.fds_rhs_system(op, form, 1.0, f, h)
+    with pytest.raises(B.FdsError) as e:
+        B.fds_solve_system(op, w)
+    assert e.value.name == "FDS_ERR_STATE"
+    ne = B.fds_filter(op, form, 1.0, nm)
+    B.fds_compress(op, rank_cap=ne + 1, oversample=10, power_iters=2, seed=7)
+    B.fds_factor(op)
+    j1, y1, st1 = B.fds_solve_system(op, w, max_iters=3, tol=1e-12, want_y=True)
+    j2, y2, st2 = B.fds_solve(op, f, h, max_iters=3, tol=1e-12, want_y=True)
+    assert st1["converged"] and st2["converged"], (st1, st2)
+    assert st1["iters"] == st2["iters"]
+    d = (torch.linalg.vector_norm(j1 - j2) / torch.linalg.vector_norm(j2)).item()
+    assert d <= 1e-14, d
+    if prec == "fp64":
+        pb = solver.Problem(nodes, k, form=form, n_modes=nm, rank_cap=ne + 1, oversample=10,
+                            power_iters=2, seed=7)
+        ops = solver.build_operators(pb)
+        fo, ho = assembly.rhs_planewave(m, k, ang, amps)
+        v = formulation.rhs_vector(form, ops.S, ops.Gmh, ops.Gi, fo.T, ho.T)
+        # w = G^{-1/2} v
+        assert solver.relerr(w.cpu().numpy().T, ops.Gmh @ v) <= 1e-12
+        assert solver.relerr(y1.cpu().numpy().T, solver.y_filtered(ops, v)) <= 1e-10
+    with pytest.raises(B.FdsError) as e:
+        B.fds_rhs_system(op, "efie", 1.0, None, h)
+    assert e.value.name == "FDS_ERR_ARG"
+    op.close()
