@@ -98,7 +98,7 @@ def solve_limits(w):
     return 50, 1e-8
 
 
-def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
+def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_early=True):
     """Times `steps` full steps of one precision variant, then `steps` solves of the
     same right-hand sides with the factors kept (the marginal rate); returns
     (seconds, profile, info, j, marginal seconds)."""
@@ -121,12 +121,15 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup):
         return j
 
     def step():
-        # the right-hand side is formed right after the assembly, so that its dense
-        # product runs on the device beside the filter's eigensolver
+        # with rhs_early the right-hand side is formed right after the assembly, so
+        # that its dense product runs on the device beside the filter's eigensolver
         op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
         f, h = B.fds_rhs_planewave(op, angles, amps)
-        wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
+        if rhs_early:
+            wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
         ne = B.fds_filter(op, w.form, w.alpha, w.n_modes)
+        if not rhs_early:
+            wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
         r = B.fds_compress(op, w.rank_cap, w.oversample, w.power_iters, w.tol, w.seed)
         B.fds_factor(op)
         info.update(n_eff=ne, rank=r)
@@ -338,6 +341,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--autotune", action="store_true",
                     help="let the GEMM autotuner time tile / split-K candidates per shape class (first use)")
+    ap.add_argument("--rhs-after-filter", action="store_true",
+                    help="form the right-hand side after the filter instead of right after the assembly")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -375,7 +380,8 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     res = {}
     for prec in variants:
-        el, prof, info, j, marg = run_variant(B, ctx, w, nodes, angles, amps, prec, args.steps, args.warmup)
+        el, prof, info, j, marg = run_variant(B, ctx, w, nodes, angles, amps, prec, args.steps, args.warmup,
+                                              rhs_early=not args.rhs_after_filter)
         far = prof.get("asm_far", (0.0, 1))
         asm_ms = far[0] / max(far[1], 1)
         res[prec] = {
