@@ -163,6 +163,81 @@ def assemble(m: Mesh, k: float, nq: int = 8, row_chunk: int | None = None):
     return S, Nm, D
 
 
+# ----------------------------------------------------------------------------- Yukawa single layer
+def yukawa_pair_blocks(m: Mesh, kappa: float, P, Q, nq: int = 8, nt: int = 32):
+    """2 x 2 blocks of the single layer with the Yukawa kernel (1/2 pi) K0(kappa R)
+    (the Calderon preconditioner of the Yukawa-Calderon TE-CFIE, paper, Filters
+    Based Fast Direct Solver, 2D case) for panel pairs (P[t], Q[t]): far pairs by
+    the tensor Gauss rule, self and adjacent pairs with the same exact logarithmic
+    parts as S (the kernel has the Laplace singularity -(1/2 pi) log R)."""
+    P = np.atleast_1d(np.asarray(P, dtype=np.int64))
+    Q = np.atleast_1d(np.asarray(Q, dtype=np.int64))
+    n = m.n
+    xi, w, psi, wpsi = _rule(nq)
+    pts = m.points(xi)
+    out = np.empty((P.size, 2, 2), dtype=np.float64)
+    near = is_near(n, P, Q)
+    far = ~near
+    if far.any():
+        Pf, Qf = P[far], Q[far]
+        diff = pts[Pf][:, :, None, :] - pts[Qf][:, None, :, :]
+        g = sf.yukawa(kappa, np.hypot(diff[..., 0], diff[..., 1]))
+        hh = (m.h[Pf] * m.h[Qf])[:, None, None]
+        out[far] = hh * np.einsum("ia,jb,tab->tij", wpsi, wpsi, g)
+    for t in np.nonzero(near)[0]:
+        p, q = int(P[t]), int(Q[t])
+        diff = pts[p][:, None, :] - pts[q][None, :, :]
+        greg = sf.yukawa_reg(kappa, np.hypot(diff[..., 0], diff[..., 1]))
+        Sreg = m.h[p] * m.h[q] * np.einsum("ia,jb,ab->ij", wpsi, wpsi, greg)
+        if p == q:
+            Lg = qd.self_log(m.h[p])
+        else:
+            if q == (p + 1) % n:
+                a, b, end_x, end_y = -m.tau[p], m.tau[q], True, False
+            else:
+                a, b, end_x, end_y = m.tau[p], -m.tau[q], False, True
+            Lg, _ = qd.adjacent_singular(m.h[p], m.h[q], a, b, m.nrm[q], end_x, end_y, nt)
+        out[t] = Sreg - Lg / TWO_PI
+    return out
+
+
+def assemble_yukawa(m: Mesh, kappa: float, nq: int = 8, row_chunk: int | None = None):
+    """Dense Yukawa single layer S_y (N x N real), symmetrised on |i - j| <= 2 like S."""
+    n = m.n
+    Sy = np.zeros((n, n), dtype=np.float64)
+    if row_chunk is None:
+        row_chunk = max(1, 2 ** 21 // (n * nq * nq))
+    qs = np.arange(n)
+    for p0 in range(0, n, row_chunk):
+        ps = np.arange(p0, min(n, p0 + row_chunk))
+        B = yukawa_pair_blocks(m, kappa, np.repeat(ps, n), np.tile(qs, ps.size), nq).reshape(ps.size, n, 2, 2)
+        for al in range(2):
+            rows = (ps + al) % n
+            Sy[rows, :] += B[:, :, al, 0] + np.roll(B[:, :, al, 1], 1, axis=1)
+    _symmetrise_band(Sy)
+    return Sy
+
+
+def entries_yukawa(m: Mesh, kappa: float, I, J, nq: int = 8):
+    """Sampled entries of S_y one by one, the same rule as assemble_yukawa()."""
+    I = np.asarray(I, dtype=np.int64)
+    J = np.asarray(J, dtype=np.int64)
+    n = m.n
+
+    def raw(I, J):
+        v = np.zeros(I.size, dtype=np.float64)
+        for al in range(2):
+            for be in range(2):
+                v += yukawa_pair_blocks(m, kappa, (I - al) % n, (J - be) % n, nq)[:, al, be]
+        return v
+
+    v = raw(I, J)
+    band = band_mask(n, I, J)
+    if band.any():
+        v[band] = 0.5 * (v[band] + raw(J[band], I[band]))
+    return v
+
+
 def band_mask(n: int, i, j, width: int = 2):
     d = np.abs(np.asarray(i) - np.asarray(j)) % n
     return (d <= width) | (d >= n - width)

@@ -12,6 +12,14 @@ Readings taken where the printed text is garbled or silent:
   * MFIE: Z_h = I/2 - G^{-1/2} D G^{-1/2}, v_h = -G^{-1/2} h; its compact part
     is C_h = -G^{-1/2} D G^{-1/2} (the filtered MFIE is I/2 + P C_h).
   * CFIE: Z_e + alpha Z_h, v_e + alpha v_h, beta = (1 + 2 alpha)/4.
+  * Yukawa-Calderon CFIE ("ycfie", paper, Filters Based Fast Direct Solver, 2D
+    case, the filtered Yukawa-Calderon TE-CFIE): the CFIE with the single layer
+    of the Calderon product and of v_e taken at the imaginary wavenumber i k
+    (kernel (1/2 pi) K0(k R), the "localised" preconditioner):
+    Z_e = G^{-1/2} S_y G^{-1} N G^{-1/2}, v_e = -G^{-1/2} S_y G^{-1} f; the
+    compact part is again Z_e - I/4 + alpha C_h, beta = (1 + 2 alpha)/4. The
+    paper names the preconditioner but not its wavenumber; i k is this build's
+    reading.
 G^{+-1/2} and G^{-1} are formed from a dense symmetric eigendecomposition of
 G (exact to rounding).
 """
@@ -22,7 +30,7 @@ import scipy.linalg as sla
 
 from .assembly import periodic_dense
 
-FORMS = ("efie", "mfie", "cfie")
+FORMS = ("efie", "mfie", "cfie", "ycfie")
 
 
 def gram_powers(diag: np.ndarray, off: np.ndarray):
@@ -42,19 +50,21 @@ def beta_of(form: str, alpha: float = 1.0) -> float:
         return 0.25
     if form == "mfie":
         return 0.5
-    if form == "cfie":
+    if form in ("cfie", "ycfie"):
         return (1.0 + 2.0 * alpha) / 4.0
     raise ValueError(form)
 
 
-def compact_part(form: str, S, Nm, D, Gmh, Gi, alpha: float = 1.0):
-    """C = Z - beta I for the chosen formulation; returns (C, beta)."""
+def compact_part(form: str, S, Nm, D, Gmh, Gi, alpha: float = 1.0, Sy=None):
+    """C = Z - beta I for the chosen formulation; returns (C, beta). Sy: the
+    Yukawa single layer (required for "ycfie")."""
     n = S.shape[0]
     I = np.eye(n)
     Ce = Ch = None
-    if form in ("efie", "cfie"):
-        Ce = Gmh @ (S @ (Gi @ (Nm @ Gmh))) - 0.25 * I
-    if form in ("mfie", "cfie"):
+    if form in ("efie", "cfie", "ycfie"):
+        Sc = Sy if form == "ycfie" else S
+        Ce = Gmh @ (Sc @ (Gi @ (Nm @ Gmh))) - 0.25 * I
+    if form in ("mfie", "cfie", "ycfie"):
         Ch = -(Gmh @ (D @ Gmh))
     if form == "efie":
         C = Ce
@@ -65,18 +75,18 @@ def compact_part(form: str, S, Nm, D, Gmh, Gi, alpha: float = 1.0):
     return C, beta_of(form, alpha)
 
 
-def rhs_vector(form: str, S, Gmh, Gi, f, h, alpha: float = 1.0):
+def rhs_vector(form: str, S, Gmh, Gi, f, h, alpha: float = 1.0, Sy=None):
     """v for columns f, h (N x nrhs)."""
     v = 0
-    if form in ("efie", "cfie"):
-        v = -(Gmh @ (S @ (Gi @ f)))
-    if form in ("mfie", "cfie"):
+    if form in ("efie", "cfie", "ycfie"):
+        v = -(Gmh @ ((Sy if form == "ycfie" else S) @ (Gi @ f)))
+    if form in ("mfie", "cfie", "ycfie"):
         vh = -(Gmh @ h)
         v = vh if form == "mfie" else v + alpha * vh
     return v
 
 
-def system_matrix(form: str, S, Nm, D, Gmh, Gi, alpha: float = 1.0):
+def system_matrix(form: str, S, Nm, D, Gmh, Gi, alpha: float = 1.0, Sy=None):
     """Z = beta I + C (unfiltered)."""
-    C, beta = compact_part(form, S, Nm, D, Gmh, Gi, alpha)
+    C, beta = compact_part(form, S, Nm, D, Gmh, Gi, alpha, Sy)
     return C + beta * np.eye(S.shape[0])

@@ -56,6 +56,7 @@ class Operators:
     lam: np.ndarray
     n_eff: int
     Ac: np.ndarray
+    Sy: np.ndarray | None = None    # Yukawa single layer ("ycfie" only)
 
 
 def build_operators(pb: Problem) -> Operators:
@@ -64,11 +65,12 @@ def build_operators(pb: Problem) -> Operators:
     G = assembly.gram(m)
     L = assembly.laplacian(m)
     Gh, Gmh, Gi = formulation.gram_powers(*G)
-    C, beta = formulation.compact_part(pb.form, S, Nm, D, Gmh, Gi, pb.alpha)
+    Sy = assembly.assemble_yukawa(m, pb.k) if pb.form == "ycfie" else None
+    C, beta = formulation.compact_part(pb.form, S, Nm, D, Gmh, Gi, pb.alpha, Sy)
     Vn, lam, n_eff = filters.laplacian_filter(m, pb.n_modes, pb.keep_nullspace,
                                               pb.cluster_rtol, Gmh)
     Ac = Vn @ (Vn.T @ C)
-    return Operators(m, S, Nm, D, G, L, Gh, Gmh, Gi, C, beta, Vn, lam, n_eff, Ac)
+    return Operators(m, S, Nm, D, G, L, Gh, Gmh, Gi, C, beta, Vn, lam, n_eff, Ac, Sy)
 
 
 @dataclasses.dataclass
@@ -91,7 +93,7 @@ def solve(pb: Problem, ops: Operators, angles, amps) -> Solution:
     U, W, s = compress.compress(ops.Ac, Om, pb.power_iters, pb.rank_cap, pb.tol)
     lu = woodbury.factor(U, W, ops.beta)
     f, h = assembly.rhs_planewave(ops.mesh, pb.k, angles, amps)
-    v = formulation.rhs_vector(pb.form, ops.S, ops.Gmh, ops.Gi, f.T, h.T, pb.alpha)
+    v = formulation.rhs_vector(pb.form, ops.S, ops.Gmh, ops.Gi, f.T, h.T, pb.alpha, ops.Sy)
     y0 = woodbury.solve(U, W, ops.beta, lu, v)
 
     def apply_A(y):

@@ -3,8 +3,12 @@
 Paper, Notation and Background: g2(r, r') = (i/4) H0^(1)(k |r - r'|); the double
 layer D uses the normal derivative with respect to the source point r'.
 
-Bessel functions come from scipy.special (j0, y0, j1, y1); the HIP library has
-its own evaluator. H_n^(1) = J_n + i Y_n.
+Bessel functions come from scipy.special (j0, y0, j1, y1, k0); the HIP library
+has its own evaluator. H_n^(1) = J_n + i Y_n.
+
+The Yukawa kernel of the Yukawa-Calderon TE-CFIE (paper, Filters Based Fast
+Direct Solver, 2D case: the Calderon preconditioner localised) is g2 at the
+imaginary wavenumber i kappa: (i/4) H0^(1)(i kappa R) = (1/2 pi) K0(kappa R).
 """
 from __future__ import annotations
 
@@ -58,3 +62,26 @@ def dgreen_laplace_coef(R):
     """Small-R limit of dgreen_coef: the Laplace double-layer 1/(2 pi R^2)."""
     R = np.asarray(R, dtype=np.float64)
     return 1.0 / (TWO_PI * R * R)
+
+
+def yukawa(kappa: float, R):
+    """(1/2 pi) K0(kappa R) for R > 0."""
+    R = np.asarray(R, dtype=np.float64)
+    return _sp.k0(kappa * R) / TWO_PI
+
+
+def yukawa_reg_at_zero(kappa: float) -> float:
+    """lim_{R->0} (1/2 pi)(K0(kappa R) + log R) = -(log(kappa/2) + gamma_E)/(2 pi),
+    from K0(z) = -(log(z/2) + gamma_E) I0(z) + O(z^2 log z)."""
+    return -(np.log(0.5 * kappa) + EULER_GAMMA) / TWO_PI
+
+
+def yukawa_reg(kappa: float, R):
+    """Regular part (1/2 pi)(K0(kappa R) + log R), continuous at R = 0."""
+    R = np.asarray(R, dtype=np.float64)
+    out = np.empty(R.shape, dtype=np.float64)
+    z = R == 0.0
+    nz = ~z
+    out[nz] = yukawa(kappa, R[nz]) + np.log(R[nz]) / TWO_PI
+    out[z] = yukawa_reg_at_zero(kappa)
+    return out
