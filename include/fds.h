@@ -60,7 +60,14 @@ typedef struct fds_allocator {
 typedef enum fds_form {
     FDS_EFIE = 0,   /* normalised Calderon TE-EFIE, beta = 1/4                 */
     FDS_MFIE = 1,   /* normalised TE-MFIE, beta = 1/2                          */
-    FDS_CFIE = 2    /* EFIE + alpha MFIE, beta = (1 + 2 alpha)/4                */
+    FDS_CFIE = 2,   /* EFIE + alpha MFIE, beta = (1 + 2 alpha)/4                */
+    FDS_YCFIE = 3   /* filtered Yukawa-Calderon TE-CFIE (paper, Filters Based
+                       Fast Direct Solver, 2D case): the CFIE with the single
+                       layer of the Calderon product and of v_e taken at the
+                       imaginary wavenumber i k, kernel (1/2 pi) K0(k R);
+                       beta = (1 + 2 alpha)/4. The Yukawa operator is assembled
+                       (FP64) by the first fds_rhs_system or fds_filter call
+                       with this form; not available in the batched calls.   */
 } fds_form;
 
 typedef enum fds_precision { FDS_FP64 = 0, FDS_FP32 = 1, FDS_BF16 = 2 } fds_precision;
@@ -165,6 +172,13 @@ fds_status fds_hankel_eval_f32(fds_ctx ctx, const double* x, int64_t n, float* o
 fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n,
                            double* out);
 
+/* The Yukawa kernel of the Yukawa-Calderon TE-CFIE (the 2D Helmholtz kernel at
+ * the imaginary wavenumber i kappa) at distances R (device [n], R >= 0).
+ * out: device [n][2] doubles =
+ *   (1/2 pi) K0(kappa R)                               (R > 0; 0 at R = 0)
+ *   (1/2 pi) (K0(kappa R) + log R), continuous at R = 0 */
+fds_status fds_yukawa_eval(fds_ctx ctx, double kappa, const double* R, int64_t n, double* out);
+
 /* Complex GEMM on the FP64 matrix cores (the dense contractions of the
  * compression and solve stages run on this kernel):
  *   C = alpha op(A) op(B) + beta C,  column-major, C is m x n, inner size k,
@@ -235,6 +249,11 @@ fds_status fds_op_matrices(fds_op op, void** S, void** Nmat, void** D);
  * O(h) on smooth vectors, so FP32 errors there would be amplified by 1/h;
  * the band is computed and kept in FP64. Host call. */
 fds_status fds_op_nband(fds_op op, const void** Nband, int32_t* width);
+
+/* Borrowed device view of the Yukawa single layer S_y of the Yukawa-Calderon
+ * TE-CFIE ([n][n] row-major complex128 with zero imaginary parts), or NULL
+ * before the first fds_rhs_system / fds_filter call with FDS_YCFIE. Host call. */
+fds_status fds_op_yukawa(fds_op op, const void** Sy);
 
 /* Storage precision of S, N, D (FDS_FP64 or FDS_FP32). Host call. */
 fds_status fds_op_precision(fds_op op, int32_t* precision);

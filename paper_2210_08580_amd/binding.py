@@ -21,8 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfds.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fds.h")
 
-FDS_EFIE, FDS_MFIE, FDS_CFIE = 0, 1, 2
-FORMS = {"efie": FDS_EFIE, "mfie": FDS_MFIE, "cfie": FDS_CFIE}
+FDS_EFIE, FDS_MFIE, FDS_CFIE, FDS_YCFIE = 0, 1, 2, 3
+FORMS = {"efie": FDS_EFIE, "mfie": FDS_MFIE, "cfie": FDS_CFIE, "ycfie": FDS_YCFIE}
 FDS_FP64, FDS_FP32, FDS_BF16 = 0, 1, 2
 STATUS = {0: "FDS_OK", 1: "FDS_ERR_ARG", 2: "FDS_ERR_ALLOC", 3: "FDS_ERR_HIP",
           4: "FDS_ERR_STATE", 5: "FDS_ERR_SINGULAR", 6: "FDS_ERR_NOCONV", 7: "FDS_ERR_NOTIMPL"}
@@ -85,12 +85,14 @@ _SIGS = {
                             C.POINTER(C.c_float), C.c_void_p, C.c_int64]),
     "fds_op_precision": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fds_op_nband": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "fds_op_yukawa": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "fds_farfield": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_farfield_objective_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                               C.c_int64, C.c_void_p, C.POINTER(fds_solve_opts),
                                               C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.POINTER(fds_solve_stats)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_yukawa_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_zinv": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
@@ -292,6 +294,14 @@ def fds_hankel_eval_f32(ctx: Ctx, x: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def fds_yukawa_eval(ctx: Ctx, kappa: float, R: torch.Tensor) -> torch.Tensor:
+    """(n, 2): (1/2pi) K0(kappa R) and (1/2pi)(K0(kappa R) + log R)."""
+    R = R.to(device="cuda", dtype=torch.float64).contiguous()
+    out = torch.empty((R.numel(), 2), dtype=torch.float64, device="cuda")
+    _check(lib().fds_yukawa_eval(ctx.handle, float(kappa), _ptr(R), R.numel(), _ptr(out)))
+    return out
+
+
 def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:
     out = torch.empty((R.numel(), 8), dtype=torch.float64, device=R.device)
     _check(lib().fds_kernel_eval(ctx.handle, float(k), _ptr(R), R.numel(), _ptr(out)))
@@ -417,6 +427,15 @@ def fds_op_nband(op: Op):
     if not p.value:
         return None, 0
     return _view(p.value, (op.n, 2 * w.value + 1), torch.complex128, op), w.value
+
+
+def fds_op_yukawa(op: Op):
+    """The Yukawa single layer (n, n) complex128 view, or None before it is built."""
+    p = C.c_void_p()
+    _check(lib().fds_op_yukawa(op.handle, C.byref(p)))
+    if not p.value:
+        return None
+    return _view(p.value, (op.n, op.n), torch.complex128, op)
 
 
 def fds_op_precision(op: Op) -> int:

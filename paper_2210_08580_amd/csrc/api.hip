@@ -47,7 +47,7 @@ void Ctx::dfree(void* p) {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
-                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev};
+                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
         ctx->dfree(U);
@@ -123,6 +123,9 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.hk_tab32 = (float*)x.dmalloc(sizeof(float) * HK32_TAB_FLOATS);
             FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab32, &HK32_TAB[0][0][0], sizeof(float) * HK32_TAB_FLOATS,
                                        hipMemcpyHostToDevice, x.stream));
+            x.yk_tab = (double*)x.dmalloc(sizeof(double) * YK_TAB_DOUBLES);
+            FDS_HIP_TRY(hipMemcpyAsync(x.yk_tab, &YK_TAB[0][0], sizeof(double) * YK_TAB_DOUBLES,
+                                       hipMemcpyHostToDevice, x.stream));
             double g[64];
             gauss_legendre_01(32, g, g + 32);
             x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);
@@ -132,6 +135,7 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.dfree(x.hk_tab);
             x.dfree(x.hk_tab32);
             x.dfree(x.gl32);
+            x.dfree(x.yk_tab);
             delete c;
             throw;
         }
@@ -152,6 +156,7 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
         ctx->impl.dfree(ctx->impl.hk_tab);
         ctx->impl.dfree(ctx->impl.hk_tab32);
         ctx->impl.dfree(ctx->impl.gl32);
+        ctx->impl.dfree(ctx->impl.yk_tab);
         delete ctx;
     });
 }
@@ -219,6 +224,15 @@ fds_status fds_hankel_eval_f32(fds_ctx ctx, const double* x, int64_t n, float* o
         FDS_REQUIRE(ctx && x && out && n >= 0, FDS_ERR_ARG, "bad argument");
         if (n == 0) return;
         launch_hankel_eval_f32(ctx->impl, x, n, out);
+    });
+}
+
+fds_status fds_yukawa_eval(fds_ctx ctx, double kappa, const double* R, int64_t n, double* out) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && R && out && n >= 0, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(std::isfinite(kappa) && kappa > 0.0, FDS_ERR_ARG, "kappa must be finite and > 0");
+        if (n == 0) return;
+        launch_yukawa_eval(ctx->impl, kappa, R, n, out);
     });
 }
 
@@ -431,6 +445,13 @@ fds_status fds_op_nband(fds_op op, const void** Nband, int32_t* width) {
     });
 }
 
+fds_status fds_op_yukawa(fds_op op, const void** Sy) {
+    return guarded([&] {
+        FDS_REQUIRE(op && Sy, FDS_ERR_ARG, "NULL argument");
+        *Sy = op->impl.Sy;
+    });
+}
+
 fds_status fds_op_precision(fds_op op, int32_t* precision) {
     return guarded([&] {
         FDS_REQUIRE(op && precision, FDS_ERR_ARG, "NULL argument");
@@ -473,7 +494,8 @@ fds_status fds_filter(fds_op op, fds_form form, double alpha, const fds_filter_o
     return guarded([&] {
         FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
         require_stage(op->impl, Stage::Assembled, "fds_filter");
-        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE, FDS_ERR_ARG, "bad form");
+        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE || form == FDS_YCFIE, FDS_ERR_ARG,
+                    "bad form");
         FDS_REQUIRE(std::isfinite(alpha), FDS_ERR_ARG, "alpha must be finite");
         int nm = 21;
         bool keep = true;
@@ -485,7 +507,7 @@ fds_status fds_filter(fds_op op, fds_form form, double alpha, const fds_filter_o
         }
         FDS_REQUIRE(nm >= 1 && nm <= op->impl.n, FDS_ERR_ARG, "n_modes must be in [1, n]");
         FDS_REQUIRE(keep || nm >= 2, FDS_ERR_ARG, "n_modes must be >= 2 without the null mode");
-        if (form == FDS_CFIE)
+        if (form == FDS_CFIE || form == FDS_YCFIE)
             FDS_REQUIRE(std::fabs(1.0 + 2.0 * alpha) > 1e-12, FDS_ERR_ARG, "CFIE with beta = 0");
         run_filter(op->impl, form, alpha, nm, keep, crt);
         if (n_eff) *n_eff = op->impl.n_eff;
@@ -613,7 +635,8 @@ fds_status fds_rhs_system(fds_op op, fds_form form, double alpha, const void* f,
     return guarded([&] {
         FDS_REQUIRE(op && w_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
         require_stage(op->impl, Stage::Assembled, "fds_rhs_system");
-        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE, FDS_ERR_ARG, "bad form");
+        FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE || form == FDS_YCFIE, FDS_ERR_ARG,
+                    "bad form");
         FDS_REQUIRE(std::isfinite(alpha), FDS_ERR_ARG, "alpha must be finite");
         if (nrhs == 0) return;
         run_rhs_system(op->impl, form, alpha, (const double2*)f, (const double2*)h, nrhs, (double2*)w_out);

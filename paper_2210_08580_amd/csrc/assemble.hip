@@ -735,4 +735,130 @@ void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
     c.dfree(dbuf);
 }
 
+// ---------------------------------------------------------------- Yukawa single layer
+// S_y with the kernel (1/2pi) K0(kappa |x - y|) (the single layer at the
+// imaginary wavenumber i kappa), the preconditioner of the Yukawa-Calderon
+// TE-CFIE (paper, Filters Based Fast Direct Solver, 2D case: the localised
+// Calderon preconditioner). FP64, stored row-major as complex128 with zero
+// imaginary parts so that the complex products take it unchanged.
+// A workgroup forms the 2 x 2 pair blocks of panels [i0 - 1, i0 + YT) x
+// [j0 - 1, j0 + YT) in LDS (one per thread: far pairs by the 8 x 8 rule, self
+// and adjacent pairs with their logarithmic parts exact) and adds the four that
+// meet each entry of its YT x YT tile: entry (i, j) takes block (i - a, j - b)[a][b].
+struct YukParams {
+    const double* __restrict__ gx;
+    const double* __restrict__ gy;
+    const double* __restrict__ h;
+    const double* __restrict__ nx;
+    const double* __restrict__ ny;
+    const double* __restrict__ ytab;
+    const double* __restrict__ gl32;
+    double2* __restrict__ Sy;
+    double kappa;
+    int n;
+};
+
+constexpr int YT = 15;   // entries per tile side: (YT + 1)^2 = 256 pair blocks, one per thread
+
+__global__ __launch_bounds__(256) void asm_yukawa_kernel(YukParams P, W8 wt) {
+    __shared__ double blk[(YT + 1) * (YT + 1)][4];
+    const int n = P.n;
+    const int i0 = blockIdx.y * YT, j0 = blockIdx.x * YT;
+    {
+        const int t = threadIdx.x;
+        const int a = t / (YT + 1), b = t % (YT + 1);
+        const int p = (i0 - 1 + a + n) % n, q = (j0 - 1 + b + n) % n;
+        const int d = (q - p + n) % n;
+        double B[2][2];
+        if (d <= 1 || d == n - 1) {
+            const int s = d == 0 ? 1 : (d == 1 ? 2 : 0);
+            double2 So[2][2], Do[2][2];
+            near_pair_blocks<false, true>(P.gx + 8 * p, P.gy + 8 * p, P.gx + 8 * q, P.gy + 8 * q, P.h[p], P.h[q],
+                                          P.nx[p], P.ny[p], P.nx[q], P.ny[q], s, P.kappa, P.ytab, P.gl32, wt, So,
+                                          Do);
+#pragma unroll
+            for (int al = 0; al < 2; ++al)
+#pragma unroll
+                for (int be = 0; be < 2; ++be) B[al][be] = So[al][be].x;
+        } else {
+            double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+            const double* px = P.gx + 8 * p;
+            const double* py = P.gy + 8 * p;
+            const double* qx = P.gx + 8 * q;
+            const double* qy = P.gy + 8 * q;
+            for (int u = 0; u < 8; ++u) {
+                double kv[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const double dx = px[u] - qx[v], dy = py[u] - qy[v];
+                    kv[v] = yk_k0(P.kappa * sqrt(fma(dx, dx, dy * dy)), P.ytab);
+                }
+                double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    r0 = fma(wt.wp0[v], kv[v], r0);
+                    r1 = fma(wt.wp1[v], kv[v], r1);
+                }
+                acc[0][0] = fma(wt.wp0[u], r0, acc[0][0]);
+                acc[0][1] = fma(wt.wp0[u], r1, acc[0][1]);
+                acc[1][0] = fma(wt.wp1[u], r0, acc[1][0]);
+                acc[1][1] = fma(wt.wp1[u], r1, acc[1][1]);
+            }
+            const double sc = kInv2Pi * P.h[p] * P.h[q];
+#pragma unroll
+            for (int al = 0; al < 2; ++al)
+#pragma unroll
+                for (int be = 0; be < 2; ++be) B[al][be] = sc * acc[al][be];
+        }
+        blk[t][0] = B[0][0];
+        blk[t][1] = B[0][1];
+        blk[t][2] = B[1][0];
+        blk[t][3] = B[1][1];
+    }
+    __syncthreads();
+    if (threadIdx.x < YT * YT) {
+        const int ti = threadIdx.x / YT, tj = threadIdx.x % YT;
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < n && j < n) {
+            const int a = ti + 1, b = tj + 1;
+            const double v = blk[a * (YT + 1) + b][0] + blk[a * (YT + 1) + b - 1][1] +
+                             blk[(a - 1) * (YT + 1) + b][2] + blk[(a - 1) * (YT + 1) + b - 1][3];
+            P.Sy[(int64_t)i * n + j] = make_double2(v, 0.0);
+        }
+    }
+}
+
+// Averages the entries (i, j) and (j, i) on the band |i - j| <= 2 (cyclic), like S.
+__global__ void sym_band_kernel(double2* __restrict__ M, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n) return;
+    const int i = t / 3, d = t - 3 * (t / 3);
+    if (d == 0) return;
+    const int j = (i + d) % n;
+    const int64_t ij = (int64_t)i * n + j, ji = (int64_t)j * n + i;
+    const double2 a = M[ij], b = M[ji];
+    const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    M[ij] = m;
+    M[ji] = m;
+}
+
+void launch_assemble_yukawa(Op& op, double kappa, double2* Sy) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    W8 wt;
+    WLow wlow;
+    far_rules(op, wt, wlow);
+    YukParams yp;
+    yp.gx = op.gx; yp.gy = op.gy; yp.h = op.h; yp.nx = op.nx; yp.ny = op.ny;
+    yp.ytab = c.yk_tab; yp.gl32 = c.gl32; yp.Sy = Sy; yp.kappa = kappa; yp.n = n;
+    const unsigned nt = (unsigned)((n + YT - 1) / YT);
+    FDS_REQUIRE(nt <= 65535u, FDS_ERR_NOTIMPL, "Yukawa operator limited to n <= 983025");
+    {
+        KScope _ks(c, "asm_yukawa");
+        hipLaunchKernelGGL(asm_yukawa_kernel, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt);
+        hipLaunchKernelGGL(sym_band_kernel, dim3((3 * n + 255) / 256), dim3(256), 0, c.stream, Sy, n);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
 }  // namespace fds

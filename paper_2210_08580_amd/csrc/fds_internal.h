@@ -64,6 +64,7 @@ struct Ctx {
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
     float* hk_tab32 = nullptr;    // device copy of the single-precision table
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
+    double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
     void* dmalloc(size_t bytes);
     void dfree(void* p);
 };
@@ -170,6 +171,8 @@ struct Op {
     float2* S32 = nullptr;
     float2* N32 = nullptr;
     float2* D32 = nullptr;
+    double2* Sy = nullptr;        // Yukawa single layer (kernel (1/2pi) K0(k R)), complex128 with zero
+                                  // imaginary parts; built by the first Yukawa-Calderon CFIE call
     double2* Nband = nullptr;     // FP32 operators: N on the cyclic band |d| <= nbw in complex128,
                                   // [n][2 nbw + 1] (N[i][(i + d) mod n] at [i][d + nbw]); N32 is zero there
     int nbw = 0;
@@ -209,11 +212,13 @@ void launch_rhs_planewave(Op& op, const double* angles, const double2* amps, int
 void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out);
 void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out);
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
+void launch_yukawa_eval(Ctx& c, double kappa, const double* R, int64_t n, double* out);
 // pipeline.hip: Gershgorin interval of the Gram matrix from host panel lengths
 void gram_gershgorin(const std::vector<double>& h, double& lo, double& hi);
 // assemble.hip
 void launch_assemble(Op& op);
 void launch_assemble_batch(Ctx& c, Op* const* ops, int nops);
+void launch_assemble_yukawa(Op& op, double kappa, double2* Sy);
 // gauss rules (host)
 void gauss_legendre_01(int n, double* x, double* w);
 

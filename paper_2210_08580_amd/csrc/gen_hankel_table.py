@@ -22,6 +22,16 @@ same three regions with degree-DEG32 interpolants and shorter series/expansions,
 checked in a float32 emulation (argument x and the table variable t formed in
 float64, everything after in float32) against 4e-7 max(|f|, 1).
 
+A third set (YK_*) evaluates K0, the modified Bessel function of the second kind
+of the Yukawa kernel (1/2pi) K0(kappa R) (Helmholtz at the imaginary wavenumber
+i kappa), in FP64:
+  x < YK_XS   ascending series (A&S 9.6.12, 9.6.13):
+                I0 = sum q^m/(m!)^2,  K0 = -(log(x/2) + gamma) I0 + sum_{m>=1} H_m q^m/(m!)^2
+  YK_XS <= x < XA  exp(x) K0(x) interpolated on unit intervals like the tables above
+  x >= XA     K0 = sqrt(pi/(2x)) exp(-x) sum_k a_k(0) x^-k  (A&S 9.7.2)
+checked against mpmath in relative error (4e-16 max(|f|, 1) in the series range,
+where the log term dominates, 6e-16 relative elsewhere).
+
 Run:  python gen_hankel_table.py   (writes hankel_table.inc next to this file)
 """
 from __future__ import annotations
@@ -206,6 +216,58 @@ def table32():
     return ser, asy, tabs, nas
 
 
+YK_XS = 2
+YK_NSER = 16
+
+
+def yk_sets():
+    """Series, table and asymptotic coefficients of K0 (FP64)."""
+    ci0, ck0 = [], []
+    H = mp.mpf(0)
+    for m in range(YK_NSER):
+        f2 = mp.factorial(m) ** 2
+        if m >= 1:
+            H += mp.mpf(1) / m
+        ci0.append(1 / f2)
+        ck0.append(H / f2)
+    f = lambda x: mp.exp(x) * mp.besselk(0, x)
+    tab = [cheb_monomial(f, c) for c in range(YK_XS, XA)]
+    # asymptotic: first neglected term below 1e-18 at x = XA
+    a = [mp.mpf(1)]
+    for k in range(1, 60):
+        a.append(a[-1] * (0 - (2 * k - 1) ** 2) / (k * 8))
+    nas = next(k for k in range(2, 60) if abs(a[k]) / mp.mpf(XA) ** k < 1e-18)
+    return [float(v) for v in ci0], [float(v) for v in ck0], [[float(v) for v in cc] for cc in tab], \
+        [float(v) for v in a[:nas]]
+
+
+def yk_emulate(x, ci0, ck0, tab, asy):
+    x = np.float64(x)
+    if x < YK_XS:
+        q = x * x / 4
+        i0 = horner(ci0, q)
+        return -(np.log(0.5 * x) + np.euler_gamma) * i0 + q * horner(ck0[1:], q)
+    if x < XA:
+        c = int(np.floor(x))
+        return np.exp(-x) * horner(tab[c - YK_XS], x - (c + 0.5))
+    return np.sqrt(np.pi / (2.0 * x)) * np.exp(-x) * horner(asy, 1.0 / x)
+
+
+def yk_check(sets):
+    xs = np.concatenate([np.geomspace(1e-6, YK_XS, 300, endpoint=False),
+                         np.linspace(YK_XS, XA, 2400, endpoint=False),
+                         np.linspace(XA, 200, 600)])
+    worst = 0.0
+    for x in xs:
+        ref = float(mp.besselk(0, mp.mpf(float(x))))
+        got = float(yk_emulate(x, *sets))
+        err = abs(got - ref) / (max(abs(ref), 1.0) if x < YK_XS else abs(ref))
+        worst = max(worst, err / (4e-16 if x < YK_XS else 6e-16))
+    print(f"K0 set: asymptotic terms {len(sets[3])}; worst error / tolerance {worst:.3f}")
+    if worst > 1.0:
+        sys.exit("K0 table accuracy check failed")
+
+
 def main():
     ser = series_coeffs()
     nas = asym_terms_needed(XA)
@@ -231,6 +293,8 @@ def main():
     if worst > 4e-16:
         sys.exit("table accuracy check failed")
     ser32, asy32, tab32, nas32 = table32()
+    yk = yk_sets()
+    yk_check(yk)
     out = os.path.join(HERE, "hankel_table.inc")
     with open(out, "w") as fh:
         fh.write("// Generated by gen_hankel_table.py; do not edit.\n")
@@ -265,6 +329,16 @@ def main():
             for m in range(DEG32 + 1):
                 fh.write("  {" + ", ".join(repr(float(np.float32(tab32[f][c][m]))) + "f" for f in range(4)) + "},\n")
             fh.write(" },\n")
+        fh.write("};\n")
+        ci0, ck0, ytab, yasy = yk
+        fh.write(f"#define YK_XS {YK_XS}\n#define YK_NSER {YK_NSER}\n#define YK_NASY {len(yasy)}\n")
+        fh.write("static constexpr double YK_SER_I0[%d] = {" % len(ci0) + ", ".join(repr(v) for v in ci0) + "};\n")
+        fh.write("static constexpr double YK_SER_K0[%d] = {" % len(ck0) + ", ".join(repr(v) for v in ck0) + "};\n")
+        fh.write("static constexpr double YK_ASY[%d] = {" % len(yasy) + ", ".join(repr(v) for v in yasy) + "};\n")
+        fh.write(f"// [interval c-{YK_XS}][coefficient of t^m] of exp(x) K0(x)\n")
+        fh.write(f"static constexpr double YK_TAB[{XA - YK_XS}][{DEG + 1}] = {{\n")
+        for cc in ytab:
+            fh.write("  {" + ", ".join(repr(v) for v in cc) + "},\n")
         fh.write("};\n")
     print("wrote", out)
 

@@ -174,6 +174,17 @@ __global__ void kernel_eval_kernel(double k, const double* __restrict__ Rs, int6
     o[3] = gr.y;
 }
 
+// Yukawa kernel values at distances R: out[i] = ((1/2pi) K0(kappa R) (R > 0, else 0),
+// (1/2pi)(K0(kappa R) + log R), continuous at R = 0).
+__global__ void yukawa_eval_kernel(double kappa, const double* __restrict__ Rs, int64_t n,
+                                   const double* __restrict__ ytab, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double R = Rs[i];
+    out[2 * i] = R > 0.0 ? kInv2Pi * yk_k0(kappa * R, ytab) : 0.0;
+    out[2 * i + 1] = yukawa_reg(kappa, R, ytab);
+}
+
 // ----------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -226,6 +237,15 @@ void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out) {
         KScope _ks(c, "hankel_eval");
         hipLaunchKernelGGL(hankel_eval_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
                            c.hk_tab32, out);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+void launch_yukawa_eval(Ctx& c, double kappa, const double* R, int64_t n, double* out) {
+    {
+        KScope _ks(c, "yukawa_eval");
+        hipLaunchKernelGGL(yukawa_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, kappa, R, n,
+                           c.yk_tab, out);
     }
     FDS_HIP_TRY(hipGetLastError());
 }

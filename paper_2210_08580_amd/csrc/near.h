@@ -32,7 +32,9 @@ __device__ __forceinline__ void corner_lin(bool end, int al, double& c0, double&
 // the logarithmic parts integrated exactly (closed form on a self pair, Duffy's
 // corner split with 32 points in the angle on adjacent pairs) and the smooth
 // remainders by the 8 x 8 rule. px, py / qx, qy: the 8 Gauss points of the panels.
-template <bool WANT_D>
+// YUK: the Yukawa kernel (1/2pi) K0(k R) instead of g (tab is then the K0 table);
+// it has the same logarithmic part, its S block is real and no D block is formed.
+template <bool WANT_D, bool YUK = false>
 __device__ __forceinline__ void near_pair_blocks(const double* px, const double* py, const double* qx,
                                                  const double* qy, double hp, double hq, double nxp, double nyp,
                                                  double nxq, double nyq, int s, double k,
@@ -51,11 +53,11 @@ __device__ __forceinline__ void near_pair_blocks(const double* px, const double*
         for (int b = 0; b < 8; ++b) {
             const double dx = xa - qx[b], dy = ya - qy[b];
             const double R = sqrt(fma(dx, dx, dy * dy));
-            const double2 g = green_reg(k, R, tab);
+            const double2 g = YUK ? make_double2(yukawa_reg(k, R, tab), 0.0) : green_reg(k, R, tab);
             const double wa[2] = {wt.wp0[a], wt.wp1[a]};
             const double wb[2] = {wt.wp0[b], wt.wp1[b]};
             double2 rem = make_double2(0.0, 0.0);
-            if (WANT_D && s != 1) {
+            if (WANT_D && !YUK && s != 1) {
                 const double2 r0 = dlayer_rem(k, R, tab);
                 const double dn = fma(dx, nxq, dy * nyq) / R;
                 rem = cscale(r0, dn);

@@ -40,10 +40,31 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
 // vectors) would be amplified by ||N|| / |lambda_N(low modes)| ~ 1/h.
 // The complex128 band of N (half-width w) replaces the zeros of the complex64
 // matrix on load (N is symmetric, so op(N) = N for OP_N and OP_T).
+// Formulation helpers: the EFIE part is present in EFIE, CFIE and the
+// Yukawa-Calderon CFIE, the MFIE part in MFIE, CFIE and YCFIE; the single layer
+// of the Calderon product is S (operator 0) or the Yukawa S_y (operator 3).
+static inline bool has_efie(int f) { return f == FDS_EFIE || f == FDS_CFIE || f == FDS_YCFIE; }
+static inline bool has_mfie(int f) { return f == FDS_MFIE || f == FDS_CFIE || f == FDS_YCFIE; }
+static inline int s_op(int f) { return f == FDS_YCFIE ? 3 : 0; }
+
+// Assembles the Yukawa single layer (kernel (1/2pi) K0(k R)) on first use.
+void ensure_yukawa(Op& op) {
+    if (op.Sy) return;
+    Ctx& c = *op.ctx;
+    op.Sy = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)op.n * op.n));
+    launch_assemble_yukawa(op, op.k, op.Sy);
+}
+
 static void op_gemm(Op& op, int which, int opa, int64_t ncols, double2 alpha, const double2* X, double2 beta,
                     double2* Y) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
+    if (which == 3) {   // the symmetric Yukawa single layer, FP64 in every precision
+        FDS_REQUIRE(op.Sy != nullptr, FDS_ERR_STATE, "Yukawa operator not assembled");
+        GemmTag tag(c, "gemm_op_y");
+        zgemm(c, OP_N, OP_N, n, (int)ncols, n, alpha, op.Sy, n, X, n, beta, Y, n);
+        return;
+    }
     // S and N are stored exactly symmetric (mirror writes of one value, symmetrised
     // near band), so their transposed products are the untransposed ones
     if (which != 2 && opa == OP_T) opa = OP_N;
@@ -73,7 +94,10 @@ static void op_gemm_vg(Op& op, int which, double2 alpha, double2 beta, double2* 
     bool done;
     {
         GemmTag tag(c, "gemm_op_vg");
-        if (op.prec == FDS_FP32) {
+        if (which == 3) {
+            FDS_REQUIRE(op.Sy != nullptr, FDS_ERR_STATE, "Yukawa operator not assembled");
+            done = zgemm_real_b(c, n, ne, n, alpha, op.Sy, n, op.Vg, n, beta, Y, n);
+        } else if (op.prec == FDS_FP32) {
             const float2* M = which == 0 ? op.S32 : (which == 1 ? op.N32 : op.D32);
             BandA band;
             if (which == 1) {
@@ -240,18 +264,20 @@ static void filter_prepare(Op& op, int form, double alpha, int n_modes, bool kee
 void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
+    if (form == FDS_YCFIE) ensure_yukawa(op);   // enqueued first: it runs beside the eigensolver
     filter_prepare(op, form, alpha, n_modes, keep_null, cluster_rtol);
     const int ne = op.n_eff;
-    if (form == FDS_EFIE || form == FDS_CFIE) {
-        // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T)
+    if (has_efie(form)) {
+        // Bt = N^T G^{-1} S^T Vg - G Vg / 4  (S, N stored row-major: as column-major arrays they are S^T, N^T;
+        // S_y in place of S for the Yukawa-Calderon CFIE)
         double2* X = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * ne));
-        op_gemm_vg(op, 0, kOne, kZero, X);
+        op_gemm_vg(op, s_op(form), kOne, kZero, X);
         gram_inv(op, X, ne, X);
         op_gemm(op, 1, OP_N, ne, kOne, X, kZero, op.Bt);
         gram_mul<double2>(c, op.g_diag, op.g_off, n, op.Vgc, ne, n, -0.25, 0.0, X, n);
         axpby(c, kOne, X, kOne, op.Bt, (int64_t)n * ne);
         c.dfree(X);
-        if (form == FDS_CFIE)   // + alpha * (-D^T Vg)
+        if (form == FDS_CFIE || form == FDS_YCFIE)   // + alpha * (-D^T Vg)
             op_gemm_vg(op, 2, make_double2(-alpha, 0.0), kOne, op.Bt);
     } else {
         op_gemm_vg(op, 2, make_double2(-1.0, 0.0), kZero, op.Bt);
@@ -498,15 +524,15 @@ static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int
     const size_t blk = sizeof(double2) * (size_t)tot;
     FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
     axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, tot);
-    if (op.form == FDS_EFIE || op.form == FDS_CFIE) {
+    if (has_efie(op.form)) {
         op_gemm(op, 1, OP_T, nrhs, kOne, jv, kZero, t1);          // N j
         gram_inv(op, t1, nrhs, t1);
-        op_gemm(op, 0, OP_T, nrhs, kOne, t1, kZero, t2);          // S G^-1 N j
+        op_gemm(op, s_op(op.form), OP_T, nrhs, kOne, t1, kZero, t2);   // S G^-1 N j (S_y for YCFIE)
         gram_inv(op, t2, nrhs, t2);
         axpby(c, make_double2(-1.0, 0.0), t2, kOne, res, tot);
         axpby(c, make_double2(0.25, 0.0), jv, kOne, res, tot);
     }
-    if (op.form == FDS_MFIE || op.form == FDS_CFIE) {
+    if (has_mfie(op.form)) {
         const double a = op.form == FDS_MFIE ? 1.0 : op.alpha;
         op_gemm(op, 2, OP_T, nrhs, kOne, jv, kZero, t1);          // D j
         gram_inv(op, t1, nrhs, t1);
@@ -522,15 +548,16 @@ void run_rhs_system(Op& op, int form, double alpha, const double2* f, const doub
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
     const size_t blk = sizeof(double2) * (size_t)n * nrhs;
+    if (form == FDS_YCFIE) ensure_yukawa(op);
     double2* t = static_cast<double2*>(c.dmalloc(blk));
-    if (form == FDS_EFIE || form == FDS_CFIE) {
+    if (has_efie(form)) {
         FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
         gram_inv(op, f, nrhs, t);
-        // S = (S stored row-major)^T as a column-major array
-        op_gemm(op, 0, OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, w);
+        // S = (S stored row-major)^T as a column-major array (S_y for YCFIE)
+        op_gemm(op, s_op(form), OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, w);
         gram_inv(op, w, nrhs, w);
     }
-    if (form == FDS_MFIE || form == FDS_CFIE) {
+    if (has_mfie(form)) {
         FDS_REQUIRE(h != nullptr, FDS_ERR_ARG, "h is required for the MFIE/CFIE");
         gram_inv(op, h, nrhs, t);
         if (form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), t, kZero, w, (int64_t)n * nrhs);
