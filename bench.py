@@ -32,7 +32,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
+def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form: str | None = None):
     """Time the CPU oracle stage by stage at N = n_sample on the same curve, k,
     formulation and filter, and scale each stage to N = n_full by its
     complexity: assembly and solve O(N^2) (per right-hand side), dense operator
@@ -43,15 +43,16 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
     from oracle import assembly, compress, filters, formulation, geometry, rng, woodbury
     from paper_2210_08580_amd import workloads as wl
 
-    w = wl.workload(wname, n=n_sample, nrhs=nrhs)
+    w = wl.workload(wname, n=n_sample, nrhs=nrhs, form=form)
     m = geometry.mesh(w.nodes)
     t = {}
     t0 = time.perf_counter()
     S, Nm, D = assembly.assemble(m, w.k)
+    Sy = assembly.assemble_yukawa(m, w.k) if w.form == "ycfie" else None
     t["assemble"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Gh, Gmh, Gi = formulation.gram_powers(*assembly.gram(m))
-    C, beta = formulation.compact_part(w.form, S, Nm, D, Gmh, Gi, w.alpha)
+    C, beta = formulation.compact_part(w.form, S, Nm, D, Gmh, Gi, w.alpha, Sy)
     Vn, lam, ne = filters.laplacian_filter(m, w.n_modes, True, 1e-6, Gmh)
     Ac = Vn @ (Vn.T @ C)
     t["dense"] = time.perf_counter() - t0
@@ -62,7 +63,7 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
     t["compress"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     f, h = assembly.rhs_planewave(m, w.k, w.angles, w.amps)
-    v = formulation.rhs_vector(w.form, S, Gmh, Gi, f.T, h.T, w.alpha)
+    v = formulation.rhs_vector(w.form, S, Gmh, Gi, f.T, h.T, w.alpha, Sy)
     y = woodbury.solve(U, W, beta, lu, v)
     y, hist = woodbury.refine(lambda x: beta * x + Ac @ x, U, W, beta, lu, v, y, 1e-10, 2)
     j = Gmh @ y
@@ -76,8 +77,8 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024):
         "unit": "RHS solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle pipeline at N={n_sample} (same curve, k, EFIE, n_modes, rank cap, "
-                   f"{nrhs} RHS) took {sample_s:.1f} s; stages scaled to N={n_full} "
+        "sample": (f"oracle pipeline at N={n_sample} (same curve, k, formulation, n_modes, rank cap, "
+                   f"{nrhs} RHS, {w.form.upper()}) took {sample_s:.1f} s; stages scaled to N={n_full} "
                    f"(assembly, compression, solve x(N/Ns)^2, dense algebra x(N/Ns)^3): "
                    + ", ".join(f"{k}={v:.2f}s" for k, v in t.items())),
         "est_seconds_per_step": est,
@@ -294,23 +295,30 @@ def measured_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def roofline(prof, n, ne, nrhs, steps, precision):
+def roofline(prof, n, ne, nrhs, steps, precision, form="efie"):
     """Roofline of the kernel family with the largest total time (HIP events on
     the context stream): achieved = algorithmic work per launch / mean launch time."""
     name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     per_launch_s = (tot_ms / 1e3) / max(launches, 1)
     traffic = None
     sym = {"fp32": "float2", "fp64": "double2"}[precision]
-    if name in ("gemm_op", "gemm_op_vg"):
+    if name in ("gemm_op", "gemm_op_vg", "gemm_op_y"):
         # N x N operator products on one kernel symbol each, 8 flop per complex
         # multiply-add (4 with the real V_g). gemm_op_vg: S^T V_g (n_eff columns);
         # gemm_op: N^T (G^-1 S^T V_g) (n_eff columns) and S^T (G^-1 f) (nrhs columns),
-        # one launch of each per step of this workload
-        per_step = 4.0 * n * n * ne if name == "gemm_op_vg" else 8.0 * n * n * (ne + nrhs)
+        # one launch of each per step of this workload; with the Yukawa-Calderon
+        # CFIE the second is the FP64 Yukawa product gemm_op_y
+        if name == "gemm_op_vg":
+            per_step = 4.0 * n * n * ne
+        elif name == "gemm_op_y":
+            per_step = 8.0 * n * n * nrhs
+        else:
+            per_step = 8.0 * n * n * (ne + (0 if form == "ycfie" else nrhs))
         work = per_step * steps / max(launches, 1)
+        asym = "double2" if name == "gemm_op_y" else sym
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
-                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0>" % (sym, "double" if name == "gemm_op_vg" else "double2")}
-        traffic = measured_traffic(name + ":" + precision)
+                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0>" % (asym, "double" if name == "gemm_op_vg" else "double2")}
+        traffic = measured_traffic(name + ":" + precision) if form != "ycfie" else None
     elif name == "asm_far":
         work = 32.0 * n * n * FLOP_PER_POINT_PAIR
         roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
@@ -341,6 +349,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--autotune", action="store_true",
                     help="let the GEMM autotuner time tile / split-K candidates per shape class (first use)")
+    ap.add_argument("--form", default=None, choices=["efie", "mfie", "cfie", "ycfie"],
+                    help="formulation (default: the workload's; ycfie = Yukawa-Calderon CFIE)")
     ap.add_argument("--rhs-after-filter", action="store_true",
                     help="form the right-hand side after the filter instead of right after the assembly")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -361,7 +371,7 @@ def main():
     from paper_2210_08580_amd import binding as B
     from paper_2210_08580_amd import workloads as wl
 
-    w = wl.workload(args.workload, nrhs=args.nrhs)
+    w = wl.workload(args.workload, nrhs=args.nrhs, form=args.form)
     n, nrhs = w.n, w.nrhs
     ctx = B.fds_ctx_create(0)
     if args.autotune:
@@ -405,7 +415,7 @@ def main():
     r = res[main_v]
     info = r["info"]
     ne = info["n_eff"]
-    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v)
+    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form)
     extra.update({"n_eff": ne, "rank": info["rank"]})
     for prec, rv in res.items():
         extra[prec] = {
@@ -433,7 +443,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle sample at N={args.cpu_sample_n}")
-        out["cpu_baseline"] = cpu_baseline(args.workload, n, nrhs, args.cpu_sample_n)
+        out["cpu_baseline"] = cpu_baseline(args.workload, n, nrhs, args.cpu_sample_n, args.form)
     if args.autotune:
         out["extra"]["autotune"] = B.fds_autotune_read(ctx)
     ctx.close()

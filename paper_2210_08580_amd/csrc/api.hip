@@ -123,9 +123,14 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.hk_tab32 = (float*)x.dmalloc(sizeof(float) * HK32_TAB_FLOATS);
             FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab32, &HK32_TAB[0][0][0], sizeof(float) * HK32_TAB_FLOATS,
                                        hipMemcpyHostToDevice, x.stream));
-            x.yk_tab = (double*)x.dmalloc(sizeof(double) * YK_TAB_DOUBLES);
-            FDS_HIP_TRY(hipMemcpyAsync(x.yk_tab, &YK_TAB[0][0], sizeof(double) * YK_TAB_DOUBLES,
-                                       hipMemcpyHostToDevice, x.stream));
+            std::vector<double> yk(YK_ALL_DOUBLES);
+            std::copy(&YK_TAB[0][0], &YK_TAB[0][0] + YK_TAB_DOUBLES, yk.begin());
+            std::copy(YK_SER_I0, YK_SER_I0 + YK_NSER, yk.begin() + YK_OFF_I0);
+            std::copy(YK_SER_K0, YK_SER_K0 + YK_NSER, yk.begin() + YK_OFF_K0);
+            std::copy(YK_ASY, YK_ASY + YK_NASY, yk.begin() + YK_OFF_ASY);
+            x.yk_tab = (double*)x.dmalloc(sizeof(double) * YK_ALL_DOUBLES);
+            FDS_HIP_TRY(hipMemcpyAsync(x.yk_tab, yk.data(), sizeof(double) * YK_ALL_DOUBLES, hipMemcpyHostToDevice,
+                                       x.stream));
             double g[64];
             gauss_legendre_01(32, g, g + 32);
             x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);

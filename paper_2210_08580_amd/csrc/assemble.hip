@@ -748,6 +748,7 @@ void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
 struct YukParams {
     const double* __restrict__ gx;
     const double* __restrict__ gy;
+    const double* __restrict__ nodes;
     const double* __restrict__ h;
     const double* __restrict__ nx;
     const double* __restrict__ ny;
@@ -760,72 +761,299 @@ struct YukParams {
 
 constexpr int YT = 15;   // entries per tile side: (YT + 1)^2 = 256 pair blocks, one per thread
 
-__global__ __launch_bounds__(256) void asm_yukawa_kernel(YukParams P, W8 wt) {
-    __shared__ double blk[(YT + 1) * (YT + 1)][4];
-    const int n = P.n;
-    const int i0 = blockIdx.y * YT, j0 = blockIdx.x * YT;
-    {
-        const int t = threadIdx.x;
-        const int a = t / (YT + 1), b = t % (YT + 1);
-        const int p = (i0 - 1 + a + n) % n, q = (j0 - 1 + b + n) % n;
-        const int d = (q - p + n) % n;
-        double B[2][2];
-        if (d <= 1 || d == n - 1) {
-            const int s = d == 0 ? 1 : (d == 1 ? 2 : 0);
-            double2 So[2][2], Do[2][2];
-            near_pair_blocks<false, true>(P.gx + 8 * p, P.gy + 8 * p, P.gx + 8 * q, P.gy + 8 * q, P.h[p], P.h[q],
-                                          P.nx[p], P.ny[p], P.nx[q], P.ny[q], s, P.kappa, P.ytab, P.gl32, wt, So,
-                                          Do);
+// Gauss order of a far pair from its gap g (midpoint distance minus the two
+// half-lengths) in units of the longer panel. The orders keep the quadrature
+// error of every block below 1e-13 of the near-diagonal block size against the
+// 8 x 8 rule (measured on the star, ellipse and random curves for k R from 0.1 to
+// 20: orders 6, 5, 4, 3 first meet it at gaps 2, 5, 14, 58; the thresholds below
+// leave a margin of 1.5 to 2).
+__device__ __forceinline__ int yukawa_order(double gap) {
+    return gap < 3.0 ? 8 : (gap < 8.0 ? 6 : (gap < 24.0 ? 5 : (gap < 100.0 ? 4 : 3)));
+}
+
+// Entries of tile row b (rows b*YT .. min(b*YT + YT, n) - 1) use the panel pairs of
+// the cyclic run of panels that starts at b*YT - 1; this is its length.
+__host__ __device__ inline int yuk_run_len(int b, int n) {
+    const int e = b * YT + YT < n ? b * YT + YT : n;
+    return e - b * YT + 1;
+}
+
+// True when tile (bi, bj) uses the block of a self or adjacent panel pair (cyclic
+// panel distance <= 1): the run of row bi widened by one panel on each side meets
+// the run of column bj (two cyclic intervals meet iff one holds the other's start).
+__host__ __device__ inline bool yuk_tile_near(int bi, int bj, int n) {
+    const int li = yuk_run_len(bi, n) + 2, lj = yuk_run_len(bj, n);
+    if (li >= n || lj >= n) return true;
+    const int si = ((bi * YT - 2) % n + n) % n, sj = ((bj * YT - 1) % n + n) % n;
+    return ((sj - si) % n + n) % n < li || ((si - sj) % n + n) % n < lj;
+}
+
+// K0 by the unit-interval table with the interval clamped to the table: exact for
+// YK_XS <= x < YK_XA (other arguments are redone by yk_k0).
+__device__ __forceinline__ double yk_k0_tab(double x, const double* __restrict__ ytab) {
+    int c = (int)x;
+    c = c < YK_XS ? YK_XS : (c > YK_XA - 1 ? YK_XA - 1 : c);
+    const double t = x - ((double)c + 0.5);
+    const double* cf = ytab + (c - YK_XS) * (HK_DEG + 1);
+    double acc = cf[HK_DEG];
 #pragma unroll
-            for (int al = 0; al < 2; ++al)
-#pragma unroll
-                for (int be = 0; be < 2; ++be) B[al][be] = So[al][be].x;
-        } else {
-            double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-            const double* px = P.gx + 8 * p;
-            const double* py = P.gy + 8 * p;
-            const double* qx = P.gx + 8 * q;
-            const double* qy = P.gy + 8 * q;
-            for (int u = 0; u < 8; ++u) {
-                double kv[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    const double dx = px[u] - qx[v], dy = py[u] - qy[v];
-                    kv[v] = yk_k0(P.kappa * sqrt(fma(dx, dx, dy * dy)), P.ytab);
-                }
-                double r0 = 0.0, r1 = 0.0;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    r0 = fma(wt.wp0[v], kv[v], r0);
-                    r1 = fma(wt.wp1[v], kv[v], r1);
-                }
-                acc[0][0] = fma(wt.wp0[u], r0, acc[0][0]);
-                acc[0][1] = fma(wt.wp0[u], r1, acc[0][1]);
-                acc[1][0] = fma(wt.wp1[u], r0, acc[1][0]);
-                acc[1][1] = fma(wt.wp1[u], r1, acc[1][1]);
-            }
-            const double sc = kInv2Pi * P.h[p] * P.h[q];
-#pragma unroll
-            for (int al = 0; al < 2; ++al)
-#pragma unroll
-                for (int be = 0; be < 2; ++be) B[al][be] = sc * acc[al][be];
-        }
-        blk[t][0] = B[0][0];
-        blk[t][1] = B[0][1];
-        blk[t][2] = B[1][0];
-        blk[t][3] = B[1][1];
+    for (int m = HK_DEG - 1; m >= 0; --m) acc = fma(acc, t, cf[m]);
+    return acc;
+}
+
+// Panel endpoints of a far pair: node and edge vector of p and q.
+struct PairGeom {
+    double px0, py0, pex, pey, qx0, qy0, qex, qey;
+};
+
+// sqrt of a normal positive argument: the hardware reciprocal square root refined
+// by two coupled Newton steps for sqrt(s) and 1/(2 sqrt(s)) (Goldschmidt's
+// iteration), without the range scaling a general sqrt needs for denormals.
+__device__ __forceinline__ double sqrt_normal(double s) {
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, hh = 0.5 * y;
+    const double r = fma(-hh, g, 0.5);
+    g = fma(g, r, g);
+    hh = fma(hh, r, hh);
+    double d = fma(-g, g, s);
+    g = fma(d, hh, g);
+    d = fma(-g, g, s);
+    return fma(d, hh, g);
+}
+
+typedef __attribute__((address_space(4))) const double const_double;
+
+// Point NO-rule node v of a panel: the stored 8-point node or node + xi * edge.
+template <int NO>
+__device__ __forceinline__ void yuk_node(const YukParams& P, const WLow& wl, int panel, double x0, double y0,
+                                         double ex, double ey, int v, double& x, double& y) {
+    if (NO == 8) {
+        x = P.gx[8 * panel + v];
+        y = P.gy[8 * panel + v];
+    } else {
+        constexpr int off = low_rule_offset(NO < 8 ? NO : 2);
+        x = fma(wl.r[off + v], ex, x0);
+        y = fma(wl.r[off + v], ey, y0);
     }
-    __syncthreads();
+}
+
+// Weights w psi_0, w psi_1 of node v of the NO-point rule.
+template <int NO>
+__device__ __forceinline__ void yuk_wts(const W8& wt, const WLow& wl, int v, double& w0, double& w1) {
+    constexpr int off = low_rule_offset(NO < 8 ? NO : 2);
+    w0 = NO == 8 ? wt.wp0[v] : wl.r[off + NO + v];
+    w1 = NO == 8 ? wt.wp1[v] : wl.r[off + 2 * NO + v];
+}
+
+// The NO x NO Gauss product rule of a far pair block (without the factor
+// h_p h_q / 2pi), one row of NO kernel values at a time. When every argument of
+// the row, over the whole wave, lies in one unit interval of the K0 table (the
+// common case: neighbouring pairs see nearly the same distances), the interval's
+// coefficients are wave-uniform scalar loads; otherwise each lane reads its own
+// from the LDS copy. Returns true when some argument lies outside the table; the
+// caller then redoes the block through yk_k0.
+template <int NO>
+__device__ __forceinline__ bool yuk_far_rule(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
+                                             const WLow& wl, int p, int q, const PairGeom& g, double acc[2][2]) {
+    double yb[NO], zb[NO];
+#pragma unroll
+    for (int v = 0; v < NO; ++v) yuk_node<NO>(P, wl, q, g.qx0, g.qy0, g.qex, g.qey, v, yb[v], zb[v]);
+    bool rare = false;
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+        double xa, ya, wa0, wa1;
+        yuk_node<NO>(P, wl, p, g.px0, g.py0, g.pex, g.pey, u, xa, ya);
+        yuk_wts<NO>(wt, wl, u, wa0, wa1);
+        double xv[NO];
+        double lo = 1e300, hi = 0.0;
+#pragma unroll
+        for (int v = 0; v < NO; ++v) {
+            const double dx = xa - yb[v], dy = ya - zb[v];
+            xv[v] = P.kappa * sqrt_normal(fmax(fma(dx, dx, dy * dy), 1e-280));
+            lo = fmin(lo, xv[v]);
+            hi = fmax(hi, xv[v]);
+        }
+        rare |= lo < (double)YK_XS || hi >= (double)YK_XA;
+        const int c0 = __builtin_amdgcn_readfirstlane((int)xv[0]);
+        const bool one = c0 >= YK_XS && c0 < YK_XA && (int)lo == c0 && (int)hi == c0;
+        double r0 = 0.0, r1 = 0.0;
+        if (__all(one)) {
+            const const_double* cf = (const const_double*)(P.ytab + (c0 - YK_XS) * (HK_DEG + 1));
+            const double cm = (double)c0 + 0.5;
+#pragma unroll
+            for (int v = 0; v < NO; ++v) {
+                const double t = xv[v] - cm;
+                double k = cf[HK_DEG];
+#pragma unroll
+                for (int m = HK_DEG - 1; m >= 0; --m) k = fma(k, t, cf[m]);
+                double w0, w1;
+                yuk_wts<NO>(wt, wl, v, w0, w1);
+                r0 = fma(w0, k, r0);
+                r1 = fma(w1, k, r1);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NO; ++v) {
+                const double k = yk_k0_tab(xv[v], ytab);
+                double w0, w1;
+                yuk_wts<NO>(wt, wl, v, w0, w1);
+                r0 = fma(w0, k, r0);
+                r1 = fma(w1, k, r1);
+            }
+        }
+        acc[0][0] = fma(wa0, r0, acc[0][0]);
+        acc[0][1] = fma(wa0, r1, acc[0][1]);
+        acc[1][0] = fma(wa1, r0, acc[1][0]);
+        acc[1][1] = fma(wa1, r1, acc[1][1]);
+    }
+    return rare;
+}
+
+// The same rule with every kernel value through yk_k0 (series and asymptotic
+// ranges included).
+template <int NO>
+__device__ __forceinline__ void yuk_far_rule_any(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
+                                              const WLow& wl, int p, int q, const PairGeom& g, double acc[2][2]) {
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+        double xa, ya, wa0, wa1;
+        yuk_node<NO>(P, wl, p, g.px0, g.py0, g.pex, g.pey, u, xa, ya);
+        yuk_wts<NO>(wt, wl, u, wa0, wa1);
+        double r0 = 0.0, r1 = 0.0;
+#pragma unroll 1
+        for (int v = 0; v < NO; ++v) {
+            double yb, zb, w0, w1;
+            yuk_node<NO>(P, wl, q, g.qx0, g.qy0, g.qex, g.qey, v, yb, zb);
+            yuk_wts<NO>(wt, wl, v, w0, w1);
+            const double dx = xa - yb, dy = ya - zb;
+            const double k = yk_k0(P.kappa * sqrt(fma(dx, dx, dy * dy)), ytab);
+            r0 = fma(w0, k, r0);
+            r1 = fma(w1, k, r1);
+        }
+        acc[0][0] = fma(wa0, r0, acc[0][0]);
+        acc[0][1] = fma(wa0, r1, acc[0][1]);
+        acc[1][0] = fma(wa1, r0, acc[1][0]);
+        acc[1][1] = fma(wa1, r1, acc[1][1]);
+    }
+}
+
+template <int NO>
+__device__ __forceinline__ void yuk_far_order(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
+                                              const WLow& wl, int p, int q, const PairGeom& g, double acc[2][2]) {
+    if (yuk_far_rule<NO>(P, ytab, wt, wl, p, q, g, acc)) {
+        acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = 0.0;
+        yuk_far_rule_any<NO>(P, ytab, wt, wl, p, q, g, acc);
+    }
+}
+
+// Block of a far pair (cyclic distance >= 2), the Gauss order chosen by its gap.
+__device__ __forceinline__ void yuk_far_block(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
+                                              const WLow& wl, int p, int q, double B[2][2]) {
+    const int n = P.n;
+    const int p1 = p + 1 == n ? 0 : p + 1, q1 = q + 1 == n ? 0 : q + 1;
+    PairGeom g;
+    g.px0 = P.nodes[2 * p];
+    g.py0 = P.nodes[2 * p + 1];
+    g.qx0 = P.nodes[2 * q];
+    g.qy0 = P.nodes[2 * q + 1];
+    g.pex = P.nodes[2 * p1] - g.px0;
+    g.pey = P.nodes[2 * p1 + 1] - g.py0;
+    g.qex = P.nodes[2 * q1] - g.qx0;
+    g.qey = P.nodes[2 * q1 + 1] - g.qy0;
+    const double hp = P.h[p], hq = P.h[q];
+    const double mdx = g.px0 + 0.5 * g.pex - g.qx0 - 0.5 * g.qex, mdy = g.py0 + 0.5 * g.pey - g.qy0 - 0.5 * g.qey;
+    const double gap = (sqrt(fma(mdx, mdx, mdy * mdy)) - 0.5 * (hp + hq)) / fmax(hp, hq);
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    switch (yukawa_order(gap)) {
+        case 8: yuk_far_order<8>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 6: yuk_far_order<6>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 5: yuk_far_order<5>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 4: yuk_far_order<4>(P, ytab, wt, wl, p, q, g, acc); break;
+        default: yuk_far_order<3>(P, ytab, wt, wl, p, q, g, acc); break;
+    }
+    const double sc = kInv2Pi * hp * hq;
+#pragma unroll
+    for (int al = 0; al < 2; ++al)
+#pragma unroll
+        for (int be = 0; be < 2; ++be) B[al][be] = sc * acc[al][be];
+}
+
+__device__ __forceinline__ void yuk_load_table(const YukParams& P, double* ytab) {
+    for (int t = threadIdx.x; t < YK_ALL_DOUBLES; t += blockDim.x) ytab[t] = P.ytab[t];
+}
+
+// Entry (i, j) of the tile is the sum of the four pair blocks that hold its hat
+// functions: blk[a][b] is the block of the panels (i0 - 1 + a, j0 - 1 + b).
+__device__ __forceinline__ void yuk_tile_store(const YukParams& P, const double (*blk)[4], int i0, int j0) {
     if (threadIdx.x < YT * YT) {
         const int ti = threadIdx.x / YT, tj = threadIdx.x % YT;
         const int i = i0 + ti, j = j0 + tj;
-        if (i < n && j < n) {
+        if (i < P.n && j < P.n) {
             const int a = ti + 1, b = tj + 1;
             const double v = blk[a * (YT + 1) + b][0] + blk[a * (YT + 1) + b - 1][1] +
                              blk[(a - 1) * (YT + 1) + b][2] + blk[(a - 1) * (YT + 1) + b - 1][3];
-            P.Sy[(int64_t)i * n + j] = make_double2(v, 0.0);
+            P.Sy[(int64_t)i * P.n + j] = make_double2(v, 0.0);
         }
     }
+}
+
+// Tiles that hold no self or adjacent pair: far blocks only. Tiles with such a pair
+// return at once (the near kernel owns them).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void asm_yukawa_far_kernel(YukParams P, W8 wt, WLow wl) {
+    if (yuk_tile_near(blockIdx.y, blockIdx.x, P.n)) return;
+    __shared__ double blk[(YT + 1) * (YT + 1)][4];
+    __shared__ double ytab[YK_ALL_DOUBLES];
+    yuk_load_table(P, ytab);
+    __syncthreads();
+    const int n = P.n;
+    const int i0 = blockIdx.y * YT, j0 = blockIdx.x * YT;
+    const int t = threadIdx.x;
+    const int p = (i0 - 1 + t / (YT + 1) + n) % n, q = (j0 - 1 + t % (YT + 1) + n) % n;
+    const int d = (q - p + n) % n;
+    double B[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    // a self or adjacent pair can sit only in a slot no entry of this tile uses
+    if (!(d <= 1 || d == n - 1)) yuk_far_block(P, ytab, wt, wl, p, q, B);
+    blk[t][0] = B[0][0];
+    blk[t][1] = B[0][1];
+    blk[t][2] = B[1][0];
+    blk[t][3] = B[1][1];
+    __syncthreads();
+    yuk_tile_store(P, blk, i0, j0);
+}
+
+// The tiles listed in `tiles` (those with a self or adjacent pair): near pairs by
+// the singular quadrature, the rest like the far kernel.
+__global__ __launch_bounds__(256) void asm_yukawa_near_kernel(YukParams P, W8 wt, WLow wl,
+                                                              const int2* __restrict__ tiles) {
+    __shared__ double blk[(YT + 1) * (YT + 1)][4];
+    __shared__ double ytab[YK_ALL_DOUBLES];
+    yuk_load_table(P, ytab);
+    __syncthreads();
+    const int n = P.n;
+    const int2 tb = tiles[blockIdx.x];
+    const int i0 = tb.x * YT, j0 = tb.y * YT;
+    const int t = threadIdx.x;
+    const int p = (i0 - 1 + t / (YT + 1) + n) % n, q = (j0 - 1 + t % (YT + 1) + n) % n;
+    const int d = (q - p + n) % n;
+    double B[2][2];
+    if (d <= 1 || d == n - 1) {
+        const int s = d == 0 ? 1 : (d == 1 ? 2 : 0);
+        double2 So[2][2], Do[2][2];
+        near_pair_blocks<false, true>(P.gx + 8 * p, P.gy + 8 * p, P.gx + 8 * q, P.gy + 8 * q, P.h[p], P.h[q],
+                                      P.nx[p], P.ny[p], P.nx[q], P.ny[q], s, P.kappa, ytab, P.gl32, wt, So, Do);
+#pragma unroll
+        for (int al = 0; al < 2; ++al)
+#pragma unroll
+            for (int be = 0; be < 2; ++be) B[al][be] = So[al][be].x;
+    } else {
+        yuk_far_block(P, ytab, wt, wl, p, q, B);
+    }
+    blk[t][0] = B[0][0];
+    blk[t][1] = B[0][1];
+    blk[t][2] = B[1][0];
+    blk[t][3] = B[1][1];
+    __syncthreads();
+    yuk_tile_store(P, blk, i0, j0);
 }
 
 // Averages the entries (i, j) and (j, i) on the band |i - j| <= 2 (cyclic), like S.
@@ -849,16 +1077,32 @@ void launch_assemble_yukawa(Op& op, double kappa, double2* Sy) {
     WLow wlow;
     far_rules(op, wt, wlow);
     YukParams yp;
-    yp.gx = op.gx; yp.gy = op.gy; yp.h = op.h; yp.nx = op.nx; yp.ny = op.ny;
+    yp.gx = op.gx; yp.gy = op.gy; yp.nodes = op.nodes; yp.h = op.h; yp.nx = op.nx; yp.ny = op.ny;
     yp.ytab = c.yk_tab; yp.gl32 = c.gl32; yp.Sy = Sy; yp.kappa = kappa; yp.n = n;
-    const unsigned nt = (unsigned)((n + YT - 1) / YT);
-    FDS_REQUIRE(nt <= 65535u, FDS_ERR_NOTIMPL, "Yukawa operator limited to n <= 983025");
+    const int nt = (n + YT - 1) / YT;
+    FDS_REQUIRE(nt <= 65535, FDS_ERR_NOTIMPL, "Yukawa operator limited to n <= 983025");
+    // Tiles with a self or adjacent pair lie within two tile rows of the diagonal or
+    // in the wrap-around corners; the predicate decides among these candidates.
+    std::vector<int2> near;
+    for (int bi = 0; bi < nt; ++bi) {
+        int cand[9] = {bi - 2, bi - 1, bi, bi + 1, bi + 2, 0, 1, nt - 2, nt - 1};
+        for (int& v : cand) v = ((v % nt) + nt) % nt;
+        std::sort(cand, cand + 9);
+        const int nc = (int)(std::unique(cand, cand + 9) - cand);
+        for (int k = 0; k < nc; ++k)
+            if (yuk_tile_near(bi, cand[k], n)) near.push_back(make_int2(bi, cand[k]));
+    }
+    int2* dnear = static_cast<int2*>(c.dmalloc(sizeof(int2) * near.size()));
+    FDS_HIP_TRY(hipMemcpyAsync(dnear, near.data(), sizeof(int2) * near.size(), hipMemcpyHostToDevice, c.stream));
     {
         KScope _ks(c, "asm_yukawa");
-        hipLaunchKernelGGL(asm_yukawa_kernel, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt);
+        hipLaunchKernelGGL(asm_yukawa_far_kernel, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt, wlow);
+        hipLaunchKernelGGL(asm_yukawa_near_kernel, dim3((unsigned)near.size()), dim3(256), 0, c.stream, yp, wt,
+                           wlow, dnear);
         hipLaunchKernelGGL(sym_band_kernel, dim3((3 * n + 255) / 256), dim3(256), 0, c.stream, Sy, n);
     }
     FDS_HIP_TRY(hipGetLastError());
+    c.dfree(dnear);
 }
 
 }  // namespace fds

@@ -27,8 +27,9 @@ of the Yukawa kernel (1/2pi) K0(kappa R) (Helmholtz at the imaginary wavenumber
 i kappa), in FP64:
   x < YK_XS   ascending series (A&S 9.6.12, 9.6.13):
                 I0 = sum q^m/(m!)^2,  K0 = -(log(x/2) + gamma) I0 + sum_{m>=1} H_m q^m/(m!)^2
-  YK_XS <= x < XA  exp(x) K0(x) interpolated on unit intervals like the tables above
-  x >= XA     K0 = sqrt(pi/(2x)) exp(-x) sum_k a_k(0) x^-k  (A&S 9.7.2)
+  YK_XS <= x < YK_XA  K0(x) itself (no exponential scaling, so the device needs no exp
+                      there) interpolated on unit intervals like the tables above
+  x >= YK_XA  K0 = sqrt(pi/(2x)) exp(-x) sum_k a_k(0) x^-k  (A&S 9.7.2)
 checked against mpmath in relative error (4e-16 max(|f|, 1) in the series range,
 where the log term dominates, 6e-16 relative elsewhere).
 
@@ -217,6 +218,7 @@ def table32():
 
 
 YK_XS = 2
+YK_XA = 40
 YK_NSER = 16
 
 
@@ -230,13 +232,13 @@ def yk_sets():
             H += mp.mpf(1) / m
         ci0.append(1 / f2)
         ck0.append(H / f2)
-    f = lambda x: mp.exp(x) * mp.besselk(0, x)
-    tab = [cheb_monomial(f, c) for c in range(YK_XS, XA)]
-    # asymptotic: first neglected term below 1e-18 at x = XA
+    f = lambda x: mp.besselk(0, x)
+    tab = [cheb_monomial(f, c) for c in range(YK_XS, YK_XA)]
+    # asymptotic: first neglected term below 1e-18 at x = YK_XA
     a = [mp.mpf(1)]
     for k in range(1, 60):
         a.append(a[-1] * (0 - (2 * k - 1) ** 2) / (k * 8))
-    nas = next(k for k in range(2, 60) if abs(a[k]) / mp.mpf(XA) ** k < 1e-18)
+    nas = next(k for k in range(2, 60) if abs(a[k]) / mp.mpf(YK_XA) ** k < 1e-18)
     return [float(v) for v in ci0], [float(v) for v in ck0], [[float(v) for v in cc] for cc in tab], \
         [float(v) for v in a[:nas]]
 
@@ -247,16 +249,16 @@ def yk_emulate(x, ci0, ck0, tab, asy):
         q = x * x / 4
         i0 = horner(ci0, q)
         return -(np.log(0.5 * x) + np.euler_gamma) * i0 + q * horner(ck0[1:], q)
-    if x < XA:
+    if x < YK_XA:
         c = int(np.floor(x))
-        return np.exp(-x) * horner(tab[c - YK_XS], x - (c + 0.5))
+        return horner(tab[c - YK_XS], x - (c + 0.5))
     return np.sqrt(np.pi / (2.0 * x)) * np.exp(-x) * horner(asy, 1.0 / x)
 
 
 def yk_check(sets):
     xs = np.concatenate([np.geomspace(1e-6, YK_XS, 300, endpoint=False),
-                         np.linspace(YK_XS, XA, 2400, endpoint=False),
-                         np.linspace(XA, 200, 600)])
+                         np.linspace(YK_XS, YK_XA, 3800, endpoint=False),
+                         np.linspace(YK_XA, 200, 600)])
     worst = 0.0
     for x in xs:
         ref = float(mp.besselk(0, mp.mpf(float(x))))
@@ -331,12 +333,12 @@ def main():
             fh.write(" },\n")
         fh.write("};\n")
         ci0, ck0, ytab, yasy = yk
-        fh.write(f"#define YK_XS {YK_XS}\n#define YK_NSER {YK_NSER}\n#define YK_NASY {len(yasy)}\n")
+        fh.write(f"#define YK_XS {YK_XS}\n#define YK_XA {YK_XA}\n#define YK_NSER {YK_NSER}\n#define YK_NASY {len(yasy)}\n")
         fh.write("static constexpr double YK_SER_I0[%d] = {" % len(ci0) + ", ".join(repr(v) for v in ci0) + "};\n")
         fh.write("static constexpr double YK_SER_K0[%d] = {" % len(ck0) + ", ".join(repr(v) for v in ck0) + "};\n")
         fh.write("static constexpr double YK_ASY[%d] = {" % len(yasy) + ", ".join(repr(v) for v in yasy) + "};\n")
-        fh.write(f"// [interval c-{YK_XS}][coefficient of t^m] of exp(x) K0(x)\n")
-        fh.write(f"static constexpr double YK_TAB[{XA - YK_XS}][{DEG + 1}] = {{\n")
+        fh.write(f"// [interval c-{YK_XS}][coefficient of t^m] of K0(x)\n")
+        fh.write(f"static constexpr double YK_TAB[{YK_XA - YK_XS}][{DEG + 1}] = {{\n")
         for cc in ytab:
             fh.write("  {" + ", ".join(repr(v) for v in cc) + "},\n")
         fh.write("};\n")
