@@ -43,7 +43,12 @@ def test_yukawa_eval_parity(ctx, kappa):
     assert np.all(np.abs(out[:, 1] - reg) <= 4e-15 * np.maximum(terms, 1.0))
 
 
-YUK_CASES = [("circle", 64, 1.0), ("star", 200, 10.0), ("ellipse", 257, 5.0), ("random", 131, 2.0)]
+# n = 16, 46, 151 leave one entry in the last 15-wide tile (the tile classes of
+# the assembly meet at the wrap-around); k = 60 on the star takes most
+# arguments k R past the table into the asymptotic range; k = 1 on the unit
+# circle keeps every argument in the series range.
+YUK_CASES = [("circle", 64, 1.0), ("star", 200, 10.0), ("ellipse", 257, 5.0), ("random", 131, 2.0),
+             ("ellipse", 16, 2.0), ("circle", 46, 3.0), ("random", 151, 7.0), ("star", 300, 60.0)]
 
 
 @pytest.mark.parametrize("kind,n,k", YUK_CASES)
