@@ -179,6 +179,22 @@ fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n,
  *   (1/2 pi) (K0(kappa R) + log R), continuous at R = 0 */
 fds_status fds_yukawa_eval(fds_ctx ctx, double kappa, const double* R, int64_t n, double* out);
 
+/* ------------------------------------------------------------ mesh generation */
+
+/* Equal-chord (homogeneous) mesh of a closed curve (paper, Laplacian Filters,
+ * Two-Dimensional Case: on a homogeneously discretised curve the filter is
+ * diagonalised by the DFT; fds_filter then builds it in closed form). The curve
+ * is the trigonometric polynomial
+ *     x(t) = sum_{m=0}^{degree} ax[m] cos(m t) + bx[m] sin(m t),  y(t) likewise,
+ * t in [0, 2 pi), counter-clockwise and simple. Returns in nodes (host, [n][2])
+ * the points r(t_0 = 0), r(t_1), ..., r(t_{n-1}), 0 < t_1 < ... < t_{n-1} < 2 pi,
+ * whose n chords |r(t_{i+1}) - r(t_i)| (cyclic) are equal, and that length in
+ * *chord (may be NULL). ax, bx, ay, by: host [degree + 1] doubles (bx[0], by[0]
+ * unused). 4 <= n <= 2^24, 1 <= degree <= 4096. Runs on the host (no context,
+ * no GPU); FDS_ERR_ARG if no such mesh is found (e.g. a self-intersecting curve). */
+fds_status fds_equal_chord_nodes(int32_t degree, const double* ax, const double* bx, const double* ay,
+                                 const double* by, int64_t n, double* nodes, double* chord);
+
 /* Complex GEMM on the FP64 matrix cores (the dense contractions of the
  * compression and solve stages run on this kernel):
  *   C = alpha op(A) op(B) + beta C,  column-major, C is m x n, inner size k,

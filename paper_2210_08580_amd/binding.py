@@ -93,6 +93,8 @@ _SIGS = {
                                               C.POINTER(fds_solve_stats)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_yukawa_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_equal_chord_nodes": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_void_p, C.c_void_p]),
     "fds_zinv": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "fds_zgemm": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                             C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
@@ -300,6 +302,21 @@ def fds_yukawa_eval(ctx: Ctx, kappa: float, R: torch.Tensor) -> torch.Tensor:
     out = torch.empty((R.numel(), 2), dtype=torch.float64, device="cuda")
     _check(lib().fds_yukawa_eval(ctx.handle, float(kappa), _ptr(R), R.numel(), _ptr(out)))
     return out
+
+
+def fds_equal_chord_nodes(trig, n: int):
+    """Equal-chord mesh of the trigonometric-polynomial curve trig = (ax, bx, ay, by)
+    (host call, no GPU needed): returns (nodes (n, 2) numpy array, chord length)."""
+    import numpy as np
+    ax, bx, ay, by = (np.ascontiguousarray(v, dtype=np.float64) for v in trig)
+    d = ax.size - 1
+    if not (bx.size == ay.size == by.size == d + 1):
+        raise ValueError("coefficient arrays of different lengths")
+    nodes = np.empty((int(n), 2), dtype=np.float64)
+    chord = C.c_double(0.0)
+    _check(lib().fds_equal_chord_nodes(d, ax.ctypes.data, bx.ctypes.data, ay.ctypes.data, by.ctypes.data,
+                                       int(n), nodes.ctypes.data, C.addressof(chord)))
+    return nodes, chord.value
 
 
 def fds_kernel_eval(ctx: Ctx, k: float, R: torch.Tensor) -> torch.Tensor:

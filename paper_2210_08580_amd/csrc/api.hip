@@ -47,7 +47,7 @@ void Ctx::dfree(void* p) {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
-                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy};
+                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy, gpow[0], gpow[1]};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
         ctx->dfree(U);
@@ -241,6 +241,11 @@ fds_status fds_yukawa_eval(fds_ctx ctx, double kappa, const double* R, int64_t n
     });
 }
 
+fds_status fds_equal_chord_nodes(int32_t degree, const double* ax, const double* bx, const double* ay,
+                                 const double* by, int64_t n, double* nodes, double* chord) {
+    return guarded([&] { equal_chord_mesh(degree, ax, bx, ay, by, n, nodes, chord); });
+}
+
 fds_status fds_kernel_eval(fds_ctx ctx, double k, const double* R, int64_t n, double* out) {
     return guarded([&] {
         FDS_REQUIRE(ctx && R && out && n >= 0, FDS_ERR_ARG, "bad argument");
@@ -338,6 +343,16 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
     op.n = n;
     op.k = k;
     op.prec = opts ? opts->precision : FDS_FP64;
+    {
+        double hmin = 1e300, hmax = 0.0, hsum = 0.0;
+        for (double v : hh) {
+            hmin = std::min(hmin, v);
+            hmax = std::max(hmax, v);
+            hsum += v;
+        }
+        op.h_mean = hsum / (double)n;
+        op.homog = hmax - hmin <= kHomogTol * op.h_mean;
+    }
     op.h_host = std::move(hh);
     try {
         const size_t nd = sizeof(double) * n;

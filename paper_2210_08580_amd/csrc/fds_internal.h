@@ -192,6 +192,12 @@ struct Op {
     double* gfac = nullptr;       // exact cyclic Thomas factors of G [3n+2] (small or irregular meshes)
     double* gband = nullptr;      // banded G^{-1} [(2 GW + 1) n] (regular meshes)
     double cheb_lo = 0.0, cheb_hi = 0.0;
+    // homogeneous (equal-chord) mesh: all panel lengths within kHomogTol of their mean
+    // h_mean; G and L are then circulant, the filter modes are the DFT modes, and
+    // G^{+-1/2} are circulants applied as bands (gpow[0]: p = -1, gpow[1]: p = +1)
+    bool homog = false;
+    double h_mean = 0.0;
+    double* gpow[2] = {nullptr, nullptr};
     // skeleton and Woodbury core
     int32_t rank = 0;
     std::vector<double> sv;       // singular values of the last truncating compression (host)
@@ -213,6 +219,11 @@ void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out);
 void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out);
 void launch_kernel_eval(Ctx& c, double k, const double* R, int64_t n, double* out);
 void launch_yukawa_eval(Ctx& c, double kappa, const double* R, int64_t n, double* out);
+// Relative spread of the panel lengths below which a mesh counts as homogeneous.
+constexpr double kHomogTol = 1e-10;
+// Equal-chord mesh of a trigonometric-polynomial curve (host, mesher.hip).
+void equal_chord_mesh(int d, const double* ax, const double* bx, const double* ay, const double* by, int64_t n,
+                      double* nodes, double* chord);
 // pipeline.hip: Gershgorin interval of the Gram matrix from host panel lengths
 void gram_gershgorin(const std::vector<double>& h, double& lo, double& hi);
 // assemble.hip

@@ -875,7 +875,96 @@ __global__ void cluster_ritz_kernel(const double* __restrict__ h, int n, const d
 }
 
 // ---------------------------------------------------------------- host driver
+// ---------------------------------------------------------------- homogeneous meshes
+// Paper, Laplacian Filters, Two-Dimensional Case: with all panels of length h, G
+// and L are circulant (G = (h/6) circ(4, 1, .., 1), L = (1/h) circ(2, -1, .., -1)),
+// the DFT diagonalises both, and the pencil eigenpairs are
+//   mu_m = lambda_L / lambda_G = 12 sin^2(pi m/n) / (h^2 (2 + cos(2 pi m/n))),
+//   vectors cos(2 pi m j/n), sin(2 pi m j/n),
+// mu increasing in min(m, n - m): the filter keeps the lowest frequencies and needs
+// no eigensolver. Column c of the basis holds mode code[c] = 2 m + (1 for the sine),
+// scaled to G-norm one: 1/sqrt(n lambda_G) for m = 0 and m = n/2, sqrt(2/(n lambda_G))
+// otherwise.
+__global__ void dft_basis_kernel(int n, double h, const int* __restrict__ code, double* __restrict__ X) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int col = blockIdx.y;
+    const int m = code[col] >> 1;
+    const bool sine = code[col] & 1;
+    double sm, cm, sv, cv;
+    sincospi(2.0 * (double)m / (double)n, &sm, &cm);
+    const double lamg = (h / 3.0) * (2.0 + cm);
+    const double w = (m == 0 || 2 * m == n) ? 1.0 : 2.0;
+    sincospi(2.0 * (double)(((int64_t)m * j) % n) / (double)n, &sv, &cv);
+    X[(int64_t)col * n + j] = (sine ? sv : cv) * sqrt(w / ((double)n * lamg));
+}
+
+static void dft_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const double h = op.h_mean;
+    const int start = keep_null ? 0 : 1;
+    int want = keep_null ? n_modes : n_modes - 1;
+    FDS_REQUIRE(want >= 1 && start + want <= n, FDS_ERR_ARG, "n_modes out of range");
+    // modes in increasing order of mu: m = 0, then (cos, sin) for m = 1 .. (n-1)/2, then
+    // the single m = n/2 for even n
+    std::vector<int> code;
+    std::vector<double> mu;
+    auto mu_of = [&](int m) {
+        const double s = std::sin(kPiHost * m / n);
+        return 12.0 * s * s / (h * h * (2.0 + std::cos(2.0 * kPiHost * m / n)));
+    };
+    code.push_back(0);
+    mu.push_back(0.0);
+    for (int m = 1; 2 * m < n; ++m) {
+        code.push_back(2 * m);
+        code.push_back(2 * m + 1);
+        mu.push_back(mu_of(m));
+        mu.push_back(mu_of(m));
+    }
+    if (n % 2 == 0) {
+        code.push_back(n);
+        mu.push_back(mu_of(n / 2));
+    }
+    code.erase(code.begin(), code.begin() + start);
+    mu.erase(mu.begin(), mu.begin() + start);
+    // the cut guard of the general path: never split a (near-)degenerate group
+    int ne = want;
+    while (ne < (int)mu.size() && mu[ne] - mu[ne - 1] <= cluster_rtol * std::max(std::fabs(mu[ne - 1]), std::fabs(mu[ne])))
+        ++ne;
+    code.resize(ne);
+    FDS_REQUIRE(ne <= 65535, FDS_ERR_NOTIMPL, "more than 65535 filter modes");
+    op.filt_lam.assign(mu.begin(), mu.begin() + std::min((int)mu.size(), ne + 2));
+    int* dcode = static_cast<int*>(c.dmalloc(sizeof(int) * ne));
+    FDS_HIP_TRY(hipMemcpyAsync(dcode, code.data(), sizeof(int) * ne, hipMemcpyHostToDevice, c.stream));
+    double* X = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
+    {
+        KScope _ks(c, "filter_dft");
+        hipLaunchKernelGGL(dft_basis_kernel, dim3((n + 255) / 256, ne), dim3(256), 0, c.stream, n, h, dcode, X);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    // the kept eigenvalues stay readable through lam_dev like the general path's Ritz values
+    double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * ne));
+    FDS_HIP_TRY(hipMemcpyAsync(dlam, mu.data(), sizeof(double) * ne, hipMemcpyHostToDevice, c.stream));
+    // the host vectors above must outlive the copies from pageable memory
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    c.dfree(dcode);
+    c.dfree(op.lam_dev);
+    op.lam_dev = dlam;
+    op.lam_dev_n = ne;
+    c.dfree(op.Vg);
+    c.dfree(op.Vn);
+    op.Vn = nullptr;
+    op.Vg = X;
+    op.n_eff = ne;
+}
+
 void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
+    if (op.homog) {
+        gram_gershgorin(op.h_host, op.cheb_lo, op.cheb_hi);
+        dft_filter_basis(op, n_modes, keep_null, cluster_rtol);
+        return;
+    }
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
     // bounds of the pencil's spectrum (Gershgorin on the host panel lengths):

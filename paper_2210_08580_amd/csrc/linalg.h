@@ -62,6 +62,8 @@ void gram_band_build(Ctx& c, const double* d, const double* e, int n, double* ba
 template <typename T>
 void gram_band_apply(Ctx& c, const double* band, int n, const T* X, int64_t ncols, T* Y);
 std::vector<double> cheb_coeffs(int p, double lo, double hi);
+// G^{p/2} (p = +-1) of a homogeneous mesh (panel length h) as a band (gram_band_apply layout)
+void gram_circ_band(Ctx& c, double h, int n, int p, double* band /* (2GW+1) n */);
 template <typename T>
 void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p, T* X,
                    int64_t ncols);

@@ -214,6 +214,57 @@ void gram_band_apply(Ctx& c, const double* band, int n, const T* X, int64_t ncol
 template void gram_band_apply<double>(Ctx&, const double*, int, const double*, int64_t, double*);
 template void gram_band_apply<double2>(Ctx&, const double*, int, const double2*, int64_t, double2*);
 
+// ============================================================ circulant G^{p/2}
+// On a homogeneous mesh (all panels of length h) G = (h/6) circ(4, 1, 0, ..., 0, 1)
+// has the DFT modes as eigenvectors with eigenvalues lambda_m = (h/3)(2 + cos(2 pi m/n)),
+// so G^{p/2} is the circulant whose first row is the inverse DFT of lambda^{p/2}:
+//   c_d = (1/n) sum_m lambda_m^{p/2} cos(2 pi m d/n).
+// lambda^{p/2} is analytic in the strip |Im theta| < acosh 2 (the branch point is
+// where 2 + cos theta = 0), so c_d decays like (2 + sqrt 3)^{-|d|}: below 1e-17 c_0
+// from |d| = 30 on, well inside the band half-width GW.
+__global__ void circ_row_kernel(double h, int n, int p, double* __restrict__ row) {
+    __shared__ double red[256];
+    const int d = blockIdx.x;
+    double acc = 0.0;
+    for (int m = threadIdx.x; m < n; m += blockDim.x) {
+        double sm, cm, sd, cd;
+        sincospi(2.0 * (double)m / (double)n, &sm, &cm);
+        const double lam = (h / 3.0) * (2.0 + cm);
+        const double f = p > 0 ? sqrt(lam) : 1.0 / sqrt(lam);
+        sincospi(2.0 * (double)(((int64_t)m * d) % n) / (double)n, &sd, &cd);
+        acc = fma(f, cd, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row[d] = red[0] / (double)n;
+}
+
+// band[t][i] = c_{|t - GW|}: the layout of gram_band_apply (row i, column i - GW + t)
+__global__ void circ_band_kernel(const double* __restrict__ row, int n, double* __restrict__ band) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)(2 * GW + 1) * n) return;
+    const int t = (int)(k / n);
+    band[k] = row[t >= GW ? t - GW : GW - t];
+}
+
+void gram_circ_band(Ctx& c, double h, int n, int p, double* band) {
+    FDS_REQUIRE(n > 2 * GW + 1, FDS_ERR_ARG, "circulant band needs n > 2 GW + 1");
+    double* row = static_cast<double*>(c.dmalloc(sizeof(double) * (GW + 1)));
+    {
+        KScope _ks(c, "gram_circ");
+        hipLaunchKernelGGL(circ_row_kernel, dim3(GW + 1), dim3(256), 0, c.stream, h, n, p, row);
+        const int64_t tot = (int64_t)(2 * GW + 1) * n;
+        hipLaunchKernelGGL(circ_band_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, row, n,
+                           band);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(row);
+}
+
 // ============================================================ Chebyshev G^{p/2}
 // f(x) = x^{p/2} on [lo, hi] expanded in Chebyshev polynomials of
 // t = (2x - lo - hi)/(hi - lo); coefficients by interpolation at Chebyshev points.
@@ -249,22 +300,27 @@ std::vector<double> cheb_coeffs(int p, double lo, double hi) {
 
 // One Clenshaw step for all vectors:
 //   bj = a_j X + 2 That(b1) - b2,  That(v) = (2 G v - (lo+hi) v)/(hi-lo)
-// final (last=1): Y = a_0 X + That(b1) - b2
+// final (tw = 1): Y = a_0 X + That(b1) - b2. A null b1 or b2 stands for zero (the
+// first two steps), so no buffer needs clearing; `out` may alias X (each element
+// reads only its own X entry).
 template <typename T>
 __global__ void clenshaw_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
-                                const T* __restrict__ X, const T* __restrict__ b1, const T* __restrict__ b2,
-                                T* __restrict__ out, int64_t ncols, double aj, double s1, double s0,
-                                double tw) {
+                                const T* X, const T* __restrict__ b1, const T* __restrict__ b2, T* out,
+                                int64_t ncols, double aj, double s1, double s0, double tw) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * ncols) return;
     const int i = (int)(t % n);
     const int64_t c = t / n;
     const int64_t o = c * n;
-    const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
-    const T gb = b1[o + i] * d[i] + b1[o + im] * e[im] + b1[o + ip] * e[i];
-    // That(b1) = s1 * G b1 + s0 * b1
-    const T th = gb * s1 + b1[o + i] * s0;
-    out[o + i] = X[o + i] * aj + th * tw - b2[o + i];
+    T v = X[o + i] * aj;
+    if (b1) {
+        const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
+        const T gb = b1[o + i] * d[i] + b1[o + im] * e[im] + b1[o + ip] * e[i];
+        // That(b1) = s1 * G b1 + s0 * b1
+        v = v + (gb * s1 + b1[o + i] * s0) * tw;
+    }
+    if (b2) v = v - b2[o + i];
+    out[o + i] = v;
 }
 
 template <typename T>
@@ -276,32 +332,26 @@ void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, d
     const size_t bytes = sizeof(T) * (size_t)n * ncols;
     T* bufs[3];
     for (int i = 0; i < 3; ++i) bufs[i] = static_cast<T*>(c.dmalloc(bytes));
-    FDS_HIP_TRY(hipMemsetAsync(bufs[1], 0, bytes, c.stream));
-    FDS_HIP_TRY(hipMemsetAsync(bufs[2], 0, bytes, c.stream));
     const double s1 = 2.0 / (hi - lo), s0 = -(hi + lo) / (hi - lo);
     const int64_t tot = (int64_t)n * ncols;
     const unsigned nb = (unsigned)((tot + 255) / 256);
-    // rotate: cur = b_j, p1 = b_{j+1}, p2 = b_{j+2}
+    // rotate: cur = b_j, p1 = b_{j+1}, p2 = b_{j+2} (b_{deg+1} = b_{deg+2} = 0)
     int cur = 0, p1 = 1, p2 = 2;
-    for (int j = deg; j >= 1; --j) {
+    for (int j = deg; j >= 0; --j) {
+        const T* b1 = j < deg ? bufs[p1] : nullptr;
+        const T* b2 = j < deg - 1 ? bufs[p2] : nullptr;
+        T* out = j > 0 ? bufs[cur] : X;
         {
-        KScope _ks(c, "gram_pow_half");
-        hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
-                           bufs[cur], ncols, a[j], s1, s0, 2.0);
-    }
+            KScope _ks(c, "gram_pow_half");
+            hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, b1, b2, out,
+                               ncols, a[j], s1, s0, j > 0 ? 2.0 : 1.0);
+        }
         FDS_HIP_TRY(hipGetLastError());
         const int t = p2;
         p2 = p1;
         p1 = cur;
         cur = t;
     }
-    {
-        KScope _ks(c, "gram_pow_half");
-        hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, bufs[p1], bufs[p2],
-                       bufs[cur], ncols, a[0], s1, s0, 1.0);
-    }
-    FDS_HIP_TRY(hipGetLastError());
-    FDS_HIP_TRY(hipMemcpyAsync(X, bufs[cur], bytes, hipMemcpyDeviceToDevice, c.stream));
     for (int i = 0; i < 3; ++i) c.dfree(bufs[i]);
 }
 template void gram_pow_half<double>(Ctx&, const double*, const double*, int, double, double, int, double*,

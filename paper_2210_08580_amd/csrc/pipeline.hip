@@ -213,12 +213,34 @@ void ensure_cheb_bounds(Op& op) {
     gram_gershgorin(op.h_host, op.cheb_lo, op.cheb_hi);
 }
 
+// The band of G^{p/2} (p = +-1) on a homogeneous mesh large enough for the band
+// (n > 4 GW, like the banded G^{-1}); null otherwise (Chebyshev series then).
+static const double* gram_circ(Op& op, int p) {
+    if (!op.homog || op.n <= 4 * GW) return nullptr;
+    double*& b = op.gpow[p > 0 ? 1 : 0];
+    if (!b) {
+        b = static_cast<double*>(op.ctx->dmalloc(sizeof(double) * (2 * GW + 1) * (size_t)op.n));
+        gram_circ_band(*op.ctx, op.h_mean, (int)op.n, p, b);
+    }
+    return b;
+}
+
 void apply_gram_power(Op& op, int p, double2* X, int64_t ncols) {
     if (p == -2) {
         gram_inv(op, X, ncols, X);
         return;
     }
     FDS_REQUIRE(p == 1 || p == -1, FDS_ERR_ARG, "p must be -2, -1 or 1");
+    if (ncols <= 0) return;
+    if (const double* band = gram_circ(op, p)) {
+        Ctx& c = *op.ctx;
+        const size_t bytes = sizeof(double2) * (size_t)op.n * ncols;
+        double2* t = static_cast<double2*>(c.dmalloc(bytes));
+        gram_band_apply<double2>(c, band, (int)op.n, X, ncols, t);
+        FDS_HIP_TRY(hipMemcpyAsync(X, t, bytes, hipMemcpyDeviceToDevice, c.stream));
+        c.dfree(t);
+        return;
+    }
     ensure_cheb_bounds(op);
     gram_pow_half<double2>(*op.ctx, op.g_diag, op.g_off, (int)op.n, op.cheb_lo, op.cheb_hi, p, X, ncols);
 }
@@ -228,9 +250,14 @@ const double* filter_basis_view(Op& op) {
         Ctx& c = *op.ctx;
         const size_t bytes = sizeof(double) * (size_t)op.n * op.n_eff;
         op.Vn = static_cast<double*>(c.dmalloc(bytes));
-        FDS_HIP_TRY(hipMemcpyAsync(op.Vn, op.Vg, bytes, hipMemcpyDeviceToDevice, c.stream));
-        ensure_cheb_bounds(op);
-        gram_pow_half<double>(c, op.g_diag, op.g_off, (int)op.n, op.cheb_lo, op.cheb_hi, 1, op.Vn, op.n_eff);
+        if (const double* band = gram_circ(op, 1)) {
+            gram_band_apply<double>(c, band, (int)op.n, op.Vg, op.n_eff, op.Vn);
+        } else {
+            FDS_HIP_TRY(hipMemcpyAsync(op.Vn, op.Vg, bytes, hipMemcpyDeviceToDevice, c.stream));
+            ensure_cheb_bounds(op);
+            gram_pow_half<double>(c, op.g_diag, op.g_off, (int)op.n, op.cheb_lo, op.cheb_hi, 1, op.Vn,
+                                  op.n_eff);
+        }
     }
     return op.Vn;
 }

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "curve_nodes", "circle", "star", "ellipse", "perturbed_circle",
-    "random_polar", "random_coeffs", "random_curve", "planewaves", "workload",
+    "random_polar", "random_coeffs", "random_curve", "curve_trig", "planewaves", "workload",
 ]
 
 
@@ -90,6 +90,27 @@ def curve_nodes(kind: str, n: int, **kw) -> np.ndarray:
     fn = {"circle": circle, "star": star, "ellipse": ellipse,
           "perturbed_circle": perturbed_circle, "random": random_curve}[kind]
     return np.ascontiguousarray(fn(n, **kw), dtype=np.float64)
+
+
+def curve_trig(kind: str, degree: int = 24, **kw):
+    """The same curve as curve_nodes(kind) as a trigonometric polynomial in
+    Cartesian form, x(t) = sum_m ax[m] cos(m t) + bx[m] sin(m t) (y likewise),
+    m = 0 .. degree: every curve here is one (degree 1 for the circle and the
+    ellipse, 6 for the star, 9 for the perturbed circle, 17 for the random curves).
+    Coefficients from the DFT of 4 (degree + 1) samples, entries below 1e-14 of the
+    largest set to zero. Returns (ax, bx, ay, by)."""
+    K = 4 * (degree + 1)
+    pts = curve_nodes(kind, K, **kw)
+    out = []
+    for col in (0, 1):
+        X = np.fft.rfft(pts[:, col]) / K
+        a = 2.0 * X.real[:degree + 1]
+        b = -2.0 * X.imag[:degree + 1]
+        a[0] *= 0.5
+        b[0] = 0.0
+        out += [a, b]
+    big = max(np.abs(v).max() for v in out)
+    return tuple(np.where(np.abs(v) < 1e-14 * big, 0.0, v) for v in out)
 
 
 def planewaves(seed: int, nrhs: int):
