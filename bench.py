@@ -44,6 +44,8 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form:
     from paper_2210_08580_amd import workloads as wl
 
     w = wl.workload(wname, n=n_sample, nrhs=nrhs, form=form)
+    if w.nodes is None:     # equal-chord workload: the oracle's mesher
+        w.nodes = geometry.equal_chord_nodes(w.trig, w.n_nodes)
     m = geometry.mesh(w.nodes)
     t = {}
     t0 = time.perf_counter()
@@ -88,6 +90,7 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form:
 WORKLOAD_DESC = {
     "star8192": "star r=1+0.3cos5t", "star4096": "star r=1+0.3cos5t",
     "ellipse16384": "ellipse 2 x 0.5", "circle256": "unit circle",
+    "star8192ec": "star r=1+0.3cos5t, equal-chord mesh",
 }
 
 
@@ -340,8 +343,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star8192",
-                    help="star8192 (default), star4096, ellipse16384, circle256, batch64 (64 curves, graph "
-                         "replay) or grad8192 (far-field gradient)")
+                    help="star8192 (default), star8192ec (equal-chord mesh), star4096, ellipse16384, circle256, "
+                         "batch64 (64 curves, graph replay) or grad8192 (far-field gradient)")
     ap.add_argument("--nrhs", type=int, default=None, help="right-hand sides (default: the workload's)")
     ap.add_argument("--variants", default="fp64,fp32",
                     help="assembly precisions to time: fp64 (plain) and/or fp32 (mixed)")
@@ -372,6 +375,8 @@ def main():
     from paper_2210_08580_amd import workloads as wl
 
     w = wl.workload(args.workload, nrhs=args.nrhs, form=args.form)
+    if w.nodes is None:     # equal-chord workload: the library's host mesher (outside the timed steps)
+        w.nodes, _ = B.fds_equal_chord_nodes(w.trig, w.n_nodes)
     n, nrhs = w.n, w.nrhs
     ctx = B.fds_ctx_create(0)
     if args.autotune:

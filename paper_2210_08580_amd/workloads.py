@@ -144,10 +144,14 @@ class Workload:
     seed: int = 0               # sketch seed
     angles: np.ndarray = None
     amps: np.ndarray = None
+    # equal-chord workloads: nodes is None; the caller meshes the curve `trig`
+    # (curve_trig coefficients) with n_nodes equal chords
+    trig: tuple = None
+    n_nodes: int = 0
 
     @property
     def n(self) -> int:
-        return int(self.nodes.shape[0])
+        return int(self.nodes.shape[0]) if self.nodes is not None else int(self.n_nodes)
 
     @property
     def nrhs(self) -> int:
@@ -161,6 +165,8 @@ def workload(name: str, n: int | None = None, nrhs: int | None = None,
     circle256   unit circle, k=1, EFIE, n=21 kept modes (M=10), rank cap 32, 8 RHS
     star4096    star r=1+0.3cos5t, k=10, n=255 (M=127), r=256, p=10, q=2, 256 RHS
     star8192    the same star at N=8192 (the throughput workload)
+    star8192ec  the same star and parameters on an equal-chord (homogeneous) mesh of
+                N=8192 nodes: nodes is None, the caller meshes w.trig
     ellipse16384  ellipse 2 x 0.5, k=5, n=511, r=128 (lossy), p=10, q=2, 1024 RHS
     """
     if name == "circle256":
@@ -173,6 +179,11 @@ def workload(name: str, n: int | None = None, nrhs: int | None = None,
         ang, amp = planewaves(1 if name == "star4096" else 2, nrhs or 256)
         return Workload(name, star(N), 10.0, form or "efie", 1.0, 255, 256, 10, 2,
                         0.0, 7, ang, amp)
+    if name == "star8192ec":
+        N = n or 8192
+        ang, amp = planewaves(2, nrhs or 256)
+        return Workload(name, None, 10.0, form or "efie", 1.0, 255, 256, 10, 2,
+                        0.0, 7, ang, amp, curve_trig("star"), N)
     if name == "ellipse16384":
         N = n or 16384
         ang, amp = planewaves(3, nrhs or 1024)
