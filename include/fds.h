@@ -332,8 +332,24 @@ fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_
  * projected block does not converge. */
 fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out);
 
+/* The skeleton by adaptive cross approximation instead (paper, Inversion of the
+ * structured matrices: Bebendorf's ACA is the other skeleton-detecting algorithm
+ * it cites). ACA with partial pivoting of the filtered compact part in the
+ * normalised coordinates, A_y = V_n B_y (N x N, read by rows and columns through
+ * its two factors, never formed): first row 0; each step takes the residual
+ * row, its largest entry outside the used columns as pivot, b = row / pivot, the
+ * residual pivot column as a, and the next row at the largest entry of a outside
+ * the used rows; it stops once ||a|| ||b|| <= tol ||S||_F (S the sum of the
+ * crosses so far) or after rank_cap crosses. A residual row that vanishes is
+ * skipped for the lowest unused row. fds_op_singular_values then returns the
+ * cross norms ||a_k|| ||b_k||. Same stage rules and views as fds_compress.
+ * Synchronises (once per cross). rank_out (host, may be NULL) receives r.
+ * Errors: FDS_ERR_ARG if rank_cap < 1 or tol < 0. */
+fds_status fds_compress_aca(fds_op op, int32_t rank_cap, double tol, int32_t* rank_out);
+
 /* Singular values (descending) of the projected block B of the last
- * truncating fds_compress call (none after the exact skeleton). Host call:
+ * truncating fds_compress call (none after the exact skeleton), or after
+ * fds_compress_aca the cross norms ||a_k|| ||b_k|| in step order. Host call:
  * copies min(cap, available) values to host `out`, the number to *count. */
 fds_status fds_op_singular_values(fds_op op, double* out, int32_t cap, int32_t* count);
 

@@ -93,6 +93,7 @@ _SIGS = {
                                               C.POINTER(fds_solve_stats)]),
     "fds_kernel_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
     "fds_yukawa_eval": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fds_compress_aca": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_int32)]),
     "fds_equal_chord_nodes": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                         C.c_void_p, C.c_void_p]),
     "fds_zinv": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
@@ -514,6 +515,13 @@ def fds_compress(op: Op, rank_cap: int, oversample: int = 10, power_iters: int =
                           float(tol), C.c_uint64(seed & ((1 << 64) - 1)))
     r = C.c_int32()
     _check(lib().fds_compress(op.handle, C.byref(o), C.byref(r)))
+    return r.value
+
+
+def fds_compress_aca(op: Op, rank_cap: int, tol: float = 0.0) -> int:
+    """Skeleton by adaptive cross approximation (partial pivoting); returns the rank."""
+    r = C.c_int32()
+    _check(lib().fds_compress_aca(op.handle, int(rank_cap), float(tol), C.byref(r)))
     return r.value
 
 

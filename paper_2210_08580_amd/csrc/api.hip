@@ -600,6 +600,15 @@ fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_
     });
 }
 
+fds_status fds_compress_aca(fds_op op, int32_t rank_cap, double tol, int32_t* rank_out) {
+    return guarded([&] {
+        FDS_REQUIRE(op != nullptr, FDS_ERR_ARG, "op is NULL");
+        require_stage(op->impl, Stage::Filtered, "fds_compress_aca");
+        run_compress_aca(op->impl, rank_cap, tol);
+        if (rank_out) *rank_out = op->impl.rank;
+    });
+}
+
 fds_status fds_op_singular_values(fds_op op, double* out, int32_t cap, int32_t* count) {
     return guarded([&] {
         FDS_REQUIRE(op && count && cap >= 0 && (out || cap == 0), FDS_ERR_ARG, "bad argument");
