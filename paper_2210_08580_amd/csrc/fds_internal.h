@@ -59,6 +59,7 @@ struct Ctx {
     fds_allocator alloc{};
     bool has_alloc = false;
     const char* gemm_tag = nullptr;            // profiling name of GEMM launches (nullptr: "gemm")
+    int split_hint = 0;                        // split-K factor forced on the next GEMMs (0: heuristic)
     bool autotune = false;                     // time GEMM split-K candidates on first use
     std::map<std::string, int> tuned;          // shape class -> chosen split-K factor
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
@@ -131,6 +132,16 @@ struct GemmTag {
     ~GemmTag() { c.gemm_tag = old; }
     GemmTag(const GemmTag&) = delete;
     GemmTag& operator=(const GemmTag&) = delete;
+};
+
+// Forces a split-K factor on the GEMMs enqueued in its scope.
+struct SplitHint {
+    Ctx& c;
+    int old;
+    SplitHint(Ctx& ctx, int z) : c(ctx), old(ctx.split_hint) { ctx.split_hint = z; }
+    ~SplitHint() { c.split_hint = old; }
+    SplitHint(const SplitHint&) = delete;
+    SplitHint& operator=(const SplitHint&) = delete;
 };
 
 enum class Stage : int { Assembled = 1, Filtered = 2, Compressed = 3, Factored = 4 };

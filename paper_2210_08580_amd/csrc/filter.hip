@@ -748,8 +748,13 @@ __device__ double block_sum(double v, double* sh) {
 
 // G-inner product Gram-Schmidt inside each cluster [cb[c], cb[c+1]) (workgroup
 // per cluster); X node-major [n][nw].
-__global__ void cluster_gs_kernel(Pencil P, const int* __restrict__ cb, int nw, double* __restrict__ X) {
-    __shared__ double sh[256];
+#ifndef GS_BS
+#define GS_BS 1024   // one wide workgroup per cluster: the strided column walks are latency-bound
+#endif
+
+__global__ __launch_bounds__(GS_BS) void cluster_gs_kernel(Pencil P, const int* __restrict__ cb, int nw,
+                                                           double* __restrict__ X) {
+    __shared__ double sh[GS_BS];
     const int n = P.n;
     const int c0 = cb[blockIdx.x], c1 = cb[blockIdx.x + 1];
     for (int j = c0; j < c1; ++j) {
@@ -1102,7 +1107,7 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
         FDS_HIP_TRY(hipGetLastError());
         {
             KScope _ks(c, "filter_cluster_gs");
-            hipLaunchKernelGGL(cluster_gs_kernel, dim3(ncl), dim3(256), 0, c.stream, P, dcb, ne, Xn);
+            hipLaunchKernelGGL(cluster_gs_kernel, dim3(ncl), dim3(GS_BS), 0, c.stream, P, dcb, ne, Xn);
         }
         FDS_HIP_TRY(hipGetLastError());
     }
@@ -1115,9 +1120,9 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     }
     FDS_HIP_TRY(hipGetLastError());
     // Newton-Schulz in the G inner product: with M = V^T G V = I + E (|E| ~ 1e-12 after
-    // the inverse iteration), V <- V (3I - M)/2 leaves V^T G V = I + O(E^2).
+    // the inverse iteration), V <- V (3I - M)/2 leaves V^T G V = I + O(E^2): one pass.
     double* M = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)ne * ne));
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < 1; ++pass) {
         gram_mul<double>(c, op.g_diag, op.g_off, n, X, ne, n, 1.0, 0.0, Wk, n);
         dgemm(c, OP_T, OP_N, ne, ne, n, 1.0, X, n, Wk, n, 0.0, M, ne);
         dgemm(c, OP_N, OP_N, n, ne, ne, -0.5, X, n, M, ne, 0.0, Xn, n);

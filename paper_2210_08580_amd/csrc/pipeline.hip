@@ -570,6 +570,10 @@ static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int
 // Right-hand side in j coordinates, w = G^{-1/2} v: -G^{-1} S G^{-1} f (EFIE),
 // -G^{-1} h (MFIE), the EFIE one + alpha times the MFIE one (CFIE). Needs only the
 // assembled operator.
+#ifndef RHS_SPLIT
+#define RHS_SPLIT 4
+#endif
+
 void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,
                     double2* w) {
     Ctx& c = *op.ctx;
@@ -580,7 +584,13 @@ void run_rhs_system(Op& op, int form, double alpha, const double2* f, const doub
     if (has_efie(form)) {
         FDS_REQUIRE(f != nullptr, FDS_ERR_ARG, "f is required for the EFIE/CFIE");
         gram_inv(op, f, nrhs, t);
-        // S = (S stored row-major)^T as a column-major array (S_y for YCFIE)
+        // S = (S stored row-major)^T as a column-major array (S_y for YCFIE). Split K
+        // in RHS_SPLIT parts: the output tiles of this product alone fill the chip
+        // with one workgroup per compute unit, each holding a whole unit's registers,
+        // so latency-bound kernels that run beside it (the filter's eigensolver on the
+        // side stream) would wait for a whole tile; with more, shorter work items they
+        // keep a few units and the product flows around them.
+        SplitHint sh(c, RHS_SPLIT);
         op_gemm(op, s_op(form), OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, w);
         gram_inv(op, w, nrhs, w);
     }
