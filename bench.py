@@ -102,7 +102,7 @@ def solve_limits(w):
     return 50, 1e-8
 
 
-def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_early=True):
+def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_early=True, marginal=True):
     """Times `steps` full steps of one precision variant, then `steps` solves of the
     same right-hand sides with the factors kept (the marginal rate); returns
     (seconds, profile, info, j, marginal seconds)."""
@@ -158,6 +158,8 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_ea
     t1 = time.perf_counter()
     B.fds_profile_enable(ctx, False)
     prof = B.fds_profile_read(ctx)
+    if not marginal:
+        return t1 - t0, prof, info, j, None
     op = build()
     solve(op)
     torch.cuda.synchronize()
@@ -414,6 +416,8 @@ def main():
                     help="let the GEMM autotuner time tile / split-K candidates per shape class (first use)")
     ap.add_argument("--form", default=None, choices=["efie", "mfie", "cfie", "ycfie"],
                     help="formulation (default: the workload's; ycfie = Yukawa-Calderon CFIE)")
+    ap.add_argument("--no-marginal", action="store_true",
+                    help="skip the solve-only (marginal) rate, e.g. so that a profile holds the timed steps only")
     ap.add_argument("--rhs-after-filter", action="store_true",
                     help="form the right-hand side after the filter instead of right after the assembly")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -458,12 +462,12 @@ def main():
     res = {}
     for prec in variants:
         el, prof, info, j, marg = run_variant(B, ctx, w, nodes, angles, amps, prec, args.steps, args.warmup,
-                                              rhs_early=not args.rhs_after_filter)
+                                              rhs_early=not args.rhs_after_filter, marginal=not args.no_marginal)
         far = prof.get("asm_far", (0.0, 1))
         asm_ms = far[0] / max(far[1], 1)
         res[prec] = {
             "value": nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-            "marginal_rhs_per_s": nrhs * args.steps / marg,
+            "marginal_rhs_per_s": nrhs * args.steps / marg if marg else None,
             "prof": prof, "info": info, "j": j,
             "assembly_entries_per_s": 3.0 * n * n / (asm_ms / 1e3) if asm_ms > 0 else None,
         }
