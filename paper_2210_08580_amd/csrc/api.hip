@@ -19,11 +19,10 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-void* Ctx::dmalloc(size_t bytes) {
-    if (bytes == 0) bytes = 16;
+void* Ctx::raw_alloc(size_t bytes, hipStream_t s) {
     void* p = nullptr;
     if (has_alloc) {
-        p = alloc.alloc(bytes, (void*)stream, alloc.user);
+        p = alloc.alloc(bytes, (void*)s, alloc.user);
         if (!p) throw Error{FDS_ERR_ALLOC, "allocator callback returned NULL"};
         return p;
     }
@@ -35,13 +34,85 @@ void* Ctx::dmalloc(size_t bytes) {
     return p;
 }
 
-void Ctx::dfree(void* p) {
-    if (!p) return;
+void Ctx::raw_free(void* p, hipStream_t s) {
     if (has_alloc) {
-        alloc.release(p, (void*)stream, alloc.user);
+        alloc.release(p, (void*)s, alloc.user);
         return;
     }
     (void)hipFree(p);
+}
+
+// size classes: powers of two up to 1 MiB, then multiples of 2 MiB
+static size_t size_class(size_t b) {
+    if (b <= ((size_t)1 << 20)) {
+        size_t c = 512;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (b + g - 1) / g * g;
+}
+
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+void* Ctx::dmalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    std::lock_guard<std::mutex> lk(pool_mu);
+    if (capturing(stream)) {
+        void* p = raw_alloc(bytes, stream);
+        live[p] = Block{bytes, stream, false};
+        return p;
+    }
+    const size_t cls = size_class(bytes);
+    void* p = nullptr;
+    auto it = cache.find({stream, cls});
+    if (it != cache.end() && !it->second.empty()) {
+        p = it->second.back();
+        it->second.pop_back();
+    } else {
+        try {
+            p = raw_alloc(cls, stream);
+        } catch (const Error&) {
+            // give the cached blocks back and try once more
+            for (auto& kv : cache)
+                for (void* q : kv.second) raw_free(q, kv.first.first);
+            cache.clear();
+            p = raw_alloc(cls, stream);
+        }
+    }
+    live[p] = Block{cls, stream, true};
+    return p;
+}
+
+void Ctx::dfree(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(pool_mu);
+    auto it = live.find(p);
+    if (it == live.end()) {   // not from dmalloc: hand it straight back
+        raw_free(p, stream);
+        return;
+    }
+    const Block b = it->second;
+    live.erase(it);
+    if (!b.pooled) {
+        raw_free(p, b.stream);
+    } else if (capturing(stream)) {
+        held.push_back({p, b.stream});
+    } else {
+        cache[{b.stream, b.bytes}].push_back(p);
+    }
+}
+
+void Ctx::release_cache() {
+    std::lock_guard<std::mutex> lk(pool_mu);
+    for (auto& kv : cache)
+        for (void* q : kv.second) raw_free(q, kv.first.first);
+    cache.clear();
+    for (auto& h : held) raw_free(h.first, h.second);
+    held.clear();
 }
 
 Op::~Op() {
@@ -152,16 +223,17 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
     return guarded([&] {
         if (!ctx) return;
         (void)hipStreamSynchronize(ctx->impl.stream);
-        if (ctx->impl.side) {
-            (void)hipStreamSynchronize(ctx->impl.side);
-            (void)hipStreamDestroy(ctx->impl.side);
-            ctx->impl.side = nullptr;
-        }
+        if (ctx->impl.side) (void)hipStreamSynchronize(ctx->impl.side);
         resolve_profile(ctx->impl);
         ctx->impl.dfree(ctx->impl.hk_tab);
         ctx->impl.dfree(ctx->impl.hk_tab32);
         ctx->impl.dfree(ctx->impl.gl32);
         ctx->impl.dfree(ctx->impl.yk_tab);
+        ctx->impl.release_cache();
+        if (ctx->impl.side) {
+            (void)hipStreamDestroy(ctx->impl.side);
+            ctx->impl.side = nullptr;
+        }
         delete ctx;
     });
 }

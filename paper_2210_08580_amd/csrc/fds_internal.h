@@ -4,6 +4,8 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -66,8 +68,25 @@ struct Ctx {
     float* hk_tab32 = nullptr;    // device copy of the single-precision table
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
+    // Device memory: a size-class cache in front of the allocator callback (or
+    // hipMalloc), one free list per stream, so that a block is reused only on the
+    // stream it was last allocated on (stream order then separates its old and new
+    // uses). While the stream is being captured into a graph, allocations go to the
+    // allocator directly and cached blocks freed meanwhile are never reused.
+    struct Block {
+        size_t bytes;
+        hipStream_t stream;
+        bool pooled;
+    };
+    std::mutex pool_mu;
+    std::unordered_map<void*, Block> live;
+    std::map<std::pair<hipStream_t, size_t>, std::vector<void*>> cache;
+    std::vector<std::pair<void*, hipStream_t>> held;
     void* dmalloc(size_t bytes);
     void dfree(void* p);
+    void release_cache();         // hands every cached (and held) block back to the allocator
+    void* raw_alloc(size_t bytes, hipStream_t s);
+    void raw_free(void* p, hipStream_t s);
 };
 
 // Brackets the launches made during its lifetime with two events on the
