@@ -350,12 +350,8 @@ fds_status fds_zinv(fds_ctx ctx, int64_t r, const void* A, void* Ainv, double* s
         FDS_REQUIRE(ctx && A && Ainv && r >= 1, FDS_ERR_ARG, "bad argument");
         FDS_REQUIRE(r <= 2048, FDS_ERR_NOTIMPL, "dense inverse of order above 2048");
         Ctx& c = ctx->impl;
-        double* st = static_cast<double*>(c.dmalloc(sizeof(double) * 2));
-        gj_inverse(c, (double2*)const_cast<void*>(A), (double2*)Ainv, (int)r, st);
         double hs[2];
-        FDS_HIP_TRY(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
-        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-        c.dfree(st);
+        gj_inverse(c, (double2*)const_cast<void*>(A), (double2*)Ainv, (int)r, hs);
         if (stats) {
             stats[0] = hs[0];
             stats[1] = hs[1];

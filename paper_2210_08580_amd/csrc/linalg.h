@@ -70,6 +70,7 @@ void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, d
 
 // Inverse of a complex r x r column-major matrix (A is left unchanged).
 // stats[0] = min |pivot|, stats[1] = max |A|.
+// stats (host, 2): min |pivot| and max |A| entry; waits for the device
 void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats);
 
 void real_to_complex(Ctx& c, const double* x, double2* y, int64_t n);

@@ -615,16 +615,42 @@ __global__ __launch_bounds__(256) void gj_nopiv_panel_kernel(const double2* __re
     }
 }
 
-// out[0] = max |R - I| for the r x r product R = A A^{-1}, out[1] = max |A| (one workgroup)
+// Per-workgroup partial maxima of |R - I| and |A| over the r x r product R = A A^{-1}:
+// part[2 b] and part[2 b + 1] for workgroup b (a grid-stride walk).
 __global__ void inv_check_kernel(const double2* __restrict__ R, const double2* __restrict__ A, int r,
-                                 double* __restrict__ out) {
+                                 double* __restrict__ part) {
     __shared__ double s0[256], s1[256];
     double e = 0.0, m = 0.0;
-    for (int64_t t = threadIdx.x; t < (int64_t)r * r; t += blockDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)r * r;
+         t += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(t % r), j = (int)(t / r);
         const double2 v = R[t];
         e = fmax(e, hypot(v.x - (i == j ? 1.0 : 0.0), v.y));
         m = fmax(m, hypot(A[t].x, A[t].y));
+    }
+    s0[threadIdx.x] = e;
+    s1[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + st]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// out[0] = max |R - I|, out[1] = max |A| from np partial pairs (one workgroup)
+__global__ void inv_check_final_kernel(const double* __restrict__ part, int np, double* __restrict__ out) {
+    __shared__ double s0[256], s1[256];
+    double e = 0.0, m = 0.0;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        e = fmax(e, part[2 * t]);
+        m = fmax(m, part[2 * t + 1]);
     }
     s0[threadIdx.x] = e;
     s1[threadIdx.x] = m;
@@ -725,25 +751,29 @@ __global__ void gj_stats_kernel(const double* __restrict__ bmax, int nblk, const
     }
 }
 
-void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats) {
+void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* hstats) {
     FDS_REQUIRE(r >= 1 && r <= 2048, FDS_ERR_NOTIMPL, "dense inverse of order above 2048");
     // augmented [A | I] ping-pong; the inverse ends in the right half
     const int64_t tot = 2 * (int64_t)r * r;
     const unsigned nblk = (unsigned)((tot + 255) / 256);
+    const int ncb = (int)std::min<int64_t>(64, ((int64_t)r * r + 255) / 256);   // residual-check workgroups
     double2* M0 = static_cast<double2*>(c.dmalloc(sizeof(double2) * 2 * (size_t)r * r));
     double2* M1 = static_cast<double2*>(c.dmalloc(sizeof(double2) * 2 * (size_t)r * r));
     double2* W = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * GJ_NB));
     int* perm = static_cast<int*>(c.dmalloc(sizeof(int) * (size_t)r));
-    double* pabs = static_cast<double*>(c.dmalloc(sizeof(double) * ((size_t)r + nblk + 2)));
+    // pabs [r] | bmax [nblk] | check partials [2 ncb] | out: check (2), stats (2)
+    double* pabs = static_cast<double*>(c.dmalloc(sizeof(double) * ((size_t)r + nblk + 2 * ncb + 4)));
     double* bmax = pabs + r;
-    double* chk = bmax + nblk;
+    double* cpart = bmax + nblk;
+    double* res = cpart + 2 * ncb;
     const dim3 ugrid((unsigned)((r + 63) / 64), (unsigned)((2 * r + 15) / 16));
     double2* in = M0;
     double2* out = M1;
     // Fast path: no row interchanges (K = I + W U / beta is a second-kind operator
     // whose pivots rarely need them), accepted when max |A A^{-1} - I| <= 8 eps r
     // (the backward-stable level; pivot growth shows as a larger residual);
-    // otherwise partial pivoting from the start.
+    // otherwise partial pivoting from the start. The residual and the pivot
+    // statistics are read back together (one host wait on the fast path).
     {
         KScope _ks(c, "gj_inverse");
         hipLaunchKernelGGL(gj_init_kernel, dim3(nblk), dim3(256), 0, c.stream, A, M0, r, bmax);
@@ -761,38 +791,43 @@ void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* stats) {
     zgemm(c, OP_N, OP_N, r, r, r, make_double2(1.0, 0.0), A, r, Ainv, r, make_double2(0.0, 0.0), out, r);
     {
         KScope _ks(c, "gj_inverse");
-        hipLaunchKernelGGL(inv_check_kernel, dim3(1), dim3(256), 0, c.stream, out, A, r, chk);
+        hipLaunchKernelGGL(inv_check_kernel, dim3(ncb), dim3(256), 0, c.stream, out, A, r, cpart);
+        hipLaunchKernelGGL(inv_check_final_kernel, dim3(1), dim3(256), 0, c.stream, cpart, ncb, res);
+        hipLaunchKernelGGL(gj_stats_kernel, dim3(1), dim3(256), 0, c.stream, bmax, (int)nblk, pabs, r, res + 2);
     }
     FDS_HIP_TRY(hipGetLastError());
-    double hchk[2];
-    FDS_HIP_TRY(hipMemcpyAsync(hchk, chk, sizeof(hchk), hipMemcpyDeviceToHost, c.stream));
+    double hres[4];
+    FDS_HIP_TRY(hipMemcpyAsync(hres, res, sizeof(hres), hipMemcpyDeviceToHost, c.stream));
     FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    if (!(hchk[0] <= 8.0 * 2.220446049250313e-16 * r)) {
+    if (!(hres[0] <= 8.0 * 2.220446049250313e-16 * r)) {
         in = M0;
         out = M1;
-        KScope _ks(c, "gj_inverse");
-        hipLaunchKernelGGL(gj_init_kernel, dim3(nblk), dim3(256), 0, c.stream, A, M0, r, bmax);
-        for (int j0 = 0; j0 < r;) {
-            const int rows = r - j0;
-            // the panel (rows of stride nb | 1 complex128) and its row order in at most 56 KiB of LDS
-            const int lim = (57344 / rows - 4) / 16;
-            int nb = std::max(1, std::min({GJ_NB, rows, lim}));
-            if ((nb | 1) > lim && nb > 1) --nb;
-            hipLaunchKernelGGL(gj_panel_kernel, dim3(1), dim3(256), (sizeof(double2) * (nb | 1) + sizeof(int)) * rows,
-                               c.stream, in, r, j0, nb, perm, W, pabs);
-            hipLaunchKernelGGL(gj_update_kernel, ugrid, dim3(256), 0, c.stream, in, out, r, j0, nb, perm, W);
-            std::swap(in, out);
-            j0 += nb;
+        {
+            KScope _ks(c, "gj_inverse");
+            hipLaunchKernelGGL(gj_init_kernel, dim3(nblk), dim3(256), 0, c.stream, A, M0, r, bmax);
+            for (int j0 = 0; j0 < r;) {
+                const int rows = r - j0;
+                // the panel (rows of stride nb | 1 complex128) and its row order in at most 56 KiB of LDS
+                const int lim = (57344 / rows - 4) / 16;
+                int nb = std::max(1, std::min({GJ_NB, rows, lim}));
+                if ((nb | 1) > lim && nb > 1) --nb;
+                hipLaunchKernelGGL(gj_panel_kernel, dim3(1), dim3(256),
+                                   (sizeof(double2) * (nb | 1) + sizeof(int)) * rows, c.stream, in, r, j0, nb, perm,
+                                   W, pabs);
+                hipLaunchKernelGGL(gj_update_kernel, ugrid, dim3(256), 0, c.stream, in, out, r, j0, nb, perm, W);
+                std::swap(in, out);
+                j0 += nb;
+            }
+            hipLaunchKernelGGL(gj_stats_kernel, dim3(1), dim3(256), 0, c.stream, bmax, (int)nblk, pabs, r, res + 2);
         }
         FDS_HIP_TRY(hipGetLastError());
         FDS_HIP_TRY(hipMemcpyAsync(Ainv, in + (size_t)r * r, sizeof(double2) * (size_t)r * r,
                                    hipMemcpyDeviceToDevice, c.stream));
+        FDS_HIP_TRY(hipMemcpyAsync(hres + 2, res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        FDS_HIP_TRY(hipStreamSynchronize(c.stream));
     }
-    {
-        KScope _ks(c, "gj_inverse");
-        hipLaunchKernelGGL(gj_stats_kernel, dim3(1), dim3(256), 0, c.stream, bmax, (int)nblk, pabs, r, stats);
-    }
-    FDS_HIP_TRY(hipGetLastError());
+    hstats[0] = hres[2];
+    hstats[1] = hres[3];
     c.dfree(M0);
     c.dfree(M1);
     c.dfree(W);

@@ -511,12 +511,8 @@ void run_factor(Op& op) {
     zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, K, r);
     add_diag(c, K, r, 1.0);
     op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
-    double* st = static_cast<double*>(c.dmalloc(sizeof(double) * 2));
-    gj_inverse(c, K, op.K, r, st);
     double hs[2];
-    FDS_HIP_TRY(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
-    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    c.dfree(st);
+    gj_inverse(c, K, op.K, r, hs);
     c.dfree(K);
     FDS_REQUIRE(hs[0] >= 64.0 * 2.220446049250313e-16 * hs[1], FDS_ERR_SINGULAR,
                 "Woodbury core is numerically singular");
