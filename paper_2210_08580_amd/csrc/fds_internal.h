@@ -61,7 +61,7 @@ struct Ctx {
     fds_allocator alloc{};
     bool has_alloc = false;
     const char* gemm_tag = nullptr;            // profiling name of GEMM launches (nullptr: "gemm")
-    int split_hint = 0;                        // split-K factor forced on the next GEMMs (0: heuristic)
+    int split_hint = 0;                        // least split-K factor of the next GEMMs (0: heuristic)
     bool autotune = false;                     // time GEMM split-K candidates on first use
     std::map<std::string, int> tuned;          // shape class -> chosen split-K factor
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
@@ -153,7 +153,7 @@ struct GemmTag {
     GemmTag& operator=(const GemmTag&) = delete;
 };
 
-// Forces a split-K factor on the GEMMs enqueued in its scope.
+// Raises the split-K factor of the GEMMs enqueued in its scope to at least z.
 struct SplitHint {
     Ctx& c;
     int old;

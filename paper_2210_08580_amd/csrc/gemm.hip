@@ -521,7 +521,7 @@ static int choose_config(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, 
     } else {
         cfg = split_for(((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N));
     }
-    if (c.split_hint > 0) return (cfg & 256) | std::min(c.split_hint, 64);
+    if (c.split_hint > 0) return (cfg & 256) | std::min(std::max(cfg & 255, c.split_hint), 64);
     if (!c.autotune) return cfg;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return cfg;
