@@ -123,9 +123,15 @@ typedef struct fds_solve_stats {
 
 /* Creates a context on GPU `device`; all work is ordered on `hip_stream`
  * (a hipStream_t; NULL = the default stream). `alloc` may be NULL (the
- * library then uses hipMalloc/hipFree). */
+ * library then uses hipMalloc/hipFree). Device memory that the library frees
+ * stays in the context's cache (per stream and size class) for its next
+ * allocations; the cache is handed back to `alloc` when an allocation fails
+ * and when the context is destroyed. Allocations made while the stream is
+ * being captured into a graph bypass the cache. */
 fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* alloc,
                           fds_ctx* out);
+/* Waits for the context's streams, returns its cached memory and destroys it
+ * (operators of the context must be destroyed first). */
 fds_status fds_ctx_destroy(fds_ctx ctx);
 /* Waits for all enqueued work; reports asynchronous device errors. */
 fds_status fds_sync(fds_ctx ctx);
