@@ -202,6 +202,9 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.yk_tab = (double*)x.dmalloc(sizeof(double) * YK_ALL_DOUBLES);
             FDS_HIP_TRY(hipMemcpyAsync(x.yk_tab, yk.data(), sizeof(double) * YK_ALL_DOUBLES, hipMemcpyHostToDevice,
                                        x.stream));
+            x.yk_tab32 = (float*)x.dmalloc(sizeof(float) * YK32_TAB_FLOATS);
+            FDS_HIP_TRY(hipMemcpyAsync(x.yk_tab32, &YK32_TAB[0][0], sizeof(float) * YK32_TAB_FLOATS,
+                                       hipMemcpyHostToDevice, x.stream));
             double g[64];
             gauss_legendre_01(32, g, g + 32);
             x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);
@@ -212,6 +215,7 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.dfree(x.hk_tab32);
             x.dfree(x.gl32);
             x.dfree(x.yk_tab);
+            x.dfree(x.yk_tab32);
             delete c;
             throw;
         }
@@ -229,6 +233,7 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
         ctx->impl.dfree(ctx->impl.hk_tab32);
         ctx->impl.dfree(ctx->impl.gl32);
         ctx->impl.dfree(ctx->impl.yk_tab);
+        ctx->impl.dfree(ctx->impl.yk_tab32);
         ctx->impl.release_cache();
         if (ctx->impl.side) {
             (void)hipStreamDestroy(ctx->impl.side);

@@ -753,6 +753,7 @@ struct YukParams {
     const double* __restrict__ nx;
     const double* __restrict__ ny;
     const double* __restrict__ ytab;
+    const float* __restrict__ ytab32;   // float32 interval table (FP32 operators)
     const double* __restrict__ gl32;
     double2* __restrict__ Sy;
     double kappa;
@@ -852,7 +853,24 @@ __device__ __forceinline__ void yuk_wts(const W8& wt, const WLow& wl, int v, dou
 // coefficients are wave-uniform scalar loads; otherwise each lane reads its own
 // from the LDS copy. Returns true when some argument lies outside the table; the
 // caller then redoes the block through yk_k0.
-template <int NO>
+typedef __attribute__((address_space(4))) const float const_float;
+
+// K0 at x (float) from the float32 interval table, the interval clamped like yk_k0_tab
+__device__ __forceinline__ double yk_k0_tab32(float x, const float* __restrict__ tab) {
+    int c = (int)x;
+    c = c < YK_XS ? YK_XS : (c > YK_XA - 1 ? YK_XA - 1 : c);
+    const float t = x - ((float)c + 0.5f);
+    const float* cf = tab + (c - YK_XS) * (YK32_DEG + 1);
+    float acc = cf[YK32_DEG];
+#pragma unroll
+    for (int m = YK32_DEG - 1; m >= 0; --m) acc = fmaf(acc, t, cf[m]);
+    return (double)acc;
+}
+
+// F32: the kernel values of the table range in single precision (distance squared
+// rounded to float, float sqrt, float32 table): relative error ~2e-7, like the FP32
+// far field of S, N and D; the accumulation stays in FP64.
+template <int NO, bool F32>
 __device__ __forceinline__ bool yuk_far_rule(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
                                              const WLow& wl, int p, int q, const PairGeom& g, double acc[2][2]) {
     double yb[NO], zb[NO];
@@ -864,37 +882,63 @@ __device__ __forceinline__ bool yuk_far_rule(const YukParams& P, const double* _
         double xa, ya, wa0, wa1;
         yuk_node<NO>(P, wl, p, g.px0, g.py0, g.pex, g.pey, u, xa, ya);
         yuk_wts<NO>(wt, wl, u, wa0, wa1);
-        double xv[NO];
-        double lo = 1e300, hi = 0.0;
+        typedef typename std::conditional<F32, float, double>::type real;
+        real xv[NO];
+        real lo = (real)1e30, hi = (real)0;
 #pragma unroll
         for (int v = 0; v < NO; ++v) {
             const double dx = xa - yb[v], dy = ya - zb[v];
-            xv[v] = P.kappa * sqrt_normal(fmax(fma(dx, dx, dy * dy), 1e-280));
+            const double s2 = fmax(fma(dx, dx, dy * dy), 1e-280);
+            if constexpr (F32)
+                xv[v] = (float)P.kappa * __builtin_sqrtf((float)s2);
+            else
+                xv[v] = P.kappa * sqrt_normal(s2);
             lo = fmin(lo, xv[v]);
             hi = fmax(hi, xv[v]);
         }
-        rare |= lo < (double)YK_XS || hi >= (double)YK_XA;
+        rare |= lo < (real)YK_XS || hi >= (real)YK_XA;
         const int c0 = __builtin_amdgcn_readfirstlane((int)xv[0]);
         const bool one = c0 >= YK_XS && c0 < YK_XA && (int)lo == c0 && (int)hi == c0;
         double r0 = 0.0, r1 = 0.0;
         if (__all(one)) {
-            const const_double* cf = (const const_double*)(P.ytab + (c0 - YK_XS) * (HK_DEG + 1));
-            const double cm = (double)c0 + 0.5;
+            if constexpr (F32) {
+                const const_float* cf = (const const_float*)(P.ytab32 + (c0 - YK_XS) * (YK32_DEG + 1));
+                const float cm = (float)c0 + 0.5f;
 #pragma unroll
-            for (int v = 0; v < NO; ++v) {
-                const double t = xv[v] - cm;
-                double k = cf[HK_DEG];
+                for (int v = 0; v < NO; ++v) {
+                    const float t = xv[v] - cm;
+                    float kf = cf[YK32_DEG];
 #pragma unroll
-                for (int m = HK_DEG - 1; m >= 0; --m) k = fma(k, t, cf[m]);
-                double w0, w1;
-                yuk_wts<NO>(wt, wl, v, w0, w1);
-                r0 = fma(w0, k, r0);
-                r1 = fma(w1, k, r1);
+                    for (int m = YK32_DEG - 1; m >= 0; --m) kf = fmaf(kf, t, cf[m]);
+                    const double k = (double)kf;
+                    double w0, w1;
+                    yuk_wts<NO>(wt, wl, v, w0, w1);
+                    r0 = fma(w0, k, r0);
+                    r1 = fma(w1, k, r1);
+                }
+            } else {
+                const const_double* cf = (const const_double*)(P.ytab + (c0 - YK_XS) * (HK_DEG + 1));
+                const double cm = (double)c0 + 0.5;
+#pragma unroll
+                for (int v = 0; v < NO; ++v) {
+                    const double t = xv[v] - cm;
+                    double k = cf[HK_DEG];
+#pragma unroll
+                    for (int m = HK_DEG - 1; m >= 0; --m) k = fma(k, t, cf[m]);
+                    double w0, w1;
+                    yuk_wts<NO>(wt, wl, v, w0, w1);
+                    r0 = fma(w0, k, r0);
+                    r1 = fma(w1, k, r1);
+                }
             }
         } else {
 #pragma unroll
             for (int v = 0; v < NO; ++v) {
-                const double k = yk_k0_tab(xv[v], ytab);
+                double k;
+                if constexpr (F32)
+                    k = yk_k0_tab32(xv[v], P.ytab32);
+                else
+                    k = yk_k0_tab(xv[v], ytab);
                 double w0, w1;
                 yuk_wts<NO>(wt, wl, v, w0, w1);
                 r0 = fma(w0, k, r0);
@@ -937,16 +981,17 @@ __device__ __forceinline__ void yuk_far_rule_any(const YukParams& P, const doubl
     }
 }
 
-template <int NO>
+template <int NO, bool F32>
 __device__ __forceinline__ void yuk_far_order(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
                                               const WLow& wl, int p, int q, const PairGeom& g, double acc[2][2]) {
-    if (yuk_far_rule<NO>(P, ytab, wt, wl, p, q, g, acc)) {
+    if (yuk_far_rule<NO, F32>(P, ytab, wt, wl, p, q, g, acc)) {
         acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = 0.0;
         yuk_far_rule_any<NO>(P, ytab, wt, wl, p, q, g, acc);
     }
 }
 
 // Block of a far pair (cyclic distance >= 2), the Gauss order chosen by its gap.
+template <bool F32>
 __device__ __forceinline__ void yuk_far_block(const YukParams& P, const double* __restrict__ ytab, const W8& wt,
                                               const WLow& wl, int p, int q, double B[2][2]) {
     const int n = P.n;
@@ -965,11 +1010,11 @@ __device__ __forceinline__ void yuk_far_block(const YukParams& P, const double* 
     const double gap = (sqrt(fma(mdx, mdx, mdy * mdy)) - 0.5 * (hp + hq)) / fmax(hp, hq);
     double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     switch (yukawa_order(gap)) {
-        case 8: yuk_far_order<8>(P, ytab, wt, wl, p, q, g, acc); break;
-        case 6: yuk_far_order<6>(P, ytab, wt, wl, p, q, g, acc); break;
-        case 5: yuk_far_order<5>(P, ytab, wt, wl, p, q, g, acc); break;
-        case 4: yuk_far_order<4>(P, ytab, wt, wl, p, q, g, acc); break;
-        default: yuk_far_order<3>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 8: yuk_far_order<8, F32>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 6: yuk_far_order<6, F32>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 5: yuk_far_order<5, F32>(P, ytab, wt, wl, p, q, g, acc); break;
+        case 4: yuk_far_order<4, F32>(P, ytab, wt, wl, p, q, g, acc); break;
+        default: yuk_far_order<3, F32>(P, ytab, wt, wl, p, q, g, acc); break;
     }
     const double sc = kInv2Pi * hp * hq;
 #pragma unroll
@@ -999,7 +1044,9 @@ __device__ __forceinline__ void yuk_tile_store(const YukParams& P, const double 
 
 // Tiles that hold no self or adjacent pair: far blocks only. Tiles with such a pair
 // return at once (the near kernel owns them).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void asm_yukawa_far_kernel(YukParams P, W8 wt, WLow wl) {
+template <bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void asm_yukawa_far_kernel(YukParams P, W8 wt,
+                                                                                                   WLow wl) {
     if (yuk_tile_near(blockIdx.y, blockIdx.x, P.n)) return;
     __shared__ double blk[(YT + 1) * (YT + 1)][4];
     __shared__ double ytab[YK_ALL_DOUBLES];
@@ -1012,7 +1059,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     const int d = (q - p + n) % n;
     double B[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     // a self or adjacent pair can sit only in a slot no entry of this tile uses
-    if (!(d <= 1 || d == n - 1)) yuk_far_block(P, ytab, wt, wl, p, q, B);
+    if (!(d <= 1 || d == n - 1)) yuk_far_block<F32>(P, ytab, wt, wl, p, q, B);
     blk[t][0] = B[0][0];
     blk[t][1] = B[0][1];
     blk[t][2] = B[1][0];
@@ -1046,7 +1093,7 @@ __global__ __launch_bounds__(256) void asm_yukawa_near_kernel(YukParams P, W8 wt
 #pragma unroll
             for (int be = 0; be < 2; ++be) B[al][be] = So[al][be].x;
     } else {
-        yuk_far_block(P, ytab, wt, wl, p, q, B);
+        yuk_far_block<false>(P, ytab, wt, wl, p, q, B);
     }
     blk[t][0] = B[0][0];
     blk[t][1] = B[0][1];
@@ -1078,7 +1125,7 @@ void launch_assemble_yukawa(Op& op, double kappa, double2* Sy) {
     far_rules(op, wt, wlow);
     YukParams yp;
     yp.gx = op.gx; yp.gy = op.gy; yp.nodes = op.nodes; yp.h = op.h; yp.nx = op.nx; yp.ny = op.ny;
-    yp.ytab = c.yk_tab; yp.gl32 = c.gl32; yp.Sy = Sy; yp.kappa = kappa; yp.n = n;
+    yp.ytab = c.yk_tab; yp.ytab32 = c.yk_tab32; yp.gl32 = c.gl32; yp.Sy = Sy; yp.kappa = kappa; yp.n = n;
     const int nt = (n + YT - 1) / YT;
     FDS_REQUIRE(nt <= 65535, FDS_ERR_NOTIMPL, "Yukawa operator limited to n <= 983025");
     // Tiles with a self or adjacent pair lie within two tile rows of the diagonal or
@@ -1096,7 +1143,10 @@ void launch_assemble_yukawa(Op& op, double kappa, double2* Sy) {
     FDS_HIP_TRY(hipMemcpyAsync(dnear, near.data(), sizeof(int2) * near.size(), hipMemcpyHostToDevice, c.stream));
     {
         KScope _ks(c, "asm_yukawa");
-        hipLaunchKernelGGL(asm_yukawa_far_kernel, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt, wlow);
+        if (op.prec == FDS_FP32)
+            hipLaunchKernelGGL(asm_yukawa_far_kernel<true>, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt, wlow);
+        else
+            hipLaunchKernelGGL(asm_yukawa_far_kernel<false>, dim3(nt, nt), dim3(256), 0, c.stream, yp, wt, wlow);
         hipLaunchKernelGGL(asm_yukawa_near_kernel, dim3((unsigned)near.size()), dim3(256), 0, c.stream, yp, wt,
                            wlow, dnear);
         hipLaunchKernelGGL(sym_band_kernel, dim3((3 * n + 255) / 256), dim3(256), 0, c.stream, Sy, n);

@@ -68,6 +68,7 @@ struct Ctx {
     float* hk_tab32 = nullptr;    // device copy of the single-precision table
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
+    float* yk_tab32 = nullptr;    // device copy of the float32 K0 interval table
     // Device memory: a size-class cache in front of the allocator callback (or
     // hipMalloc), one free list per stream, so that a block is reused only on the
     // stream it was last allocated on (stream order then separates its old and new

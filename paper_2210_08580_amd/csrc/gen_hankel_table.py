@@ -270,6 +270,30 @@ def yk_check(sets):
         sys.exit("K0 table accuracy check failed")
 
 
+YK32_DEG = 8
+
+
+def yk32_table():
+    """K0 on the unit intervals of [YK_XS, YK_XA) for single-precision evaluation
+    (t = x - c - 1/2 and the Horner sums in float32), checked against mpmath."""
+    f = lambda x: mp.besselk(0, x)
+    tab = [[float(v) for v in cheb_monomial(f, c, YK32_DEG)] for c in range(YK_XS, YK_XA)]
+    f4 = np.float32
+    worst = 0.0
+    for x in np.linspace(YK_XS, YK_XA, 3800, endpoint=False):
+        c = int(np.floor(x))
+        t = f4(f4(x) - f4(c + 0.5))
+        acc = f4(tab[c - YK_XS][-1])
+        for v in tab[c - YK_XS][-2::-1]:
+            acc = f4(acc * t + f4(v))
+        ref = float(mp.besselk(0, mp.mpf(float(f4(x)))))
+        worst = max(worst, abs(float(acc) - ref) / ref)
+    print(f"K0 float32 table: worst relative error {worst:.3e}")
+    if worst > 6e-7:
+        sys.exit("float32 K0 table accuracy check failed")
+    return tab
+
+
 def main():
     ser = series_coeffs()
     nas = asym_terms_needed(XA)
@@ -297,6 +321,7 @@ def main():
     ser32, asy32, tab32, nas32 = table32()
     yk = yk_sets()
     yk_check(yk)
+    yk32 = yk32_table()
     out = os.path.join(HERE, "hankel_table.inc")
     with open(out, "w") as fh:
         fh.write("// Generated by gen_hankel_table.py; do not edit.\n")
@@ -341,6 +366,12 @@ def main():
         fh.write(f"static constexpr double YK_TAB[{YK_XA - YK_XS}][{DEG + 1}] = {{\n")
         for cc in ytab:
             fh.write("  {" + ", ".join(repr(v) for v in cc) + "},\n")
+        fh.write("};\n")
+        fh.write(f"#define YK32_DEG {YK32_DEG}\n")
+        fh.write(f"// the same intervals for float32 evaluation (t and the sums in float32)\n")
+        fh.write(f"static constexpr float YK32_TAB[{YK_XA - YK_XS}][{YK32_DEG + 1}] = {{\n")
+        for cc in yk32:
+            fh.write("  {" + ", ".join(repr(float(np.float32(v))) + "f" for v in cc) + "},\n")
         fh.write("};\n")
     print("wrote", out)
 
