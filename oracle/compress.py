@@ -11,7 +11,7 @@ Householder QR (LAPACK via SciPy):
     B = Q^H A,  B = U~ Sigma V~^H (SVD)
 and truncates to r: U = Q U~_r Sigma_r, W = V~_r^H so that A ~ U W.
 
-Truncation (this build's reading; the paper only names a tolerance eps):
+Truncation (the reading taken here; the paper only names a tolerance eps):
     r = min(rank_cap, #{sigma_i > max(eps, 1e-13) sigma_1}),
 then r is lowered while sigma_r < (1 + 1e-6) sigma_{r+1}, so that a pair of
 (numerically) equal singular values is never split.

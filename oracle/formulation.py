@@ -18,8 +18,8 @@ Readings taken where the printed text is garbled or silent:
     (kernel (1/2 pi) K0(k R), the "localised" preconditioner):
     Z_e = G^{-1/2} S_y G^{-1} N G^{-1/2}, v_e = -G^{-1/2} S_y G^{-1} f; the
     compact part is again Z_e - I/4 + alpha C_h, beta = (1 + 2 alpha)/4. The
-    paper names the preconditioner but not its wavenumber; i k is this build's
-    reading.
+    paper names the preconditioner but not its wavenumber; i k is the reading
+    taken here.
 G^{+-1/2} and G^{-1} are formed from a dense symmetric eigendecomposition of
 G (exact to rounding).
 """
