@@ -62,7 +62,7 @@ __device__ __forceinline__ double2 cexpi(double ph) {
 // ------------------------------------------------------------------ far-field matrix
 // F[l + i nang] = c_inf (i k) sum_{p in {i-1, i}} (th_l . (h n)_p) sum_al w psi e^{-i k th_l . x_al},
 // (h n)_p = (e_y, -e_x) for the edge e = P_{p+1} - P_p.
-__global__ void farfield_matrix_kernel(const double* __restrict__ nodes, int n, const double* __restrict__ thetas,
+__global__ __launch_bounds__(256) void farfield_matrix_kernel(const double* __restrict__ nodes, int n, const double* __restrict__ thetas,
                                        int nang, double k, Rule8A r, double2* __restrict__ F) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * nang) return;
@@ -140,7 +140,7 @@ __global__ void amp_grad_kernel(const double2* __restrict__ E, const double2* __
 // Far-field term +2 Re sum_l sum_i Q_li dF_li/dx and right-hand-side term
 // -2 Re sum_r sum_i mu_ri df_ri/dx, each a sum over panels p of a function of
 // (P_p, P_{p+1}). gp[p] = {d/dP_p (x, y), d/dP_{p+1} (x, y)}.
-__global__ void panel_grad_kernel(const double* __restrict__ nodes, int n, double k, Rule8A r,
+__global__ __launch_bounds__(64) void panel_grad_kernel(const double* __restrict__ nodes, int n, double k, Rule8A r,
                                   const double* __restrict__ thetas, int nang,
                                   const double2* __restrict__ Qp,   // E J^H: Q_li = conj(Qp[l + i nang])
                                   const double* __restrict__ angles, const double2* __restrict__ amps, int nrhs,
@@ -376,7 +376,7 @@ __device__ void near_n_block(const double (&P)[4][2], int s, double k, const dou
 
 // -2 Re d/dx [sum_ab M_eff(p+a, q+b) N^{pq}_ab] for the ordered near pairs
 // (q = p - 1, p, p + 1), by central differences in each node coordinate.
-__global__ void pair_grad_near_kernel(const double* __restrict__ nodes, int n, double k,
+__global__ __launch_bounds__(64) void pair_grad_near_kernel(const double* __restrict__ nodes, int n, double k,
                                       const double* __restrict__ tab, const double* __restrict__ gl32, Rule8A r,
                                       W8 wt, const double2* __restrict__ M, double* __restrict__ grad) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;

@@ -472,7 +472,7 @@ struct NearParams {
     int n;
 };
 
-__global__ void asm_near_block_kernel(NearParams P, W8 wt) {
+__global__ __launch_bounds__(128) void asm_near_block_kernel(NearParams P, W8 wt) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = P.n;
     if (t >= 3 * n) return;

@@ -87,7 +87,7 @@ __global__ void sparse_kernel(const double* __restrict__ h, int n, double* __res
 }
 
 // f_i = <phi_i, du/dn>, h_i = <phi_i, u>, u = A exp(i k d.x), du/dn = i k (n.d) u.
-__global__ void rhs_planewave_kernel(const double* __restrict__ gx, const double* __restrict__ gy,
+__global__ __launch_bounds__(256) void rhs_planewave_kernel(const double* __restrict__ gx, const double* __restrict__ gy,
                                      const double* __restrict__ h, const double* __restrict__ nx,
                                      const double* __restrict__ ny, int n, double k, Rule8Arg wr,
                                      Rule8Arg xr, const double* __restrict__ angles,
