@@ -169,26 +169,45 @@ __global__ void gram_band_kernel(const double* __restrict__ d, const double* __r
     }
 }
 
-// Y = G^{-1} X (out of place) with the band: workgroup = 256 rows of one vector.
+// Y = B X (out of place) with the band B (G^{-1}, or a circulant G^{+-1/2}): workgroup =
+// 256 rows of GB_COLS vectors, so that each band coefficient read from L2 serves
+// GB_COLS vectors. Columns past the last are staged from the last one (no branch in
+// the tap loop) and not stored.
+#ifndef GB_COLS
+#define GB_COLS 2
+#endif
+
 template <typename T>
-__global__ __launch_bounds__(256) void gram_band_apply_kernel(const double* __restrict__ band, int n,
+__global__ __launch_bounds__(256) void gram_band_apply_kernel(const double* __restrict__ band, int n, int64_t ncols,
                                                               const T* __restrict__ X, T* __restrict__ Y) {
-    __shared__ T xs[256 + 2 * GW];
-    const int64_t col = blockIdx.y;
+    __shared__ T xs[GB_COLS][256 + 2 * GW];
+    const int64_t c0 = (int64_t)blockIdx.y * GB_COLS;
     const int r0 = blockIdx.x * 256;
-    const T* x = X + col * n;
-    for (int t = threadIdx.x; t < 256 + 2 * GW; t += 256) {
-        int j = r0 - GW + t;
-        j = ((j % n) + n) % n;
-        xs[t] = x[j];
+#pragma unroll
+    for (int c = 0; c < GB_COLS; ++c) {
+        const int64_t cc = c0 + c < ncols ? c0 + c : ncols - 1;
+        const T* x = X + cc * n;
+        for (int t = threadIdx.x; t < 256 + 2 * GW; t += 256) {
+            int j = r0 - GW + t;
+            j = ((j % n) + n) % n;
+            xs[c][t] = x[j];
+        }
     }
     __syncthreads();
     const int i = r0 + threadIdx.x;
     if (i >= n) return;
-    T acc{};
-#pragma unroll 8
-    for (int t = 0; t < 2 * GW + 1; ++t) acc = acc + xs[threadIdx.x + t] * band[(int64_t)t * n + i];
-    Y[col * n + i] = acc;
+    T acc[GB_COLS];
+#pragma unroll
+    for (int c = 0; c < GB_COLS; ++c) acc[c] = T{};
+#pragma unroll 4
+    for (int t = 0; t < 2 * GW + 1; ++t) {
+        const double b = band[(int64_t)t * n + i];
+#pragma unroll
+        for (int c = 0; c < GB_COLS; ++c) acc[c] = acc[c] + xs[c][threadIdx.x + t] * b;
+    }
+#pragma unroll
+    for (int c = 0; c < GB_COLS; ++c)
+        if (c0 + c < ncols) Y[(c0 + c) * n + i] = acc[c];
 }
 
 void gram_band_build(Ctx& c, const double* d, const double* e, int n, double* band) {
@@ -206,8 +225,8 @@ void gram_band_apply(Ctx& c, const double* band, int n, const T* X, int64_t ncol
     if (ncols <= 0) return;
     {
         KScope _ks(c, "gram_inv");
-        hipLaunchKernelGGL(gram_band_apply_kernel<T>, dim3((n + 255) / 256, (unsigned)ncols), dim3(256), 0,
-                           c.stream, band, n, X, Y);
+        hipLaunchKernelGGL(gram_band_apply_kernel<T>, dim3((n + 255) / 256, (unsigned)((ncols + GB_COLS - 1) / GB_COLS)),
+                           dim3(256), 0, c.stream, band, n, ncols, X, Y);
     }
     FDS_HIP_TRY(hipGetLastError());
 }
