@@ -118,12 +118,13 @@ void Ctx::release_cache() {
 Op::~Op() {
     if (!ctx) return;
     void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
-                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy, gpow[0], gpow[1]};
+                    Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy, gpow[0], gpow[1], Btr};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
         ctx->dfree(U);
         ctx->dfree(W);
     }
+    if (Wr != Btr) ctx->dfree(Wr);
     if (ev_mesh) (void)hipEventDestroy(ev_mesh);
 }
 

@@ -237,6 +237,8 @@ struct Op {
     bool owns_uw = false;         // U/W are separate allocations (else views of Vgc/Bt)
     double2* K = nullptr;         // [rank][rank] Woodbury core inverse K^{-1} (column-major)
     double2* Up = nullptr;        // [rank][n]  U_j K^{-1}
+    double2* Btr = nullptr;       // Bt as an n_eff x n column-major matrix (rows of Bt^T), for untransposed products
+    double2* Wr = nullptr;        // W likewise, rank x n (aliases Btr when W is Bt)
     int32_t* piv = nullptr;       // [rank]
     ~Op();
 };

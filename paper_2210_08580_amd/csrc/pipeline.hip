@@ -494,6 +494,44 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
     op.stage = Stage::Compressed;
 }
 
+// X (n x m column-major, i.e. m vectors of length n) -> Y = X^T (m x n column-major)
+__global__ void ctranspose_kernel(const double2* __restrict__ X, int n, int m, double2* __restrict__ Y) {
+    __shared__ double2 t[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx over n, by over m
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int i = bx + threadIdx.x, j = by + k;
+        if (i < n && j < m) t[k][threadIdx.x] = X[(int64_t)j * n + i];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int j = by + threadIdx.x, i = bx + k;
+        if (i < n && j < m) Y[(int64_t)i * m + j] = t[threadIdx.x][k];
+    }
+}
+
+static double2* ctranspose(Ctx& c, const double2* X, int n, int m) {
+    double2* Y = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * m));
+    {
+        KScope _ks(c, "transpose");
+        hipLaunchKernelGGL(ctranspose_kernel, dim3((n + 31) / 32, (m + 31) / 32), dim3(32, 8), 0, c.stream, X, n, m,
+                           Y);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    return Y;
+}
+
+// The rows of Bt^T and of W as column-major matrices, so that the products with
+// them in the factor and the solves run untransposed (Gauss's three products,
+// row-contiguous loads).
+static void make_rows(Op& op) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    if (op.Wr != op.Btr) c.dfree(op.Wr);
+    c.dfree(op.Btr);
+    op.Btr = ctranspose(c, op.Bt, n, op.n_eff);
+    op.Wr = op.W == op.Bt ? op.Btr : (op.rank > 0 ? ctranspose(c, op.W, n, op.rank) : nullptr);
+}
+
 void run_factor(Op& op) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n, r = op.rank;
@@ -501,14 +539,15 @@ void run_factor(Op& op) {
     c.dfree(op.Up);
     op.K = nullptr;
     op.Up = nullptr;
+    make_rows(op);
     if (r == 0) {
         op.stage = Stage::Factored;
         return;
     }
     FDS_REQUIRE(r <= 2048, FDS_ERR_NOTIMPL, "skeleton rank above 2048");
-    // K = I + beta^{-1} W_j U_j ; W_j = Bt^T (stored as n x r column-major "W^T")
+    // K = I + beta^{-1} W_j U_j ; W_j as the r x n matrix Wr
     double2* K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
-    zgemm(c, OP_T, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.W, n, op.U, n, kZero, K, r);
+    zgemm(c, OP_N, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.Wr, r, op.U, n, kZero, K, r);
     add_diag(c, K, r, 1.0);
     op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
     double hs[2];
@@ -529,7 +568,7 @@ static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
     const int n = (int)op.n, r = op.rank;
     const double ib = 1.0 / op.beta;
     if (r > 0) {
-        zgemm(c, OP_T, OP_N, r, (int)nrhs, n, kOne, op.W, n, b, n, kZero, z, r);
+        zgemm(c, OP_N, OP_N, r, (int)nrhs, n, kOne, op.Wr, r, b, n, kZero, z, r);
         zgemm(c, OP_N, OP_N, n, (int)nrhs, r, make_double2(-ib * ib, 0.0), op.Up, n, z, r,
               make_double2(ib, 0.0), b, n);
     } else {
@@ -649,7 +688,7 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
             // res = w - beta j - V_g (Bt^T j)
             FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
             axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, (int64_t)n * nrhs);
-            zgemm(c, OP_T, OP_N, ne, (int)nrhs, n, kOne, op.Bt, n, jv, n, kZero, z, ne);
+            zgemm(c, OP_N, OP_N, ne, (int)nrhs, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
             zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
         }
         if (stats) {
