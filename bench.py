@@ -9,8 +9,13 @@ N = 8192 panels, k = 10, normalised Calderon TE-EFIE, 255 kept Laplacian modes,
 rank cap 256, oversampling 10, 2 power iterations and 256 plane-wave
 right-hand sides. Inputs are resident in device memory before timing starts.
 
-Prints one JSON line (metric, value, roofline of the dominant kernel, and the
-CPU oracle timed on a bounded sample of the same workload).
+Prints one JSON line: metric and value (RHS solves/s of the mixed-precision
+variant when its solution is within 1e-6 of the plain FP64 one, else the FP64
+rate), the roofline of the dominant kernel family and the HBM roofline of the
+assembly, both variants' rates, stage breakdowns and errors against stored
+oracle solutions, the truncating-regime workload (ellipse 2 x 0.5, N = 16384,
+rank 128 < 511 kept modes, so the randomised range finder runs) timed the
+same way, and the CPU oracle timed on a bounded sample of the workload.
 """
 from __future__ import annotations
 
@@ -25,33 +30,63 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RHS solves/s at N=8192, relerr<=1e-6, mixed vs FP64 plain; assembly entries/s"
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector and FP64 matrix (dense)
-FLOP_PER_POINT_PAIR = 225.0   # algorithmic work of one Gauss point pair (see design notes)
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+ASM_KERNELS = ("asm_far", "asm_far_band", "asm_near", "asm_band")   # the dense assembly of S, N, D
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form: str | None = None):
-    """Time the CPU oracle stage by stage at N = n_sample on the same curve, k,
-    formulation and filter, and scale each stage to N = n_full by its
-    complexity: assembly and solve O(N^2) (per right-hand side), dense operator
-    algebra and filter O(N^3), compression O(N^2 l)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form: str | None = None,
+                 asm_rows: int = 8):
+    """The CPU oracle, as it stands, timed on a bounded sample of the workload and
+    scaled to one step at N = n_full (an extrapolated estimate, labelled as such).
+
+    * Assembly, the oracle's largest stage, is timed at the full size: the oracle
+      assembles S, N, D panel row by panel row against all N columns, and
+      `asm_rows` rows of the full-size mesh are timed and scaled by N / asm_rows.
+    * The dense operator algebra (Gram powers, compact part, filter), compression
+      and solve are timed at N = n_sample on the same curve, wave number,
+      formulation, filter and right-hand sides, and scaled by their complexity:
+      O(N^3) for the dense eigendecompositions and products, O(N^2) for the
+      compression (fixed sketch width) and for the solve (per right-hand side)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import assembly, compress, filters, formulation, geometry, rng, woodbury
     from paper_2210_08580_amd import workloads as wl
 
+    t = {}
+    # assembly rows at the full size
+    wf = wl.workload(wname, nrhs=nrhs, form=form)
+    if wf.nodes is None:     # equal-chord workload: the oracle's mesher
+        wf.nodes = geometry.equal_chord_nodes(wf.trig, wf.n_nodes)
+    mf = geometry.mesh(wf.nodes)
+    nf = mf.n
+    ps = np.arange(asm_rows)
+    t0 = time.perf_counter()
+    assembly.pair_blocks(mf, wf.k, np.repeat(ps, nf), np.tile(np.arange(nf), ps.size))
+    t["assemble_rows"] = time.perf_counter() - t0
+    asm_full = t["assemble_rows"] * nf / asm_rows
+
     w = wl.workload(wname, n=n_sample, nrhs=nrhs, form=form)
-    if w.nodes is None:     # equal-chord workload: the oracle's mesher
+    if w.nodes is None:
         w.nodes = geometry.equal_chord_nodes(w.trig, w.n_nodes)
     m = geometry.mesh(w.nodes)
-    t = {}
-    t0 = time.perf_counter()
     S, Nm, D = assembly.assemble(m, w.k)
     Sy = assembly.assemble_yukawa(m, w.k) if w.form == "ycfie" else None
-    t["assemble"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Gh, Gmh, Gi = formulation.gram_powers(*assembly.gram(m))
     C, beta = formulation.compact_part(w.form, S, Nm, D, Gmh, Gi, w.alpha, Sy)
@@ -60,7 +95,7 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form:
     t["dense"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Om = rng.sketch(w.seed, m.n, w.rank_cap + w.oversample)
-    U, W, s = compress.compress(Ac, Om, w.power_iters, w.rank_cap, w.tol)
+    U, W, sv = compress.compress(Ac, Om, w.power_iters, w.rank_cap, w.tol)
     lu = woodbury.factor(U, W, beta)
     t["compress"] = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -70,20 +105,26 @@ def cpu_baseline(wname: str, n_full: int, nrhs: int, n_sample: int = 1024, form:
     y, hist = woodbury.refine(lambda x: beta * x + Ac @ x, U, W, beta, lu, v, y, 1e-10, 2)
     j = Gmh @ y
     t["solve"] = time.perf_counter() - t0
-    r = n_full / n_sample
-    est = t["assemble"] * r ** 2 + t["dense"] * r ** 3 + t["compress"] * r ** 2 + t["solve"] * r ** 2
+    r = nf / m.n
+    est = asm_full + t["dense"] * r ** 3 + t["compress"] * r ** 2 + t["solve"] * r ** 2
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    sample_s = sum(t.values())
     return {
         "value": nrhs / est,
         "unit": "RHS solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle pipeline at N={n_sample} (same curve, k, formulation, n_modes, rank cap, "
-                   f"{nrhs} RHS, {w.form.upper()}) took {sample_s:.1f} s; stages scaled to N={n_full} "
-                   f"(assembly, compression, solve x(N/Ns)^2, dense algebra x(N/Ns)^3): "
-                   + ", ".join(f"{k}={v:.2f}s" for k, v in t.items())),
+        "extrapolated": True,
+        "cpu_model": _cpu_model(),
+        "host_cpus": len(os.sched_getaffinity(0)),
+        "sample": (f"extrapolated estimate: oracle assembly of {asm_rows} panel rows at N={nf} "
+                   f"({t['assemble_rows']:.2f} s, scaled x{nf // asm_rows}); dense algebra, filter, "
+                   f"compression and {nrhs}-RHS solve at N={m.n} on the same {w.form.upper()} workload "
+                   f"(dense={t['dense']:.2f} s x(N/{m.n})^3, compress={t['compress']:.2f} s and "
+                   f"solve={t['solve']:.2f} s x(N/{m.n})^2); assembly single-threaded NumPy, "
+                   f"dense algebra on {threads} BLAS threads"),
         "est_seconds_per_step": est,
+        "est_stage_seconds": {"assemble": asm_full, "dense": t["dense"] * r ** 3,
+                              "compress": t["compress"] * r ** 2, "solve": t["solve"] * r ** 2},
     }
 
 
@@ -171,6 +212,40 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_ea
     op.close()
     log(f"{precision}: marginal solves done")
     return t1 - t0, prof, info, j, t3 - t2
+
+
+def stage_breakdown(B, ctx, w, nodes, angles, amps, precision):
+    """One extra (untimed) step with a device synchronisation after every stage:
+    wall milliseconds per stage. The synchronisations serialise what the timed
+    step overlaps (the filter's eigensolver runs beside the assembly there), so
+    the stages add up to more than a timed step."""
+    import torch
+    iters, tol = solve_limits(w)
+    out = {}
+    torch.cuda.synchronize()
+
+    def lap(name, t0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out[name] = 1e3 * (t1 - t0)
+        return t1
+
+    t = time.perf_counter()
+    op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
+    t = lap("assemble", t)
+    f, h = B.fds_rhs_planewave(op, angles, amps)
+    wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
+    t = lap("rhs", t)
+    B.fds_filter(op, w.form, w.alpha, w.n_modes)
+    t = lap("filter", t)
+    B.fds_compress(op, w.rank_cap, w.oversample, w.power_iters, w.tol, w.seed)
+    t = lap("compress", t)
+    B.fds_factor(op)
+    t = lap("factor", t)
+    B.fds_solve_system(op, wv, max_iters=iters, tol=tol)
+    lap("solve", t)
+    op.close()
+    return out
 
 
 def run_batch64(args):
@@ -341,6 +416,8 @@ def run_table1(args):
 RELERR_BOUND = 1e-6   # solution error bound of the metric (mixed against FP64)
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_star8192.json")
+ASM_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "assemble.hip")
+ASM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_assembly_star8192.json")
 
 
 def measured_traffic(kernel):
@@ -360,13 +437,63 @@ def measured_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def assembly_bytes(n, precision):
+    """Algorithmic HBM bytes of one assembly: the stored S, N, D (complex128, or
+    complex64 plus N on the cyclic band |i - j| <= 63 in complex128)."""
+    if precision == "fp64":
+        return 48.0 * n * n
+    w = min(63, (n - 1) // 2)
+    return 24.0 * n * n + 16.0 * n * (2 * w + 1)
+
+
+def measured_asm_traffic(precision):
+    """HBM bytes written per assembly from the committed counter summary, or None
+    when there is none or the assembly source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(ASM_TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(ASM_SOURCE, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("variants", {}).get(precision, {}).get("write_bytes_per_assembly")
+
+
+def assembly_roofline(prof, n, steps, precision):
+    """HBM roofline of the dense assembly (every asm_* kernel of a step, HIP events
+    on the context stream): achieved = algorithmic bytes written / assembly time."""
+    ms = sum(prof.get(k, (0.0, 0))[0] for k in ASM_KERNELS) / steps
+    if ms <= 0.0:
+        return None
+    byts = assembly_bytes(n, precision)
+    gbs = byts / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": measured_asm_traffic(precision), "kernels": list(ASM_KERNELS),
+            "ms_per_assembly": ms, "bytes_per_assembly": byts, "entries_per_s": 3.0 * n * n / (ms / 1e3),
+            "kernel_ms": {k: prof[k][0] / steps for k in ASM_KERNELS if k in prof}}
+
+
 def roofline(prof, n, ne, nrhs, steps, precision, form="efie"):
     """Roofline of the kernel family with the largest total time (HIP events on
-    the context stream): achieved = algorithmic work per launch / mean launch time."""
-    name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    the context stream): achieved = algorithmic work per launch / mean launch time.
+    The assembly kernels count as one family (the dense S, N, D written once)."""
+    fam = dict(prof)
+    asm = [k for k in ASM_KERNELS if k in fam]
+    if asm:
+        fam["assembly"] = (sum(fam.pop(k)[0] for k in asm), steps)
+    name, (tot_ms, launches) = max(fam.items(), key=lambda kv: kv[1][0])
+    if name == "assembly":
+        roof = assembly_roofline(prof, n, steps, precision)
+        roof.update(kernel="assembly", launches=steps, avg_launch_ms=roof["ms_per_assembly"])
+        return roof
     per_launch_s = (tot_ms / 1e3) / max(launches, 1)
     traffic = None
     sym = {"fp32": "float2", "fp64": "double2"}[precision]
+    work = None
+    roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
     if name in ("gemm_op", "gemm_op_vg", "gemm_op_y"):
         # N x N operator products on one kernel symbol each, 8 flop per complex
         # multiply-add (4 with the real V_g). gemm_op_vg: S^T V_g (n_eff columns);
@@ -384,12 +511,6 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie"):
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
                 "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0>" % (asym, "double" if name == "gemm_op_vg" else "double2")}
         traffic = measured_traffic(name + ":" + precision) if form != "ycfie" else None
-    elif name == "asm_far":
-        work = 32.0 * n * n * FLOP_PER_POINT_PAIR
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
-    else:
-        work = None
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
     if work is not None:
         ach = work / per_launch_s / 1e12
         roof.update(achieved=ach, frac=ach / roof["peak"])
@@ -420,6 +541,10 @@ def main():
                     help="skip the solve-only (marginal) rate, e.g. so that a profile holds the timed steps only")
     ap.add_argument("--rhs-after-filter", action="store_true",
                     help="form the right-hand side after the filter instead of right after the assembly")
+    ap.add_argument("--no-truncating", action="store_true",
+                    help="skip the truncating-regime workload (ellipse 2 x 0.5, N=16384) timed after the headline")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the per-stage breakdown (one extra synchronised step per variant)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -459,18 +584,77 @@ def main():
         del src, dst
 
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    res, extra, main_v = run_workload(B, ctx, w, nodes, angles, amps, variants, args)
+    r = res[main_v]
+    info = r["info"]
+    ne = info["n_eff"]
+    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form)
+    asm_roof = assembly_roofline(r["prof"], n, args.steps, main_v)
+    precision = {"fp64": "fp64 plain", "fp32": "mixed: FP32 far-field assembly, complex64 operators, "
+                 "FP64 products, FP64 Woodbury and refinement"}[main_v]
+    out = {
+        "metric": METRIC, "value": r["value"], "unit": "RHS solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if main_v == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": workload_desc(w, ne), "precision": precision},
+        "roofline": roof,
+        "roofline_assembly": asm_roof,
+        "extra": extra,
+    }
+    if not args.no_truncating and args.workload == "star8192":
+        # the truncating regime (rank 128 < 511 kept modes: the randomised range finder,
+        # projection and truncation run) on the ellipse 2 x 0.5 at N = 16384
+        wt = wl.workload("ellipse16384")
+        log("truncating workload: " + wt.name)
+        tn = torch.from_numpy(wt.nodes).cuda()
+        ta = torch.from_numpy(wt.angles).cuda()
+        tm = torch.from_numpy(wt.amps).cuda()
+        rt, et, mt = run_workload(B, ctx, wt, tn, ta, tm, variants, args)
+        t = rt[mt]
+        et.update({"value": t["value"], "unit": "RHS solves/s", "ms_per_step": t["ms_per_step"],
+                   "variant_reported": mt, "config": workload_desc(wt, t["info"]["n_eff"]),
+                   "roofline_assembly": assembly_roofline(t["prof"], wt.n, args.steps, mt)})
+        out["truncating"] = et
+        del tn
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle sample")
+        out["cpu_baseline"] = cpu_baseline(args.workload, n, nrhs, args.cpu_sample_n, args.form)
+    if args.autotune:
+        out["extra"]["autotune"] = B.fds_autotune_read(ctx)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def workload_desc(w, ne):
+    ell = w.rank_cap + w.oversample
+    if w.tol == 0.0 and w.rank_cap >= ne and ell >= ne:
+        skel = (f"r={w.rank_cap} (exact skeleton: rank n_eff={ne} <= r, no sketch is formed, "
+                f"p={w.oversample} and q={w.power_iters} unused)")
+    else:
+        skel = (f"r={w.rank_cap} p={w.oversample} q={w.power_iters} tol={w.tol:g} (truncating: randomised "
+                f"range finder with {w.power_iters} subspace iterations, sketch width {ell} < n_eff={ne})")
+    return (f"{w.name}: {WORKLOAD_DESC.get(w.name, w.name)} N={w.n} k={w.k} {w.form.upper()} "
+            f"n_modes={w.n_modes} {skel} nrhs={w.nrhs}")
+
+
+def run_workload(B, ctx, w, nodes, angles, amps, variants, args):
+    """Times every precision variant of one workload; returns (per-variant results,
+    extra record, the variant that qualifies for the metric)."""
+    import torch
+    n, nrhs = w.n, w.nrhs
     res = {}
     for prec in variants:
         el, prof, info, j, marg = run_variant(B, ctx, w, nodes, angles, amps, prec, args.steps, args.warmup,
                                               rhs_early=not args.rhs_after_filter, marginal=not args.no_marginal)
-        far = prof.get("asm_far", (0.0, 1))
-        asm_ms = far[0] / max(far[1], 1)
         res[prec] = {
             "value": nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
             "marginal_rhs_per_s": nrhs * args.steps / marg if marg else None,
             "prof": prof, "info": info, "j": j,
-            "assembly_entries_per_s": 3.0 * n * n / (asm_ms / 1e3) if asm_ms > 0 else None,
         }
+        if not args.no_stages:
+            res[prec]["stages_ms"] = stage_breakdown(B, ctx, w, nodes, angles, amps, prec)
     extra = {}
     main_v = "fp32" if "fp32" in res else variants[0]
     if "fp32" in res and "fp64" in res:
@@ -483,42 +667,34 @@ def main():
             # outside it does not qualify, the FP64 one is reported instead
             main_v = "fp64"
             extra["mixed_outside_relerr_bound"] = True
-    r = res[main_v]
-    info = r["info"]
-    ne = info["n_eff"]
-    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form)
-    extra.update({"n_eff": ne, "rank": info["rank"]})
+    # the first right-hand sides of the batch against the oracle's filtered solution,
+    # stored by tests/golden/make_fullsize.py (which runs the CPU oracle only)
+    gold = os.path.join(ROOT, "tests", "golden", f"fullsize_{w.name}_{w.form}.npz")
+    if os.path.exists(gold):
+        import numpy as np
+        with np.load(gold, allow_pickle=False) as z:
+            jf, ang = z["j_fil"], z["angles"]
+        if np.array_equal(ang, w.angles[:ang.size]):
+            for prec, rv in res.items():
+                jg = rv["j"][:ang.size].cpu().numpy()
+                rv["relerr_vs_oracle"] = float(np.max(np.linalg.norm(jg - jf, axis=1) / np.linalg.norm(jf, axis=1)))
+            extra["relerr_vs_oracle_rhs"] = int(ang.size)
+    info = res[main_v]["info"]
+    extra.update({"n_eff": info["n_eff"], "rank": info["rank"]})
     for prec, rv in res.items():
+        asm = assembly_roofline(rv["prof"], n, args.steps, prec)
         extra[prec] = {
             "value": rv["value"], "ms_per_step": rv["ms_per_step"],
             "marginal_rhs_per_s": rv["marginal_rhs_per_s"],
-            "assembly_entries_per_s": rv["assembly_entries_per_s"],
+            "relerr_vs_oracle": rv.get("relerr_vs_oracle"),
+            "assembly_entries_per_s": asm["entries_per_s"] if asm else None,
+            "assembly_hbm_frac": asm["frac"] if asm else None,
             "refine_iters": rv["info"]["refine"]["iters"], "final_relres": rv["info"]["refine"]["relres"],
+            "stages_ms_serialised": rv.get("stages_ms"),
             "kernel_ms_per_step": {k: v[0] / args.steps
                                    for k, v in sorted(rv["prof"].items(), key=lambda kv: -kv[1][0])},
         }
-    precision = {"fp64": "fp64 plain", "fp32": "mixed: FP32 far-field assembly, complex64 operators, "
-                 "FP64 products, FP64 Woodbury and refinement"}[main_v]
-    out = {
-        "metric": METRIC, "value": r["value"], "unit": "RHS solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if main_v == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"{w.name}: {WORKLOAD_DESC.get(w.name, w.name)} N={n} k={w.k} {w.form.upper()} "
-                               f"n_modes={w.n_modes} r={w.rank_cap} p={w.oversample} "
-                               f"q={w.power_iters} nrhs={nrhs}",
-                   "precision": precision},
-        "roofline": roof,
-        "extra": extra,
-    }
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle sample at N={args.cpu_sample_n}")
-        out["cpu_baseline"] = cpu_baseline(args.workload, n, nrhs, args.cpu_sample_n, args.form)
-    if args.autotune:
-        out["extra"]["autotune"] = B.fds_autotune_read(ctx)
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    return res, extra, main_v
 
 
 if __name__ == "__main__":

@@ -369,8 +369,11 @@ fds_status fds_op_factors(fds_op op, const void** U, const void** W, int32_t* ra
 
 /* ----------------------------------------------------------------- factor */
 
-/* LU with partial pivoting of the Woodbury core K = I_r + beta^{-1} W U
- * (paper, Inversion of the structured matrices). Synchronises to check the
+/* Inverse of the Woodbury core K = I_r + beta^{-1} W U (paper, Inversion of
+ * the structured matrices) by blocked Gauss-Jordan elimination: first without
+ * row interchanges, kept when max |K K^{-1} - I| <= 8 eps r; otherwise redone
+ * with partial pivoting. K^{-1} is folded into the skeleton (U K^{-1}), so a
+ * solve is two products. Synchronises once to check the residual and the
  * pivots; FDS_ERR_SINGULAR if min|pivot| < 64 eps max|K|. */
 fds_status fds_factor(fds_op op);
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import assembly, geometry
+from oracle import assembly, formulation, geometry, solver
 from paper_2210_08580_amd import batch
 from paper_2210_08580_amd import binding as B
 from paper_2210_08580_amd import workloads as wl
@@ -121,4 +121,16 @@ def test_graph_captured_solves(sctx):
     sctx.stream.synchronize()
     for a, b in zip(outs, eager):
         assert (a - b).abs().max().item() <= 1e-13 * b.abs().max().item()
+    # every replayed solution against the oracle's filtered solution j = G^{-1/2} y_fil
+    for i, (pr, out) in enumerate(zip(probs, outs)):
+        nodes = pr["nodes"].cpu().numpy()
+        pb = solver.Problem(nodes, pr["k"], form="cfie", n_modes=pr["n_modes"])
+        ops = solver.build_operators(pb)
+        assert ops.n_eff == pipe.n_eff[i]
+        fo, ho = assembly.rhs_planewave(ops.mesh, pr["k"], ang[i].numpy(), amp[i].numpy())
+        v = formulation.rhs_vector("cfie", ops.S, ops.Gmh, ops.Gi, fo.T, ho.T)
+        jf = ops.Gmh @ solver.y_filtered(ops, v)
+        err = solver.relerr(out.cpu().numpy().T, jf)
+        print(f"  replayed solve {i} (N={nodes.shape[0]}) vs the oracle: {err:.2e}", flush=True)
+        assert err <= 1e-10
     pipe.close()

@@ -110,9 +110,10 @@ def test_dft_filter_solve_parity(ctx, kind, n, k, form, nm, prec):
     fo, ho = assembly.rhs_planewave(m, k, ang, amps)
     v = formulation.rhs_vector(form, ops.S, ops.Gmh, ops.Gi, fo.T, ho.T, 1.0, ops.Sy)
     yf = solver.y_filtered(ops, v)
-    tol = 1e-10 if prec == "fp64" else 2e-6
-    assert solver.relerr(y.cpu().numpy().T, yf) <= tol
-    assert solver.relerr(j.cpu().numpy().T, ops.Gmh @ yf) <= tol
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    ey, ej = solver.relerr(y.cpu().numpy().T, yf), solver.relerr(j.cpu().numpy().T, ops.Gmh @ yf)
+    _say(f"  y vs y_fil {ey:.2e}, j vs j_fil {ej:.2e} (bound {tol:g})")
+    assert ey <= tol and ej <= tol
     op.close()
 
 

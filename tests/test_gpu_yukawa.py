@@ -114,8 +114,10 @@ def test_yukawa_cfie_solve_parity(ctx, kind, n, k, nm, alpha, prec):
     fo, ho = assembly.rhs_planewave(m, k, ang, amps)
     v = formulation.rhs_vector("ycfie", ops.S, ops.Gmh, ops.Gi, fo.T, ho.T, alpha, ops.Sy)
     yf = solver.y_filtered(ops, v)
-    tol = 1e-10 if prec == "fp64" else 2e-6
-    assert solver.relerr(y.cpu().numpy().T, yf) <= tol
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    err = solver.relerr(y.cpu().numpy().T, yf)
+    _say(f"  y vs y_fil {err:.2e} (bound {tol:g})")
+    assert err <= tol
     # the split path gives the same solution
     w = B.fds_rhs_system(op, "ycfie", alpha, f, h)
     j2, _, st2 = B.fds_solve_system(op, w, max_iters=8, tol=1e-12)
