@@ -421,6 +421,21 @@ fds_status fds_rhs_system(fds_op op, fds_form form, double alpha, const void* f,
 fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out, void* y_out,
                             const fds_solve_opts* opts, fds_solve_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fds_solve_system with
+ * stats == NULL, y_out == NULL, refinement against the filtered operator and
+ * max_iters = sweeps, computed without any device allocation. Its work space
+ * is a static device array of 32 MiB inside the library (one per GPU, held
+ * until the process ends): the right-hand sides are processed in blocks of cb
+ * columns, 16 (n + max(rank, n_eff)) cb bytes in 24 MiB of it, the split-K
+ * partial sums of the products in the rest. Calls that overlap on one GPU
+ * (from several threads or streams, any context) share that array and race;
+ * the caller serialises them. w, j_out: device [nrhs][n] complex128 (j_out may
+ * not alias w). Asynchronous. Requires a factored operator. Errors:
+ * FDS_ERR_ARG for sweeps outside [0, 1000] or when one right-hand side does
+ * not fit (16 (n + max(rank, n_eff)) > 24 MiB). */
+fds_status fds_solve_system_noalloc(fds_op op, const void* w, int64_t nrhs, void* j_out, int32_t sweeps);
+
 /* --------------------------------------------------------- inverse problem */
 
 /* Far fields of currents j (device [nrhs][n] complex128) at angles thetas

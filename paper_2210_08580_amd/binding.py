@@ -132,6 +132,7 @@ _SIGS = {
                                  C.c_void_p]),
     "fds_solve_system": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
+    "fds_solve_system_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
 }
 
 _lib = None
@@ -593,6 +594,15 @@ def fds_solve_system(op: Op, w: torch.Tensor, max_iters: int = 4, tol: float = 1
     hist = list(st.history[: st.iters + 1]) if stats else []
     return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
                   "history": hist}
+
+
+def fds_solve_system_noalloc(op: Op, w: torch.Tensor, j_out: torch.Tensor, sweeps: int = 2) -> torch.Tensor:
+    """Allocation-free Woodbury solve with `sweeps` filtered refinement sweeps into the
+    caller's j_out (nrhs, n); asynchronous on the context's stream."""
+    if w.shape != j_out.shape or w.dtype != torch.complex128 or j_out.dtype != torch.complex128:
+        raise ValueError("w and j_out must be complex128 tensors of the same shape")
+    _check(lib().fds_solve_system_noalloc(op.handle, _ptr(w), w.shape[0], _ptr(j_out), int(sweeps)))
+    return j_out
 
 
 # ----------------------------------------------------------------- inverse problem

@@ -59,6 +59,7 @@ static bool capturing(hipStream_t s) {
 }
 
 void* Ctx::dmalloc(size_t bytes) {
+    if (noalloc) throw Error{FDS_ERR_STATE, "internal error: device allocation inside an allocation-free call"};
     if (bytes == 0) bytes = 16;
     std::lock_guard<std::mutex> lk(pool_mu);
     if (capturing(stream)) {
@@ -211,6 +212,7 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.gl32 = (double*)x.dmalloc(sizeof(double) * 64);
             FDS_HIP_TRY(hipMemcpyAsync(x.gl32, g, sizeof(g), hipMemcpyHostToDevice, x.stream));
             FDS_HIP_TRY(hipStreamSynchronize(x.stream));
+            init_noalloc_scratch(x);
         } catch (...) {
             x.dfree(x.hk_tab);
             x.dfree(x.hk_tab32);
@@ -763,6 +765,16 @@ fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out,
         FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
         if (nrhs == 0) return;
         run_solve_system(op->impl, (const double2*)w, nrhs, (double2*)j_out, (double2*)y_out, it, tol, stats, unf);
+    });
+}
+
+fds_status fds_solve_system_noalloc(fds_op op, const void* w, int64_t nrhs, void* j_out, int32_t sweeps) {
+    return guarded([&] {
+        FDS_REQUIRE(op && w && j_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        require_stage(op->impl, Stage::Factored, "fds_solve_system_noalloc");
+        FDS_REQUIRE(sweeps >= 0 && sweeps <= 1000, FDS_ERR_ARG, "sweeps out of range");
+        if (nrhs == 0) return;
+        run_solve_system_noalloc(op->impl, (const double2*)w, nrhs, (double2*)j_out, sweeps);
     });
 }
 

@@ -69,6 +69,14 @@ struct Ctx {
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
     float* yk_tab32 = nullptr;    // device copy of the float32 K0 interval table
+    // Allocation-free calls (fds_solve_system_noalloc): `scratch` is this device's
+    // address of the library's static scratch array (set once per device at context
+    // creation). While `noalloc` is set every device allocation is refused, the
+    // split-K partial sums of the GEMMs go to ws (ws_bytes) and nothing is autotuned.
+    void* scratch = nullptr;
+    bool noalloc = false;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
     // Device memory: a size-class cache in front of the allocator callback (or
     // hipMalloc), one free list per stream, so that a block is reused only on the
     // stream it was last allocated on (stream order then separates its old and new
@@ -142,6 +150,23 @@ struct SideStream {
     }
     SideStream(const SideStream&) = delete;
     SideStream& operator=(const SideStream&) = delete;
+};
+
+// Allocation-free mode for the enclosed work (see Ctx::noalloc).
+struct NoAlloc {
+    Ctx& c;
+    NoAlloc(Ctx& ctx, void* ws, size_t ws_bytes) : c(ctx) {
+        c.noalloc = true;
+        c.ws = ws;
+        c.ws_bytes = ws_bytes;
+    }
+    ~NoAlloc() {
+        c.noalloc = false;
+        c.ws = nullptr;
+        c.ws_bytes = 0;
+    }
+    NoAlloc(const NoAlloc&) = delete;
+    NoAlloc& operator=(const NoAlloc&) = delete;
 };
 
 // Sets the profiling name of the GEMM launches made during its lifetime.

@@ -522,7 +522,7 @@ static int choose_config(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, 
         cfg = split_for(((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N));
     }
     if (c.split_hint > 0) return (cfg & 256) | std::min(std::max(cfg & 255, c.split_hint), 64);
-    if (!c.autotune) return cfg;
+    if (!c.autotune || c.noalloc) return cfg;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return cfg;
     char key[160];
@@ -587,11 +587,16 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
     const int bm = big ? BB_M : GB_M, bn = big ? BB_N : GB_N;
     const int gm = (m + bm - 1) / bm, gn = (n + bn - 1) / bn;
     int nz = std::max(1, cfg & 255);
+    if (c.noalloc && nz > 1) {   // the partial sums must fit the caller's workspace
+        const size_t per = sizeof(T) * (size_t)m * n;
+        nz = std::max(1, std::min<int>(nz, (int)std::min<size_t>(c.ws_bytes / per, 64)));
+    }
     int kchunk = (k + nz - 1) / nz;
     kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
     nz = (k + kchunk - 1) / kchunk;
     T* part = nullptr;
-    if (nz > 1) part = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
+    if (nz > 1)
+        part = c.noalloc ? static_cast<T*>(c.ws) : static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)nz * m * n));
     {
         KScope _ks(c, c.gemm_tag ? c.gemm_tag : (std::is_same<T, float2>::value ? "gemm_c64" : "gemm"));
         if constexpr (big_ok<T, TA>()) {
@@ -616,7 +621,7 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
                                m, n, nz, alpha, part, beta, C, ldc);
         }
         FDS_HIP_TRY(hipGetLastError());
-        c.dfree(part);
+        if (!c.noalloc) c.dfree(part);
     }
 }
 

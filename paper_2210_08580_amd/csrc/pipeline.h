@@ -20,6 +20,9 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
                int max_iters, double tol, fds_solve_stats* stats, bool unfiltered = false);
 void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y);
+// allocation-free Woodbury solve + filtered refinement sweeps (static scratch array)
+void init_noalloc_scratch(Ctx& c);
+void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps);
 // adjoint.hip
 void run_farfield(Op& op, const double2* J, int64_t nrhs, const double* thetas, int nang, double2* out);
 void run_farfield_grad(Op& op, const double* angles, const double2* amps, int64_t nrhs, const double* thetas,

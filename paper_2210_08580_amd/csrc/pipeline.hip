@@ -18,6 +18,8 @@
 // same in both coordinates (paper, Inversion of the structured matrices).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "fds_internal.h"
@@ -725,6 +727,65 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
         stats->converged = conv ? 1 : 0;
         stats->relres = rel;
         FDS_REQUIRE(conv, FDS_ERR_NOCONV, "refinement did not reach the requested tolerance");
+    }
+}
+
+// ---------------------------------------------------------------- allocation-free solve
+// Scratch of fds_solve_system_noalloc: a file-scope device array, one copy on
+// each GPU, held until the process ends. Its host-side name is not a device
+// address: each device's address is obtained once, at context creation with
+// that device current, and kept in Ctx::scratch; kernels only ever receive
+// that address.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void init_noalloc_scratch(Ctx& c) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;   // device -> address of its copy of `scratch`
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(c.device);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        FDS_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = addr.emplace(c.device, p).first;
+    }
+    c.scratch = it->second;
+}
+
+// fds_solve_system with stats == NULL, y_out == NULL, the filtered refinement and
+// max_iters = sweeps, without device allocations: the right-hand sides are taken
+// in column blocks whose residual (n x cb) and small products (r x cb) fit three
+// quarters of the scratch array; the rest holds the split-K partial sums.
+void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps) {
+    Ctx& c = *op.ctx;
+    FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
+    const int n = (int)op.n, ne = op.n_eff;
+    const int zr = std::max(op.rank, sweeps > 0 ? ne : 0);
+    const size_t col = sizeof(double2) * ((size_t)n + (size_t)std::max(zr, 1));
+    const int64_t cb = std::min<int64_t>(nrhs, (int64_t)((kScratchBytes / 4 * 3) / col));
+    FDS_REQUIRE(cb >= 1, FDS_ERR_ARG,
+                "system too large for the allocation-free solve: 16 (n + max(rank, n_eff)) bytes per right-hand "
+                "side must fit 24 MiB");
+    double2* res = static_cast<double2*>(c.scratch);
+    double2* z = res + (size_t)n * cb;
+    const size_t used = (sizeof(double2) * ((size_t)n + std::max(zr, 1)) * cb + 255) / 256 * 256;
+    NoAlloc na(c, static_cast<unsigned char*>(c.scratch) + used, kScratchBytes - used);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += cb) {
+        const int64_t nb = std::min(cb, nrhs - c0);
+        const int64_t tot = (int64_t)n * nb;
+        const double2* wv = w + (size_t)c0 * n;
+        double2* jv = j_out + (size_t)c0 * n;
+        FDS_HIP_TRY(hipMemcpyAsync(jv, wv, sizeof(double2) * tot, hipMemcpyDeviceToDevice, c.stream));
+        woodbury_apply(op, jv, nb, z);
+        for (int it = 0; it < sweeps; ++it) {
+            // res = w - beta j - V_g (Bt^T j); j += Woodbury(res)
+            FDS_HIP_TRY(hipMemcpyAsync(res, wv, sizeof(double2) * tot, hipMemcpyDeviceToDevice, c.stream));
+            axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, tot);
+            zgemm(c, OP_N, OP_N, ne, (int)nb, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
+            zgemm(c, OP_N, OP_N, n, (int)nb, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+            woodbury_apply(op, res, nb, z);
+            axpby(c, kOne, res, kOne, jv, tot);
+        }
     }
 }
 
