@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "RHS solves/s at N=8192, relerr<=1e-6, mixed vs FP64 plain; assembly entries/s"
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector and FP64 matrix (dense)
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
-ASM_KERNELS = ("asm_far", "asm_far_band", "asm_near", "asm_band")   # the dense assembly of S, N, D
+ASM_KERNELS = ("asm_far", "asm_nband", "asm_near", "asm_band")   # the dense assembly of S, N, D
 
 
 def log(msg):
@@ -169,6 +169,7 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_ea
         # with rhs_early the right-hand side is formed right after the assembly, so
         # that its dense product runs on the device beside the filter's eigensolver
         op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
+        info["nbw"] = B.fds_op_nband(op)[1]
         f, h = B.fds_rhs_planewave(op, angles, amps)
         if rhs_early:
             wv = B.fds_rhs_system(op, w.form, w.alpha, f, h)
@@ -437,13 +438,12 @@ def measured_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def assembly_bytes(n, precision):
+def assembly_bytes(n, precision, nbw=0):
     """Algorithmic HBM bytes of one assembly: the stored S, N, D (complex128, or
-    complex64 plus N on the cyclic band |i - j| <= 63 in complex128)."""
+    complex64 plus N on the cyclic band |i - j| <= nbw in complex128)."""
     if precision == "fp64":
         return 48.0 * n * n
-    w = min(63, (n - 1) // 2)
-    return 24.0 * n * n + 16.0 * n * (2 * w + 1)
+    return 24.0 * n * n + 16.0 * n * (2 * nbw + 1)
 
 
 def measured_asm_traffic(precision):
@@ -462,13 +462,13 @@ def measured_asm_traffic(precision):
     return rec.get("variants", {}).get(precision, {}).get("write_bytes_per_assembly")
 
 
-def assembly_roofline(prof, n, steps, precision):
+def assembly_roofline(prof, n, steps, precision, nbw=0):
     """HBM roofline of the dense assembly (every asm_* kernel of a step, HIP events
     on the context stream): achieved = algorithmic bytes written / assembly time."""
     ms = sum(prof.get(k, (0.0, 0))[0] for k in ASM_KERNELS) / steps
     if ms <= 0.0:
         return None
-    byts = assembly_bytes(n, precision)
+    byts = assembly_bytes(n, precision, nbw)
     gbs = byts / (ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
             "traffic": measured_asm_traffic(precision), "kernels": list(ASM_KERNELS),
@@ -476,7 +476,7 @@ def assembly_roofline(prof, n, steps, precision):
             "kernel_ms": {k: prof[k][0] / steps for k in ASM_KERNELS if k in prof}}
 
 
-def roofline(prof, n, ne, nrhs, steps, precision, form="efie"):
+def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
     """Roofline of the kernel family with the largest total time (HIP events on
     the context stream): achieved = algorithmic work per launch / mean launch time.
     The assembly kernels count as one family (the dense S, N, D written once)."""
@@ -486,7 +486,7 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie"):
         fam["assembly"] = (sum(fam.pop(k)[0] for k in asm), steps)
     name, (tot_ms, launches) = max(fam.items(), key=lambda kv: kv[1][0])
     if name == "assembly":
-        roof = assembly_roofline(prof, n, steps, precision)
+        roof = assembly_roofline(prof, n, steps, precision, nbw)
         roof.update(kernel="assembly", launches=steps, avg_launch_ms=roof["ms_per_assembly"])
         return roof
     per_launch_s = (tot_ms / 1e3) / max(launches, 1)
@@ -588,8 +588,8 @@ def main():
     r = res[main_v]
     info = r["info"]
     ne = info["n_eff"]
-    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form)
-    asm_roof = assembly_roofline(r["prof"], n, args.steps, main_v)
+    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form, info.get("nbw", 0))
+    asm_roof = assembly_roofline(r["prof"], n, args.steps, main_v, info.get("nbw", 0))
     precision = {"fp64": "fp64 plain", "fp32": "mixed: FP32 far-field assembly, complex64 operators, "
                  "FP64 products, FP64 Woodbury and refinement"}[main_v]
     out = {
@@ -615,7 +615,8 @@ def main():
         t = rt[mt]
         et.update({"value": t["value"], "unit": "RHS solves/s", "ms_per_step": t["ms_per_step"],
                    "variant_reported": mt, "config": workload_desc(wt, t["info"]["n_eff"]),
-                   "roofline_assembly": assembly_roofline(t["prof"], wt.n, args.steps, mt)})
+                   "roofline_assembly": assembly_roofline(t["prof"], wt.n, args.steps, mt,
+                                                          t["info"].get("nbw", 0))})
         out["truncating"] = et
         del tn
     if not args.no_cpu_baseline:
@@ -682,7 +683,7 @@ def run_workload(B, ctx, w, nodes, angles, amps, variants, args):
     info = res[main_v]["info"]
     extra.update({"n_eff": info["n_eff"], "rank": info["rank"]})
     for prec, rv in res.items():
-        asm = assembly_roofline(rv["prof"], n, args.steps, prec)
+        asm = assembly_roofline(rv["prof"], n, args.steps, prec, rv["info"].get("nbw", 0))
         extra[prec] = {
             "value": rv["value"], "ms_per_step": rv["ms_per_step"],
             "marginal_rhs_per_s": rv["marginal_rhs_per_s"],

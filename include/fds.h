@@ -78,9 +78,14 @@ typedef struct fds_asm_opts {
                             FDS_FP32: complex64 operators, far-pair kernel values
                             and accumulation in FP32 (distances and Bessel
                             arguments in FP64), self/adjacent-pair quadrature in
-                            FP64; every product with S, N, D then runs on the
-                            FP32 matrix cores (mixed precision)                */
-    int32_t reserved[6];
+                            FP64, N and S near the diagonal in FP64 (band_width);
+                            the products with S, N, D widen the complex64
+                            operands and run on the FP64 matrix cores        */
+    int32_t band_width;  /* FDS_FP32 only: half-width w of the cyclic band
+                            |i - j| <= w on which N (and S) are computed in FP64,
+                            N kept in complex128 (fds_op_nband); 0 = default
+                            (63, or 127 above 8192 panels); clipped to (n-1)/2 */
+    int32_t reserved[5];
 } fds_asm_opts;
 
 typedef struct fds_filter_opts {
@@ -297,7 +302,8 @@ fds_status fds_apply_gram(fds_op op, int32_t p, void* X, int64_t ncols);
  * meshes) and the compact part of the chosen formulation (paper, Filters
  * Based Fast Direct Solver, 2D case). Builds B = V_n^T C (n_eff x n).
  * n_eff (host, may be NULL) receives the number of kept modes after the
- * cluster guard. Errors: FDS_ERR_ARG for n_modes outside [1, n]. */
+ * cluster guard. Errors: FDS_ERR_ARG for n_modes outside [1, n], or for a CFIE
+ * with alpha = -1/2 (beta = 0: no second-kind part). */
 fds_status fds_filter(fds_op op, fds_form form, double alpha,
                       const fds_filter_opts* opts, int32_t* n_eff);
 
@@ -420,6 +426,23 @@ fds_status fds_rhs_system(fds_op op, fds_form form, double alpha, const void* f,
                           int64_t nrhs, void* w_out);
 fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out, void* y_out,
                             const fds_solve_opts* opts, fds_solve_stats* stats);
+
+/* The adjoint solve (paper, Inversion of the structured matrices: the Woodbury
+ * identity of beta I + U W, here of its conjugate transpose beta I + W^H U^H):
+ * solves (beta I + P C)^H y = v for the filtered operator of the last
+ * fds_filter call (opts->unfiltered = 1: of beta I + C, the operator of the
+ * normalised formulation, whose adjoint solution is that of the Galerkin system
+ * transposed and conjugated). The adjoint Woodbury solve with the conjugated
+ * skeleton and core, then FP64 refinement against the adjoint operator
+ * (max_iters, tol as in fds_solve), in y-coordinates (the paper's normalised
+ * unknowns, y = G^{1/2} j). v: device [nrhs][n] complex128; y_out: device
+ * [nrhs][n] complex128; u_out: device [nrhs][n] complex128 or NULL, receives
+ * G^{-1/2} y (the adjoint's current coefficients). Outputs may not alias v.
+ * opts may be NULL (max_iters 4, tol 1e-12). stats: as in fds_solve
+ * (FDS_ERR_NOCONV if given and the tolerance was not met). Requires a factored
+ * operator. */
+fds_status fds_solve_adjoint(fds_op op, const void* v, int64_t nrhs, void* y_out, void* u_out,
+                             const fds_solve_opts* opts, fds_solve_stats* stats);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): fds_solve_system with

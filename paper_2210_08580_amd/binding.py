@@ -45,7 +45,8 @@ class fds_allocator(C.Structure):
 
 
 class fds_asm_opts(C.Structure):
-    _fields_ = [("nquad", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("nquad", C.c_int32), ("precision", C.c_int32), ("band_width", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class fds_filter_opts(C.Structure):
@@ -133,6 +134,8 @@ _SIGS = {
     "fds_solve_system": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
     "fds_solve_system_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
+    "fds_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                    C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
 }
 
 _lib = None
@@ -404,13 +407,15 @@ class Op:
 
 
 def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | None = None,
-                 precision: str | None = None) -> Op:
-    """precision: "fp64" (default) or "fp32" (complex64 operators, mixed precision)."""
+                 precision: str | None = None, band_width: int = 0) -> Op:
+    """precision: "fp64" (default) or "fp32" (complex64 operators, mixed precision);
+    band_width: FP32 only, half-width of the FP64 band of N (0: the library's default)."""
     nodes = nodes.to(device="cuda", dtype=torch.float64).contiguous()
     if precision is not None:
         opts = fds_asm_opts()
         opts.nquad = 8
         opts.precision = {"fp64": FDS_FP64, "fp32": FDS_FP32}[precision]
+        opts.band_width = int(band_width)
     h = C.c_void_p()
     _check(lib().fds_assemble(ctx.handle, _ptr(nodes), nodes.shape[0], float(k),
                               C.byref(opts) if opts is not None else None, C.byref(h)))
@@ -594,6 +599,21 @@ def fds_solve_system(op: Op, w: torch.Tensor, max_iters: int = 4, tol: float = 1
     hist = list(st.history[: st.iters + 1]) if stats else []
     return j, y, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres,
                   "history": hist}
+
+
+def fds_solve_adjoint(op: Op, v: torch.Tensor, max_iters: int = 4, tol: float = 1e-12, want_u: bool = False,
+                      stats: bool = True, unfiltered: bool = False):
+    """Solves (beta I + P C)^H y = v (unfiltered: (beta I + C)^H y = v) for the rows of
+    v (nrhs, n); returns (y, u = G^{-1/2} y or None, stats)."""
+    v = v.to(device="cuda", dtype=torch.complex128).contiguous()
+    y = torch.empty_like(v)
+    u = torch.empty_like(v) if want_u else None
+    o = fds_solve_opts(int(max_iters), FDS_FP64, float(tol), int(bool(unfiltered)), 0)
+    st = fds_solve_stats()
+    _check(lib().fds_solve_adjoint(op.handle, _ptr(v), v.shape[0], _ptr(y), _ptr(u), C.byref(o),
+                                   C.byref(st) if stats else None))
+    hist = list(st.history[: st.iters + 1]) if stats else []
+    return y, u, {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres, "history": hist}
 
 
 def fds_solve_system_noalloc(op: Op, w: torch.Tensor, j_out: torch.Tensor, sweeps: int = 2) -> torch.Tensor:

@@ -396,6 +396,7 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
                     "only the 8-point rule is implemented");
         FDS_REQUIRE(opts->precision == FDS_FP64 || opts->precision == FDS_FP32, FDS_ERR_NOTIMPL,
                     "assembly precision must be FDS_FP64 or FDS_FP32");
+        FDS_REQUIRE(opts->band_width >= 0, FDS_ERR_ARG, "band_width must be >= 0");
     }
     // host-side geometry validation (O(n) copy)
     std::vector<double> hn(2 * n);
@@ -448,7 +449,8 @@ static fds_op_s* new_operator(Ctx& c, const double* nodes, int64_t n, double k, 
             op.N32 = (float2*)c.dmalloc(mat);
             op.D32 = (float2*)c.dmalloc(mat);
             // cyclic band |d| <= nbw, with 2 nbw + 1 <= n so that the taps are distinct
-            op.nbw = (int)std::min<int64_t>(63, (n - 1) / 2);
+            const int64_t req = opts && opts->band_width > 0 ? opts->band_width : (n > 8192 ? 127 : 63);
+            op.nbw = (int)std::min<int64_t>(req, (n - 1) / 2);
             op.Nband = (double2*)c.dmalloc(sizeof(double2) * (2 * op.nbw + 1) * (size_t)n);
         } else {
             const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
@@ -765,6 +767,27 @@ fds_status fds_solve_system(fds_op op, const void* w, int64_t nrhs, void* j_out,
         FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
         if (nrhs == 0) return;
         run_solve_system(op->impl, (const double2*)w, nrhs, (double2*)j_out, (double2*)y_out, it, tol, stats, unf);
+    });
+}
+
+fds_status fds_solve_adjoint(fds_op op, const void* v, int64_t nrhs, void* y_out, void* u_out,
+                             const fds_solve_opts* opts, fds_solve_stats* stats) {
+    return guarded([&] {
+        FDS_REQUIRE(op && v && y_out && nrhs >= 0, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(v != y_out && v != u_out, FDS_ERR_ARG, "outputs may not alias v");
+        require_stage(op->impl, Stage::Factored, "fds_solve_adjoint");
+        int it = 4;
+        double tol = 1e-12;
+        bool unf = false;
+        if (opts) {
+            FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 solves are implemented");
+            it = opts->max_iters;
+            tol = opts->tol;
+            unf = opts->unfiltered != 0;
+        }
+        FDS_REQUIRE(it >= 0 && it <= 1000, FDS_ERR_ARG, "max_iters out of range");
+        if (nrhs == 0) return;
+        run_solve_adjoint(op->impl, (const double2*)v, nrhs, (double2*)y_out, (double2*)u_out, it, tol, stats, unf);
     });
 }
 

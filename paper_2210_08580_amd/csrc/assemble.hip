@@ -45,35 +45,6 @@ namespace fds {
 constexpr int TB = 63;          // output columns (= rows) per tile
 constexpr int WAVES = 4;        // wavefronts per workgroup
 
-// Does tile (I, J) of the TB x TB tiling hold an entry (i, c) with cyclic
-// |c - i| <= bw? The differences c - i over the tile fill [dmin, dmax].
-__host__ __device__ inline bool tile_in_band(int I, int J, int n, int bw) {
-    if (bw < 0) return false;
-    const int r0 = I * TB, r1 = (n < r0 + TB ? n : r0 + TB) - 1;
-    const int c0 = J * TB, c1 = (n < c0 + TB ? n : c0 + TB) - 1;
-    const int dmin = c0 - r1, dmax = c1 - r0;
-    for (int m = -1; m <= 1; ++m)
-        if (dmax >= m * n - bw && dmin <= m * n + bw) return true;
-    return false;
-}
-
-// Band tiles by index t in [0, 3T): (I, I + o mod T), I = t / 3, o = t % 3. With
-// bw <= TB every band entry lies within cyclic tile distance 2 (2 only across the
-// narrow last tile); an index whose unordered pair {I, J} misses the band or was
-// already produced by a smaller index yields false, so each band tile comes once.
-__host__ __device__ inline bool band_tile(int t, int T, int n, int bw, int& I, int& J) {
-    I = t / 3;
-    const int o = t % 3;
-    J = (I + o) % T;
-    if (!tile_in_band(I, J, n, bw)) return false;
-    for (int o2 = 0; o2 < o; ++o2)
-        if ((I + o2) % T == J) return false;
-    for (int o2 = 0; o2 < 3; ++o2)
-        if ((J + o2) % T == I && 3 * J + o2 < t) return false;
-    return true;
-}
-
-
 // reduced far-field rules: [order 4: xi, w psi_0, w psi_1][order 3: same]
 // Reduced Gauss rules on [0, 1] for n = 2 .. 6 points, rule n at offset
 // low_rule_offset(n): xi[n], w psi_0(xi)[n], w psi_1(xi)[n].
@@ -95,9 +66,8 @@ struct FarParams {
     void* __restrict__ S;             // complex128 or complex64, row-major n x n
     void* __restrict__ Nm;
     void* __restrict__ D;
-    double2* __restrict__ nband;      // N on the cyclic band |d| <= bw (FP32 operators)
-    int bw;                           // band half-width (-1: no band)
-    int band_pass;                    // 1: the tiles holding band entries (FP32 operators), 0: the others
+    int bw;                           // FP32 operators: N on the cyclic band |d| <= bw is written as
+                                      // zero here (asm_nband_kernel computes it in FP64); -1: no band
     double k;
     int n;
     int nsub;
@@ -192,16 +162,10 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
     const int64_t tile = work / P.nsub;
     const int sub = (int)(work - tile * P.nsub);
     const int n = P.n;
-    int I, J;
-    if (P.band_pass) {
-        if (!band_tile((int)tile, (n + TB - 1) / TB, n, P.bw, I, J)) return;
-    } else {
-        J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
-        while ((int64_t)J * (J + 1) / 2 > tile) --J;
-        while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
-        I = (int)(tile - (int64_t)J * (J + 1) / 2);
-        if (tile_in_band(I, J, n, P.bw)) return;   // done by the band pass
-    }
+    int J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((int64_t)J * (J + 1) / 2 > tile) --J;
+    while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
+    const int I = (int)(tile - (int64_t)J * (J + 1) / 2);
     const int i0 = I * TB + sub * P.tr;
     const int i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), n);
     if (i0 >= i1) return;
@@ -234,7 +198,10 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
         const int p = pr < 0 ? pr + n : pr;
         int dd = p - q;
         dd = dd < 0 ? -dd : dd;
-        const bool active = qvalid && dd > 1 && dd < n - 1;
+        // far pairs; with an FP64 band (complex64 operators) those whose four entries
+        // (offsets o - 1 .. o + 1, o = q - p) all lie in it are left to the band kernel
+        const int cd = dd < n - dd ? dd : n - dd;
+        const bool active = qvalid && cd > 1 && cd >= P.bw;
         CT S00 = z, S01 = z, S10 = z, S11 = z;
         CT D00 = z, D01 = z, D10 = z, D11 = z;
         CT T00 = z, T01 = z, T10 = z, T11 = z;
@@ -387,15 +354,9 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
             dcy = 2 * dcy > n ? dcy - n : dcy;
             const bool inband = (dcy < 0 ? -dcy : dcy) <= P.bw;
             if (writes) {
-                if (inband) {
-                    // N on the band is kept in complex128 (written by the FP64 band
-                    // pass); the complex64 matrix holds zeros there
-                    const int bs = 2 * P.bw + 1;
-                    const double2 vb = make_double2((double)vN.x, (double)vN.y);
-                    P.nband[(int64_t)i * bs + dcy + P.bw] = vb;
-                    if (mirror) P.nband[(int64_t)col * bs - dcy + P.bw] = vb;
-                    vN = CT{0, 0};
-                }
+                // N on the band is kept in complex128 (asm_nband_kernel); the complex64
+                // matrix holds zeros there
+                if (inband) vN = CT{0, 0};
                 OT wS, wN, wD, wT;
                 to_out(cadd(rS1, nS), wS);
                 to_out(vN, wN);
@@ -457,6 +418,188 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarP
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+// ------------------------------------------------ the band of complex64 operators
+// The hypersingular N of the mixed-precision operators on the cyclic band
+// |j - i| <= w, in FP64 and stored in complex128 (its O(1) entries near the
+// diagonal meet eigenvalues O(h) on smooth vectors, so FP32 errors there would
+// be amplified ~1/h), and S and D there in FP64 (complex64 output). The FP32 far
+// pass leaves out the panel pairs whose four entries all lie in the band.
+// Far panel pairs only: the self and adjacent pairs follow in asm_near /
+// asm_band.
+// Pass 1 (asm_nband_blocks_kernel): one wavefront per 64 consecutive row panels p
+// and one panel offset o = q - p in [2, w + 1], uniform over the wavefront and
+// with it the quadrature order. It stores the 2 x 2 blocks of S, N, D and of the
+// transposed double layer T (D(j, i) from the same kernel values) of the pair
+// (p, p + o) as blk[o - 2][m][p], m = 4 kind + 2 a + b.
+// Pass 2 (asm_nband_combine_kernel): one thread per entry (i, d), d in [0, w],
+// j = i + d: X(i, j) = B(i, d)[0][0] + B(i, d - 1)[0][1] + B(i - 1, d)[1][1]
+// + B(i - 1, d + 1)[1][0] with B(p, o) = 0 for |o| <= 1; N and S are symmetric
+// and D(j, i) is the same sum over T, so (j, i) is written from the same thread.
+struct NBandParams {
+    const double* __restrict__ gx;
+    const double* __restrict__ gy;
+    const double* __restrict__ h;
+    const double* __restrict__ nx;
+    const double* __restrict__ ny;
+    const double* __restrict__ nodes;
+    const double* __restrict__ tab;   // HK_TAB (FP64)
+    double2* __restrict__ blk;        // [w][16][n] pair blocks
+    double2* __restrict__ nband;      // [n][2 w + 1]
+    float2* __restrict__ S;           // complex64 S, N (zero on the band) and D, row-major n x n
+    float2* __restrict__ D;
+    double k;
+    int n, w;
+    int nrb;                          // row blocks of 64
+};
+
+__global__ __launch_bounds__(64 * WAVES) void asm_nband_blocks_kernel(NBandParams P, W8 wt, WLow wl) {
+    __shared__ double tab[HK_TAB_DOUBLES];
+    __shared__ double wsh[16];
+    __shared__ double rl[WLOW_DOUBLES];
+    for (int t = threadIdx.x; t < HK_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
+    if (threadIdx.x < 8) {
+        wsh[threadIdx.x] = wt.wp0[threadIdx.x];
+        wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
+    }
+    if (threadIdx.x < WLOW_DOUBLES) rl[threadIdx.x] = wl.r[threadIdx.x];
+    __syncthreads();
+    const int wave = blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave >= P.nrb * P.w) return;
+    const int oi = wave / P.nrb, rb = wave - oi * P.nrb;
+    const int o = oi + 2;
+    const int n = P.n;
+    const int lane = threadIdx.x & 63;
+    const int pr = rb * 64 + lane;
+    const bool valid = pr < n;
+    const int p = valid ? pr : n - 1;
+    int q = p + o;
+    q = q >= n ? q - n : q;
+    const double k = P.k;
+    const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
+    const double hq = P.h[q], nxq = P.nx[q], nyq = P.ny[q];
+    const int p1 = p + 1 == n ? 0 : p + 1, q1 = q + 1 == n ? 0 : q + 1;
+    const double px0 = P.nodes[2 * p], py0 = P.nodes[2 * p + 1];
+    const double pex = P.nodes[2 * p1] - px0, pey = P.nodes[2 * p1 + 1] - py0;
+    const double qx0 = P.nodes[2 * q], qy0 = P.nodes[2 * q + 1];
+    const double qex = P.nodes[2 * q1] - qx0, qey = P.nodes[2 * q1 + 1] - qy0;
+    int ord = 0;
+    if (valid) {
+        const double hm = fmax(hp, hq);
+        const double dist = hypot(px0 + 0.5 * pex - qx0 - 0.5 * qex, py0 + 0.5 * pey - qy0 - 0.5 * qey) - 0.5 * (hp + hq);
+        const double kh = k * hm;
+        ord = 8;
+        if (kh <= 0.2 && dist >= 12.0 * hm) ord = 6;
+        if (kh <= 0.2 && dist >= 24.0 * hm) ord = 5;
+        if (kh <= 0.1 && dist >= 64.0 * hm) ord = 4;
+        if (kh <= 0.016 && dist >= 512.0 * hm) ord = 3;
+    }
+    const int no = __builtin_amdgcn_readfirstlane(wave_max_int(ord));
+    const double2 z = make_double2(0.0, 0.0);
+    double2 S[2][2] = {{z, z}, {z, z}}, D[2][2] = {{z, z}, {z, z}}, T[2][2] = {{z, z}, {z, z}};
+    const double* rx = rl + low_rule_offset(no < 8 ? no : 2);
+#pragma unroll 1
+    for (int a = 0; a < no; ++a) {
+        double xa, ya, wa0, wa1;
+        if (no == 8) {
+            xa = P.gx[8 * p + a];
+            ya = P.gy[8 * p + a];
+            wa0 = wsh[a];
+            wa1 = wsh[8 + a];
+        } else {
+            xa = px0 + rx[a] * pex;
+            ya = py0 + rx[a] * pey;
+            wa0 = rx[no + a];
+            wa1 = rx[2 * no + a];
+        }
+        double2 g0 = z, g1 = z, d0 = z, d1 = z, t0 = z, t1 = z;
+#pragma unroll 1
+        for (int b = 0; b < no; ++b) {
+            double yb, zb, w0, w1;
+            if (no == 8) {
+                yb = P.gx[8 * q + b];
+                zb = P.gy[8 * q + b];
+                w0 = wsh[b];
+                w1 = wsh[8 + b];
+            } else {
+                yb = qx0 + rx[b] * qex;
+                zb = qy0 + rx[b] * qey;
+                w0 = rx[no + b];
+                w1 = rx[2 * no + b];
+            }
+            const double dx = xa - yb, dy = ya - zb;
+            const double R = sqrt(fma(dx, dx, dy * dy));
+            const Bessel01 bs = hk_eval(k * R, tab);
+            const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
+            const double kr = 0.25 * k / R;
+            const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
+            const double dq = fma(dx, nxq, dy * nyq), dp = -fma(dx, nxp, dy * nyp);
+            const double2 cd = cscale(c, dq), ct = cscale(c, dp);
+            g0 = fma_cr(w0, g, g0);
+            g1 = fma_cr(w1, g, g1);
+            d0 = fma_cr(w0, cd, d0);
+            d1 = fma_cr(w1, cd, d1);
+            t0 = fma_cr(w0, ct, t0);
+            t1 = fma_cr(w1, ct, t1);
+        }
+        S[0][0] = fma_cr(wa0, g0, S[0][0]); S[0][1] = fma_cr(wa0, g1, S[0][1]);
+        S[1][0] = fma_cr(wa1, g0, S[1][0]); S[1][1] = fma_cr(wa1, g1, S[1][1]);
+        D[0][0] = fma_cr(wa0, d0, D[0][0]); D[0][1] = fma_cr(wa0, d1, D[0][1]);
+        D[1][0] = fma_cr(wa1, d0, D[1][0]); D[1][1] = fma_cr(wa1, d1, D[1][1]);
+        T[0][0] = fma_cr(wa0, t0, T[0][0]); T[0][1] = fma_cr(wa0, t1, T[0][1]);
+        T[1][0] = fma_cr(wa1, t0, T[1][0]); T[1][1] = fma_cr(wa1, t1, T[1][1]);
+    }
+    if (!valid) return;
+    const double hh = hp * hq;
+    // Maue form N_ab = s_a s_b I0/(hp hq) - k^2 (n_p.n_q) S_ab; the sums above lack the
+    // factor hp hq of S_ab and I0, which cancels in the first term
+    const double2 I0h = cadd(cadd(S[0][0], S[0][1]), cadd(S[1][0], S[1][1]));
+    const double kk = -k * k * fma(nxp, nxq, nyp * nyq) * hh;
+    double2* out = P.blk + (size_t)oi * 16 * n + p;
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            const int m = 2 * a2 + b2;
+            const double2 nab = a2 == b2 ? cadd(I0h, cscale(S[a2][b2], kk)) : csub(cscale(S[a2][b2], kk), I0h);
+            out[(size_t)(0 + m) * n] = cscale(S[a2][b2], hh);
+            out[(size_t)(4 + m) * n] = nab;
+            out[(size_t)(8 + m) * n] = cscale(D[a2][b2], hh);
+            out[(size_t)(12 + m) * n] = cscale(T[a2][b2], hh);
+        }
+}
+
+__global__ __launch_bounds__(256) void asm_nband_combine_kernel(NBandParams P) {
+    const int n = P.n, w = P.w;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * (w + 1)) return;
+    const int d = (int)(t / n), i = (int)(t - (int64_t)d * n);
+    const int im = i == 0 ? n - 1 : i - 1;
+    double2 x[4];   // S, N, D, T
+#pragma unroll
+    for (int kd = 0; kd < 4; ++kd) x[kd] = make_double2(0.0, 0.0);
+    // (p, o, a, b): (i, d, 0, 0), (i, d - 1, 0, 1), (i - 1, d, 1, 1), (i - 1, d + 1, 1, 0)
+    const int ps[4] = {i, i, im, im}, os[4] = {d, d - 1, d, d + 1}, ms[4] = {0, 1, 3, 2};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (os[u] < 2) continue;
+        const double2* b = P.blk + (size_t)(os[u] - 2) * 16 * n + ps[u];
+#pragma unroll
+        for (int kd = 0; kd < 4; ++kd) x[kd] = cadd(x[kd], b[(size_t)(4 * kd + ms[u]) * n]);
+    }
+    int j = i + d;
+    j = j >= n ? j - n : j;
+    const int bs = 2 * w + 1;
+    const float2 sf = make_float2((float)x[0].x, (float)x[0].y);
+    P.nband[(int64_t)i * bs + w + d] = x[1];
+    P.S[(int64_t)i * n + j] = sf;
+    P.D[(int64_t)i * n + j] = make_float2((float)x[2].x, (float)x[2].y);
+    if (d > 0) {
+        P.nband[(int64_t)j * bs + w - d] = x[1];
+        P.S[(int64_t)j * n + i] = sf;
+        P.D[(int64_t)j * n + i] = make_float2((float)x[3].x, (float)x[3].y);
+    }
+}
 
 // ----------------------------------------------------------------- near pairs
 struct NearParams {
@@ -618,9 +761,7 @@ static FarParams far_params(Op& op) {
     fp.D = f32 ? (void*)op.D32 : (void*)op.D;
     fp.k = op.k;
     fp.n = n;
-    fp.nband = op.Nband;
     fp.bw = f32 ? op.nbw : -1;
-    fp.band_pass = 0;
     const int64_t T = (n + TB - 1) / TB;
     fp.nsub = 2;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
@@ -659,6 +800,32 @@ static void launch_near_band(Op& op, const FarParams& fp, const W8& wt) {
     c.dfree(nb);   // stream-ordered release (see Ctx::dfree)
 }
 
+// S, N, D on the cyclic band |d| <= nbw of complex64 operators, in FP64.
+static void launch_nband(Op& op, const W8& wt, const WLow& wlow) {
+    Ctx& c = *op.ctx;
+    NBandParams P;
+    P.gx = op.gx; P.gy = op.gy; P.h = op.h; P.nx = op.nx; P.ny = op.ny; P.nodes = op.nodes;
+    P.tab = c.hk_tab;
+    P.nband = op.Nband;
+    P.S = op.S32;
+    P.D = op.D32;
+    P.k = op.k;
+    P.n = (int)op.n;
+    P.w = op.nbw;
+    P.nrb = (P.n + 63) / 64;
+    P.blk = static_cast<double2*>(c.dmalloc(sizeof(double2) * 16 * (size_t)P.n * std::max(P.w, 1)));
+    {
+        KScope _ks(c, "asm_nband");
+        const unsigned nb1 = (unsigned)(((int64_t)P.nrb * P.w + WAVES - 1) / WAVES);
+        if (nb1 > 0)
+            hipLaunchKernelGGL(asm_nband_blocks_kernel, dim3(nb1), dim3(64 * WAVES), 0, c.stream, P, wt, wlow);
+        const int64_t tot = (int64_t)P.n * (P.w + 1);
+        hipLaunchKernelGGL(asm_nband_combine_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, P);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    c.dfree(P.blk);   // stream-ordered release (see Ctx::dfree)
+}
+
 void launch_assemble(Op& op) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
@@ -667,7 +834,6 @@ void launch_assemble(Op& op) {
     far_rules(op, wt, wlow);
     const FarParams fp = far_params(op);
     const bool f32 = op.prec == FDS_FP32;
-    const int64_t T = (n + TB - 1) / TB;
     const unsigned nblk = (unsigned)((fp.nwork + WAVES - 1) / WAVES);
     {
         KScope _ks(c, "asm_far");
@@ -678,23 +844,7 @@ void launch_assemble(Op& op) {
                                wlow);
     }
     FDS_HIP_TRY(hipGetLastError());
-    if (f32) {
-        // the tiles holding band entries, in FP64 (complex64 output, N on the band
-        // in complex128), split 8 ways for occupancy
-        FarParams bpf = fp;
-        bpf.tab = c.hk_tab;
-        bpf.band_pass = 1;
-        bpf.nsub = 8;
-        bpf.tr = (TB + bpf.nsub - 1) / bpf.nsub;
-        bpf.nwork = 3 * T * bpf.nsub;
-        const unsigned nb2 = (unsigned)((bpf.nwork + WAVES - 1) / WAVES);
-        {
-            KScope _ks(c, "asm_far_band");
-            hipLaunchKernelGGL((asm_far_kernel<false, true>), dim3(nb2), dim3(64 * WAVES), 0, c.stream, bpf, wt,
-                               wlow);
-        }
-        FDS_HIP_TRY(hipGetLastError());
-    }
+    if (f32) launch_nband(op, wt, wlow);
     launch_near_band(op, fp, wt);
 }
 

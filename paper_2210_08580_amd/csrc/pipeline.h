@@ -16,10 +16,12 @@ void run_factor(Op& op);
 void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,
                     double2* w);
 void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, double2* y_out, int max_iters,
-                      double tol, fds_solve_stats* stats, bool unfiltered);
+                      double tol, fds_solve_stats* stats, bool unfiltered, bool adjoint = false);
 void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2* j_out, double2* y_out,
                int max_iters, double tol, fds_solve_stats* stats, bool unfiltered = false);
 void gram_inv(Op& op, const double2* X, int64_t ncols, double2* Y);
+void run_solve_adjoint(Op& op, const double2* v, int64_t nrhs, double2* y_out, double2* u_out, int max_iters,
+                       double tol, fds_solve_stats* stats, bool unfiltered);
 // allocation-free Woodbury solve + filtered refinement sweeps (static scratch array)
 void init_noalloc_scratch(Ctx& c);
 void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps);

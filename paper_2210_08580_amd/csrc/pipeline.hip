@@ -578,6 +578,78 @@ static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
     }
 }
 
+// The adjoint system. With y = G^{1/2} u, the adjoint (beta I + P C)^H y = v of the
+// paper's filtered system reads, in the coordinates u (the adjoint's current
+// coefficients),
+//     (beta I + G^{-1} conj(Bt) V_g^T G) u = w' = G^{-1/2} v,
+// and its skeleton form beta I + G^{-1} W_j^H U_j^H G has the Woodbury inverse
+//     b/beta - beta^{-2} G^{-1} W_j^H (K^{-1})^H U_j^H G b
+// with the same core K = I + W_j U_j/beta, ((U_j K^{-1})^H = Up^H).
+// b <- that inverse applied to b (n x nrhs); z: r x nrhs, t: n x nrhs scratch.
+static void woodbury_apply_adj(Op& op, double2* b, int64_t nrhs, double2* z, double2* t) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, r = op.rank;
+    const double ib = 1.0 / op.beta;
+    if (r > 0) {
+        gram_mul<double2>(c, op.g_diag, op.g_off, n, b, nrhs, n, 1.0, 0.0, t, n);
+        zgemm(c, OP_C, OP_N, r, (int)nrhs, n, kOne, op.Up, n, t, n, kZero, z, r);
+        zgemm(c, OP_C, OP_N, n, (int)nrhs, r, kOne, op.Wr, r, z, r, kZero, t, n);
+        gram_inv(op, t, nrhs, t);
+        axpby(c, make_double2(-ib * ib, 0.0), t, make_double2(ib, 0.0), b, (int64_t)n * nrhs);
+    } else {
+        axpby(c, kZero, b, make_double2(ib, 0.0), b, (int64_t)n * nrhs);
+    }
+}
+
+// res = w' - (beta I + G^{-1} conj(Bt) V_g^T G) u  (filtered adjoint; z: n_eff x nrhs, t: n x nrhs)
+static void filtered_residual_adj(Op& op, const double2* w, const double2* u, int64_t nrhs, double2* res,
+                                  double2* z, double2* t) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n, ne = op.n_eff;
+    const int64_t tot = (int64_t)n * nrhs;
+    gram_mul<double2>(c, op.g_diag, op.g_off, n, u, nrhs, n, 1.0, 0.0, t, n);
+    zgemm(c, OP_T, OP_N, ne, (int)nrhs, n, kOne, op.Vgc, n, t, n, kZero, z, ne);
+    zgemm(c, OP_C, OP_N, n, (int)nrhs, ne, kOne, op.Btr, ne, z, ne, kZero, t, n);
+    gram_inv(op, t, nrhs, t);
+    FDS_HIP_TRY(hipMemcpyAsync(res, w, sizeof(double2) * tot, hipMemcpyDeviceToDevice, c.stream));
+    axpby(c, make_double2(-op.beta, 0.0), u, kOne, res, tot);
+    axpby(c, make_double2(-1.0, 0.0), t, kOne, res, tot);
+}
+
+// res = w' - (beta I + C_u^H) u for the unfiltered operator in the adjoint coordinates:
+// C_u^H u = G^{-1} N^H G^{-1} S^H u - u/4 (EFIE part), -G^{-1} D^H u (MFIE part).
+// S, N are complex symmetric and G real, so with u~ = conj(u) the products are
+// conj(G^{-1} N G^{-1} S u~) and conj(G^{-1} D^T u~): the stored operators are used
+// untransposed (as for the forward residual), and complex64 ones through their
+// FP64 band as well. t0, t1, t2: n x nrhs scratch.
+static void unfiltered_residual_adj(Op& op, const double2* w, const double2* u, int64_t nrhs, double2* res,
+                                    double2* t0, double2* t1, double2* t2) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const int64_t tot = (int64_t)n * nrhs;
+    conj_copy(c, u, t0, tot);                                            // u~
+    bool any = false;
+    if (has_efie(op.form)) {
+        op_gemm(op, s_op(op.form), OP_T, nrhs, kOne, t0, kZero, t1);     // S u~ (S_y for YCFIE)
+        gram_inv(op, t1, nrhs, t1);
+        op_gemm(op, 1, OP_T, nrhs, kOne, t1, kZero, t2);                 // N G^-1 S u~
+        gram_inv(op, t2, nrhs, t2);
+        any = true;
+    }
+    if (has_mfie(op.form)) {
+        const double a = op.form == FDS_MFIE ? 1.0 : op.alpha;
+        op_gemm(op, 2, OP_N, nrhs, kOne, t0, kZero, t1);                 // D^T u~ (column-major view of D)
+        gram_inv(op, t1, nrhs, t1);
+        if (any) axpby(c, make_double2(-a, 0.0), t1, kOne, t2, tot);     // E - alpha M
+        else axpby(c, make_double2(-a, 0.0), t1, kZero, t2, tot);        // -M
+    }
+    conj_copy(c, t2, t1, tot);
+    FDS_HIP_TRY(hipMemcpyAsync(res, w, sizeof(double2) * tot, hipMemcpyDeviceToDevice, c.stream));
+    const double bu = has_efie(op.form) ? op.beta - 0.25 : op.beta;
+    axpby(c, make_double2(-bu, 0.0), u, kOne, res, tot);
+    axpby(c, make_double2(-1.0, 0.0), t1, kOne, res, tot);
+}
+
 // r = w - (beta I + C_j) j with the unfiltered compact part in j coordinates,
 // C_j = G^{-1} S G^{-1} N - I/4 (EFIE), -G^{-1} D (MFIE), EFIE + alpha MFIE (CFIE).
 static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int64_t nrhs, double2* res,
@@ -656,16 +728,21 @@ void run_solve(Op& op, const double2* f, const double2* h, int64_t nrhs, double2
 
 // The Woodbury solve and refinement from w (j coordinates, the filter's form).
 void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, double2* y_out, int max_iters,
-                      double tol, fds_solve_stats* stats, bool unfiltered) {
+                      double tol, fds_solve_stats* stats, bool unfiltered, bool adjoint) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n, ne = op.n_eff;
     const size_t blk = sizeof(double2) * (size_t)n * nrhs;
     double2* res = static_cast<double2*>(c.dmalloc(blk));
     double2* z = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)std::max(op.rank, ne) * nrhs));
+    double2* ta = adjoint ? static_cast<double2*>(c.dmalloc(blk)) : nullptr;   // adjoint Woodbury scratch
+    auto precond = [&](double2* b) {
+        if (adjoint) woodbury_apply_adj(op, b, nrhs, z, ta);
+        else woodbury_apply(op, b, nrhs, z);
+    };
     // ---- Woodbury solve
     double2* jv = j_out;
     FDS_HIP_TRY(hipMemcpyAsync(jv, w, blk, hipMemcpyDeviceToDevice, c.stream));
-    woodbury_apply(op, jv, nrhs, z);
+    precond(jv);
     // ---- refinement against beta I + V_g Bt^T (the uncompressed filtered operator)
     double* nrm = static_cast<double*>(c.dmalloc(sizeof(double) * 2 * nrhs));
     std::vector<double> hn(2 * nrhs);
@@ -678,13 +755,19 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
     }
     double2* t1 = nullptr;
     double2* t2 = nullptr;
-    if (unfiltered) {
+    double2* t0 = nullptr;
+    if (unfiltered || adjoint) {
         t1 = static_cast<double2*>(c.dmalloc(blk));
         t2 = static_cast<double2*>(c.dmalloc(blk));
     }
+    if (unfiltered && adjoint) t0 = static_cast<double2*>(c.dmalloc(blk));
     for (int it = 0;; ++it) {
         if (!stats && it >= max_iters) break;
-        if (unfiltered) {
+        if (adjoint && unfiltered) {
+            unfiltered_residual_adj(op, w, jv, nrhs, res, t0, t1, t2);
+        } else if (adjoint) {
+            filtered_residual_adj(op, w, jv, nrhs, res, z, t1);
+        } else if (unfiltered) {
             unfiltered_residual(op, w, jv, nrhs, res, t1, t2);
         } else {
             // res = w - beta j - V_g (Bt^T j)
@@ -709,7 +792,7 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
             }
         }
         if (it >= max_iters) break;
-        woodbury_apply(op, res, nrhs, z);
+        precond(res);
         axpby(c, kOne, res, kOne, jv, (int64_t)n * nrhs);
         ++iters;
     }
@@ -720,14 +803,37 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
     c.dfree(nrm);
     c.dfree(res);
     c.dfree(z);
+    c.dfree(t0);
     c.dfree(t1);
     c.dfree(t2);
+    c.dfree(ta);
     if (stats) {
         stats->iters = iters;
         stats->converged = conv ? 1 : 0;
         stats->relres = rel;
         FDS_REQUIRE(conv, FDS_ERR_NOCONV, "refinement did not reach the requested tolerance");
     }
+}
+
+// The adjoint solve (beta I + P C)^H y = v (or of the unfiltered operator) from v
+// in the normalised coordinates: u = G^{-1/2} y is solved for with w' = G^{-1/2} v.
+void run_solve_adjoint(Op& op, const double2* v, int64_t nrhs, double2* y_out, double2* u_out, int max_iters,
+                       double tol, fds_solve_stats* stats, bool unfiltered) {
+    Ctx& c = *op.ctx;
+    const size_t blk = sizeof(double2) * (size_t)op.n * nrhs;
+    double2* wv = static_cast<double2*>(c.dmalloc(blk));
+    double2* u = u_out ? u_out : static_cast<double2*>(c.dmalloc(blk));
+    try {
+        FDS_HIP_TRY(hipMemcpyAsync(wv, v, blk, hipMemcpyDeviceToDevice, c.stream));
+        apply_gram_power(op, -1, wv, nrhs);
+        run_solve_system(op, wv, nrhs, u, y_out, max_iters, tol, stats, unfiltered, true);
+    } catch (...) {
+        c.dfree(wv);
+        if (!u_out) c.dfree(u);
+        throw;
+    }
+    c.dfree(wv);
+    if (!u_out) c.dfree(u);
 }
 
 // ---------------------------------------------------------------- allocation-free solve

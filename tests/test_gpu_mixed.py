@@ -58,30 +58,36 @@ def test_cgemm_parity(ctx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() <= 8 * EPS32 * scale
 
 
-ASM_CASES = [("star", 300, 10.0), ("ellipse", 257, 5.0), ("circle", 64, 1.0), ("random", 400, 20.0),
-             ("star", 190, 10.0), ("star", 40, 3.0),
-             # band tiles next to a narrow last tile (127 = 2 x 63 + 1, 130 = 2 x 63 + 4, 64 = 63 + 1)
-             ("ellipse", 127, 4.0), ("random", 130, 6.0), ("star", 64, 2.0)]
+ASM_CASES = [("star", 300, 10.0, 0), ("ellipse", 257, 5.0, 0), ("circle", 64, 1.0, 0), ("random", 400, 20.0, 0),
+             ("star", 190, 10.0, 0), ("star", 40, 3.0, 0),
+             # band widths around the runs of 8 offsets and the row blocks of 63 panels
+             ("ellipse", 127, 4.0, 0), ("random", 130, 6.0, 0), ("star", 64, 2.0, 0),
+             ("star", 600, 10.0, 127), ("ellipse", 301, 5.0, 100), ("random", 200, 3.0, 5), ("circle", 9, 1.0, 0)]
 
 
-@pytest.mark.parametrize("kind,n,k", ASM_CASES)
-def test_fp32_assembly_parity(ctx, kind, n, k):
-    print(f"case: fp32 assembly {kind} n={n} k={k}", flush=True)
+@pytest.mark.parametrize("kind,n,k,bw", ASM_CASES)
+def test_fp32_assembly_parity(ctx, kind, n, k, bw):
+    print(f"case: fp32 assembly {kind} n={n} k={k} band_width={bw}", flush=True)
     nodes = wl.curve_nodes(kind, n)
-    op = B.fds_assemble(ctx, torch.from_numpy(nodes).cuda(), k, precision="fp32")
+    op = B.fds_assemble(ctx, torch.from_numpy(nodes).cuda(), k, precision="fp32", band_width=bw)
     assert B.fds_op_precision(op) == B.FDS_FP32
     got = [t.cpu().numpy().astype(np.complex128) for t in B.fds_op_matrices(op)]
     # N near the diagonal is kept in complex128 beside zeros in the complex64 matrix
     band, w = B.fds_op_nband(op)
     band = band.cpu().numpy()
-    assert w == min(63, (n - 1) // 2)
+    assert w == min(bw if bw > 0 else 63, (n - 1) // 2)
     i = np.arange(n)
     ref = assembly.assemble(geometry.mesh(nodes), k)
+    smax = np.abs(ref[0]).max()
     for d in range(-w, w + 1):
-        assert np.all(got[1][i, (i + d) % n] == 0)
-        got[1][i, (i + d) % n] = band[:, d + w]
+        j = (i + d) % n
+        assert np.all(got[1][i, j] == 0)
+        got[1][i, j] = band[:, d + w]
         # the band is FP64: same tolerance as the FP64 assembly parity
-        assert np.abs(band[:, d + w] - ref[1][i, (i + d) % n]).max() <= 1e-12 * np.abs(ref[1]).max()
+        assert np.abs(band[:, d + w] - ref[1][i, j]).max() <= 1e-12 * np.abs(ref[1]).max()
+        # S there: FP64 values rounded to complex64 (twice on |d| <= 2, where the
+        # near-pair blocks are added to the stored far part)
+        assert np.all(np.abs(got[0][i, j] - ref[0][i, j]) <= 2.5e-7 * np.abs(ref[0][i, j]) + 1e-13 * smax)
     for name, g, r in zip("SND", got, ref):
         err = np.abs(g - r).max() / np.abs(r).max()
         assert err <= 2e-6, (name, err)
