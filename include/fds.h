@@ -84,7 +84,8 @@ typedef struct fds_asm_opts {
     int32_t band_width;  /* FDS_FP32 only: half-width w of the cyclic band
                             |i - j| <= w on which N (and S) are computed in FP64,
                             N kept in complex128 (fds_op_nband); 0 = default
-                            (63, or 127 above 8192 panels); clipped to (n-1)/2 */
+                            (63 up to 8192 panels, n/64 - 1 above); clipped to
+                            (n-1)/2 */
     int32_t reserved[5];
 } fds_asm_opts;
 

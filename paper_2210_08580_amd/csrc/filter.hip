@@ -207,8 +207,12 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
         __syncthreads();
         if (k0 + (int)threadIdx.x < kend) sh[threadIdx.x] = st[k0 + threadIdx.x];
         __syncthreads();
+        // the next step's coefficients are read from LDS one step ahead, so that their
+        // latency overlaps the current step; B and s are rescaled every fourth step (one
+        // step changes their magnitude by well under 1e40, far inside the exponent range)
+        SturmStep t = sh[0];
         for (int k = k0; k < kend; ++k) {
-            const SturmStep t = sh[k - k0];
+            const SturmStep tn = sh[min(k + 1, kend - 1) - k0];
             double det = fma(b11, b22, -b12 * b12);
             if (det == 0.0) det = 1e-300 * (fabs(b11 * b22) + b12 * b12 + 1e-300);
             cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
@@ -219,11 +223,19 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
             const double n11 = fma(det, m1, -(s1 * e1) * b22);
             const double n22 = fma(det, m2, -(s2 * e2) * b11);
             const double n12 = fma(det, x, (s1 * e2) * b12);
-            const double f = inv_pow2_of(fmax(fmax(fabs(n11), fabs(n22)), fmax(fabs(n12), 1e-300)));
-            b11 = n11 * f;
-            b22 = n22 * f;
-            b12 = n12 * f;
-            sc = det * f;
+            if ((k & 3) == 3) {
+                const double f = inv_pow2_of(fmax(fmax(fabs(n11), fabs(n22)), fmax(fabs(n12), 1e-300)));
+                b11 = n11 * f;
+                b22 = n22 * f;
+                b12 = n12 * f;
+                sc = det * f;
+            } else {
+                b11 = n11;
+                b22 = n22;
+                b12 = n12;
+                sc = det;
+            }
+            t = tn;
         }
     }
     double det = fma(b11, b22, -b12 * b12);
@@ -257,8 +269,12 @@ __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int idx = first + i;
     const int NS = 64 * BS_WAVES;
-    // tight bracket: eigenvalue idx of the P1 pencil lies above lc = l1c ceil(idx/2)^2 and
-    // below lc (1 + hfac lc) (hfac = h_max^2 / 6), with small safety margins
+    // tight bracket: eigenvalue idx of the P1 pencil lies above lc = l1c ceil(idx/2)^2 (the
+    // polygon's Laplace-Beltrami eigenvalue, of which the P1 value is a Rayleigh-Ritz
+    // upper bound) by about the interpolation excess lc^2 <h^2>/12 (hfac = <h^2>/12 with
+    // <h^2> = sum h^3 / sum h); measured on star, ellipse, random and perturbed curves
+    // the deviation from lc (1 + hfac lc) stays within 0.32 of that excess, so the
+    // bracket [lc (1 + 0.2 hfac lc), lc (1 + 1.6 hfac lc)] with small safety margins
     double lo, hi;
     if (idx == 0) {
         lo = -1e-6 * l1c;
@@ -266,8 +282,8 @@ __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, 
     } else {
         const double kk = (double)((idx + 1) / 2);
         const double lc = l1c * kk * kk;
-        lo = lc * (1.0 - 1e-9);
-        hi = lc * (1.0 + hfac * lc) * (1.0 + 1e-6) + 1e-6 * l1c;
+        lo = lc * (1.0 + 0.2 * hfac * lc) * (1.0 - 1e-9);
+        hi = lc * (1.0 + 1.6 * hfac * lc) * (1.0 + 1e-9) + 1e-9 * l1c;
     }
     if (!(hi > lo)) {
         lo = glo;
@@ -420,17 +436,18 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
     auto band = [&](const double* B, int t, int j) {   // entry t of row j of A (h = 0) or A' (h = 1)
         return h == 0 ? B[(int64_t)t * n + j] : B[(int64_t)(4 - t) * n + (n - 1 - j)];
     };
-    double w0[5], w1[5], w2[5];
-    // rows 0, 1, 2, shifted to the columns 0..4 of the window
+    // window rows A, B, C (the rows j, j+1, j+2 of the partly eliminated band,
+    // shifted to the columns j .. j+4) and their right-hand-side entries
+    double A[5], Bw[5], Cw[5];
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
-        w0[t] = t + 2 < 5 ? band(Lb, t + 2, 0) - s * band(Gb, t + 2, 0) : 0.0;
-        w1[t] = t + 1 < 5 ? band(Lb, t + 1, 1) - s * band(Gb, t + 1, 1) : 0.0;
-        w2[t] = band(Lb, t, 2) - s * band(Gb, t, 2);
+        A[t] = t + 2 < 5 ? band(Lb, t + 2, 0) - s * band(Gb, t + 2, 0) : 0.0;
+        Bw[t] = t + 1 < 5 ? band(Lb, t + 1, 1) - s * band(Gb, t + 1, 1) : 0.0;
+        Cw[t] = band(Lb, t, 2) - s * band(Gb, t, 2);
     }
-    double y0 = start_value(i, node_of(trow(h, 0, n), n));
-    double y1 = start_value(i, node_of(trow(h, 1, n), n));
-    double y2 = start_value(i, node_of(trow(h, 2, n), n));
+    double yA = start_value(i, node_of(trow(h, 0, n), n));
+    double yB = start_value(i, node_of(trow(h, 1, n), n));
+    double yC = start_value(i, node_of(trow(h, 2, n), n));
     __shared__ double rows[64][10];
     for (int j0 = 0; j0 < m; j0 += 64) {
         // stage band rows j0+3 .. j0+66 in LDS (one per lane); every lane reads them all
@@ -452,55 +469,57 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
                 nl[t] = rows[j - j0][t];
                 ng[t] = rows[j - j0][5 + t];
             }
-            // rows j+1, j+2 exist: j + 2 <= m + 1 <= n - 3
-            int p = 0;
-            double best = fabs(w0[0]);
-            if (fabs(w1[0]) > best) { p = 1; best = fabs(w1[0]); }
-            if (fabs(w2[0]) > best) { p = 2; }
-            if (p == 1) {
+            const double ynext = start_value(i, node_of(trow(h, j + 3, n), n));   // j + 3 <= n - 2
+            // partial pivoting among the rows j, j+1, j+2 (rows j+1, j+2 exist: j + 2 <= m + 1
+            // <= n - 3), as selects: pivot row U, remaining rows R1, R2 in their order
+            const double fa = fabs(A[0]), fb = fabs(Bw[0]), fc = fabs(Cw[0]);
+            const bool sB = fb > fa;
+            const bool sC = fc > (sB ? fb : fa);
+            const bool sBo = sB && !sC;
+            const int p = sC ? 2 : (sB ? 1 : 0);
+            double U[5], R1[5], R2[5];
 #pragma unroll
-                for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w1[t]; w1[t] = q; }
-            } else if (p == 2) {
-#pragma unroll
-                for (int t = 0; t < 5; ++t) { const double q = w0[t]; w0[t] = w2[t]; w2[t] = q; }
+            for (int t = 0; t < 5; ++t) {
+                U[t] = sC ? Cw[t] : (sB ? Bw[t] : A[t]);
+                R1[t] = sBo ? A[t] : Bw[t];
+                R2[t] = sC ? A[t] : Cw[t];
             }
-            if (fabs(w0[0]) < pivmin) w0[0] = w0[0] < 0.0 ? -pivmin : pivmin;
-            const double inv = recip(w0[0]);
-            const double l1 = w1[0] * inv, l2 = w2[0] * inv;
-#pragma unroll
-            for (int t = 1; t < 5; ++t) {
-                w1[t] -= l1 * w0[t];
-                w2[t] -= l2 * w0[t];
-            }
-            {
-                const double a0 = y0, a1 = y1, a2 = y2;
-                y0 = p == 1 ? a1 : (p == 2 ? a2 : a0);
-                y1 = p == 1 ? a0 : a1;
-                y2 = p == 2 ? a0 : a2;
-            }
-            y1 -= l1 * y0;
-            y2 -= l2 * y0;
+            const double yU = sC ? yC : (sB ? yB : yA);
+            const double yR1 = sBo ? yA : yB;
+            const double yR2 = sC ? yA : yC;
+            const double u0 = fabs(U[0]) < pivmin ? (U[0] < 0.0 ? -pivmin : pivmin) : U[0];
+            const double inv = recip(u0);
+            const double l1 = R1[0] * inv, l2 = R2[0] * inv;
             if (act) {
                 const int64_t e = (int64_t)j * nw + i;
                 F.L[e] = make_double2(l1, l2);
                 F.P[e] = p;
-                F.IZ[e] = make_double2(inv, y0);
-                F.U12[e] = make_double2(w0[1], w0[2]);
-                F.U34[e] = make_double2(w0[3], w0[4]);
+                F.IZ[e] = make_double2(inv, yU);
+                F.U12[e] = make_double2(U[1], U[2]);
+                F.U34[e] = make_double2(U[3], U[4]);
             }
-            y0 = y1;
-            y1 = y2;
-            y2 = start_value(i, node_of(trow(h, j + 3, n), n));   // j + 3 <= n - 2
+            // eliminate and shift the window by one column
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                w0[t] = w1[t + 1];
-                w1[t] = w2[t + 1];
+                A[t] = fma(-l1, U[t + 1], R1[t + 1]);
+                Bw[t] = fma(-l2, U[t + 1], R2[t + 1]);
             }
-            w0[4] = 0.0;
-            w1[4] = 0.0;
+            A[4] = 0.0;
+            Bw[4] = 0.0;
 #pragma unroll
-            for (int t = 0; t < 5; ++t) w2[t] = fma(-s, ng[t], nl[t]);
+            for (int t = 0; t < 5; ++t) Cw[t] = fma(-s, ng[t], nl[t]);
+            yA = fma(-l1, yU, yR1);
+            yB = fma(-l2, yU, yR2);
+            yC = ynext;
         }
+    }
+    // the two reduced rows and their right-hand sides
+    double w0[5], w1[5];
+    const double y0 = yA, y1 = yB;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        w0[t] = A[t];
+        w1[t] = Bw[t];
     }
     if (act) {
         double* q = IF + (int64_t)h * 10 * nw + i;
@@ -746,31 +765,29 @@ __device__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// G-inner product Gram-Schmidt inside each cluster [cb[c], cb[c+1]) (workgroup
-// per cluster); X node-major [n][nw].
-#ifndef GS_BS
-#define GS_BS 1024   // one wide workgroup per cluster: the strided column walks are latency-bound
-#endif
-
-__global__ __launch_bounds__(GS_BS) void cluster_gs_kernel(Pencil P, const int* __restrict__ cb, int nw,
-                                                           double* __restrict__ X) {
-    __shared__ double sh[GS_BS];
+// Gram-Schmidt in the G inner product inside each cluster [cb[c], cb[c+1]) of
+// vector-major X (vector j at X + j n, contiguous; one workgroup per cluster):
+// every pass over a vector is one coalesced sweep.
+__global__ __launch_bounds__(256) void cluster_gs_vm_kernel(Pencil P, const int* __restrict__ cb,
+                                                            double* __restrict__ X) {
+    __shared__ double sh[256];
     const int n = P.n;
     const int c0 = cb[blockIdx.x], c1 = cb[blockIdx.x + 1];
     for (int j = c0; j < c1; ++j) {
+        double* xj = X + (int64_t)j * n;
         for (int i = c0; i <= j; ++i) {
+            const double* xi = X + (int64_t)i * n;
             double part = 0.0;
             for (int k = threadIdx.x; k < n; k += blockDim.x) {
                 const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
-                part += X[(int64_t)k * nw + i] * (P.gd[k] * X[(int64_t)k * nw + j] + P.go[km] * X[(int64_t)km * nw + j] +
-                                                  P.go[k] * X[(int64_t)kp * nw + j]);
+                part += xi[k] * (P.gd[k] * xj[k] + P.go[km] * xj[km] + P.go[k] * xj[kp]);
             }
             const double dot = block_sum(part, sh);
             if (i < j) {
-                for (int k = threadIdx.x; k < n; k += blockDim.x) X[(int64_t)k * nw + j] -= dot * X[(int64_t)k * nw + i];
+                for (int k = threadIdx.x; k < n; k += blockDim.x) xj[k] -= dot * xi[k];
             } else {
                 const double sc = 1.0 / sqrt(dot);
-                for (int k = threadIdx.x; k < n; k += blockDim.x) X[(int64_t)k * nw + j] *= sc;
+                for (int k = threadIdx.x; k < n; k += blockDim.x) xj[k] *= sc;
             }
             __syncthreads();
         }
@@ -1010,19 +1027,16 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // Tight brackets: the P1 pencil is the Rayleigh-Ritz discretisation of -d^2/ds^2
     // on the polygon of perimeter Ph, whose eigenvalues are (2 pi k/Ph)^2 (k = 0, 1, 1,
     // 2, 2, ...), so eigenvalue index idx lies above lam_c = (2 pi ceil(idx/2)/Ph)^2, and
-    // its relative excess is about lam h^2/12 (exactly to leading order on uniform
-    // meshes; h_max bounds the interpolation error otherwise, and the excess measured
-    // on star, ellipse and random curves stays below 0.074 lam^2 h_max^2); the upper
-    // end allows lam^2 h_max^2 / 6. The kernel checks each bracket with the inertia
-    // counts and falls back to the global one. The eigenvalues are wanted to 3e-10
-    // relative only (three rounds of 256 shifts from these brackets): each of the two
-    // inverse-iteration solves then damps the other eigen-components by ~3e-10 /
-    // (relative gap), and the reported eigenvalues are the Rayleigh quotients of the
-    // final vectors (Rayleigh-Ritz inside each cluster).
-    double Ph = 0.0, hmax = 0.0;
+    // its relative excess is about lam_c <h^2>/12 with <h^2> = sum h^3 / sum h (exactly
+    // to leading order on uniform meshes); the kernel brackets the eigenvalue by 0.2 and
+    // 1.6 times that excess (see bisect_scaled_kernel), checks each bracket with the
+    // inertia counts and falls back to the global one. The eigenvalues are wanted to
+    // 2e-8 relative only (below), and the reported eigenvalues are the Rayleigh
+    // quotients of the final vectors (Rayleigh-Ritz inside each cluster).
+    double Ph = 0.0, h3 = 0.0;
     for (double v : hh) {
         Ph += v;
-        hmax = std::max(hmax, v);
+        h3 += v * v * v;
     }
     const int K = n / 2;
     SturmStep* dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
@@ -1032,13 +1046,20 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     }
     FDS_HIP_TRY(hipGetLastError());
     const double l1c = (2.0 * kPiHost / Ph) * (2.0 * kPiHost / Ph);
+    // Precision of the shifts: inverse iteration needs them accurate against the gap
+    // between the kept and the excluded modes only (components of other kept modes
+    // stay inside the kept subspace). 2e-8 relative (two rounds of 256 shifts from the
+    // brackets) damps the excluded modes by 2e-8 / (relative gap at the cut) per
+    // solve, ~1e-6 for the usual gap between Fourier pairs; when the cut gap is below
+    // 2e-3 (a damping above 1e-5 per solve) the eigenvalues are bisected again to 6e-10.
+    double rtol = 2e-8;
     for (;;) {
         nw = std::min(n - start, want + extra);
         double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
         {
             KScope _ks(c, "filter_bisect");
             hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, l1c,
-                               hmax * hmax / 6.0, -1e-3 * lam_hi, lam_hi, 3e-10, 4e-16 * lam_hi, start, nw, dlam);
+                               h3 / (12.0 * Ph), -1e-3 * lam_hi, lam_hi, rtol, 4e-16 * lam_hi, start, nw, dlam);
         }
         FDS_HIP_TRY(hipGetLastError());
         lam.assign(nw, 0.0);
@@ -1052,6 +1073,11 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
             ++ne;
         }
         if (ne < nw || start + nw == n) {
+            if (ne < nw && rtol > 6e-10 &&
+                lam[ne] - lam[ne - 1] < 2e-3 * std::max(std::fabs(lam[ne]), std::fabs(lam[ne - 1]))) {
+                rtol = 6e-10;
+                continue;
+            }
             want = std::min(ne, nw);
             break;
         }
@@ -1087,9 +1113,9 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
                            fac, facM, IF);
     }
     FDS_HIP_TRY(hipGetLastError());
-    // inverse iteration from a pseudo-random right-hand side: two solves; the
-    // shifts are accurate to ~1e-13 relative, so each solve removes the other
-    // eigen-components to that level (Gram-Schmidt inside clusters after each)
+    // inverse iteration from a pseudo-random right-hand side: two solves, each
+    // damping the excluded modes by (shift error) / (gap at the cut); Gram-Schmidt
+    // inside clusters once the solves are done
     for (int it = 0; it < 2; ++it) {
         if (it > 0) {
             KScope _ks(c, "filter_invit_fwd");
@@ -1105,11 +1131,6 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
                                pivmin, Xn);
         }
         FDS_HIP_TRY(hipGetLastError());
-        {
-            KScope _ks(c, "filter_cluster_gs");
-            hipLaunchKernelGGL(cluster_gs_kernel, dim3(ncl), dim3(GS_BS), 0, c.stream, P, dcb, ne, Xn);
-        }
-        FDS_HIP_TRY(hipGetLastError());
     }
     // to vector-major (each eigenvector contiguous)
     double* X = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));
@@ -1117,6 +1138,14 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
         KScope _ks(c, "transpose");
         hipLaunchKernelGGL(transpose_kernel, dim3((ne + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, c.stream, Xn, n,
                            ne, X);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    // Gram-Schmidt in the G inner product inside each cluster (a degenerate pair's two
+    // vectors are independent combinations of its eigenvectors after the solves; the
+    // other components are already damped to rounding), with G-normalisation
+    {
+        KScope _ks(c, "filter_cluster_gs");
+        hipLaunchKernelGGL(cluster_gs_vm_kernel, dim3(ncl), dim3(256), 0, c.stream, P, dcb, X);
     }
     FDS_HIP_TRY(hipGetLastError());
     // Newton-Schulz in the G inner product: with M = V^T G V = I + E (|E| ~ 1e-12 after
