@@ -1,7 +1,8 @@
 // Sparse and small dense linear algebra on the device (the GEMMs are in gemm.hip):
 //   * the periodic tridiagonal Gram matrix G: factorisation (cyclic Thomas with
 //     a Sherman-Morrison correction), block solves G^{-1} X, block products G X;
-//   * Chebyshev-series application of G^{+-1/2} (Clenshaw recurrence);
+//   * Chebyshev-series application of G^{+-1/2} (Clenshaw recurrence, up to 32
+//     steps per launch);
 //   * the inverse of the small dense Woodbury core (blocked Gauss-Jordan with
 //     partial pivoting).
 #include <algorithm>
@@ -342,6 +343,87 @@ __global__ void clenshaw_kernel(const double* __restrict__ d, const double* __re
     out[o + i] = v;
 }
 
+// Several Clenshaw steps in one launch (temporal blocking). A workgroup owns
+// CB_ROWS consecutive rows of one vector plus a halo of `steps` rows on each
+// side (rows taken cyclically, so a short vector simply repeats in the halo),
+// holds b_{j+1}, b_{j+2} of those rows in LDS and runs `steps` steps; after step
+// s only rows [s, S - s) of the window are still exact, which after the last
+// step is the owned block plus one row on each side. It writes b_{jlo} and
+// b_{jlo+1} of its own rows to fresh buffers (the inputs are still read by the
+// neighbouring blocks' halos). The last step (j = 0, which reads X only in its
+// own row) is left to clenshaw_kernel so that the result may overwrite X.
+constexpr int CB_ROWS = 1024;
+constexpr int CB_STEPS = 32;
+constexpr int CB_THREADS = 256;
+constexpr int CB_SLOTS = (CB_ROWS + 2 * CB_STEPS + CB_THREADS - 1) / CB_THREADS;
+struct ChebBlock {
+    double a[CB_STEPS];   // a_j for j = jhi, jhi - 1, ..., jhi - steps + 1
+};
+template <typename T>
+__device__ __forceinline__ T cb_zero() {
+    if constexpr (std::is_same<T, double>::value) return 0.0;
+    else return make_double2(0.0, 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(CB_THREADS) void clenshaw_block_kernel(
+    const double* __restrict__ d, const double* __restrict__ e, int n, const T* __restrict__ X,
+    const T* __restrict__ b1in, const T* __restrict__ b2in, T* __restrict__ b1out, T* __restrict__ b2out,
+    int nchunk, ChebBlock cf, int steps, double s1, double s0) {
+    __shared__ T bufA[CB_ROWS + 2 * CB_STEPS];
+    __shared__ T bufB[CB_ROWS + 2 * CB_STEPS];
+    const int chunk = (int)(blockIdx.x % (unsigned)nchunk);
+    const int64_t col = blockIdx.x / (unsigned)nchunk;
+    const int r0 = chunk * CB_ROWS;
+    const int rows = min(CB_ROWS, n - r0);
+    const int S = rows + 2 * steps;
+    const int64_t o = col * (int64_t)n;
+    T xr[CB_SLOTS];
+    double dr[CB_SLOTS], em[CB_SLOTS], ep[CB_SLOTS];
+    T* bp = bufA;   // b_{j+1}
+    T* bq = bufB;   // b_{j+2}
+#pragma unroll
+    for (int u = 0; u < CB_SLOTS; ++u) {
+        const int t = threadIdx.x + u * CB_THREADS;
+        if (t < S) {
+            int r = (r0 - steps + t) % n;
+            r = r < 0 ? r + n : r;
+            const int rm = r == 0 ? n - 1 : r - 1;
+            xr[u] = X[o + r];
+            dr[u] = d[r];
+            em[u] = e[rm];
+            ep[u] = e[r];
+            bp[t] = b1in ? b1in[o + r] : cb_zero<T>();
+            bq[t] = b2in ? b2in[o + r] : cb_zero<T>();
+        }
+    }
+    __syncthreads();
+    for (int s = 1; s <= steps; ++s) {
+        const double aj = cf.a[s - 1];
+#pragma unroll
+        for (int u = 0; u < CB_SLOTS; ++u) {
+            const int t = threadIdx.x + u * CB_THREADS;
+            if (t >= s && t < S - s) {
+                const T gb = bp[t] * dr[u] + bp[t - 1] * em[u] + bp[t + 1] * ep[u];
+                bq[t] = xr[u] * aj + (gb * s1 + bp[t] * s0) * 2.0 - bq[t];
+            }
+        }
+        T* tmp = bp;
+        bp = bq;
+        bq = tmp;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < CB_SLOTS; ++u) {
+        const int t = threadIdx.x + u * CB_THREADS;
+        if (t >= steps && t < steps + rows) {
+            const int r = r0 + t - steps;
+            b1out[o + r] = bp[t];
+            b2out[o + r] = bq[t];
+        }
+    }
+}
+
 template <typename T>
 void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, double hi, int p,
                    T* X, int64_t ncols) {
@@ -349,29 +431,37 @@ void gram_pow_half(Ctx& c, const double* d, const double* e, int n, double lo, d
     const std::vector<double> a = cheb_coeffs(p, lo, hi);
     const int deg = (int)a.size() - 1;
     const size_t bytes = sizeof(T) * (size_t)n * ncols;
-    T* bufs[3];
-    for (int i = 0; i < 3; ++i) bufs[i] = static_cast<T*>(c.dmalloc(bytes));
     const double s1 = 2.0 / (hi - lo), s0 = -(hi + lo) / (hi - lo);
     const int64_t tot = (int64_t)n * ncols;
-    const unsigned nb = (unsigned)((tot + 255) / 256);
-    // rotate: cur = b_j, p1 = b_{j+1}, p2 = b_{j+2} (b_{deg+1} = b_{deg+2} = 0)
-    int cur = 0, p1 = 1, p2 = 2;
-    for (int j = deg; j >= 0; --j) {
-        const T* b1 = j < deg ? bufs[p1] : nullptr;
-        const T* b2 = j < deg - 1 ? bufs[p2] : nullptr;
-        T* out = j > 0 ? bufs[cur] : X;
-        {
-            KScope _ks(c, "gram_pow_half");
-            hipLaunchKernelGGL(clenshaw_kernel<T>, dim3(nb), dim3(256), 0, c.stream, d, e, n, X, b1, b2, out,
-                               ncols, a[j], s1, s0, j > 0 ? 2.0 : 1.0);
+    const int nchunk = (n + CB_ROWS - 1) / CB_ROWS;
+    FDS_REQUIRE((int64_t)nchunk * ncols < (int64_t)1 << 31, FDS_ERR_ARG, "too many vectors for one launch");
+    // b_{j+1}, b_{j+2} in (in1, in2); each block of steps writes (out1, out2)
+    T* bufs[4];
+    for (int i = 0; i < 4; ++i) bufs[i] = static_cast<T*>(c.dmalloc(bytes));
+    T *in1 = nullptr, *in2 = nullptr;
+    int fresh = 0;   // index of the first of the two free buffers
+    int j = deg;     // next step to run
+    {
+        KScope _ks(c, "gram_pow_half");
+        while (j >= 1) {
+            const int steps = std::min(CB_STEPS, j);
+            ChebBlock cf{};
+            for (int s = 0; s < steps; ++s) cf.a[s] = a[j - s];
+            T* o1 = bufs[fresh];
+            T* o2 = bufs[fresh + 1];
+            hipLaunchKernelGGL(clenshaw_block_kernel<T>, dim3((unsigned)(nchunk * ncols)), dim3(CB_THREADS), 0,
+                               c.stream, d, e, n, X, in1, in2, o1, o2, nchunk, cf, steps, s1, s0);
+            in1 = o1;
+            in2 = o2;
+            fresh = 2 - fresh;
+            j -= steps;
         }
-        FDS_HIP_TRY(hipGetLastError());
-        const int t = p2;
-        p2 = p1;
-        p1 = cur;
-        cur = t;
+        // j = 0: Y = a_0 X + That(b_1) - b_2, written over X
+        hipLaunchKernelGGL(clenshaw_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, d, e, n,
+                           X, in1, in2, X, ncols, a[0], s1, s0, 1.0);
     }
-    for (int i = 0; i < 3; ++i) c.dfree(bufs[i]);
+    FDS_HIP_TRY(hipGetLastError());
+    for (int i = 0; i < 4; ++i) c.dfree(bufs[i]);
 }
 template void gram_pow_half<double>(Ctx&, const double*, const double*, int, double, double, int, double*,
                                     int64_t);

@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "fds_internal.h"
+#include "linalg.h"
 #include "lowrank.h"
 
 namespace fds {
@@ -90,20 +91,30 @@ void sketch(Ctx& c, uint64_t seed, int64_t n, int ell, double2* Om) {
 }
 
 // ----------------------------------------------------------------- Householder QR
-// Launch j: workgroup b owns column c = j + b. For j > 0 it applies
-// H_{j-1}^H (a <- a - conj(tau) v (v^H a)) to its column over rows j-1..M-1;
-// the owner of column j then builds H_j from rows j..M-1. Every thread walks
-// the same rows in every loop, so it only re-reads what it wrote itself.
-__global__ __launch_bounds__(HH_BS) void hh_step_kernel(double2* __restrict__ A, int64_t lda, int M, int j,
+// Blocked Householder QR with the compact WY form (Schreiber & Van Loan 1989):
+// the reflectors H_j = I - tau_j v_j v_j^H of a panel of QR_NB columns are found
+// column by column (hh_step_kernel), their product is I - V T V^H with T upper
+// triangular, and the columns right of the panel are updated by
+// A2 <- (I - V T^H V^H) A2 in three matrix-core products. Q = H_0 H_1 ... [I; 0]
+// is formed panel by panel from the right, Q2 <- (I - V T V^H) Q2.
+constexpr int QR_NB = 32;
+
+// Launch j (panel starting at column j0): workgroup b owns column c = j + b.
+// For j > j0 it applies H_{j-1}^H (a <- a - conj(tau) v (v^H a)) to its column
+// over rows j-1..M-1; the owner of column j then builds H_j from rows j..M-1.
+// Every thread walks the same rows in every loop, so it only re-reads what it
+// wrote itself.
+__global__ __launch_bounds__(HH_BS) void hh_step_kernel(double2* __restrict__ A, int64_t lda, int M, int j, int j0,
                                                         double2* __restrict__ tau) {
     __shared__ double sh[4 * (HH_BS / 64)];
     __shared__ double2 alpha_sh;
     const int c = j + blockIdx.x;
     const int tid = threadIdx.x;
     double2* a = A + (int64_t)c * lda;
-    const int base = j > 0 ? j - 1 : 0;
+    const bool apply = j > j0;
+    const int base = apply ? j - 1 : j;
     double nrm2 = 0.0;
-    if (j > 0) {
+    if (apply) {
         const double2* v = A + (int64_t)(j - 1) * lda;
         const double2 tj = tau[j - 1];
         double s[2] = {0.0, 0.0};
@@ -128,9 +139,9 @@ __global__ __launch_bounds__(HH_BS) void hh_step_kernel(double2* __restrict__ A,
         }
     } else {
 #pragma unroll 4
-        for (int r = tid; r < M; r += HH_BS) {
+        for (int r = j + tid; r < M; r += HH_BS) {
             const double2 ar = a[r];
-            if (r == 0) alpha_sh = ar;
+            if (r == j) alpha_sh = ar;
             else nrm2 += ar.x * ar.x + ar.y * ar.y;
         }
     }
@@ -156,34 +167,42 @@ __global__ __launch_bounds__(HH_BS) void hh_step_kernel(double2* __restrict__ A,
     if (tid == 0) tau[j] = tj;
 }
 
-// Q <- H_j Q on columns j..m-1 (rows j..M-1), Q initially [I; 0].
-__global__ __launch_bounds__(HH_BS) void hh_formq_kernel(const double2* __restrict__ A, int64_t lda,
-                                                         const double2* __restrict__ tau, int M, int j,
-                                                         double2* __restrict__ Q, int64_t ldq) {
-    __shared__ double sh[4 * (HH_BS / 64)];
-    const double2 tj = tau[j];
-    if (tj.x == 0.0 && tj.y == 0.0) return;
-    const int c = j + blockIdx.x;
-    const int tid = threadIdx.x;
-    const double2* v = A + (int64_t)j * lda;
-    double2* q = Q + (int64_t)c * ldq;
-    double s[2] = {0.0, 0.0};
-#pragma unroll 4
-    for (int r = j + tid; r < M; r += HH_BS) {
-        const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
-        const double2 qr = q[r];
-        s[0] += vr.x * qr.x + vr.y * qr.y;
-        s[1] += vr.x * qr.y - vr.y * qr.x;
-    }
-    block_sum_k<2, HH_BS>(s, sh);
-    const double2 f = cmul(tj, make_double2(s[0], s[1]));
-#pragma unroll 4
-    for (int r = j + tid; r < M; r += HH_BS) {
-        const double2 vr = r == j ? make_double2(1.0, 0.0) : v[r];
-        q[r] = csub(q[r], cmul(vr, f));
-    }
+// The reflectors of columns k0..k0+kb-1 as an explicit (M - k0) x kb block:
+// unit diagonal, zeros above it.
+__global__ void hh_panel_v_kernel(const double2* __restrict__ A, int64_t lda, int M, int k0, int kb,
+                                  double2* __restrict__ V) {
+    const int Mv = M - k0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Mv * kb) return;
+    const int cc = (int)(t / Mv), r = (int)(t % Mv);
+    V[t] = r < cc ? make_double2(0.0, 0.0)
+                  : (r == cc ? make_double2(1.0, 0.0) : A[(int64_t)(k0 + cc) * lda + k0 + r]);
 }
 
+// T (kb x kb, column-major, upper triangular) with H_k0 ... H_{k0+kb-1} = I - V T V^H,
+// from tau and the Gram matrix VV = V^H V: T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] VV[0:i, i].
+__global__ __launch_bounds__(64) void hh_larft_kernel(const double2* __restrict__ tau, int kb,
+                                                      const double2* __restrict__ VV, double2* __restrict__ T) {
+    __shared__ double2 ts[QR_NB][QR_NB + 1];   // ts[row][col]
+    const int r = threadIdx.x;
+    for (int i = 0; i < kb; ++i) {
+        const double2 ti = tau[i];
+        double2 v = make_double2(0.0, 0.0);
+        if (r < i) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int l = r; l < i; ++l) s = cadd(s, cmul(ts[r][l], VV[(int64_t)i * kb + l]));
+            v = make_double2(-(ti.x * s.x - ti.y * s.y), -(ti.x * s.y + ti.y * s.x));
+        } else if (r == i) {
+            v = ti;
+        }
+        if (r < kb) ts[r][i] = v;
+        __syncthreads();
+    }
+    for (int t = r; t < kb * kb; t += 64) T[t] = ts[t % kb][t / kb];
+}
+
+// Q <- [I; 0] (M x m)
 __global__ void eye_kernel(double2* __restrict__ Q, int64_t ldq, int M, int m) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)M * m) return;
@@ -203,24 +222,75 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
 
 void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) {
     FDS_REQUIRE(m >= 1 && M >= m, FDS_ERR_ARG, "Householder QR needs rows >= columns >= 1");
-    {
-        KScope _ks(c, "qr_householder");
-        for (int j = 0; j < m; ++j) {
-            const unsigned g = j == 0 ? 1u : (unsigned)(m - j);
-            hipLaunchKernelGGL(hh_step_kernel, dim3(g), dim3(HH_BS), 0, c.stream, A, (int64_t)M, M, j, tau);
+    const int npan = (m + QR_NB - 1) / QR_NB;
+    const bool blocks = npan > 1 || Q;
+    // per panel k (columns k0 = k QR_NB ..): V_k ((M - k0) x kb at V + k0 M) and T_k
+    double2* V = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m)) : nullptr;
+    double2* T = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * QR_NB * (size_t)npan)) : nullptr;
+    double2* VV = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * QR_NB)) : nullptr;
+    double2* W = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * (size_t)m)) : nullptr;
+    double2* W2 = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * (size_t)m)) : nullptr;
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+    for (int k = 0; k < npan; ++k) {
+        const int k0 = k * QR_NB, kb = std::min(QR_NB, m - k0), Mv = M - k0, mt = m - k0 - kb;
+        {
+            KScope _ks(c, "qr_householder");
+            for (int j = k0; j < k0 + kb; ++j) {
+                const unsigned g = j == k0 ? 1u : (unsigned)(k0 + kb - j);
+                hipLaunchKernelGGL(hh_step_kernel, dim3(g), dim3(HH_BS), 0, c.stream, A, (int64_t)M, M, j, k0,
+                                   tau);
+            }
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        if (!blocks) break;
+        double2* Vk = V + (size_t)k0 * M;
+        double2* Tk = T + (size_t)k * QR_NB * QR_NB;
+        {
+            KScope _ks(c, "qr_householder");
+            hipLaunchKernelGGL(hh_panel_v_kernel, dim3(nblk((int64_t)Mv * kb, 256)), dim3(256), 0, c.stream, A,
+                               (int64_t)M, M, k0, kb, Vk);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        zgemm(c, OP_C, OP_N, kb, kb, Mv, one, Vk, Mv, Vk, Mv, zero, VV, kb);
+        {
+            KScope _ks(c, "qr_householder");
+            hipLaunchKernelGGL(hh_larft_kernel, dim3(1), dim3(64), 0, c.stream, tau + k0, kb, VV, Tk);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        if (mt > 0) {
+            // A2 <- A2 - V (T^H (V^H A2)), A2 = rows k0.., columns k0 + kb..
+            double2* A2 = A + (int64_t)(k0 + kb) * M + k0;
+            zgemm(c, OP_C, OP_N, kb, mt, Mv, one, Vk, Mv, A2, M, zero, W, kb);
+            zgemm(c, OP_C, OP_N, kb, mt, kb, one, Tk, kb, W, kb, zero, W2, kb);
+            zgemm(c, OP_N, OP_N, Mv, mt, kb, mone, Vk, Mv, W2, kb, one, A2, M);
         }
     }
-    FDS_HIP_TRY(hipGetLastError());
-    if (!Q) return;
-    {
-        KScope _ks(c, "qr_form_q");
-        hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)M * m, 256)), dim3(256), 0, c.stream, Q, (int64_t)M, M,
-                           m);
-        for (int j = m - 1; j >= 0; --j)
-            hipLaunchKernelGGL(hh_formq_kernel, dim3((unsigned)(m - j)), dim3(HH_BS), 0, c.stream, A, (int64_t)M,
-                               tau, M, j, Q, (int64_t)M);
+    if (Q) {
+        {
+            KScope _ks(c, "qr_form_q");
+            hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)M * m, 256)), dim3(256), 0, c.stream, Q, (int64_t)M,
+                               M, m);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        for (int k = npan - 1; k >= 0; --k) {
+            // Q2 <- Q2 - V (T (V^H Q2)), Q2 = rows k0.., columns k0.. (the columns
+            // left of k0 are still zero in those rows)
+            const int k0 = k * QR_NB, kb = std::min(QR_NB, m - k0), Mv = M - k0, mq = m - k0;
+            const double2* Vk = V + (size_t)k0 * M;
+            const double2* Tk = T + (size_t)k * QR_NB * QR_NB;
+            double2* Q2 = Q + (int64_t)k0 * M + k0;
+            zgemm(c, OP_C, OP_N, kb, mq, Mv, one, Vk, Mv, Q2, M, zero, W, kb);
+            zgemm(c, OP_N, OP_N, kb, mq, kb, one, Tk, kb, W, kb, zero, W2, kb);
+            zgemm(c, OP_N, OP_N, Mv, mq, kb, mone, Vk, Mv, W2, kb, one, Q2, M);
+        }
     }
-    FDS_HIP_TRY(hipGetLastError());
+    if (blocks) {
+        c.dfree(V);
+        c.dfree(T);
+        c.dfree(VV);
+        c.dfree(W);
+        c.dfree(W2);
+    }
 }
 
 void r_adjoint(Ctx& c, const double2* A, int M, int m, double2* X) {
