@@ -70,7 +70,12 @@ typedef enum fds_form {
                        with this form; not available in the batched calls.   */
 } fds_form;
 
-typedef enum fds_precision { FDS_FP64 = 0, FDS_FP32 = 1, FDS_BF16 = 2 } fds_precision;
+/* Arithmetic of the stored operators. There is no reduced-precision sketch:
+ * the randomised range finder works in the coordinates of the kept filter
+ * modes, where each sketch product is N x n_eff x l (a small fraction of the
+ * N^2 operator products), and its accuracy bounds the skeleton, whose errors
+ * only the full-cost refinement sweeps could remove. */
+typedef enum fds_precision { FDS_FP64 = 0, FDS_FP32 = 1 } fds_precision;
 
 typedef struct fds_asm_opts {
     int32_t nquad;       /* Gauss points per panel; only 8 is supported          */
@@ -260,6 +265,79 @@ fds_status fds_op_destroy(fds_op op);
  * each operator. out: host array of `count` handles; on error none is created. */
 fds_status fds_assemble_batch(fds_ctx ctx, int32_t count, const double* const* nodes, const int64_t* n,
                               const double* k, fds_op* out);
+
+/* ------------------------------------------------------------------ batches
+ * Many problems in one call (paper, Filters Based Fast Direct Solver: the
+ * factorisation is computed once per geometry and reused for every right-hand
+ * side; Inversion of the structured matrices). A batch assembles the operators
+ * of all curves by one persistent far-field launch, filters, compresses and
+ * factors each of them, and then records the plane-wave right-hand sides, the
+ * Woodbury solves and a fixed number of refinement sweeps of every problem in
+ * one HIP graph, which each fds_batch_replay launches at once. The set-up is
+ * not in the graph: the number of kept modes (cut guard) and the skeleton rank
+ * are decided from computed eigenvalues and singular values. */
+typedef struct fds_problem {
+    const double* nodes;   /* device [n][2], as for fds_assemble                 */
+    int64_t n;             /* panels, >= 8                                       */
+    double k;              /* wave number > 0                                    */
+    int32_t n_modes;       /* filtering point n in [1, n]                        */
+    int32_t nrhs;          /* plane waves, >= 1                                  */
+    const double* angles;  /* device [nrhs] directions (radians); read at every
+                              replay                                             */
+    const void* amps;      /* device [nrhs] complex128 amplitudes; read at every
+                              replay                                             */
+    void* j_out;           /* device [nrhs][n] complex128: the current
+                              coefficients j, written at every replay            */
+} fds_problem;
+
+typedef struct fds_batch_opts {
+    int32_t precision;     /* FDS_FP64 or FDS_FP32 (as fds_asm_opts.precision;
+                              default band width)                                */
+    int32_t form;          /* fds_form                                           */
+    double alpha;          /* CFIE coupling (FDS_CFIE, FDS_YCFIE)                */
+    int32_t rank_cap;      /* skeleton rank cap; 0: each problem's n_eff (exact
+                              skeleton)                                          */
+    int32_t oversample;    /* p (fds_compress_opts)                              */
+    int32_t power_iters;   /* q                                                  */
+    int32_t sweeps;        /* refinement sweeps after each Woodbury solve, against
+                              the filtered operator (fixed count, no residual
+                              test: nothing is read back by the host)            */
+    double tol;            /* compression tolerance eps                          */
+    uint64_t seed;         /* sketch seed                                        */
+    int32_t reserved[4];
+} fds_batch_opts;
+
+typedef struct fds_batch_s* fds_batch;
+
+/* Builds the batch: batched assembly (all far tiles of all problems in one
+ * persistent launch; FP32 operators add their FP64 band of N per problem),
+ * filter (FP64 EFIE/MFIE/CFIE: grouped products over all problems), skeleton
+ * compression and Woodbury factor per problem, one eager run of every solve,
+ * then the capture of those solves into one graph. Right-hand-side and
+ * solution buffers are the caller's (probs[i].angles, amps, j_out) and must
+ * stay valid until fds_batch_destroy; the library allocates the per-problem
+ * right-hand-side workspace (4 n nrhs complex128 per problem, 3 for the EFIE).
+ * The solves use the context's allocation-free scratch array (as
+ * fds_solve_system_noalloc), so a replay must not overlap another call on the
+ * same GPU that uses it. Errors: FDS_ERR_ARG for bad sizes or options
+ * (including a problem whose 16 (n + max(rank, n_eff)) bytes per right-hand
+ * side exceed 24 MiB), FDS_ERR_SINGULAR from a factor, FDS_ERR_HIP if the
+ * capture fails; on error nothing is created. Synchronises the stream. */
+fds_status fds_batch_create(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* opts,
+                            fds_batch* out);
+/* One launch of the recorded graph on the context's stream: the right-hand
+ * sides from the current angles and amplitudes, the Woodbury solve and the
+ * sweeps of every problem, j written to each j_out. Asynchronous. */
+fds_status fds_batch_replay(fds_batch b);
+/* Borrowed operator of problem i (for fds_op_info and the views); valid until
+ * fds_batch_destroy. */
+fds_status fds_batch_op(fds_batch b, int64_t i, fds_op* op);
+/* Waits for the context's stream, then frees the graph, the operators and the
+ * workspace. */
+fds_status fds_batch_destroy(fds_batch b);
+/* fds_batch_create, one fds_batch_replay, a stream synchronisation and
+ * fds_batch_destroy: the nb problems solved end to end in one call. */
+fds_status fds_batch_run(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* opts);
 
 /* Sizes: n, kept filter modes (0 before fds_filter), skeleton rank (0 before
  * fds_compress). Any output pointer may be NULL. Host call, no sync. */

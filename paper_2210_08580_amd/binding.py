@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fds.h")
 
 FDS_EFIE, FDS_MFIE, FDS_CFIE, FDS_YCFIE = 0, 1, 2, 3
 FORMS = {"efie": FDS_EFIE, "mfie": FDS_MFIE, "cfie": FDS_CFIE, "ycfie": FDS_YCFIE}
-FDS_FP64, FDS_FP32, FDS_BF16 = 0, 1, 2
+FDS_FP64, FDS_FP32 = 0, 1
 STATUS = {0: "FDS_OK", 1: "FDS_ERR_ARG", 2: "FDS_ERR_ALLOC", 3: "FDS_ERR_HIP",
           4: "FDS_ERR_STATE", 5: "FDS_ERR_SINGULAR", 6: "FDS_ERR_NOCONV", 7: "FDS_ERR_NOTIMPL"}
 
@@ -61,6 +61,17 @@ class fds_compress_opts(C.Structure):
 class fds_solve_opts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
                 ("unfiltered", C.c_int32), ("reserved", C.c_int32)]
+
+
+class fds_problem(C.Structure):
+    _fields_ = [("nodes", C.c_void_p), ("n", C.c_int64), ("k", C.c_double), ("n_modes", C.c_int32),
+                ("nrhs", C.c_int32), ("angles", C.c_void_p), ("amps", C.c_void_p), ("j_out", C.c_void_p)]
+
+
+class fds_batch_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("alpha", C.c_double), ("rank_cap", C.c_int32),
+                ("oversample", C.c_int32), ("power_iters", C.c_int32), ("sweeps", C.c_int32), ("tol", C.c_double),
+                ("seed", C.c_uint64), ("reserved", C.c_int32 * 4)]
 
 
 class fds_solve_stats(C.Structure):
@@ -134,6 +145,12 @@ _SIGS = {
     "fds_solve_system": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
     "fds_solve_system_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
+    "fds_batch_create": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(fds_problem), C.POINTER(fds_batch_opts),
+                                   C.POINTER(C.c_void_p)]),
+    "fds_batch_replay": (C.c_int, [C.c_void_p]),
+    "fds_batch_op": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]),
+    "fds_batch_destroy": (C.c_int, [C.c_void_p]),
+    "fds_batch_run": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(fds_problem), C.POINTER(fds_batch_opts)]),
     "fds_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                     C.POINTER(fds_solve_opts), C.POINTER(fds_solve_stats)]),
 }
@@ -144,8 +161,11 @@ _is_finalizing = sys.is_finalizing
 
 
 def _close_all():
-    # close operators before contexts, while torch is still alive
+    # close operators, then batches (which own operators), then contexts, while
+    # torch is still alive
     for o in [o for o in list(_live) if isinstance(o, Op)]:
+        o.close()
+    for o in [o for o in list(_live) if type(o).__name__ == "Batch"]:
         o.close()
     for o in list(_live):
         o.close()
@@ -623,6 +643,89 @@ def fds_solve_system_noalloc(op: Op, w: torch.Tensor, j_out: torch.Tensor, sweep
         raise ValueError("w and j_out must be complex128 tensors of the same shape")
     _check(lib().fds_solve_system_noalloc(op.handle, _ptr(w), w.shape[0], _ptr(j_out), int(sweeps)))
     return j_out
+
+
+# ----------------------------------------------------------------- batches
+class _BorrowedOp(Op):
+    """An operator owned by a batch (never destroyed through this handle)."""
+
+    def close(self):
+        self.handle = None
+
+
+def _batch_args(problems, precision, form, alpha, rank_cap, oversample, power_iters, sweeps, tol, seed):
+    keep = []
+    arr = (fds_problem * len(problems))()
+    for i, p in enumerate(problems):
+        nodes = p["nodes"].to(device="cuda", dtype=torch.float64).contiguous()
+        ang, amp, jo = p["angles"], p["amps"], p["j_out"]
+        if ang.dtype != torch.float64 or not ang.is_cuda or not ang.is_contiguous():
+            raise ValueError("angles must be contiguous float64 CUDA tensors")
+        if amp.dtype != torch.complex128 or not amp.is_cuda or not amp.is_contiguous() or amp.numel() != ang.numel():
+            raise ValueError("amps must be contiguous complex128 CUDA tensors, one per angle")
+        if jo.dtype != torch.complex128 or not jo.is_cuda or tuple(jo.shape) != (ang.numel(), nodes.shape[0]):
+            raise ValueError("j_out must be a complex128 CUDA tensor of shape (nrhs, n)")
+        keep += [nodes, ang, amp, jo]
+        arr[i] = fds_problem(_ptr(nodes), nodes.shape[0], float(p["k"]), int(p["n_modes"]), ang.numel(),
+                             _ptr(ang), _ptr(amp), _ptr(jo))
+    o = fds_batch_opts()
+    o.precision = {"fp64": FDS_FP64, "fp32": FDS_FP32}[precision]
+    o.form = FORMS[form]
+    o.alpha = float(alpha)
+    o.rank_cap, o.oversample, o.power_iters = int(rank_cap), int(oversample), int(power_iters)
+    o.sweeps, o.tol, o.seed = int(sweeps), float(tol), int(seed)
+    return arr, o, keep
+
+
+class Batch:
+    """fds_batch_create: operators of every problem built and factored, the solves
+    of all problems recorded in one graph. problems: list of dicts with nodes
+    (n, 2), k, n_modes and the caller-owned CUDA tensors angles (nrhs,) float64,
+    amps (nrhs,) complex128 and j_out (nrhs, n) complex128, which every replay()
+    reads (angles, amps) and writes (j_out)."""
+
+    def __init__(self, ctx: Ctx, problems, precision="fp64", form="cfie", alpha=1.0, rank_cap=0, oversample=10,
+                 power_iters=2, sweeps=0, tol=0.0, seed=1):
+        self.ctx = ctx
+        arr, o, self._keep = _batch_args(problems, precision, form, alpha, rank_cap, oversample, power_iters,
+                                         sweeps, tol, seed)
+        h = C.c_void_p()
+        _check(lib().fds_batch_create(ctx.handle, len(problems), arr, C.byref(o), C.byref(h)))
+        self.handle = h
+        self.outputs = [p["j_out"] for p in problems]
+        _live.add(self)
+
+    def replay(self):
+        _check(lib().fds_batch_replay(self.handle))
+        return self.outputs
+
+    def op(self, i: int) -> Op:
+        h = C.c_void_p()
+        _check(lib().fds_batch_op(self.handle, int(i), C.byref(h)))
+        return _BorrowedOp(self.ctx, h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fds_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if _is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fds_batch_run(ctx: Ctx, problems, precision="fp64", form="cfie", alpha=1.0, rank_cap=0, oversample=10,
+                  power_iters=2, sweeps=0, tol=0.0, seed=1):
+    """All problems solved end to end by one call (set-up, one graph launch); the
+    solutions are in each problem's j_out when it returns."""
+    arr, o, keep = _batch_args(problems, precision, form, alpha, rank_cap, oversample, power_iters, sweeps, tol,
+                               seed)
+    _check(lib().fds_batch_run(ctx.handle, len(problems), arr, C.byref(o)))
+    return [p["j_out"] for p in problems]
 
 
 # ----------------------------------------------------------------- inverse problem

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -801,6 +802,168 @@ fds_status fds_solve_system_noalloc(fds_op op, const void* w, int64_t nrhs, void
         FDS_REQUIRE(sweeps >= 0 && sweeps <= 1000, FDS_ERR_ARG, "sweeps out of range");
         if (nrhs == 0) return;
         run_solve_system_noalloc(op->impl, (const double2*)w, nrhs, (double2*)j_out, sweeps);
+    });
+}
+
+// ------------------------------------------------------------------ batches
+struct fds_batch_s {
+    Ctx* c = nullptr;
+    std::vector<fds_op_s*> ops;
+    std::vector<BatchItem> items;
+    std::vector<void*> bufs;
+    int sweeps = 0;
+    hipGraphExec_t exec = nullptr;
+    ~fds_batch_s() {
+        if (c) (void)hipStreamSynchronize(c->stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        for (void* b : bufs) c->dfree(b);
+        for (auto* o : ops) delete o;
+    }
+};
+
+// Records the solves of every problem into one graph on a private stream (the
+// context's stream may be the legacy default stream, which cannot be captured).
+static hipGraphExec_t capture_batch(fds_batch_s& b) {
+    Ctx& c = *b.c;
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    hipStream_t cs = nullptr;
+    FDS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const hipStream_t old = c.stream;
+    const bool prof = c.prof;
+    c.stream = cs;
+    c.prof = false;   // no timing events inside the graph
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    try {
+        FDS_HIP_TRY(err);
+        for (size_t i = 0; i < b.items.size(); ++i) run_batch_item(b.ops[i]->impl, b.items[i], b.sweeps);
+        FDS_HIP_TRY(hipStreamEndCapture(cs, &g));
+        FDS_HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    } catch (...) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(cs, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+            hipGraph_t bad = nullptr;
+            (void)hipStreamEndCapture(cs, &bad);
+            if (bad) (void)hipGraphDestroy(bad);
+        }
+        if (g) (void)hipGraphDestroy(g);
+        c.stream = old;
+        c.prof = prof;
+        (void)hipStreamDestroy(cs);
+        throw;
+    }
+    (void)hipGraphDestroy(g);
+    c.stream = old;
+    c.prof = prof;
+    FDS_HIP_TRY(hipStreamDestroy(cs));
+    return ge;
+}
+
+static fds_batch_s* make_batch(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* o) {
+    FDS_REQUIRE(ctx && probs && o && nb >= 1 && nb <= (1 << 16), FDS_ERR_ARG, "bad argument");
+    FDS_REQUIRE(o->precision == FDS_FP64 || o->precision == FDS_FP32, FDS_ERR_ARG, "precision must be FP64 or FP32");
+    const int form = o->form;
+    FDS_REQUIRE(form == FDS_EFIE || form == FDS_MFIE || form == FDS_CFIE || form == FDS_YCFIE, FDS_ERR_ARG,
+                "bad form");
+    FDS_REQUIRE(std::isfinite(o->alpha), FDS_ERR_ARG, "alpha must be finite");
+    if (form == FDS_CFIE || form == FDS_YCFIE)
+        FDS_REQUIRE(std::fabs(1.0 + 2.0 * o->alpha) > 1e-12, FDS_ERR_ARG, "CFIE with beta = 0");
+    FDS_REQUIRE(o->rank_cap >= 0 && o->oversample >= 0 && o->power_iters >= 0 && o->tol >= 0.0, FDS_ERR_ARG,
+                "bad compression options");
+    FDS_REQUIRE(o->sweeps >= 0 && o->sweeps <= 1000, FDS_ERR_ARG, "sweeps out of range");
+    for (int64_t i = 0; i < nb; ++i) {
+        const fds_problem& p = probs[i];
+        FDS_REQUIRE(p.nodes && p.angles && p.amps && p.j_out, FDS_ERR_ARG, "NULL pointer in a problem");
+        FDS_REQUIRE(p.n >= 8 && p.n <= (int64_t)1 << 20, FDS_ERR_ARG, "n must be in [8, 2^20]");
+        FDS_REQUIRE(p.n_modes >= 1 && p.n_modes <= p.n, FDS_ERR_ARG, "n_modes must be in [1, n]");
+        FDS_REQUIRE(p.nrhs >= 1, FDS_ERR_ARG, "nrhs must be >= 1");
+    }
+    Ctx& c = ctx->impl;
+    FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
+    auto* b = new fds_batch_s();
+    b->c = &c;
+    b->sweeps = o->sweeps;
+    try {
+        fds_asm_opts ao{};
+        ao.precision = o->precision;
+        for (int64_t i = 0; i < nb; ++i)
+            b->ops.push_back(new_operator(c, probs[i].nodes, probs[i].n, probs[i].k, &ao));
+        std::vector<Op*> ops;
+        for (auto* op : b->ops) ops.push_back(&op->impl);
+        launch_assemble_batch(c, ops.data(), (int)nb);
+        for (Op* op : ops) op->stage = Stage::Assembled;
+        std::vector<int> nm(nb);
+        for (int64_t i = 0; i < nb; ++i) nm[i] = probs[i].n_modes;
+        if (o->precision == FDS_FP64 && form != FDS_YCFIE) {
+            run_filter_batch(ops.data(), (int)nb, form, o->alpha, nm.data(), true, 1e-6);
+        } else {
+            for (int64_t i = 0; i < nb; ++i) run_filter(*ops[i], form, o->alpha, nm[i], true, 1e-6);
+        }
+        for (Op* op : ops) {
+            run_compress(*op, o->rank_cap > 0 ? o->rank_cap : op->n_eff, o->oversample, o->power_iters, o->tol,
+                         o->seed);
+            run_factor(*op);
+        }
+        for (int64_t i = 0; i < nb; ++i) {
+            const fds_problem& p = probs[i];
+            const size_t blk = sizeof(double2) * (size_t)p.n * (size_t)p.nrhs;
+            BatchItem it{};
+            it.angles = p.angles;
+            it.amps = static_cast<const double2*>(p.amps);
+            it.nrhs = p.nrhs;
+            it.j = static_cast<double2*>(p.j_out);
+            double2** slots[4] = {&it.f, &it.h, &it.w, &it.t};
+            for (int s = 0; s < 4; ++s) {
+                if (s == 1 && !(form == FDS_MFIE || form == FDS_CFIE || form == FDS_YCFIE)) continue;
+                *slots[s] = static_cast<double2*>(c.dmalloc(blk));
+                b->bufs.push_back(*slots[s]);
+            }
+            b->items.push_back(it);
+        }
+        // one eager run: builds whatever the solves create lazily and checks
+        // that every problem fits the scratch array before anything is recorded
+        for (int64_t i = 0; i < nb; ++i) run_batch_item(*ops[i], b->items[i], b->sweeps);
+        b->exec = capture_batch(*b);
+    } catch (...) {
+        delete b;
+        throw;
+    }
+    return b;
+}
+
+fds_status fds_batch_create(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* opts,
+                            fds_batch* out) {
+    return guarded([&] {
+        FDS_REQUIRE(out != nullptr, FDS_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        *out = make_batch(ctx, nb, probs, opts);
+    });
+}
+
+fds_status fds_batch_replay(fds_batch b) {
+    return guarded([&] {
+        FDS_REQUIRE(b && b->exec, FDS_ERR_ARG, "bad batch");
+        FDS_HIP_TRY(hipGraphLaunch(b->exec, b->c->stream));
+    });
+}
+
+fds_status fds_batch_op(fds_batch b, int64_t i, fds_op* op) {
+    return guarded([&] {
+        FDS_REQUIRE(b && op && i >= 0 && i < (int64_t)b->ops.size(), FDS_ERR_ARG, "bad argument");
+        *op = b->ops[i];
+    });
+}
+
+fds_status fds_batch_destroy(fds_batch b) {
+    return guarded([&] { delete b; });
+}
+
+fds_status fds_batch_run(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* opts) {
+    return guarded([&] {
+        std::unique_ptr<fds_batch_s> b(make_batch(ctx, nb, probs, opts));
+        FDS_HIP_TRY(hipGraphLaunch(b->exec, b->c->stream));
+        FDS_HIP_TRY(hipStreamSynchronize(b->c->stream));
     });
 }
 

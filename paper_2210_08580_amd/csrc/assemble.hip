@@ -393,13 +393,14 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 
 // items from a global counter until the queue (all tiles of all operators,
 // prefix[j] = first item of operator j) is exhausted; every wavefront exits
 // once the counter passes the total.
+template <bool F32, bool OUT32>
 __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarParams* __restrict__ jobs,
                                                                       const int64_t* __restrict__ prefix, int njobs,
                                                                       unsigned long long* __restrict__ counter,
-                                                                      const double* __restrict__ tabg, W8 wt,
+                                                                      const void* __restrict__ tabg, W8 wt,
                                                                       WLow wl) {
-    __shared__ FarShared<false> sh;
-    far_shared_setup<false>(sh, tabg, wt, wl);
+    __shared__ FarShared<F32> sh;
+    far_shared_setup<F32>(sh, tabg, wt, wl);
     const int64_t total = prefix[njobs];
     for (;;) {
         unsigned long long w = 0;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarP
             else hi = mid - 1;
         }
         const int j = __builtin_amdgcn_readfirstlane(lo);
-        far_work_item<false, false>(jobs[j], (int64_t)w - prefix[j], sh);
+        far_work_item<F32, OUT32>(jobs[j], (int64_t)w - prefix[j], sh);
     }
 }
 
@@ -848,8 +849,10 @@ void launch_assemble(Op& op) {
     launch_near_band(op, fp, wt);
 }
 
-// All far tiles of several FP64 operators in one persistent launch, then the
-// per-operator near-pair and band kernels. Geometry must already be built.
+// All far tiles of several operators of one precision in one persistent launch
+// (with complex64 operators: the FP32 pass), then the per-operator FP64 band of
+// N (complex64 operators) and the near-pair and band kernels. Geometry must
+// already be built.
 void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
     if (nops <= 0) return;
     std::vector<FarParams> jobs(nops);
@@ -857,8 +860,9 @@ void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
     W8 wt;
     WLow wlow;
     far_rules(*ops[0], wt, wlow);
+    const bool f32 = ops[0]->prec == FDS_FP32;
     for (int j = 0; j < nops; ++j) {
-        FDS_REQUIRE(ops[j]->prec == FDS_FP64, FDS_ERR_NOTIMPL, "batched assembly is FP64 only");
+        FDS_REQUIRE(ops[j]->prec == ops[0]->prec, FDS_ERR_ARG, "a batch holds operators of one precision");
         jobs[j] = far_params(*ops[j]);
         prefix[j + 1] = prefix[j] + jobs[j].nwork;
     }
@@ -877,11 +881,18 @@ void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
     {
         KScope _ks(c, "asm_far_batch");
         hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, c.stream, counter);
-        hipLaunchKernelGGL(asm_far_batch_kernel, dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs, dprefix, nops,
-                           counter, c.hk_tab, wt, wlow);
+        if (f32)
+            hipLaunchKernelGGL((asm_far_batch_kernel<true, true>), dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
+                               dprefix, nops, counter, jobs[0].tab, wt, wlow);
+        else
+            hipLaunchKernelGGL((asm_far_batch_kernel<false, false>), dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
+                               dprefix, nops, counter, jobs[0].tab, wt, wlow);
     }
     FDS_HIP_TRY(hipGetLastError());
-    for (int j = 0; j < nops; ++j) launch_near_band(*ops[j], jobs[j], wt);
+    for (int j = 0; j < nops; ++j) {
+        if (f32) launch_nband(*ops[j], wt, wlow);
+        launch_near_band(*ops[j], jobs[j], wt);
+    }
     c.dfree(dbuf);
 }
 

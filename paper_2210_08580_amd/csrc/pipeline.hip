@@ -895,4 +895,40 @@ void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j
     }
 }
 
+// The right-hand side w of the filter's form from f and h with caller-owned
+// workspace t (n x nrhs); f is overwritten. Makes no allocation (split-K partial
+// sums go to the context's workspace while one is set).
+static void rhs_system_ws(Op& op, double2* f, const double2* h, int64_t nrhs, double2* w, double2* t) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const int form = op.form;
+    if (has_efie(form)) {
+        gram_inv(op, f, nrhs, t);
+        {
+            SplitHint sh(c, RHS_SPLIT);
+            op_gemm(op, s_op(form), OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, f);
+        }
+        gram_inv(op, f, nrhs, w);
+    }
+    if (has_mfie(form)) {
+        gram_inv(op, h, nrhs, t);
+        if (form == FDS_MFIE) axpby(c, make_double2(-1.0, 0.0), t, kZero, w, (int64_t)n * nrhs);
+        else axpby(c, make_double2(-op.alpha, 0.0), t, kOne, w, (int64_t)n * nrhs);
+    }
+}
+
+// One problem of a batch: plane-wave right-hand sides, w, the Woodbury solve and
+// `sweeps` filtered refinement sweeps, with no allocation and no host read, so
+// that the launches can be recorded into a graph.
+void run_batch_item(Op& op, const BatchItem& it, int sweeps) {
+    Ctx& c = *op.ctx;
+    FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
+    {
+        NoAlloc na(c, c.scratch, kScratchBytes);
+        launch_rhs_planewave(op, it.angles, it.amps, it.nrhs, it.f, it.h);
+        rhs_system_ws(op, it.f, it.h, it.nrhs, it.w, it.t);
+    }
+    run_solve_system_noalloc(op, it.w, it.nrhs, it.j, sweeps);
+}
+
 }  // namespace fds
