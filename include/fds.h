@@ -316,13 +316,13 @@ typedef struct fds_batch_s* fds_batch;
  * then the capture of those solves into one graph. Right-hand-side and
  * solution buffers are the caller's (probs[i].angles, amps, j_out) and must
  * stay valid until fds_batch_destroy; the library allocates the per-problem
- * right-hand-side workspace (4 n nrhs complex128 per problem, 3 for the EFIE).
- * The solves use the context's allocation-free scratch array (as
- * fds_solve_system_noalloc), so a replay must not overlap another call on the
- * same GPU that uses it. Errors: FDS_ERR_ARG for bad sizes or options
- * (including a problem whose 16 (n + max(rank, n_eff)) bytes per right-hand
- * side exceed 24 MiB), FDS_ERR_SINGULAR from a factor, FDS_ERR_HIP if the
- * capture fails; on error nothing is created. Synchronises the stream. */
+ * right-hand-side workspace (4 n nrhs complex128 per problem, 3 for the EFIE)
+ * and the workspace of the graph's branches: the problems are spread over up
+ * to 8 independent branches (largest n^2 nrhs first, each to the least loaded
+ * branch), which the device may run side by side. Replays of one batch must
+ * not overlap each other. Errors: FDS_ERR_ARG for bad sizes or options,
+ * FDS_ERR_SINGULAR from a factor, FDS_ERR_HIP if the capture fails; on error
+ * nothing is created. Synchronises the stream. */
 fds_status fds_batch_create(fds_ctx ctx, int64_t nb, const fds_problem* probs, const fds_batch_opts* opts,
                             fds_batch* out);
 /* One launch of the recorded graph on the context's stream: the right-hand

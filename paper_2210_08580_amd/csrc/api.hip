@@ -810,6 +810,9 @@ struct fds_batch_s {
     Ctx* c = nullptr;
     std::vector<fds_op_s*> ops;
     std::vector<BatchItem> items;
+    std::vector<int> chain;          // chain (graph branch) of each problem
+    std::vector<void*> chain_ws;     // workspace of each chain
+    std::vector<size_t> chain_bytes;
     std::vector<void*> bufs;
     int sweeps = 0;
     hipGraphExec_t exec = nullptr;
@@ -821,42 +824,68 @@ struct fds_batch_s {
     }
 };
 
-// Records the solves of every problem into one graph on a private stream (the
-// context's stream may be the legacy default stream, which cannot be captured).
+constexpr int kBatchChains = 8;
+
+// Records the solves of every problem into one graph. The problems are split
+// into up to kBatchChains chains (longest first, each to the least loaded chain
+// by n^2 nrhs), each captured on its own stream forked from and joined back to
+// the origin stream, so that the graph's branches run side by side; each chain
+// has its own workspace. Private streams are used because the context's stream
+// may be the legacy default stream, which cannot be captured.
 static hipGraphExec_t capture_batch(fds_batch_s& b) {
     Ctx& c = *b.c;
+    const int nch = (int)b.chain_ws.size();
     FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    hipStream_t cs = nullptr;
-    FDS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    std::vector<hipStream_t> st(nch + 1, nullptr);
+    std::vector<hipEvent_t> ev(nch + 1, nullptr);
     const hipStream_t old = c.stream;
     const bool prof = c.prof;
-    c.stream = cs;
-    c.prof = false;   // no timing events inside the graph
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    bool capturing = false;
+    auto cleanup = [&]() {
+        c.stream = old;
+        c.prof = prof;
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto s : st)
+            if (s) (void)hipStreamDestroy(s);
+    };
     try {
-        FDS_HIP_TRY(err);
-        for (size_t i = 0; i < b.items.size(); ++i) run_batch_item(b.ops[i]->impl, b.items[i], b.sweeps);
-        FDS_HIP_TRY(hipStreamEndCapture(cs, &g));
+        for (int i = 0; i <= nch; ++i) {
+            FDS_HIP_TRY(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+            FDS_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+        }
+        c.prof = false;   // no timing events inside the graph
+        FDS_HIP_TRY(hipStreamBeginCapture(st[nch], hipStreamCaptureModeThreadLocal));
+        capturing = true;
+        FDS_HIP_TRY(hipEventRecord(ev[nch], st[nch]));
+        for (int i = 0; i < nch; ++i) FDS_HIP_TRY(hipStreamWaitEvent(st[i], ev[nch], 0));
+        for (size_t i = 0; i < b.items.size(); ++i) {
+            const int ch = b.chain[i];
+            c.stream = st[ch];
+            run_batch_item(b.ops[i]->impl, b.items[i], b.sweeps, b.chain_ws[ch], b.chain_bytes[ch]);
+        }
+        for (int i = 0; i < nch; ++i) {
+            FDS_HIP_TRY(hipEventRecord(ev[i], st[i]));
+            FDS_HIP_TRY(hipStreamWaitEvent(st[nch], ev[i], 0));
+        }
+        c.stream = old;
+        capturing = false;
+        FDS_HIP_TRY(hipStreamEndCapture(st[nch], &g));
         FDS_HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     } catch (...) {
-        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(cs, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+        if (capturing) {
             hipGraph_t bad = nullptr;
-            (void)hipStreamEndCapture(cs, &bad);
+            (void)hipStreamEndCapture(st[nch], &bad);
             if (bad) (void)hipGraphDestroy(bad);
         }
         if (g) (void)hipGraphDestroy(g);
-        c.stream = old;
-        c.prof = prof;
-        (void)hipStreamDestroy(cs);
+        cleanup();
         throw;
     }
     (void)hipGraphDestroy(g);
-    c.stream = old;
-    c.prof = prof;
-    FDS_HIP_TRY(hipStreamDestroy(cs));
+    cleanup();
     return ge;
 }
 
@@ -880,7 +909,6 @@ static fds_batch_s* make_batch(fds_ctx ctx, int64_t nb, const fds_problem* probs
         FDS_REQUIRE(p.nrhs >= 1, FDS_ERR_ARG, "nrhs must be >= 1");
     }
     Ctx& c = ctx->impl;
-    FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
     auto* b = new fds_batch_s();
     b->c = &c;
     b->sweeps = o->sweeps;
@@ -921,9 +949,35 @@ static fds_batch_s* make_batch(fds_ctx ctx, int64_t nb, const fds_problem* probs
             }
             b->items.push_back(it);
         }
+        // chains: longest problems first, each to the least loaded chain
+        const int nch = (int)std::min<int64_t>(nb, kBatchChains);
+        std::vector<int64_t> order(nb);
+        for (int64_t i = 0; i < nb; ++i) order[i] = i;
+        auto cost = [&](int64_t i) { return (double)probs[i].n * (double)probs[i].n * (double)probs[i].nrhs; };
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t z) { return cost(a) > cost(z); });
+        std::vector<double> load(nch, 0.0);
+        b->chain.assign(nb, 0);
+        b->chain_bytes.assign(nch, 0);
+        for (int64_t i : order) {
+            const int ch = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[ch] += cost(i);
+            b->chain[i] = ch;
+            // residual and small products (3/4 of the workspace), then room for the
+            // split-K partial sums of the right-hand-side product (4 n nrhs complex)
+            const Op& op = *ops[i];
+            const size_t zr = (size_t)std::max({op.rank, op.n_eff, 1});
+            const size_t need = (size_t)16 * probs[i].nrhs * ((size_t)op.n + zr) / 3 * 4 +
+                                (size_t)64 * op.n * probs[i].nrhs + ((size_t)4 << 20);
+            b->chain_bytes[ch] = std::max(b->chain_bytes[ch], (need + 255) / 256 * 256);
+        }
+        for (int ch = 0; ch < nch; ++ch) {
+            b->chain_ws.push_back(c.dmalloc(b->chain_bytes[ch]));
+            b->bufs.push_back(b->chain_ws.back());
+        }
         // one eager run: builds whatever the solves create lazily and checks
-        // that every problem fits the scratch array before anything is recorded
-        for (int64_t i = 0; i < nb; ++i) run_batch_item(*ops[i], b->items[i], b->sweeps);
+        // that nothing allocates before anything is recorded
+        for (int64_t i = 0; i < nb; ++i)
+            run_batch_item(*ops[i], b->items[i], b->sweeps, b->chain_ws[b->chain[i]], b->chain_bytes[b->chain[i]]);
         b->exec = capture_batch(*b);
     } catch (...) {
         delete b;

@@ -25,6 +25,8 @@ void run_solve_adjoint(Op& op, const double2* v, int64_t nrhs, double2* y_out, d
 // allocation-free Woodbury solve + filtered refinement sweeps (static scratch array)
 void init_noalloc_scratch(Ctx& c);
 void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps);
+void run_solve_system_ws(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps, void* ws,
+                         size_t ws_bytes);
 // one problem of a batch (capture-safe: no allocation, no host read)
 struct BatchItem {
     const double* angles;
@@ -32,7 +34,7 @@ struct BatchItem {
     int64_t nrhs;
     double2 *f, *h, *w, *t, *j;
 };
-void run_batch_item(Op& op, const BatchItem& it, int sweeps);
+void run_batch_item(Op& op, const BatchItem& it, int sweeps, void* ws, size_t ws_bytes);
 // adjoint.hip
 void run_farfield(Op& op, const double2* J, int64_t nrhs, const double* thetas, int nang, double2* out);
 void run_farfield_grad(Op& op, const double* angles, const double2* amps, int64_t nrhs, const double* thetas,

@@ -865,17 +865,26 @@ void init_noalloc_scratch(Ctx& c) {
 void run_solve_system_noalloc(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps) {
     Ctx& c = *op.ctx;
     FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
+    run_solve_system_ws(op, w, nrhs, j_out, sweeps, c.scratch, kScratchBytes);
+}
+
+// The same solve on a caller-given workspace: up to 3/4 of it holds the residual
+// and the small products of a block of right-hand sides, the rest the GEMMs'
+// split-K partial sums. Every device allocation in between raises an error.
+void run_solve_system_ws(Op& op, const double2* w, int64_t nrhs, double2* j_out, int sweeps, void* ws,
+                         size_t ws_bytes) {
+    Ctx& c = *op.ctx;
     const int n = (int)op.n, ne = op.n_eff;
     const int zr = std::max(op.rank, sweeps > 0 ? ne : 0);
     const size_t col = sizeof(double2) * ((size_t)n + (size_t)std::max(zr, 1));
-    const int64_t cb = std::min<int64_t>(nrhs, (int64_t)((kScratchBytes / 4 * 3) / col));
+    const int64_t cb = std::min<int64_t>(nrhs, (int64_t)((ws_bytes / 4 * 3) / col));
     FDS_REQUIRE(cb >= 1, FDS_ERR_ARG,
                 "system too large for the allocation-free solve: 16 (n + max(rank, n_eff)) bytes per right-hand "
-                "side must fit 24 MiB");
-    double2* res = static_cast<double2*>(c.scratch);
+                "side must fit 3/4 of the workspace");
+    double2* res = static_cast<double2*>(ws);
     double2* z = res + (size_t)n * cb;
     const size_t used = (sizeof(double2) * ((size_t)n + std::max(zr, 1)) * cb + 255) / 256 * 256;
-    NoAlloc na(c, static_cast<unsigned char*>(c.scratch) + used, kScratchBytes - used);
+    NoAlloc na(c, static_cast<unsigned char*>(ws) + used, ws_bytes - used);
     for (int64_t c0 = 0; c0 < nrhs; c0 += cb) {
         const int64_t nb = std::min(cb, nrhs - c0);
         const int64_t tot = (int64_t)n * nb;
@@ -920,15 +929,14 @@ static void rhs_system_ws(Op& op, double2* f, const double2* h, int64_t nrhs, do
 // One problem of a batch: plane-wave right-hand sides, w, the Woodbury solve and
 // `sweeps` filtered refinement sweeps, with no allocation and no host read, so
 // that the launches can be recorded into a graph.
-void run_batch_item(Op& op, const BatchItem& it, int sweeps) {
+void run_batch_item(Op& op, const BatchItem& it, int sweeps, void* ws, size_t ws_bytes) {
     Ctx& c = *op.ctx;
-    FDS_REQUIRE(c.scratch != nullptr, FDS_ERR_STATE, "scratch array not initialised");
     {
-        NoAlloc na(c, c.scratch, kScratchBytes);
+        NoAlloc na(c, ws, ws_bytes);
         launch_rhs_planewave(op, it.angles, it.amps, it.nrhs, it.f, it.h);
         rhs_system_ws(op, it.f, it.h, it.nrhs, it.w, it.t);
     }
-    run_solve_system_noalloc(op, it.w, it.nrhs, it.j, sweeps);
+    run_solve_system_ws(op, it.w, it.nrhs, it.j, sweeps, ws, ws_bytes);
 }
 
 }  // namespace fds
