@@ -17,8 +17,9 @@
 //     N^{pq}_ab = sum_{al,be} w_al w_be g(R) [s_a s_b - k^2 (e_p.e_q) psi_a(xi_al) psi_b(xi_be)],
 //     so only g(|x_al - y_be|) and e_p.e_q depend on the nodes; dg/dx = -c (x - y),
 //     c = (ik/4) H1(kR)/R.
-//   self and adjacent pairs: central differences of the same singular
-//     quadrature (step 1e-6 of the panel length), which is smooth in the nodes.
+//   self and adjacent pairs: fourth-order central differences of the same
+//     singular quadrature (steps 1e-3 and 2e-3 of the shorter panel), which is
+//     analytic in the nodes.
 // The S and N bands |i - j| <= 2 are symmetrised in the assembly, so M enters
 // there as (M_ij + M_ji)/2. Amplitudes: J is quadratic in A_r, F j_r = A_r a_r,
 //     dJ/dRe A_r + i dJ/dIm A_r = 2 sum_l e_lr conj(a_lr).
@@ -393,21 +394,28 @@ __global__ __launch_bounds__(64) void pair_grad_near_kernel(const double* __rest
     }
     const double2 Mw[2][2] = {{m_eff(M, n, p, q), m_eff(M, n, p, q1)}, {m_eff(M, n, p1, q), m_eff(M, n, p1, q1)}};
     const double hmin = fmin(hypot(P[1][0] - P[0][0], P[1][1] - P[0][1]), hypot(P[3][0] - P[2][0], P[3][1] - P[2][1]));
-    const double del = 1e-6 * hmin;
+    // Fourth-order central difference, f' = (8 (f(d) - f(-d)) - (f(2d) - f(-2d))) / (12 d),
+    // with d = 1e-3 of the shorter panel: the blocks are analytic in the node
+    // coordinates on the scale of the panel length h, so the truncation error is
+    // ~(d/h)^4 / 30 ~ 3e-14 and the rounding error ~1.5 u / (d/h) ~ 2e-13 of the
+    // block scale (a second-order difference at this accuracy would need d ~ 1e-6 h,
+    // where rounding alone reaches 1e-10).
+    const double del = 1e-3 * hmin;
+    const double offs[4] = {del, -del, 2.0 * del, -2.0 * del};
     // distinct nodes of the pair: perturbing one moves every slot that holds it
     for (int v = 0; v < 4; ++v) {
         bool dup = false;
         for (int u = 0; u < v; ++u) dup = dup || nid[u] == nid[v];
         if (dup) continue;
         for (int ax = 0; ax < 2; ++ax) {
-            double ph[2];
-            for (int sg = 0; sg < 2; ++sg) {
+            double ph[4];
+            for (int sg = 0; sg < 4; ++sg) {
                 double Q[4][2];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     Q[u][0] = P[u][0];
                     Q[u][1] = P[u][1];
-                    if (nid[u] == nid[v]) Q[u][ax] += sg == 0 ? del : -del;
+                    if (nid[u] == nid[v]) Q[u][ax] += offs[sg];
                 }
                 double2 Nb[2][2];
                 near_n_block(Q, s, k, tab, gl32, r, wt, Nb);
@@ -418,7 +426,8 @@ __global__ __launch_bounds__(64) void pair_grad_near_kernel(const double* __rest
                     for (int b = 0; b < 2; ++b) phi = cadd(phi, cmul(Mw[a][b], Nb[a][b]));
                 ph[sg] = phi.x;
             }
-            atomicAdd(grad + 2 * nid[v] + ax, -2.0 * (ph[0] - ph[1]) / (2.0 * del));
+            const double d1 = (8.0 * (ph[0] - ph[1]) - (ph[2] - ph[3])) / (12.0 * del);
+            atomicAdd(grad + 2 * nid[v] + ax, -2.0 * d1);
         }
     }
 }

@@ -88,7 +88,9 @@ def test_gradient_vs_oracle(ctx, n, nm):
     assert st["converged"], st
     assert abs(J - Jo) <= 1e-10 * Jo
     gn = gn.cpu().numpy()
-    assert np.abs(gn - go).max() <= 1e-7 * np.abs(go).max(), np.abs(gn - go).max() / np.abs(go).max()
+    err = np.abs(gn - go).max() / np.abs(go).max()
+    print(f"  node gradient vs oracle: {err:.2e} of its largest component (bound 1e-8)", flush=True)
+    assert err <= 1e-8, err
     assert np.abs(ga.cpu().numpy() - gao).max() <= 1e-9 * np.abs(gao).max()
     op.close()
 

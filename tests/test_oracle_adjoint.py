@@ -60,6 +60,34 @@ def test_adjoint_gradient_vs_objective_fd():
         assert abs(fd - np.sum(g * dirn)) <= 2e-6 * np.abs(g).sum()
 
 
+def _objective_derivative(nodes, k, angles, amps, thetas, T, dirn, h):
+    """d/dt J(nodes + t dirn) at t = 0 by Richardson extrapolation of central
+    differences of the objective itself (dense LU solves; no adjoint, no dN)."""
+    def J(t):
+        return adjoint.objective(nodes + t * dirn, k, angles, amps, thetas, T)
+    d1 = (J(h) - J(-h)) / (2 * h)
+    d2 = (J(2 * h) - J(-2 * h)) / (4 * h)
+    return (4 * d1 - d2) / 3
+
+
+def test_adjoint_gradient_to_1e10():
+    """The adjoint gradient with differentiated operators against the derivative
+    of the objective along smooth and random directions, both to fourth order:
+    agreement to 1e-10 of the directional derivative's scale."""
+    nodes, k, angles, amps, thetas, T = _problem(n=40)
+    _, g, _ = adjoint.gradient(nodes, k, angles, amps, thetas, T)
+    n = nodes.shape[0]
+    t = 2 * np.pi * np.arange(n) / n
+    rs = np.random.default_rng(13)
+    h = 1e-3 * np.mean(geometry.mesh(nodes).h)
+    dirs = [np.stack([np.cos(t), np.sin(t)], 1) * np.cos(3 * t)[:, None], rs.standard_normal(nodes.shape)]
+    for dirn in dirs:
+        fd = _objective_derivative(nodes, k, angles, amps, thetas, T, dirn, h)
+        an = float(np.sum(g * dirn))
+        scale = float(np.sum(np.abs(g * dirn)))
+        assert abs(fd - an) <= 1e-10 * scale, (fd, an, scale)
+
+
 def test_amplitude_gradient_closed_form_vs_fd():
     nodes, k, angles, amps, thetas, T = _problem(n=40)
     _, _, ga = adjoint.gradient(nodes, k, angles, amps, thetas, T, rel_step=1e-3)
