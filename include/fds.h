@@ -67,7 +67,8 @@ typedef enum fds_form {
                        imaginary wavenumber i k, kernel (1/2 pi) K0(k R);
                        beta = (1 + 2 alpha)/4. The Yukawa operator is assembled
                        (FP64) by the first fds_rhs_system or fds_filter call
-                       with this form; not available in the batched calls.   */
+                       with this form; not available in fds_filter_batch
+                       (fds_batch_create filters such batches per problem). */
 } fds_form;
 
 /* Arithmetic of the stored operators. There is no reduced-precision sketch:
