@@ -168,7 +168,9 @@ def run_variant(B, ctx, w, nodes, angles, amps, precision, steps, warmup, rhs_ea
     def step():
         # with rhs_early the right-hand side is formed right after the assembly, so
         # that its dense product runs on the device beside the filter's eigensolver
-        op = B.fds_assemble(ctx, nodes, w.k, precision=precision)
+        # filter_modes starts the filter's eigensolver inside fds_assemble, beside the
+        # dense assembly kernels
+        op = B.fds_assemble(ctx, nodes, w.k, precision=precision, filter_modes=w.n_modes)
         info["nbw"] = B.fds_op_nband(op)[1]
         f, h = B.fds_rhs_planewave(op, angles, amps)
         if rhs_early:

@@ -92,7 +92,14 @@ typedef struct fds_asm_opts {
                             N kept in complex128 (fds_op_nband); 0 = default
                             (63 up to 8192 panels, n/64 - 1 above); clipped to
                             (n-1)/2 */
-    int32_t reserved[5];
+    int32_t filter_modes; /* 0, or the filtering point n_modes of a coming
+                            fds_filter (null mode kept): the Laplacian
+                            eigensolver needs only the mesh, so its bisection
+                            is started here on the context's second stream and
+                            runs beside the dense assembly; fds_filter with
+                            that n_modes and keep_nullspace = 1 continues from
+                            it (any other filter call discards it) */
+    int32_t reserved[4];
 } fds_asm_opts;
 
 typedef struct fds_filter_opts {

@@ -46,7 +46,7 @@ class fds_allocator(C.Structure):
 
 class fds_asm_opts(C.Structure):
     _fields_ = [("nquad", C.c_int32), ("precision", C.c_int32), ("band_width", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("filter_modes", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class fds_filter_opts(C.Structure):
@@ -427,15 +427,18 @@ class Op:
 
 
 def fds_assemble(ctx: Ctx, nodes: torch.Tensor, k: float, opts: fds_asm_opts | None = None,
-                 precision: str | None = None, band_width: int = 0) -> Op:
+                 precision: str | None = None, band_width: int = 0, filter_modes: int = 0) -> Op:
     """precision: "fp64" (default) or "fp32" (complex64 operators, mixed precision);
-    band_width: FP32 only, half-width of the FP64 band of N (0: the library's default)."""
+    band_width: FP32 only, half-width of the FP64 band of N (0: the library's default);
+    filter_modes: the filtering point of a coming fds_filter (null mode kept), whose
+    eigensolver then starts here, beside the dense assembly (0: none)."""
     nodes = nodes.to(device="cuda", dtype=torch.float64).contiguous()
-    if precision is not None:
+    if precision is not None or filter_modes:
         opts = fds_asm_opts()
         opts.nquad = 8
-        opts.precision = {"fp64": FDS_FP64, "fp32": FDS_FP32}[precision]
+        opts.precision = {"fp64": FDS_FP64, "fp32": FDS_FP32}[precision or "fp64"]
         opts.band_width = int(band_width)
+        opts.filter_modes = int(filter_modes)
     h = C.c_void_p()
     _check(lib().fds_assemble(ctx.handle, _ptr(nodes), nodes.shape[0], float(k),
                               C.byref(opts) if opts is not None else None, C.byref(h)))

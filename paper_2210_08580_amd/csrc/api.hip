@@ -119,7 +119,8 @@ void Ctx::release_cache() {
 
 Op::~Op() {
     if (!ctx) return;
-    void* ptrs[] = {nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
+    if (pre_active && ctx->side) (void)hipStreamSynchronize(ctx->side);
+    void* ptrs[] = {pre_Lb, pre_Gb, pre_steps, pre_lam,nodes, h, nx, ny, gx, gy, g_diag, g_off, l_diag, l_off, S, Nm, D, S32, N32, D32, Nband,
                     Vn, Vg, Vgc, Bt, gfac, gband, K, Up, piv, lam_dev, Sy, gpow[0], gpow[1], Btr};
     for (void* p : ptrs) ctx->dfree(p);
     if (owns_uw) {
@@ -480,8 +481,11 @@ fds_status fds_assemble(fds_ctx ctx, const double* nodes, int64_t n, double k,
     return guarded([&] {
         FDS_REQUIRE(ctx && nodes && out, FDS_ERR_ARG, "NULL argument");
         *out = nullptr;
+        FDS_REQUIRE(!opts || (opts->filter_modes >= 0 && opts->filter_modes <= n), FDS_ERR_ARG,
+                    "filter_modes must be in [0, n]");
         fds_op_s* o = new_operator(ctx->impl, nodes, n, k, opts);
         try {
+            if (opts && opts->filter_modes > 0) prefetch_filter(o->impl, opts->filter_modes);
             launch_assemble(o->impl);
             o->impl.stage = Stage::Assembled;
         } catch (...) {

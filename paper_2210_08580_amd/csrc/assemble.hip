@@ -149,6 +149,24 @@ __device__ __forceinline__ void far_shared_setup(FarShared<F32>& sh, const void*
     __syncthreads();
 }
 
+// MG consecutive output entries (MG * sizeof(T) = 32 bytes, 32-byte aligned) as
+// 16-byte stores issued together.
+template <typename T, int MG>
+__device__ __forceinline__ void store_group(T* __restrict__ p, const T (&v)[MG]) {
+    if constexpr (sizeof(T) == 8) {
+        float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+        for (int u = 0; u < MG / 2; ++u) {
+            const float2 a = *reinterpret_cast<const float2*>(&v[2 * u]);
+            const float2 b = *reinterpret_cast<const float2*>(&v[2 * u + 1]);
+            q[u] = make_float4(a.x, a.y, b.x, b.y);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < MG; ++u) p[u] = v[u];
+    }
+}
+
 // One work item (nsub-th of a 63 x 63 tile) of one operator, executed by one
 // wavefront. F32: kernel values and sums in FP32; OUT32: complex64 outputs.
 template <bool F32, bool OUT32>
@@ -193,6 +211,15 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
 
     const CT z = CT{0, 0};
     CT pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z, pH0 = z, pH1 = z;
+    // The mirror entries (column col, rows i) of MG consecutive rows are kept and
+    // written together: MG * sizeof(OT) = 32 bytes per lane, one whole memory
+    // sector, instead of MG partial writes to it spread over the row loop (the
+    // write traffic of single 8- or 16-byte column-strided stores was 2.7x and 1.8x
+    // the stored bytes). Groups that straddle the work item's rows are written entry
+    // by entry.
+    constexpr int MG = OUT32 ? 4 : 2;
+    OT mS[MG], mN[MG], mT[MG];
+    const bool mgroup = mirror && (n % MG) == 0;
 
     for (int pr = i0 - 1; pr < i1; ++pr) {
         const int p = pr < 0 ? pr + n : pr;
@@ -367,10 +394,28 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
                 oN[rc] = wN;
                 oD[rc] = wD;
                 if (mirror) {
-                    const int64_t cr = (int64_t)col * n + i;
-                    oS[cr] = wS;
-                    oN[cr] = wN;
-                    oD[cr] = wT;
+                    const int g = i - i % MG;   // i >= 0: the group's first row
+                    if (mgroup && g >= i0 && g + MG <= i1) {
+                        const int r = i - g;   // uniform over the wave: registers by constant index
+#pragma unroll
+                        for (int u = 0; u < MG; ++u)
+                            if (u == r) {
+                                mS[u] = wS;
+                                mN[u] = wN;
+                                mT[u] = wT;
+                            }
+                        if (r == MG - 1) {
+                            const int64_t cr = (int64_t)col * n + g;
+                            store_group<OT, MG>(oS + cr, mS);
+                            store_group<OT, MG>(oN + cr, mN);
+                            store_group<OT, MG>(oD + cr, mT);
+                        }
+                    } else {
+                        const int64_t cr = (int64_t)col * n + i;
+                        oS[cr] = wS;
+                        oN[cr] = wN;
+                        oD[cr] = wT;
+                    }
                 }
             }
         }

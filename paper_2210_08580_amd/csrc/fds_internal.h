@@ -125,10 +125,13 @@ struct KScope {
 // main stream is ordered after everything the enclosed work launched. Every
 // launch, copy, allocation and timing made through the context in between goes
 // to the side stream, so the main stream's queued kernels keep running beside it.
+// With join = false the main stream is not ordered after the enclosed work
+// (a later SideStream scope, or an explicit wait, must do it).
 struct SideStream {
     Ctx& c;
     hipStream_t main;
-    SideStream(Ctx& ctx, hipEvent_t after) : c(ctx), main(ctx.stream) {
+    bool join;
+    SideStream(Ctx& ctx, hipEvent_t after, bool join_on_exit = true) : c(ctx), main(ctx.stream), join(join_on_exit) {
         if (!c.side && hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) {
             c.side = nullptr;
             throw Error{FDS_ERR_HIP, "hipStreamCreateWithFlags failed"};
@@ -139,6 +142,7 @@ struct SideStream {
     }
     ~SideStream() {
         c.stream = main;
+        if (!join) return;
         hipEvent_t e = nullptr;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess && hipEventRecord(e, c.side) == hipSuccess &&
             hipStreamWaitEvent(main, e, 0) == hipSuccess) {
@@ -237,6 +241,15 @@ struct Op {
     double alpha = 1.0;
     double beta = 0.25;
     int32_t n_eff = 0;
+    // Laplacian eigensolver started by fds_assemble (filtering-point hint) on the
+    // side stream: the folded bands, the Sturm steps and the first bisection launch
+    // for eigenvalues pre_start .. pre_start + pre_nw - 1, picked up by the filter
+    bool pre_active = false;
+    int pre_modes = 0, pre_nw = 0, pre_extra = 0;
+    double* pre_Lb = nullptr;
+    double* pre_Gb = nullptr;
+    void* pre_steps = nullptr;
+    double* pre_lam = nullptr;
     std::vector<double> filt_lam; // pencil eigenvalues of the last filter call (host)
     double* lam_dev = nullptr;    // Rayleigh-Ritz values of the kept modes, copied into filt_lam
     int32_t lam_dev_n = 0;        //   on first read (0: filt_lam is current)

@@ -207,14 +207,15 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
         __syncthreads();
         if (k0 + (int)threadIdx.x < kend) sh[threadIdx.x] = st[k0 + threadIdx.x];
         __syncthreads();
-        // the next step's coefficients are read from LDS one step ahead, so that their
-        // latency overlaps the current step; B and s are rescaled every fourth step (one
-        // step changes their magnitude by well under 1e40, far inside the exponent range)
-        SturmStep t = sh[0];
-        for (int k = k0; k < kend; ++k) {
-            const SturmStep tn = sh[min(k + 1, kend - 1) - k0];
+        // Two steps per iteration with two coefficient sets: the set of step k + 1 is
+        // read from LDS while step k runs and that of k + 2 while k + 1 runs, so the
+        // loads overlap the arithmetic and no register copies are needed. B and s are
+        // rescaled every fourth step (one step changes their magnitude by well under
+        // 1e40, far inside the exponent range). An exactly singular leading block
+        // (det = 0) counts as a tiny positive determinant.
+        auto step = [&](const SturmStep& t, int k) {
             double det = fma(b11, b22, -b12 * b12);
-            if (det == 0.0) det = 1e-300 * (fabs(b11 * b22) + b12 * b12 + 1e-300);
+            det = det == 0.0 ? 1e-300 : det;
             cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
             const double e1 = fma(-sig, t.go1, t.lo1), e2 = fma(-sig, t.go2, t.lo2);
             const double m1 = fma(-sig, t.gd1, t.ld1), m2 = fma(-sig, t.gd2, t.ld2);
@@ -235,11 +236,19 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
                 b12 = n12;
                 sc = det;
             }
-            t = tn;
+        };
+        SturmStep ta = sh[0];
+        int k = k0;
+        for (; k + 1 < kend; k += 2) {
+            const SturmStep tb = sh[k + 1 - k0];
+            step(ta, k);
+            ta = sh[min(k + 2, kend - 1) - k0];
+            step(tb, k + 1);
         }
+        if (k < kend) step(ta, k);
     }
     double det = fma(b11, b22, -b12 * b12);
-    if (det == 0.0) det = 1e-300 * (fabs(b11 * b22) + b12 * b12 + 1e-300);
+    det = det == 0.0 ? 1e-300 : det;
     cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
     if (odd) {
         // middle node: val = m - (u1^2 c - 2 u1 u2 b + u2^2 a)/det(A), with A = B/sc
@@ -981,49 +990,38 @@ static void dft_filter_basis(Op& op, int n_modes, bool keep_null, double cluster
     op.n_eff = ne;
 }
 
-void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
-    if (op.homog) {
-        gram_gershgorin(op.h_host, op.cheb_lo, op.cheb_hi);
-        dft_filter_basis(op, n_modes, keep_null, cluster_rtol);
-        return;
-    }
+// Host quantities of the eigensolver for one mesh and filtering point: the
+// pencil's spectrum bounds (Gershgorin on the host panel lengths,
+// 0 <= lambda <= max_i (|l_ii| + |l_i,i-1| + |l_i,i+1|) / lambda_min(G)), the
+// index range of the wanted eigenvalues and the tight-bracket coefficients.
+struct EigSetup {
+    double gmin, gmax, lam_hi, mnorm, l1c, hfac;
+    int start, want, extra;
+};
+
+static EigSetup eig_setup(Op& op, int n_modes, bool keep_null) {
     Ctx& c = *op.ctx;
     const int n = (int)op.n;
-    // bounds of the pencil's spectrum (Gershgorin on the host panel lengths):
-    // 0 <= lambda <= max_i (|l_ii| + |l_i,i-1| + |l_i,i+1|) / lambda_min(G)
     const std::vector<double>& hh = op.h_host;
-    double gmin = 0.0, gmax = 0.0, lmax = 0.0;
-    gram_gershgorin(hh, gmin, gmax);
+    EigSetup e{};
+    double lmax = 0.0;
+    gram_gershgorin(hh, e.gmin, e.gmax);
     for (int i = 0; i < n; ++i) {
         const double hm = hh[i == 0 ? n - 1 : i - 1], hp = hh[i];
         lmax = std::max(lmax, 2.0 / hm + 2.0 / hp);
     }
-    op.cheb_lo = gmin;
-    op.cheb_hi = gmax;
-    const double lam_hi = 1.01 * lmax / gmin;
-    const double mnorm = lmax + lam_hi * gmax;
-
-    Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, n};
-    double* Lb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
-    double* Gb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
-    {
-        KScope _ks(c, "filter_fold");
-        hipLaunchKernelGGL(fold_bands_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, P, Lb, Gb);
-    }
-    FDS_HIP_TRY(hipGetLastError());
-    const int start = keep_null ? 0 : 1;
-    int want = keep_null ? n_modes : n_modes - 1;
-    FDS_REQUIRE(want >= 1 && start + want <= n, FDS_ERR_ARG, "n_modes out of range");
-    // eigenvalues start .. start+nw-1 (a few beyond the cut for the cluster guard)
-    std::vector<double> lam;
-    int nw = 0;
+    e.lam_hi = 1.01 * lmax / e.gmin;
+    e.mnorm = lmax + e.lam_hi * e.gmax;
+    e.start = keep_null ? 0 : 1;
+    e.want = keep_null ? n_modes : n_modes - 1;
+    FDS_REQUIRE(e.want >= 1 && e.start + e.want <= n, FDS_ERR_ARG, "n_modes out of range");
     // One workgroup per eigenvalue, each alone on a compute unit for the whole
     // latency-bound recurrence: two eigenvalues past the cut guard it against a
     // split cluster, one when the second would put a workgroup past a multiple
     // of the CU count (a wider cluster at the cut is found and bisected again).
     int ncu = 0;
     FDS_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
-    int extra = (ncu > 0 && (want + 2) % ncu == 1) ? 1 : 2;
+    e.extra = (ncu > 0 && (e.want + 2) % ncu == 1) ? 1 : 2;
     // Tight brackets: the P1 pencil is the Rayleigh-Ritz discretisation of -d^2/ds^2
     // on the polygon of perimeter Ph, whose eigenvalues are (2 pi k/Ph)^2 (k = 0, 1, 1,
     // 2, 2, ...), so eigenvalue index idx lies above lam_c = (2 pi ceil(idx/2)/Ph)^2, and
@@ -1038,14 +1036,113 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
         Ph += v;
         h3 += v * v * v;
     }
+    e.l1c = (2.0 * kPiHost / Ph) * (2.0 * kPiHost / Ph);
+    e.hfac = h3 / (12.0 * Ph);
+    return e;
+}
+
+// The folded bands and the Sturm-step table of the pencil (device buffers).
+static void eig_tables(Op& op, double*& Lb, double*& Gb, SturmStep*& dst) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, n};
+    Lb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
+    Gb = static_cast<double*>(c.dmalloc(sizeof(double) * 5 * (size_t)n));
+    {
+        KScope _ks(c, "filter_fold");
+        hipLaunchKernelGGL(fold_bands_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, P, Lb, Gb);
+    }
+    FDS_HIP_TRY(hipGetLastError());
     const int K = n / 2;
-    SturmStep* dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
+    dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
     {
         KScope _ks(c, "filter_bisect");
         hipLaunchKernelGGL(sturm_steps_kernel, dim3((K + 255) / 256), dim3(256), 0, c.stream, P, dst);
     }
     FDS_HIP_TRY(hipGetLastError());
-    const double l1c = (2.0 * kPiHost / Ph) * (2.0 * kPiHost / Ph);
+}
+
+static void launch_bisect(Op& op, const EigSetup& e, const SturmStep* dst, int nw, double rtol, double* dlam) {
+    Ctx& c = *op.ctx;
+    Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, (int)op.n};
+    {
+        KScope _ks(c, "filter_bisect");
+        hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, e.l1c, e.hfac,
+                           -1e-3 * e.lam_hi, e.lam_hi, rtol, 4e-16 * e.lam_hi, e.start, nw, dlam);
+    }
+    FDS_HIP_TRY(hipGetLastError());
+}
+
+// Starts the eigensolver of filtering point n_modes (null mode kept) on the
+// current stream: tables and the first bisection, results left on the device
+// for compute_filter_basis.
+void prefetch_filter_eigs(Op& op, int n_modes) {
+    Ctx& c = *op.ctx;
+    const int n = (int)op.n;
+    const EigSetup e = eig_setup(op, n_modes, true);
+    double *Lb = nullptr, *Gb = nullptr;
+    SturmStep* dst = nullptr;
+    eig_tables(op, Lb, Gb, dst);
+    const int nw = std::min(n - e.start, e.want + e.extra);
+    double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
+    launch_bisect(op, e, dst, nw, 2e-8, dlam);
+    op.pre_active = true;
+    op.pre_modes = n_modes;
+    op.pre_nw = nw;
+    op.pre_extra = e.extra;
+    op.pre_Lb = Lb;
+    op.pre_Gb = Gb;
+    op.pre_steps = dst;
+    op.pre_lam = dlam;
+}
+
+void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol) {
+    Ctx& c = *op.ctx;
+    // a started eigensolver is used when it matches, otherwise released
+    const bool pre = op.pre_active && op.pre_modes == n_modes && keep_null;
+    double* pLam = nullptr;
+    if (op.pre_active) {
+        op.pre_active = false;
+        if (!pre) {
+            c.dfree(op.pre_Lb);
+            c.dfree(op.pre_Gb);
+            c.dfree(op.pre_steps);
+            c.dfree(op.pre_lam);
+            op.pre_Lb = op.pre_Gb = nullptr;
+            op.pre_steps = nullptr;
+            op.pre_lam = nullptr;
+        }
+    }
+    if (op.homog) {
+        gram_gershgorin(op.h_host, op.cheb_lo, op.cheb_hi);
+        dft_filter_basis(op, n_modes, keep_null, cluster_rtol);
+        return;
+    }
+    const int n = (int)op.n;
+    const EigSetup e = eig_setup(op, n_modes, keep_null);
+    op.cheb_lo = e.gmin;
+    op.cheb_hi = e.gmax;
+    const double mnorm = e.mnorm;
+    Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, n};
+    double *Lb = nullptr, *Gb = nullptr;
+    SturmStep* dst = nullptr;
+    if (pre) {
+        Lb = op.pre_Lb;
+        Gb = op.pre_Gb;
+        dst = static_cast<SturmStep*>(op.pre_steps);
+        pLam = op.pre_lam;
+        op.pre_Lb = op.pre_Gb = nullptr;
+        op.pre_steps = nullptr;
+        op.pre_lam = nullptr;
+    } else {
+        eig_tables(op, Lb, Gb, dst);
+    }
+    const int start = e.start;
+    int want = e.want;
+    int extra = e.extra;
+    // eigenvalues start .. start+nw-1 (a few beyond the cut for the cluster guard)
+    std::vector<double> lam;
+    int nw = 0;
     // Precision of the shifts: inverse iteration needs them accurate against the gap
     // between the kept and the excluded modes only (components of other kept modes
     // stay inside the kept subspace). 2e-8 relative (two rounds of 256 shifts from the
@@ -1055,13 +1152,14 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     double rtol = 2e-8;
     for (;;) {
         nw = std::min(n - start, want + extra);
-        double* dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
-        {
-            KScope _ks(c, "filter_bisect");
-            hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, l1c,
-                               h3 / (12.0 * Ph), -1e-3 * lam_hi, lam_hi, rtol, 4e-16 * lam_hi, start, nw, dlam);
+        double* dlam = nullptr;
+        if (pLam) {   // the first launch was made by prefetch_filter_eigs with these parameters
+            dlam = pLam;
+            pLam = nullptr;
+        } else {
+            dlam = static_cast<double*>(c.dmalloc(sizeof(double) * nw));
+            launch_bisect(op, e, dst, nw, rtol, dlam);
         }
-        FDS_HIP_TRY(hipGetLastError());
         lam.assign(nw, 0.0);
         FDS_HIP_TRY(hipMemcpyAsync(lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost, c.stream));
         FDS_HIP_TRY(hipStreamSynchronize(c.stream));

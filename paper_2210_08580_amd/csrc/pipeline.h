@@ -8,6 +8,7 @@ void ensure_gram_factor(Op& op);
 void apply_gram_power(Op& op, int p, double2* X, int64_t ncols);
 const double* filter_basis_view(Op& op);
 void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol);
+void prefetch_filter(Op& op, int n_modes);
 void run_filter_batch(Op* const* ops, int count, int form, double alpha, const int* n_modes, bool keep_null,
                       double cluster_rtol);
 void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed);

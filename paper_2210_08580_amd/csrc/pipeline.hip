@@ -33,6 +33,7 @@ static const double2 kOne = {1.0, 0.0};
 static const double2 kZero = {0.0, 0.0};
 
 void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rtol);
+void prefetch_filter_eigs(Op& op, int n_modes);
 
 // Y = alpha op(M) X + beta Y for the column-major view M of a stored operator
 // (which: 0 = S, 1 = N, 2 = D; the row-major n x n matrix read column-major is
@@ -262,6 +263,23 @@ const double* filter_basis_view(Op& op) {
         }
     }
     return op.Vn;
+}
+
+// The first bisection of the Laplacian eigensolver (filtering point n_modes, null
+// mode kept), enqueued on the side stream after the mesh event: it overlaps the
+// dense assembly that the caller enqueues next on the main stream. The main
+// stream is joined to it by the filter's own side-stream scope.
+void prefetch_filter(Op& op, int n_modes) {
+    if (op.homog) return;   // the DFT basis of a homogeneous mesh needs no eigensolver
+    Ctx& c = *op.ctx;
+    if (!op.ev_mesh) FDS_HIP_TRY(hipEventCreateWithFlags(&op.ev_mesh, hipEventDisableTiming));
+    if (!op.ev_mesh_fresh) {
+        FDS_HIP_TRY(hipEventRecord(op.ev_mesh, c.stream));
+        op.ev_mesh_fresh = true;
+    }
+    SideStream side(c, op.ev_mesh, false);
+    ensure_gram_factor(op);
+    prefetch_filter_eigs(op, n_modes);
 }
 
 static void filter_prepare(Op& op, int form, double alpha, int n_modes, bool keep_null, double cluster_rtol) {
