@@ -180,8 +180,8 @@ fds_status fds_autotune_read(fds_ctx ctx, int32_t cap, char* keys, int32_t* spli
 /* ------------------------------------------------------- special functions */
 
 /* Bessel functions of the Hankel kernel (paper, Notation and Background:
- * g2 = (i/4) H0^(1)(k|r - r'|)). x: device [n] doubles, x > 0.
- * out: device [n][4] doubles = J0, Y0, J1, Y1 at each x. */
+ * g2 = (i/4) H0^(1)(k|r - r'|)), by the FP64 evaluator of the far-pair assembly.
+ * x: device [n] doubles, x > 0. out: device [n][4] doubles = J0, Y0, J1, Y1 at each x. */
 fds_status fds_hankel_eval(fds_ctx ctx, const double* x, int64_t n, double* out);
 
 /* Single-precision evaluation used by the FP32 far-field assembly (scaled

@@ -195,8 +195,11 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             x.hk_tab = (double*)x.dmalloc(sizeof(double) * HK_TAB_DOUBLES);
             FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab, &HK_TAB[0][0][0], sizeof(double) * HK_TAB_DOUBLES,
                                        hipMemcpyHostToDevice, x.stream));
-            x.hk_tab32 = (float*)x.dmalloc(sizeof(float) * HK32_TAB_FLOATS);
-            FDS_HIP_TRY(hipMemcpyAsync(x.hk_tab32, &HK32_TAB[0][0][0], sizeof(float) * HK32_TAB_FLOATS,
+            x.hf_tab = (double*)x.dmalloc(sizeof(double) * HF_TAB_DOUBLES);
+            FDS_HIP_TRY(hipMemcpyAsync(x.hf_tab, &HF_TAB[0][0][0], sizeof(double) * HF_TAB_DOUBLES,
+                                       hipMemcpyHostToDevice, x.stream));
+            x.hf_tab32 = (float*)x.dmalloc(sizeof(float) * HF32_TAB_FLOATS);
+            FDS_HIP_TRY(hipMemcpyAsync(x.hf_tab32, &HF32_TAB[0][0][0], sizeof(float) * HF32_TAB_FLOATS,
                                        hipMemcpyHostToDevice, x.stream));
             std::vector<double> yk(YK_ALL_DOUBLES);
             std::copy(&YK_TAB[0][0], &YK_TAB[0][0] + YK_TAB_DOUBLES, yk.begin());
@@ -217,7 +220,8 @@ fds_status fds_ctx_create(int device, void* hip_stream, const fds_allocator* all
             init_noalloc_scratch(x);
         } catch (...) {
             x.dfree(x.hk_tab);
-            x.dfree(x.hk_tab32);
+            x.dfree(x.hf_tab);
+            x.dfree(x.hf_tab32);
             x.dfree(x.gl32);
             x.dfree(x.yk_tab);
             x.dfree(x.yk_tab32);
@@ -235,7 +239,8 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
         if (ctx->impl.side) (void)hipStreamSynchronize(ctx->impl.side);
         resolve_profile(ctx->impl);
         ctx->impl.dfree(ctx->impl.hk_tab);
-        ctx->impl.dfree(ctx->impl.hk_tab32);
+        ctx->impl.dfree(ctx->impl.hf_tab);
+        ctx->impl.dfree(ctx->impl.hf_tab32);
         ctx->impl.dfree(ctx->impl.gl32);
         ctx->impl.dfree(ctx->impl.yk_tab);
         ctx->impl.dfree(ctx->impl.yk_tab32);

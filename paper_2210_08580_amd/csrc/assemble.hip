@@ -96,51 +96,30 @@ __device__ __forceinline__ int wave_max_int(int v) {
     return v;
 }
 
-// Element types of the far-field kernel: FP64 throughout, or FP32 kernel values
-// and accumulation (geometry, distances and Bessel arguments stay FP64).
-template <bool F32>
-struct FarT;
-template <>
-struct FarT<false> {
-    typedef double R;
-    typedef double2 C;
-    static constexpr int TAB_BYTES = 8 * HK_TAB_DOUBLES;
-};
-template <>
-struct FarT<true> {
-    typedef float R;
-    typedef float2 C;
-    static constexpr int TAB_BYTES = 4 * HK32_TAB_FLOATS;
-};
-
-// g = (i/4) H0(kR) and c = (ik/4) H1(kR)/R at one point pair
-__device__ __forceinline__ void far_kernel_values(double k, double R, const void* tab, double2& g, double2& c) {
-    const Bessel01 bs = hk_eval_hot(k * R, static_cast<const double*>(tab));
+// g = (i/4) H0(kR) and c = (ik/4) H1(kR)/R at one point pair (FP64)
+__device__ __forceinline__ void far_kernel_values(double k, double R, const double* tab, double2& g, double2& c) {
+    const Bessel01 bs = hf_eval(k * R, tab);
     g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
     const double kr = 0.25 * k / R;
     c = make_double2(-kr * bs.y1, kr * bs.j1);
 }
-__device__ __forceinline__ void far_kernel_values(double k, double R, const void* tab, float2& g, float2& c) {
-    const Bessel01f bs = hk32_eval_hot(k * R, static_cast<const float*>(tab));
-    g = make_float2(-0.25f * bs.y0, 0.25f * bs.j0);
-    const float kr = (float)(0.25 * k) * __builtin_amdgcn_rcpf((float)R);
-    c = make_float2(-kr * bs.y1, kr * bs.j1);
-}
 
 // LDS copies shared by the workgroup: the Bessel table and the quadrature rules.
-template <bool F32>
+template <int TAB_BYTES>
 struct FarShared {
-    __attribute__((aligned(16))) char tab[FarT<F32>::TAB_BYTES];
+    __attribute__((aligned(16))) char tab[TAB_BYTES];
     double wsh[16];            // w_b psi_0(xi_b), w_b psi_1(xi_b)
     double rl[WLOW_DOUBLES];   // reduced rules (n = 2 .. 6): xi, w psi_0, w psi_1
 };
+typedef FarShared<8 * HF_TAB_DOUBLES> FarShared64;
+typedef FarShared<4 * HF32_TAB_FLOATS> FarShared32;
 
-template <bool F32>
-__device__ __forceinline__ void far_shared_setup(FarShared<F32>& sh, const void* tabg, const W8& wt,
+template <int TAB_BYTES>
+__device__ __forceinline__ void far_shared_setup(FarShared<TAB_BYTES>& sh, const void* tabg, const W8& wt,
                                                  const WLow& wl) {
     const int4* src = static_cast<const int4*>(tabg);
     int4* dst = reinterpret_cast<int4*>(sh.tab);
-    for (int t = threadIdx.x; t < FarT<F32>::TAB_BYTES / 16; t += blockDim.x) dst[t] = src[t];
+    for (int t = threadIdx.x; t < TAB_BYTES / 16; t += blockDim.x) dst[t] = src[t];
     if (threadIdx.x < 8) {
         sh.wsh[threadIdx.x] = wt.wp0[threadIdx.x];
         sh.wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
@@ -167,31 +146,84 @@ __device__ __forceinline__ void store_group(T* __restrict__ p, const T (&v)[MG])
     }
 }
 
-// One work item (nsub-th of a 63 x 63 tile) of one operator, executed by one
-// wavefront. F32: kernel values and sums in FP32; OUT32: complex64 outputs.
-template <bool F32, bool OUT32>
-__device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, FarShared<F32>& sh) {
-    typedef typename FarT<F32>::R RT;
-    typedef typename FarT<F32>::C CT;
-    typedef typename std::conditional<OUT32, float2, double2>::type OT;
-    const void* tab = sh.tab;
-    const double* wsh = sh.wsh;
-    const int lane = threadIdx.x & 63;
+// Tile of a work item: row range [i0, i1), column block j0, whether it mirrors.
+struct FarTile {
+    int i0, i1, j0;
+    bool mirror;
+};
+__device__ __forceinline__ FarTile far_tile(const FarParams& P, int64_t work) {
     const int64_t tile = work / P.nsub;
     const int sub = (int)(work - tile * P.nsub);
-    const int n = P.n;
     int J = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
     while ((int64_t)J * (J + 1) / 2 > tile) --J;
     while ((int64_t)(J + 1) * (J + 2) / 2 <= tile) ++J;
     const int I = (int)(tile - (int64_t)J * (J + 1) / 2);
-    const int i0 = I * TB + sub * P.tr;
-    const int i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), n);
+    FarTile t;
+    t.i0 = I * TB + sub * P.tr;
+    t.i1 = min(min(I * TB + (sub + 1) * P.tr, I * TB + TB), P.n);
+    t.j0 = J * TB;
+    t.mirror = I != J;
+    return t;
+}
+
+// Writes the entries (i, col) of S, N, D and, above the diagonal, the mirror entries
+// (col, i) of S, N (symmetric) and D (from the transposed double layer T). The mirror
+// entries of MG consecutive rows are kept and written together: MG * sizeof(OT) = 32
+// bytes per lane, one whole memory sector, instead of MG partial writes to it spread
+// over the row loop (single 8- or 16-byte column-strided stores cost 2.7x and 1.8x the
+// stored bytes in write traffic). Groups that straddle the work item's rows are
+// written entry by entry.
+template <typename OT, int MG>
+struct MirrorRows {
+    OT mS[MG], mN[MG], mT[MG];
+};
+template <typename OT, int MG>
+__device__ __forceinline__ void far_store(OT* __restrict__ oS, OT* __restrict__ oN, OT* __restrict__ oD, int n,
+                                          const FarTile& T, bool mgroup, int i, int col, OT wS, OT wN, OT wD, OT wT,
+                                          MirrorRows<OT, MG>& M) {
+    const int64_t rc = (int64_t)i * n + col;
+    oS[rc] = wS;
+    oN[rc] = wN;
+    oD[rc] = wD;
+    if (!T.mirror) return;
+    const int g = i - i % MG;   // i >= 0: the group's first row
+    if (mgroup && g >= T.i0 && g + MG <= T.i1) {
+        const int r = i - g;   // uniform over the wave: registers by constant index
+#pragma unroll
+        for (int u = 0; u < MG; ++u)
+            if (u == r) {
+                M.mS[u] = wS;
+                M.mN[u] = wN;
+                M.mT[u] = wT;
+            }
+        if (r == MG - 1) {
+            const int64_t cr = (int64_t)col * n + g;
+            store_group<OT, MG>(oS + cr, M.mS);
+            store_group<OT, MG>(oN + cr, M.mN);
+            store_group<OT, MG>(oD + cr, M.mT);
+        }
+    } else {
+        const int64_t cr = (int64_t)col * n + i;
+        oS[cr] = wS;
+        oN[cr] = wN;
+        oD[cr] = wT;
+    }
+}
+
+// One work item (nsub-th of a 63 x 63 tile) of an FP64 operator, executed by one
+// wavefront.
+__device__ __forceinline__ void far_work_item64(const FarParams& P, int64_t work, FarShared64& sh) {
+    typedef double2 CT;
+    const double* tab = reinterpret_cast<const double*>(sh.tab);
+    const double* wsh = sh.wsh;
+    const int lane = threadIdx.x & 63;
+    const FarTile T = far_tile(P, work);
+    const int i0 = T.i0, i1 = T.i1, j0 = T.j0;
     if (i0 >= i1) return;
-    const int j0 = J * TB;
-    const bool mirror = (I != J);
-    OT* __restrict__ oS = static_cast<OT*>(P.S);
-    OT* __restrict__ oN = static_cast<OT*>(P.Nm);
-    OT* __restrict__ oD = static_cast<OT*>(P.D);
+    const int n = P.n;
+    double2* __restrict__ oS = static_cast<double2*>(P.S);
+    double2* __restrict__ oN = static_cast<double2*>(P.Nm);
+    double2* __restrict__ oD = static_cast<double2*>(P.D);
 
     const int qraw = j0 - 1 + lane;
     const bool qvalid = qraw < n;
@@ -210,52 +242,34 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
     const double qcx = qx0 + 0.5 * qex, qcy = qy0 + 0.5 * qey;
 
     const CT z = CT{0, 0};
-    CT pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z, pH0 = z, pH1 = z;
-    // The mirror entries (column col, rows i) of MG consecutive rows are kept and
-    // written together: MG * sizeof(OT) = 32 bytes per lane, one whole memory
-    // sector, instead of MG partial writes to it spread over the row loop (the
-    // write traffic of single 8- or 16-byte column-strided stores was 2.7x and 1.8x
-    // the stored bytes). Groups that straddle the work item's rows are written entry
-    // by entry.
-    constexpr int MG = OUT32 ? 4 : 2;
-    OT mS[MG], mN[MG], mT[MG];
-    const bool mgroup = mirror && (n % MG) == 0;
+    CT pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
+    MirrorRows<double2, 2> M;
+    const bool mgroup = T.mirror && (n % 2) == 0;
 
     for (int pr = i0 - 1; pr < i1; ++pr) {
         const int p = pr < 0 ? pr + n : pr;
         int dd = p - q;
         dd = dd < 0 ? -dd : dd;
-        // far pairs; with an FP64 band (complex64 operators) those whose four entries
-        // (offsets o - 1 .. o + 1, o = q - p) all lie in it are left to the band kernel
         const int cd = dd < n - dd ? dd : n - dd;
-        const bool active = qvalid && cd > 1 && cd >= P.bw;
+        const bool active = qvalid && cd > 1;
         CT S00 = z, S01 = z, S10 = z, S11 = z;
         CT D00 = z, D01 = z, D10 = z, D11 = z;
         CT T00 = z, T01 = z, T10 = z, T11 = z;
-        CT H00 = z, H01 = z, H10 = z, H11 = z;   // FP32 only: far N blocks, non-Maue form
         const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
-        const RT nnpq = (RT)fma(nxp, nxq, nyp * nyq);
-        const RT kk2 = (RT)(k * k);
-        // quadrature order for this row panel, uniform over the wavefront
         const int p1 = p + 1 == n ? 0 : p + 1;
         const double px0 = P.nodes[2 * p], py0 = P.nodes[2 * p + 1];
         const double pex = P.nodes[2 * p1] - px0, pey = P.nodes[2 * p1 + 1] - py0;
+        // quadrature order for this row panel, uniform over the wavefront
         int ord = 0;
         if (active) {
             const double hm = fmax(hp, hq);
             const double dist = hypot(px0 + 0.5 * pex - qcx, py0 + 0.5 * pey - qcy) - 0.5 * (hp + hq);
             const double kh = k * hm;
             ord = 8;
-            if constexpr (F32) {
-                if (kh <= 0.5 && dist >= 6.0 * hm) ord = 4;
-                if (kh <= 0.15 && dist >= 16.0 * hm) ord = 3;
-                if (kh <= 0.025 && dist >= 200.0 * hm) ord = 2;
-            } else {
-                if (kh <= 0.2 && dist >= 12.0 * hm) ord = 6;
-                if (kh <= 0.2 && dist >= 24.0 * hm) ord = 5;
-                if (kh <= 0.1 && dist >= 64.0 * hm) ord = 4;
-                if (kh <= 0.016 && dist >= 512.0 * hm) ord = 3;
-            }
+            if (kh <= 0.2 && dist >= 12.0 * hm) ord = 6;
+            if (kh <= 0.2 && dist >= 24.0 * hm) ord = 5;
+            if (kh <= 0.1 && dist >= 64.0 * hm) ord = 4;
+            if (kh <= 0.016 && dist >= 512.0 * hm) ord = 3;
         }
         ord = wave_max_int(ord);
         if (active) {
@@ -275,7 +289,7 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
                     wa0 = rx[no + a];
                     wa1 = rx[2 * no + a];
                 }
-                CT Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z, Hg0 = z, Hg1 = z;
+                CT Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z;
 #pragma unroll 1
                 for (int b = 0; b < no; ++b) {
                     double yb, zb, w0, w1;
@@ -291,65 +305,35 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
                         w1 = rx[2 * no + b];
                     }
                     const double dx = xa - yb, dy = ya - zb;
-                    const double R2 = fma(dx, dx, dy * dy);
-                    double R;
-                    if constexpr (F32) {
-                        // FP32 reciprocal square root refined by one Newton step in FP64
-                        // (relative error ~1e-14, ample for FP32 kernel values)
-                        const double r0 = (double)__builtin_amdgcn_rsqf((float)R2);
-                        R = R2 * (r0 * fma(-0.5 * R2, r0 * r0, 1.5));
-                    } else {
-                        R = sqrt(R2);
-                    }
+                    const double R = sqrt(fma(dx, dx, dy * dy));
                     CT g, c;
                     far_kernel_values(k, R, tab, g, c);
-                    const RT dq = (RT)fma(dx, nxq, dy * nyq);
-                    const RT dp = (RT)(-fma(dx, nxp, dy * nyp));
+                    const double dq = fma(dx, nxq, dy * nyq);
+                    const double dp = -fma(dx, nxp, dy * nyp);
                     const CT cd = CT{c.x * dq, c.y * dq}, ct = CT{c.x * dp, c.y * dp};
-                    Sg0 = fma_cr((RT)w0, g, Sg0);
-                    Sg1 = fma_cr((RT)w1, g, Sg1);
-                    Dg0 = fma_cr((RT)w0, cd, Dg0);
-                    Dg1 = fma_cr((RT)w1, cd, Dg1);
-                    Tg0 = fma_cr((RT)w0, ct, Tg0);
-                    Tg1 = fma_cr((RT)w1, ct, Tg1);
-                    if constexpr (F32) {
-                        // N kernel without the Maue cancellation (far entries only):
-                        // d_sx d_sy g - k^2 (n_p.n_q) g = k^2 g (u v - nn) + c (nn - 2 u v),
-                        // u = tau_p.d/R, v = tau_q.d/R, nn = n_p.n_q = tau_p.tau_q
-                        const RT ir = (RT)__builtin_amdgcn_rcpf((float)R);
-                        const RT u = (RT)fma(-dx, nyp, dy * nxp) * ir;
-                        const RT v = (RT)fma(-dx, nyq, dy * nxq) * ir;
-                        const RT uv = u * v;
-                        const RT a1 = kk2 * (uv - nnpq), a2 = nnpq - 2.0f * uv;
-                        const CT hk = CT{fmaf(a1, g.x, a2 * c.x), fmaf(a1, g.y, a2 * c.y)};
-                        Hg0 = fma_cr((RT)w0, hk, Hg0);
-                        Hg1 = fma_cr((RT)w1, hk, Hg1);
-                    }
+                    Sg0 = fma_cr(w0, g, Sg0);
+                    Sg1 = fma_cr(w1, g, Sg1);
+                    Dg0 = fma_cr(w0, cd, Dg0);
+                    Dg1 = fma_cr(w1, cd, Dg1);
+                    Tg0 = fma_cr(w0, ct, Tg0);
+                    Tg1 = fma_cr(w1, ct, Tg1);
                 }
-                const RT a0 = (RT)wa0, a1 = (RT)wa1;
-                S00 = fma_cr(a0, Sg0, S00); S01 = fma_cr(a0, Sg1, S01);
-                S10 = fma_cr(a1, Sg0, S10); S11 = fma_cr(a1, Sg1, S11);
-                D00 = fma_cr(a0, Dg0, D00); D01 = fma_cr(a0, Dg1, D01);
-                D10 = fma_cr(a1, Dg0, D10); D11 = fma_cr(a1, Dg1, D11);
-                T00 = fma_cr(a0, Tg0, T00); T01 = fma_cr(a0, Tg1, T01);
-                T10 = fma_cr(a1, Tg0, T10); T11 = fma_cr(a1, Tg1, T11);
-                if constexpr (F32) {
-                    H00 = fma_cr(a0, Hg0, H00); H01 = fma_cr(a0, Hg1, H01);
-                    H10 = fma_cr(a1, Hg0, H10); H11 = fma_cr(a1, Hg1, H11);
-                }
+                S00 = fma_cr(wa0, Sg0, S00); S01 = fma_cr(wa0, Sg1, S01);
+                S10 = fma_cr(wa1, Sg0, S10); S11 = fma_cr(wa1, Sg1, S11);
+                D00 = fma_cr(wa0, Dg0, D00); D01 = fma_cr(wa0, Dg1, D01);
+                D10 = fma_cr(wa1, Dg0, D10); D11 = fma_cr(wa1, Dg1, D11);
+                T00 = fma_cr(wa0, Tg0, T00); T01 = fma_cr(wa0, Tg1, T01);
+                T10 = fma_cr(wa1, Tg0, T10); T11 = fma_cr(wa1, Tg1, T11);
             }
-            const RT hh = (RT)(hp * hq);
+            const double hh = hp * hq;
             S00 = cscale(S00, hh); S01 = cscale(S01, hh); S10 = cscale(S10, hh); S11 = cscale(S11, hh);
             D00 = cscale(D00, hh); D01 = cscale(D01, hh); D10 = cscale(D10, hh); D11 = cscale(D11, hh);
             T00 = cscale(T00, hh); T01 = cscale(T01, hh); T10 = cscale(T10, hh); T11 = cscale(T11, hh);
-            if constexpr (F32) {
-                H00 = cscale(H00, hh); H01 = cscale(H01, hh); H10 = cscale(H10, hh); H11 = cscale(H11, hh);
-            }
         }
         // Maue form of N from S: N_ab = s_a s_b I0/(hp hq) - k^2 (np.nq) S_ab
         const CT I0 = cadd(cadd(S00, S01), cadd(S10, S11));
-        const CT I0h = cscale(I0, (RT)(1.0 / (hp * hq)));
-        const RT kk = (RT)(-k * k * fma(nxp, nxq, nyp * nyq));
+        const CT I0h = cscale(I0, 1.0 / (hp * hq));
+        const double kk = -k * k * fma(nxp, nxq, nyp * nyq);
         const CT N00 = cadd(I0h, cscale(S00, kk));
         const CT N01 = csub(cscale(S01, kk), I0h);
         const CT N10 = csub(cscale(S10, kk), I0h);
@@ -364,88 +348,291 @@ __device__ __forceinline__ void far_work_item(const FarParams& P, int64_t work, 
             const CT rT0 = cadd(T00, pT0), rT1 = cadd(T01, pT1);
             const CT nS = shfl_down1(rS0), nN = shfl_down1(rN0);
             const CT nD = shfl_down1(rD0), nT = shfl_down1(rT0);
-            CT vN = cadd(rN1, nN);
-            if constexpr (F32) {
-                // In FP32 the Maue sum of the four panel pairs of a far entry cancels
-                // like (h/R)^2; entries whose four pairs are all far (cyclic |i - j| >= 3)
-                // take the integrated-back kernel instead, which is cancellation-free.
-                const CT rH0 = cadd(H00, pH0), rH1 = cadd(H01, pH1);
-                const CT nH = shfl_down1(rH0);
-                int dij = i - col;
-                dij = dij < 0 ? -dij : dij;
-                if (dij >= 3 && dij <= n - 3) vN = cadd(rH1, nH);
+            if (writes)
+                far_store<double2, 2>(oS, oN, oD, n, T, mgroup, i, col, cadd(rS1, nS), cadd(rN1, nN),
+                                      cadd(rD1, nD), cadd(rT1, nT), M);
+        }
+        pS0 = S10; pS1 = S11; pN0 = N10; pN1 = N11;
+        pD0 = D10; pD1 = D11; pT0 = T10; pT1 = T11;
+    }
+}
+
+// ------------------------------------------------ FP32 far pass (complex64 operators)
+// Kernel values and sums in FP32; point coordinates, distances and the Bessel
+// argument in FP64 (the table variable is an FP32 offset from an FP64 interval
+// centre, so the rounding of x never enters). N only off the FP64 band, where
+// the four panel pairs of every entry are >= 3 panels apart, so the Maue sum
+// (which cancels like (h/R)^2 there) is replaced by the integrated-back kernel
+//   d_sx d_sy g - k^2 (n_p.n_q) g = k^2 g (u v - nn) + c (nn - 2 u v),
+//   u = tau_p.d/R, v = tau_q.d/R, nn = n_p.n_q = tau_p.tau_q.
+// Weights carry the panel lengths (row: h_p w_a psi_alpha, column: h_q w_b psi_beta),
+// so the pair blocks need no final scaling.
+struct Far32Col {   // per lane: the column panel q
+    double qx0, qy0, qex, qey;
+    float nxq, nyq, hq;
+};
+struct Far32Row {   // wave-uniform: the row panel p
+    double px0, py0, pex, pey;
+    float nxp, nyp, hp, nn;
+};
+struct Far32Sum {   // b-sums of one row point: (S, D, T, H) x (psi_0, psi_1) of the column panel
+    float2 s0, s1, d0, d1, t0, t1, h0, h1;
+};
+struct Far32Blk {   // 2 x 2 blocks of the pair: [alpha][beta] of S, D, T, H
+    float2 S[2][2], D[2][2], T[2][2], H[2][2];
+};
+
+__device__ __forceinline__ void far32_point(double xa, double ya, double yb, double zb, float w0, float w1,
+                                            double k, float kq, float kk2q, const Far32Row& r, const Far32Col& cq,
+                                            const float* tab, Far32Sum& A) {
+    const double dx = xa - yb, dy = ya - zb;
+    const double R2 = fma(dx, dx, dy * dy);
+    // FP32 reciprocal square root refined by one Newton step in FP64 (relative
+    // error ~1e-14: the Bessel argument needs FP64 accuracy, nothing else does)
+    const double r0 = (double)__builtin_amdgcn_rsqf((float)R2);
+    const double ri = r0 * fma(-0.5 * R2, r0 * r0, 1.5);
+    const Bessel01f bs = hf32_eval(k * (R2 * ri), tab);
+    const float ir = (float)ri;
+    const float dxf = (float)dx, dyf = (float)dy;
+    // g = (i/4) H0 and c = (ik/4) H1 / R
+    const float2 g = make_float2(-0.25f * bs.y0, 0.25f * bs.j0);
+    const float kr = kq * ir;
+    const float2 c = make_float2(-kr * bs.y1, kr * bs.j1);
+    const float dq = fmaf(dxf, cq.nxq, dyf * cq.nyq);
+    const float dp = -fmaf(dxf, r.nxp, dyf * r.nyp);
+    const float u = fmaf(dyf, r.nxp, -dxf * r.nyp) * ir;
+    const float v = fmaf(dyf, cq.nxq, -dxf * cq.nyq) * ir;
+    const float uv = u * v;
+    const float a1 = kk2q * (uv - r.nn), a2 = fmaf(-2.0f, uv, r.nn);
+    const float2 hk = make_float2(fmaf(a1, g.x, a2 * c.x), fmaf(a1, g.y, a2 * c.y));
+    const float2 cd = make_float2(c.x * dq, c.y * dq), ct = make_float2(c.x * dp, c.y * dp);
+    A.s0 = fma_cr(w0, g, A.s0);
+    A.s1 = fma_cr(w1, g, A.s1);
+    A.d0 = fma_cr(w0, cd, A.d0);
+    A.d1 = fma_cr(w1, cd, A.d1);
+    A.t0 = fma_cr(w0, ct, A.t0);
+    A.t1 = fma_cr(w1, ct, A.t1);
+    A.h0 = fma_cr(w0, hk, A.h0);
+    A.h1 = fma_cr(w1, hk, A.h1);
+}
+
+__device__ __forceinline__ void far32_fold(float wa0, float wa1, const Far32Sum& A, Far32Blk& B) {
+    B.S[0][0] = fma_cr(wa0, A.s0, B.S[0][0]); B.S[0][1] = fma_cr(wa0, A.s1, B.S[0][1]);
+    B.S[1][0] = fma_cr(wa1, A.s0, B.S[1][0]); B.S[1][1] = fma_cr(wa1, A.s1, B.S[1][1]);
+    B.D[0][0] = fma_cr(wa0, A.d0, B.D[0][0]); B.D[0][1] = fma_cr(wa0, A.d1, B.D[0][1]);
+    B.D[1][0] = fma_cr(wa1, A.d0, B.D[1][0]); B.D[1][1] = fma_cr(wa1, A.d1, B.D[1][1]);
+    B.T[0][0] = fma_cr(wa0, A.t0, B.T[0][0]); B.T[0][1] = fma_cr(wa0, A.t1, B.T[0][1]);
+    B.T[1][0] = fma_cr(wa1, A.t0, B.T[1][0]); B.T[1][1] = fma_cr(wa1, A.t1, B.T[1][1]);
+    B.H[0][0] = fma_cr(wa0, A.h0, B.H[0][0]); B.H[0][1] = fma_cr(wa0, A.h1, B.H[0][1]);
+    B.H[1][0] = fma_cr(wa1, A.h0, B.H[1][0]); B.H[1][1] = fma_cr(wa1, A.h1, B.H[1][1]);
+}
+
+// The 2-point rule (xi = 1/2 -+ 1/(2 sqrt 3), w = 1/2), fully unrolled: w psi_0 and
+// w psi_1 at the two points are (c_hi, c_lo) and (c_lo, c_hi).
+constexpr double G2_LO = 0.21132486540518711775;
+constexpr double G2_HI = 0.78867513459481288225;
+constexpr float G2_CHI = 0.39433756729740644113f;
+constexpr float G2_CLO = 0.10566243270259355887f;
+
+// Adds the blocks of one far panel pair with the NO-point rule to B: NO = 2 (constants), 3 or 4
+// (points and weights from the LDS rule table rl), 8 (the panels' stored Gauss
+// points and the weights wsh).
+template <int NO>
+__device__ __forceinline__ void far32_blocks(const FarParams& P, int p, int q, const Far32Row& r,
+                                             const Far32Col& cq, const double (&yq)[4], float kq, float kk2q,
+                                             const float* tab, const double* rl, const double* wsh, Far32Blk& B) {
+    const double k = P.k;
+    const float2 z = make_float2(0.f, 0.f);
+    if constexpr (NO == 2) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const double xi = a == 0 ? G2_LO : G2_HI;
+            const double xa = fma(xi, r.pex, r.px0), ya = fma(xi, r.pey, r.py0);
+            Far32Sum A = {z, z, z, z, z, z, z, z};
+            far32_point(xa, ya, yq[0], yq[1], cq.hq * G2_CHI, cq.hq * G2_CLO, k, kq, kk2q, r, cq, tab, A);
+            far32_point(xa, ya, yq[2], yq[3], cq.hq * G2_CLO, cq.hq * G2_CHI, k, kq, kk2q, r, cq, tab, A);
+            const float wa0 = r.hp * (a == 0 ? G2_CHI : G2_CLO), wa1 = r.hp * (a == 0 ? G2_CLO : G2_CHI);
+            far32_fold(wa0, wa1, A, B);
+        }
+    } else {
+        const double* rx = rl + low_rule_offset(NO < 8 ? NO : 2);
+#pragma unroll 1
+        for (int a = 0; a < NO; ++a) {
+            double xa, ya;
+            float wa0, wa1;
+            if constexpr (NO == 8) {
+                xa = P.gx[8 * p + a];
+                ya = P.gy[8 * p + a];
+                wa0 = (float)(r.hp * wsh[a]);
+                wa1 = (float)(r.hp * wsh[8 + a]);
+            } else {
+                xa = fma(rx[a], r.pex, r.px0);
+                ya = fma(rx[a], r.pey, r.py0);
+                wa0 = (float)(r.hp * rx[NO + a]);
+                wa1 = (float)(r.hp * rx[2 * NO + a]);
             }
-            // cyclic offset col - i in (-n/2, n/2]
+            Far32Sum A = {z, z, z, z, z, z, z, z};
+            constexpr int UB = NO == 8 ? 1 : NO;
+#pragma unroll UB
+            for (int b = 0; b < NO; ++b) {
+                double yb, zb;
+                float w0, w1;
+                if constexpr (NO == 8) {
+                    yb = P.gx[8 * q + b];
+                    zb = P.gy[8 * q + b];
+                    w0 = (float)(cq.hq * wsh[b]);
+                    w1 = (float)(cq.hq * wsh[8 + b]);
+                } else {
+                    yb = fma(rx[b], cq.qex, cq.qx0);
+                    zb = fma(rx[b], cq.qey, cq.qy0);
+                    w0 = (float)(cq.hq * rx[NO + b]);
+                    w1 = (float)(cq.hq * rx[2 * NO + b]);
+                }
+                far32_point(xa, ya, yb, zb, w0, w1, k, kq, kk2q, r, cq, tab, A);
+            }
+            far32_fold(wa0, wa1, A, B);
+        }
+    }
+}
+
+// One work item of a complex64 operator. The Gauss order (8 down to 2 points per
+// panel) is taken per row panel as the largest any lane of the wavefront needs
+// (thresholds in the comment at the top of this file); the squared midpoint
+// distance is compared, which needs no square root.
+__device__ __forceinline__ void far_work_item32(const FarParams& P, int64_t work, FarShared32& sh) {
+    const float* tab = reinterpret_cast<const float*>(sh.tab);
+    const int lane = threadIdx.x & 63;
+    const FarTile T = far_tile(P, work);
+    const int i0 = T.i0, i1 = T.i1, j0 = T.j0;
+    if (i0 >= i1) return;
+    const int n = P.n;
+    float2* __restrict__ oS = static_cast<float2*>(P.S);
+    float2* __restrict__ oN = static_cast<float2*>(P.Nm);
+    float2* __restrict__ oD = static_cast<float2*>(P.D);
+
+    const int qraw = j0 - 1 + lane;
+    const bool qvalid = qraw < n;
+    const int q = qraw < 0 ? n - 1 : (qvalid ? qraw : 0);
+    const int col = j0 + lane;
+    const bool writes = (lane < TB) && (col < n);
+    const double k = P.k;
+    const float kq = (float)(0.25 * k), kk2q = (float)(k * k);
+    const float kf = (float)k;
+
+    Far32Col cq;
+    {
+        const int q1 = q + 1 == n ? 0 : q + 1;
+        cq.qx0 = P.nodes[2 * q];
+        cq.qy0 = P.nodes[2 * q + 1];
+        cq.qex = P.nodes[2 * q1] - cq.qx0;
+        cq.qey = P.nodes[2 * q1 + 1] - cq.qy0;
+        cq.nxq = (float)P.nx[q];
+        cq.nyq = (float)P.ny[q];
+        cq.hq = (float)P.h[q];
+    }
+    const double yq[4] = {fma(G2_LO, cq.qex, cq.qx0), fma(G2_LO, cq.qey, cq.qy0), fma(G2_HI, cq.qex, cq.qx0),
+                          fma(G2_HI, cq.qey, cq.qy0)};
+    const double qcx = fma(0.5, cq.qex, cq.qx0), qcy = fma(0.5, cq.qey, cq.qy0);
+
+    const float2 z = make_float2(0.f, 0.f);
+    float2 pS0 = z, pS1 = z, pH0 = z, pH1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
+    MirrorRows<float2, 4> M;
+    const bool mgroup = T.mirror && (n % 4) == 0;
+
+    for (int pr = i0 - 1; pr < i1; ++pr) {
+        const int p = pr < 0 ? pr + n : pr;
+        int dd = p - q;
+        dd = dd < 0 ? -dd : dd;
+        // far pairs whose four entries (offsets o - 1 .. o + 1, o = q - p) do not all
+        // lie in the FP64 band (those are left to the band kernel)
+        const int cd = dd < n - dd ? dd : n - dd;
+        const bool active = qvalid && cd > 1 && cd >= P.bw;
+        Far32Row r;
+        const int p1 = p + 1 == n ? 0 : p + 1;
+        r.px0 = P.nodes[2 * p];
+        r.py0 = P.nodes[2 * p + 1];
+        r.pex = P.nodes[2 * p1] - r.px0;
+        r.pey = P.nodes[2 * p1 + 1] - r.py0;
+        const double nxp = P.nx[p], nyp = P.ny[p];
+        r.nxp = (float)nxp;
+        r.nyp = (float)nyp;
+        r.hp = (float)P.h[p];
+        r.nn = fmaf(r.nxp, cq.nxq, r.nyp * cq.nyq);
+        // orders: 4 for gap >= 6 hm (kh <= 0.5), 3 for >= 16 hm (kh <= 0.15), 2 for
+        // >= 200 hm (kh <= 0.025), else 8; gap = |midpoint distance| - (hp + hq)/2
+        const float mx = (float)(fma(0.5, r.pex, r.px0) - qcx), my = (float)(fma(0.5, r.pey, r.py0) - qcy);
+        const float m2 = fmaf(mx, mx, my * my);
+        const float hm = fmaxf(r.hp, cq.hq), hs = 0.5f * (r.hp + cq.hq), kh = kf * hm;
+        const float e2 = fmaf(200.0f, hm, hs), e3 = fmaf(16.0f, hm, hs), e4 = fmaf(6.0f, hm, hs);
+        const bool over2 = active && !(kh <= 0.025f && m2 >= e2 * e2);
+        const bool over3 = active && !(kh <= 0.15f && m2 >= e3 * e3);
+        const bool over4 = active && !(kh <= 0.5f && m2 >= e4 * e4);
+        const int ord = __ballot(over4) ? 8 : (__ballot(over3) ? 4 : (__ballot(over2) ? 3 : 2));
+        Far32Blk B;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) B.S[a][b] = B.D[a][b] = B.T[a][b] = B.H[a][b] = z;
+        if (active) {
+            if (ord == 2) far32_blocks<2>(P, p, q, r, cq, yq, kq, kk2q, tab, sh.rl, sh.wsh, B);
+            else if (ord == 3) far32_blocks<3>(P, p, q, r, cq, yq, kq, kk2q, tab, sh.rl, sh.wsh, B);
+            else if (ord == 4) far32_blocks<4>(P, p, q, r, cq, yq, kq, kk2q, tab, sh.rl, sh.wsh, B);
+            else far32_blocks<8>(P, p, q, r, cq, yq, kq, kk2q, tab, sh.rl, sh.wsh, B);
+        }
+        if (pr >= i0) {
+            const int i = pr;
+            // row i receives psi_0 of the current row panel and psi_1 of the previous one
+            const float2 rS0 = cadd(B.S[0][0], pS0), rS1 = cadd(B.S[0][1], pS1);
+            const float2 rH0 = cadd(B.H[0][0], pH0), rH1 = cadd(B.H[0][1], pH1);
+            const float2 rD0 = cadd(B.D[0][0], pD0), rD1 = cadd(B.D[0][1], pD1);
+            const float2 rT0 = cadd(B.T[0][0], pT0), rT1 = cadd(B.T[0][1], pT1);
+            const float2 nS = shfl_down1(rS0), nH = shfl_down1(rH0);
+            const float2 nD = shfl_down1(rD0), nT = shfl_down1(rT0);
+            // cyclic offset col - i in (-n/2, n/2]; N on the band is kept in complex128
+            // (asm_nband_kernel), the complex64 matrix holds zeros there
             int dcy = col - i;
             dcy = dcy < 0 ? dcy + n : dcy;
             dcy = 2 * dcy > n ? dcy - n : dcy;
             const bool inband = (dcy < 0 ? -dcy : dcy) <= P.bw;
-            if (writes) {
-                // N on the band is kept in complex128 (asm_nband_kernel); the complex64
-                // matrix holds zeros there
-                if (inband) vN = CT{0, 0};
-                OT wS, wN, wD, wT;
-                to_out(cadd(rS1, nS), wS);
-                to_out(vN, wN);
-                to_out(cadd(rD1, nD), wD);
-                to_out(cadd(rT1, nT), wT);
-                const int64_t rc = (int64_t)i * n + col;
-                oS[rc] = wS;
-                oN[rc] = wN;
-                oD[rc] = wD;
-                if (mirror) {
-                    const int g = i - i % MG;   // i >= 0: the group's first row
-                    if (mgroup && g >= i0 && g + MG <= i1) {
-                        const int r = i - g;   // uniform over the wave: registers by constant index
-#pragma unroll
-                        for (int u = 0; u < MG; ++u)
-                            if (u == r) {
-                                mS[u] = wS;
-                                mN[u] = wN;
-                                mT[u] = wT;
-                            }
-                        if (r == MG - 1) {
-                            const int64_t cr = (int64_t)col * n + g;
-                            store_group<OT, MG>(oS + cr, mS);
-                            store_group<OT, MG>(oN + cr, mN);
-                            store_group<OT, MG>(oD + cr, mT);
-                        }
-                    } else {
-                        const int64_t cr = (int64_t)col * n + i;
-                        oS[cr] = wS;
-                        oN[cr] = wN;
-                        oD[cr] = wT;
-                    }
-                }
-            }
+            const float2 vN = inband ? z : cadd(rH1, nH);
+            if (writes)
+                far_store<float2, 4>(oS, oN, oD, n, T, mgroup, i, col, cadd(rS1, nS), vN, cadd(rD1, nD),
+                                     cadd(rT1, nT), M);
         }
-        pS0 = S10; pS1 = S11; pN0 = N10; pN1 = N11;
-        pD0 = D10; pD1 = D11; pT0 = T10; pT1 = T11;
-        pH0 = H10; pH1 = H11;
+        pS0 = B.S[1][0]; pS1 = B.S[1][1]; pH0 = B.H[1][0]; pH1 = B.H[1][1];
+        pD0 = B.D[1][0]; pD1 = B.D[1][1]; pT0 = B.T[1][0]; pT1 = B.T[1][1];
     }
 }
 
-template <bool F32, bool OUT32>
-__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel(FarParams P, W8 wt, WLow wl) {
-    __shared__ FarShared<F32> sh;
-    far_shared_setup<F32>(sh, P.tab, wt, wl);
+__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel64(FarParams P, W8 wt, WLow wl) {
+    __shared__ FarShared64 sh;
+    far_shared_setup(sh, P.tab, wt, wl);
     const int64_t work = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (work >= P.nwork) return;
-    far_work_item<F32, OUT32>(P, work, sh);
+    far_work_item64(P, work, sh);
+}
+
+__global__ __launch_bounds__(64 * WAVES, 2) void asm_far_kernel32(FarParams P, W8 wt, WLow wl) {
+    __shared__ FarShared32 sh;
+    far_shared_setup(sh, P.tab, wt, wl);
+    const int64_t work = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (work >= P.nwork) return;
+    far_work_item32(P, work, sh);
 }
 
 // Many operators in one launch: a persistent grid whose wavefronts take work
 // items from a global counter until the queue (all tiles of all operators,
 // prefix[j] = first item of operator j) is exhausted; every wavefront exits
 // once the counter passes the total.
-template <bool F32, bool OUT32>
+template <bool F32>
 __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarParams* __restrict__ jobs,
                                                                       const int64_t* __restrict__ prefix, int njobs,
                                                                       unsigned long long* __restrict__ counter,
                                                                       const void* __restrict__ tabg, W8 wt,
                                                                       WLow wl) {
-    __shared__ FarShared<F32> sh;
-    far_shared_setup<F32>(sh, tabg, wt, wl);
+    typedef typename std::conditional<F32, FarShared32, FarShared64>::type SH;
+    __shared__ SH sh;
+    far_shared_setup(sh, tabg, wt, wl);
     const int64_t total = prefix[njobs];
     for (;;) {
         unsigned long long w = 0;
@@ -459,7 +646,8 @@ __global__ __launch_bounds__(64 * WAVES, 2) void asm_far_batch_kernel(const FarP
             else hi = mid - 1;
         }
         const int j = __builtin_amdgcn_readfirstlane(lo);
-        far_work_item<F32, OUT32>(jobs[j], (int64_t)w - prefix[j], sh);
+        if constexpr (F32) far_work_item32(jobs[j], (int64_t)w - prefix[j], sh);
+        else far_work_item64(jobs[j], (int64_t)w - prefix[j], sh);
     }
 }
 
@@ -489,7 +677,7 @@ struct NBandParams {
     const double* __restrict__ nx;
     const double* __restrict__ ny;
     const double* __restrict__ nodes;
-    const double* __restrict__ tab;   // HK_TAB (FP64)
+    const double* __restrict__ tab;   // HF_TAB (FP64 far-field set)
     double2* __restrict__ blk;        // [w][16][n] pair blocks
     double2* __restrict__ nband;      // [n][2 w + 1]
     float2* __restrict__ S;           // complex64 S, N (zero on the band) and D, row-major n x n
@@ -500,10 +688,10 @@ struct NBandParams {
 };
 
 __global__ __launch_bounds__(64 * WAVES) void asm_nband_blocks_kernel(NBandParams P, W8 wt, WLow wl) {
-    __shared__ double tab[HK_TAB_DOUBLES];
+    __shared__ double tab[HF_TAB_DOUBLES];
     __shared__ double wsh[16];
     __shared__ double rl[WLOW_DOUBLES];
-    for (int t = threadIdx.x; t < HK_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
+    for (int t = threadIdx.x; t < HF_TAB_DOUBLES; t += blockDim.x) tab[t] = P.tab[t];
     if (threadIdx.x < 8) {
         wsh[threadIdx.x] = wt.wp0[threadIdx.x];
         wsh[8 + threadIdx.x] = wt.wp1[threadIdx.x];
@@ -575,7 +763,7 @@ __global__ __launch_bounds__(64 * WAVES) void asm_nband_blocks_kernel(NBandParam
             }
             const double dx = xa - yb, dy = ya - zb;
             const double R = sqrt(fma(dx, dx, dy * dy));
-            const Bessel01 bs = hk_eval(k * R, tab);
+            const Bessel01 bs = hf_eval(k * R, tab);
             const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
             const double kr = 0.25 * k / R;
             const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
@@ -800,7 +988,7 @@ static FarParams far_params(Op& op) {
     FarParams fp;
     fp.gx = op.gx; fp.gy = op.gy; fp.h = op.h; fp.nx = op.nx; fp.ny = op.ny;
     const bool f32 = op.prec == FDS_FP32;
-    fp.tab = f32 ? (const void*)c.hk_tab32 : (const void*)c.hk_tab;
+    fp.tab = f32 ? (const void*)c.hf_tab32 : (const void*)c.hf_tab;
     fp.nodes = op.nodes;
     fp.S = f32 ? (void*)op.S32 : (void*)op.S;
     fp.Nm = f32 ? (void*)op.N32 : (void*)op.Nm;
@@ -851,7 +1039,7 @@ static void launch_nband(Op& op, const W8& wt, const WLow& wlow) {
     Ctx& c = *op.ctx;
     NBandParams P;
     P.gx = op.gx; P.gy = op.gy; P.h = op.h; P.nx = op.nx; P.ny = op.ny; P.nodes = op.nodes;
-    P.tab = c.hk_tab;
+    P.tab = c.hf_tab;
     P.nband = op.Nband;
     P.S = op.S32;
     P.D = op.D32;
@@ -884,9 +1072,9 @@ void launch_assemble(Op& op) {
     {
         KScope _ks(c, "asm_far");
         if (f32)
-            hipLaunchKernelGGL((asm_far_kernel<true, true>), dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
+            hipLaunchKernelGGL(asm_far_kernel32, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt, wlow);
         else
-            hipLaunchKernelGGL((asm_far_kernel<false, false>), dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt,
+            hipLaunchKernelGGL(asm_far_kernel64, dim3(nblk), dim3(64 * WAVES), 0, c.stream, fp, wt,
                                wlow);
     }
     FDS_HIP_TRY(hipGetLastError());
@@ -927,10 +1115,10 @@ void launch_assemble_batch(Ctx& c, Op* const* ops, int nops) {
         KScope _ks(c, "asm_far_batch");
         hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, c.stream, counter);
         if (f32)
-            hipLaunchKernelGGL((asm_far_batch_kernel<true, true>), dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
+            hipLaunchKernelGGL(asm_far_batch_kernel<true>, dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
                                dprefix, nops, counter, jobs[0].tab, wt, wlow);
         else
-            hipLaunchKernelGGL((asm_far_batch_kernel<false, false>), dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
+            hipLaunchKernelGGL(asm_far_batch_kernel<false>, dim3(grid), dim3(64 * WAVES), 0, c.stream, djobs,
                                dprefix, nops, counter, jobs[0].tab, wt, wlow);
     }
     FDS_HIP_TRY(hipGetLastError());

@@ -65,7 +65,8 @@ struct Ctx {
     bool autotune = false;                     // time GEMM split-K candidates on first use
     std::map<std::string, int> tuned;          // shape class -> chosen split-K factor
     double* hk_tab = nullptr;     // device copy of the Bessel coefficient table
-    float* hk_tab32 = nullptr;    // device copy of the single-precision table
+    double* hf_tab = nullptr;     // device copies of the far-field sets (quarter intervals)
+    float* hf_tab32 = nullptr;
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
     float* yk_tab32 = nullptr;    // device copy of the float32 K0 interval table

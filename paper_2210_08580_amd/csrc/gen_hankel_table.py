@@ -17,10 +17,10 @@ Three regions of the real argument x > 0 (J0, Y0, J1, Y1):
 The script checks a float64 emulation of the device formulas against mpmath and
 refuses to write the table unless every region is within 4e-16 max(|f|, 1).
 
-A second, single-precision set (HK32_*) serves the FP32 far-field assembly: the
-same three regions with degree-DEG32 interpolants and shorter series/expansions,
-checked in a float32 emulation (argument x and the table variable t formed in
-float64, everything after in float32) against 4e-7 max(|f|, 1).
+The single-precision asymptotic expansion (HK32_ASY_*, shorter than the FP64 one)
+serves the far-field FP32 set below beyond its table, checked in a float32
+emulation (argument x formed in float64, the phase reduced in float64, everything
+after in float32) against 4e-7 max(|f|, 1).
 
 A third set (YK_*) evaluates K0, the modified Bessel function of the second kind
 of the Yukawa kernel (1/2pi) K0(kappa R) (Helmholtz at the imaginary wavenumber
@@ -32,6 +32,17 @@ i kappa), in FP64:
   x >= YK_XA  K0 = sqrt(pi/(2x)) exp(-x) sum_k a_k(0) x^-k  (A&S 9.7.2)
 checked against mpmath in relative error (4e-16 max(|f|, 1) in the series range,
 where the log term dominates, 6e-16 relative elsewhere).
+
+Two further sets (HF_*, HF32_*) serve the far-field assembly kernels, one table
+lookup for every argument below HF_XF (FP64) or HF32_XF (FP32): quarter-unit
+intervals [c/4, (c+1)/4), interpolated like the tables above in t = x - (c + 1/2)/4
+(degree HF_DEG or HF32_DEG). On the first eight intervals (x < 2) the table holds
+the parts of Y0 and Y1 that stay regular at x = 0,
+  Y0r = Y0 - (2/pi) J0 log x,   Y1r = Y1 - (2/pi) J1 log x + 2/(pi x)
+(A&S 9.1.11 and 9.1.13 with log(x/2) = log x - log 2: both are power series), and
+the evaluator adds the logarithmic and 1/x terms back; above it holds Y0, Y1
+themselves. Beyond HF_XF the asymptotic expansions above apply. Checked like the
+other sets (FP64: 4e-16 max(|f|, 1); FP32 emulation: 4e-7 max(|f|, 1)).
 
 Run:  python gen_hankel_table.py   (writes hankel_table.inc next to this file)
 """
@@ -47,8 +58,6 @@ mp.mp.dps = 50
 XS, XA = 2, 25
 DEG = 15
 NSER = 16
-DEG32 = 9
-NSER32 = 9
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -196,25 +205,11 @@ def emulate32(x, tabs, ser, asy):
             amp * (p1 * c1 - q1 * s1), amp * (p1 * s1 + q1 * c1))
 
 
-def table32():
-    ser = [[float(v) for v in s[:NSER32]] for s in series_coeffs()]
+def asym32():
+    """Coefficients of the single-precision asymptotic expansion (x >= HF32_XF)."""
     nas = asym_terms_needed(XA, tol=2e-9)
     asy = [[float(v) for v in s] for s in (*asym_coeffs(0, nas)[:2], *asym_coeffs(1, nas)[:2])]
-    F = fns()
-    tabs = [[[float(v) for v in cheb_monomial(F[f], c, DEG32)] for c in range(XS, XA)] for f in range(4)]
-    xs = np.concatenate([np.geomspace(1e-4, XS, 300, endpoint=False),
-                         np.linspace(XS, XA, 2300, endpoint=False),
-                         np.linspace(XA, 200, 600)])
-    worst = 0.0
-    for x in xs:
-        got = emulate32(x, tabs, ser, asy)
-        for f in range(4):
-            ref = float(F[f](mp.mpf(float(x))))
-            worst = max(worst, abs(float(got[f]) - ref) / max(1.0, abs(ref)))
-    print(f"fp32 set: asymptotic terms {nas}; worst scaled error {worst:.3e}")
-    if worst > 4e-7:
-        sys.exit("fp32 table accuracy check failed")
-    return ser, asy, tabs, nas
+    return asy, nas
 
 
 YK_XS = 2
@@ -294,6 +289,97 @@ def yk32_table():
     return tab
 
 
+HF_XF = 32
+HF_DEG = 9
+HF32_XF = 64
+HF32_DEG = 5
+HF_SMALL = 8      # quarter intervals below x = 2 hold the regular parts
+
+
+def hf_fns():
+    """J0, Y0 (or its regular part), J1, Y1 (or its regular part) on the quarter
+    intervals; `small` selects the regular parts."""
+    tp = 2 / mp.pi
+
+    def y0r(x):
+        return mp.bessely(0, x) - tp * mp.besselj(0, x) * mp.log(x)
+
+    def y1r(x):
+        return mp.bessely(1, x) - tp * mp.besselj(1, x) * mp.log(x) + tp / x
+    return ([lambda x: mp.besselj(0, x), y0r, lambda x: mp.besselj(1, x), y1r],
+            [lambda x: mp.besselj(0, x), lambda x: mp.bessely(0, x), lambda x: mp.besselj(1, x),
+             lambda x: mp.bessely(1, x)])
+
+
+def cheb_monomial_q(f, c, deg):
+    """Degree-`deg` Chebyshev interpolant of f on the quarter interval [c/4, (c+1)/4]
+    in monomials of t = x - (c + 1/2)/4 (cheb_monomial on the unit interval of the
+    scaled function, rescaled)."""
+    g = lambda u: f(u / 4)
+    mono = cheb_monomial(g, c, deg)          # in s = 4x - (c + 1/2) = 4 t
+    return [m * 4 ** i for i, m in enumerate(mono)]
+
+
+def hf_table(xf, deg):
+    small, plain = hf_fns()
+    return [[[float(v) for v in cheb_monomial_q((small if c < HF_SMALL else plain)[f], c, deg)]
+             for c in range(4 * xf)] for f in range(4)]
+
+
+def hf_emulate(x, tab, asy, xf):
+    x = np.float64(x)
+    if x >= xf:
+        return emulate(x, None, None, asy)
+    c = int(np.floor(4 * x))
+    t = x - (c + 0.5) / 4
+    j0, y0, j1, y1 = (horner(tab[f][c], t) for f in range(4))
+    if c < HF_SMALL:
+        l = np.log(x)
+        tp = 2 / np.pi
+        y0 = y0 + tp * j0 * l
+        y1 = y1 + tp * j1 * l - tp / x
+    return j0, y0, j1, y1
+
+
+def hf32_emulate(x, tab, asy32, xf):
+    f4 = np.float32
+    x = np.float64(x)
+    if x >= xf:
+        return emulate32(x, None, None, asy32)
+    c = int(np.floor(4 * x))
+    t = f4(x - (c + 0.5) / 4)
+
+    def h32(cc):
+        acc = f4(cc[-1])
+        for v in cc[-2::-1]:
+            acc = f4(acc * t + f4(v))
+        return acc
+    j0, y0, j1, y1 = (h32(tab[f][c]) for f in range(4))
+    if c < HF_SMALL:
+        xf4 = f4(x)
+        l = f4(np.log(xf4))
+        tp = f4(2 / np.pi)
+        y0 = f4(y0 + f4(tp * j0) * l)
+        y1 = f4(f4(y1 + f4(tp * j1) * l) - f4(tp * f4(f4(1) / xf4)))
+    return j0, y0, j1, y1
+
+
+def hf_check(tab, asy, xf, emu, tol, label):
+    F = fns()
+    xs = np.concatenate([np.geomspace(1e-6, 2.0, 400, endpoint=False),
+                         np.linspace(2.0, xf, 40 * xf, endpoint=False),
+                         np.linspace(xf, 3 * xf, 200)])
+    worst = 0.0
+    for x in xs:
+        got = emu(x, tab, asy, xf)
+        for f in range(4):
+            ref = float(F[f](mp.mpf(float(x))))
+            worst = max(worst, abs(float(got[f]) - ref) / max(1.0, abs(ref)))
+    print(f"{label}: worst scaled error {worst:.3e}")
+    if worst > tol:
+        sys.exit(f"{label} accuracy check failed")
+
+
 def main():
     ser = series_coeffs()
     nas = asym_terms_needed(XA)
@@ -318,10 +404,15 @@ def main():
     print(f"asymptotic terms: {nas}; worst scaled error {worst:.3e}")
     if worst > 4e-16:
         sys.exit("table accuracy check failed")
-    ser32, asy32, tab32, nas32 = table32()
+    asy32, nas32 = asym32()
     yk = yk_sets()
     yk_check(yk)
     yk32 = yk32_table()
+    hf = hf_table(HF_XF, HF_DEG)
+    hf_check(hf, asyd, HF_XF, hf_emulate, 4e-16, f"far FP64 set (quarter intervals to {HF_XF}, degree {HF_DEG})")
+    hf32 = hf_table(HF32_XF, HF32_DEG)
+    hf_check(hf32, asy32, HF32_XF, hf32_emulate, 4e-7,
+             f"far FP32 set (quarter intervals to {HF32_XF}, degree {HF32_DEG})")
     out = os.path.join(HERE, "hankel_table.inc")
     with open(out, "w") as fh:
         fh.write("// Generated by gen_hankel_table.py; do not edit.\n")
@@ -343,20 +434,10 @@ def main():
                 fh.write("  {" + ", ".join(repr(tabd[f][c][m]) for f in range(4)) + "},\n")
             fh.write(" },\n")
         fh.write("};\n")
-        fh.write(f"#define HK32_DEG {DEG32}\n#define HK32_NSER {NSER32}\n#define HK32_NASY {nas32}\n")
-        for nm, v in zip(("HK32_SER_J0", "HK32_SER_Y0", "HK32_SER_J1", "HK32_SER_Y1"), ser32):
-            fh.write(f"static constexpr float {nm}[{len(v)}] = {{" + ", ".join(repr(x) + "f" for x in
-                                                                            np.float32(v).tolist()) + "};\n")
+        fh.write(f"#define HK32_NASY {nas32}\n")
         for nm, v in zip(("HK32_ASY_P0", "HK32_ASY_Q0", "HK32_ASY_P1", "HK32_ASY_Q1"), asy32):
             fh.write(f"static constexpr float {nm}[{len(v)}] = {{" + ", ".join(repr(x) + "f" for x in
                                                                             np.float32(v).tolist()) + "};\n")
-        fh.write(f"static constexpr float HK32_TAB[{nint}][{DEG32 + 1}][4] = {{\n")
-        for c in range(nint):
-            fh.write(" {\n")
-            for m in range(DEG32 + 1):
-                fh.write("  {" + ", ".join(repr(float(np.float32(tab32[f][c][m]))) + "f" for f in range(4)) + "},\n")
-            fh.write(" },\n")
-        fh.write("};\n")
         ci0, ck0, ytab, yasy = yk
         fh.write(f"#define YK_XS {YK_XS}\n#define YK_XA {YK_XA}\n#define YK_NSER {YK_NSER}\n#define YK_NASY {len(yasy)}\n")
         fh.write("static constexpr double YK_SER_I0[%d] = {" % len(ci0) + ", ".join(repr(v) for v in ci0) + "};\n")
@@ -366,6 +447,19 @@ def main():
         fh.write(f"static constexpr double YK_TAB[{YK_XA - YK_XS}][{DEG + 1}] = {{\n")
         for cc in ytab:
             fh.write("  {" + ", ".join(repr(v) for v in cc) + "},\n")
+        fh.write("};\n")
+        fh.write(f"#define HF_XF {HF_XF}\n#define HF_DEG {HF_DEG}\n#define HF32_XF {HF32_XF}\n"
+                 f"#define HF32_DEG {HF32_DEG}\n#define HF_SMALL {HF_SMALL}\n")
+        fh.write("// [quarter interval c][coefficient of t^m][J0, Y0 (regular part for c < HF_SMALL), J1, Y1 (same)]\n")
+        fh.write(f"static constexpr double HF_TAB[{4 * HF_XF}][{HF_DEG + 1}][4] = {{\n")
+        for c in range(4 * HF_XF):
+            fh.write(" {" + ", ".join("{" + ", ".join(repr(hf[f][c][m]) for f in range(4)) + "}"
+                                      for m in range(HF_DEG + 1)) + "},\n")
+        fh.write("};\n")
+        fh.write(f"static constexpr float HF32_TAB[{4 * HF32_XF}][{HF32_DEG + 1}][4] = {{\n")
+        for c in range(4 * HF32_XF):
+            fh.write(" {" + ", ".join("{" + ", ".join(repr(float(np.float32(hf32[f][c][m]))) + "f" for f in range(4))
+                                      + "}" for m in range(HF32_DEG + 1)) + "},\n")
         fh.write("};\n")
         fh.write(f"#define YK32_DEG {YK32_DEG}\n")
         fh.write(f"// the same intervals for float32 evaluation (t and the sums in float32)\n")

@@ -133,7 +133,7 @@ __global__ void hankel_eval_kernel(const double* __restrict__ x, int64_t n,
                                    const double* __restrict__ tab, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Bessel01 b = hk_eval(x[i], tab);
+    const Bessel01 b = hf_eval(x[i], tab);
     out[4 * i + 0] = b.j0;
     out[4 * i + 1] = b.y0;
     out[4 * i + 2] = b.j1;
@@ -144,7 +144,7 @@ __global__ void hankel_eval_f32_kernel(const double* __restrict__ x, int64_t n, 
                                        float* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Bessel01f b = hk32_eval_hot(x[i], tab);
+    const Bessel01f b = hf32_eval(x[i], tab);
     out[4 * i + 0] = b.j0;
     out[4 * i + 1] = b.y0;
     out[4 * i + 2] = b.j1;
@@ -227,7 +227,7 @@ void launch_hankel_eval(Ctx& c, const double* x, int64_t n, double* out) {
     {
         KScope _ks(c, "hankel_eval");
         hipLaunchKernelGGL(hankel_eval_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
-                       c.hk_tab, out);
+                       c.hf_tab, out);
     }
     FDS_HIP_TRY(hipGetLastError());
 }
@@ -236,7 +236,7 @@ void launch_hankel_eval_f32(Ctx& c, const double* x, int64_t n, float* out) {
     {
         KScope _ks(c, "hankel_eval");
         hipLaunchKernelGGL(hankel_eval_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, c.stream, x, n,
-                           c.hk_tab32, out);
+                           c.hf_tab32, out);
     }
     FDS_HIP_TRY(hipGetLastError());
 }
