@@ -159,11 +159,31 @@ struct SturmStep {
     double lo1, go1, lo2, go2, ld1, gd1, ld2, gd2, xl, xg;
 };
 
-__global__ void sturm_steps_kernel(Pencil P, SturmStep* __restrict__ st) {
+// Entry k (0 <= k < K) of the table of the bottom-up recurrence: the coupling
+// E_k = diag(f(k), f(n-2-k)) to block k+1 and the diagonal block
+// D_k = [[m(k), x_k], [x_k, m(n-1-k)]] (x_0 = f(n-1), x_{K-1} = f(K-1) for an even
+// n, else 0), in the fields (lo1, go1), (lo2, go2), (ld1, gd1), (ld2, gd2), (xl, xg).
+__global__ void sturm_steps_kernel(Pencil P, SturmStep* __restrict__ st, SturmStep* __restrict__ sb) {
     const int n = P.n, K = n / 2;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K - 1) return;
     const bool odd = (n & 1) != 0;
+    if (k < K && k + 1 < n) {
+        SturmStep b;
+        b.lo1 = P.lo[k];
+        b.go1 = P.go[k];
+        b.lo2 = P.lo[n - 2 - k];
+        b.go2 = P.go[n - 2 - k];
+        b.ld1 = P.ld[k];
+        b.gd1 = P.gd[k];
+        b.ld2 = P.ld[n - 1 - k];
+        b.gd2 = P.gd[n - 1 - k];
+        const bool xk = k == 0 || (!odd && k == K - 1);
+        const int xo = k == 0 ? n - 1 : K - 1;
+        b.xl = xk ? P.lo[xo] : 0.0;
+        b.xg = xk ? P.go[xo] : 0.0;
+        sb[k] = b;
+    }
+    if (k >= K - 1) return;
     SturmStep t;
     t.lo1 = P.lo[k];
     t.go1 = P.go[k];
@@ -261,18 +281,122 @@ __device__ int pencil_count_scaled(const Pencil& P, const SturmStep* __restrict_
     return cnt;
 }
 
+// One step of the scaled block recurrence (top-down from block k to k+1, or
+// bottom-up from block k+1 to k with the bottom table): counts the inertia of the
+// current block B / s, then B <- det(B) D - s E adj(B) E, s <- det(B), rescaled by
+// a power of two when `rescale`.
+__device__ __forceinline__ void sturm_step(const SturmStep& t, double sig, bool rescale, double& b11, double& b22,
+                                           double& b12, double& sc, int& cnt) {
+    double det = fma(b11, b22, -b12 * b12);
+    det = det == 0.0 ? 1e-300 : det;
+    cnt += det < 0.0 ? 1 : ((b11 < 0.0) != (sc < 0.0) ? 2 : 0);
+    const double e1 = fma(-sig, t.go1, t.lo1), e2 = fma(-sig, t.go2, t.lo2);
+    const double m1 = fma(-sig, t.gd1, t.ld1), m2 = fma(-sig, t.gd2, t.ld2);
+    const double x = fma(-sig, t.xg, t.xl);
+    const double s1 = sc * e1, s2 = sc * e2;
+    const double n11 = fma(det, m1, -(s1 * e1) * b22);
+    const double n22 = fma(det, m2, -(s2 * e2) * b11);
+    const double n12 = fma(det, x, (s1 * e2) * b12);
+    if (rescale) {
+        const double f = inv_pow2_of(fmax(fmax(fabs(n11), fabs(n22)), fmax(fabs(n12), 1e-300)));
+        b11 = n11 * f;
+        b22 = n22 * f;
+        b12 = n12 * f;
+        sc = det * f;
+    } else {
+        b11 = n11;
+        b22 = n22;
+        b12 = n12;
+        sc = det;
+    }
+}
+
+// The same inertia count with the block elimination run from both ends at once
+// (Sylvester's law holds for any elimination order): blocks 0 .. M-1 top-down and
+// K-1 .. M+1 bottom-up (the middle node of an odd n first), two independent
+// chains per lane of half the length, then the meeting block
+// A_M + C_M - D_M (the Schur complements of both sides). sb: bottom table.
+__device__ int pencil_count_2e(const Pencil& P, const SturmStep* __restrict__ st, const SturmStep* __restrict__ sb,
+                               double sig, SturmStep* __restrict__ shT, SturmStep* __restrict__ shB) {
+    const int n = P.n;
+    const int K = n / 2;
+    const bool odd = (n & 1) != 0;
+    const int M = (K - 1) / 2;
+    const int LT = M, LB = K - 1 - M;   // LB = LT or LT + 1
+    double b11 = pm(P, 0, sig), b22 = pm(P, n - 1, sig), b12 = pf(P, n - 1, sig), sc = 1.0;
+    double c11, c22, c12, tc;
+    int cnt = 0;
+    if (odd) {
+        // the middle node K, coupled to nodes K-1 and K+1 of block K-1 by f(K-1), f(K)
+        double cm = pm(P, K, sig);
+        cm = cm == 0.0 ? 1e-300 : cm;
+        cnt += cm < 0.0 ? 1 : 0;
+        const double u1 = pf(P, K - 1, sig), u2 = pf(P, K, sig);
+        c11 = fma(cm, pm(P, K - 1, sig), -u1 * u1);
+        c22 = fma(cm, pm(P, K + 1, sig), -u2 * u2);
+        c12 = -u1 * u2;
+        tc = cm;
+    } else {
+        c11 = pm(P, K - 1, sig);
+        c22 = pm(P, K, sig);
+        c12 = pf(P, K - 1, sig);
+        tc = 1.0;
+    }
+    for (int j0 = 0; j0 < LB; j0 += BS_CHUNK) {
+        const int jend = min(LB, j0 + BS_CHUNK);
+        __syncthreads();
+        const int t = (int)threadIdx.x;
+        if (j0 + t < LT) shT[t] = st[j0 + t];
+        if (j0 + t < LB) shB[t] = sb[K - 2 - (j0 + t)];
+        __syncthreads();
+        // two steps of each chain per iteration with two coefficient sets, so that the
+        // LDS reads of the next steps overlap the arithmetic (no register copies)
+        SturmStep ta = shT[0], ba = shB[0];
+        for (int j = j0; j < jend; j += 2) {
+            const int l1 = min(j + 1, jend - 1) - j0;
+            const SturmStep tb = shT[l1], bb = shB[l1];
+            if (j < LT) sturm_step(ta, sig, (j & 3) == 3, b11, b22, b12, sc, cnt);
+            sturm_step(ba, sig, (j & 3) == 3, c11, c22, c12, tc, cnt);
+            const int l2 = min(j + 2, jend - 1) - j0;
+            ta = shT[l2];
+            ba = shB[l2];
+            if (j + 1 < jend) {
+                if (j + 1 < LT) sturm_step(tb, sig, ((j + 1) & 3) == 3, b11, b22, b12, sc, cnt);
+                sturm_step(bb, sig, ((j + 1) & 3) == 3, c11, c22, c12, tc, cnt);
+            }
+        }
+    }
+    // meeting block: A_M = B / s, C_M = C / t, both holding D_M once
+    const SturmStep d = sb[M];
+    const double is = 1.0 / sc, it = 1.0 / tc;
+    const double m1 = fma(-sig, d.gd1, d.ld1), m2 = fma(-sig, d.gd2, d.ld2), x = fma(-sig, d.xg, d.xl);
+    const double a11 = fma(b11, is, fma(c11, it, -m1));
+    const double a22 = fma(b22, is, fma(c22, it, -m2));
+    const double a12 = fma(b12, is, fma(c12, it, -x));
+    double det = fma(a11, a22, -a12 * a12);
+    det = det == 0.0 ? 1e-300 : det;
+    cnt += det < 0.0 ? 1 : (a11 < 0.0 ? 2 : 0);
+    return cnt;
+}
+
+// the two-ended count from this many node pairs on
+constexpr int BS_TWO_ENDED_K = 64;
+
 // One workgroup per eigenvalue index first + i. Each round evaluates 256 shifts
 // spread over [lo, hi] (endpoints included) and keeps the sub-interval that
 // holds the eigenvalue. The first round tries the caller's tight bracket
 // (lo0[i], hi0[i]) and falls back to the global bracket when its endpoint counts
 // do not enclose the index.
 __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, const SturmStep* __restrict__ st,
+                                                                      const SturmStep* __restrict__ sb,
                                                                       double l1c, double hfac, double glo,
                                                                       double ghi, double rtol, double atol,
                                                                       int first, int nw, double* __restrict__ lam) {
     __shared__ unsigned long long mk[BS_WAVES];
     __shared__ int flags[2];
     __shared__ SturmStep stsh[BS_CHUNK];
+    __shared__ SturmStep stsb[BS_CHUNK];
+    const bool two_ended = P.n / 2 >= BS_TWO_ENDED_K;
     const int i = blockIdx.x;
     if (i >= nw) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -303,7 +427,7 @@ __global__ __launch_bounds__(64 * BS_WAVES) void bisect_scaled_kernel(Pencil P, 
         const double w = hi - lo;
         if (w <= fmax(rtol * fmax(fabs(lo), fabs(hi)), atol)) break;
         const double s = tid == NS - 1 ? hi : lo + w * (double)tid / (double)(NS - 1);
-        const int cnt = pencil_count_scaled(P, st, s, stsh);
+        const int cnt = two_ended ? pencil_count_2e(P, st, sb, s, stsh, stsb) : pencil_count_scaled(P, st, s, stsh);
         const unsigned long long m = __ballot(cnt > idx);
         if (lane == 0) mk[wv] = m;
         if (tid == 0) flags[0] = cnt > idx;                 // eigenvalue below lo
@@ -1054,10 +1178,12 @@ static void eig_tables(Op& op, double*& Lb, double*& Gb, SturmStep*& dst) {
     }
     FDS_HIP_TRY(hipGetLastError());
     const int K = n / 2;
-    dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)std::max(K - 1, 1)));
+    // top-down steps [K - 1], then the bottom-up table [K]
+    dst = static_cast<SturmStep*>(c.dmalloc(sizeof(SturmStep) * (size_t)(std::max(K - 1, 1) + std::max(K, 1))));
     {
         KScope _ks(c, "filter_bisect");
-        hipLaunchKernelGGL(sturm_steps_kernel, dim3((K + 255) / 256), dim3(256), 0, c.stream, P, dst);
+        hipLaunchKernelGGL(sturm_steps_kernel, dim3((K + 255) / 256), dim3(256), 0, c.stream, P, dst,
+                           dst + std::max(K - 1, 1));
     }
     FDS_HIP_TRY(hipGetLastError());
 }
@@ -1067,7 +1193,9 @@ static void launch_bisect(Op& op, const EigSetup& e, const SturmStep* dst, int n
     Pencil P{op.l_diag, op.l_off, op.g_diag, op.g_off, (int)op.n};
     {
         KScope _ks(c, "filter_bisect");
-        hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst, e.l1c, e.hfac,
+        const int K = (int)op.n / 2;
+        hipLaunchKernelGGL(bisect_scaled_kernel, dim3(nw), dim3(64 * BS_WAVES), 0, c.stream, P, dst,
+                           dst + std::max(K - 1, 1), e.l1c, e.hfac,
                            -1e-3 * e.lam_hi, e.lam_hi, rtol, 4e-16 * e.lam_hi, e.start, nw, dlam);
     }
     FDS_HIP_TRY(hipGetLastError());
