@@ -16,9 +16,10 @@
 //   most kh along a panel; C_2 ~ 1.4e-2, C_3 ~ 1.9e-4, C_4 ~ 5e-8 for these
 //   kernels) and a part from the kernel's singularity at distance d that decays
 //   like (d/h)^{-2n} (Bernstein ellipse). Against a 20-point rule the thresholds
-//   below keep both at the rounding level of the arithmetic used:
-//     FP64 (<= ~1e-15 relative): 6 points for d >= 12 h and 5 for d >= 24 h
-//       (kh <= 0.2), 4 for d >= 64 h (kh <= 0.1), 3 for d >= 512 h (kh <= 0.016);
+//   below keep both at the rounding level of the arithmetic used (the onsets
+//   measured over random panel orientations, with margins of 1.5 to 2.5):
+//     FP64 (<= ~1e-15 relative): 6 points for d >= 6 h and 5 for d >= 12 h
+//       (kh <= 0.2), 4 for d >= 32 h (kh <= 0.1), 3 for d >= 200 h (kh <= 0.016);
 //     FP32 (<= ~1e-8, below its rounding): 4 points for d >= 6 h (kh <= 0.5),
 //       3 for d >= 16 h (kh <= 0.15), 2 for d >= 200 h (kh <= 0.025).
 //   One wavefront owns a 63 x 63 output tile: its 64 lanes hold the 64
@@ -94,14 +95,6 @@ __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
-}
-
-// g = (i/4) H0(kR) and c = (ik/4) H1(kR)/R at one point pair (FP64)
-__device__ __forceinline__ void far_kernel_values(double k, double R, const double* tab, double2& g, double2& c) {
-    const Bessel01 bs = hf_eval(k * R, tab);
-    g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
-    const double kr = 0.25 * k / R;
-    c = make_double2(-kr * bs.y1, kr * bs.j1);
 }
 
 // LDS copies shared by the workgroup: the Bessel table and the quadrature rules.
@@ -210,12 +203,121 @@ __device__ __forceinline__ void far_store(OT* __restrict__ oS, OT* __restrict__ 
     }
 }
 
+// FP64 far pass: b-sums of one row point, (S, D, T) x (psi_0, psi_1) of the column panel.
+struct Far64Sum {
+    double2 s0, s1, d0, d1, t0, t1;
+};
+struct Far64Blk {   // 2 x 2 blocks [alpha][beta] of S, D, T of a panel pair (without hp hq)
+    double2 S[2][2], D[2][2], T[2][2];
+};
+struct Far64Geo {
+    double k, k4;   // k, k/4
+    double nxp, nyp, nxq, nyq;
+};
+
+// One point pair: 1/R by the FP64 reciprocal square root refined by one Newton
+// step (a few ulp; R2 is a normal number for distinct points), so neither a square
+// root nor a division is needed: g = (i/4) H0(kR), c = (ik/4) H1(kR)/R.
+__device__ __forceinline__ void far64_point(double xa, double ya, double yb, double zb, double w0, double w1,
+                                            const Far64Geo& G, const double* tab, Far64Sum& A) {
+    const double dx = xa - yb, dy = ya - zb;
+    const double R2 = fma(dx, dx, dy * dy);
+    const double r0 = __builtin_amdgcn_rsq(R2);
+    const double ri = r0 * fma(-0.5 * R2, r0 * r0, 1.5);
+    const Bessel01 bs = hf_eval(G.k * (R2 * ri), tab);
+    const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
+    const double kr = G.k4 * ri;
+    const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
+    const double dq = fma(dx, G.nxq, dy * G.nyq);
+    const double dp = -fma(dx, G.nxp, dy * G.nyp);
+    const double2 cd = make_double2(c.x * dq, c.y * dq), ct = make_double2(c.x * dp, c.y * dp);
+    A.s0 = fma_cr(w0, g, A.s0);
+    A.s1 = fma_cr(w1, g, A.s1);
+    A.d0 = fma_cr(w0, cd, A.d0);
+    A.d1 = fma_cr(w1, cd, A.d1);
+    A.t0 = fma_cr(w0, ct, A.t0);
+    A.t1 = fma_cr(w1, ct, A.t1);
+}
+
+__device__ __forceinline__ void far64_fold(double wa0, double wa1, const Far64Sum& A, Far64Blk& B) {
+    B.S[0][0] = fma_cr(wa0, A.s0, B.S[0][0]); B.S[0][1] = fma_cr(wa0, A.s1, B.S[0][1]);
+    B.S[1][0] = fma_cr(wa1, A.s0, B.S[1][0]); B.S[1][1] = fma_cr(wa1, A.s1, B.S[1][1]);
+    B.D[0][0] = fma_cr(wa0, A.d0, B.D[0][0]); B.D[0][1] = fma_cr(wa0, A.d1, B.D[0][1]);
+    B.D[1][0] = fma_cr(wa1, A.d0, B.D[1][0]); B.D[1][1] = fma_cr(wa1, A.d1, B.D[1][1]);
+    B.T[0][0] = fma_cr(wa0, A.t0, B.T[0][0]); B.T[0][1] = fma_cr(wa0, A.t1, B.T[0][1]);
+    B.T[1][0] = fma_cr(wa1, A.t0, B.T[1][0]); B.T[1][1] = fma_cr(wa1, A.t1, B.T[1][1]);
+}
+
+// The 3-point rule on [0, 1]: xi = 1/2 -+ sqrt(3/20), 1/2; w = 5/18, 4/9, 5/18.
+constexpr double G3_X0 = 0.11270166537925831148;
+constexpr double G3_X2 = 0.88729833462074168852;
+constexpr double G3_W0 = 0.27777777777777777778;
+constexpr double G3_W1 = 0.44444444444444444444;
+
+// Adds the blocks of one far panel pair with the NO-point rule to B: NO = 3
+// (constants, fully unrolled; the column points in yq), 4, 5, 6 (points and
+// weights from the LDS rule table rl), 8 (the panels' stored Gauss points).
+template <int NO>
+__device__ __forceinline__ void far64_blocks(const FarParams& P, int p, int q, double px0, double py0, double pex,
+                                             double pey, double qx0, double qy0, double qex, double qey,
+                                             const double (&yq)[6], const Far64Geo& G, const double* tab,
+                                             const double* rl, const double* wsh, Far64Blk& B) {
+    const double2 z = make_double2(0.0, 0.0);
+    if constexpr (NO == 3) {
+        const double xs[3] = {G3_X0, 0.5, G3_X2};
+        const double w0s[3] = {G3_W0 * (1.0 - G3_X0), G3_W1 * 0.5, G3_W0 * (1.0 - G3_X2)};
+        const double w1s[3] = {G3_W0 * G3_X0, G3_W1 * 0.5, G3_W0 * G3_X2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xa = fma(xs[a], pex, px0), ya = fma(xs[a], pey, py0);
+            Far64Sum A = {z, z, z, z, z, z};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) far64_point(xa, ya, yq[2 * b], yq[2 * b + 1], w0s[b], w1s[b], G, tab, A);
+            far64_fold(w0s[a], w1s[a], A, B);
+        }
+    } else {
+        const double* rx = rl + low_rule_offset(NO < 8 ? NO : 2);
+#pragma unroll 1
+        for (int a = 0; a < NO; ++a) {
+            double xa, ya, wa0, wa1;
+            if constexpr (NO == 8) {
+                xa = P.gx[8 * p + a];
+                ya = P.gy[8 * p + a];
+                wa0 = wsh[a];
+                wa1 = wsh[8 + a];
+            } else {
+                xa = fma(rx[a], pex, px0);
+                ya = fma(rx[a], pey, py0);
+                wa0 = rx[NO + a];
+                wa1 = rx[2 * NO + a];
+            }
+            Far64Sum A = {z, z, z, z, z, z};
+#pragma unroll 1
+            for (int b = 0; b < NO; ++b) {
+                double yb, zb, w0, w1;
+                if constexpr (NO == 8) {
+                    yb = P.gx[8 * q + b];
+                    zb = P.gy[8 * q + b];
+                    w0 = wsh[b];
+                    w1 = wsh[8 + b];
+                } else {
+                    yb = fma(rx[b], qex, qx0);
+                    zb = fma(rx[b], qey, qy0);
+                    w0 = rx[NO + b];
+                    w1 = rx[2 * NO + b];
+                }
+                far64_point(xa, ya, yb, zb, w0, w1, G, tab, A);
+            }
+            far64_fold(wa0, wa1, A, B);
+        }
+    }
+}
+
 // One work item (nsub-th of a 63 x 63 tile) of an FP64 operator, executed by one
 // wavefront.
 __device__ __forceinline__ void far_work_item64(const FarParams& P, int64_t work, FarShared64& sh) {
     typedef double2 CT;
     const double* tab = reinterpret_cast<const double*>(sh.tab);
-    const double* wsh = sh.wsh;
     const int lane = threadIdx.x & 63;
     const FarTile T = far_tile(P, work);
     const int i0 = T.i0, i1 = T.i1, j0 = T.j0;
@@ -231,8 +333,6 @@ __device__ __forceinline__ void far_work_item64(const FarParams& P, int64_t work
     const int col = j0 + lane;
     const bool writes = (lane < TB) && (col < n);
 
-    const double* __restrict__ qgx = P.gx + 8 * q;
-    const double* __restrict__ qgy = P.gy + 8 * q;
     const double hq = P.h[q], nxq = P.nx[q], nyq = P.ny[q];
     const double k = P.k;
     // panel q as node + t * edge (for the reduced rules) and its midpoint
@@ -240,6 +340,8 @@ __device__ __forceinline__ void far_work_item64(const FarParams& P, int64_t work
     const double qx0 = P.nodes[2 * q], qy0 = P.nodes[2 * q + 1];
     const double qex = P.nodes[2 * q1] - qx0, qey = P.nodes[2 * q1 + 1] - qy0;
     const double qcx = qx0 + 0.5 * qex, qcy = qy0 + 0.5 * qey;
+    const double yq[6] = {fma(G3_X0, qex, qx0), fma(G3_X0, qey, qy0), qcx, qcy, fma(G3_X2, qex, qx0),
+                          fma(G3_X2, qey, qy0)};
 
     const CT z = CT{0, 0};
     CT pS0 = z, pS1 = z, pN0 = z, pN1 = z, pD0 = z, pD1 = z, pT0 = z, pT1 = z;
@@ -252,87 +354,56 @@ __device__ __forceinline__ void far_work_item64(const FarParams& P, int64_t work
         dd = dd < 0 ? -dd : dd;
         const int cd = dd < n - dd ? dd : n - dd;
         const bool active = qvalid && cd > 1;
-        CT S00 = z, S01 = z, S10 = z, S11 = z;
-        CT D00 = z, D01 = z, D10 = z, D11 = z;
-        CT T00 = z, T01 = z, T10 = z, T11 = z;
         const double hp = P.h[p], nxp = P.nx[p], nyp = P.ny[p];
         const int p1 = p + 1 == n ? 0 : p + 1;
         const double px0 = P.nodes[2 * p], py0 = P.nodes[2 * p + 1];
         const double pex = P.nodes[2 * p1] - px0, pey = P.nodes[2 * p1 + 1] - py0;
-        // quadrature order for this row panel, uniform over the wavefront
-        int ord = 0;
+        // quadrature order for this row panel, uniform over the wavefront (the largest
+        // any lane needs); gap = |midpoint distance| - (hp + hq)/2 against multiples of
+        // hm = max(hp, hq), compared squared
+        const float mx = (float)(px0 + 0.5 * pex - qcx), my = (float)(py0 + 0.5 * pey - qcy);
+        const float m2 = fmaf(mx, mx, my * my);
+        const float hmf = (float)fmax(hp, hq), hsf = (float)(0.5 * (hp + hq)), kh = (float)k * hmf;
+        const float e3 = fmaf(200.0f, hmf, hsf), e4 = fmaf(32.0f, hmf, hsf);
+        const float e5 = fmaf(12.0f, hmf, hsf), e6 = fmaf(6.0f, hmf, hsf);
+        const bool over3 = active && !(kh <= 0.016f && m2 >= e3 * e3);
+        const bool over4 = active && !(kh <= 0.1f && m2 >= e4 * e4);
+        const bool over5 = active && !(kh <= 0.2f && m2 >= e5 * e5);
+        const bool over6 = active && !(kh <= 0.2f && m2 >= e6 * e6);
+        const int ord = __ballot(over6) ? 8 : (__ballot(over5) ? 6 : (__ballot(over4) ? 5 : (__ballot(over3) ? 4 : 3)));
+        Far64Blk B;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) B.S[a][b] = B.D[a][b] = B.T[a][b] = z;
+        CT I0h = z;   // sum of the four S blocks divided by hp hq (the Maue term)
         if (active) {
-            const double hm = fmax(hp, hq);
-            const double dist = hypot(px0 + 0.5 * pex - qcx, py0 + 0.5 * pey - qcy) - 0.5 * (hp + hq);
-            const double kh = k * hm;
-            ord = 8;
-            if (kh <= 0.2 && dist >= 12.0 * hm) ord = 6;
-            if (kh <= 0.2 && dist >= 24.0 * hm) ord = 5;
-            if (kh <= 0.1 && dist >= 64.0 * hm) ord = 4;
-            if (kh <= 0.016 && dist >= 512.0 * hm) ord = 3;
-        }
-        ord = wave_max_int(ord);
-        if (active) {
-            const int no = ord;
-            const double* rx = sh.rl + low_rule_offset(no < 8 ? no : 2);
-#pragma unroll 1
-            for (int a = 0; a < no; ++a) {
-                double xa, ya, wa0, wa1;
-                if (no == 8) {
-                    xa = P.gx[8 * p + a];
-                    ya = P.gy[8 * p + a];
-                    wa0 = wsh[a];
-                    wa1 = wsh[8 + a];
-                } else {
-                    xa = px0 + rx[a] * pex;
-                    ya = py0 + rx[a] * pey;
-                    wa0 = rx[no + a];
-                    wa1 = rx[2 * no + a];
-                }
-                CT Sg0 = z, Sg1 = z, Dg0 = z, Dg1 = z, Tg0 = z, Tg1 = z;
-#pragma unroll 1
-                for (int b = 0; b < no; ++b) {
-                    double yb, zb, w0, w1;
-                    if (no == 8) {
-                        yb = qgx[b];
-                        zb = qgy[b];
-                        w0 = wsh[b];
-                        w1 = wsh[8 + b];
-                    } else {
-                        yb = qx0 + rx[b] * qex;
-                        zb = qy0 + rx[b] * qey;
-                        w0 = rx[no + b];
-                        w1 = rx[2 * no + b];
-                    }
-                    const double dx = xa - yb, dy = ya - zb;
-                    const double R = sqrt(fma(dx, dx, dy * dy));
-                    CT g, c;
-                    far_kernel_values(k, R, tab, g, c);
-                    const double dq = fma(dx, nxq, dy * nyq);
-                    const double dp = -fma(dx, nxp, dy * nyp);
-                    const CT cd = CT{c.x * dq, c.y * dq}, ct = CT{c.x * dp, c.y * dp};
-                    Sg0 = fma_cr(w0, g, Sg0);
-                    Sg1 = fma_cr(w1, g, Sg1);
-                    Dg0 = fma_cr(w0, cd, Dg0);
-                    Dg1 = fma_cr(w1, cd, Dg1);
-                    Tg0 = fma_cr(w0, ct, Tg0);
-                    Tg1 = fma_cr(w1, ct, Tg1);
-                }
-                S00 = fma_cr(wa0, Sg0, S00); S01 = fma_cr(wa0, Sg1, S01);
-                S10 = fma_cr(wa1, Sg0, S10); S11 = fma_cr(wa1, Sg1, S11);
-                D00 = fma_cr(wa0, Dg0, D00); D01 = fma_cr(wa0, Dg1, D01);
-                D10 = fma_cr(wa1, Dg0, D10); D11 = fma_cr(wa1, Dg1, D11);
-                T00 = fma_cr(wa0, Tg0, T00); T01 = fma_cr(wa0, Tg1, T01);
-                T10 = fma_cr(wa1, Tg0, T10); T11 = fma_cr(wa1, Tg1, T11);
-            }
+            const Far64Geo G{k, 0.25 * k, nxp, nyp, nxq, nyq};
+            if (ord == 3)
+                far64_blocks<3>(P, p, q, px0, py0, pex, pey, qx0, qy0, qex, qey, yq, G, tab, sh.rl, sh.wsh, B);
+            else if (ord == 4)
+                far64_blocks<4>(P, p, q, px0, py0, pex, pey, qx0, qy0, qex, qey, yq, G, tab, sh.rl, sh.wsh, B);
+            else if (ord == 5)
+                far64_blocks<5>(P, p, q, px0, py0, pex, pey, qx0, qy0, qex, qey, yq, G, tab, sh.rl, sh.wsh, B);
+            else if (ord == 6)
+                far64_blocks<6>(P, p, q, px0, py0, pex, pey, qx0, qy0, qex, qey, yq, G, tab, sh.rl, sh.wsh, B);
+            else
+                far64_blocks<8>(P, p, q, px0, py0, pex, pey, qx0, qy0, qex, qey, yq, G, tab, sh.rl, sh.wsh, B);
+            I0h = cadd(cadd(B.S[0][0], B.S[0][1]), cadd(B.S[1][0], B.S[1][1]));
             const double hh = hp * hq;
-            S00 = cscale(S00, hh); S01 = cscale(S01, hh); S10 = cscale(S10, hh); S11 = cscale(S11, hh);
-            D00 = cscale(D00, hh); D01 = cscale(D01, hh); D10 = cscale(D10, hh); D11 = cscale(D11, hh);
-            T00 = cscale(T00, hh); T01 = cscale(T01, hh); T10 = cscale(T10, hh); T11 = cscale(T11, hh);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    B.S[a][b] = cscale(B.S[a][b], hh);
+                    B.D[a][b] = cscale(B.D[a][b], hh);
+                    B.T[a][b] = cscale(B.T[a][b], hh);
+                }
         }
+        const CT S00 = B.S[0][0], S01 = B.S[0][1], S10 = B.S[1][0], S11 = B.S[1][1];
+        const CT D00 = B.D[0][0], D01 = B.D[0][1], D10 = B.D[1][0], D11 = B.D[1][1];
+        const CT T00 = B.T[0][0], T01 = B.T[0][1], T10 = B.T[1][0], T11 = B.T[1][1];
         // Maue form of N from S: N_ab = s_a s_b I0/(hp hq) - k^2 (np.nq) S_ab
-        const CT I0 = cadd(cadd(S00, S01), cadd(S10, S11));
-        const CT I0h = cscale(I0, 1.0 / (hp * hq));
         const double kk = -k * k * fma(nxp, nxq, nyp * nyq);
         const CT N00 = cadd(I0h, cscale(S00, kk));
         const CT N01 = csub(cscale(S01, kk), I0h);
@@ -762,10 +833,12 @@ __global__ __launch_bounds__(64 * WAVES) void asm_nband_blocks_kernel(NBandParam
                 w1 = rx[2 * no + b];
             }
             const double dx = xa - yb, dy = ya - zb;
-            const double R = sqrt(fma(dx, dx, dy * dy));
-            const Bessel01 bs = hf_eval(k * R, tab);
+            const double R2 = fma(dx, dx, dy * dy);
+            const double r0 = __builtin_amdgcn_rsq(R2);
+            const double ri = r0 * fma(-0.5 * R2, r0 * r0, 1.5);
+            const Bessel01 bs = hf_eval(k * (R2 * ri), tab);
             const double2 g = make_double2(-0.25 * bs.y0, 0.25 * bs.j0);
-            const double kr = 0.25 * k / R;
+            const double kr = 0.25 * k * ri;
             const double2 c = make_double2(-kr * bs.y1, kr * bs.j1);
             const double dq = fma(dx, nxq, dy * nyq), dp = -fma(dx, nxp, dy * nyp);
             const double2 cd = cscale(c, dq), ct = cscale(c, dp);
