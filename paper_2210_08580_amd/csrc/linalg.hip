@@ -662,65 +662,120 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double2* __restrict
     }
 }
 
-// Panel of the unpivoted variant: F = A_pp^{-1} by Gauss-Jordan on [A_pp | I]
-// (A_pp the current nb x nb diagonal block, no row interchanges), the row order
-// the identity, W[i] = F[i - j0] - e_{i - j0} on the pivot rows and -M[i] F
-// (panel columns) on every other row.
-__global__ __launch_bounds__(256) void gj_nopiv_panel_kernel(const double2* __restrict__ M, int r, int j0, int nb,
-                                                             int* __restrict__ perm, double2* __restrict__ W,
-                                                             double* __restrict__ pabs) {
+// One panel of the unpivoted variant in a single launch: every workgroup inverts
+// the nb x nb diagonal block itself (Gauss-Jordan on [A_pp | I] in LDS, no row
+// interchanges; F = A_pp^{-1}), forms the row multipliers of its 64 rows
+// (W[i] = F[i - j0] - e_{i - j0} on the pivot rows, -M[i] F on the others; the
+// panel columns of M read once) and applies them to its 16 columns:
+// Mout[i][c] = M[i][c] + sum_b W[i][b] M[j0 + b][c] (columns left of j0 + nb become
+// unit vectors). Workgroup (0, 0) also records the pivot magnitudes.
+__global__ __launch_bounds__(256) void gj_nopiv_step_kernel(const double2* __restrict__ M, double2* __restrict__ Mout,
+                                                            int r, int j0, int nb, double* __restrict__ pabs) {
     __shared__ double2 F[GJ_NB][2 * GJ_NB];
-    __shared__ double2 fa[GJ_NB];
     __shared__ double spiv[GJ_NB];
+    __shared__ double2 Ws[64][GJ_NB + 1];
+    __shared__ double2 Xp[GJ_NB][16];
     const int tid = threadIdx.x;
-    for (int t = tid; t < nb * 2 * nb; t += blockDim.x) {
-        const int a = t / (2 * nb), b = t % (2 * nb);
-        F[a][b] = b < nb ? M[j0 + a + (int64_t)(j0 + b) * r] : make_double2(b - nb == a ? 1.0 : 0.0, 0.0);
+    const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 16;
+    for (int t = tid; t < nb * 16; t += blockDim.x) {
+        const int b = t / 16, cc = t % 16, c = c0 + cc;
+        Xp[b][cc] = c < 2 * r ? M[j0 + b + (int64_t)c * r] : make_double2(0.0, 0.0);
+    }
+    // Gauss-Jordan on [A_pp | I] by the first wavefront with the rows in registers:
+    // lane 4 i + q holds entries 8 q .. 8 q + 7 of row i (columns past 2 nb are zero);
+    // the scaled pivot row is passed through LDS, the pivot-column entries of the
+    // other rows by shuffles within each group of four lanes
+    if (tid < 64) {
+        const int i = tid >> 2, q = tid & 3;
+        double2 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = 8 * q + u;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < nb && b < nb) v = M[j0 + i + (int64_t)(j0 + b) * r];
+            else if (i < nb && b < 2 * nb) v = make_double2(b - nb == i ? 1.0 : 0.0, 0.0);
+            x[u] = v;
+        }
+        for (int a = 0; a < nb; ++a) {
+            // F[i][a] of this lane's row, from lane 4 i + a / 8 (register a % 8)
+            double2 own = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u == (a & 7)) own = x[u];
+            const int src = (tid & ~3) | (a >> 3);
+            const double2 fi = make_double2(__shfl(own.x, src, 64), __shfl(own.y, src, 64));
+            if (i == a) {
+                const double den = fi.x * fi.x + fi.y * fi.y;
+                double rd = 0.0;
+                if (den > 0.0) {
+                    rd = __builtin_amdgcn_rcp(den);
+                    rd = fma(rd, fma(-den, rd, 1.0), rd);
+                    rd = fma(rd, fma(-den, rd, 1.0), rd);
+                }
+                const double2 pinv = make_double2(fi.x * rd, -fi.y * rd);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = cmul(x[u], pinv);
+                    F[0][8 * q + u] = x[u];   // F[0] doubles as the pivot-row buffer here
+                }
+                if (q == 0) spiv[a] = den;
+            }
+            wave_sync();
+            if (i != a) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = csub(x[u], cmul(fi, F[0][8 * q + u]));
+            }
+            wave_sync();
+        }
+        // the pivot-row buffer has been read by every lane (last wave_sync above); only
+        // this wavefront touches F before the barrier below
+        if (i < nb) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) F[i][8 * q + u] = x[u];
+        }
     }
     __syncthreads();
-    for (int a = 0; a < nb; ++a) {
-        const double2 pv = F[a][a];
-        const double den = pv.x * pv.x + pv.y * pv.y;
-        const double2 pinv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0.0, 0.0);
-        if (tid == 0) spiv[a] = den;
-        if (tid < nb) fa[tid] = F[tid][a];
-        __syncthreads();
-        if (tid < 2 * nb) F[a][tid] = cmul(F[a][tid], pinv);
-        __syncthreads();
-        for (int t = tid; t < nb * 2 * nb; t += blockDim.x) {
-            const int i = t / (2 * nb), b = t % (2 * nb);
-            if (i != a) F[i][b] = csub(F[i][b], cmul(fa[i], F[a][b]));
-        }
-        __syncthreads();
-    }
-    if (tid < nb) pabs[j0 + tid] = sqrt(spiv[tid]);
-    for (int i = tid; i < r; i += blockDim.x) {
-        perm[i] = i;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid < nb) pabs[j0 + tid] = sqrt(spiv[tid]);
+    // multipliers of row i = i0 + (tid & 63), columns b = 4 (tid >> 6) .. + 3
+    {
+        const int li = tid & 63, i = i0 + li, bq = 4 * (tid >> 6);
         const bool piv = i >= j0 && i < j0 + nb;
-        const int ip = piv ? i - j0 : 0;
-        double2 ma[GJ_NB], acc[GJ_NB];
+        double2 acc[4];
 #pragma unroll
-        for (int a = 0; a < GJ_NB; ++a) {
-            const double2 v = M[i + (int64_t)(j0 + min(a, nb - 1)) * r];
-            ma[a] = (a < nb && !piv) ? v : make_double2(0.0, 0.0);
+        for (int u = 0; u < 4; ++u) {
+            const int b = bq + u;
+            const double2 fb = (piv && b < nb) ? F[i - j0][nb + b] : make_double2(0.0, 0.0);
+            acc[u] = make_double2(fb.x - (piv && b == i - j0 ? 1.0 : 0.0), fb.y);
+        }
+        if (!piv && i < r) {
+#pragma unroll 4
+            for (int a = 0; a < nb; ++a) {
+                const double2 m0 = M[i + (int64_t)(j0 + a) * r];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (bq + u < nb) acc[u] = csub(acc[u], cmul(m0, F[a][nb + bq + u]));
+            }
         }
 #pragma unroll
-        for (int b = 0; b < GJ_NB; ++b) {
-            const double2 fb = F[ip][(nb + b) & (2 * GJ_NB - 1)];
-            acc[b] = piv ? make_double2(fb.x - (b == ip ? 1.0 : 0.0), fb.y) : make_double2(0.0, 0.0);
+        for (int u = 0; u < 4; ++u) Ws[li][bq + u] = acc[u];
+    }
+    __syncthreads();
+    const int li = tid & 63, i = i0 + li;
+    if (i >= r) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int cc = (tid >> 6) + 4 * q, c = c0 + cc;
+        if (c >= 2 * r) continue;
+        double2 v;
+        if (c < j0 + nb) {
+            v = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        } else {
+            v = M[i + (int64_t)c * r];
+#pragma unroll
+            for (int b = 0; b < GJ_NB; ++b)
+                if (b < nb) v = cadd(v, cmul(Ws[li][b], Xp[b][cc]));
         }
-        // ma[0] is consumed and the rest rotated down (static register indices)
-#pragma unroll 1
-        for (int a = 0; a < nb; ++a) {
-            const double2 m0 = ma[0];
-#pragma unroll
-            for (int q = 0; q + 1 < GJ_NB; ++q) ma[q] = ma[q + 1];
-#pragma unroll
-            for (int b = 0; b < GJ_NB; ++b) acc[b] = csub(acc[b], cmul(m0, F[a][(nb + b) & (2 * GJ_NB - 1)]));
-        }
-#pragma unroll
-        for (int b = 0; b < GJ_NB; ++b)
-            if (b < nb) W[i + (int64_t)b * r] = acc[b];
+        Mout[i + (int64_t)c * r] = v;
     }
 }
 
@@ -888,8 +943,7 @@ void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* hstats) {
         hipLaunchKernelGGL(gj_init_kernel, dim3(nblk), dim3(256), 0, c.stream, A, M0, r, bmax);
         for (int j0 = 0; j0 < r;) {
             const int nb = std::min(GJ_NB, r - j0);
-            hipLaunchKernelGGL(gj_nopiv_panel_kernel, dim3(1), dim3(256), 0, c.stream, in, r, j0, nb, perm, W, pabs);
-            hipLaunchKernelGGL(gj_update_kernel, ugrid, dim3(256), 0, c.stream, in, out, r, j0, nb, perm, W);
+            hipLaunchKernelGGL(gj_nopiv_step_kernel, ugrid, dim3(256), 0, c.stream, in, out, r, j0, nb, pabs);
             std::swap(in, out);
             j0 += nb;
         }
