@@ -1070,7 +1070,9 @@ static FarParams far_params(Op& op) {
     fp.n = n;
     fp.bw = f32 ? op.nbw : -1;
     const int64_t T = (n + TB - 1) / TB;
-    fp.nsub = 2;
+    // work items per tile: a quarter tile in FP64 (better balance of the higher orders
+    // near the diagonal over the wavefronts), half a tile in FP32
+    fp.nsub = f32 ? 2 : 4;
     fp.tr = (TB + fp.nsub - 1) / fp.nsub;
     fp.nwork = T * (T + 1) / 2 * fp.nsub;
     return fp;
