@@ -9,8 +9,10 @@
 // tridiagonal L - sigma G is reordered as a block tridiagonal matrix of 2x2
 // blocks by pairing node k with node n-1-k; the block LDL^T recurrence
 // A_{k+1} = D_{k+1} - E_k A_k^{-1} E_k then gives the count of negative
-// eigenvalues as the sum over blocks. One workgroup of four wavefronts refines
-// one eigenvalue, its 256 lanes evaluating 256 shifts per round (multisection).
+// eigenvalues as the sum over blocks; it runs from both ends of the block
+// sequence at once (two chains of half the length per lane, then the meeting
+// block). One workgroup of four wavefronts refines one eigenvalue, its 256 lanes
+// evaluating 256 shifts per round (multisection).
 // Eigenvectors: inverse iteration (L - lambda G) x_new = G x_old with a banded
 // LU with partial pivoting of the same folded ordering (bandwidth 2), run from
 // both ends of the band at once (one thread per eigenvalue and half, a 4 x 4
