@@ -259,7 +259,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int k, T alpha,
 constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
 
 // TB = double: a real B operand (two real MFMAs per complex-by-real tile step).
-template <typename TA, typename TB, int OPA, int OPB>
+// WN = 2: 128 x 64 tile, 2 x 2 wavefronts of 64 x 32; WN = 1 (narrow outputs of at
+// most 32 columns): 128 x 32 tile, 4 x 1 wavefronts of 32 x 32.
+template <typename TA, typename TB, int OPA, int OPB, int WN = 2>
 __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, double2 alpha,
                                                        const TA* __restrict__ A, int64_t lda,
                                                        const TB* __restrict__ B, int64_t ldb, double2 beta,
@@ -267,22 +269,26 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                                                        double2* __restrict__ part, BandA bd) {
     constexpr bool BCPLX = std::is_same<TB, double2>::value;
     constexpr bool GAUSS3 = BCPLX && OPA == OP_N;   // transposed-A loads leave no registers for a third product
+    constexpr int BN = 32 * WN;             // tile columns
+    constexpr int WM = 4 / WN;              // wavefronts along the rows
+    constexpr int RT = BB_M / (16 * WM);    // 16-row MFMA tiles per wavefront
+    constexpr int EB = BB_K * BN / 256;     // B elements staged per thread and slice
     // two LDS buffers: slice i is multiplied from one while slice i + 1 is staged into the other
     __shared__ double2 sA[2][BB_K][BB_M + BB_PAD];
-    __shared__ TB sB[2][BB_K][BB_N + BB_PAD];
+    __shared__ TB sB[2][BB_K][BN + BB_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;
-    const int row0 = blockIdx.x * BB_M, col0 = blockIdx.y * BB_N;
+    const int wm = w % WM, wn = w / WM;
+    const int row0 = blockIdx.x * BB_M, col0 = blockIdx.y * BN;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(k, kbeg + kchunk);
     // complex B and untransposed A: Gauss's three products per tile, T1 = ar br,
     // T2 = ai bi, T3 = (ar + ai)(br + bi); Re = T1 - T2, Im = T3 - T1 - T2 (the sums
     // are formed after the LDS reads). Other complex cases: four products. Real B:
     // accR = ar b, accI = ai b.
-    d4 accR[4][2], accI[4][2], acc3[4][2];
+    d4 accR[RT][2], accI[RT][2], acc3[RT][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             accR[a][b] = d4{0.0, 0.0, 0.0, 0.0};
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
     // raw operands in flight (complex64 A is widened when staged to LDS, so the
     // loads of the next slice are not waited on while the current one computes)
     TA ra[8];
-    TB rb[4];
+    TB rb[EB];
     auto loadAB = [&](int kk) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -310,14 +316,14 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             ra[e] = v;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < EB; ++e) {
             int j, p;
             if (OPB == OP_N) {
                 p = tid & 15;
                 j = (tid >> 4) + 16 * e;
             } else {
-                j = tid & 63;
-                p = (tid >> 6) + 4 * e;
+                j = tid % BN;
+                p = tid / BN + (256 / BN) * e;
             }
             const int gj = col0 + j, gp = kk + p;
             TB v{};
@@ -353,9 +359,9 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             sA[buf][p][i] = v;
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < EB; ++e) {
             if (OPB == OP_N) sB[buf][tid & 15][(tid >> 4) + 16 * e] = rb[e];
-            else sB[buf][(tid >> 6) + 4 * e][tid & 63] = rb[e];
+            else sB[buf][tid / BN + (256 / BN) * e][tid % BN] = rb[e];
         }
     };
     auto compute = [&](int buf) {
@@ -365,20 +371,20 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
 #pragma unroll 2
         for (int kc = 0; kc < BB_K / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
-            double2 a[4];
+            double2 a[RT];
             TB b[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = sA[buf][pr][wm * 64 + r * 16 + (lane & 15)];
+            for (int r = 0; r < RT; ++r) a[r] = sA[buf][pr][wm * (16 * RT) + r * 16 + (lane & 15)];
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = sB[buf][pr][wn * 32 + c * 16 + (lane & 15)];
             if constexpr (GAUSS3) {
-                double as[4], bs[2];
+                double as[RT], bs[2];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) as[r] = a[r].x + a[r].y;
+                for (int r = 0; r < RT; ++r) as[r] = a[r].x + a[r].y;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < RT; ++r)
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                     }
             } else if constexpr (BCPLX) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < RT; ++r)
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         accR[r][c] = mfma16(a[r].x, b[c].x, accR[r][c]);
@@ -397,7 +403,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
                     }
             } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < RT; ++r)
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         accR[r][c] = mfma16(a[r].x, b[c], accR[r][c]);
@@ -425,12 +431,12 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
         buf ^= 1;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gi = row0 + wm * 64 + r * 16 + acc_row(0.0, lane, v);
+                const int gi = row0 + wm * (16 * RT) + r * 16 + acc_row(0.0, lane, v);
                 const int gj = col0 + wn * 32 + c * 16 + (lane & 15);
                 if (gi >= m || gj >= n) continue;
                 const double2 acc = GAUSS3 ? make_double2(accR[r][c][v] - accI[r][c][v],
@@ -514,14 +520,19 @@ static int choose_config(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, 
         return std::min(nz, 64);
     };
     const bool bigp = big_ok<T, TA>() && m >= BB_M && n >= BB_N;
+    // outputs of at most 32 columns: the 128 x 32 tile (a 64 x 64 tile would leave half
+    // of its wavefronts without columns)
+    const bool narrowp = big_ok<T, TA>() && m >= BB_M && n <= 32;
     int cfg;
     if (bigp) {
         const int tb = ((m + BB_M - 1) / BB_M) * ((n + BB_N - 1) / BB_N);
         cfg = 256 | split_for(4 * tb);
+    } else if (narrowp) {
+        cfg = 512 | split_for(4 * ((m + BB_M - 1) / BB_M));
     } else {
         cfg = split_for(((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N));
     }
-    if (c.split_hint > 0) return (cfg & 256) | std::min(std::max(cfg & 255, c.split_hint), 64);
+    if (c.split_hint > 0) return (cfg & 768) | std::min(std::max(cfg & 255, c.split_hint), 64);
     if (!c.autotune || c.noalloc) return cfg;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return cfg;
@@ -531,14 +542,14 @@ static int choose_config(Ctx& c, int m, int n, int k, const TA* A, int64_t lda, 
     auto it = c.tuned.find(key);
     if (it != c.tuned.end()) return it->second;
     std::vector<int> cand;
-    for (int big = 0; big <= (bigp ? 1 : 0); ++big) {
-        const int tiles = big ? ((m + BB_M - 1) / BB_M) * ((n + BB_N - 1) / BB_N)
+    for (int big = 0; big <= (bigp || narrowp ? 1 : 0); ++big) {
+        const int tiles = big ? ((m + BB_M - 1) / BB_M) * (narrowp ? 1 : (n + BB_N - 1) / BB_N)
                               : ((m + GB_M - 1) / GB_M) * ((n + GB_N - 1) / GB_N);
         for (int z = 1; z <= 64; z *= 2) {
             if (z > 1 && ((int64_t)z * 2 * GB_K > k || (int64_t)z * m * n * sizeof(T) > ((int64_t)1 << 29) ||
                           (int64_t)tiles * z > 8192))
                 continue;
-            cand.push_back((big ? 256 : 0) | z);
+            cand.push_back((big ? (narrowp ? 512 : 256) : 0) | z);
         }
     }
     T* scratch = static_cast<T*>(c.dmalloc(sizeof(T) * (size_t)m * n));
@@ -584,7 +595,8 @@ template <typename T, typename TA, int OPA, int OPB>
 static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64_t lda, const T* B, int64_t ldb,
                         T beta, T* C, int64_t ldc, int cfg, const BandA& bd) {
     const bool big = big_ok<T, TA>() && (cfg & 256);
-    const int bm = big ? BB_M : GB_M, bn = big ? BB_N : GB_N;
+    const bool narrow = big_ok<T, TA>() && (cfg & 512);
+    const int bm = big || narrow ? BB_M : GB_M, bn = narrow ? 32 : (big ? BB_N : GB_N);
     const int gm = (m + bm - 1) / bm, gn = (n + bn - 1) / bn;
     int nz = std::max(1, cfg & 255);
     if (c.noalloc && nz > 1) {   // the partial sums must fit the caller's workspace
@@ -600,7 +612,10 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
     {
         KScope _ks(c, c.gemm_tag ? c.gemm_tag : (std::is_same<T, float2>::value ? "gemm_c64" : "gemm"));
         if constexpr (big_ok<T, TA>()) {
-            if (big) {
+            if (narrow) {
+                hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB, 1>), dim3(gm, gn, nz), dim3(256), 0, c.stream,
+                                   m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
+            } else if (big) {
                 hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n, k,
                                    alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
             } else {

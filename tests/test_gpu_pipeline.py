@@ -29,7 +29,9 @@ def _crand(rs, shape):
 
 @pytest.mark.parametrize("opa,opb", [(a, b) for a in range(3) for b in range(3)])
 @pytest.mark.parametrize("m,n,k", [(70, 33, 129), (40, 40, 5000), (1, 65, 17), (128, 64, 64), (300, 200, 700),
-                                   (257, 130, 3000)])
+                                   (257, 130, 3000),
+                                   # outputs of at most 32 columns (the 128 x 32 tile), ragged rows
+                                   (300, 32, 700), (129, 1, 513), (257, 17, 3000)])
 def test_zgemm_parity(ctx, opa, opb, m, n, k):
     _say(f"case: zgemm op=({opa},{opb}) m={m} n={n} k={k}")
     rs = np.random.default_rng(m * 7 + n * 3 + k + opa * 11 + opb)
