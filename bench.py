@@ -531,7 +531,7 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
         work = per_step * steps / max(launches, 1)
         asym = "double2" if name == "gemm_op_y" else sym
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
-                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0>" % (asym, "double" if name == "gemm_op_vg" else "double2")}
+                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0, 2>" % (asym, "double" if name == "gemm_op_vg" else "double2")}
         traffic = measured_traffic(name + ":" + precision) if form != "ycfie" else None
     if work is not None:
         ach = work / per_launch_s / 1e12
