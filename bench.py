@@ -498,6 +498,26 @@ def assembly_roofline(prof, n, steps, precision, nbw=0):
             "kernel_ms": {k: prof[k][0] / steps for k in ASM_KERNELS if k in prof}}
 
 
+COMPRESSION_KERNELS = ("gemm_sketch", "qr_householder", "qr_update", "qr_form_q", "svd_jacobi", "sketch")
+
+
+def compression_roofline(prof, w, ne, steps):
+    """Matrix-core roofline of the randomised compression's sketch products (HIP events
+    on the context stream): (2q + 2) products of 8 N n_eff l flop per step (l = r + p,
+    the sketch width) over the `gemm_sketch` time, with the compression's other kernel
+    times beside it (QR column steps, their compact-WY products, Jacobi SVD)."""
+    ell = min(w.rank_cap + w.oversample, ne)
+    ms = prof.get("gemm_sketch", (0.0, 0))[0] / steps
+    if ms <= 0.0:
+        return None
+    flop = (2 * w.power_iters + 2) * 8.0 * w.n * ne * ell
+    ach = flop / (ms / 1e3) / 1e12
+    return {"bound": "mfma", "kernel": "gemm_sketch", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64_TFLOPS, "flop_per_step": flop, "sketch_width": ell,
+            "kernel_ms": {k: prof[k][0] / steps for k in COMPRESSION_KERNELS if k in prof},
+            "compression_ms": sum(prof[k][0] for k in COMPRESSION_KERNELS if k in prof) / steps}
+
+
 def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
     """Roofline of the kernel family with the largest total time (HIP events on
     the context stream): achieved = algorithmic work per launch / mean launch time.
@@ -635,10 +655,14 @@ def main():
         tm = torch.from_numpy(wt.amps).cuda()
         rt, et, mt = run_workload(B, ctx, wt, tn, ta, tm, variants, args)
         t = rt[mt]
+        tne = t["info"]["n_eff"]
         et.update({"value": t["value"], "unit": "RHS solves/s", "ms_per_step": t["ms_per_step"],
-                   "variant_reported": mt, "config": workload_desc(wt, t["info"]["n_eff"]),
+                   "variant_reported": mt, "config": workload_desc(wt, tne),
+                   "roofline": roofline(t["prof"], wt.n, tne, wt.nrhs, args.steps, mt, wt.form,
+                                        t["info"].get("nbw", 0)),
                    "roofline_assembly": assembly_roofline(t["prof"], wt.n, args.steps, mt,
-                                                          t["info"].get("nbw", 0))})
+                                                          t["info"].get("nbw", 0)),
+                   "roofline_compression": compression_roofline(t["prof"], wt, tne, args.steps)})
         out["truncating"] = et
         del tn
     if not args.no_cpu_baseline:

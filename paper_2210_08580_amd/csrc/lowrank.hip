@@ -231,6 +231,7 @@ void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) 
     double2* W = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * (size_t)m)) : nullptr;
     double2* W2 = blocks ? static_cast<double2*>(c.dmalloc(sizeof(double2) * QR_NB * (size_t)m)) : nullptr;
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+    GemmTag tg(c, "qr_update");   // the compact-WY products
     for (int k = 0; k < npan; ++k) {
         const int k0 = k * QR_NB, kb = std::min(QR_NB, m - k0), Mv = M - k0, mt = m - k0 - kb;
         {

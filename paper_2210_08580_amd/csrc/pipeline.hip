@@ -446,17 +446,26 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
         for (int it = 0;; ++it) {
             // X = B_y T = Bt^T G^{-1/2} T ; Qz = orth(X)
             apply_gram_power(op, -1, T, m);
-            zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
+            {
+                GemmTag tg(c, "gemm_sketch");
+                zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
+            }
             householder_qr(c, X, ne, m, tau, Qz);
             if (it == power_iters) break;
             // Z = B_y^H Qz ; T = orth(Z)
-            zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+            {
+                GemmTag tg(c, "gemm_sketch");
+                zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+            }
             apply_gram_power(op, -1, Z, m);
             householder_qr(c, Z, n, m, tau, Qp);
             std::swap(T, Qp);
         }
         // projected block B = Q^H A_y = Qz^H B_y, held as B^H = B_y^H Qz
-        zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+        {
+            GemmTag tg(c, "gemm_sketch");
+            zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
+        }
         apply_gram_power(op, -1, Z, m);
         c.dfree(T);
         c.dfree(X);
