@@ -116,7 +116,15 @@ typedef struct fds_compress_opts {
     int32_t precision;     /* FDS_FP64                                           */
     double tol;            /* eps: keep sigma_i > eps sigma_1 (0: rank cap only)  */
     uint64_t seed;         /* sketch seed (SplitMix64 counter rule)              */
+    int32_t qr;            /* orthonormalisation of the sketch and projected
+                              blocks: FDS_QR_AUTO (CholeskyQR2 when the block
+                              has at most 140 columns and the factorisation
+                              certifies itself, else Householder) or
+                              FDS_QR_HOUSEHOLDER (always blocked Householder) */
+    int32_t reserved;
 } fds_compress_opts;
+
+enum { FDS_QR_AUTO = 0, FDS_QR_HOUSEHOLDER = 1 };
 
 typedef struct fds_solve_opts {
     int32_t max_iters;     /* refinement sweeps after the Woodbury solve          */
@@ -240,6 +248,21 @@ fds_status fds_zgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n
  * FDS_ERR_ARG for r < 1 or NULL pointers, FDS_ERR_NOTIMPL for r > 2048.
  * Synchronises the context stream. Test and diagnostic entry point. */
 fds_status fds_zinv(fds_ctx ctx, int64_t r, const void* A, void* Ainv, double* stats);
+
+/* QR of a dense complex128 M x m matrix (M >= m >= 1) with the explicit
+ * orthonormal factor, by the routine that orthonormalises the sketch and the
+ * projected block in fds_compress (paper, Inversion of the structured
+ * matrices: the orthonormal basis of the sampled range). method: FDS_QR_AUTO
+ * (CholeskyQR2 for m <= 140 when ||Q1^H Q1 - I||_F < 1/2 after its first pass
+ * and every pivot is positive, else Householder) or FDS_QR_HOUSEHOLDER.
+ * A: device, column-major, leading dimension M, caller-owned; overwritten, its
+ * upper triangle receives R (what lies below is unspecified). Q: device, M x m,
+ * leading dimension M, caller-owned, not aliased with A. householder_used
+ * (host, may be NULL): 1 when the Householder factorisation produced the
+ * result. FDS_ERR_ARG for bad sizes, NULL pointers or method. Synchronises the
+ * context stream. Test and diagnostic entry point. */
+fds_status fds_zqr(fds_ctx ctx, int64_t M, int64_t m, void* A, void* Q, int32_t method,
+                   int32_t* householder_used);
 
 /* fds_zgemm for complex64 operands on the FP32 matrix cores (FP32 accumulation);
  * alpha and beta: host complex64 (2 floats each). */
@@ -422,12 +445,12 @@ fds_status fds_op_filter_eigenvalues(fds_op op, double* out, int32_t cap, int32_
  *     is formed);
  *   - l < n_eff: Y = C_f Omega with the SplitMix64 sketch Omega (n x l,
  *     fds_compress_opts.seed), power_iters subspace iterations with
- *     Householder re-orthonormalisation, B = Q^H C_f, SVD of B;
+ *     re-orthonormalisation (fds_compress_opts.qr), B = Q^H C_f, SVD of B;
  *   - otherwise (l >= n_eff but truncating): SVD of C_f itself.
  * The rank is r = min(rank_cap, #{sigma_i > max(tol, 1e-13) sigma_1}), lowered
  * while sigma_r < (1 + 1e-6) sigma_{r+1} (no split of a repeated value).
  * Synchronises. rank_out (host, may be NULL) receives r. Errors: FDS_ERR_ARG
- * if l > n on the sketched branch; FDS_ERR_NOCONV if the Jacobi SVD of the
+ * if l > n on the sketched branch or qr is not one of FDS_QR_*; FDS_ERR_NOCONV if the Jacobi SVD of the
  * projected block does not converge. */
 fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_out);
 

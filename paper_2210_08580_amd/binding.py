@@ -24,6 +24,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fds.h")
 FDS_EFIE, FDS_MFIE, FDS_CFIE, FDS_YCFIE = 0, 1, 2, 3
 FORMS = {"efie": FDS_EFIE, "mfie": FDS_MFIE, "cfie": FDS_CFIE, "ycfie": FDS_YCFIE}
 FDS_FP64, FDS_FP32 = 0, 1
+FDS_QR_AUTO, FDS_QR_HOUSEHOLDER = 0, 1
 STATUS = {0: "FDS_OK", 1: "FDS_ERR_ARG", 2: "FDS_ERR_ALLOC", 3: "FDS_ERR_HIP",
           4: "FDS_ERR_STATE", 5: "FDS_ERR_SINGULAR", 6: "FDS_ERR_NOCONV", 7: "FDS_ERR_NOTIMPL"}
 
@@ -55,7 +56,8 @@ class fds_filter_opts(C.Structure):
 
 class fds_compress_opts(C.Structure):
     _fields_ = [("rank_cap", C.c_int32), ("oversample", C.c_int32), ("power_iters", C.c_int32),
-                ("precision", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64)]
+                ("precision", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64), ("qr", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class fds_solve_opts(C.Structure):
@@ -131,6 +133,8 @@ _SIGS = {
     "fds_op_filter_eigenvalues": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                             C.POINTER(C.c_int32)]),
     "fds_compress": (C.c_int, [C.c_void_p, C.POINTER(fds_compress_opts), C.POINTER(C.c_int32)]),
+    "fds_zqr": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                          C.POINTER(C.c_int32)]),
     "fds_op_singular_values": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                          C.POINTER(C.c_int32)]),
     "fds_op_factors": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -361,6 +365,18 @@ def fds_zinv(ctx: Ctx, A: torch.Tensor):
     return out, (st[0], st[1])
 
 
+def fds_zqr(ctx: Ctx, A: torch.Tensor, method: int = FDS_QR_AUTO):
+    """QR of the M x m complex128 column-major matrix held by A (shape (m, M), the
+    matrix is A.T). A is overwritten (R in its upper triangle); returns (Q in the
+    same layout, whether the Householder factorisation produced it)."""
+    m, M = A.shape
+    assert A.dtype == torch.complex128 and A.is_contiguous()
+    Q = torch.empty_like(A)
+    used = C.c_int32()
+    _check(lib().fds_zqr(ctx.handle, M, m, _ptr(A), _ptr(Q), int(method), C.byref(used)))
+    return Q, bool(used.value)
+
+
 def fds_zgemm(ctx: Ctx, opa: int, opb: int, A: torch.Tensor, Bm: torch.Tensor, Cm: torch.Tensor,
               alpha: complex = 1.0, beta: complex = 0.0):
     """Cm = alpha op(A) op(Bm) + beta Cm on column-major views.
@@ -539,9 +555,10 @@ def fds_op_filter_eigenvalues(op: Op, cap: int = 4096):
 
 
 def fds_compress(op: Op, rank_cap: int, oversample: int = 10, power_iters: int = 2,
-                 tol: float = 0.0, seed: int = 0, precision: int = FDS_FP64) -> int:
+                 tol: float = 0.0, seed: int = 0, precision: int = FDS_FP64, qr: int = 0) -> int:
+    """qr: FDS_QR_AUTO (0) or FDS_QR_HOUSEHOLDER (1)."""
     o = fds_compress_opts(int(rank_cap), int(oversample), int(power_iters), int(precision),
-                          float(tol), C.c_uint64(seed & ((1 << 64) - 1)))
+                          float(tol), C.c_uint64(seed & ((1 << 64) - 1)), int(qr), 0)
     r = C.c_int32()
     _check(lib().fds_compress(op.handle, C.byref(o), C.byref(r)))
     return r.value

@@ -12,6 +12,7 @@
 #include "fds_internal.h"
 #include "hankel.h"
 #include "linalg.h"
+#include "lowrank.h"
 #include "pipeline.h"
 
 namespace fds {
@@ -374,6 +375,28 @@ fds_status fds_zinv(fds_ctx ctx, int64_t r, const void* A, void* Ainv, double* s
     });
 }
 
+fds_status fds_zqr(fds_ctx ctx, int64_t M, int64_t m, void* A, void* Q, int32_t method,
+                   int32_t* householder_used) {
+    return guarded([&] {
+        FDS_REQUIRE(ctx && A && Q && A != Q, FDS_ERR_ARG, "bad argument");
+        FDS_REQUIRE(m >= 1 && M >= m && M < (1 << 30), FDS_ERR_ARG, "QR needs rows >= columns >= 1");
+        FDS_REQUIRE(method == FDS_QR_AUTO || method == FDS_QR_HOUSEHOLDER, FDS_ERR_ARG, "bad qr method");
+        Ctx& c = ctx->impl;
+        double2* tau = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m));
+        bool chol = false;
+        try {
+            chol = qr_explicit(c, static_cast<double2*>(A), (int)M, (int)m, tau, static_cast<double2*>(Q),
+                               method == FDS_QR_AUTO);
+            FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+        } catch (...) {
+            c.dfree(tau);
+            throw;
+        }
+        c.dfree(tau);
+        if (householder_used) *householder_used = chol ? 0 : 1;
+    });
+}
+
 fds_status fds_cgemm(fds_ctx ctx, int32_t opa, int32_t opb, int64_t m, int64_t n, int64_t k,
                      const float* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                      const float* beta, void* C, int64_t ldc) {
@@ -686,7 +709,9 @@ fds_status fds_compress(fds_op op, const fds_compress_opts* opts, int32_t* rank_
         FDS_REQUIRE(op && opts, FDS_ERR_ARG, "NULL argument");
         require_stage(op->impl, Stage::Filtered, "fds_compress");
         FDS_REQUIRE(opts->precision == FDS_FP64, FDS_ERR_NOTIMPL, "only FP64 compression is implemented");
-        run_compress(op->impl, opts->rank_cap, opts->oversample, opts->power_iters, opts->tol, opts->seed);
+        FDS_REQUIRE(opts->qr == FDS_QR_AUTO || opts->qr == FDS_QR_HOUSEHOLDER, FDS_ERR_ARG, "bad qr method");
+        run_compress(op->impl, opts->rank_cap, opts->oversample, opts->power_iters, opts->tol, opts->seed,
+                     opts->qr == FDS_QR_HOUSEHOLDER);
         if (rank_out) *rank_out = op->impl.rank;
     });
 }

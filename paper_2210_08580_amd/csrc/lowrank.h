@@ -7,10 +7,12 @@ namespace fds {
 // Omega (n x ell, column-major) of the counter-based SplitMix64 sketch.
 void sketch(Ctx& c, uint64_t seed, int64_t n, int ell, double2* Om);
 
-// Householder QR of A (M x m column-major, ld M, M >= m): A is overwritten by
-// R (upper triangle) and the reflectors; tau[m]. If Q is not null it receives
-// the explicit M x m orthonormal factor.
-void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q);
+// QR of A (M x m column-major, ld M, M >= m) with the explicit orthonormal
+// factor Q (M x m): CholeskyQR2 (when allowed) if it certifies itself, else blocked
+// Householder. The upper triangle of A receives R; what lies below it is left
+// unspecified. tau[m] is workspace.
+// Returns true when CholeskyQR2 produced the result.
+bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky = true);
 // X (m x m) = R^H from a factored A.
 void r_adjoint(Ctx& c, const double2* A, int M, int m, double2* X);
 

@@ -220,7 +220,7 @@ __global__ void r_adjoint_kernel(const double2* __restrict__ A, int64_t lda, int
 
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) {
+static void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) {
     FDS_REQUIRE(m >= 1 && M >= m, FDS_ERR_ARG, "Householder QR needs rows >= columns >= 1");
     const int npan = (m + QR_NB - 1) / QR_NB;
     const bool blocks = npan > 1 || Q;
@@ -292,6 +292,284 @@ void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q) 
         c.dfree(W);
         c.dfree(W2);
     }
+}
+
+// ----------------------------------------------------------------- Cholesky QR
+// CholeskyQR2 (Fukaya, Nakatsukasa, Yanagisawa & Yamamoto, ScalA 2014):
+// G1 = A^H A = R1^H R1, Q1 = A R1^{-1}; G2 = Q1^H Q1 = R2^H R2, Q = Q1 R2^{-1};
+// R = R2 R1. The Gram products and the right-multiplications are matrix-core
+// GEMMs; each Cholesky factor and its triangular inverse come from one
+// workgroup holding the packed lower triangle of the Gram matrix in LDS.
+// The first pass leaves Q1 with ||Q1^H Q1 - I|| of order kappa(A)^2 u, and the
+// second pass, started from a well-conditioned Q1, is accurate to unit
+// roundoff. The second Gram matrix certifies the first pass: ||G2 - I||_F < 1/2
+// bounds kappa(Q1)^2 by 3. When that check or a pivot fails the blocked
+// Householder factorisation runs instead.
+constexpr int CQ_BS = 1024;
+constexpr int CQ_MAX = 140;   // packed triangle (157,920 B) and the buffers below fit 160 KiB of LDS
+constexpr int CQ_TRI = CQ_MAX * (CQ_MAX + 1) / 2;
+
+// packed column-major lower triangle: column c holds rows c..m-1
+__device__ __forceinline__ int cq_idx(int m, int r, int c) { return c * (2 * m - c - 1) / 2 + r; }
+
+// sum over the Lr consecutive lanes of a row group (Lr a power of two <= 64)
+__device__ __forceinline__ double group_sum(double v, int Lr) {
+    for (int o = 1; o < Lr; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// lanes per row when u rows share the workgroup: the largest power of two
+// <= 64 with u Lr <= CQ_BS
+__device__ __forceinline__ int lanes_per_row(int u) {
+    int Lr = 64;
+    while (Lr > 1 && u * Lr > CQ_BS) Lr >>= 1;
+    return Lr;
+}
+
+constexpr int CB = 4;   // columns per step of the factorisation and of the inversion
+
+// G (m x m Hermitian, column-major, ld m) = L L^H. Writes R = L^H and Ri = L^{-H}
+// (m x m upper triangular, zeros below). flag: set to 1 when a pivot is not
+// positive or, with check, when ||G - I||_F >= 1/2; with check the previous flag
+// is kept (or-ed), without it the flag is overwritten.
+//
+// Both halves take CB columns per step, one row of the step per group of Lr
+// lanes (the lanes split the row's inner products), with two barriers per step:
+// the inner products over finished columns first, then the CB x CB triangular
+// part within the step, which every row solves in registers.
+__global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restrict__ G, int m, int check,
+                                                         double2* __restrict__ R, double2* __restrict__ Ri,
+                                                         int* __restrict__ flag) {
+    __shared__ double2 L[CQ_TRI];    // packed lower triangle
+    __shared__ double pv[CQ_MAX];    // 1 / pivot while factoring, then 1 / L(j, j)
+    __shared__ double2 dblk[CB][CB];  // partial sums of a step's diagonal block
+    __shared__ double red[CQ_BS / 64];
+    const int tid = threadIdx.x;
+    double dev = 0.0;
+    for (int t = tid; t < m * m; t += CQ_BS) {
+        const int r = t % m, c = t / m;
+        const double2 g = G[t];
+        if (r >= c) L[cq_idx(m, r, c)] = g;
+        const double ex = g.x - (r == c ? 1.0 : 0.0);
+        dev += ex * ex + g.y * g.y;
+    }
+    {
+        double v[1] = {dev};
+        block_sum_k<1, CQ_BS>(v, red);   // barriers: L is complete afterwards
+        dev = v[0];
+    }
+    int bad = check && !(dev < 0.25);
+
+    // Cholesky, Crout order, unnormalised: with d_l the pivots,
+    //   Lh(r, c) = G(r, c) - sum_{l<c} Lh(r, l) conj(Lh(c, l)) / d_l,  d_c = Lh(c, c),
+    // and L(r, c) = Lh(r, c) / sqrt(d_c).
+    for (int j = 0; j < m; j += CB) {
+        const int bw = min(CB, m - j), u = m - j, Lr = lanes_per_row(u);
+        const int g = tid / Lr, q = tid % Lr, r = j + g;
+        const bool act = g < u;
+        double2 part[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) part[c] = make_double2(0.0, 0.0);
+        if (act) {
+            for (int l = q; l < j; l += Lr) {
+                const double2 a = L[cq_idx(m, r, l)];
+                const double w = pv[l];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    if (c < bw && j + c <= r) {
+                        const double2 b = L[cq_idx(m, j + c, l)];
+                        part[c].x += w * (a.x * b.x + a.y * b.y);
+                        part[c].y += w * (a.y * b.x - a.x * b.y);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            part[c].x = group_sum(part[c].x, Lr);
+            part[c].y = group_sum(part[c].y, Lr);
+        }
+        if (act && q == 0) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < bw && j + c <= r) {
+                    const double2 gv = L[cq_idx(m, r, j + c)];
+                    part[c] = make_double2(gv.x - part[c].x, gv.y - part[c].y);
+                    if (r < j + bw) dblk[r - j][c] = part[c];
+                }
+            }
+        }
+        __syncthreads();
+        if (act && q == 0) {
+            // the step's diagonal block, finished in registers by every row
+            double2 D[CB][CB];
+            double dinv[CB];
+#pragma unroll
+            for (int a2 = 0; a2 < CB; ++a2)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) D[a2][c] = (a2 < bw && c <= a2) ? dblk[a2][c] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                dinv[c] = 1.0 / D[c][c].x;
+#pragma unroll
+                for (int a2 = c + 1; a2 < CB; ++a2) {
+                    const double2 f = make_double2(D[a2][c].x * dinv[c], D[a2][c].y * dinv[c]);
+#pragma unroll
+                    for (int e = c + 1; e <= a2; ++e) {   // D[a2][e] -= f conj(D[e][c])
+                        const double2 b = D[e][c];
+                        D[a2][e].x -= f.x * b.x + f.y * b.y;
+                        D[a2][e].y -= f.y * b.x - f.x * b.y;
+                    }
+                }
+            }
+            // the row's own entries of the step: the same elimination
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < bw && j + c <= r) {
+#pragma unroll
+                    for (int e = 0; e < c; ++e) {   // part[c] -= part[e] conj(D[c][e]) / d_e
+                        const double2 b = D[c][e];
+                        const double2 f = make_double2(part[e].x * dinv[e], part[e].y * dinv[e]);
+                        part[c].x -= f.x * b.x + f.y * b.y;
+                        part[c].y -= f.y * b.x - f.x * b.y;
+                    }
+                    L[cq_idx(m, r, j + c)] = part[c];
+                }
+            }
+            if (r < j + bw) pv[r] = dinv[r - j];
+        }
+        __syncthreads();
+    }
+    // normalise: L(r, l) = Lh(r, l) / sqrt(d_l), L(l, l) = sqrt(d_l)
+    for (int t = tid; t < m * m; t += CQ_BS) {
+        const int r = t % m, c = t / m;
+        if (r < c) continue;
+        double2& x = L[cq_idx(m, r, c)];
+        if (r == c) {
+            if (!(x.x > 0.0)) bad = 1;
+            x = make_double2(sqrt(x.x), 0.0);
+        } else {
+            const double s = sqrt(pv[c]);
+            x.x *= s;
+            x.y *= s;
+        }
+    }
+    bad = __syncthreads_or(bad);
+    for (int t = tid; t < m * m; t += CQ_BS) {
+        const int r = t % m, c = t / m;
+        R[t] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? L[cq_idx(m, r, r)].x : 0.0, 0.0);
+    }
+    if (tid < m) pv[tid] = 1.0 / L[cq_idx(m, tid, tid)].x;
+    __syncthreads();
+
+    // X = L^{-1} in place below the diagonal (the diagonal of X kept in pv),
+    // column blocks from the right: for a row r and a column c of the block,
+    //   X(r, c) = -X(c, c) sum_{l=c+1}^{r} X(r, l) L(l, c),
+    // the terms with l past the block first (finished columns), then the
+    // block's own columns from its right end.
+    for (int j = ((m - 1) / CB) * CB; j >= 0; j -= CB) {
+        const int bw = min(CB, m - j), u = m - j, Lr = lanes_per_row(u);
+        const int g = tid / Lr, q = tid % Lr, r = j + g;
+        const bool act = g < u;
+        double2 y[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) y[c] = make_double2(0.0, 0.0);
+        if (act) {
+            for (int l = j + bw + q; l <= r; l += Lr) {
+                const double2 a = l < r ? L[cq_idx(m, r, l)] : make_double2(pv[r], 0.0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    if (c < bw) {
+                        const double2 b = L[cq_idx(m, l, j + c)];
+                        y[c].x += a.x * b.x - a.y * b.y;
+                        y[c].y += a.x * b.y + a.y * b.x;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            y[c].x = group_sum(y[c].x, Lr);
+            y[c].y = group_sum(y[c].y, Lr);
+        }
+        double2 xr[CB] = {};   // X(r, j + c)
+        if (act && q == 0) {
+            const int top = min(bw - 1, r - j);   // X(r, j + top) is the diagonal when r is in the block
+#pragma unroll
+            for (int c = CB - 1; c >= 0; --c) {
+                xr[c] = make_double2(0.0, 0.0);
+                if (c > top) continue;
+                if (j + c == r) {
+                    xr[c] = make_double2(pv[r], 0.0);
+                    continue;
+                }
+                double2 s = y[c];
+#pragma unroll
+                for (int e = c + 1; e < CB; ++e) {
+                    if (e <= top) {
+                        const double2 b = L[cq_idx(m, j + e, j + c)];
+                        s.x += xr[e].x * b.x - xr[e].y * b.y;
+                        s.y += xr[e].x * b.y + xr[e].y * b.x;
+                    }
+                }
+                const double dc = -pv[j + c];
+                xr[c] = make_double2(dc * s.x, dc * s.y);
+            }
+        }
+        __syncthreads();
+        if (act && q == 0) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c < bw && j + c < r) L[cq_idx(m, r, j + c)] = xr[c];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < m * m; t += CQ_BS) {
+        const int r = t % m, c = t / m;
+        Ri[t] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? pv[r] : 0.0, 0.0);
+    }
+    if (tid == 0) *flag = (check ? *flag : 0) | bad;
+}
+
+// CholeskyQR2 of A (M x m): Q receives the orthonormal factor and the upper
+// triangle of A the R factor. Returns false, with A unchanged, when the
+// factorisation does not certify itself.
+static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q) {
+    if (m > CQ_MAX) return false;
+    const size_t mm = (size_t)m * m;
+    double2* G = static_cast<double2*>(c.dmalloc(sizeof(double2) * mm * 4));
+    double2 *R1 = G + mm, *R2 = G + 2 * mm, *Ri = G + 3 * mm;
+    double2* Q1 = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m));
+    int* flag = static_cast<int*>(c.dmalloc(sizeof(int)));
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    GemmTag tg(c, "qr_gram");
+    double2* R[2] = {R1, R2};
+    const double2* in[2] = {A, Q1};
+    double2* out[2] = {Q1, Q};
+    for (int pass = 0; pass < 2; ++pass) {
+        zgemm(c, OP_C, OP_N, m, m, M, one, in[pass], M, in[pass], M, zero, G, m);
+        {
+            KScope _ks(c, "qr_cholesky");
+            hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CQ_BS), 0, c.stream, G, m, pass, R[pass], Ri, flag);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        zgemm(c, OP_N, OP_N, M, m, m, one, in[pass], M, Ri, m, zero, out[pass], M);
+    }
+    int bad = 1;
+    FDS_HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    FDS_HIP_TRY(hipStreamSynchronize(c.stream));
+    if (!bad) zgemm(c, OP_N, OP_N, m, m, m, one, R2, m, R1, m, zero, A, M);
+    c.dfree(G);
+    c.dfree(Q1);
+    c.dfree(flag);
+    return !bad;
+}
+
+bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky) {
+    FDS_REQUIRE(m >= 1 && M >= m && Q, FDS_ERR_ARG, "QR needs rows >= columns >= 1 and an output");
+    if (cholesky && cholesky_qr2(c, A, M, m, Q)) return true;
+    householder_qr(c, A, M, m, tau, Q);
+    return false;
 }
 
 void r_adjoint(Ctx& c, const double2* A, int M, int m, double2* X) {

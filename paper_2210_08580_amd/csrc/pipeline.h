@@ -11,7 +11,8 @@ void run_filter(Op& op, int form, double alpha, int n_modes, bool keep_null, dou
 void prefetch_filter(Op& op, int n_modes);
 void run_filter_batch(Op* const* ops, int count, int form, double alpha, const int* n_modes, bool keep_null,
                       double cluster_rtol);
-void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed);
+void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed,
+                  bool householder = false);
 void run_compress_aca(Op& op, int rank_cap, double tol);   // aca.hip
 void run_factor(Op& op);
 void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,

@@ -399,7 +399,8 @@ static int truncation_rank(const std::vector<double>& s, int rank_cap, double to
     return r;
 }
 
-void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed) {
+void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double tol, uint64_t seed,
+                  bool householder) {
     const int ne = op.n_eff;
     const int ell = rank_cap + oversample;
     FDS_REQUIRE(rank_cap >= 1 && oversample >= 0 && power_iters >= 0 && tol >= 0.0, FDS_ERR_ARG,
@@ -450,7 +451,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
                 GemmTag tg(c, "gemm_sketch");
                 zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
             }
-            householder_qr(c, X, ne, m, tau, Qz);
+            qr_explicit(c, X, ne, m, tau, Qz, !householder);
             if (it == power_iters) break;
             // Z = B_y^H Qz ; T = orth(Z)
             {
@@ -458,7 +459,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
                 zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
             }
             apply_gram_power(op, -1, Z, m);
-            householder_qr(c, Z, n, m, tau, Qp);
+            qr_explicit(c, Z, n, m, tau, Qp, !householder);
             std::swap(T, Qp);
         }
         // projected block B = Q^H A_y = Qz^H B_y, held as B^H = B_y^H Qz
@@ -478,7 +479,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
     // B^H = Q_P R (Householder), R^H = Uh diag(s) Vh^H (Jacobi):
     //     B = Uh diag(s) (Q_P Vh)^H
     double2* QP = static_cast<double2*>(c.dmalloc(sizeof(double2) * nm));
-    householder_qr(c, Z, n, m, tau, QP);
+    qr_explicit(c, Z, n, m, tau, QP, !householder);
     double2* RH = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)m * m));
     r_adjoint(c, Z, n, m, RH);
     c.dfree(Z);

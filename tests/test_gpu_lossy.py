@@ -29,9 +29,11 @@ def ctx():
     c.close()
 
 
+@pytest.mark.parametrize("qr", [B.FDS_QR_AUTO, B.FDS_QR_HOUSEHOLDER])
 @pytest.mark.parametrize("kind,n,k,form,nm,cap,p,q,tol,conv", CASES)
-def test_lossy_compress_parity(ctx, kind, n, k, form, nm, cap, p, q, tol, conv):
-    print(f"case: lossy {kind} n={n} k={k} {form} n_modes={nm} cap={cap} p={p} q={q} tol={tol}", flush=True)
+def test_lossy_compress_parity(ctx, kind, n, k, form, nm, cap, p, q, tol, conv, qr):
+    print(f"case: lossy {kind} n={n} k={k} {form} n_modes={nm} cap={cap} p={p} q={q} tol={tol} qr={qr}",
+          flush=True)
     nodes = wl.curve_nodes(kind, n)
     seed = 7
     pb = solver.Problem(nodes, k, form=form, n_modes=nm, rank_cap=cap, oversample=p, power_iters=q,
@@ -43,7 +45,16 @@ def test_lossy_compress_parity(ctx, kind, n, k, form, nm, cap, p, q, tol, conv):
     op = B.fds_assemble(ctx, torch.from_numpy(nodes).cuda(), k)
     ne = B.fds_filter(op, form, 1.0, nm)
     assert ne == ops.n_eff
-    r = B.fds_compress(op, rank_cap=cap, oversample=p, power_iters=q, tol=tol, seed=seed)
+    torch.cuda.synchronize()
+    B.fds_profile_read(ctx)
+    B.fds_profile_enable(ctx, True)
+    r = B.fds_compress(op, rank_cap=cap, oversample=p, power_iters=q, tol=tol, seed=seed, qr=qr)
+    B.fds_profile_enable(ctx, False)
+    ran = B.fds_profile_read(ctx)
+    # every block here has a condition number far below u^{-1/2}: CholeskyQR2
+    # certifies itself on all of them unless Householder is asked for
+    assert ("qr_cholesky" in ran) == (qr == B.FDS_QR_AUTO), sorted(ran)
+    assert ("qr_householder" in ran) == (qr == B.FDS_QR_HOUSEHOLDER), sorted(ran)
     assert r == ro
     sv = np.array(B.fds_op_singular_values(op))
     kk = min(len(sv), len(so))
