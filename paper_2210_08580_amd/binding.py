@@ -161,7 +161,6 @@ _SIGS = {
 
 _lib = None
 _live = weakref.WeakSet()
-_is_finalizing = sys.is_finalizing
 
 
 def _close_all():
@@ -264,8 +263,9 @@ class Ctx:
             lib().fds_ctx_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if _is_finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        # the default argument outlives the module globals at interpreter exit
+        if _fin():
             return
         try:
             self.close()
@@ -422,8 +422,9 @@ class Op:
             lib().fds_op_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if _is_finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        # the default argument outlives the module globals at interpreter exit
+        if _fin():
             return
         try:
             self.close()
@@ -729,8 +730,9 @@ class Batch:
             lib().fds_batch_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if _is_finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        # the default argument outlives the module globals at interpreter exit
+        if _fin():
             return
         try:
             self.close()

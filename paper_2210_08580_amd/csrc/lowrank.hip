@@ -305,54 +305,85 @@ static void householder_qr(Ctx& c, double2* A, int M, int m, double2* tau, doubl
 // roundoff. The second Gram matrix certifies the first pass: ||G2 - I||_F < 1/2
 // bounds kappa(Q1)^2 by 3. When that check or a pivot fails the blocked
 // Householder factorisation runs instead.
-constexpr int CQ_BS = 1024;
+constexpr int CQ_BS = 512;
 constexpr int CQ_MAX = 140;   // packed triangle (157,920 B) and the buffers below fit 160 KiB of LDS
 constexpr int CQ_TRI = CQ_MAX * (CQ_MAX + 1) / 2;
 
 // packed column-major lower triangle: column c holds rows c..m-1
 __device__ __forceinline__ int cq_idx(int m, int r, int c) { return c * (2 * m - c - 1) / 2 + r; }
 
-// sum over the Lr consecutive lanes of a row group (Lr a power of two <= 64)
-__device__ __forceinline__ double group_sum(double v, int Lr) {
-    for (int o = 1; o < Lr; o <<= 1) v += __shfl_xor(v, o, 64);
+// Sums over groups of Ls consecutive lanes (Ls a power of two <= 16) by DPP
+// moves within rows of 16 lanes: lane ^ 1, lane ^ 2, then the mirror images in
+// the half row and in the row; every lane of a group ends with the group's sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double group_sum(double v, int Ls) {
+    if (Ls >= 2) v += dpp_mov<0xB1>(v);    // quad_perm(1, 0, 3, 2)
+    if (Ls >= 4) v += dpp_mov<0x4E>(v);    // quad_perm(2, 3, 0, 1)
+    if (Ls >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+    if (Ls >= 16) v += dpp_mov<0x140>(v);  // row_mirror
     return v;
 }
 
-// lanes per row when u rows share the workgroup: the largest power of two
-// <= 64 with u Lr <= CQ_BS
-__device__ __forceinline__ int lanes_per_row(int u) {
-    int Lr = 64;
-    while (Lr > 1 && u * Lr > CQ_BS) Lr >>= 1;
-    return Lr;
+constexpr int CB = 16;   // columns per step of the factorisation and of the inversion
+constexpr int CT = 4;    // register tile: CT rows x CT columns per thread
+
+// lanes splitting one tile's inner products: at most 16, the tiles times the
+// lanes within the workgroup, and at least four terms per lane
+__device__ __forceinline__ int slices(int tiles, int len) {
+    int Ls = 16;
+    while (Ls > 1 && (tiles * Ls > CQ_BS || len < 4 * Ls)) Ls >>= 1;
+    return Ls;
 }
 
-constexpr int CB = 4;   // columns per step of the factorisation and of the inversion
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+
+// sum each tile entry over the Ls lanes of its group (every lane takes part)
+__device__ __forceinline__ void tile_sum(double2 (&acc)[CT][CT], int Ls) {
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+#pragma unroll
+        for (int k = 0; k < CT; ++k) {
+            acc[i][k].x = group_sum(acc[i][k].x, Ls);
+            acc[i][k].y = group_sum(acc[i][k].y, Ls);
+        }
+}
 
 // G (m x m Hermitian, column-major, ld m) = L L^H. Writes R = L^H and Ri = L^{-H}
 // (m x m upper triangular, zeros below). flag: set to 1 when a pivot is not
 // positive or, with check, when ||G - I||_F >= 1/2; with check the previous flag
 // is kept (or-ed), without it the flag is overwritten.
 //
-// Both halves take CB columns per step, one row of the step per group of Lr
-// lanes (the lanes split the row's inner products), with two barriers per step:
-// the inner products over finished columns first, then the CB x CB triangular
-// part within the step, which every row solves in registers.
+// Both halves go CB columns per step. The inner products over finished columns
+// are a small matrix product: CT x CT register tiles, each split over Ls lanes.
+// The CB x CB triangular part within a step is then solved one row per thread
+// (the factorisation's diagonal block by wavefront 0 first).
 __global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restrict__ G, int m, int check,
                                                          double2* __restrict__ R, double2* __restrict__ Ri,
                                                          int* __restrict__ flag) {
-    __shared__ double2 L[CQ_TRI];    // packed lower triangle
-    __shared__ double pv[CQ_MAX];    // 1 / pivot while factoring, then 1 / L(j, j)
-    __shared__ double2 dblk[CB][CB];  // partial sums of a step's diagonal block
+    __shared__ double2 L[CQ_TRI];       // packed lower triangle
+    __shared__ double pv[CQ_MAX];       // 1 / pivot while factoring, then 1 / L(j, j)
+    __shared__ double2 blk[CB][CB];     // a step's diagonal block of L during the inversion
     __shared__ double red[CQ_BS / 64];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double dev = 0.0;
-    for (int t = tid; t < m * m; t += CQ_BS) {
-        const int r = t % m, c = t / m;
-        const double2 g = G[t];
-        if (r >= c) L[cq_idx(m, r, c)] = g;
-        const double ex = g.x - (r == c ? 1.0 : 0.0);
-        dev += ex * ex + g.y * g.y;
-    }
+    // whole-matrix loops: column c per wavefront, rows by lane
+    for (int c = wave; c < m; c += CQ_BS / 64)
+        for (int r = lane; r < m; r += 64) {
+            const double2 g = G[(size_t)c * m + r];
+            if (r >= c) L[cq_idx(m, r, c)] = g;
+            const double ex = g.x - (r == c ? 1.0 : 0.0);
+            dev += ex * ex + g.y * g.y;
+        }
     {
         double v[1] = {dev};
         block_sum_k<1, CQ_BS>(v, red);   // barriers: L is complete afterwards
@@ -364,170 +395,193 @@ __global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restri
     //   Lh(r, c) = G(r, c) - sum_{l<c} Lh(r, l) conj(Lh(c, l)) / d_l,  d_c = Lh(c, c),
     // and L(r, c) = Lh(r, c) / sqrt(d_c).
     for (int j = 0; j < m; j += CB) {
-        const int bw = min(CB, m - j), u = m - j, Lr = lanes_per_row(u);
-        const int g = tid / Lr, q = tid % Lr, r = j + g;
-        const bool act = g < u;
-        double2 part[CB];
+        const int bw = min(CB, m - j), u = m - j;
+        {   // rows r >= j, the step's columns, terms l < j
+            const int tiles = ((u + CT - 1) / CT) * (CB / CT), Ls = slices(tiles, j);
+            const int ti = tid / Ls, s = tid % Ls;
+            const bool act = ti < tiles;
+            const int r0 = j + (ti / (CB / CT)) * CT, c0 = (ti % (CB / CT)) * CT;
+            double2 acc[CT][CT] = {};
+            if (act) {
+                for (int l = s; l < j; l += Ls) {
+                    const double w = pv[l];
+                    const double2* col = L + cq_idx(m, 0, l);   // column l, indexed by row
+                    double2 a[CT], b[CT];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) part[c] = make_double2(0.0, 0.0);
-        if (act) {
-            for (int l = q; l < j; l += Lr) {
-                const double2 a = L[cq_idx(m, r, l)];
-                const double w = pv[l];
+                    for (int i = 0; i < CT; ++i) a[i] = r0 + i < m ? col[r0 + i] : make_double2(0.0, 0.0);
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    if (c < bw && j + c <= r) {
-                        const double2 b = L[cq_idx(m, j + c, l)];
-                        part[c].x += w * (a.x * b.x + a.y * b.y);
-                        part[c].y += w * (a.y * b.x - a.x * b.y);
+                    for (int k = 0; k < CT; ++k) {
+                        const double2 v = c0 + k < bw ? col[j + c0 + k] : make_double2(0.0, 0.0);
+                        b[k] = make_double2(w * v.x, -w * v.y);
                     }
+#pragma unroll
+                    for (int i = 0; i < CT; ++i)
+#pragma unroll
+                        for (int k = 0; k < CT; ++k) cfma(acc[i][k], a[i], b[k]);
                 }
             }
-        }
+            tile_sum(acc, Ls);
+            if (act && s == 0) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            part[c].x = group_sum(part[c].x, Lr);
-            part[c].y = group_sum(part[c].y, Lr);
-        }
-        if (act && q == 0) {
+                for (int i = 0; i < CT; ++i)
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                if (c < bw && j + c <= r) {
-                    const double2 gv = L[cq_idx(m, r, j + c)];
-                    part[c] = make_double2(gv.x - part[c].x, gv.y - part[c].y);
-                    if (r < j + bw) dblk[r - j][c] = part[c];
-                }
+                    for (int k = 0; k < CT; ++k) {
+                        const int r = r0 + i, c = c0 + k;
+                        if (r < m && c < bw && j + c <= r) {
+                            double2& x = L[cq_idx(m, r, j + c)];
+                            x.x -= acc[i][k].x;
+                            x.y -= acc[i][k].y;
+                        }
+                    }
             }
         }
         __syncthreads();
-        if (act && q == 0) {
-            // the step's diagonal block, finished in registers by every row
-            double2 D[CB][CB];
-            double dinv[CB];
-#pragma unroll
-            for (int a2 = 0; a2 < CB; ++a2)
-#pragma unroll
-                for (int c = 0; c < CB; ++c) D[a2][c] = (a2 < bw && c <= a2) ? dblk[a2][c] : make_double2(0.0, 0.0);
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                dinv[c] = 1.0 / D[c][c].x;
-#pragma unroll
-                for (int a2 = c + 1; a2 < CB; ++a2) {
-                    const double2 f = make_double2(D[a2][c].x * dinv[c], D[a2][c].y * dinv[c]);
-#pragma unroll
-                    for (int e = c + 1; e <= a2; ++e) {   // D[a2][e] -= f conj(D[e][c])
-                        const double2 b = D[e][c];
-                        D[a2][e].x -= f.x * b.x + f.y * b.y;
-                        D[a2][e].y -= f.y * b.x - f.x * b.y;
+        if (wave == 0) {   // the diagonal block, right-looking, in place
+            for (int c = 0; c < bw; ++c) {
+                const double id = 1.0 / L[cq_idx(m, j + c, j + c)].x;
+                for (int t = lane; t < CB * CB; t += 64) {
+                    const int a = t / CB, e = t % CB;
+                    if (c < e && e <= a && a < bw) {
+                        const double2 la = L[cq_idx(m, j + a, j + c)], le = L[cq_idx(m, j + e, j + c)];
+                        double2& x = L[cq_idx(m, j + a, j + e)];
+                        x.x -= id * (la.x * le.x + la.y * le.y);
+                        x.y -= id * (la.y * le.x - la.x * le.y);
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            // the row's own entries of the step: the same elimination
+            if (lane < bw) pv[j + lane] = 1.0 / L[cq_idx(m, j + lane, j + lane)].x;
+        }
+        __syncthreads();
+        {   // rows below the block: the triangular part, one row per thread
+            const int r = j + bw + tid;
+            if (r < m) {
+                int cb[CB];   // the block's columns, indexed by row
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                if (c < bw && j + c <= r) {
+                for (int c = 0; c < CB; ++c) cb[c] = cq_idx(m, 0, min(j + c, m - 1));
+                double2 p[CB];
 #pragma unroll
-                    for (int e = 0; e < c; ++e) {   // part[c] -= part[e] conj(D[c][e]) / d_e
-                        const double2 b = D[c][e];
-                        const double2 f = make_double2(part[e].x * dinv[e], part[e].y * dinv[e]);
-                        part[c].x -= f.x * b.x + f.y * b.y;
-                        part[c].y -= f.y * b.x - f.x * b.y;
+                for (int c = 0; c < CB; ++c) p[c] = c < bw ? L[cb[c] + r] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 1; c < CB; ++c) {
+                    if (c < bw) {
+#pragma unroll
+                        for (int e = 0; e < c; ++e) {   // p[c] -= p[e] conj(Lh(j+c, j+e)) / d_{j+e}
+                            const double2 v = L[cb[e] + j + c];
+                            const double w = pv[j + e];
+                            p[c].x -= w * (p[e].x * v.x + p[e].y * v.y);
+                            p[c].y -= w * (p[e].y * v.x - p[e].x * v.y);
+                        }
                     }
-                    L[cq_idx(m, r, j + c)] = part[c];
                 }
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c < bw) L[cb[c] + r] = p[c];
             }
-            if (r < j + bw) pv[r] = dinv[r - j];
         }
         __syncthreads();
     }
     // normalise: L(r, l) = Lh(r, l) / sqrt(d_l), L(l, l) = sqrt(d_l)
-    for (int t = tid; t < m * m; t += CQ_BS) {
-        const int r = t % m, c = t / m;
-        if (r < c) continue;
-        double2& x = L[cq_idx(m, r, c)];
-        if (r == c) {
-            if (!(x.x > 0.0)) bad = 1;
-            x = make_double2(sqrt(x.x), 0.0);
-        } else {
-            const double s = sqrt(pv[c]);
-            x.x *= s;
-            x.y *= s;
+    for (int c = wave; c < m; c += CQ_BS / 64) {
+        const double sc = sqrt(pv[c]);
+        for (int r = c + lane; r < m; r += 64) {
+            double2& x = L[cq_idx(m, r, c)];
+            if (r == c) {
+                if (!(x.x > 0.0)) bad = 1;
+                x = make_double2(sqrt(x.x), 0.0);
+            } else {
+                x.x *= sc;
+                x.y *= sc;
+            }
         }
     }
     bad = __syncthreads_or(bad);
-    for (int t = tid; t < m * m; t += CQ_BS) {
-        const int r = t % m, c = t / m;
-        R[t] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? L[cq_idx(m, r, r)].x : 0.0, 0.0);
-    }
+    for (int c = wave; c < m; c += CQ_BS / 64)
+        for (int r = lane; r < m; r += 64)
+            R[(size_t)c * m + r] = r < c ? cconj(L[cq_idx(m, c, r)])
+                                         : make_double2(r == c ? L[cq_idx(m, r, r)].x : 0.0, 0.0);
     if (tid < m) pv[tid] = 1.0 / L[cq_idx(m, tid, tid)].x;
     __syncthreads();
 
     // X = L^{-1} in place below the diagonal (the diagonal of X kept in pv),
     // column blocks from the right: for a row r and a column c of the block,
     //   X(r, c) = -X(c, c) sum_{l=c+1}^{r} X(r, l) L(l, c),
-    // the terms with l past the block first (finished columns), then the
-    // block's own columns from its right end.
+    // the terms past the block (finished columns) as a tiled product first, then
+    // the block's own columns from its right end, one row per thread.
     for (int j = ((m - 1) / CB) * CB; j >= 0; j -= CB) {
-        const int bw = min(CB, m - j), u = m - j, Lr = lanes_per_row(u);
-        const int g = tid / Lr, q = tid % Lr, r = j + g;
-        const bool act = g < u;
-        double2 y[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) y[c] = make_double2(0.0, 0.0);
+        const int bw = min(CB, m - j), jb = j + bw, ub = m - jb;
+        const int tiles = ((ub + CT - 1) / CT) * (CB / CT), Ls = slices(tiles, ub);
+        const int ti = tid / Ls, s = tid % Ls;
+        const bool act = ti < tiles;
+        const int r0 = jb + (ti / (CB / CT)) * CT, c0 = (ti % (CB / CT)) * CT;
+        double2 acc[CT][CT] = {};
         if (act) {
-            for (int l = j + bw + q; l <= r; l += Lr) {
-                const double2 a = l < r ? L[cq_idx(m, r, l)] : make_double2(pv[r], 0.0);
+            const int lend = min(r0 + CT - 1, m - 1);
+            int cb[CT];   // the block's columns, indexed by row
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    if (c < bw) {
-                        const double2 b = L[cq_idx(m, l, j + c)];
-                        y[c].x += a.x * b.x - a.y * b.y;
-                        y[c].y += a.x * b.y + a.y * b.x;
-                    }
+            for (int k = 0; k < CT; ++k) cb[k] = cq_idx(m, 0, min(j + c0 + k, m - 1));
+            for (int l = jb + s; l <= lend; l += Ls) {
+                const double2* col = L + cq_idx(m, 0, l);
+                double2 a[CT], b[CT];
+#pragma unroll
+                for (int i = 0; i < CT; ++i) {
+                    const int r = r0 + i;
+                    a[i] = (r < m && l <= r) ? (l < r ? col[r] : make_double2(pv[r], 0.0)) : make_double2(0.0, 0.0);
                 }
+#pragma unroll
+                for (int k = 0; k < CT; ++k) b[k] = c0 + k < bw ? L[cb[k] + l] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int i = 0; i < CT; ++i)
+#pragma unroll
+                    for (int k = 0; k < CT; ++k) cfma(acc[i][k], a[i], b[k]);
             }
         }
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            y[c].x = group_sum(y[c].x, Lr);
-            y[c].y = group_sum(y[c].y, Lr);
+        tile_sum(acc, Ls);
+        for (int t = tid; t < CB * CB; t += CQ_BS) {
+            const int a = t / CB, c = t % CB;
+            blk[a][c] = (a < bw && c <= a) ? L[cq_idx(m, j + a, j + c)] : make_double2(0.0, 0.0);
         }
-        double2 xr[CB] = {};   // X(r, j + c)
-        if (act && q == 0) {
-            const int top = min(bw - 1, r - j);   // X(r, j + top) is the diagonal when r is in the block
+        __syncthreads();
+        if (act && s == 0) {   // the partial sums replace L below the block
 #pragma unroll
-            for (int c = CB - 1; c >= 0; --c) {
-                xr[c] = make_double2(0.0, 0.0);
-                if (c > top) continue;
-                if (j + c == r) {
-                    xr[c] = make_double2(pv[r], 0.0);
-                    continue;
-                }
-                double2 s = y[c];
+            for (int i = 0; i < CT; ++i)
 #pragma unroll
-                for (int e = c + 1; e < CB; ++e) {
-                    if (e <= top) {
-                        const double2 b = L[cq_idx(m, j + e, j + c)];
-                        s.x += xr[e].x * b.x - xr[e].y * b.y;
-                        s.y += xr[e].x * b.y + xr[e].y * b.x;
+                for (int k = 0; k < CT; ++k)
+                    if (r0 + i < m && c0 + k < bw) L[cq_idx(m, r0 + i, j + c0 + k)] = acc[i][k];
+        }
+        __syncthreads();
+        {
+            const int r = j + tid;
+            if (r < m) {
+                const bool below = r >= jb;
+                const int top = below ? bw - 1 : r - j;
+                double2 x[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    x[c] = below ? (c < bw ? L[cq_idx(m, r, j + c)] : make_double2(0.0, 0.0))
+                                 : make_double2(c == top ? pv[r] : 0.0, 0.0);
+#pragma unroll
+                for (int c = CB - 1; c >= 0; --c) {
+                    if (c < top || (below && c == top)) {
+                        double2 sum = x[c];
+#pragma unroll
+                        for (int e = c + 1; e < CB; ++e)
+                            if (e <= top) cfma(sum, x[e], blk[e][c]);
+                        const double dc = -pv[j + c];
+                        x[c] = make_double2(dc * sum.x, dc * sum.y);
                     }
                 }
-                const double dc = -pv[j + c];
-                xr[c] = make_double2(dc * s.x, dc * s.y);
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c < top || (below && c == top)) L[cq_idx(m, r, j + c)] = x[c];
             }
         }
         __syncthreads();
-        if (act && q == 0) {
-#pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < bw && j + c < r) L[cq_idx(m, r, j + c)] = xr[c];
-        }
-        __syncthreads();
     }
-    for (int t = tid; t < m * m; t += CQ_BS) {
-        const int r = t % m, c = t / m;
-        Ri[t] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? pv[r] : 0.0, 0.0);
-    }
+    for (int c = wave; c < m; c += CQ_BS / 64)
+        for (int r = lane; r < m; r += 64)
+            Ri[(size_t)c * m + r] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? pv[r] : 0.0, 0.0);
     if (tid == 0) *flag = (check ? *flag : 0) | bad;
 }
 
