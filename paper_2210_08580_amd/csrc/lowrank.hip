@@ -600,8 +600,14 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q) {
     double2* R[2] = {R1, R2};
     const double2* in[2] = {A, Q1};
     double2* out[2] = {Q1, Q};
+    // the Gram product has only a few output tiles: split its long inner dimension
+    // into chunks of about 64 rows (at most 64 parts) so that it fills the chip
+    const int gsplit = std::max(1, std::min(64, (M + 63) / 64));
     for (int pass = 0; pass < 2; ++pass) {
-        zgemm(c, OP_C, OP_N, m, m, M, one, in[pass], M, in[pass], M, zero, G, m);
+        {
+            SplitHint sh(c, gsplit);
+            zgemm(c, OP_C, OP_N, m, m, M, one, in[pass], M, in[pass], M, zero, G, m);
+        }
         {
             KScope _ks(c, "qr_cholesky");
             hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CQ_BS), 0, c.stream, G, m, pass, R[pass], Ri, flag);
