@@ -14,8 +14,11 @@
 //
 // One-sided Jacobi (Hestenes 1958; Demmel & Veselic, SIAM J. Matrix Anal.
 // Appl. 13, 1992) rotates pairs of columns of X until they are mutually
-// orthogonal: X V = U Sigma with V unitary. Pairs are visited in the round-
-// robin (circle) order, m/2 disjoint pairs per launch, one workgroup per pair.
+// orthogonal: X V = U Sigma with V unitary. Up to 312 columns the columns are
+// grouped in blocks of 8 and the block pairs visited in the round-robin (circle)
+// order, one launch per round, each workgroup sweeping the 16 columns of its
+// pair in LDS; wider matrices go pair by pair (m/2 disjoint pairs per launch,
+// one workgroup per pair).
 // The relative accuracy of small singular values is what the truncation rule
 // needs, which a Gram-matrix eigensolver would not deliver.
 #include <algorithm>
@@ -699,6 +702,145 @@ __global__ __launch_bounds__(LR_BS) void jacobi_round_kernel(double2* __restrict
     if (tid == 0) atomicAdd(counter, 1);
 }
 
+// Block one-sided Jacobi (the columns grouped in blocks of JB; block pairs in the
+// circle order, one launch per round): workgroup k takes its pair of blocks,
+// holds their 2 JB columns of X and of V in LDS and rotates the JB x JB cross
+// pairs of the two blocks (JB inner rounds, one wavefront per pair), in the
+// sweep's first round also the pairs within each block, with the threshold and
+// rotation of jacobi_round_kernel. A sweep (every block pair once) visits every
+// column pair exactly once, so it is a cyclic Jacobi ordering.
+constexpr int JB = 8;
+constexpr int JB_MAXROWS = 312;   // X and V columns of two blocks: 2 x 16 x 312 x 16 B of LDS
+constexpr int JB_LD = (2 * JB * JB_MAXROWS + 64 * JB - 1) / (64 * JB);   // column entries per thread
+
+// 1/sqrt(x) and 1/x for x > 0: hardware estimates and two Newton steps each
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double recip_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
+// sum over the wavefront without LDS traffic: DPP sums within rows of 16 lanes,
+// then the four row sums read out of lanes 0, 16, 32 and 48
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v = group_sum(v, 16);
+    const long long b = __double_as_longlong(v);
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+        t += __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    }
+    return t;
+}
+
+// columns c of the block pair (2 JB of them, rows entries each) between global
+// memory and LDS, all loads of a thread issued before its LDS stores
+template <bool LOAD>
+__device__ __forceinline__ void jb_move(double2* __restrict__ G, int64_t ld, int rows, int m, int P, int Q,
+                                        double2 (*S)[JB_MAXROWS]) {
+    double2 buf[JB_LD];
+#pragma unroll
+    for (int u = 0; u < JB_LD; ++u) {
+        const int i = threadIdx.x + u * 64 * JB;
+        const int c = i / rows, r = i - c * rows;
+        const int g = (c < JB ? P : Q) * JB + (c % JB);
+        const bool ok = c < 2 * JB && g < m;
+        if (LOAD) buf[u] = ok ? G[(int64_t)g * ld + r] : make_double2(0.0, 0.0);
+        else if (ok) G[(int64_t)g * ld + r] = S[c][r];
+    }
+    if (LOAD) {
+#pragma unroll
+        for (int u = 0; u < JB_LD; ++u) {
+            const int i = threadIdx.x + u * 64 * JB;
+            const int c = i / rows, r = i - c * rows;
+            if (c < 2 * JB) S[c][r] = buf[u];
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * JB) void jacobi_block_kernel(double2* __restrict__ X, int rows,
+                                                               double2* __restrict__ V, int m, int nbp, int round,
+                                                               double tol, int* __restrict__ counter) {
+    __shared__ double2 xs[2 * JB][JB_MAXROWS];
+    __shared__ double2 vs[2 * JB][JB_MAXROWS];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int k = blockIdx.x, L = nbp - 1;
+    const int P = k == 0 ? round : (round + k) % L;
+    const int Q = k == 0 ? L : (round - k + L) % L;
+    auto gcol = [&](int c) { return (c < JB ? P : Q) * JB + (c % JB); };
+    jb_move<true>(X, rows, rows, m, P, Q, xs);
+    jb_move<true>(V, m, m, m, P, Q, vs);
+    __syncthreads();
+    int rot = 0;
+    // one rotation of local columns p and q by the calling wavefront
+    auto rotate = [&](int p, int q) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int r = lane; r < rows; r += 64) {
+            const double2 a = xs[p][r], b = xs[q][r];
+            s0 += a.x * a.x + a.y * a.y;
+            s1 += b.x * b.x + b.y * b.y;
+            s2 += a.x * b.x + a.y * b.y;   // conj(a) b
+            s3 += a.x * b.y - a.y * b.x;
+        }
+        const double al = wave_sum_dpp(s0), be = wave_sum_dpp(s1), gr = wave_sum_dpp(s2), gi = wave_sum_dpp(s3);
+        const double ag2 = gr * gr + gi * gi;
+        if (!(al > 0.0 && be > 0.0 && ag2 > tol * tol * al * be)) return;
+        // the rotation of jacobi_round_kernel, with square roots and quotients
+        // from the hardware estimates refined by Newton steps
+        const double iag = rsqrt_nr(ag2);
+        const double zeta = (be - al) * 0.5 * iag;
+        const double q1 = 1.0 + zeta * zeta;
+        const double sq = q1 * rsqrt_nr(q1);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) * recip_nr(fabs(zeta) + sq);
+        const double cs = rsqrt_nr(1.0 + t * t), sn = cs * t;
+        const double2 e = make_double2(gr * iag, -gi * iag);
+        const double2 se = cscale(e, sn), ce = cscale(e, cs);
+        for (int r = lane; r < rows; r += 64) {
+            const double2 a = xs[p][r], b = xs[q][r];
+            xs[p][r] = csub(cscale(a, cs), cmul(se, b));
+            xs[q][r] = cadd(cscale(a, sn), cmul(ce, b));
+        }
+        for (int r = lane; r < m; r += 64) {
+            const double2 a = vs[p][r], b = vs[q][r];
+            vs[p][r] = csub(cscale(a, cs), cmul(se, b));
+            vs[q][r] = cadd(cscale(a, sn), cmul(ce, b));
+        }
+        ++rot;
+    };
+    // the pairs within each block once per sweep (in the sweep's first round every
+    // block sits in exactly one workgroup): circle order on the JB columns of a
+    // block, JB / 2 wavefronts per block
+    if (round == 0) {
+        const int base = (w / (JB / 2)) * JB, pw = w % (JB / 2);
+        for (int ir = 0; ir < JB - 1; ++ir) {
+            const int p = base + (pw == 0 ? ir : (ir + pw) % (JB - 1));
+            const int q = base + (pw == 0 ? JB - 1 : (ir - pw + JB - 1) % (JB - 1));
+            if (gcol(p) < m && gcol(q) < m) rotate(p, q);   // uniform within the wavefront
+            __syncthreads();
+        }
+    }
+    // the cross pairs of the two blocks: JB rounds, wavefront w pairs column w of
+    // the first block with column (w + s) mod JB of the second
+    for (int sft = 0; sft < JB; ++sft) {
+        const int p = w, q = JB + (w + sft) % JB;
+        if (gcol(p) < m && gcol(q) < m) rotate(p, q);
+        __syncthreads();
+    }
+    jb_move<false>(X, rows, rows, m, P, Q, xs);
+    jb_move<false>(V, m, m, m, P, Q, vs);
+    if (lane == 0 && rot > 0) atomicAdd(counter, rot);
+}
+
 __global__ void colnorm_kernel(const double2* __restrict__ X, int rows, double* __restrict__ out) {
     __shared__ double sh[4 * (LR_BS / 64)];
     const double2* x = X + (int64_t)blockIdx.x * rows;
@@ -743,6 +885,7 @@ int jacobi_svd(Ctx& c, double2* X, int m, double2* Uo, double2* Vo, double* sig,
     int* iw = static_cast<int*>(c.dmalloc(sizeof(int) * ((size_t)m + 1)));
     int* counter = iw + m;
     const int mpad = m + (m & 1);
+    const int nb = (m + JB - 1) / JB, nbp = std::max(2, nb + (nb & 1));   // blocks, padded to even
     const double tol = 2.0 * std::sqrt((double)m) * 2.220446049250313e-16;
     hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)m * m, 256)), dim3(256), 0, c.stream, V, (int64_t)m, m, m);
     FDS_HIP_TRY(hipGetLastError());
@@ -752,9 +895,15 @@ int jacobi_svd(Ctx& c, double2* X, int m, double2* Uo, double2* Vo, double* sig,
         {
             KScope _ks(c, "svd_jacobi");
             hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c.stream, counter);
-            for (int rd = 0; rd < mpad - 1; ++rd)
-                hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)(mpad / 2)), dim3(LR_BS), 0, c.stream, X, m,
-                                   V, m, mpad, rd, tol, counter);
+            if (m <= JB_MAXROWS) {
+                for (int rd = 0; rd < nbp - 1; ++rd)
+                    hipLaunchKernelGGL(jacobi_block_kernel, dim3((unsigned)(nbp / 2)), dim3(64 * JB), 0, c.stream, X,
+                                       m, V, m, nbp, rd, tol, counter);
+            } else {
+                for (int rd = 0; rd < mpad - 1; ++rd)
+                    hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)(mpad / 2)), dim3(LR_BS), 0, c.stream, X,
+                                       m, V, m, mpad, rd, tol, counter);
+            }
         }
         FDS_HIP_TRY(hipGetLastError());
         int hc = 0;
