@@ -449,6 +449,9 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
             apply_gram_power(op, -1, T, m);
             {
                 GemmTag tg(c, "gemm_sketch");
+                // n_eff x l output, inner dimension N: few tiles, so the inner
+                // dimension is split into chunks of about 256 (at most 64 parts)
+                SplitHint sh(c, std::max(1, std::min(64, n / 256)));
                 zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
             }
             qr_explicit(c, X, ne, m, tau, Qz, !householder);
