@@ -498,14 +498,16 @@ def assembly_roofline(prof, n, steps, precision, nbw=0):
             "kernel_ms": {k: prof[k][0] / steps for k in ASM_KERNELS if k in prof}}
 
 
-COMPRESSION_KERNELS = ("gemm_sketch", "qr_householder", "qr_update", "qr_form_q", "svd_jacobi", "sketch")
+COMPRESSION_KERNELS = ("gemm_sketch", "qr_gram", "qr_cholesky", "qr_householder", "qr_update", "qr_form_q",
+                       "svd_jacobi", "sketch")
 
 
 def compression_roofline(prof, w, ne, steps):
     """Matrix-core roofline of the randomised compression's sketch products (HIP events
     on the context stream): (2q + 2) products of 8 N n_eff l flop per step (l = r + p,
     the sketch width) over the `gemm_sketch` time, with the compression's other kernel
-    times beside it (QR column steps, their compact-WY products, Jacobi SVD)."""
+    times beside it (CholeskyQR2 Gram products and factorisations, the Householder
+    fallback, the Jacobi SVD)."""
     ell = min(w.rank_cap + w.oversample, ne)
     ms = prof.get("gemm_sketch", (0.0, 0))[0] / steps
     if ms <= 0.0:
