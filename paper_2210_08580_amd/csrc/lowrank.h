@@ -12,7 +12,11 @@ void sketch(Ctx& c, uint64_t seed, int64_t n, int ell, double2* Om);
 // Householder. The upper triangle of A receives R; what lies below it is left
 // unspecified. tau[m] is workspace.
 // Returns true when CholeskyQR2 produced the result.
-bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky = true);
+// basis_only: Q need only be a well-conditioned basis of range(A) (the
+// CholeskyQR path then stops after its first pass, certified ||Q^H Q - I||_F < 1/2;
+// A = Q R still holds); Householder always returns an orthonormal Q.
+bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky = true,
+                 bool basis_only = false);
 // X (m x m) = R^H from a factored A.
 void r_adjoint(Ctx& c, const double2* A, int M, int m, double2* X);
 

@@ -588,15 +588,30 @@ __global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restri
     if (tid == 0) *flag = (check ? *flag : 0) | bad;
 }
 
+// flag |= (||G - I||_F >= 1/2), G m x m (column-major, ld m)
+__global__ __launch_bounds__(256) void gram_check_kernel(const double2* __restrict__ G, int m, int* __restrict__ flag) {
+    __shared__ double sh[4 * 4];
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < m * m; t += 256) {
+        const double2 g = G[t];
+        const double ex = g.x - (t % m == t / m ? 1.0 : 0.0);
+        v[0] += ex * ex + g.y * g.y;
+    }
+    block_sum_k<1, 256>(v, sh);
+    if (threadIdx.x == 0 && !(v[0] < 0.25)) *flag = 1;
+}
+
 // CholeskyQR2 of A (M x m): Q receives the orthonormal factor and the upper
-// triangle of A the R factor. Returns false, with A unchanged, when the
-// factorisation does not certify itself.
-static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q) {
+// triangle of A the R factor. With basis_only the first pass is the result:
+// Q = A R1^{-1} spans range(A) with ||Q^H Q - I||_F < 1/2 (certified by its
+// Gram matrix), which is what a subspace iteration step needs. Returns false,
+// with A unchanged, when the factorisation does not certify itself.
+static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q, bool basis_only) {
     if (m > CQ_MAX) return false;
     const size_t mm = (size_t)m * m;
     double2* G = static_cast<double2*>(c.dmalloc(sizeof(double2) * mm * 4));
     double2 *R1 = G + mm, *R2 = G + 2 * mm, *Ri = G + 3 * mm;
-    double2* Q1 = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m));
+    double2* Q1 = basis_only ? nullptr : static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m));
     int* flag = static_cast<int*>(c.dmalloc(sizeof(int)));
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
     GemmTag tg(c, "qr_gram");
@@ -606,10 +621,16 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q) {
     // the Gram product has only a few output tiles: split its long inner dimension
     // into chunks of about 64 rows (at most 64 parts) so that it fills the chip
     const int gsplit = std::max(1, std::min(64, (M + 63) / 64));
+    if (basis_only) out[0] = Q;
     for (int pass = 0; pass < 2; ++pass) {
         {
             SplitHint sh(c, gsplit);
             zgemm(c, OP_C, OP_N, m, m, M, one, in[pass], M, in[pass], M, zero, G, m);
+        }
+        if (basis_only && pass == 1) {
+            KScope _ks(c, "qr_cholesky");
+            hipLaunchKernelGGL(gram_check_kernel, dim3(1), dim3(256), 0, c.stream, G, m, flag);
+            break;
         }
         {
             KScope _ks(c, "qr_cholesky");
@@ -617,20 +638,27 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q) {
         }
         FDS_HIP_TRY(hipGetLastError());
         zgemm(c, OP_N, OP_N, M, m, m, one, in[pass], M, Ri, m, zero, out[pass], M);
+        if (basis_only) in[1] = Q;
     }
     int bad = 1;
     FDS_HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-    if (!bad) zgemm(c, OP_N, OP_N, m, m, m, one, R2, m, R1, m, zero, A, M);
+    if (!bad) {
+        if (basis_only)
+            FDS_HIP_TRY(hipMemcpy2DAsync(A, sizeof(double2) * (size_t)M, R1, sizeof(double2) * (size_t)m,
+                                         sizeof(double2) * (size_t)m, (size_t)m, hipMemcpyDeviceToDevice, c.stream));
+        else
+            zgemm(c, OP_N, OP_N, m, m, m, one, R2, m, R1, m, zero, A, M);
+    }
     c.dfree(G);
     c.dfree(Q1);
     c.dfree(flag);
     return !bad;
 }
 
-bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky) {
+bool qr_explicit(Ctx& c, double2* A, int M, int m, double2* tau, double2* Q, bool cholesky, bool basis_only) {
     FDS_REQUIRE(m >= 1 && M >= m && Q, FDS_ERR_ARG, "QR needs rows >= columns >= 1 and an output");
-    if (cholesky && cholesky_qr2(c, A, M, m, Q)) return true;
+    if (cholesky && cholesky_qr2(c, A, M, m, Q, basis_only)) return true;
     householder_qr(c, A, M, m, tau, Q);
     return false;
 }

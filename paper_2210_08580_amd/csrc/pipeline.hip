@@ -454,7 +454,9 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
                 SplitHint sh(c, std::max(1, std::min(64, n / 256)));
                 zgemm(c, OP_T, OP_N, ne, m, n, kOne, op.Bt, n, T, n, kZero, X, ne);
             }
-            qr_explicit(c, X, ne, m, tau, Qz, !householder);
+            // the intermediate bases only carry the span forward; the last Q_z is the
+            // orthonormal range basis of the projection
+            qr_explicit(c, X, ne, m, tau, Qz, !householder, it < power_iters);
             if (it == power_iters) break;
             // Z = B_y^H Qz ; T = orth(Z)
             {
@@ -462,7 +464,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
                 zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
             }
             apply_gram_power(op, -1, Z, m);
-            qr_explicit(c, Z, n, m, tau, Qp, !householder);
+            qr_explicit(c, Z, n, m, tau, Qp, !householder, true);
             std::swap(T, Qp);
         }
         // projected block B = Q^H A_y = Qz^H B_y, held as B^H = B_y^H Qz
