@@ -951,7 +951,11 @@ void gj_inverse(Ctx& c, double2* A, double2* Ainv, int r, double* hstats) {
     FDS_HIP_TRY(hipGetLastError());
     FDS_HIP_TRY(hipMemcpyAsync(Ainv, in + (size_t)r * r, sizeof(double2) * (size_t)r * r, hipMemcpyDeviceToDevice,
                                c.stream));
-    zgemm(c, OP_N, OP_N, r, r, r, make_double2(1.0, 0.0), A, r, Ainv, r, make_double2(0.0, 0.0), out, r);
+    {
+        // few output tiles: split the inner dimension into 64-long chunks
+        SplitHint sh(c, std::max(1, std::min(64, r / 64)));
+        zgemm(c, OP_N, OP_N, r, r, r, make_double2(1.0, 0.0), A, r, Ainv, r, make_double2(0.0, 0.0), out, r);
+    }
     {
         KScope _ks(c, "gj_inverse");
         hipLaunchKernelGGL(inv_check_kernel, dim3(ncb), dim3(256), 0, c.stream, out, A, r, cpart);

@@ -603,7 +603,11 @@ static void woodbury_apply(Op& op, double2* b, int64_t nrhs, double2* z) {
     const int n = (int)op.n, r = op.rank;
     const double ib = 1.0 / op.beta;
     if (r > 0) {
-        zgemm(c, OP_N, OP_N, r, (int)nrhs, n, kOne, op.Wr, r, b, n, kZero, z, r);
+        {
+            // r x nrhs output with the long inner dimension n: 256-long chunks of it
+            SplitHint sh(c, std::max(1, std::min(64, n / 256)));
+            zgemm(c, OP_N, OP_N, r, (int)nrhs, n, kOne, op.Wr, r, b, n, kZero, z, r);
+        }
         zgemm(c, OP_N, OP_N, n, (int)nrhs, r, make_double2(-ib * ib, 0.0), op.Up, n, z, r,
               make_double2(ib, 0.0), b, n);
     } else {
@@ -810,7 +814,10 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
             // res = w - beta j - V_g (Bt^T j)
             FDS_HIP_TRY(hipMemcpyAsync(res, w, blk, hipMemcpyDeviceToDevice, c.stream));
             axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, (int64_t)n * nrhs);
-            zgemm(c, OP_N, OP_N, ne, (int)nrhs, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
+            {
+                SplitHint sh(c, std::max(1, std::min(64, n / 256)));
+                zgemm(c, OP_N, OP_N, ne, (int)nrhs, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
+            }
             zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
         }
         if (stats) {
