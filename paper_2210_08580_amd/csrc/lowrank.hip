@@ -361,21 +361,19 @@ __device__ __forceinline__ void tile_sum(double2 (&acc)[CT][CT], int Ls) {
         }
 }
 
-// G (m x m Hermitian, column-major, ld m) = L L^H. Writes R = L^H and Ri = L^{-H}
-// (m x m upper triangular, zeros below). flag: set to 1 when a pivot is not
-// positive or, with check, when ||G - I||_F >= 1/2; with check the previous flag
-// is kept (or-ed), without it the flag is overwritten.
+// G (m x m Hermitian, column-major, ld m) = L L^H. Writes R = L^H (m x m upper
+// triangular, zeros below). flag: set to 1 when a pivot is not positive or, with
+// check, when ||G - I||_F >= 1/2; with check the previous flag is kept (or-ed),
+// without it the flag is overwritten.
 //
-// Both halves go CB columns per step. The inner products over finished columns
-// are a small matrix product: CT x CT register tiles, each split over Ls lanes.
-// The CB x CB triangular part within a step is then solved one row per thread
-// (the factorisation's diagonal block by wavefront 0 first).
-__global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restrict__ G, int m, int check,
-                                                         double2* __restrict__ R, double2* __restrict__ Ri,
-                                                         int* __restrict__ flag) {
+// CB columns per step. The inner products over finished columns are a small
+// matrix product: CT x CT register tiles, each split over Ls lanes. The step's
+// CB x CB diagonal block is then factored by wavefront 0 and the rest of the
+// step solved one row per thread.
+__global__ __launch_bounds__(CQ_BS) void chol_kernel(const double2* __restrict__ G, int m, int check,
+                                                     double2* __restrict__ R, int* __restrict__ flag) {
     __shared__ double2 L[CQ_TRI];       // packed lower triangle
-    __shared__ double pv[CQ_MAX];       // 1 / pivot while factoring, then 1 / L(j, j)
-    __shared__ double2 blk[CB][CB];     // a step's diagonal block of L during the inversion
+    __shared__ double pv[CQ_MAX];       // 1 / pivot
     __shared__ double red[CQ_BS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double dev = 0.0;
@@ -504,88 +502,75 @@ __global__ __launch_bounds__(CQ_BS) void chol_inv_kernel(const double2* __restri
         for (int r = lane; r < m; r += 64)
             R[(size_t)c * m + r] = r < c ? cconj(L[cq_idx(m, c, r)])
                                          : make_double2(r == c ? L[cq_idx(m, r, r)].x : 0.0, 0.0);
-    if (tid < m) pv[tid] = 1.0 / L[cq_idx(m, tid, tid)].x;
-    __syncthreads();
+    if (tid == 0) *flag = (check ? *flag : 0) | bad;
+}
 
-    // X = L^{-1} in place below the diagonal (the diagonal of X kept in pv),
-    // column blocks from the right: for a row r and a column c of the block,
-    //   X(r, c) = -X(c, c) sum_{l=c+1}^{r} X(r, l) L(l, c),
-    // the terms past the block (finished columns) as a tiled product first, then
-    // the block's own columns from its right end, one row per thread.
-    for (int j = ((m - 1) / CB) * CB; j >= 0; j -= CB) {
-        const int bw = min(CB, m - j), jb = j + bw, ub = m - jb;
-        const int tiles = ((ub + CT - 1) / CT) * (CB / CT), Ls = slices(tiles, ub);
-        const int ti = tid / Ls, s = tid % Ls;
-        const bool act = ti < tiles;
-        const int r0 = jb + (ti / (CB / CT)) * CT, c0 = (ti % (CB / CT)) * CT;
-        double2 acc[CT][CT] = {};
-        if (act) {
-            const int lend = min(r0 + CT - 1, m - 1);
-            int cb[CT];   // the block's columns, indexed by row
-#pragma unroll
-            for (int k = 0; k < CT; ++k) cb[k] = cq_idx(m, 0, min(j + c0 + k, m - 1));
-            for (int l = jb + s; l <= lend; l += Ls) {
-                const double2* col = L + cq_idx(m, 0, l);
-                double2 a[CT], b[CT];
-#pragma unroll
-                for (int i = 0; i < CT; ++i) {
-                    const int r = r0 + i;
-                    a[i] = (r < m && l <= r) ? (l < r ? col[r] : make_double2(pv[r], 0.0)) : make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int k = 0; k < CT; ++k) b[k] = c0 + k < bw ? L[cb[k] + l] : make_double2(0.0, 0.0);
-#pragma unroll
-                for (int i = 0; i < CT; ++i)
-#pragma unroll
-                    for (int k = 0; k < CT; ++k) cfma(acc[i][k], a[i], b[k]);
-            }
-        }
-        tile_sum(acc, Ls);
-        for (int t = tid; t < CB * CB; t += CQ_BS) {
-            const int a = t / CB, c = t % CB;
-            blk[a][c] = (a < bw && c <= a) ? L[cq_idx(m, j + a, j + c)] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        if (act && s == 0) {   // the partial sums replace L below the block
-#pragma unroll
-            for (int i = 0; i < CT; ++i)
-#pragma unroll
-                for (int k = 0; k < CT; ++k)
-                    if (r0 + i < m && c0 + k < bw) L[cq_idx(m, r0 + i, j + c0 + k)] = acc[i][k];
+// Y = R^{-1} for R upper triangular (m x m, column-major, ld m) from Y R = I,
+// whose rows are independent: workgroup w forms rows r0 = 16 w .. r0 + 15,
+// column blocks C = c0 .. c0 + 15 from the left (c0 >= r0):
+//   T = -Y[rows, r0 : c0] R[r0 : c0, C]                    (one entry per thread)
+//   y(i, c) = (T(i, c) + [r0 + i == c] - sum_{q in C, q < c} y(i, q) R(q, c)) / R(c, c)
+// the latter one row per thread, left to right. Entries left of the diagonal are 0.
+constexpr int TI_B = 16;
+
+__global__ __launch_bounds__(256) void tri_inv_kernel(const double2* __restrict__ R, int m,
+                                                      double2* __restrict__ Y) {
+    __shared__ double2 ys[TI_B][CQ_MAX];        // this workgroup's rows of Y
+    __shared__ double2 rb[CQ_MAX][TI_B + 1];    // the column block of R, rows r0 .. c0 + 15
+    __shared__ double2 ts[TI_B][TI_B + 1];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * TI_B;
+    for (int t = tid; t < TI_B * m; t += 256) ys[t / m][t % m] = make_double2(0.0, 0.0);
+    for (int c0 = r0; c0 < m; c0 += TI_B) {
+        const int cw = min(TI_B, m - c0), lend = c0 + cw;
+        __syncthreads();   // the previous block's ys and rb reads are done
+        for (int t = tid; t < (lend - r0) * cw; t += 256) {
+            const int j = t / (lend - r0), l = r0 + t % (lend - r0);
+            rb[l][j] = R[(size_t)(c0 + j) * m + l];
         }
         __syncthreads();
         {
-            const int r = j + tid;
-            if (r < m) {
-                const bool below = r >= jb;
-                const int top = below ? bw - 1 : r - j;
-                double2 x[CB];
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    x[c] = below ? (c < bw ? L[cq_idx(m, r, j + c)] : make_double2(0.0, 0.0))
-                                 : make_double2(c == top ? pv[r] : 0.0, 0.0);
-#pragma unroll
-                for (int c = CB - 1; c >= 0; --c) {
-                    if (c < top || (below && c == top)) {
-                        double2 sum = x[c];
-#pragma unroll
-                        for (int e = c + 1; e < CB; ++e)
-                            if (e <= top) cfma(sum, x[e], blk[e][c]);
-                        const double dc = -pv[j + c];
-                        x[c] = make_double2(dc * sum.x, dc * sum.y);
-                    }
+            const int i = tid / TI_B, j = tid % TI_B;
+            double2 acc = make_double2(0.0, 0.0);
+            if (j < cw)
+                for (int l = r0; l < c0; ++l) {
+                    const double2 a = ys[i][l], b = rb[l][j];
+                    acc.x -= a.x * b.x - a.y * b.y;
+                    acc.y -= a.x * b.y + a.y * b.x;
                 }
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c < top || (below && c == top)) L[cq_idx(m, r, j + c)] = x[c];
-            }
+            ts[i][j] = acc;
         }
         __syncthreads();
+        if (tid < TI_B && r0 + tid < m) {
+            const int i = tid, r = r0 + i;
+            double2 yv[TI_B];
+#pragma unroll
+            for (int j = 0; j < TI_B; ++j) {
+                yv[j] = make_double2(0.0, 0.0);
+                const int c = c0 + j;
+                if (j >= cw || c < r) continue;
+                double2 sacc = ts[i][j];
+                if (c == r) sacc.x += 1.0;
+#pragma unroll
+                for (int q = 0; q < j; ++q) {
+                    const double2 b = rb[c0 + q][j];
+                    sacc.x -= yv[q].x * b.x - yv[q].y * b.y;
+                    sacc.y -= yv[q].x * b.y + yv[q].y * b.x;
+                }
+                const double2 d = rb[c][j];   // real positive diagonal of a Cholesky factor
+                const double id = 1.0 / d.x;
+                yv[j] = make_double2(sacc.x * id, sacc.y * id);
+            }
+#pragma unroll
+            for (int j = 0; j < TI_B; ++j)
+                if (j < cw) ys[i][c0 + j] = yv[j];
+        }
     }
-    for (int c = wave; c < m; c += CQ_BS / 64)
-        for (int r = lane; r < m; r += 64)
-            Ri[(size_t)c * m + r] = r < c ? cconj(L[cq_idx(m, c, r)]) : make_double2(r == c ? pv[r] : 0.0, 0.0);
-    if (tid == 0) *flag = (check ? *flag : 0) | bad;
+    __syncthreads();
+    for (int t = tid; t < TI_B * m; t += 256) {
+        const int i = t % TI_B, c = t / TI_B;
+        if (r0 + i < m) Y[(size_t)c * m + r0 + i] = ys[i][c];
+    }
 }
 
 // flag |= (||G - I||_F >= 1/2), G m x m (column-major, ld m)
@@ -634,7 +619,9 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q, bool basi
         }
         {
             KScope _ks(c, "qr_cholesky");
-            hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CQ_BS), 0, c.stream, G, m, pass, R[pass], Ri, flag);
+            hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CQ_BS), 0, c.stream, G, m, pass, R[pass], flag);
+            hipLaunchKernelGGL(tri_inv_kernel, dim3((unsigned)((m + TI_B - 1) / TI_B)), dim3(256), 0, c.stream,
+                               R[pass], m, Ri);
         }
         FDS_HIP_TRY(hipGetLastError());
         zgemm(c, OP_N, OP_N, M, m, m, one, in[pass], M, Ri, m, zero, out[pass], M);
