@@ -63,6 +63,21 @@ __device__ __forceinline__ void block_sum_k(double (&v)[K], double* sh) {
     }
 }
 
+// 1/sqrt(x) and 1/x for x > 0: hardware estimates and two Newton steps each
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double recip_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 // ----------------------------------------------------------------- sketch
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), one output step of state z.
 __device__ __forceinline__ uint64_t splitmix64_out(uint64_t z) {
@@ -374,6 +389,7 @@ __global__ __launch_bounds__(CQ_BS) void chol_kernel(const double2* __restrict__
                                                      double2* __restrict__ R, int* __restrict__ flag) {
     __shared__ double2 L[CQ_TRI];       // packed lower triangle
     __shared__ double pv[CQ_MAX];       // 1 / pivot
+    __shared__ double2 colc[CB];        // a column of the diagonal block
     __shared__ double red[CQ_BS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double dev = 0.0;
@@ -437,22 +453,43 @@ __global__ __launch_bounds__(CQ_BS) void chol_kernel(const double2* __restrict__
             }
         }
         __syncthreads();
-        if (wave == 0) {   // the diagonal block, right-looking, in place
-            for (int c = 0; c < bw; ++c) {
-                const double id = 1.0 / L[cq_idx(m, j + c, j + c)].x;
-                for (int t = lane; t < CB * CB; t += 64) {
-                    const int a = t / CB, e = t % CB;
-                    if (c < e && e <= a && a < bw) {
-                        const double2 la = L[cq_idx(m, j + a, j + c)], le = L[cq_idx(m, j + e, j + c)];
-                        double2& x = L[cq_idx(m, j + a, j + e)];
-                        x.x -= id * (la.x * le.x + la.y * le.y);
-                        x.y -= id * (la.y * le.x - la.x * le.y);
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+        if (wave == 0) {
+            // the diagonal block, right-looking, in the registers of wavefront 0:
+            // lane 4a + q holds D(a, q + 4k), k = 0..3; column c goes round through colc
+            const int a = lane >> 2, q = lane & 3;
+            double2 x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e = q + 4 * k;
+                x[k] = (a < bw && e <= a) ? L[cq_idx(m, j + a, j + e)] : make_double2(0.0, 0.0);
             }
-            if (lane < bw) pv[j + lane] = 1.0 / L[cq_idx(m, j + lane, j + lane)].x;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < bw) {   // uniform
+                    if (q == (c & 3)) colc[a] = x[c >> 2];
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    const double id = recip_nr(colc[c].x);
+                    const double2 la = colc[a];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int e = q + 4 * k;
+                        if (c < e && e <= a && a < bw) {   // D(a, e) -= D(a, c) conj(D(e, c)) / d_c
+                            const double2 le = colc[e];
+                            x[k].x -= id * (la.x * le.x + la.y * le.y);
+                            x[k].y -= id * (la.y * le.x - la.x * le.y);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();   // colc is rewritten by the next column
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e = q + 4 * k;
+                if (a < bw && e <= a) L[cq_idx(m, j + a, j + e)] = x[k];
+                if (a < bw && e == a) pv[j + a] = 1.0 / x[k].x;
+            }
         }
         __syncthreads();
         {   // rows below the block: the triangular part, one row per thread
@@ -727,21 +764,6 @@ __global__ __launch_bounds__(LR_BS) void jacobi_round_kernel(double2* __restrict
 constexpr int JB = 8;
 constexpr int JB_MAXROWS = 312;   // X and V columns of two blocks: 2 x 16 x 312 x 16 B of LDS
 constexpr int JB_LD = (2 * JB * JB_MAXROWS + 64 * JB - 1) / (64 * JB);   // column entries per thread
-
-// 1/sqrt(x) and 1/x for x > 0: hardware estimates and two Newton steps each
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    return y;
-}
-
-__device__ __forceinline__ double recip_nr(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    y = fma(y, fma(-x, y, 1.0), y);
-    y = fma(y, fma(-x, y, 1.0), y);
-    return y;
-}
 
 // sum over the wavefront without LDS traffic: DPP sums within rows of 16 lanes,
 // then the four row sums read out of lanes 0, 16, 32 and 48
