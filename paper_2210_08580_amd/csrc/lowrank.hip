@@ -16,7 +16,7 @@
 // Appl. 13, 1992) rotates pairs of columns of X until they are mutually
 // orthogonal: X V = U Sigma with V unitary. Up to 312 columns the columns are
 // grouped in blocks of 8 and the block pairs visited in the round-robin (circle)
-// order, one launch per round, each workgroup sweeping the 16 columns of its
+// order, one launch per round, each workgroup rotating the 16 columns of its
 // pair in LDS; wider matrices go pair by pair (m/2 disjoint pairs per launch,
 // one workgroup per pair).
 // The relative accuracy of small singular values is what the truncation rule
@@ -761,9 +761,12 @@ __global__ __launch_bounds__(LR_BS) void jacobi_round_kernel(double2* __restrict
 // sweep's first round also the pairs within each block, with the threshold and
 // rotation of jacobi_round_kernel. A sweep (every block pair once) visits every
 // column pair exactly once, so it is a cyclic Jacobi ordering.
-constexpr int JB = 8;
-constexpr int JB_MAXROWS = 312;   // X and V columns of two blocks: 2 x 16 x 312 x 16 B of LDS
-constexpr int JB_LD = (2 * JB * JB_MAXROWS + 64 * JB - 1) / (64 * JB);   // column entries per thread
+// rows held in LDS for blocks of B columns: X and V columns of two blocks,
+// 2 x 2B x rows x 16 B within 156 KiB (312 rows for B = 8, 156 for B = 16)
+template <int B>
+constexpr int jb_maxrows() { return 159744 / (2 * 2 * B * 16); }
+template <int B>
+constexpr int jb_ld() { return (2 * B * jb_maxrows<B>() + 64 * B - 1) / (64 * B); }   // entries per thread
 
 // sum over the wavefront without LDS traffic: DPP sums within rows of 16 lanes,
 // then the four row sums read out of lanes 0, 16, 32 and 48
@@ -782,9 +785,10 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 
 // columns c of the block pair (2 JB of them, rows entries each) between global
 // memory and LDS, all loads of a thread issued before its LDS stores
-template <bool LOAD>
+template <int JB, bool LOAD>
 __device__ __forceinline__ void jb_move(double2* __restrict__ G, int64_t ld, int rows, int m, int P, int Q,
-                                        double2 (*S)[JB_MAXROWS]) {
+                                        double2 (*S)[jb_maxrows<JB>()]) {
+    constexpr int JB_LD = jb_ld<JB>();
     double2 buf[JB_LD];
 #pragma unroll
     for (int u = 0; u < JB_LD; ++u) {
@@ -805,18 +809,20 @@ __device__ __forceinline__ void jb_move(double2* __restrict__ G, int64_t ld, int
     }
 }
 
+template <int JB>
 __global__ __launch_bounds__(64 * JB) void jacobi_block_kernel(double2* __restrict__ X, int rows,
                                                                double2* __restrict__ V, int m, int nbp, int round,
                                                                double tol, int* __restrict__ counter) {
-    __shared__ double2 xs[2 * JB][JB_MAXROWS];
-    __shared__ double2 vs[2 * JB][JB_MAXROWS];
+    constexpr int MR = jb_maxrows<JB>();
+    __shared__ double2 xs[2 * JB][MR];
+    __shared__ double2 vs[2 * JB][MR];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int k = blockIdx.x, L = nbp - 1;
     const int P = k == 0 ? round : (round + k) % L;
     const int Q = k == 0 ? L : (round - k + L) % L;
     auto gcol = [&](int c) { return (c < JB ? P : Q) * JB + (c % JB); };
-    jb_move<true>(X, rows, rows, m, P, Q, xs);
-    jb_move<true>(V, m, m, m, P, Q, vs);
+    jb_move<JB, true>(X, rows, rows, m, P, Q, xs);
+    jb_move<JB, true>(V, m, m, m, P, Q, vs);
     __syncthreads();
     int rot = 0;
     // one rotation of local columns p and q by the calling wavefront
@@ -873,8 +879,8 @@ __global__ __launch_bounds__(64 * JB) void jacobi_block_kernel(double2* __restri
         if (gcol(p) < m && gcol(q) < m) rotate(p, q);
         __syncthreads();
     }
-    jb_move<false>(X, rows, rows, m, P, Q, xs);
-    jb_move<false>(V, m, m, m, P, Q, vs);
+    jb_move<JB, false>(X, rows, rows, m, P, Q, xs);
+    jb_move<JB, false>(V, m, m, m, P, Q, vs);
     if (lane == 0 && rot > 0) atomicAdd(counter, rot);
 }
 
@@ -922,7 +928,10 @@ int jacobi_svd(Ctx& c, double2* X, int m, double2* Uo, double2* Vo, double* sig,
     int* iw = static_cast<int*>(c.dmalloc(sizeof(int) * ((size_t)m + 1)));
     int* counter = iw + m;
     const int mpad = m + (m & 1);
-    const int nb = (m + JB - 1) / JB, nbp = std::max(2, nb + (nb & 1));   // blocks, padded to even
+    // blocks of 8 columns (16-column blocks, 5 workgroups of 16 wavefronts at 138
+    // columns, took 4.1 ms against 3.0 ms: fewer workgroups, twice the rounds per launch)
+    constexpr int jb = 8;
+    const int nb = (m + jb - 1) / jb, nbp = std::max(2, nb + (nb & 1));   // blocks, padded to even
     const double tol = 2.0 * std::sqrt((double)m) * 2.220446049250313e-16;
     hipLaunchKernelGGL(eye_kernel, dim3(nblk((int64_t)m * m, 256)), dim3(256), 0, c.stream, V, (int64_t)m, m, m);
     FDS_HIP_TRY(hipGetLastError());
@@ -932,10 +941,10 @@ int jacobi_svd(Ctx& c, double2* X, int m, double2* Uo, double2* Vo, double* sig,
         {
             KScope _ks(c, "svd_jacobi");
             hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c.stream, counter);
-            if (m <= JB_MAXROWS) {
+            if (m <= jb_maxrows<jb>()) {
                 for (int rd = 0; rd < nbp - 1; ++rd)
-                    hipLaunchKernelGGL(jacobi_block_kernel, dim3((unsigned)(nbp / 2)), dim3(64 * JB), 0, c.stream, X,
-                                       m, V, m, nbp, rd, tol, counter);
+                    hipLaunchKernelGGL(jacobi_block_kernel<jb>, dim3((unsigned)(nbp / 2)), dim3(64 * jb), 0, c.stream,
+                                       X, m, V, m, nbp, rd, tol, counter);
             } else {
                 for (int rd = 0; rd < mpad - 1; ++rd)
                     hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)(mpad / 2)), dim3(LR_BS), 0, c.stream, X,

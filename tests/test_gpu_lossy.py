@@ -19,6 +19,8 @@ CASES = [
     ("ellipse", 300, 5.0, "cfie", 61, 30, 10, 2, 1e-10, True),   # CFIE
     ("star", 600, 10.0, "efie", 63, 40, 10, 0, 0.0, True),       # no power iterations
     ("star", 600, 10.0, "efie", 63, 50, 10, 2, 1e-9, True),
+    # l >= n_eff with 156 < n_eff <= 312: Householder QR, Jacobi SVD in blocks of 8 columns
+    ("ellipse", 600, 5.0, "efie", 201, 210, 10, 0, 1e-6, True),
     # l >= n_eff with n_eff > 312: Householder QR and the pair-by-pair Jacobi SVD
     ("ellipse", 800, 5.0, "efie", 321, 330, 10, 0, 1e-6, True),
 ]
