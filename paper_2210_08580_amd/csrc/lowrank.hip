@@ -610,6 +610,118 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(const double2* __restrict_
     }
 }
 
+// Gram matrix G = A^H A of a tall block (M x m, m <= GT_COLS, column-major, ld
+// lda) on the FP64 matrix cores. Workgroup b sums rows [b GT_ROWS, (b + 1) GT_ROWS)
+// into the 45 lower 16 x 16 tiles of its partial (the columns zero-padded to
+// GT_COLS); gram_tall_reduce_kernel adds the partials in a fixed order and fills
+// the upper triangle by conjugate symmetry. Per tile, Gauss's three real products
+// with a = conj(A(k, i)), b = A(k, j): T1 = ar br, T2 = ai bi,
+// T3 = (ar - ai)(br + bi); Re G = T1 + T2, Im G = T3 - T1 + T2.
+typedef double gd4 __attribute__((ext_vector_type(4)));
+constexpr int GT_COLS = 144;                      // 9 column blocks of 16 (>= CQ_MAX)
+constexpr int GT_T = GT_COLS / 16;
+constexpr int GT_NTILE = GT_T * (GT_T + 1) / 2;   // 45 lower tiles
+constexpr int GT_ROWS = 64;
+constexpr int GT_WAVES = 8;
+constexpr int GT_TPW = (GT_NTILE + GT_WAVES - 1) / GT_WAVES;   // tiles per wavefront (6)
+
+__global__ __launch_bounds__(64 * GT_WAVES) void gram_tall_kernel(const double2* __restrict__ A, int64_t lda, int M,
+                                                                  int m, double2* __restrict__ part) {
+    __shared__ double sr[GT_ROWS][GT_COLS + 1];
+    __shared__ double si[GT_ROWS][GT_COLS + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.x * GT_ROWS;
+    for (int t = tid; t < GT_ROWS * GT_COLS; t += 64 * GT_WAVES) {
+        const int k = t % GT_ROWS, c = t / GT_ROWS;   // consecutive threads: consecutive rows of a column
+        const double2 v = (r0 + k < M && c < m) ? A[(int64_t)c * lda + r0 + k] : make_double2(0.0, 0.0);
+        sr[k][c] = v.x;
+        si[k][c] = v.y;
+    }
+    __syncthreads();
+    // this wavefront's tiles: w, w + GT_WAVES, ... in the row-major order of the lower triangle
+    int ti[GT_TPW], tj[GT_TPW];
+#pragma unroll
+    for (int u = 0; u < GT_TPW; ++u) {
+        int t = w + u * GT_WAVES, i = 0;
+        while (t > i) { t -= i + 1; ++i; }   // t-th entry of row i: (i, t), t <= i
+        ti[u] = i;
+        tj[u] = t;
+    }
+    gd4 t1[GT_TPW], t2[GT_TPW], t3[GT_TPW];
+#pragma unroll
+    for (int u = 0; u < GT_TPW; ++u) {
+        t1[u] = gd4{0.0, 0.0, 0.0, 0.0};
+        t2[u] = gd4{0.0, 0.0, 0.0, 0.0};
+        t3[u] = gd4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int ln = lane & 15, lk = lane >> 4;
+    for (int kk = 0; kk < GT_ROWS; kk += 4) {
+        const int k = kk + lk;
+#pragma unroll
+        for (int u = 0; u < GT_TPW; ++u) {
+            if (w + u * GT_WAVES >= GT_NTILE) continue;   // uniform
+            const int ci = ti[u] * 16 + ln, cj = tj[u] * 16 + ln;
+            const double ar = sr[k][ci], ai = si[k][ci], br = sr[k][cj], bi = si[k][cj];
+            t1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, t1[u], 0, 0, 0);
+            t2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, t2[u], 0, 0, 0);
+            t3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar - ai, br + bi, t3[u], 0, 0, 0);
+        }
+    }
+    double2* P = part + (int64_t)blockIdx.x * GT_COLS * GT_COLS;   // column-major GT_COLS x GT_COLS
+#pragma unroll
+    for (int u = 0; u < GT_TPW; ++u) {
+        if (w + u * GT_WAVES >= GT_NTILE) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ti[u] * 16 + lk + 4 * v, j = tj[u] * 16 + ln;
+            P[(int64_t)j * GT_COLS + i] = make_double2(t1[u][v] + t2[u][v], t3[u][v] - t1[u][v] + t2[u][v]);
+        }
+    }
+}
+
+// G (m x m, ld m) = sum of the nb partials' lower tiles, upper triangle by
+// symmetry. Workgroup j takes column j of the stored tiles (rows from the first
+// row of its tile block on, contiguous in every partial) and writes G(i, j) and
+// G(j, i) = conj(G(i, j)).
+__global__ __launch_bounds__(GT_COLS) void gram_tall_reduce_kernel(const double2* __restrict__ part, int nb, int m,
+                                                                   double2* __restrict__ G) {
+    const int j = blockIdx.x;
+    const int i = (j / 16) * 16 + threadIdx.x;
+    if (i >= m) return;
+    // eight partial sums (partials b = 8q + u go to sum u) keep eight loads in flight
+    const double2* src = part + (int64_t)j * GT_COLS + i;
+    constexpr int64_t ST = (int64_t)GT_COLS * GT_COLS;
+    double sx[8], sy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sx[u] = sy[u] = 0.0;
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 v = src[(b + u) * ST];
+            sx[u] += v.x;
+            sy[u] += v.y;
+        }
+    }
+    for (int u = 0; b < nb; ++b, ++u) {
+        const double2 v = src[b * ST];
+        sx[u] += v.x;
+        sy[u] += v.y;
+    }
+    const double2 s = make_double2(((sx[0] + sx[1]) + (sx[2] + sx[3])) + ((sx[4] + sx[5]) + (sx[6] + sx[7])),
+                                   ((sy[0] + sy[1]) + (sy[2] + sy[3])) + ((sy[4] + sy[5]) + (sy[6] + sy[7])));
+    G[(int64_t)j * m + i] = s;
+    if (i / 16 != j / 16) G[(int64_t)i * m + j] = make_double2(s.x, -s.y);   // the diagonal tiles are stored whole
+}
+
+static void gram_tall(Ctx& c, const double2* A, int M, int m, double2* G, double2* part) {
+    const int nb = (M + GT_ROWS - 1) / GT_ROWS;
+    KScope _ks(c, "qr_gram");
+    hipLaunchKernelGGL(gram_tall_kernel, dim3((unsigned)nb), dim3(64 * GT_WAVES), 0, c.stream, A, (int64_t)M, M, m,
+                       part);
+    hipLaunchKernelGGL(gram_tall_reduce_kernel, dim3((unsigned)m), dim3(GT_COLS), 0, c.stream, part, nb, m, G);
+}
+
 // flag |= (||G - I||_F >= 1/2), G m x m (column-major, ld m)
 __global__ __launch_bounds__(256) void gram_check_kernel(const double2* __restrict__ G, int m, int* __restrict__ flag) {
     __shared__ double sh[4 * 4];
@@ -635,20 +747,17 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q, bool basi
     double2 *R1 = G + mm, *R2 = G + 2 * mm, *Ri = G + 3 * mm;
     double2* Q1 = basis_only ? nullptr : static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m));
     int* flag = static_cast<int*>(c.dmalloc(sizeof(int)));
+    // partial Gram matrices, one per 64-row chunk
+    double2* part = static_cast<double2*>(
+        c.dmalloc(sizeof(double2) * GT_COLS * GT_COLS * (size_t)((M + GT_ROWS - 1) / GT_ROWS)));
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
     GemmTag tg(c, "qr_gram");
     double2* R[2] = {R1, R2};
     const double2* in[2] = {A, Q1};
     double2* out[2] = {Q1, Q};
-    // the Gram product has only a few output tiles: split its long inner dimension
-    // into chunks of about 64 rows (at most 64 parts) so that it fills the chip
-    const int gsplit = std::max(1, std::min(64, (M + 63) / 64));
     if (basis_only) out[0] = Q;
     for (int pass = 0; pass < 2; ++pass) {
-        {
-            SplitHint sh(c, gsplit);
-            zgemm(c, OP_C, OP_N, m, m, M, one, in[pass], M, in[pass], M, zero, G, m);
-        }
+        gram_tall(c, in[pass], M, m, G, part);
         if (basis_only && pass == 1) {
             KScope _ks(c, "qr_cholesky");
             hipLaunchKernelGGL(gram_check_kernel, dim3(1), dim3(256), 0, c.stream, G, m, flag);
@@ -677,6 +786,7 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q, bool basi
     c.dfree(G);
     c.dfree(Q1);
     c.dfree(flag);
+    c.dfree(part);
     return !bad;
 }
 
