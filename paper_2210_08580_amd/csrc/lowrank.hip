@@ -349,32 +349,8 @@ __device__ __forceinline__ double group_sum(double v, int Ls) {
     return v;
 }
 
-constexpr int CB = 16;   // columns per step of the factorisation and of the inversion
-constexpr int CT = 4;    // register tile: CT rows x CT columns per thread
-
-// lanes splitting one tile's inner products: at most 16, the tiles times the
-// lanes within the workgroup, and at least four terms per lane
-__device__ __forceinline__ int slices(int tiles, int len) {
-    int Ls = 16;
-    while (Ls > 1 && (tiles * Ls > CQ_BS || len < 4 * Ls)) Ls >>= 1;
-    return Ls;
-}
-
-__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
-}
-
-// sum each tile entry over the Ls lanes of its group (every lane takes part)
-__device__ __forceinline__ void tile_sum(double2 (&acc)[CT][CT], int Ls) {
-#pragma unroll
-    for (int i = 0; i < CT; ++i)
-#pragma unroll
-        for (int k = 0; k < CT; ++k) {
-            acc[i][k].x = group_sum(acc[i][k].x, Ls);
-            acc[i][k].y = group_sum(acc[i][k].y, Ls);
-        }
-}
+typedef double cgd4 __attribute__((ext_vector_type(4)));
+constexpr int CB = 16;   // columns per step of the factorisation
 
 // G (m x m Hermitian, column-major, ld m) = L L^H. Writes R = L^H (m x m upper
 // triangular, zeros below). flag: set to 1 when a pivot is not positive or, with
@@ -382,9 +358,9 @@ __device__ __forceinline__ void tile_sum(double2 (&acc)[CT][CT], int Ls) {
 // without it the flag is overwritten.
 //
 // CB columns per step. The inner products over finished columns are a small
-// matrix product: CT x CT register tiles, each split over Ls lanes. The step's
-// CB x CB diagonal block is then factored by wavefront 0 and the rest of the
-// step solved one row per thread.
+// matrix product on the FP64 matrix cores (one 16-row tile per wavefront); the
+// step's CB x CB diagonal block is then factored by wavefront 0 and the rest of
+// the step solved one row per thread.
 __global__ __launch_bounds__(CQ_BS) void chol_kernel(const double2* __restrict__ G, int m, int check,
                                                      double2* __restrict__ R, int* __restrict__ flag) {
     __shared__ double2 L[CQ_TRI];       // packed lower triangle
@@ -413,43 +389,33 @@ __global__ __launch_bounds__(CQ_BS) void chol_kernel(const double2* __restrict__
     // and L(r, c) = Lh(r, c) / sqrt(d_c).
     for (int j = 0; j < m; j += CB) {
         const int bw = min(CB, m - j), u = m - j;
-        {   // rows r >= j, the step's columns, terms l < j
-            const int tiles = ((u + CT - 1) / CT) * (CB / CT), Ls = slices(tiles, j);
-            const int ti = tid / Ls, s = tid % Ls;
-            const bool act = ti < tiles;
-            const int r0 = j + (ti / (CB / CT)) * CT, c0 = (ti % (CB / CT)) * CT;
-            double2 acc[CT][CT] = {};
-            if (act) {
-                for (int l = s; l < j; l += Ls) {
-                    const double w = pv[l];
+        {   // rows r >= j, the step's columns, terms l < j, on the FP64 matrix cores: one
+            // 16-row tile per wavefront, S = Lh[rows, :j] (conj(Lh[j + c, :j]) / d)^T by
+            // Gauss's three products (T1 = ar br, T2 = ai bi, T3 = (ar + ai)(br + bi))
+            const int nrt = (u + 15) / 16, ln = lane & 15, lk = lane >> 4;
+            for (int rt = wave; rt < nrt && j > 0; rt += CQ_BS / 64) {   // uniform per wavefront
+                const int r0 = j + rt * 16, ra = r0 + ln;
+                cgd4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0}, t3 = {0.0, 0.0, 0.0, 0.0};
+                for (int l0 = 0; l0 < j; l0 += 4) {   // j is a multiple of 16
+                    const int l = l0 + lk;
                     const double2* col = L + cq_idx(m, 0, l);   // column l, indexed by row
-                    double2 a[CT], b[CT];
-#pragma unroll
-                    for (int i = 0; i < CT; ++i) a[i] = r0 + i < m ? col[r0 + i] : make_double2(0.0, 0.0);
-#pragma unroll
-                    for (int k = 0; k < CT; ++k) {
-                        const double2 v = c0 + k < bw ? col[j + c0 + k] : make_double2(0.0, 0.0);
-                        b[k] = make_double2(w * v.x, -w * v.y);
-                    }
-#pragma unroll
-                    for (int i = 0; i < CT; ++i)
-#pragma unroll
-                        for (int k = 0; k < CT; ++k) cfma(acc[i][k], a[i], b[k]);
+                    const double2 av = ra < m ? col[ra] : make_double2(0.0, 0.0);
+                    const double2 bv = ln < bw ? col[j + ln] : make_double2(0.0, 0.0);
+                    const double w = pv[l];
+                    const double br = w * bv.x, bi = -w * bv.y;
+                    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, br, t1, 0, 0, 0);
+                    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bi, t2, 0, 0, 0);
+                    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, br + bi, t3, 0, 0, 0);
                 }
-            }
-            tile_sum(acc, Ls);
-            if (act && s == 0) {
 #pragma unroll
-                for (int i = 0; i < CT; ++i)
-#pragma unroll
-                    for (int k = 0; k < CT; ++k) {
-                        const int r = r0 + i, c = c0 + k;
-                        if (r < m && c < bw && j + c <= r) {
-                            double2& x = L[cq_idx(m, r, j + c)];
-                            x.x -= acc[i][k].x;
-                            x.y -= acc[i][k].y;
-                        }
+                for (int v = 0; v < 4; ++v) {   // element v: row r0 + lk + 4 v, column ln
+                    const int r = r0 + lk + 4 * v, c = ln;
+                    if (r < m && c < bw && j + c <= r) {
+                        double2& x = L[cq_idx(m, r, j + c)];
+                        x.x -= t1[v] - t2[v];
+                        x.y -= t3[v] - t1[v] - t2[v];
                     }
+                }
             }
         }
         __syncthreads();
