@@ -345,17 +345,20 @@ __global__ void clenshaw_kernel(const double* __restrict__ d, const double* __re
 
 // Several Clenshaw steps in one launch (temporal blocking). A workgroup owns
 // CB_ROWS consecutive rows of one vector plus a halo of `steps` rows on each
-// side (rows taken cyclically, so a short vector simply repeats in the halo),
-// holds b_{j+1}, b_{j+2} of those rows in LDS and runs `steps` steps; after step
-// s only rows [s, S - s) of the window are still exact, which after the last
-// step is the owned block plus one row on each side. It writes b_{jlo} and
-// b_{jlo+1} of its own rows to fresh buffers (the inputs are still read by the
-// neighbouring blocks' halos). The last step (j = 0, which reads X only in its
-// own row) is left to clenshaw_kernel so that the result may overwrite X.
-constexpr int CB_ROWS = 1024;
-constexpr int CB_STEPS = 32;
+// side (rows taken cyclically, so a short vector simply repeats in the halo).
+// Each thread holds CB_R consecutive rows of that window, with their b_{j+1},
+// b_{j+2}, X and G coefficients, in registers; per step it needs only the last
+// row of the thread before it and the first row of the thread after it (DPP
+// wave shifts, and through LDS across wavefronts). After step s only window rows
+// [s, S - s) are still exact, which after the last step is the owned block plus
+// one row on each side. It writes b_{jlo} and b_{jlo+1} of its own rows to fresh
+// buffers (the inputs are still read by the neighbouring blocks' halos). The
+// last step (j = 0, which reads X only in its own row) is left to
+// clenshaw_kernel so that the result may overwrite X.
+constexpr int CB_R = 5;                               // window rows per thread
 constexpr int CB_THREADS = 256;
-constexpr int CB_SLOTS = (CB_ROWS + 2 * CB_STEPS + CB_THREADS - 1) / CB_THREADS;
+constexpr int CB_STEPS = 32;
+constexpr int CB_ROWS = CB_R * CB_THREADS - 2 * CB_STEPS;   // 1216 owned rows
 struct ChebBlock {
     double a[CB_STEPS];   // a_j for j = jhi, jhi - 1, ..., jhi - steps + 1
 };
@@ -365,26 +368,40 @@ __device__ __forceinline__ T cb_zero() {
     else return make_double2(0.0, 0.0);
 }
 
+// the value of the lane before (CTRL 0x138, wave_shr:1) or after (0x130, wave_shl:1)
+template <int CTRL>
+__device__ __forceinline__ double cb_dpp(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double cb_shift(double v) { return cb_dpp<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double2 cb_shift(double2 v) { return make_double2(cb_dpp<CTRL>(v.x), cb_dpp<CTRL>(v.y)); }
+
 template <typename T>
 __global__ __launch_bounds__(CB_THREADS) void clenshaw_block_kernel(
     const double* __restrict__ d, const double* __restrict__ e, int n, const T* __restrict__ X,
     const T* __restrict__ b1in, const T* __restrict__ b2in, T* __restrict__ b1out, T* __restrict__ b2out,
     int nchunk, ChebBlock cf, int steps, double s1, double s0) {
-    __shared__ T bufA[CB_ROWS + 2 * CB_STEPS];
-    __shared__ T bufB[CB_ROWS + 2 * CB_STEPS];
+    constexpr int NW = CB_THREADS / 64;
+    __shared__ T edgeL[2][NW], edgeR[2][NW];   // first and last row of each wavefront, by step parity
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int chunk = (int)(blockIdx.x % (unsigned)nchunk);
     const int64_t col = blockIdx.x / (unsigned)nchunk;
     const int r0 = chunk * CB_ROWS;
     const int rows = min(CB_ROWS, n - r0);
     const int S = rows + 2 * steps;
     const int64_t o = col * (int64_t)n;
-    T xr[CB_SLOTS];
-    double dr[CB_SLOTS], em[CB_SLOTS], ep[CB_SLOTS];
-    T* bp = bufA;   // b_{j+1}
-    T* bq = bufB;   // b_{j+2}
+    T xr[CB_R], bp[CB_R], bq[CB_R];
+    double dr[CB_R], em[CB_R], ep[CB_R];
 #pragma unroll
-    for (int u = 0; u < CB_SLOTS; ++u) {
-        const int t = threadIdx.x + u * CB_THREADS;
+    for (int u = 0; u < CB_R; ++u) {
+        const int t = tid * CB_R + u;
+        xr[u] = bp[u] = bq[u] = cb_zero<T>();
+        dr[u] = em[u] = ep[u] = 0.0;
         if (t < S) {
             int r = (r0 - steps + t) % n;
             r = r < 0 ? r + n : r;
@@ -393,33 +410,41 @@ __global__ __launch_bounds__(CB_THREADS) void clenshaw_block_kernel(
             dr[u] = d[r];
             em[u] = e[rm];
             ep[u] = e[r];
-            bp[t] = b1in ? b1in[o + r] : cb_zero<T>();
-            bq[t] = b2in ? b2in[o + r] : cb_zero<T>();
+            if (b1in) bp[u] = b1in[o + r];
+            if (b2in) bq[u] = b2in[o + r];
         }
     }
-    __syncthreads();
     for (int s = 1; s <= steps; ++s) {
         const double aj = cf.a[s - 1];
-#pragma unroll
-        for (int u = 0; u < CB_SLOTS; ++u) {
-            const int t = threadIdx.x + u * CB_THREADS;
-            if (t >= s && t < S - s) {
-                const T gb = bp[t] * dr[u] + bp[t - 1] * em[u] + bp[t + 1] * ep[u];
-                bq[t] = xr[u] * aj + (gb * s1 + bp[t] * s0) * 2.0 - bq[t];
-            }
-        }
-        T* tmp = bp;
-        bp = bq;
-        bq = tmp;
+        const int par = s & 1;
+        T left = cb_shift<0x138>(bp[CB_R - 1]);   // last row of the lane before
+        T right = cb_shift<0x130>(bp[0]);         // first row of the lane after
+        if (lane == 63) edgeR[par][w] = bp[CB_R - 1];
+        if (lane == 0) edgeL[par][w] = bp[0];
         __syncthreads();
+        if (lane == 0 && w > 0) left = edgeR[par][w - 1];
+        if (lane == 63 && w < NW - 1) right = edgeL[par][w + 1];
+        T nb[CB_R];
+#pragma unroll
+        for (int u = 0; u < CB_R; ++u) {
+            const T lm = u == 0 ? left : bp[u - 1];
+            const T rp = u == CB_R - 1 ? right : bp[u + 1];
+            const T gb = bp[u] * dr[u] + lm * em[u] + rp * ep[u];
+            nb[u] = xr[u] * aj + (gb * s1 + bp[u] * s0) * 2.0 - bq[u];
+        }
+#pragma unroll
+        for (int u = 0; u < CB_R; ++u) {
+            bq[u] = bp[u];
+            bp[u] = nb[u];
+        }
     }
 #pragma unroll
-    for (int u = 0; u < CB_SLOTS; ++u) {
-        const int t = threadIdx.x + u * CB_THREADS;
+    for (int u = 0; u < CB_R; ++u) {
+        const int t = tid * CB_R + u;
         if (t >= steps && t < steps + rows) {
             const int r = r0 + t - steps;
-            b1out[o + r] = bp[t];
-            b2out[o + r] = bq[t];
+            b1out[o + r] = bp[u];
+            b2out[o + r] = bq[u];
         }
     }
 }
