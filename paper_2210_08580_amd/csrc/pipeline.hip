@@ -461,6 +461,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
             // Z = B_y^H Qz ; T = orth(Z)
             {
                 GemmTag tg(c, "gemm_sketch");
+                SplitHint sh(c, 2);   // 3 N/128 tiles: two K parts balance them over the chip
                 zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
             }
             apply_gram_power(op, -1, Z, m);
@@ -470,6 +471,7 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
         // projected block B = Q^H A_y = Qz^H B_y, held as B^H = B_y^H Qz
         {
             GemmTag tg(c, "gemm_sketch");
+            SplitHint sh(c, 2);
             zgemm(c, OP_N, OP_N, n, m, ne, kOne, cBt, n, Qz, ne, kZero, Z, n);
         }
         apply_gram_power(op, -1, Z, m);
