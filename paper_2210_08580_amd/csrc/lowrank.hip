@@ -577,8 +577,8 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(const double2* __restrict_
 }
 
 // Gram matrix G = A^H A of a tall block (M x m, m <= GT_COLS, column-major, ld
-// lda) on the FP64 matrix cores. Workgroup b sums rows [b GT_ROWS, (b + 1) GT_ROWS)
-// into the 45 lower 16 x 16 tiles of its partial (the columns zero-padded to
+// lda) on the FP64 matrix cores. Workgroup b sums the GT_ROWS-row chunks b,
+// b + grid, ... into the 45 lower 16 x 16 tiles of its partial (the columns zero-padded to
 // GT_COLS); gram_tall_reduce_kernel adds the partials in a fixed order and fills
 // the upper triangle by conjugate symmetry. Per tile, Gauss's three real products
 // with a = conj(A(k, i)), b = A(k, j): T1 = ar br, T2 = ai bi,
@@ -596,14 +596,6 @@ __global__ __launch_bounds__(64 * GT_WAVES) void gram_tall_kernel(const double2*
     __shared__ double sr[GT_ROWS][GT_COLS + 1];
     __shared__ double si[GT_ROWS][GT_COLS + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.x * GT_ROWS;
-    for (int t = tid; t < GT_ROWS * GT_COLS; t += 64 * GT_WAVES) {
-        const int k = t % GT_ROWS, c = t / GT_ROWS;   // consecutive threads: consecutive rows of a column
-        const double2 v = (r0 + k < M && c < m) ? A[(int64_t)c * lda + r0 + k] : make_double2(0.0, 0.0);
-        sr[k][c] = v.x;
-        si[k][c] = v.y;
-    }
-    __syncthreads();
     // this wavefront's tiles: w, w + GT_WAVES, ... in the row-major order of the lower triangle
     int ti[GT_TPW], tj[GT_TPW];
 #pragma unroll
@@ -621,16 +613,28 @@ __global__ __launch_bounds__(64 * GT_WAVES) void gram_tall_kernel(const double2*
         t3[u] = gd4{0.0, 0.0, 0.0, 0.0};
     }
     const int ln = lane & 15, lk = lane >> 4;
-    for (int kk = 0; kk < GT_ROWS; kk += 4) {
-        const int k = kk + lk;
+    const int nchunk = (M + GT_ROWS - 1) / GT_ROWS;
+    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {   // chunks of GT_ROWS rows
+        const int r0 = ch * GT_ROWS;
+        __syncthreads();   // the previous chunk's reads are done
+        for (int t = tid; t < GT_ROWS * GT_COLS; t += 64 * GT_WAVES) {
+            const int k = t % GT_ROWS, c = t / GT_ROWS;   // consecutive threads: consecutive rows of a column
+            const double2 v = (r0 + k < M && c < m) ? A[(int64_t)c * lda + r0 + k] : make_double2(0.0, 0.0);
+            sr[k][c] = v.x;
+            si[k][c] = v.y;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < GT_ROWS; kk += 4) {
+            const int k = kk + lk;
 #pragma unroll
-        for (int u = 0; u < GT_TPW; ++u) {
-            if (w + u * GT_WAVES >= GT_NTILE) continue;   // uniform
-            const int ci = ti[u] * 16 + ln, cj = tj[u] * 16 + ln;
-            const double ar = sr[k][ci], ai = si[k][ci], br = sr[k][cj], bi = si[k][cj];
-            t1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, t1[u], 0, 0, 0);
-            t2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, t2[u], 0, 0, 0);
-            t3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar - ai, br + bi, t3[u], 0, 0, 0);
+            for (int u = 0; u < GT_TPW; ++u) {
+                if (w + u * GT_WAVES >= GT_NTILE) continue;   // uniform
+                const int ci = ti[u] * 16 + ln, cj = tj[u] * 16 + ln;
+                const double ar = sr[k][ci], ai = si[k][ci], br = sr[k][cj], bi = si[k][cj];
+                t1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, t1[u], 0, 0, 0);
+                t2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, t2[u], 0, 0, 0);
+                t3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar - ai, br + bi, t3[u], 0, 0, 0);
+            }
         }
     }
     double2* P = part + (int64_t)blockIdx.x * GT_COLS * GT_COLS;   // column-major GT_COLS x GT_COLS
@@ -680,8 +684,11 @@ __global__ __launch_bounds__(GT_COLS) void gram_tall_reduce_kernel(const double2
     if (i / 16 != j / 16) G[(int64_t)i * m + j] = make_double2(s.x, -s.y);   // the diagonal tiles are stored whole
 }
 
+// workgroups of the tall Gram kernel (and partials): one per 64-row chunk, at most 512
+static inline int gram_tall_groups(int M) { return std::min(512, (M + GT_ROWS - 1) / GT_ROWS); }
+
 static void gram_tall(Ctx& c, const double2* A, int M, int m, double2* G, double2* part) {
-    const int nb = (M + GT_ROWS - 1) / GT_ROWS;
+    const int nb = gram_tall_groups(M);
     KScope _ks(c, "qr_gram");
     hipLaunchKernelGGL(gram_tall_kernel, dim3((unsigned)nb), dim3(64 * GT_WAVES), 0, c.stream, A, (int64_t)M, M, m,
                        part);
@@ -713,9 +720,8 @@ static bool cholesky_qr2(Ctx& c, double2* A, int M, int m, double2* Q, bool basi
     double2 *R1 = G + mm, *R2 = G + 2 * mm, *Ri = G + 3 * mm;
     double2* Q1 = basis_only ? nullptr : static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)M * m));
     int* flag = static_cast<int*>(c.dmalloc(sizeof(int)));
-    // partial Gram matrices, one per 64-row chunk
-    double2* part = static_cast<double2*>(
-        c.dmalloc(sizeof(double2) * GT_COLS * GT_COLS * (size_t)((M + GT_ROWS - 1) / GT_ROWS)));
+    // partial Gram matrices, one per workgroup of the tall Gram kernel
+    double2* part = static_cast<double2*>(c.dmalloc(sizeof(double2) * GT_COLS * GT_COLS * (size_t)gram_tall_groups(M)));
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
     GemmTag tg(c, "qr_gram");
     double2* R[2] = {R1, R2};

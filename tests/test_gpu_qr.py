@@ -47,7 +47,7 @@ def _check(A, Q, R, orth_tol, res_tol):
 
 
 @pytest.mark.parametrize("M,m", [(3000, 100), (16384, 138), (511, 138), (64, 64), (7, 1), (600, 140), (600, 141),
-                                 (2000, 17)])
+                                 (2000, 17), (40037, 138)])   # 40037 rows: more 64-row chunks than workgroups
 @pytest.mark.parametrize("method", [B.FDS_QR_AUTO, B.FDS_QR_HOUSEHOLDER])
 def test_qr_well_conditioned(ctx, M, m, method):
     print(f"case: zqr M={M} m={m} method={method}", flush=True)
