@@ -83,6 +83,7 @@ __device__ __forceinline__ void ld_into(const T* p, int op, T& v) { v = ld_op(p,
 // complex128 value of a raw A element under op (conjugated for OP_C)
 __device__ __forceinline__ double2 widen_op(float2 f, int op) { return make_double2(f.x, op == OP_C ? -f.y : f.y); }
 __device__ __forceinline__ double2 widen_op(double2 d, int op) { return op == OP_C ? make_double2(d.x, -d.y) : d; }
+__device__ __forceinline__ float2 conj_op(float2 f, int op) { return op == OP_C ? make_float2(f.x, -f.y) : f; }
 
 // op(A)[gi][gp] from the complex128 band when |gp - gi| (cyclic) <= w
 __device__ __forceinline__ bool band_lookup(const BandA& bd, int gi, int gp, double2& v) {
@@ -261,21 +262,30 @@ constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
 // TB = double: a real B operand (two real MFMAs per complex-by-real tile step).
 // WN = 2: 128 x 64 tile, 2 x 2 wavefronts of 64 x 32; WN = 1 (narrow outputs of at
 // most 32 columns): 128 x 32 tile, 4 x 1 wavefronts of 32 x 32.
-template <typename TA, typename TB, int OPA, int OPB, int WN = 2>
-__global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, double2 alpha,
-                                                       const TA* __restrict__ A, int64_t lda,
-                                                       const TB* __restrict__ B, int64_t ldb, double2 beta,
-                                                       double2* __restrict__ C, int64_t ldc, int kchunk,
-                                                       double2* __restrict__ part, BandA bd) {
+// AL32 (complex64 A without a complex128 band): A stays complex64 in LDS and is
+// widened when read from it, which halves its LDS footprint. A complex B then
+// takes K slices of 32 (half the barriers per matrix-core step, one slice of
+// loads in flight for twice as long); a real B keeps slices of 16 and fits two
+// workgroups per compute unit (registers capped at two wavefronts per SIMD).
+template <typename TA, typename TB, int OPA, int OPB, int WN = 2, bool AL32 = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    (AL32 && !std::is_same<TB, double2>::value) ? 2 : 1, (AL32 && !std::is_same<TB, double2>::value) ? 2 : 1)))
+void gemm_big_kernel(int m, int n, int k, double2 alpha, const TA* __restrict__ A, int64_t lda,
+                     const TB* __restrict__ B, int64_t ldb, double2 beta, double2* __restrict__ C, int64_t ldc,
+                     int kchunk, double2* __restrict__ part, BandA bd) {
     constexpr bool BCPLX = std::is_same<TB, double2>::value;
+    static_assert(!AL32 || std::is_same<TA, float2>::value, "complex64 LDS staging needs a complex64 A");
     constexpr bool GAUSS3 = BCPLX && OPA == OP_N;   // transposed-A loads leave no registers for a third product
+    constexpr int KS = (AL32 && BCPLX) ? 32 : BB_K; // K slice depth
     constexpr int BN = 32 * WN;             // tile columns
     constexpr int WM = 4 / WN;              // wavefronts along the rows
     constexpr int RT = BB_M / (16 * WM);    // 16-row MFMA tiles per wavefront
-    constexpr int EB = BB_K * BN / 256;     // B elements staged per thread and slice
+    constexpr int EA = KS * BB_M / 256;     // A elements staged per thread and slice
+    constexpr int EB = KS * BN / 256;       // B elements staged per thread and slice
+    typedef typename std::conditional<AL32, float2, double2>::type SA;
     // two LDS buffers: slice i is multiplied from one while slice i + 1 is staged into the other
-    __shared__ double2 sA[2][BB_K][BB_M + BB_PAD];
-    __shared__ TB sB[2][BB_K][BN + BB_PAD];
+    __shared__ SA sA[2][KS][BB_M + BB_PAD];
+    __shared__ TB sB[2][KS][BN + BB_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wm = w % WM, wn = w / WM;
@@ -295,21 +305,35 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             accI[a][b] = d4{0.0, 0.0, 0.0, 0.0};
             acc3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
         }
-    // raw operands in flight (complex64 A is widened when staged to LDS, so the
-    // loads of the next slice are not waited on while the current one computes)
-    TA ra[8];
+    // raw operands in flight (complex64 A is widened when staged to LDS, or when
+    // read from it under AL32, so the loads of the next slice are not waited on
+    // while the current one computes)
+    TA ra[EA];
     TB rb[EB];
+    // staging maps: element e of a thread is row i / column j, slice row p
+    auto amap = [&](int e, int& i, int& p) {
+        if (OPA == OP_N) {
+            i = tid & 127;
+            p = (tid >> 7) + 2 * e;
+        } else {
+            p = tid % KS;
+            i = tid / KS + (256 / KS) * e;
+        }
+    };
+    auto bmap = [&](int e, int& j, int& p) {
+        if (OPB == OP_N) {
+            p = tid % KS;
+            j = tid / KS + (256 / KS) * e;
+        } else {
+            j = tid % BN;
+            p = tid / BN + (256 / BN) * e;
+        }
+    };
     auto loadAB = [&](int kk) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < EA; ++e) {
             int i, p;
-            if (OPA == OP_N) {
-                i = tid & 127;
-                p = (tid >> 7) + 2 * e;
-            } else {
-                p = tid & 15;
-                i = (tid >> 4) + 16 * e;
-            }
+            amap(e, i, p);
             const int gi = row0 + i, gp = kk + p;
             TA v{};
             if (gi < m && gp < kend) v = (OPA == OP_N) ? A[gi + (int64_t)gp * lda] : A[gp + (int64_t)gi * lda];
@@ -318,13 +342,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
             int j, p;
-            if (OPB == OP_N) {
-                p = tid & 15;
-                j = (tid >> 4) + 16 * e;
-            } else {
-                j = tid % BN;
-                p = tid / BN + (256 / BN) * e;
-            }
+            bmap(e, j, p);
             const int gj = col0 + j, gp = kk + p;
             TB v{};
             if (gj < n && gp < kend) {
@@ -334,34 +352,33 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
             rb[e] = v;
         }
     };
-    // does the K slice [kk, kk + BB_K) meet the band of the row block (uniform)?
+    // does the K slice [kk, kk + KS) meet the band of the row block (uniform)?
     auto band_slice = [&](int kk) {
         if (!bd.nb) return false;
-        const int dmin = kk - (row0 + BB_M - 1), dmax = kk + BB_K - 1 - row0;
+        const int dmin = kk - (row0 + BB_M - 1), dmax = kk + KS - 1 - row0;
         for (int q = -1; q <= 1; ++q)
             if (dmax >= q * bd.n - bd.w && dmin <= q * bd.n + bd.w) return true;
         return false;
     };
     auto stage = [&](int kk, int buf) {
-        const bool bsl = std::is_same<TA, float2>::value && band_slice(kk);
+        const bool bsl = !AL32 && std::is_same<TA, float2>::value && band_slice(kk);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < EA; ++e) {
             int i, p;
-            if (OPA == OP_N) {
-                i = tid & 127;
-                p = (tid >> 7) + 2 * e;
+            amap(e, i, p);
+            if constexpr (AL32) {
+                sA[buf][p][i] = conj_op(ra[e], OPA);
             } else {
-                p = tid & 15;
-                i = (tid >> 4) + 16 * e;
+                double2 v = widen_op(ra[e], OPA);
+                if (bsl && row0 + i < m && kk + p < kend) band_lookup(bd, row0 + i, kk + p, v);
+                sA[buf][p][i] = v;
             }
-            double2 v = widen_op(ra[e], OPA);
-            if (bsl && row0 + i < m && kk + p < kend) band_lookup(bd, row0 + i, kk + p, v);
-            sA[buf][p][i] = v;
         }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-            if (OPB == OP_N) sB[buf][tid & 15][(tid >> 4) + 16 * e] = rb[e];
-            else sB[buf][tid / BN + (256 / BN) * e][tid % BN] = rb[e];
+            int j, p;
+            bmap(e, j, p);
+            sB[buf][p][j] = rb[e];
         }
     };
     auto compute = [&](int buf) {
@@ -369,12 +386,15 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
         // fragments of all four, and the extra live registers then spill to AGPRs
         // (moves every slice)
 #pragma unroll 2
-        for (int kc = 0; kc < BB_K / 4; ++kc) {
+        for (int kc = 0; kc < KS / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
             double2 a[RT];
             TB b[2];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) a[r] = sA[buf][pr][wm * (16 * RT) + r * 16 + (lane & 15)];
+            for (int r = 0; r < RT; ++r) {
+                const SA av = sA[buf][pr][wm * (16 * RT) + r * 16 + (lane & 15)];
+                a[r] = make_double2(av.x, av.y);
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = sB[buf][pr][wn * 32 + c * 16 + (lane & 15)];
             if constexpr (GAUSS3) {
@@ -417,15 +437,15 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(int m, int n, int k, doub
     if (kbeg < kend) {
         loadAB(kbeg);
         stage(kbeg, 0);
-        if (kbeg + BB_K < kend) loadAB(kbeg + BB_K);
+        if (kbeg + KS < kend) loadAB(kbeg + KS);
         __syncthreads();
     }
     int buf = 0;
-    for (int kk = kbeg; kk < kend; kk += BB_K) {
+    for (int kk = kbeg; kk < kend; kk += KS) {
         compute(buf);
-        if (kk + BB_K < kend) {
-            stage(kk + BB_K, buf ^ 1);
-            if (kk + 2 * BB_K < kend) loadAB(kk + 2 * BB_K);
+        if (kk + KS < kend) {
+            stage(kk + KS, buf ^ 1);
+            if (kk + 2 * KS < kend) loadAB(kk + 2 * KS);
         }
         __syncthreads();
         buf ^= 1;
@@ -603,8 +623,11 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
         const size_t per = sizeof(T) * (size_t)m * n;
         nz = std::max(1, std::min<int>(nz, (int)std::min<size_t>(c.ws_bytes / per, 64)));
     }
+    // a complex64 A without a complex128 band stays complex64 in LDS (K slices of 32)
+    const bool al32 = std::is_same<TA, float2>::value && !bd.nb && (big || narrow);
+    const int kq = al32 ? 2 * GB_K : GB_K;
     int kchunk = (k + nz - 1) / nz;
-    kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
+    kchunk = (kchunk + kq - 1) / kq * kq;
     nz = (k + kchunk - 1) / kchunk;
     T* part = nullptr;
     if (nz > 1)
@@ -612,7 +635,22 @@ static void gemm_launch(Ctx& c, int m, int n, int k, T alpha, const TA* A, int64
     {
         KScope _ks(c, c.gemm_tag ? c.gemm_tag : (std::is_same<T, float2>::value ? "gemm_c64" : "gemm"));
         if constexpr (big_ok<T, TA>()) {
-            if (narrow) {
+            bool done = false;
+            if constexpr (std::is_same<TA, float2>::value) {
+                if (al32) {
+                    if (narrow)
+                        hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB, 1, true>), dim3(gm, gn, nz),
+                                           dim3(256), 0, c.stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                           kchunk, part, bd);
+                    else
+                        hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB, 2, true>), dim3(gm, gn, nz),
+                                           dim3(256), 0, c.stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                           kchunk, part, bd);
+                    done = true;
+                }
+            }
+            if (done) {
+            } else if (narrow) {
                 hipLaunchKernelGGL((gemm_big_kernel<TA, double2, OPA, OPB, 1>), dim3(gm, gn, nz), dim3(256), 0, c.stream,
                                    m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
             } else if (big) {
@@ -678,8 +716,12 @@ static bool gemm_real_b(Ctx& c, int m, int n, int k, double2 alpha, const TA* A,
                         int64_t ldb, double2 beta, double2* C, int64_t ldc, const BandA& bd) {
     if (m < BB_M || n < BB_N || k <= 0) return false;
     const int gm = (m + BB_M - 1) / BB_M, gn = (n + BB_N - 1) / BB_N;
+    // complex64 A without a band: complex64 in LDS, two workgroups per compute unit,
+    // so split K until about 512 workgroups are in flight; else one per compute unit
+    const bool al32 = std::is_same<TA, float2>::value && !bd.nb;
+    const int want = al32 ? 512 : 128;
     int nz = 1;
-    if (4 * gm * gn < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + 4 * gm * gn - 1) / (4 * gm * gn), (k + 255) / 256));
+    if (gm * gn < want && k > 4 * GB_K) nz = std::max(1, std::min((want + gm * gn - 1) / (gm * gn), (k + 255) / 256));
     nz = std::min(nz, 64);
     int kchunk = (k + nz - 1) / nz;
     kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
@@ -688,8 +730,17 @@ static bool gemm_real_b(Ctx& c, int m, int n, int k, double2 alpha, const TA* A,
     if (nz > 1) part = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)nz * m * n));
     {
         KScope _ks(c, c.gemm_tag ? c.gemm_tag : "gemm");
-        hipLaunchKernelGGL((gemm_big_kernel<TA, double, OP_N, OP_N>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m, n,
-                           k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
+        bool done = false;
+        if constexpr (std::is_same<TA, float2>::value) {
+            if (al32) {
+                hipLaunchKernelGGL((gemm_big_kernel<TA, double, OP_N, OP_N, 2, true>), dim3(gm, gn, nz), dim3(256), 0,
+                                   c.stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
+                done = true;
+            }
+        }
+        if (!done)
+            hipLaunchKernelGGL((gemm_big_kernel<TA, double, OP_N, OP_N>), dim3(gm, gn, nz), dim3(256), 0, c.stream, m,
+                               n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, bd);
     }
     FDS_HIP_TRY(hipGetLastError());
     if (part) {
