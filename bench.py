@@ -437,7 +437,8 @@ def run_table1(args):
 
 
 RELERR_BOUND = 1e-6   # solution error bound of the metric (mixed against FP64)
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "gemm.hip")
+# the GEMM kernels and the pipeline that chooses their split-K factors
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2210_08580_amd", "csrc", f) for f in ("gemm.hip", "pipeline.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_star8192.json")
 ASM_SOURCE = os.path.join(ROOT, "paper_2210_08580_amd", "csrc", "assemble.hip")
 ASM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_assembly_star8192.json")
@@ -445,13 +446,16 @@ ASM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_assembly_star8192.jso
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    when there is none or the GEMM source has changed since it was taken."""
+    when there is none or the GEMM or pipeline source has changed since it was taken."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        with open(KERNEL_SOURCE, "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in KERNEL_SOURCES:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+        digest = h.hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != digest:
@@ -484,7 +488,7 @@ def measured_asm_traffic(precision):
     return rec.get("variants", {}).get(precision, {}).get("write_bytes_per_assembly")
 
 
-def assembly_roofline(prof, n, steps, precision, nbw=0):
+def assembly_roofline(prof, n, steps, precision, nbw=0, workload="star8192"):
     """HBM roofline of the dense assembly (every asm_* kernel of a step, HIP events
     on the context stream): achieved = algorithmic bytes written / assembly time."""
     ms = sum(prof.get(k, (0.0, 0))[0] for k in ASM_KERNELS) / steps
@@ -493,7 +497,8 @@ def assembly_roofline(prof, n, steps, precision, nbw=0):
     byts = assembly_bytes(n, precision, nbw)
     gbs = byts / (ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-            "traffic": measured_asm_traffic(precision), "kernels": list(ASM_KERNELS),
+            "traffic": measured_asm_traffic(precision) if workload == "star8192" and n == 8192 else None,
+            "kernels": list(ASM_KERNELS),
             "ms_per_assembly": ms, "bytes_per_assembly": byts, "entries_per_s": 3.0 * n * n / (ms / 1e3),
             "kernel_ms": {k: prof[k][0] / steps for k in ASM_KERNELS if k in prof}}
 
@@ -520,17 +525,19 @@ def compression_roofline(prof, w, ne, steps):
             "compression_ms": sum(prof[k][0] for k in COMPRESSION_KERNELS if k in prof) / steps}
 
 
-def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
+def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0, workload="star8192"):
     """Roofline of the kernel family with the largest total time (HIP events on
     the context stream): achieved = algorithmic work per launch / mean launch time.
-    The assembly kernels count as one family (the dense S, N, D written once)."""
+    The assembly kernels count as one family (the dense S, N, D written once).
+    `traffic` comes from the committed counter records, which cover the EFIE star8192
+    workload only (null elsewhere)."""
     fam = dict(prof)
     asm = [k for k in ASM_KERNELS if k in fam]
     if asm:
         fam["assembly"] = (sum(fam.pop(k)[0] for k in asm), steps)
     name, (tot_ms, launches) = max(fam.items(), key=lambda kv: kv[1][0])
     if name == "assembly":
-        roof = assembly_roofline(prof, n, steps, precision, nbw)
+        roof = assembly_roofline(prof, n, steps, precision, nbw, workload)
         roof.update(kernel="assembly", launches=steps, avg_launch_ms=roof["ms_per_assembly"])
         return roof
     per_launch_s = (tot_ms / 1e3) / max(launches, 1)
@@ -539,7 +546,7 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
     work = None
     roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS}
     if name in ("gemm_op", "gemm_op_vg", "gemm_op_y"):
-        # N x N operator products on one kernel symbol each, 8 flop per complex
+        # N x N operator products, one tag each, 8 flop per complex
         # multiply-add (4 with the real V_g). gemm_op_vg: S^T V_g (n_eff columns);
         # gemm_op: N^T (G^-1 S^T V_g) (n_eff columns) and S^T (G^-1 f) (nrhs columns),
         # one launch of each per step of this workload; with the Yukawa-Calderon
@@ -552,9 +559,17 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0):
             per_step = 8.0 * n * n * (ne + (0 if form == "ycfie" else nrhs))
         work = per_step * steps / max(launches, 1)
         asym = "double2" if name == "gemm_op_y" else sym
-        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
-                "kernel_symbol": "gemm_big_kernel<%s, %s, 0, 0, 2>" % (asym, "double" if name == "gemm_op_vg" else "double2")}
-        traffic = measured_traffic(name + ":" + precision) if form != "ycfie" else None
+        # complex64 operators without a complex128 band run the instance that keeps
+        # A complex64 in LDS (last template argument true); N, with its band, the other
+        if asym == "float2" and name == "gemm_op":
+            ksym = ("gemm_big_kernel<float2, double2, 0, 0, 2, true> (S G^-1 f) and "
+                    "gemm_big_kernel<float2, double2, 0, 0, 2, false> (N X)")
+        else:
+            ksym = "gemm_big_kernel<%s, %s, 0, 0, 2, %s>" % (asym, "double" if name == "gemm_op_vg" else "double2",
+                                                            "true" if asym == "float2" else "false")
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS, "kernel_symbol": ksym}
+        traffic = (measured_traffic(name + ":" + precision)
+                   if form == "efie" and workload == "star8192" and n == 8192 else None)
     if work is not None:
         ach = work / per_launch_s / 1e12
         roof.update(achieved=ach, frac=ach / roof["peak"])
@@ -632,8 +647,8 @@ def main():
     r = res[main_v]
     info = r["info"]
     ne = info["n_eff"]
-    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form, info.get("nbw", 0))
-    asm_roof = assembly_roofline(r["prof"], n, args.steps, main_v, info.get("nbw", 0))
+    roof = roofline(r["prof"], n, ne, nrhs, args.steps, main_v, w.form, info.get("nbw", 0), w.name)
+    asm_roof = assembly_roofline(r["prof"], n, args.steps, main_v, info.get("nbw", 0), w.name)
     precision = {"fp64": "fp64 plain", "fp32": "mixed: FP32 far-field assembly, complex64 operators, "
                  "FP64 products, FP64 Woodbury and refinement"}[main_v]
     out = {
@@ -661,9 +676,9 @@ def main():
         et.update({"value": t["value"], "unit": "RHS solves/s", "ms_per_step": t["ms_per_step"],
                    "variant_reported": mt, "config": workload_desc(wt, tne),
                    "roofline": roofline(t["prof"], wt.n, tne, wt.nrhs, args.steps, mt, wt.form,
-                                        t["info"].get("nbw", 0)),
+                                        t["info"].get("nbw", 0), wt.name),
                    "roofline_assembly": assembly_roofline(t["prof"], wt.n, args.steps, mt,
-                                                          t["info"].get("nbw", 0)),
+                                                          t["info"].get("nbw", 0), wt.name),
                    "roofline_compression": compression_roofline(t["prof"], wt, tne, args.steps)})
         out["truncating"] = et
         del tn
@@ -731,7 +746,7 @@ def run_workload(B, ctx, w, nodes, angles, amps, variants, args):
     info = res[main_v]["info"]
     extra.update({"n_eff": info["n_eff"], "rank": info["rank"]})
     for prec, rv in res.items():
-        asm = assembly_roofline(rv["prof"], n, args.steps, prec, rv["info"].get("nbw", 0))
+        asm = assembly_roofline(rv["prof"], n, args.steps, prec, rv["info"].get("nbw", 0), w.name)
         extra[prec] = {
             "value": rv["value"], "ms_per_step": rv["ms_per_step"],
             "marginal_rhs_per_s": rv["marginal_rhs_per_s"],

@@ -719,10 +719,10 @@ static void unfiltered_residual(Op& op, const double2* w, const double2* jv, int
 // -G^{-1} h (MFIE), the EFIE one + alpha times the MFIE one (CFIE). Needs only the
 // assembled operator.
 // Split-K factor of the right-hand-side product S (G^{-1} f): about 4096 work items
-// (128 x 64 output tiles times K parts), at most 16 parts.
+// (128 x 64 output tiles times K parts), at most 8 parts.
 static int rhs_split(int n, int64_t nrhs) {
     const int64_t tiles = ((int64_t)(n + 127) / 128) * ((nrhs + 63) / 64);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(16, 4096 / std::max<int64_t>(tiles, 1)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8, 4096 / std::max<int64_t>(tiles, 1)));
 }
 
 void run_rhs_system(Op& op, int form, double alpha, const double2* f, const double2* h, int64_t nrhs,
@@ -741,7 +741,8 @@ void run_rhs_system(Op& op, int form, double alpha, const double2* f, const doub
         // latency-bound kernels that run beside it (the filter's eigensolver on the side
         // stream) would wait for a whole tile; with more, shorter work items they keep a
         // few units and the product flows around them (at N = 8192 and 256 right-hand
-        // sides 16 parts: 10.46 against 10.57 ms per step with 4).
+        // sides 8 parts: 10.05-10.06 ms per step, against 10.08 with 16 parts, which
+        // write twice the partial sums, and 10.09-10.11 with 4).
         SplitHint sh(c, rhs_split(n, nrhs));
         op_gemm(op, s_op(form), OP_T, nrhs, make_double2(-1.0, 0.0), t, kZero, w);
         gram_inv(op, w, nrhs, w);
