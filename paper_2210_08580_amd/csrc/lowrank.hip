@@ -1,16 +1,18 @@
 // Dense building blocks of the truncating skeleton compression: the counter-
-// based sketch, Householder QR of tall complex blocks with the explicit
-// orthonormal factor, and the one-sided (Hestenes) Jacobi SVD of small square
-// blocks.
+// based sketch, the QR factorisation of tall complex blocks with the explicit
+// orthonormal factor (CholeskyQR2 on the matrix cores, certified, with blocked
+// Householder QR as the fallback), and the one-sided (Hestenes) Jacobi SVD of
+// small square blocks.
 //
 // Householder QR follows the standard complex reflector construction
 // (Golub & Van Loan, Matrix Computations, sec. 5.1-5.2): column j is mapped to
 // beta e_j by H_j = I - tau_j v_j v_j^H with v_j(j) = 1 and real beta, A is
 // overwritten by R (upper triangle) and the v_j (below it), and
-// Q = H_0 H_1 ... H_{m-1} [I; 0] is formed explicitly. One launch per column:
-// the workgroup owning a column applies the previous reflector to it and the
-// owner of the next pivot column then builds the next reflector, so no two
-// workgroups ever touch the same column within a launch.
+// Q = H_0 H_1 ... H_{m-1} [I; 0] is formed explicitly. Within a panel, one
+// launch per column: the workgroup owning a column applies the previous
+// reflector to it and the owner of the next pivot column then builds the next
+// reflector, so no two workgroups ever touch the same column within a launch;
+// the panel's reflectors then update the rest of the block in compact WY form.
 //
 // One-sided Jacobi (Hestenes 1958; Demmel & Veselic, SIAM J. Matrix Anal.
 // Appl. 13, 1992) rotates pairs of columns of X until they are mutually
