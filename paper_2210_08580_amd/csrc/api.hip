@@ -246,6 +246,8 @@ fds_status fds_ctx_destroy(fds_ctx ctx) {
         ctx->impl.dfree(ctx->impl.yk_tab);
         ctx->impl.dfree(ctx->impl.yk_tab32);
         ctx->impl.release_cache();
+        if (ctx->impl.host_pin) (void)hipHostFree(ctx->impl.host_pin);
+        ctx->impl.host_pin = nullptr;
         if (ctx->impl.side) {
             (void)hipStreamDestroy(ctx->impl.side);
             ctx->impl.side = nullptr;

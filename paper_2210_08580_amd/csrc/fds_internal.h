@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of libfds.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include <cstdint>
 #include <map>
@@ -70,6 +71,24 @@ struct Ctx {
     double* gl32 = nullptr;       // 32-point Gauss-Legendre rule on [0,1]: x[32], w[32]
     double* yk_tab = nullptr;     // device copy of the K0 coefficient table (Yukawa kernel)
     float* yk_tab32 = nullptr;    // device copy of the float32 K0 interval table
+    // Pinned host buffer for small device-to-host reads that are waited on at once
+    // (nothing is in flight from it between uses, so it can be regrown freely).
+    void* host_pin = nullptr;
+    size_t host_pin_bytes = 0;
+    void* pinned_host(size_t bytes) {
+        if (bytes > host_pin_bytes) {
+            if (host_pin) (void)hipHostFree(host_pin);
+            host_pin = nullptr;
+            host_pin_bytes = 0;
+            const size_t nb = std::max<size_t>(bytes, 4096);
+            if (hipHostMalloc(&host_pin, nb, hipHostMallocDefault) != hipSuccess) {
+                host_pin = nullptr;
+                return nullptr;
+            }
+            host_pin_bytes = nb;
+        }
+        return host_pin;
+    }
     // Allocation-free calls (fds_solve_system_noalloc): `scratch` is this device's
     // address of the library's static scratch array (set once per device at context
     // creation). While `noalloc` is set every device allocation is refused, the

@@ -1280,9 +1280,10 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // solve, ~1e-6 for the usual gap between Fourier pairs; when the cut gap is below
     // 2e-3 (a damping above 1e-5 per solve) the eigenvalues are bisected again to 6e-10.
     double rtol = 2e-8;
+    double* dlam = nullptr;   // the device eigenvalues of the last bisection (kept as the shifts)
     for (;;) {
         nw = std::min(n - start, want + extra);
-        double* dlam = nullptr;
+        c.dfree(dlam);
         if (pLam) {   // the first launch was made by prefetch_filter_eigs with these parameters
             dlam = pLam;
             pLam = nullptr;
@@ -1291,9 +1292,12 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
             launch_bisect(op, e, dst, nw, rtol, dlam);
         }
         lam.assign(nw, 0.0);
-        FDS_HIP_TRY(hipMemcpyAsync(lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost, c.stream));
+        // read through a pinned buffer (no staging copy) and wait at once
+        double* hl = static_cast<double*>(c.pinned_host(sizeof(double) * nw));
+        FDS_HIP_TRY(hipMemcpyAsync(hl ? hl : lam.data(), dlam, sizeof(double) * nw, hipMemcpyDeviceToHost,
+                                   c.stream));
         FDS_HIP_TRY(hipStreamSynchronize(c.stream));
-        c.dfree(dlam);
+        if (hl) std::copy(hl, hl + nw, lam.begin());
         int ne = want;
         while (ne < nw) {
             const double a = lam[ne - 1], b = lam[ne];
@@ -1322,8 +1326,8 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     cb.push_back(ne);
     const int ncl = (int)cb.size() - 1;
 
-    double* dsig = static_cast<double*>(c.dmalloc(sizeof(double) * ne));
-    FDS_HIP_TRY(hipMemcpyAsync(dsig, lam.data(), sizeof(double) * ne, hipMemcpyHostToDevice, c.stream));
+    // the shifts: the first ne device eigenvalues, as read (nw >= ne entries)
+    double* dsig = dlam;
     int* dcb = static_cast<int*>(c.dmalloc(sizeof(int) * (ncl + 1)));
     FDS_HIP_TRY(hipMemcpyAsync(dcb, cb.data(), sizeof(int) * (ncl + 1), hipMemcpyHostToDevice, c.stream));
     // two-ended elimination: mt steps from the top, mb from the bottom, 4 interface rows
