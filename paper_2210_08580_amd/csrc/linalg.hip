@@ -700,11 +700,28 @@ __global__ __launch_bounds__(256) void gj_nopiv_step_kernel(const double2* __res
     __shared__ double spiv[GJ_NB];
     __shared__ double2 Ws[64][GJ_NB + 1];
     __shared__ double2 Xp[GJ_NB][16];
+    __shared__ double2 Pn[GJ_NB][64];        // panel columns j0 .. j0+nb-1 of this block's rows
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 16;
     for (int t = tid; t < nb * 16; t += blockDim.x) {
         const int b = t / 16, cc = t % 16, c = c0 + cc;
         Xp[b][cc] = c < 2 * r ? M[j0 + b + (int64_t)c * r] : make_double2(0.0, 0.0);
+    }
+    // loads issued before the pivot block's elimination so that their latency
+    // overlaps it: the panel columns of the workgroup's rows (into LDS, by the
+    // wavefronts that do not eliminate) and the entries each thread updates at the
+    // end (into registers)
+    if (tid >= 64) {
+        for (int t = tid - 64; t < nb * 64; t += blockDim.x - 64) {
+            const int a = t / 64, ri = i0 + (t % 64);
+            Pn[a][t % 64] = ri < r ? M[ri + (int64_t)(j0 + a) * r] : make_double2(0.0, 0.0);
+        }
+    }
+    double2 vpre[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = c0 + (tid >> 6) + 4 * q, ri = i0 + (tid & 63);
+        vpre[q] = (ri < r && c < 2 * r && c >= j0 + nb) ? M[ri + (int64_t)c * r] : make_double2(0.0, 0.0);
     }
     // Gauss-Jordan on [A_pp | I] by the first wavefront with the rows in registers:
     // lane 4 i + q holds entries 8 q .. 8 q + 7 of row i (columns past 2 nb are zero);
@@ -775,7 +792,7 @@ __global__ __launch_bounds__(256) void gj_nopiv_step_kernel(const double2* __res
         if (!piv && i < r) {
 #pragma unroll 4
             for (int a = 0; a < nb; ++a) {
-                const double2 m0 = M[i + (int64_t)(j0 + a) * r];
+                const double2 m0 = Pn[a][li];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     if (bq + u < nb) acc[u] = csub(acc[u], cmul(m0, F[a][nb + bq + u]));
@@ -795,7 +812,7 @@ __global__ __launch_bounds__(256) void gj_nopiv_step_kernel(const double2* __res
         if (c < j0 + nb) {
             v = make_double2(i == c ? 1.0 : 0.0, 0.0);
         } else {
-            v = M[i + (int64_t)c * r];
+            v = vpre[q];   // M[i + c r]
 #pragma unroll
             for (int b = 0; b < GJ_NB; ++b)
                 if (b < nb) v = cadd(v, cmul(Ws[li][b], Xp[b][cc]));
