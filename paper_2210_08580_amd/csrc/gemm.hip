@@ -267,22 +267,32 @@ constexpr int BB_M = 128, BB_N = 64, BB_K = 16, BB_PAD = 2;
 // takes K slices of 32 (half the barriers per matrix-core step, one slice of
 // loads in flight for twice as long); a real B keeps slices of 16 and fits two
 // workgroups per compute unit (registers capped at two wavefronts per SIMD).
+// TA = double: a real A (the filter basis) against a complex B, two real MFMAs per
+// step (accR = a br, accI = a bi), two workgroups per compute unit as well.
+template <typename TA, typename TB>
+constexpr int gb_waves() {
+    return (std::is_same<TA, double>::value || (std::is_same<TA, float2>::value && std::is_same<TB, double>::value))
+               ? 2 : 1;
+}
 template <typename TA, typename TB, int OPA, int OPB, int WN = 2, bool AL32 = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    (AL32 && !std::is_same<TB, double2>::value) ? 2 : 1, (AL32 && !std::is_same<TB, double2>::value) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gb_waves<TA, TB>(), gb_waves<TA, TB>())))
 void gemm_big_kernel(int m, int n, int k, double2 alpha, const TA* __restrict__ A, int64_t lda,
                      const TB* __restrict__ B, int64_t ldb, double2 beta, double2* __restrict__ C, int64_t ldc,
                      int kchunk, double2* __restrict__ part, BandA bd) {
     constexpr bool BCPLX = std::is_same<TB, double2>::value;
+    constexpr bool ACPLX = !std::is_same<TA, double>::value;
     static_assert(!AL32 || std::is_same<TA, float2>::value, "complex64 LDS staging needs a complex64 A");
-    constexpr bool GAUSS3 = BCPLX && OPA == OP_N;   // transposed-A loads leave no registers for a third product
+    static_assert(ACPLX || (BCPLX && OPA == OP_N), "a real A: untransposed, against a complex B");
+    // transposed-A loads leave no registers for a third product
+    constexpr bool GAUSS3 = ACPLX && BCPLX && OPA == OP_N;
     constexpr int KS = (AL32 && BCPLX) ? 32 : BB_K; // K slice depth
     constexpr int BN = 32 * WN;             // tile columns
     constexpr int WM = 4 / WN;              // wavefronts along the rows
     constexpr int RT = BB_M / (16 * WM);    // 16-row MFMA tiles per wavefront
     constexpr int EA = KS * BB_M / 256;     // A elements staged per thread and slice
     constexpr int EB = KS * BN / 256;       // B elements staged per thread and slice
-    typedef typename std::conditional<AL32, float2, double2>::type SA;
+    typedef typename std::conditional<AL32, float2, typename std::conditional<ACPLX, double2, double>::type>::type SA;
+    typedef typename std::conditional<ACPLX, double2, double>::type FA;   // A fragment in registers
     // two LDS buffers: slice i is multiplied from one while slice i + 1 is staged into the other
     __shared__ SA sA[2][KS][BB_M + BB_PAD];
     __shared__ TB sB[2][KS][BN + BB_PAD];
@@ -368,6 +378,8 @@ void gemm_big_kernel(int m, int n, int k, double2 alpha, const TA* __restrict__ 
             amap(e, i, p);
             if constexpr (AL32) {
                 sA[buf][p][i] = conj_op(ra[e], OPA);
+            } else if constexpr (!ACPLX) {
+                sA[buf][p][i] = ra[e];
             } else {
                 double2 v = widen_op(ra[e], OPA);
                 if (bsl && row0 + i < m && kk + p < kend) band_lookup(bd, row0 + i, kk + p, v);
@@ -388,16 +400,25 @@ void gemm_big_kernel(int m, int n, int k, double2 alpha, const TA* __restrict__ 
 #pragma unroll 2
         for (int kc = 0; kc < KS / 4; ++kc) {
             const int pr = kc * 4 + (lane >> 4);
-            double2 a[RT];
+            FA a[RT];
             TB b[2];
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
                 const SA av = sA[buf][pr][wm * (16 * RT) + r * 16 + (lane & 15)];
-                a[r] = make_double2(av.x, av.y);
+                if constexpr (ACPLX) a[r] = make_double2(av.x, av.y);
+                else a[r] = av;
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = sB[buf][pr][wn * 32 + c * 16 + (lane & 15)];
-            if constexpr (GAUSS3) {
+            if constexpr (!ACPLX) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        accR[r][c] = mfma16(a[r], b[c].x, accR[r][c]);
+                        accI[r][c] = mfma16(a[r], b[c].y, accI[r][c]);
+                    }
+            } else if constexpr (GAUSS3) {
                 double as[RT], bs[2];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) as[r] = a[r].x + a[r].y;
@@ -768,6 +789,50 @@ bool zgemm_a32_real_b(Ctx& c, int m, int n, int k, double2 alpha, const float2* 
                     "banded complex64 GEMM: square symmetric operand");
     }
     return gemm_real_b<float2>(c, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, band);
+}
+
+bool zgemm_real_a(Ctx& c, int m, int n, int k, double2 alpha, const double* A, int64_t lda, const double2* B,
+                  int64_t ldb, double2 beta, double2* C, int64_t ldc) {
+    const bool narrow = n <= 32;
+    if (m < BB_M || n <= 0 || k <= 0 || (!narrow && n < BB_N)) return false;
+    const int bn = narrow ? 32 : BB_N;
+    const int gm = (m + BB_M - 1) / BB_M, gn = (n + bn - 1) / bn;
+    // two workgroups per compute unit: split K until about 512 are in flight
+    int nz = 1;
+    if (gm * gn < 512 && k > 4 * GB_K) nz = std::max(1, std::min((512 + gm * gn - 1) / (gm * gn), (k + 255) / 256));
+    nz = std::min(nz, 64);
+    if (c.noalloc && nz > 1) {   // the partial sums must fit the caller's workspace
+        const size_t per = sizeof(double2) * (size_t)m * n;
+        nz = std::max(1, std::min<int>(nz, (int)std::min<size_t>(c.ws_bytes / per, 64)));
+    }
+    int kchunk = (k + nz - 1) / nz;
+    kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
+    nz = (k + kchunk - 1) / kchunk;
+    double2* part = nullptr;
+    if (nz > 1)
+        part = c.noalloc ? static_cast<double2*>(c.ws)
+                         : static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)nz * m * n));
+    {
+        KScope _ks(c, c.gemm_tag ? c.gemm_tag : "gemm");
+        if (narrow)
+            hipLaunchKernelGGL((gemm_big_kernel<double, double2, OP_N, OP_N, 1>), dim3(gm, gn, nz), dim3(256), 0,
+                               c.stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, BandA());
+        else
+            hipLaunchKernelGGL((gemm_big_kernel<double, double2, OP_N, OP_N, 2>), dim3(gm, gn, nz), dim3(256), 0,
+                               c.stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, BandA());
+    }
+    FDS_HIP_TRY(hipGetLastError());
+    if (part) {
+        const int64_t tot = (int64_t)m * n;
+        {
+            KScope _ks(c, "gemm_splitk_reduce");
+            hipLaunchKernelGGL(splitk_reduce_kernel<double2>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                               c.stream, m, n, nz, alpha, part, beta, C, ldc);
+        }
+        FDS_HIP_TRY(hipGetLastError());
+        if (!c.noalloc) c.dfree(part);
+    }
+    return true;
 }
 
 int autotune_entries(Ctx& c, int cap, char* keys, int* values) {

@@ -44,6 +44,11 @@ bool zgemm_real_b(Ctx& c, int m, int n, int k, double2 alpha, const double2* A, 
                   int64_t ldb, double2 beta, double2* C, int64_t ldc);
 bool zgemm_a32_real_b(Ctx& c, int m, int n, int k, double2 alpha, const float2* A, int64_t lda, const double* B,
                       int64_t ldb, double2 beta, double2* C, int64_t ldc, const BandA& band = BandA());
+// C = alpha A B + beta C (no transposes) with a real A (the filter basis) and a
+// complex B: two real MFMAs per step instead of three; returns false without
+// launching when m < 128, or n < 64 with n > 32.
+bool zgemm_real_a(Ctx& c, int m, int n, int k, double2 alpha, const double* A, int64_t lda, const double2* B,
+                  int64_t ldb, double2 beta, double2* C, int64_t ldc);
 // Complex64 variant on the FP32 matrix cores (FP32 accumulation).
 void cgemm(Ctx& c, int opa, int opb, int m, int n, int k, float2 alpha, const float2* A, int64_t lda,
            const float2* B, int64_t ldb, float2 beta, float2* C, int64_t ldc);

@@ -511,7 +511,8 @@ void run_compress(Op& op, int rank_cap, int oversample, int power_iters, double 
         }
         scale_cols(c, Ur, ne, r, sg);
         op.U = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
-        zgemm(c, OP_N, OP_N, n, r, ne, kOne, op.Vgc, n, Ur, ne, kZero, op.U, n);
+        if (!zgemm_real_a(c, n, r, ne, kOne, op.Vg, n, Ur, ne, kZero, op.U, n))
+            zgemm(c, OP_N, OP_N, n, r, ne, kOne, op.Vgc, n, Ur, ne, kZero, op.U, n);
         if (T1) c.dfree(T1);
         // W_j^T = (W_y G^{1/2})^T = G^{1/2} conj(Q_P Vh_r)
         double2* T2 = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
@@ -821,7 +822,8 @@ void run_solve_system(Op& op, const double2* w, int64_t nrhs, double2* j_out, do
                 SplitHint sh(c, std::max(1, std::min(64, n / 256)));
                 zgemm(c, OP_N, OP_N, ne, (int)nrhs, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
             }
-            zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+            if (!zgemm_real_a(c, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vg, n, z, ne, kOne, res, n))
+                zgemm(c, OP_N, OP_N, n, (int)nrhs, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
         }
         if (stats) {
             gnorms(op, res, nrhs, nrm);
@@ -944,7 +946,8 @@ void run_solve_system_ws(Op& op, const double2* w, int64_t nrhs, double2* j_out,
             FDS_HIP_TRY(hipMemcpyAsync(res, wv, sizeof(double2) * tot, hipMemcpyDeviceToDevice, c.stream));
             axpby(c, make_double2(-op.beta, 0.0), jv, kOne, res, tot);
             zgemm(c, OP_N, OP_N, ne, (int)nb, n, kOne, op.Btr, ne, jv, n, kZero, z, ne);
-            zgemm(c, OP_N, OP_N, n, (int)nb, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
+            if (!zgemm_real_a(c, n, (int)nb, ne, make_double2(-1.0, 0.0), op.Vg, n, z, ne, kOne, res, n))
+                zgemm(c, OP_N, OP_N, n, (int)nb, ne, make_double2(-1.0, 0.0), op.Vgc, n, z, ne, kOne, res, n);
             woodbury_apply(op, res, nb, z);
             axpby(c, kOne, res, kOne, jv, tot);
         }
