@@ -585,7 +585,11 @@ void run_factor(Op& op) {
     FDS_REQUIRE(r <= 2048, FDS_ERR_NOTIMPL, "skeleton rank above 2048");
     // K = I + beta^{-1} W_j U_j ; W_j as the r x n matrix Wr
     double2* K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
-    zgemm(c, OP_N, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.Wr, r, op.U, n, kZero, K, r);
+    // the exact skeleton has U = V_g (held as its complex copy): the real V_g then
+    // serves as the real operand of both products with U
+    const bool ureal = op.U == op.Vgc && op.Vg != nullptr;
+    if (!(ureal && zgemm_real_b(c, r, r, n, make_double2(1.0 / op.beta, 0.0), op.Wr, r, op.Vg, n, kZero, K, r)))
+        zgemm(c, OP_N, OP_N, r, r, n, make_double2(1.0 / op.beta, 0.0), op.Wr, r, op.U, n, kZero, K, r);
     add_diag(c, K, r, 1.0);
     op.K = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)r * r));
     double hs[2];
@@ -595,7 +599,8 @@ void run_factor(Op& op) {
                 "Woodbury core is numerically singular");
     // fold the core into U: Up = U K^{-1}
     op.Up = static_cast<double2*>(c.dmalloc(sizeof(double2) * (size_t)n * r));
-    zgemm(c, OP_N, OP_N, n, r, r, kOne, op.U, n, op.K, r, kZero, op.Up, n);
+    if (!(ureal && zgemm_real_a(c, n, r, r, kOne, op.Vg, n, op.K, r, kZero, op.Up, n)))
+        zgemm(c, OP_N, OP_N, n, r, r, kOne, op.U, n, op.K, r, kZero, op.Up, n);
     op.stage = Stage::Factored;
 }
 
