@@ -538,17 +538,27 @@ __device__ __forceinline__ double recip(double d) {
     return r;
 }
 
-// Pseudo-random start vector entries in [-1/2, 1/2): a 32-bit integer hash of
-// (eigenvalue index, node), cheap enough to sit beside the elimination.
-__device__ __forceinline__ double start_value(int i, int node) {
-    uint32_t z = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)node * 0x85EBCA77u;
-    z ^= z >> 15;
-    z *= 0x2C1B3C6Du;
-    z ^= z >> 12;
-    z *= 0x297A2D39u;
-    z ^= z >> 15;
-    return (double)z * (1.0 / 4294967296.0) - 0.5;
-}
+// Pseudo-random start vector entries in [-1/2, 1/2): Marsaglia's xorshift32
+// (J. Stat. Softw. 8(14), 2003; shifts 13, 17, 5) run along the rows each half
+// eliminates, from a seed mixed from (eigenvalue index, half). Every row enters
+// exactly one half's window once, so this defines one start vector per
+// eigenvalue; six shift/xor operations per row beside the elimination.
+struct StartSeq {
+    uint32_t z;
+    __device__ StartSeq(int i, int h) {
+        z = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(h + 1) * 0x85EBCA77u;
+        z ^= z >> 15;
+        z *= 0x2C1B3C6Du;
+        z ^= z >> 12;
+        z |= 1u;   // xorshift32 has no zero state
+    }
+    __device__ __forceinline__ double next() {
+        z ^= z << 13;
+        z ^= z >> 17;
+        z ^= z << 5;
+        return (double)z * (1.0 / 4294967296.0) - 0.5;
+    }
+};
 
 // Factorisation of both halves (blockIdx.y = half) with the forward elimination
 // of the pseudo-random right-hand side (the first inverse-iteration step): z into
@@ -580,9 +590,10 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
         Bw[t] = t + 1 < 5 ? band(Lb, t + 1, 1) - s * band(Gb, t + 1, 1) : 0.0;
         Cw[t] = band(Lb, t, 2) - s * band(Gb, t, 2);
     }
-    double yA = start_value(i, node_of(trow(h, 0, n), n));
-    double yB = start_value(i, node_of(trow(h, 1, n), n));
-    double yC = start_value(i, node_of(trow(h, 2, n), n));
+    StartSeq sq(i, h);
+    double yA = sq.next();   // rows 0, 1, 2 of this half's elimination order
+    double yB = sq.next();
+    double yC = sq.next();
     __shared__ double rows[64][10];
     for (int j0 = 0; j0 < m; j0 += 64) {
         // stage band rows j0+3 .. j0+66 in LDS (one per lane); every lane reads them all
@@ -604,7 +615,7 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
                 nl[t] = rows[j - j0][t];
                 ng[t] = rows[j - j0][5 + t];
             }
-            const double ynext = start_value(i, node_of(trow(h, j + 3, n), n));   // j + 3 <= n - 2
+            const double ynext = sq.next();   // row j + 3 (j + 3 <= n - 2)
             // partial pivoting among the rows j, j+1, j+2 (rows j+1, j+2 exist: j + 2 <= m + 1
             // <= n - 3), as selects: pivot row U, remaining rows R1, R2 in their order
             const double fa = fabs(A[0]), fb = fabs(Bw[0]), fc = fabs(Cw[0]);
