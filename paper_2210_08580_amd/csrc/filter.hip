@@ -637,12 +637,15 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
             const double inv = recip(u0);
             const double l1 = R1[0] * inv, l2 = R2[0] * inv;
             if (act) {
-                const int64_t e = (int64_t)j * nw + i;
-                F.L[e] = make_double2(l1, l2);
-                F.P[e] = p;
-                F.IZ[e] = make_double2(inv, yU);
-                F.U12[e] = make_double2(U[1], U[2]);
-                F.U34[e] = make_double2(U[3], U[4]);
+                // one 32-bit byte offset from the uniform array bases (the host keeps
+                // each record array below 4 GiB)
+                const uint32_t off = ((uint32_t)j * (uint32_t)nw + (uint32_t)i) * 16u;
+                auto at = [&](void* base) { return reinterpret_cast<double2*>(static_cast<char*>(base) + off); };
+                *at(F.L) = make_double2(l1, l2);
+                *reinterpret_cast<int*>(reinterpret_cast<char*>(F.P) + (off >> 2)) = p;
+                *at(F.IZ) = make_double2(inv, yU);
+                *at(F.U12) = make_double2(U[1], U[2]);
+                *at(F.U34) = make_double2(U[3], U[4]);
             }
             // eliminate and shift the window by one column
 #pragma unroll
@@ -1344,6 +1347,7 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // two-ended elimination: mt steps from the top, mb from the bottom, 4 interface rows
     const int mt = (n - 4) / 2, mb = n - 4 - mt;
     const int64_t facM = (int64_t)mb * ne;     // entries per record array (mb >= mt)
+    FDS_REQUIRE(facM * 16 < ((int64_t)1 << 32), FDS_ERR_NOTIMPL, "inverse-iteration records above 4 GiB per array");
     char* fac = static_cast<char*>(c.dmalloc(2 * fac_half_bytes(facM)));
     double* IF = static_cast<double*>(c.dmalloc(sizeof(double) * 20 * (size_t)ne));
     double* Xn = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));   // node-major
