@@ -530,6 +530,20 @@ __device__ __forceinline__ FacView fac_view(char* base, int64_t M, int h) {
 
 __device__ __forceinline__ int trow(int h, int j, int n) { return h == 0 ? j : n - 1 - j; }
 
+// Entry (row, i) of a [rows][nw] array by a 32-bit byte offset from its uniform base
+// (the host keeps these arrays below 4 GiB): one offset per lane instead of a
+// 64-bit address per array.
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, int row, int nw, int i) {
+    const uint32_t off = ((uint32_t)row * (uint32_t)nw + (uint32_t)i) * (uint32_t)sizeof(T);
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ const T* at32(const T* base, int row, int nw, int i) {
+    const uint32_t off = ((uint32_t)row * (uint32_t)nw + (uint32_t)i) * (uint32_t)sizeof(T);
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
 // 1/d: hardware reciprocal estimate refined by two Newton steps r <- r + r (1 - d r)
 __device__ __forceinline__ double recip(double d) {
     double r = __builtin_amdgcn_rcp(d);
@@ -637,15 +651,11 @@ __global__ __launch_bounds__(64) void invit_factor_kernel(int n, int mt, int mb,
             const double inv = recip(u0);
             const double l1 = R1[0] * inv, l2 = R2[0] * inv;
             if (act) {
-                // one 32-bit byte offset from the uniform array bases (the host keeps
-                // each record array below 4 GiB)
-                const uint32_t off = ((uint32_t)j * (uint32_t)nw + (uint32_t)i) * 16u;
-                auto at = [&](void* base) { return reinterpret_cast<double2*>(static_cast<char*>(base) + off); };
-                *at(F.L) = make_double2(l1, l2);
-                *reinterpret_cast<int*>(reinterpret_cast<char*>(F.P) + (off >> 2)) = p;
-                *at(F.IZ) = make_double2(inv, yU);
-                *at(F.U12) = make_double2(U[1], U[2]);
-                *at(F.U34) = make_double2(U[3], U[4]);
+                *at32(F.L, j, nw, i) = make_double2(l1, l2);
+                *at32(F.P, j, nw, i) = p;
+                *at32(F.IZ, j, nw, i) = make_double2(inv, yU);
+                *at32(F.U12, j, nw, i) = make_double2(U[1], U[2]);
+                *at32(F.U34, j, nw, i) = make_double2(U[3], U[4]);
             }
             // eliminate and shift the window by one column
 #pragma unroll
@@ -785,7 +795,7 @@ __global__ __launch_bounds__(64) void invit_back_kernel(int n, int mt, int mb, i
     auto step = [&](int j, double inv, double2 u12, double2 u34, double z) {
         const double part = fma(-u34.y, x4, fma(-u34.x, x3, fma(-u12.y, x2, z)));
         const double v = fma(-u12.x, x1, part) * inv;
-        if (act) X[(int64_t)node_of(trow(h, j, n), n) * nw + i] = v;
+        if (act) *at32(X, node_of(trow(h, j, n), n), nw, i) = v;
         x4 = x3;
         x3 = x2;
         x2 = x1;
@@ -798,18 +808,16 @@ __global__ __launch_bounds__(64) void invit_back_kernel(int n, int mt, int mb, i
         double2 riz[IV_DB], ru12[IV_DB], ru34[IV_DB];
 #pragma unroll
         for (int q = 0; q < IV_DB; ++q) {
-            const int64_t e = (int64_t)(j0 - q) * nw + i;
-            riz[q] = F.IZ[e];
-            ru12[q] = F.U12[e];
-            ru34[q] = F.U34[e];
+            riz[q] = *at32(F.IZ, j0 - q, nw, i);
+            ru12[q] = *at32(F.U12, j0 - q, nw, i);
+            ru34[q] = *at32(F.U34, j0 - q, nw, i);
         }
 #pragma unroll
         for (int q = 0; q < IV_DB; ++q) step(j0 - q, riz[q].x, ru12[q], ru34[q], riz[q].y);
     }
     for (; j0 >= 0; --j0) {
-        const int64_t e = (int64_t)j0 * nw + i;
-        const double2 iz = F.IZ[e];
-        step(j0, iz.x, F.U12[e], F.U34[e], iz.y);
+        const double2 iz = *at32(F.IZ, j0, nw, i);
+        step(j0, iz.x, *at32(F.U12, j0, nw, i), *at32(F.U34, j0, nw, i), iz.y);
     }
 }
 
@@ -841,7 +849,6 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(int n, int mt, int mb, in
     const bool act = i0 < nw;
     const int i = min(i0, nw - 1);
     const FacView F = fac_view(fac, M, h);
-    double* __restrict__ izd = reinterpret_cast<double*>(F.IZ);   // z_j goes to the odd entries
     auto rnode = [&](int j) { return node_of(trow(h, j, n), n); };
     double y0 = WZ[(int64_t)rnode(0) * nw + i], y1 = WZ[(int64_t)rnode(1) * nw + i];
     // one elimination step on the rows (y0, y1, a2): returns nothing, leaves the
@@ -852,7 +859,7 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(int n, int mt, int mb, in
         const double u = p == 1 ? a1 : (p == 2 ? a2 : a0);
         const double b1 = p == 1 ? a0 : a1;
         const double b2 = p == 2 ? a0 : a2;
-        if (act) izd[2 * ((int64_t)j * nw + i) + 1] = u;
+        if (act) at32(F.IZ, j, nw, i)->y = u;
         y0 = fma(-l.x, u, b1);
         y1 = fma(-l.y, u, b2);
     };
@@ -861,10 +868,9 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(int n, int mt, int mb, in
     double rr[IV_DF];
     // row j + 3 <= m + 2 <= n - 2 always exists
     auto load = [&](int j, int q) {
-        const int64_t e = (int64_t)j * nw + i;
-        rl[q] = F.L[e];
-        rp[q] = F.P[e];
-        rr[q] = WZ[(int64_t)rnode(j + 3) * nw + i];
+        rl[q] = *at32(F.L, j, nw, i);
+        rp[q] = *at32(F.P, j, nw, i);
+        rr[q] = *at32(WZ, rnode(j + 3), nw, i);
     };
     int j0 = 0;
     if (m >= 2 * IV_DF - 1) {
@@ -890,10 +896,9 @@ __global__ __launch_bounds__(64) void invit_fwd_kernel(int n, int mt, int mb, in
     // W is read-only here: the entering row of step j0 is row j0 + 2
     double y2 = WZ[(int64_t)rnode(j0 + 2) * nw + i];
     for (; j0 < m; ++j0) {
-        const int64_t e = (int64_t)j0 * nw + i;
-        const double r = WZ[(int64_t)rnode(j0 + 3) * nw + i];
-        const double2 l = F.L[e];
-        step(j0, F.P[e], make_double2(l.x, l.y), y2);
+        const double r = *at32(WZ, rnode(j0 + 3), nw, i);
+        const double2 l = *at32(F.L, j0, nw, i);
+        step(j0, *at32(F.P, j0, nw, i), make_double2(l.x, l.y), y2);
         y2 = r;
     }
     if (act) {
@@ -1347,7 +1352,8 @@ void compute_filter_basis(Op& op, int n_modes, bool keep_null, double cluster_rt
     // two-ended elimination: mt steps from the top, mb from the bottom, 4 interface rows
     const int mt = (n - 4) / 2, mb = n - 4 - mt;
     const int64_t facM = (int64_t)mb * ne;     // entries per record array (mb >= mt)
-    FDS_REQUIRE(facM * 16 < ((int64_t)1 << 32), FDS_ERR_NOTIMPL, "inverse-iteration records above 4 GiB per array");
+    FDS_REQUIRE(facM * 16 < ((int64_t)1 << 32) && (int64_t)n * ne * 8 < ((int64_t)1 << 32), FDS_ERR_NOTIMPL,
+                "inverse-iteration arrays above 4 GiB");
     char* fac = static_cast<char*>(c.dmalloc(2 * fac_half_bytes(facM)));
     double* IF = static_cast<double*>(c.dmalloc(sizeof(double) * 20 * (size_t)ne));
     double* Xn = static_cast<double*>(c.dmalloc(sizeof(double) * (size_t)n * ne));   // node-major
