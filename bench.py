@@ -582,8 +582,8 @@ def roofline(prof, n, ne, nrhs, steps, precision, form="efie", nbw=0, workload="
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="star8192",
                     help="star8192 (default), star8192ec (equal-chord mesh), star4096, ellipse16384, circle256, "
                          "batch64 (64 curves, graph replay), grad8192 (far-field gradient) or table1 (the paper's Table I)")
